@@ -1,0 +1,383 @@
+"""Seeded synthetic inputs for the proton dose engine and its oracle.
+
+This module is the only code that both the HIP path and the FP64 oracle see.
+It builds phantoms (HU grids), calibrations, beam fields and spot lists and
+holds none of the transport arithmetic: no stopping powers, no sampling, no
+geometry tracking.  Everything is deterministic given its seed (numpy PCG64).
+
+The paper's workloads are patient 4DCTs (lung, esophagus and liver, Table I)
+and their clinical plans, which are not available; the thorax below stands in
+for them with grids and voxel sizes of the same order (Table I: 427x246x161 at
+1.27x1.27x2.0 mm; here 256x256x160 at 1.5x1.5x2.0 mm) and with the breathing
+motion of up to 20 mm quoted in the introduction.  Spots carry a breathing
+phase index assigned by a simplified beam-delivery clock (Sec. 2.B: sub-plans
+per phase); the full synchrotron timing model of Appendix A is not reproduced.
+
+Conventions (shared with the C ABI):
+  * HU grids are int16 numpy arrays of shape (nz, ny, nx), C order, so x is the
+    fastest index in memory.
+  * origin_mm is the corner of voxel (0, 0, 0); voxel (i, j, k) spans
+    [o + i*d, o + (i+1)*d) on each axis.
+  * Spot positions are in the beam's-eye-view plane through the isocentre
+    along bev_u and bev_v = direction x bev_u.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# Layouts identical to the C structs pmc_spot / pmc_field (48 and 72 bytes).
+SPOT_DTYPE = np.dtype(
+    [
+        ("energy_MeV", "<f8"),
+        ("x_mm", "<f8"),
+        ("y_mm", "<f8"),
+        ("sigma_mm", "<f8"),
+        ("weight", "<f8"),
+        ("phase", "<i4"),
+        ("field", "<i4"),
+    ]
+)
+FIELD_DTYPE = np.dtype(
+    [("isocentre_mm", "<f8", 3), ("direction", "<f8", 3), ("bev_u", "<f8", 3)]
+)
+assert SPOT_DTYPE.itemsize == 48 and FIELD_DTYPE.itemsize == 72
+
+# Six-node synthetic CT calibration (HU -> mass density g/cm^3, HU -> RSP).
+# Water (HU 0) maps to exactly (1, 1).  Ref 46 of the paper (the clinical
+# calibration) is not available; these nodes are a stand-in of the usual shape.
+CALIB_HU = np.array([-1000.0, -100.0, 0.0, 100.0, 1000.0, 3000.0])
+CALIB_RHO = np.array([0.0012, 0.93, 1.00, 1.09, 1.62, 2.80])
+CALIB_RSP = np.array([0.0010, 0.95, 1.00, 1.07, 1.55, 2.45])
+
+# Single-node-pair "all water" calibration: every HU maps to (1, 1).
+WATER_CALIB = (np.array([-1024.0, 3071.0]), np.array([1.0, 1.0]), np.array([1.0, 1.0]))
+
+
+@dataclasses.dataclass
+class Phase:
+    """One CT phase: HU grid + geometry + calibration (+ optional mask)."""
+
+    hu: np.ndarray  # int16 (nz, ny, nx)
+    spacing_mm: Tuple[float, float, float]
+    origin_mm: Tuple[float, float, float]
+    calib_hu: np.ndarray
+    calib_rho: np.ndarray
+    calib_rsp: np.ndarray
+    mask: Optional[np.ndarray] = None  # uint8 (nz, ny, nx) or None
+
+    @property
+    def shape_xyz(self) -> Tuple[int, int, int]:
+        nz, ny, nx = self.hu.shape
+        return nx, ny, nz
+
+    @property
+    def nvox(self) -> int:
+        return int(self.hu.size)
+
+
+@dataclasses.dataclass
+class Plan:
+    fields: np.ndarray  # FIELD_DTYPE[n_fields]
+    spots: np.ndarray  # SPOT_DTYPE[n_spots]
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    phases: List[Phase]
+    plan: Plan
+    n_histories: int
+    seed: int  # Philox key word 0
+    request_id: int = 0
+
+
+def make_field(iso_mm, direction, bev_u) -> np.ndarray:
+    f = np.zeros((), dtype=FIELD_DTYPE)
+    f["isocentre_mm"] = iso_mm
+    f["direction"] = direction
+    f["bev_u"] = bev_u
+    return f
+
+
+def _spots(rows) -> np.ndarray:
+    a = np.zeros(len(rows), dtype=SPOT_DTYPE)
+    for i, r in enumerate(rows):
+        a[i] = r
+    return a
+
+
+# ----------------------------------------------------------------------------
+# Phantoms
+# ----------------------------------------------------------------------------
+
+def make_box(shape_xyz, spacing_mm, hu_value=0, origin_mm=None, calib=None) -> Phase:
+    nx, ny, nz = shape_xyz
+    if origin_mm is None:
+        origin_mm = (-0.5 * nx * spacing_mm[0], -0.5 * ny * spacing_mm[1], 0.0)
+    hu = np.full((nz, ny, nx), hu_value, dtype=np.int16)
+    ch, cr, cs = calib if calib is not None else (CALIB_HU, CALIB_RHO, CALIB_RSP)
+    return Phase(hu, tuple(map(float, spacing_mm)), tuple(map(float, origin_mm)),
+                 ch.copy(), cr.copy(), cs.copy())
+
+
+def make_water(n=40, spacing=2.5) -> Phase:
+    """Homogeneous water cube, n^3 voxels, all HU 0; z from 0, x/y centred."""
+    return make_box((n, n, n), (spacing, spacing, spacing), 0)
+
+
+def make_slabs() -> Phase:
+    """128^3 at 2 mm; z slabs: tissue 30 mm, bone 10 mm, lung 60 mm, tissue."""
+    p = make_box((128, 128, 128), (2.0, 2.0, 2.0), 40)
+    z_mm = (np.arange(128) + 0.5) * 2.0  # voxel centres
+    hu_z = np.where(z_mm < 30, 40, np.where(z_mm < 40, 1000, np.where(z_mm < 100, -700, 40)))
+    p.hu[:] = hu_z.astype(np.int16)[:, None, None]
+    return p
+
+
+THORAX_EXTENT_MM = (384.0, 384.0, 320.0)
+
+
+def breathing_shift_mm(t_s: float, amplitude=20.0, period=4.0) -> float:
+    """Superior-inferior displacement d(t) = A sin^4(pi t / T)."""
+    return amplitude * math.sin(math.pi * t_s / period) ** 4
+
+
+def make_thorax(shape_xyz=(256, 256, 160), phase=0, n_phases=10, period=4.0,
+                lung_scale=1.0, tumour_scale=1.0, tumour_offset_mm=(0.0, 0.0, 0.0),
+                extent_mm=THORAX_EXTENT_MM) -> Phase:
+    """Synthetic thorax phase on a grid centred on the origin.
+
+    Air -1000; body elliptic cylinder (a=160, b=110 mm) HU 40; two lung
+    ellipsoids at (+-80, 10, -20) mm, semi-axes (55, 70, 100) HU -750; spine
+    cylinder r=15 mm at (0, -75) HU 700; tumour sphere r=20 mm at
+    (-80, 20, -10) HU 40.  Painted in that order and sampled at voxel centres.
+    Lungs and tumour move +z by d(t) with t = period * phase / n_phases.
+    """
+    nx, ny, nz = shape_xyz
+    sp = (extent_mm[0] / nx, extent_mm[1] / ny, extent_mm[2] / nz)
+    org = (-0.5 * extent_mm[0], -0.5 * extent_mm[1], -0.5 * extent_mm[2])
+    x = org[0] + (np.arange(nx) + 0.5) * sp[0]
+    y = org[1] + (np.arange(ny) + 0.5) * sp[1]
+    z = org[2] + (np.arange(nz) + 0.5) * sp[2]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    d = breathing_shift_mm(period * phase / n_phases, period=period)
+    hu = np.full((nz, ny, nx), -1000, dtype=np.int16)
+    hu[(X / 160.0) ** 2 + (Y / 110.0) ** 2 <= 1.0] = 40
+    la = np.array([55.0, 70.0, 100.0]) * lung_scale
+    for cx in (-80.0, 80.0):
+        m = ((X - cx) / la[0]) ** 2 + ((Y - 10.0) / la[1]) ** 2 + ((Z - (-20.0 + d)) / la[2]) ** 2 <= 1.0
+        hu[m] = -750
+    hu[(X - 0.0) ** 2 + (Y + 75.0) ** 2 <= 15.0 ** 2] = 700
+    tr = 20.0 * tumour_scale
+    tc = (-80.0 + tumour_offset_mm[0], 20.0 + tumour_offset_mm[1], -10.0 + d + tumour_offset_mm[2])
+    hu[(X - tc[0]) ** 2 + (Y - tc[1]) ** 2 + (Z - tc[2]) ** 2 <= tr * tr] = 40
+    return Phase(hu, sp, org, CALIB_HU.copy(), CALIB_RHO.copy(), CALIB_RSP.copy())
+
+
+# ----------------------------------------------------------------------------
+# Plans and the simplified delivery clock
+# ----------------------------------------------------------------------------
+
+def assign_phases(n_spots_per_layer: Sequence[int], start_phase: int, t_spot=0.002,
+                  t_layer_switch=1.0, period=4.0, n_phases=10) -> np.ndarray:
+    """Breathing phase at each spot's start time (spots in delivery order).
+
+    The clock starts at phase `start_phase`; each spot takes t_spot seconds and
+    each change of energy layer t_layer_switch seconds.  A spot is given whole
+    to the phase it starts in (no splitting across phases).
+    """
+    phases = []
+    t = 0.0
+    for li, n in enumerate(n_spots_per_layer):
+        if li > 0:
+            t += t_layer_switch
+        for _ in range(n):
+            ph = (start_phase + int(math.floor(t / period * n_phases))) % n_phases
+            phases.append(ph)
+            t += t_spot
+    return np.array(phases, dtype=np.int32)
+
+
+def layer_grid(nu: int, nv: int, pitch: float, serpentine=True):
+    """Spot positions (u, v) of one layer on a centred nu x nv grid."""
+    us = (np.arange(nu) - 0.5 * (nu - 1)) * pitch
+    vs = (np.arange(nv) - 0.5 * (nv - 1)) * pitch
+    out = []
+    for j, v in enumerate(vs):
+        row = us if (not serpentine or j % 2 == 0) else us[::-1]
+        for u in row:
+            out.append((float(u), float(v)))
+    return out
+
+
+def plan_single(energy=150.0, sigma=5.0, iso=(0.0, 0.0, 50.0), direction=(0, 0, 1),
+                bev_u=(1, 0, 0)) -> Plan:
+    fields = np.array([make_field(iso, direction, bev_u)], dtype=FIELD_DTYPE)
+    spots = _spots([(energy, 0.0, 0.0, sigma, 1.0, 0, 0)])
+    return Plan(fields, spots)
+
+
+def plan_slabs(seed=2) -> Plan:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fields = np.array([make_field((0.0, 0.0, 128.0), (0, 0, 1), (1, 0, 0))], dtype=FIELD_DTYPE)
+    rows = []
+    for l in range(10):
+        e = 100.0 + 80.0 * l / 9.0
+        sig = 7.0 - 3.0 * (e - 100.0) / 80.0
+        for (u, v) in layer_grid(10, 5, 5.0):
+            rows.append((e, u, v, sig, 0.0, 0, 0))
+    spots = _spots(rows)
+    spots["weight"] = rng.lognormal(0.0, 0.5, size=len(spots))
+    return Plan(fields, spots)
+
+
+def plan_thorax(seed=3, n_layers=20, e_lo=90.0, e_hi=200.0, grid=(15, 10), pitch=5.0,
+                directions=((0.0, -1.0, 0.0),), spots_per_field=None,
+                iso=(-80.0, 20.0, -2.5), start_phase=None, n_phases=10) -> Plan:
+    """Thorax plan: layers delivered high -> low energy, serpentine spots.
+
+    sigma falls linearly from 7 mm at e_lo to 4 mm at e_hi.  Each spot gets the
+    breathing phase at its start time from `assign_phases`.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if start_phase is None:
+        start_phase = int(rng.integers(0, n_phases))
+    fields = []
+    rows = []
+    for fi, dvec in enumerate(directions):
+        dvec = np.asarray(dvec, dtype=float)
+        dvec = dvec / np.linalg.norm(dvec)
+        # bev_u: x axis unless the beam runs along x, then -y-ish
+        ref = np.array([0.0, 0.0, 1.0])
+        u = np.cross(ref, dvec)
+        if np.linalg.norm(u) < 1e-9:
+            u = np.array([1.0, 0.0, 0.0])
+        u = u / np.linalg.norm(u)
+        fields.append(make_field(iso, dvec, u))
+        layer_counts = []
+        pos = layer_grid(grid[0], grid[1], pitch)
+        if spots_per_field is not None:
+            per_layer = int(math.ceil(spots_per_field[fi] / n_layers))
+        else:
+            per_layer = len(pos)
+        for l in range(n_layers):
+            e = e_hi - (e_hi - e_lo) * l / max(n_layers - 1, 1)
+            sig = 7.0 - 3.0 * (e - e_lo) / (e_hi - e_lo)
+            take = pos[:per_layer] if per_layer <= len(pos) else [pos[i % len(pos)] for i in range(per_layer)]
+            if spots_per_field is not None:
+                remaining = spots_per_field[fi] - sum(layer_counts)
+                take = take[: max(0, min(len(take), remaining))]
+            layer_counts.append(len(take))
+            for (pu, pv) in take:
+                rows.append((e, pu, pv, sig, 0.0, 0, fi))
+        ph = assign_phases(layer_counts, start_phase, n_phases=n_phases)
+        base = len(rows) - len(ph)
+        for k, p in enumerate(ph):
+            r = list(rows[base + k])
+            r[5] = int(p)
+            rows[base + k] = tuple(r)
+    spots = _spots(rows)
+    spots["weight"] = rng.lognormal(0.0, 0.5, size=len(spots))
+    return Plan(np.array(fields, dtype=FIELD_DTYPE), spots)
+
+
+# ----------------------------------------------------------------------------
+# The benchmark workloads
+# ----------------------------------------------------------------------------
+
+def workload_tiny(n_histories=100_000) -> Workload:
+    """40^3 water at 2.5 mm, one 150 MeV spot along +z, sigma 5 mm."""
+    ph = make_water(40, 2.5)
+    ph.origin_mm = (-50.0, -50.0, 0.0)
+    return Workload("tiny_water_40", [ph], plan_single(150.0, 5.0, (0.0, 0.0, 50.0)), n_histories, seed=1)
+
+
+def workload_slabs(n_histories=10_000_000) -> Workload:
+    ph = make_slabs()
+    ph.origin_mm = (-128.0, -128.0, 0.0)
+    return Workload("slabs_128", [ph], plan_slabs(2), n_histories, seed=2)
+
+
+def workload_thorax4d(n_histories=50_000_000, shape_xyz=(256, 256, 160), n_phases=10) -> Workload:
+    phases = [make_thorax(shape_xyz, p, n_phases) for p in range(n_phases)]
+    plan = plan_thorax(3, n_phases=n_phases)
+    return Workload("thorax4d_256x256x160x10", phases, plan, n_histories, seed=3)
+
+
+SERVED_GRIDS = [(64, 64, 64), (96, 96, 96), (128, 128, 128), (192, 192, 120), (256, 256, 160)]
+
+
+@dataclasses.dataclass
+class ServedRequest:
+    index: int
+    arrival_s: float
+    grid: Tuple[int, int, int]
+    phase_index: int
+    phantom_key: tuple
+    n_spots: int
+    n_histories: int
+    seed: int
+
+
+def served_stream(n_requests=200, rate_hz=1.0, seed=4, h_lo=1e5, h_hi=5e7) -> List[ServedRequest]:
+    """Poisson arrivals of single-phase dose requests of mixed size."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += float(rng.exponential(1.0 / rate_hz))
+        grid = SERVED_GRIDS[int(rng.integers(0, len(SERVED_GRIDS)))]
+        ph = int(rng.integers(0, 10))
+        lung = float(rng.uniform(0.9, 1.1))
+        tum = float(rng.uniform(0.9, 1.1))
+        off = tuple(float(v) for v in rng.uniform(-10.0, 10.0, size=3))
+        n_spots = int(round(math.exp(rng.uniform(math.log(50), math.log(3000)))))
+        n_hist = int(round(math.exp(rng.uniform(math.log(h_lo), math.log(h_hi)))))
+        out.append(ServedRequest(i, t, grid, ph, (grid, ph, round(lung, 6), round(tum, 6), off),
+                                 n_spots, n_hist, int(rng.integers(0, 2**31))))
+    return out
+
+
+def served_phantom(req: ServedRequest) -> Phase:
+    grid, ph, lung, tum, off = req.phantom_key
+    return make_thorax(grid, ph, 10, lung_scale=lung, tumour_scale=tum, tumour_offset_mm=off)
+
+
+def served_plan(req: ServedRequest) -> Plan:
+    n_layers = max(1, int(math.ceil(req.n_spots / 150)))
+    per_layer = int(math.ceil(req.n_spots / n_layers))
+    nu = int(math.ceil(math.sqrt(per_layer * 1.5)))
+    nv = int(math.ceil(per_layer / nu))
+    plan = plan_thorax(req.seed % (2**31), n_layers=n_layers, e_lo=90.0, e_hi=200.0,
+                       grid=(nu, nv), spots_per_field=[req.n_spots], start_phase=0, n_phases=1)
+    plan.spots["phase"] = 0
+    return plan
+
+
+ROBUST_DIRECTIONS = ((0.0, -1.0, 0.0), (1.0, 0.0, 0.0), (1.0 / math.sqrt(2.0), -1.0 / math.sqrt(2.0), 0.0))
+ROBUST_SCENARIOS = [
+    ("nominal", (0.0, 0.0, 0.0), 1.0),
+    ("x+3", (3.0, 0.0, 0.0), 1.0), ("x-3", (-3.0, 0.0, 0.0), 1.0),
+    ("y+3", (0.0, 3.0, 0.0), 1.0), ("y-3", (0.0, -3.0, 0.0), 1.0),
+    ("z+3", (0.0, 0.0, 3.0), 1.0), ("z-3", (0.0, 0.0, -3.0), 1.0),
+    ("rsp+3.5%", (0.0, 0.0, 0.0), 1.035), ("rsp-3.5%", (0.0, 0.0, 0.0), 0.965),
+]
+
+
+def plan_robust(seed=5, shift_mm=(0.0, 0.0, 0.0)) -> Plan:
+    """3-field plan, 8000 spots (2667/2667/2666), 20 layers 90-200 MeV each.
+
+    A setup shift is applied as a translation of every field's isocentre.
+    """
+    iso = tuple(np.array([-80.0, 20.0, -2.5]) + np.asarray(shift_mm))
+    return plan_thorax(seed, n_layers=20, e_lo=90.0, e_hi=200.0, grid=(14, 10), pitch=5.0,
+                       directions=ROBUST_DIRECTIONS, spots_per_field=[2667, 2667, 2666], iso=iso)
+
+
+def scaled_calibration(phase: Phase, rsp_scale: float) -> Phase:
+    """Same phase with its HU->RSP calibration scaled (range uncertainty)."""
+    return dataclasses.replace(phase, calib_rsp=phase.calib_rsp * rsp_scale)

@@ -1,0 +1,391 @@
+"""Pins of the oracle's transport against closed forms, textbook laws and
+integer invariants.
+
+  P1  straight-ahead continuous slowing down: protons stop at the tabulated
+      restricted range and every voxel receives the telescoped energy
+      difference E(z_in) - E(z_out) with E(z) = R^-1(R0 - z).
+  P1b full physics: distal 80 % depth within 1 mm of the PSTAR CSDA range.
+  P2  Highland: RMS projected exit angle of a frozen-energy beam equals
+      the PDG formula for the slab (telescoping makes it step-independent).
+  P3  lateral spread at the exit face: the Fermi-Eyges sum of the model's own
+      angular increments weighted by the remaining lever arm.
+  P4  soft straggling: exit-energy variance equals the integral of omega^2.
+  P5  delta-ray production rate equals mu_delta per unit path.
+  P6  nuclear removal follows exp(-mu_N rho L).
+  P7  energy balance: deposited + escaped + nuclear == incident, exactly.
+  P8  brute force: a plain-Python replay of every recorded step of a few
+      histories in a 3x3x3 heterogeneous phantom (every draw recomputed).
+  P9  integer invariants: thread count, superposition over history ranges,
+      and the paper's two 3D comparison tests (Sec. 2.E) as bit-exact checks.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1809_03927_amd import workloads as W
+
+ME = 0.51099895
+MP = 938.27208816
+X0 = 36.08
+Q = 2.0 ** 32
+
+CSDA_ONLY = 1 | 2 | 4 | 8  # no straggling, no MCS, no delta, no nuclear
+
+
+def water(shape_xyz, spacing_mm, origin_mm=None, hu=0):
+    return W.make_box(shape_xyz, spacing_mm, hu, origin_mm=origin_mm)
+
+
+def with_xy(plan, x, y):
+    plan.spots["x_mm"] = x
+    plan.spots["y_mm"] = y
+    return plan
+
+
+def check_balance(bal):
+    assert bal["deposited"] + bal["escaped"] + bal["nuclear"] == bal["incident"]
+
+
+def kin(T):
+    Etot = T + MP
+    pc = math.sqrt(T * T + 2 * T * MP)
+    return (pc / Etot) ** 2, pc
+
+
+def highland_theta2(E, L):
+    """PDG Highland formula (projected angle), theta0^2 for mass path L."""
+    if L <= 0:
+        return 0.0
+    beta2, pc = kin(E)
+    th0 = 13.6 / (math.sqrt(beta2) * pc) * math.sqrt(L / X0) * (1 + 0.038 * math.log(L / (X0 * beta2)))
+    return th0 * th0
+
+
+# ----------------------------------------------------------------------------
+# P1 continuous slowing down
+# ----------------------------------------------------------------------------
+
+def test_p1_csda_stop_depth_and_depth_dose(orc):
+    E0 = 100.0
+    ph = water((3, 3, 100), (10.0, 10.0, 1.0), origin_mm=(-15.0, -15.0, 0.0))
+    plan = with_xy(W.plan_single(E0, 0.0, (0.0, 0.0, 50.0)), 0.37, -0.21)
+    R0 = orc.f64("orc_range", E0)
+    tr = orc.trace(ph, plan, 0, 0, seed=1, flags=CSDA_ONLY)
+    assert tr[-1]["fate"] == orc.FATE_STOPPED
+    assert tr[-1]["r"][2] == pytest.approx(R0, rel=1e-10)
+    assert np.all(tr["cause"][1:] != orc.CAUSE_DELTA)
+    N = 7
+    tallies, _, bal = orc.dose([ph], plan, N, seed=1, flags=CSDA_ONLY, n_threads=2)
+    check_balance(bal)
+    assert bal["escaped"] == 0 and bal["nuclear"] == 0
+    t = tallies[0].reshape(100, 3, 3)
+    per_z = t.sum(axis=(1, 2))
+    assert np.all(t.sum(axis=0)[[0, 0, 1, 2, 2], [0, 2, 0, 0, 2]] == 0)  # only the centre column
+    z = np.arange(101) * 0.1
+    E = np.array([orc.f64("orc_range_inverse", max(R0 - zz, 0.0)) if zz < R0 else 0.0 for zz in z])
+    E[0] = E0
+    k_stop = int(math.floor(R0 / 0.1))
+    qE = np.array([round(e * Q) for e in E], dtype=np.int64)
+    qE[k_stop + 1:] = 0
+    want = (qE[:-1] - qE[1:]) * N
+    assert np.all(np.abs(per_z - want) <= 2 * N), np.max(np.abs(per_z - want))
+    assert per_z[k_stop + 1:].sum() == 0
+
+
+def test_p1b_distal_80_percent_depth_vs_pstar(orc):
+    """Full physics, 100 MeV: R80 within 1 mm of PSTAR's CSDA range 7.718 cm."""
+    ph = water((20, 20, 100), (2.5, 2.5, 1.0), origin_mm=(-25.0, -25.0, 0.0))
+    plan = W.plan_single(100.0, 0.0, (0.0, 0.0, 50.0))
+    plan = with_xy(plan, 0.3, 0.2)
+    tallies, _, bal = orc.dose([ph], plan, 40_000, seed=3, n_threads=8)
+    check_balance(bal)
+    dd = tallies[0].reshape(100, 20, 20).sum(axis=(1, 2)).astype(float)
+    zc = (np.arange(100) + 0.5) * 0.1
+    kmax = int(np.argmax(dd))
+    level = 0.8 * dd[kmax]
+    k = kmax
+    while dd[k + 1] > level:
+        k += 1
+    r80 = zc[k] + (dd[k] - level) / (dd[k] - dd[k + 1]) * 0.1
+    assert abs(r80 - 7.718) < 0.1, r80
+
+
+# ----------------------------------------------------------------------------
+# P2/P3 multiple scattering
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("L_cm", [1.0, 5.0, 10.0])
+def test_p2_p3_highland_angle_and_lateral_spread(orc, L_cm):
+    E0 = 150.0
+    nz = int(round(L_cm / 0.1))
+    ph = water((1, 1, nz), (400.0, 400.0, 1.0), origin_mm=(-200.0, -200.0, 0.0))
+    plan = W.plan_single(E0, 0.0, (0.0, 0.0, 0.5 * nz))
+    flags = 16 | 1 | 4 | 8  # frozen, no straggling, no delta, no nuclear
+    n = 6000
+    ax = np.empty(n)
+    ex = np.empty(n)
+    for h in range(n):
+        tr = orc.trace(ph, plan, 0, h, seed=5, flags=flags)
+        last = tr[-1]
+        assert last["fate"] == orc.FATE_ESCAPED and last["r"][2] == pytest.approx(L_cm)
+        ax[h] = last["w"][0] / last["w"][2]
+        ex[h] = last["r"][0] - tr[0]["r"][0]
+    th0 = math.sqrt(highland_theta2(E0, L_cm))
+    rms = math.sqrt(np.mean(ax ** 2))
+    assert abs(rms / th0 - 1) < 3.5 / math.sqrt(2 * n), (rms, th0)
+    # Fermi-Eyges with the model's own increments: deflections at z_i = i dz
+    zi = np.arange(1, nz + 1) * 0.1
+    inc = np.array([highland_theta2(E0, z) - highland_theta2(E0, z - 0.1) for z in zi])
+    var_x = float(np.sum(inc * (L_cm - zi) ** 2))
+    if var_x > 0:
+        got = float(np.mean(ex ** 2))
+        assert abs(got / var_x - 1) < 4 * math.sqrt(2 / n) + 0.01, (got, var_x)
+
+
+# ----------------------------------------------------------------------------
+# P4 straggling, P5 delta production, P6 nuclear removal
+# ----------------------------------------------------------------------------
+
+def test_p4_soft_straggling_variance(orc):
+    from scipy import integrate
+    E0, L = 100.0, 1.0
+    ph = water((1, 1, 10), (400.0, 400.0, 1.0), origin_mm=(-200.0, -200.0, 0.0))
+    plan = W.plan_single(E0, 0.0, (0.0, 0.0, 5.0))
+    flags = 2 | 4 | 8
+    n = 20000
+    Ex = np.array([orc.trace(ph, plan, 0, h, seed=9, flags=flags)[-1]["E"] for h in range(n)])
+    R0 = orc.f64("orc_range", E0)
+    Emean = orc.f64("orc_range_inverse", R0 - L)
+    assert abs(Ex.mean() - Emean) < 4 * Ex.std() / math.sqrt(n) + 2e-3
+
+    def omega2(E):  # soft part of the PDG spectrum, second moment
+        beta2, pc = kin(E)
+        Etot = E + MP
+        gamma = Etot / MP
+        tmax = 2 * ME * beta2 * gamma ** 2 / (1 + 2 * gamma * ME / MP + (ME / MP) ** 2)
+        tup = min(0.1, tmax)
+        f = lambda T: T * T * 0.5 * 0.307075 * 0.555087 / beta2 * (1 - beta2 * T / tmax) / (T * T)
+        return integrate.quad(f, 0.0, tup)[0]
+
+    want = integrate.quad(lambda z: omega2(orc.f64("orc_range_inverse", R0 - z)), 0.0, L)[0]
+    got = Ex.var()
+    assert abs(got / want - 1) < 4 * math.sqrt(2 / n) + 0.03, (got, want)
+
+
+def test_p5_delta_production_rate(orc):
+    E0, L = 150.0, 5.0
+    ph = water((1, 1, 50), (400.0, 400.0, 1.0), origin_mm=(-200.0, -200.0, 0.0))
+    plan = W.plan_single(E0, 0.0, (0.0, 0.0, 25.0))
+    flags = 16 | 1 | 2 | 8  # frozen, delta only
+    n = 4000
+    _, _, bal = orc.dose([ph], plan, n, seed=13, flags=flags, n_threads=4, with_dose=False)
+    mu = orc.f64("orc_mu_delta", E0)  # pinned to the spectrum integral elsewhere
+    expect = mu * L * n
+    assert abs(bal["delta_events"] - expect) < 4 * math.sqrt(expect), (bal["delta_events"], expect)
+
+
+@pytest.mark.parametrize("hu,rho", [(0, 1.0), (1000, 1.62)])
+def test_p6_nuclear_attenuation(orc, hu, rho):
+    E0, L = 150.0, 10.0
+    ph = water((1, 1, 100), (400.0, 400.0, 1.0), origin_mm=(-200.0, -200.0, 0.0), hu=hu)
+    plan = W.plan_single(E0, 0.0, (0.0, 0.0, 50.0))
+    flags = 16 | 1 | 2 | 4  # frozen, nuclear only
+    n = 20000
+    _, _, bal = orc.dose([ph], plan, n, seed=17, flags=flags, n_threads=4, with_dose=False)
+    p = 1 - math.exp(-0.0115 * rho * L)
+    k = bal["nuclear_events"]
+    assert abs(k - n * p) < 4 * math.sqrt(n * p * (1 - p)), (k, n * p)
+    assert bal["nuclear_events"] + bal["escapes"] == n
+
+
+# ----------------------------------------------------------------------------
+# P7 energy balance
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("flags", [0, 1, 2, 4, 8, 1 | 2 | 4 | 8])
+def test_p7_energy_balance_exact(orc, flags):
+    wl = W.workload_slabs()
+    tallies, _, bal = orc.dose(wl.phases, wl.plan, 3000, seed=wl.seed, flags=flags, n_threads=8,
+                               with_dose=False)
+    check_balance(bal)
+    assert int(tallies[0].sum()) == bal["deposited"]
+    assert bal["histories"] == 3000
+
+
+def test_missing_the_grid_counts_as_escaped(orc):
+    ph = water((10, 10, 10), (1.0, 1.0, 1.0), origin_mm=(0.0, 0.0, 0.0))
+    plan = W.plan_single(100.0, 0.0, (50.0, 50.0, 5.0))  # ray along z at x=50 mm: outside
+    tallies, _, bal = orc.dose([ph], plan, 100, seed=1, n_threads=1)
+    assert bal["misses"] == 100 and bal["escaped"] == bal["incident"] and tallies[0].sum() == 0
+
+
+def test_external_mask_is_vacuum(orc):
+    ph = water((10, 10, 40), (2.0, 2.0, 2.0), origin_mm=(-10.0, -10.0, 0.0))
+    mask = np.ones_like(ph.hu, dtype=np.uint8)
+    mask[:20] = 0  # first 4 cm are outside the contour
+    ph.mask = mask
+    plan = W.plan_single(100.0, 0.0, (0.0, 0.0, 40.0))
+    tallies, doses, bal = orc.dose([ph], plan, 500, seed=2, n_threads=2)
+    check_balance(bal)
+    t = tallies[0].reshape(40, 10, 10)
+    assert t[:20].sum() == 0 and t[20:].sum() > 0
+    # in vacuum the proton does not scatter: it enters the tissue where it started
+    tr = orc.trace(ph, plan, 0, 3, seed=2)
+    first_tissue = [r for r in tr[1:] if r["voxel"] // 100 >= 20][0]
+    assert abs(first_tissue["r"][0] - tr[0]["r"][0]) < 1e-9
+
+
+# ----------------------------------------------------------------------------
+# P8 brute-force replay of single histories
+# ----------------------------------------------------------------------------
+
+def _u(words):
+    return [(int(x) + 0.5) / Q for x in words]
+
+
+def replay_history(orc, ph, plan, spot, h, seed, request_id=0):
+    """Recompute every step of one history in plain Python and compare with
+    the oracle's trace record by record."""
+    tr = orc.trace(ph, plan, spot, h, seed=seed, request_id=request_id)
+    key = [seed & 0xFFFFFFFF, request_id]
+    sp = plan.spots[spot]
+    f = plan.fields[sp["field"]]
+    nx, ny, nz = ph.shape_xyz
+    d = np.array(ph.spacing_mm) * 0.1
+    nvec = np.array([nx, ny, nz])
+    w = np.array(f["direction"], float)
+    w /= np.linalg.norm(w)
+    u0 = _u(orc.philox([0, h, spot, 0], key))
+    rad = math.sqrt(-2 * math.log(u0[0]))
+    n_nuc, n_del = -math.log(u0[2]), -math.log(u0[3])
+    assert tr[0]["n_nuc"] == pytest.approx(n_nuc, rel=1e-13)
+    assert tr[0]["n_delta"] == pytest.approx(n_del, rel=1e-13)
+    bu = np.array(f["bev_u"], float)
+    bv = np.cross(w, bu)
+    p = 0.1 * (np.array(f["isocentre_mm"]) - np.array(ph.origin_mm)) \
+        + 0.1 * (sp["x_mm"] + sp["sigma_mm"] * rad * math.cos(2 * math.pi * u0[1])) * bu \
+        + 0.1 * (sp["y_mm"] + sp["sigma_mm"] * rad * math.sin(2 * math.pi * u0[1])) * bv
+    nvec_ext = nvec * d
+    if tr[0]["fate"] == orc.FATE_MISSED:
+        # the ray runs parallel to z outside the box's x/y extent
+        assert np.allclose(tr[0]["r"], p, atol=1e-12) and len(tr) == 1
+        assert np.any((p[:2] < 0) | (p[:2] >= nvec_ext[:2]))
+        return 0
+    # entry point lies on the line p + t w and on the grid box surface
+    r0 = tr[0]["r"]
+    t_ = np.dot(r0 - p, w)
+    assert np.allclose(p + t_ * w, r0, atol=1e-12)
+    ext = nvec * d
+    on_face = np.isclose(r0, 0.0, atol=1e-12) | np.isclose(r0, ext, atol=1e-12)
+    assert on_face.any()
+    E = float(sp["energy_MeV"])
+    r = r0.copy()
+    block = 1
+    L_acc = 0.0
+    n_steps_checked = 0
+    for rec in tr[1:]:
+        vox = int(rec["voxel"])
+        i, j, k = vox % nx, (vox // nx) % ny, vox // (nx * ny)
+        hu = int(ph.hu[k, j, i])
+        hu_c = min(max(hu, -1024), 3071)
+        rho = float(np.interp(hu_c, ph.calib_hu, ph.calib_rho))
+        rsp = float(np.interp(hu_c, ph.calib_hu, ph.calib_rsp))
+        assert rec["block"] >= block + 1
+        uu = _u(orc.philox([block, h, spot, 0], key))
+        s = rec["s"]
+        # the move is a straight segment along the pre-step direction
+        assert np.allclose(r + s * w, rec["r"], rtol=0, atol=1e-11)
+        if rec["cause"] == orc.CAUSE_GEO:
+            lo = np.array([i, j, k]) * d
+            assert np.any(np.isclose(rec["r"], lo, atol=1e-12) | np.isclose(rec["r"], lo + d, atol=1e-12))
+        R = orc.f64("orc_range", E)
+        assert s <= R / rsp * (1 + 1e-12)
+        if rec["cause"] == orc.CAUSE_PHYS:
+            assert s == pytest.approx(max(0.1 * R, 0.01) / rsp, rel=1e-12)
+        if rec["fate"] == orc.FATE_STOPPED:
+            Eafter = 0.0
+        else:
+            sw = rsp * s
+            g = math.sqrt(-2 * math.log(uu[0])) * math.cos(2 * math.pi * uu[1])
+            # omega2 is used as tabulated: linear in ln E between nodes
+            om2 = np.interp(math.log(E), np.log(np.array(orc.tables().e)), np.array(orc.tables().omega2))
+            dE = E - orc.f64("orc_range_inverse", R - sw) + math.sqrt(om2 * sw) * g
+            Eafter = E - min(max(dE, 0.0), E)
+            if rec["t_delta"] > 0:
+                Eafter -= rec["t_delta"]
+            if rec["fate"] == orc.FATE_ALIVE or rec["fate"] == orc.FATE_ESCAPED:
+                assert rec["E"] == pytest.approx(Eafter, rel=1e-10, abs=1e-10)
+        # scattering: the new direction makes the sampled polar angle with the old
+        if rec["fate"] == orc.FATE_ALIVE:
+            th2 = max(0.0, highland_theta2(E, L_acc + rho * s) - highland_theta2(E, L_acc))
+            theta = math.sqrt(th2) * math.sqrt(-2 * math.log(uu[2]))
+            cos_t = float(np.dot(w, rec["w"]))
+            assert cos_t == pytest.approx(math.cos(theta), abs=1e-12)
+        L_acc += rho * s
+        w = np.array(rec["w"])
+        r = np.array(rec["r"])
+        E = rec["E"]
+        block = int(rec["block"])
+        n_steps_checked += 1
+    return n_steps_checked
+
+
+def test_p8_brute_force_step_replay(orc):
+    ph = W.make_box((3, 3, 3), (4.0, 4.0, 4.0), 0, origin_mm=(-6.0, -6.0, 0.0))
+    ph.hu[:] = np.array([[[40, -700, 1000], [0, 40, -100], [2000, 0, 40]]] * 3, dtype=np.int16)
+    ph.hu[1] = -800
+    plan = W.plan_single(60.0, 3.0, (0.0, 0.0, 6.0))
+    total = 0
+    for h in range(12):
+        total += replay_history(orc, ph, plan, 0, h, seed=21)
+    assert total > 30
+
+
+# ----------------------------------------------------------------------------
+# P9 integer invariants
+# ----------------------------------------------------------------------------
+
+def test_p9_thread_count_invariance(orc):
+    wl = W.workload_slabs()
+    a, _, ba = orc.dose(wl.phases, wl.plan, 4000, seed=2, n_threads=1, with_dose=False)
+    b, _, bb = orc.dose(wl.phases, wl.plan, 4000, seed=2, n_threads=7, with_dose=False)
+    assert np.array_equal(a[0], b[0]) and ba == bb
+
+
+def test_p9_superposition_over_history_ranges(orc):
+    wl = W.workload_tiny()
+    full, _, bf = orc.dose(wl.phases, wl.plan, 3000, seed=1, n_threads=4, with_dose=False)
+    a, ba = orc.dose_subset(wl.phases, wl.plan, 3000, 1, 0, 1234, n_threads=4)
+    b, bb = orc.dose_subset(wl.phases, wl.plan, 3000, 1, 1234, 2**32 - 1, n_threads=4)
+    assert np.array_equal(full[0], a[0] + b[0])
+    assert ba["incident"] + bb["incident"] == bf["incident"]
+
+
+def test_p9_paper_3d_comparison_tests(orc):
+    """Sec. 2.E: (1) the same CT on every phase reproduces the static dose;
+    (2) a single phase carrying the whole plan is the static run."""
+    wl = W.workload_slabs()
+    static, _, bs = orc.dose(wl.phases, wl.plan, 5000, seed=2, n_threads=8, with_dose=False)
+    plan = W.Plan(wl.plan.fields.copy(), wl.plan.spots.copy())
+    plan.spots["phase"] = np.arange(len(plan.spots)) % 10
+    per_phase, _, b4 = orc.dose(wl.phases * 10, plan, 5000, seed=2, n_threads=8, with_dose=False)
+    assert np.array_equal(static[0], np.sum(per_phase, axis=0))
+    assert bs["incident"] == b4["incident"] and bs["deposited"] == b4["deposited"]
+    # only phase 3 requested and all spots on it
+    plan.spots["phase"] = 3
+    one, _, b1 = orc.dose(wl.phases * 10, plan, 5000, seed=2, phase_ids=[3], n_threads=8,
+                          with_dose=False)
+    assert np.array_equal(static[0], one[0])
+
+
+def test_dose_conversion_definition(orc):
+    ph = W.make_slabs()
+    t = np.arange(ph.hu.size, dtype=np.int64) * 977
+    dose, rho = orc.convert(ph, t, 1000)
+    V = 0.2 ** 3
+    k = 123457
+    hu = int(ph.hu.reshape(-1)[k])
+    r = float(np.interp(hu, W.CALIB_HU, W.CALIB_RHO))
+    assert rho[k] == pytest.approx(r, rel=1e-15)
+    assert dose[k] == pytest.approx(t[k] / Q * 1.602176634e-13 / (r * V * 1e-3) / 1000, rel=1e-14)
