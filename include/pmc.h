@@ -1,0 +1,212 @@
+/*
+ * pmc.h -- C ABI of libpmc, a Monte Carlo proton dose engine for AMD MI355X
+ * (gfx950).
+ *
+ * The engine is the hot path of a 4D dose calculator (Pepin et al.,
+ * arXiv:1809.03927): it transports the pencil-beam spots of a plan, split by
+ * a delivery simulation into sub-plans per breathing phase (Sec. 2.B), through
+ * one voxelised CT per phase with class II condensed-history transport, and
+ * returns dose and density per CT voxel on the CT grid (Sec. 2.C).  Dose is
+ * energy over mass (Eq. (4): E = rho v D).
+ *
+ * Conventions for every call:
+ *  - Units at this interface are mm and MeV; doses are Gy per history.
+ *  - Arrays are plain host pointers unless a name says "dev" (device pointers
+ *    on the context's device).  Voxel arrays are nx*ny*nz long, x fastest.
+ *  - Every input is validated before any device work and copied before the
+ *    call returns; the library keeps no caller pointer.  Outputs are written
+ *    only into caller-owned buffers and only on success.
+ *  - Return value: PMC_OK (0) or a negative PMC_E_* code; pmc_last_error()
+ *    then describes the failure.  One context per host thread.
+ */
+#ifndef PMC_H
+#define PMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define PMC_OK 0
+#define PMC_E_INVAL (-1)   /* bad argument: dims, NaN, calibration order, energy, weight, direction */
+#define PMC_E_NOPHASE (-2) /* a spot or request names a phase that is not loaded */
+#define PMC_E_BUDGET (-3)  /* the request does not fit the context's device-memory budget */
+#define PMC_E_DEVICE (-4)  /* HIP runtime failure, or no device (validation-only context) */
+#define PMC_E_RANGE (-5)   /* more than PMC_MAX_HISTORIES histories in one tally */
+#define PMC_E_STATE (-6)   /* call out of order (e.g. pmc_dose before pmc_load_spots) */
+
+#define PMC_MAX_HISTORIES 50000000ull /* int64 headroom of one voxel tally */
+#define PMC_E_MIN_MEV 1.0
+#define PMC_E_MAX_MEV 300.0
+#define PMC_MAX_PHASES 64   /* phases in one request */
+
+/* ---- precision ---------------------------------------------------------- */
+#define PMC_FP32 0 /* production transport in single precision */
+#define PMC_FP64 1 /* debug transport in double precision (trace parity) */
+
+/* ---- request flags (physics switches for validation; the random-number
+ *      draw schedule never depends on them) --------------------------------*/
+#define PMC_NO_STRAGGLING 1u
+#define PMC_NO_MCS 2u
+#define PMC_NO_DELTA 4u
+#define PMC_NO_NUCLEAR 8u
+#define PMC_FROZEN 16u /* energy never changes (validation of scattering) */
+
+/* ---- engines ------------------------------------------------------------ */
+#define PMC_ENGINE_PLAIN 0      /* one launch per phase, one history per thread */
+#define PMC_ENGINE_PERSISTENT 1 /* one launch for all phases: work queue + lane refill */
+
+typedef struct pmc_context pmc_context;
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal; -1 = validation-only context */
+  int32_t precision;         /* PMC_FP32 or PMC_FP64 */
+  uint64_t seed;             /* Philox key word 0 is seed mod 2^32 */
+  uint64_t hbm_budget_bytes; /* 0: 90 % of the device memory free at creation */
+} pmc_config;
+
+/* A treatment field: isocentre (mm, CT frame), beam direction and the
+ * beam's-eye-view axis u (both unit vectors, orthogonal to 1e-6); the second
+ * BEV axis is v = direction x u. */
+typedef struct {
+  double isocentre_mm[3];
+  double direction[3];
+  double bev_u[3];
+} pmc_field;
+
+/* A plan spot (Appendix A: position, energy, weight), with the breathing
+ * phase the delivery simulation assigned it to (Sec. 2.B) and its field. */
+typedef struct {
+  double energy_MeV; /* [1, 300] */
+  double x_mm, y_mm; /* BEV position at the isocentre plane */
+  double sigma_mm;   /* Gaussian lateral sigma, >= 0 */
+  double weight;     /* > 0; histories are split in proportion */
+  int32_t phase;     /* phase id as given to pmc_load_phase */
+  int32_t field;     /* index into the fields array */
+} pmc_spot;
+
+typedef struct {
+  uint32_t request_id;    /* Philox key word 1 */
+  uint32_t flags;         /* PMC_NO_* / PMC_FROZEN */
+  uint64_t n_histories;   /* total over the spots of the listed phases, 1..PMC_MAX_HISTORIES */
+  const int32_t *phases;  /* phase ids to simulate (spots of other phases are skipped) */
+  int32_t n_phases;       /* 1..PMC_MAX_PHASES, distinct, all loaded */
+  int32_t engine;         /* PMC_ENGINE_* */
+  int32_t block_size;     /* threads per block; 0 = library default (64..1024, multiple of 64) */
+  int32_t chunk;          /* persistent engine: histories per work item; 0 = default */
+  int32_t refill_min;     /* persistent engine: refill when >= this many lanes of a wave are idle (1..64); 0 = default */
+  int32_t grid_blocks;    /* persistent engine: blocks; 0 = enough to fill the device */
+} pmc_request;
+
+/* Energy balance of a run.  128-bit unsigned totals as (lo, hi) words, in
+ * units of 2^-32 MeV: deposited + escaped + nuclear == incident exactly. */
+typedef struct {
+  uint64_t incident[2], deposited[2], escaped[2], nuclear[2], cutoff[2];
+  uint64_t histories, steps, delta_events, nuclear_events, escapes, misses;
+} pmc_balance;
+
+/* One record of a per-step trace (pmc_trace); positions in cm relative to
+ * the grid corner; cause: -1 source, 0 stop, 1 boundary, 2 delta, 3 nuclear,
+ * 4 step limit; fate: 0 alive, 1 stopped, 2 escaped, 3 nuclear, 4 missed. */
+typedef struct {
+  int32_t cause, voxel, fate;
+  uint32_t block;
+  double s, E, r[3], w[3], n_delta, n_nuc, l_acc;
+  int64_t dep;
+  double t_delta;
+} pmc_trace_rec;
+
+/* Number of uint64 words of the device counter block used by pmc_dose_device. */
+#define PMC_COUNTERS 16
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on cfg->device.  device = -1 gives a validation-only
+ * context: every argument check works, calls that need a GPU return
+ * PMC_E_DEVICE.  *out is set only on success. */
+int pmc_create(const pmc_config *cfg, pmc_context **out);
+
+/* Free the context and all device memory it owns.  NULL-safe. */
+void pmc_destroy(pmc_context *ctx);
+
+/* Message of the last failed call on ctx (empty if none); owned by ctx and
+ * valid until the next call on it.  ctx may be NULL (then a static message). */
+const char *pmc_last_error(const pmc_context *ctx);
+
+/* ---- inputs --------------------------------------------------------------- */
+
+/* Load (or replace) CT phase `phase` (0..1023): HU grid, geometry and the
+ * piecewise-linear HU -> mass density and HU -> stopping-power-ratio
+ * calibration (Sec. 2.C: HU converted to density inside the engine).
+ * calib_hu is strictly increasing, n_nodes >= 2, densities and RSPs >= 0.
+ * HU values are clamped to [-1024, 3071].  external_mask (nullable, 0/1 per
+ * voxel) bounds transport (Sec. 2.A): voxels outside it are vacuum.
+ * The HU grid stays resident on the device until replaced or unloaded. */
+int pmc_load_phase(pmc_context *ctx, int32_t phase, const int16_t *hu, int32_t nx, int32_t ny,
+                   int32_t nz, const double spacing_mm[3], const double origin_mm[3],
+                   const double *calib_hu, const double *calib_density, const double *calib_rsp,
+                   int32_t n_nodes, const uint8_t *external_mask);
+
+/* Free the device copy of a loaded phase. */
+int pmc_unload_phase(pmc_context *ctx, int32_t phase);
+
+/* Replace the plan: fields and spots (with their phase indices). */
+int pmc_load_spots(pmc_context *ctx, const pmc_field *fields, int32_t n_fields,
+                   const pmc_spot *spots, int64_t n_spots);
+
+/* ---- dose ------------------------------------------------------------------ */
+
+/* Simulate req->n_histories histories over the spots of the listed phases
+ * and return, for each listed phase i, the dose grid dose_out[i] (Gy per
+ * history, nx*ny*nz doubles; NULL entries skipped), optionally the raw
+ * tally tally_out[i] (int64, 2^-32 MeV) and the density grid density_out[i]
+ * (g/cm^3), and the energy balance.  Blocks until done. */
+int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
+             int64_t *const *tally_out, double *const *density_out, pmc_balance *balance_out);
+
+/* Device variant for callers that own device memory and streams: enqueue the
+ * transport of `req` on `stream` (a hipStream_t; NULL = default stream),
+ * ADDING into the caller's zero-initialised int64 tallies dev_tally[i] (one
+ * per listed phase, nx*ny*nz each) and into dev_counters (PMC_COUNTERS
+ * uint64 words, nullable).  Returns after enqueueing; the scratch it uses is
+ * owned by the context and reused by its next call, so calls on one context
+ * must not overlap in time.  Read the counters with pmc_balance_from_counters. */
+int pmc_dose_device(pmc_context *ctx, const pmc_request *req, void *stream,
+                    int64_t *const *dev_tally, uint64_t *dev_counters);
+
+/* Turn a device counter block (copied to the host) plus the request into a
+ * pmc_balance; the deposited total is taken from the tallies' sum, passed as
+ * a 128-bit (lo, hi) pair. */
+int pmc_balance_from_counters(pmc_context *ctx, const pmc_request *req, const uint64_t *counters,
+                              const uint64_t deposited[2], pmc_balance *out);
+
+/* Convert one device tally of `phase` into dose (Gy per history) and density
+ * on `stream` (dev_dose / dev_density: nx*ny*nz doubles, nullable). */
+int pmc_convert_device(pmc_context *ctx, int32_t phase, const int64_t *dev_tally,
+                       uint64_t n_histories, void *stream, double *dev_dose, double *dev_density);
+
+/* ---- validation hooks ------------------------------------------------------ */
+
+/* Per-step trace of one history (spot index, history index within the spot)
+ * of the loaded plan on one phase, computed by the GPU transport in the
+ * context's precision.  Writes at most max_rec records and sets *n_rec to the
+ * full length. */
+int pmc_trace(pmc_context *ctx, int32_t phase, int64_t spot, uint32_t history,
+              uint32_t request_id, uint32_t flags, pmc_trace_rec *out, int32_t max_rec,
+              int32_t *n_rec);
+
+/* Histories per spot of a request (host computation, no device): split
+ * n_histories over the spots whose phase is listed, in proportion to weight
+ * with the largest-remainder method, ties to the lower spot index. */
+int pmc_split_histories(const pmc_spot *spots, int64_t n_spots, const int32_t *phases,
+                        int32_t n_phases, uint64_t n_histories, int64_t *per_spot);
+
+/* Device memory held by the context (phases, tables, scratch), in bytes. */
+uint64_t pmc_bytes_in_use(const pmc_context *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMC_H */

@@ -107,7 +107,7 @@ def lib():
         L.orc_dose_subset.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                       C.c_int64, C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
                                       C.c_uint64, C.c_uint32, C.c_int32, C.c_uint32, C.c_uint32,
-                                      C.c_void_p, C.c_void_p]
+                                      C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]
         L.orc_trace.restype = C.c_int
         L.orc_trace.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
                                 C.c_int64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -200,8 +200,9 @@ def dose(phases, plan, n_hist: int, seed: int, request_id: int = 0, phase_ids=No
 
 
 def dose_subset(phases, plan, n_hist: int, seed: int, h_begin: int, h_end: int, request_id=0,
-                phase_ids=None, flags=0, n_threads=None):
-    """Tallies of only the histories with index in [h_begin, h_end) within each spot."""
+                phase_ids=None, flags=0, n_threads=None, h_mod=1, h_rem=0):
+    """Tallies of only the histories h (index within each spot's share) with
+    h_begin <= h < h_end and h % h_mod == h_rem."""
     if phase_ids is None:
         phase_ids = list(range(len(phases)))
     if n_threads is None:
@@ -216,11 +217,24 @@ def dose_subset(phases, plan, n_hist: int, seed: int, h_begin: int, h_end: int, 
     rc = lib().orc_dose_subset(parr, len(phases), fields.ctypes.data, len(fields),
                                spots.ctypes.data, len(spots), ids.ctypes.data, len(ids), int(seed),
                                int(request_id), int(n_hist), int(flags), int(n_threads),
-                               int(h_begin), int(h_end), tp, C.byref(bal))
+                               int(h_begin), int(h_end), int(h_mod), int(h_rem), tp,
+                               C.byref(bal))
     if rc:
         raise ValueError(f"orc_dose_subset failed: {rc}")
     del holders
     return tallies, bal.as_dict()
+
+
+def dose_batches(phases, plan, n_hist: int, seed: int, n_batches=10, request_id=0, phase_ids=None,
+                 flags=0, n_threads=None):
+    """Per-batch tallies, batch = history index mod n_batches; their sum is
+    the full run and their spread gives the per-voxel statistical error."""
+    out = []
+    for b in range(n_batches):
+        t, _ = dose_subset(phases, plan, n_hist, seed, 0, 2**32 - 1, request_id, phase_ids, flags,
+                           n_threads, h_mod=n_batches, h_rem=b)
+        out.append(t)
+    return out
 
 
 def trace(phase, plan, spot: int, h: int, seed: int, request_id: int = 0, flags: int = 0,

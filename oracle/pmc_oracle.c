@@ -431,6 +431,8 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
       double s_phys = dist(fmax(EPS_R * R, S_FLOOR), rsp);
       double d_del = dist(n_delta, mud * rsp);
       double d_nuc = dist(n_nuc, mun * rho);
+      if (d_del < 0.0) d_del = 0.0; /* rounding can leave a counter a hair below 0 */
+      if (d_nuc < 0.0) d_nuc = 0.0;
       s = s_stop;
       cause = ORC_CAUSE_STOP;
       if (dgeo < s) { s = dgeo; cause = ORC_CAUSE_GEO; }
@@ -598,7 +600,7 @@ typedef struct {
   int64_t n_spots;
   int64_t *const *tallies;
   uint64_t seed;
-  uint32_t request_id, flags, h_begin, h_end;
+  uint32_t request_id, flags, h_begin, h_end, h_mod, h_rem;
   int64_t g_begin, g_end;       /* range of the flattened history list */
   acc_t acc;
 } job_t;
@@ -628,7 +630,7 @@ static void *job_run(void *arg) {
     int64_t g1 = e < j->g_end ? e : j->g_end;
     for (int64_t g = g0; g < g1; ++g) {
       uint32_t h = (uint32_t)(g - a);
-      if (h < j->h_begin || h >= j->h_end) continue;
+      if (h < j->h_begin || h >= j->h_end || h % j->h_mod != j->h_rem) continue;
       transport(&c, s, h, j->tallies[slot], &j->acc, NULL, 0, NULL);
     }
   }
@@ -644,7 +646,9 @@ static int run_common(const orc_phase *phases, int32_t n_phases, const orc_field
                       int32_t n_fields, const orc_spot *spots, int64_t n_spots,
                       const int32_t *phase_ids, int32_t n_req_phases, uint64_t seed,
                       uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
-                      uint32_t h_begin, uint32_t h_end, int64_t *const *tallies, orc_balance *bal) {
+                      uint32_t h_begin, uint32_t h_end, uint32_t h_mod, uint32_t h_rem,
+                      int64_t *const *tallies, orc_balance *bal) {
+  if (h_mod == 0 || h_rem >= h_mod) return -1;
   if (n_phases <= 0 || n_req_phases <= 0 || n_spots <= 0 || n_hist == 0) return -1;
   for (int32_t i = 0; i < n_req_phases; ++i)
     if (phase_ids[i] < 0 || phase_ids[i] >= n_phases) return -1;
@@ -669,7 +673,7 @@ static int run_common(const orc_phase *phases, int32_t n_phases, const orc_field
     j->phases = phases; j->fields = fields; j->spots = spots; j->slot_of_spot = slot;
     j->phase_ids = phase_ids; j->offset = offset; j->count = count; j->n_spots = n_spots;
     j->tallies = tallies; j->seed = seed; j->request_id = request_id; j->flags = flags;
-    j->h_begin = h_begin; j->h_end = h_end;
+    j->h_begin = h_begin; j->h_end = h_end; j->h_mod = h_mod; j->h_rem = h_rem;
     j->g_begin = total * t / n_threads;
     j->g_end = total * (t + 1) / n_threads;
   }
@@ -702,7 +706,8 @@ int orc_dose(const orc_phase *phases, int32_t n_phases, const orc_field *fields,
              uint64_t seed, uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
              int64_t *const *tallies, double *const *dose, orc_balance *bal) {
   int rc = run_common(phases, n_phases, fields, n_fields, spots, n_spots, phase_ids, n_req_phases,
-                      seed, request_id, n_hist, flags, n_threads, 0u, 0xffffffffu, tallies, bal);
+                      seed, request_id, n_hist, flags, n_threads, 0u, 0xffffffffu, 1u, 0u, tallies,
+                      bal);
   if (rc) return rc;
   if (dose)
     for (int32_t i = 0; i < n_req_phases; ++i)
@@ -714,9 +719,11 @@ int orc_dose_subset(const orc_phase *phases, int32_t n_phases, const orc_field *
                     int32_t n_fields, const orc_spot *spots, int64_t n_spots,
                     const int32_t *phase_ids, int32_t n_req_phases, uint64_t seed,
                     uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
-                    uint32_t h_begin, uint32_t h_end, int64_t *const *tallies, orc_balance *bal) {
+                    uint32_t h_begin, uint32_t h_end, uint32_t h_mod, uint32_t h_rem,
+                    int64_t *const *tallies, orc_balance *bal) {
   return run_common(phases, n_phases, fields, n_fields, spots, n_spots, phase_ids, n_req_phases,
-                    seed, request_id, n_hist, flags, n_threads, h_begin, h_end, tallies, bal);
+                    seed, request_id, n_hist, flags, n_threads, h_begin, h_end, h_mod, h_rem,
+                    tallies, bal);
 }
 
 int orc_trace(const orc_phase *phase, const orc_field *fields, int32_t n_fields,

@@ -113,13 +113,15 @@ int orc_dose(const orc_phase *phases, int32_t n_phases, const orc_field *fields,
              uint64_t seed, uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
              int64_t *const *tallies, double *const *dose, orc_balance *bal);
 
-/* Same as orc_dose but only for the histories [h_begin, h_end) of each spot
- * (clipped to the spot's share); used for sampled comparisons at full size. */
+/* Same as orc_dose but only for the histories h of each spot (index within
+ * the spot's share) with h_begin <= h < h_end and h % h_mod == h_rem: samples
+ * of a full-size run, and the history batches of the statistical error. */
 int orc_dose_subset(const orc_phase *phases, int32_t n_phases, const orc_field *fields,
                     int32_t n_fields, const orc_spot *spots, int64_t n_spots,
                     const int32_t *phase_ids, int32_t n_req_phases, uint64_t seed,
                     uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
-                    uint32_t h_begin, uint32_t h_end, int64_t *const *tallies, orc_balance *bal);
+                    uint32_t h_begin, uint32_t h_end, uint32_t h_mod, uint32_t h_rem,
+                    int64_t *const *tallies, orc_balance *bal);
 
 /* Per-step trace of one history (spot index, history index within spot).
  * Returns the number of records written (<= max_rec) or a negative error. */

@@ -1,0 +1,590 @@
+// Device side of libpmc: precision policy, Philox4x32-10, per-lane proton
+// state and the condensed-history step shared by every transport kernel.
+//
+// One history per lane.  The step follows the class II scheme of the design
+// notes: restricted-stopping continuous loss through the range table,
+// Gaussian soft straggling, explicit hard delta rays absorbed locally,
+// telescoping Highland scattering and nuclear removal, with the dose tallied
+// as int64 fixed-point (2^-32 MeV) so that the result does not depend on the
+// order of the atomic updates (the paper sums energy with atomics, Sec. 2.D.2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pmc_internal.hpp"
+
+namespace pmc {
+
+// ---------------------------------------------------------------------------
+// constants of the transport model
+// ---------------------------------------------------------------------------
+constexpr double kMe = 0.51099895;
+constexpr double kMp = 938.27208816;
+constexpr double kX0 = 36.08;
+constexpr double kElo = 1.0;
+constexpr double kEhi = 300.0;
+constexpr double kTcut = 0.1;
+constexpr double kMuN = 0.0115;
+constexpr double kEn = 10.0;
+constexpr double kEpsR = 0.1;
+constexpr double kSfloor = 0.01;
+constexpr int kNtab = 1024;
+constexpr int kLutSize = 4096;  // integer HU -1024 .. 3071
+constexpr int kHuMin = -1024;
+constexpr int kHuMax = 3071;
+constexpr uint32_t kMaxSteps = 1u << 20;
+
+enum : uint32_t {
+  kNoStraggling = 1u, kNoMcs = 2u, kNoDelta = 4u, kNoNuclear = 8u, kFrozen = 16u
+};
+enum : int { kStop = 0, kGeo = 1, kDelta = 2, kNuc = 3, kPhys = 4 };
+enum : int { kAlive = 0, kStopped = 1, kEscaped = 2, kNuclear = 3, kMissed = 4 };
+
+// counter block layout (uint64 words)
+enum : int {
+  kCEscLo = 0, kCEscHi, kCNucLo, kCNucHi, kCCutLo, kCCutHi,
+  kCHist, kCSteps, kCDelta, kCNucEv, kCEscapes, kCMisses, kCCursor, kCSpare0, kCSpare1, kCSpare2
+};
+
+// ---------------------------------------------------------------------------
+// precision policy
+// ---------------------------------------------------------------------------
+template <typename R> struct M;
+
+template <> struct M<float> {
+  using R2 = float2;
+  using R4 = float4;
+  static __device__ __forceinline__ float log2(float x) { return __builtin_amdgcn_logf(x); }
+  static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  // cos / sin of 2 pi u for u in [0, 1): the hardware takes revolutions
+  static __device__ __forceinline__ float cos_rev(float u) { return __builtin_amdgcn_cosf(u); }
+  static __device__ __forceinline__ float sin_rev(float u) { return __builtin_amdgcn_sinf(u); }
+  static __device__ __forceinline__ float uni(uint32_t x) {
+    return ((float)(x >> 8) + 0.5f) * 0x1p-24f;
+  }
+  // fixed-point energy: E * 2^32 is an integer for any float E >= 2^-9
+  static __device__ __forceinline__ long long q(float E) { return (long long)(E * 4294967296.0f); }
+  static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
+  static __device__ __forceinline__ float fmax(float a, float b) { return __builtin_fmaxf(a, b); }
+  static __device__ __forceinline__ float fmin(float a, float b) { return __builtin_fminf(a, b); }
+};
+
+template <> struct M<double> {
+  using R2 = double2;
+  using R4 = double4;
+  static __device__ __forceinline__ double log2(double x) { return ::log2(x); }
+  static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
+  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+  static __device__ __forceinline__ double cos_rev(double u) {
+    return ::cos(6.283185307179586476925286766559 * u);
+  }
+  static __device__ __forceinline__ double sin_rev(double u) {
+    return ::sin(6.283185307179586476925286766559 * u);
+  }
+  static __device__ __forceinline__ double uni(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
+  static __device__ __forceinline__ long long q(double E) { return __double2ll_rn(E * 4294967296.0); }
+  static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
+  static __device__ __forceinline__ double fmax(double a, double b) { return __builtin_fmax(a, b); }
+  static __device__ __forceinline__ double fmin(double a, double b) { return __builtin_fmin(a, b); }
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// ---------------------------------------------------------------------------
+// per-lane state
+// ---------------------------------------------------------------------------
+template <typename R> struct Lane {
+  R l[3];         // position inside the current voxel, cm, in [0, d]
+  R w[3];         // direction
+  R E;            // kinetic energy, MeV
+  R nd, nn;       // remaining delta / nuclear interaction lengths (mean free paths)
+  R lacc;         // accumulated mass path for scattering, g/cm^2
+  int32_t ix, iy, iz;
+  int32_t v;      // linear voxel index
+  int32_t hu;     // HU of the current voxel (clamped LUT index)
+  int32_t vac;    // current voxel outside the external mask
+  uint32_t b;     // next Philox block
+  uint32_t h;     // history index within the spot
+  int32_t spot;
+  int32_t fate;   // kAlive while transported
+  uint32_t nsteps;
+  int32_t acc_v;  // merged tally: voxel and energy not yet added
+  long long acc;
+};
+
+// per-lane totals reduced at kernel end
+struct LaneCounters {
+  unsigned long long esc, nuc, cut;
+  uint32_t hist, steps, delta, nuc_ev, escapes, misses;
+};
+
+// geometry of the phase a lane is in
+template <typename R> struct Geo {
+  const int16_t *hu;
+  const uint8_t *mask;
+  unsigned long long *tally;
+  int32_t n[3];
+  int32_t nxy;
+  R d[3];
+};
+
+// physics tables: (R, mu_delta, omega^2, 0) per node, linear in log2 E
+template <typename R> struct Tab {
+  const typename M<R>::R4 *t;  // kNtab entries (LDS or global)
+  R l2e0, inv_dl2, dl2;
+};
+
+// Axis selection on values, never through a pointer: a select of addresses
+// into the lane state would keep that state out of registers.
+template <typename T>
+__device__ __forceinline__ T pick3(T x0, T x1, T x2, int k) {
+  return k == 0 ? x0 : (k == 1 ? x1 : x2);
+}
+template <typename T>
+__device__ __forceinline__ void set3(T &x0, T &x1, T &x2, int k, T v) {
+  x0 = k == 0 ? v : x0;
+  x1 = k == 1 ? v : x1;
+  x2 = k == 2 ? v : x2;
+}
+
+__device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// table lookups
+// ---------------------------------------------------------------------------
+template <typename R> struct Lookup { R R_, mud, om2; int i; };
+
+template <typename R>
+__device__ __forceinline__ Lookup<R> lookup(const Tab<R> &T, R E) {
+  const R x = (M<R>::log2(E) - T.l2e0) * T.inv_dl2;
+  int i = (int)x;  // x >= 0 for E >= E_lo
+  i = i < 0 ? 0 : (i > kNtab - 2 ? kNtab - 2 : i);
+  const R f = x - (R)i;
+  const auto a = T.t[i], b = T.t[i + 1];
+  Lookup<R> o;
+  o.R_ = a.x + f * (b.x - a.x);
+  o.mud = a.y + f * (b.y - a.y);
+  o.om2 = a.z + f * (b.z - a.z);
+  o.i = i;
+  return o;
+}
+
+// exact inverse of the piecewise-linear range table; Rn < R(E) so the
+// interval is at or below the current node i
+template <typename R>
+__device__ __forceinline__ R range_inverse(const Tab<R> &T, R Rn, int i) {
+  if (!(Rn > (R)0)) return (R)kElo;
+  int lo = i;
+  R rlo = T.t[lo].x;
+  while (lo > 0 && rlo > Rn) {
+    --lo;
+    rlo = T.t[lo].x;
+  }
+  const R rhi = T.t[lo + 1].x;
+  const R f = (Rn - rlo) / (rhi - rlo);
+  return M<R>::exp2(T.l2e0 + T.dl2 * ((R)lo + f));
+}
+
+template <typename R> struct Kin { R beta2, tmax, pbc; };
+
+template <typename R>
+__device__ __forceinline__ Kin<R> kinematics(R E) {
+  const R tau = E * (R)(1.0 / kMp);
+  const R g = (R)1 + tau;
+  const R b2g2 = tau * (tau + (R)2);
+  const R r = (R)(kMe / kMp);
+  Kin<R> k;
+  k.beta2 = b2g2 / (g * g);
+  k.tmax = (R)(2.0 * kMe) * b2g2 / ((R)1 + (R)2 * g * r + r * r);
+  k.pbc = E * (E + (R)(2.0 * kMp)) / (E + (R)kMp);
+  return k;
+}
+
+// Highland projected-angle variance for mass path L at the given kinematics
+template <typename R>
+__device__ __forceinline__ R highland2(const Kin<R> &k, R L) {
+  if (!(L > (R)0)) return (R)0;
+  const R x = L * (R)(1.0 / kX0);
+  // ln(x / beta^2) via log2
+  const R c = (R)1 + (R)(0.038 * 0.69314718055994530942) * M<R>::log2(x / k.beta2);
+  const R a = (R)13.6 / k.pbc;
+  return a * a * x * c * c;
+}
+
+// polar rotation of the unit direction w by (theta, phi = 2 pi u_phi)
+template <typename R>
+__device__ __forceinline__ void rotate(R w[3], R theta, R u_phi) {
+  R ct, st;
+  if constexpr (sizeof(R) == 4) {
+    if (theta < 0.5f) {  // Taylor series: relative error below 1e-8 here
+      const float t2 = theta * theta;
+      st = theta * (1.0f - t2 * (1.0f / 6.0f) * (1.0f - t2 * (1.0f / 20.0f) * (1.0f - t2 * (1.0f / 42.0f))));
+      ct = 1.0f - t2 * 0.5f * (1.0f - t2 * (1.0f / 12.0f) * (1.0f - t2 * (1.0f / 30.0f) * (1.0f - t2 * (1.0f / 56.0f))));
+    } else {
+      ct = __builtin_amdgcn_cosf(theta * 0.15915494309189533577f);
+      st = __builtin_amdgcn_sinf(theta * 0.15915494309189533577f);
+    }
+  } else {
+    ct = ::cos(theta);
+    st = ::sin(theta);
+  }
+  const R cp = M<R>::cos_rev(u_phi), sp = M<R>::sin_rev(u_phi);
+  const R a = w[0], b = w[1], c = w[2];
+  const R den2 = a * a + b * b;
+  R na, nb, nc;
+  if (den2 < (R)1e-20) {
+    na = st * cp;
+    nb = st * sp;
+    nc = (c >= (R)0 ? (R)1 : (R)-1) * ct;
+  } else {
+    const R den = M<R>::sqrt(den2);
+    const R inv = M<R>::div((R)1, den);
+    na = a * ct + st * (a * c * cp - b * sp) * inv;
+    nb = b * ct + st * (b * c * cp + a * sp) * inv;
+    nc = c * ct - st * cp * den;
+  }
+  R nn = na * na + nb * nb + nc * nc;
+  R inv;
+  if constexpr (sizeof(R) == 4) inv = __builtin_amdgcn_rsqf(nn);
+  else inv = 1.0 / ::sqrt(nn);
+  w[0] = na * inv;
+  w[1] = nb * inv;
+  w[2] = nc * inv;
+}
+
+template <typename R>
+__device__ __forceinline__ int clamp_hu(int hu) {
+  hu = hu < kHuMin ? kHuMin : (hu > kHuMax ? kHuMax : hu);
+  return hu - kHuMin;
+}
+
+// ---------------------------------------------------------------------------
+// source: sample the lateral offset and interaction lengths, enter the grid
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void start_history(Lane<R> &L, const SpotDev<R> &sp, int32_t spot,
+                                              uint32_t h, const Geo<R> &G, uint32_t k0, uint32_t k1,
+                                              LaneCounters &C) {
+  const uint4 x = philox(0u, h, (uint32_t)spot, 0u, k0, k1);
+  const R u0 = M<R>::uni(x.x), u1 = M<R>::uni(x.y), u2 = M<R>::uni(x.z), u3 = M<R>::uni(x.w);
+  const R rad = M<R>::sqrt((R)-2 * ((R)0.69314718055994530942 * M<R>::log2(u0)));
+  const R gx = rad * M<R>::cos_rev(u1), gy = rad * M<R>::sin_rev(u1);
+  L.nn = (R)-0.69314718055994530942 * M<R>::log2(u2);
+  L.nd = (R)-0.69314718055994530942 * M<R>::log2(u3);
+  L.E = sp.E;
+  L.h = h;
+  L.spot = spot;
+  L.b = 1u;
+  L.lacc = (R)0;
+  L.nsteps = 0;
+  L.acc_v = -1;
+  L.acc = 0;
+  C.hist += 1;
+  const R a = sp.sigma * gx, bb = sp.sigma * gy;
+  R p[3], r[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    L.w[k] = sp.w[k];
+    p[k] = sp.c[k] + a * sp.u[k] + bb * sp.v[k];
+  }
+  // slab method on [0, n d)
+  R tn = -M<R>::inf(), tf = M<R>::inf();
+  int an = -1;
+  bool missed = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R ext = (R)G.n[k] * G.d[k];
+    if (L.w[k] != (R)0) {
+      const R t1 = ((R)0 - p[k]) / L.w[k], t2 = (ext - p[k]) / L.w[k];
+      const R lo = t1 < t2 ? t1 : t2, hi = t1 < t2 ? t2 : t1;
+      if (lo > tn) { tn = lo; an = k; }
+      if (hi < tf) tf = hi;
+    } else if (p[k] < (R)0 || p[k] >= ext) {
+      missed = true;
+    }
+  }
+  if (an < 0 || !(tn < tf)) missed = true;
+  // one exit path: every field is written exactly once below
+  int idx[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r[k] = p[k] + tn * L.w[k];
+    int i;
+    R l;
+    if (k == an) {
+      i = L.w[k] > (R)0 ? 0 : G.n[k] - 1;
+      l = L.w[k] > (R)0 ? (R)0 : G.d[k];
+    } else {
+      i = (int)floor(r[k] / G.d[k]);
+      i = i < 0 ? 0 : (i > G.n[k] - 1 ? G.n[k] - 1 : i);
+      l = r[k] - (R)i * G.d[k];
+    }
+    idx[k] = missed ? 0 : i;
+    L.l[k] = missed ? p[k] : l;
+  }
+  L.ix = idx[0];
+  L.iy = idx[1];
+  L.iz = idx[2];
+  const int v = idx[0] + G.n[0] * (idx[1] + G.n[1] * idx[2]);
+  L.v = missed ? -1 : v;
+  const int hu = G.hu[v];  // v is in range in both cases (0 when missed)
+  L.hu = clamp_hu<R>(hu);
+  L.vac = (G.mask && !missed) ? (G.mask[v] == 0) : 0;
+  L.fate = missed ? kMissed : kAlive;
+  if (missed) {
+    C.esc += (unsigned long long)M<R>::q(L.E);
+    C.misses += 1;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void flush_tally(Lane<R> &L, const Geo<R> &G) {
+  if (L.acc != 0) atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
+  L.acc = 0;
+  L.acc_v = -1;
+}
+
+template <typename R>
+__device__ __forceinline__ void add_tally(Lane<R> &L, const Geo<R> &G, int32_t v, long long dep) {
+  if (dep == 0) return;
+  if (v != L.acc_v) {
+    if (L.acc != 0) atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
+    L.acc_v = v;
+    L.acc = dep;
+  } else {
+    L.acc += dep;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void trace_out(TraceRec *rec, int n, int max_rec, int cause, int voxel,
+                                          const Lane<R> &L, const Geo<R> &G, R s, long long dep,
+                                          R t_delta) {
+  if (n >= max_rec) return;
+  TraceRec &o = rec[n];
+  o.cause = cause;
+  o.voxel = voxel;
+  o.fate = L.fate;
+  o.block = L.b;
+  o.s = (double)s;
+  o.E = L.fate == kStopped ? 0.0 : (double)L.E;
+  const int idx[3] = {L.ix, L.iy, L.iz};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    o.r[k] = (double)idx[k] * (double)G.d[k] + (double)L.l[k];
+    o.w[k] = (double)L.w[k];
+  }
+  o.n_delta = (double)L.nd;
+  o.n_nuc = (double)L.nn;
+  o.l_acc = (double)L.lacc;
+  o.dep = dep;
+  o.t_delta = (double)t_delta;
+}
+
+// ---------------------------------------------------------------------------
+// one condensed-history step
+// ---------------------------------------------------------------------------
+template <typename R, bool TRACE>
+__device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &T,
+                                     const typename M<R>::R2 *lut, uint32_t k0, uint32_t k1,
+                                     uint32_t flags, LaneCounters &C, TraceRec *rec, int max_rec) {
+  using MM = M<R>;
+  const R LN2 = (R)0.69314718055994530942;
+  // 1. material
+  const auto m = lut[L.hu];
+  const R rho = m.x, rsp = m.y;
+  const bool vac = L.vac != 0;
+
+  // 2. boundary distance (lowest axis wins ties) and prefetch of the neighbour
+  R dg = MM::inf();
+  int ax = -1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R wk = L.w[k];
+    if (wk != (R)0) {
+      R t = MM::div(wk > (R)0 ? (G.d[k] - L.l[k]) : -L.l[k], wk);
+      t = t < (R)0 ? (R)0 : t;
+      if (t < dg) { dg = t; ax = k; }
+    }
+  }
+  const bool ax_pos = pick3(L.w[0], L.w[1], L.w[2], ax) > (R)0;
+  const int idx_ax = pick3(L.ix, L.iy, L.iz, ax);
+  const int n_ax = pick3(G.n[0], G.n[1], G.n[2], ax);
+  const int nb_idx = idx_ax + (ax_pos ? 1 : -1);
+  const bool nb_in = nb_idx >= 0 && nb_idx < n_ax;
+  const int stride = pick3(1, G.n[0], G.nxy, ax);
+  const int v_nb = L.v + (ax_pos ? stride : -stride);
+  int hu_nb = 0, mask_nb = 1;
+  if (nb_in) {
+    hu_nb = G.hu[v_nb];
+    if (G.mask) mask_nb = G.mask[v_nb];
+  }
+
+  // 3-4. physics limits; priority on ties stop > geo > delta > nuclear > phys
+  R s = dg, Rr = 0, mud = 0, om2 = 0, mun = 0;
+  int ti = 0;
+  int cause = kGeo;
+  if (!vac) {
+    const Lookup<R> lk = lookup(T, L.E);
+    Rr = lk.R_;
+    mud = (flags & kNoDelta) ? (R)0 : lk.mud;
+    om2 = lk.om2;
+    ti = lk.i;
+    mun = (!(flags & kNoNuclear) && L.E >= (R)kEn) ? (R)kMuN : (R)0;
+    const R inv_rsp = MM::rcp(rsp);
+    const R s_stop = (flags & kFrozen) ? MM::inf() : (rsp > (R)0 ? Rr * inv_rsp : MM::inf());
+    const R s_phys = rsp > (R)0 ? MM::fmax((R)kEpsR * Rr, (R)kSfloor) * inv_rsp : MM::inf();
+    const R cd = mud * rsp, cn = mun * rho;
+    R d_d = cd > (R)0 ? MM::div(L.nd, cd) : MM::inf();
+    R d_n = cn > (R)0 ? MM::div(L.nn, cn) : MM::inf();
+    d_d = d_d < (R)0 ? (R)0 : d_d;
+    d_n = d_n < (R)0 ? (R)0 : d_n;
+    s = s_stop;
+    cause = kStop;
+    if (dg < s) { s = dg; cause = kGeo; }
+    if (d_d < s) { s = d_d; cause = kDelta; }
+    if (d_n < s) { s = d_n; cause = kNuc; }
+    if (s_phys < s) { s = s_phys; cause = kPhys; }
+  }
+  // one fresh block per step
+  const uint4 x = philox(L.b, L.h, (uint32_t)L.spot, 0u, k0, k1);
+  L.b += 1u;
+
+  // 5. move; a boundary step lands exactly on the face
+#pragma unroll
+  for (int k = 0; k < 3; ++k) L.l[k] += s * L.w[k];
+  const R d_ax = pick3(G.d[0], G.d[1], G.d[2], ax);
+  if (cause == kGeo) set3(L.l[0], L.l[1], L.l[2], ax, ax_pos ? d_ax : (R)0);
+
+  const R E_pre = L.E;
+  long long dep = 0;
+  R t_delta = 0;
+  const int v_step = L.v;
+  if (!vac) {
+    // 6. continuous loss with Gaussian soft straggling
+    if (!(flags & kFrozen)) {
+      if (cause == kStop) {
+        L.fate = kStopped;
+      } else {
+        const R sw = rsp * s;
+        const R g = (flags & kNoStraggling)
+                        ? (R)0
+                        : MM::sqrt((R)-2 * (LN2 * MM::log2(MM::uni(x.x)))) * MM::cos_rev(MM::uni(x.y));
+        R dE = (L.E - range_inverse(T, Rr - sw, ti)) + MM::sqrt(om2 * sw) * g;
+        dE = dE < (R)0 ? (R)0 : (dE > L.E ? L.E : dE);
+        const R En = L.E - dE;
+        if (En <= (R)kElo) L.fate = kStopped;
+        else L.E = En;
+      }
+    }
+    // 7. interaction lengths with pre-step coefficients
+    L.nd -= mud * rsp * s;
+    L.nn -= mun * rho * s;
+    if (cause == kDelta) L.nd = (R)0;
+    if (cause == kNuc) L.nn = (R)0;
+    // 8. telescoping Highland at the pre-step energy
+    const Kin<R> kp = kinematics(E_pre);
+    const R l_new = L.lacc + rho * s;
+    R th2 = highland2(kp, l_new) - highland2(kp, L.lacc);
+    th2 = th2 < (R)0 ? (R)0 : th2;
+    L.lacc = l_new;
+    if (L.fate == kAlive && !(flags & kNoMcs) && th2 > (R)0) {
+      const R theta = MM::sqrt(th2) * MM::sqrt((R)-2 * (LN2 * MM::log2(MM::uni(x.z))));
+      rotate(L.w, theta, MM::uni(x.w));
+    }
+    // 9. tally by telescoping fixed-point energy
+    if (L.fate == kStopped) {
+      dep = MM::q(E_pre);
+      C.cut += (unsigned long long)MM::q(E_pre);
+    } else {
+      dep = MM::q(E_pre) - MM::q(L.E);
+    }
+    // 10. events at the step end
+    if (L.fate == kAlive && cause == kDelta) {
+      const Kin<R> k = kinematics(L.E);
+      if (k.tmax > (R)kTcut) {
+        const R a = (R)(1.0 / kTcut), bt = (R)(1.0 / kTcut) - MM::div((R)1, k.tmax);
+        const R cb = MM::div(k.beta2, k.tmax);
+        R T_d = (R)kTcut;
+        // acceptance is >= 1/2 per trial; the bound only guarantees termination
+        for (int trial = 0; trial < 4096; ++trial) {
+          const uint4 y = philox(L.b, L.h, (uint32_t)L.spot, 0u, k0, k1);
+          L.b += 1u;
+          const R t1 = MM::div((R)1, a - MM::uni(y.x) * bt);
+          if (MM::uni(y.y) < (R)1 - cb * t1) { T_d = t1; break; }
+          const R t2 = MM::div((R)1, a - MM::uni(y.z) * bt);
+          if (MM::uni(y.w) < (R)1 - cb * t2) { T_d = t2; break; }
+        }
+        const R cap = L.E - (R)kElo;
+        T_d = T_d > cap ? cap : T_d;
+        t_delta = T_d;
+        C.delta += 1;
+        if (!(flags & kFrozen)) {
+          const R En = L.E - T_d;
+          dep += MM::q(L.E) - MM::q(En);
+          L.E = En;
+          if (L.E <= (R)kElo) {
+            dep += MM::q(L.E);
+            C.cut += (unsigned long long)MM::q(L.E);
+            L.fate = kStopped;
+          }
+        }
+      }
+      const uint4 y = philox(L.b, L.h, (uint32_t)L.spot, 0u, k0, k1);
+      L.b += 1u;
+      L.nd = -LN2 * MM::log2(MM::uni(y.x));
+    } else if (L.fate == kAlive && cause == kNuc) {
+      C.nuc += (unsigned long long)MM::q(L.E);
+      C.nuc_ev += 1;
+      L.fate = kNuclear;
+    }
+    add_tally(L, G, v_step, dep);
+  }
+  C.steps += 1;
+  L.nsteps += 1;
+  // 11. boundary crossing
+  if (L.fate == kAlive && cause == kGeo) {
+    if (!nb_in) {
+      C.esc += (unsigned long long)MM::q(L.E);
+      C.escapes += 1;
+      L.fate = kEscaped;
+    } else {
+      set3(L.ix, L.iy, L.iz, ax, nb_idx);
+      set3(L.l[0], L.l[1], L.l[2], ax, ax_pos ? (R)0 : d_ax);
+      L.v = v_nb;
+      L.hu = clamp_hu<R>(hu_nb);
+      L.vac = mask_nb == 0;
+    }
+  }
+  if (L.fate == kAlive && L.nsteps >= kMaxSteps) {  // safety valve, never reached by valid input
+    C.esc += (unsigned long long)MM::q(L.E);
+    C.escapes += 1;
+    L.fate = kEscaped;
+  }
+  if constexpr (TRACE) trace_out(rec, (int)L.nsteps, max_rec, cause, v_step, L, G, s, dep, t_delta);
+}
+
+}  // namespace pmc

@@ -1,0 +1,991 @@
+// C ABI of libpmc (include/pmc.h): argument validation, ownership of device
+// memory, the history split and work decomposition, kernel launches and the
+// energy balance.
+//
+// Inputs follow the paper's statement of the problem: a CT per breathing
+// phase with its HU -> density conversion (Sec. 2.C), an optional external
+// contour bounding transport (Sec. 2.A), and plan spots (position, energy,
+// weight; Appendix A) distributed over phases by the delivery simulation
+// (Sec. 2.B).  Outputs are dose and density per CT voxel (Sec. 2.C).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "pmc.h"
+#include "pmc_internal.hpp"
+
+using pmc::SpotDev;
+using pmc::TargetDev;
+using pmc::WorkItem;
+
+namespace {
+
+thread_local std::string g_error;  // message for failures without a context
+
+constexpr int kHuLo = -1024, kHuHi = 3071, kLut = 4096;
+constexpr int kMaxPhaseId = 1023;
+constexpr double kTwo32 = 4294967296.0;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+struct PhaseRec {
+  int32_t nx = 0, ny = 0, nz = 0;
+  double sp_mm[3] = {0, 0, 0}, org_mm[3] = {0, 0, 0};
+  std::vector<float> lut32;   // (rho, rsp) x 4096
+  std::vector<double> lut64;  // (rho, rsp) x 4096
+  bool has_mask = false;
+  uint64_t version = 0;
+  int16_t *d_hu = nullptr;
+  uint8_t *d_mask = nullptr;
+  void *d_lut32 = nullptr, *d_lut64 = nullptr;
+  size_t bytes = 0;
+  long long nvox() const { return (long long)nx * ny * nz; }
+};
+
+// Device-side data of a request that depends only on its inputs (plan,
+// phases, split); rebuilt when any of them changes.
+struct Prepared {
+  bool valid = false;
+  // signature
+  uint64_t plan_version = 0, n_hist = 0;
+  std::vector<int32_t> phases;
+  std::vector<uint64_t> phase_versions;
+  int32_t engine = -1, chunk = -1, precision = -1;
+  // host side
+  std::vector<int64_t> per_spot;
+  std::vector<std::vector<int32_t>> list;      // per slot: spots with histories
+  std::vector<std::vector<long long>> first;   // per slot: prefix offsets
+  std::vector<long long> slot_hist;
+  int32_t n_items = 0;
+  bool same_lut = true;
+  unsigned __int128 incident = 0;
+  // device offsets into the request scratch buffer
+  size_t off_spots = 0, off_items = 0, off_luts = 0, off_targets = 0;
+  std::vector<size_t> off_ids, off_first;
+  std::vector<unsigned char> staging;  // pinned copy uploaded into the scratch
+};
+
+}  // namespace
+
+struct pmc_context {
+  int device = -1;
+  int precision = PMC_FP32;
+  uint64_t seed = 0;
+  uint64_t budget = 0;
+  uint64_t used = 0;
+  bool has_device = false;
+  int n_cu = 0;
+  std::string err;
+  pmc::Tables tabs;
+  void *d_tab = nullptr;
+  size_t tab_bytes = 0;
+  std::map<int32_t, PhaseRec> phases;
+  uint64_t phase_counter = 0;
+  std::vector<pmc_field> fields;
+  std::vector<pmc_spot> spots;
+  bool have_plan = false;
+  uint64_t plan_version = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool pending = false;
+  DevBuf scratch;    // request data (spots, items, lists, targets, LUTs)
+  DevBuf cursor;     // work-queue cursor (one uint64)
+  DevBuf counters;   // internal counter block
+  Prepared prep;
+};
+
+namespace {
+
+int fail(pmc_context *ctx, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  else g_error = buf;
+  return code;
+}
+
+int hip_fail(pmc_context *ctx, hipError_t e, const char *what) {
+  return fail(ctx, PMC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, call, what)                      \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+bool finite3(const double v[3]) {
+  return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+double norm3(const double v[3]) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+// piecewise-linear calibration at an integer HU, clamped to the end nodes
+double calib_at(const double *x, const double *y, int n, double hu) {
+  if (hu <= x[0]) return y[0];
+  if (hu >= x[n - 1]) return y[n - 1];
+  int i = (int)(std::upper_bound(x, x + n, hu) - x) - 1;  // x[i] <= hu < x[i+1]
+  const double t = (hu - x[i]) / (x[i + 1] - x[i]);
+  return y[i] + (y[i + 1] - y[i]) * t;
+}
+
+// grow-only device buffer with budget accounting
+int ensure(pmc_context *ctx, DevBuf &b, size_t bytes, const char *what) {
+  if (b.cap >= bytes) return PMC_OK;
+  const size_t cap = std::max(bytes, b.cap + b.cap / 2);
+  if (ctx->used - b.cap + cap > ctx->budget)
+    return fail(ctx, PMC_E_BUDGET, "%s: %zu bytes exceed the device-memory budget (%llu in use of %llu)",
+                what, cap, (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
+  if (b.p) {
+    if (ctx->pending) (void)hipStreamSynchronize(ctx->last_stream);
+    ctx->pending = false;
+    (void)hipFree(b.p);
+    ctx->used -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  HIP_TRY(ctx, hipMalloc(&b.p, cap), what);
+  b.cap = cap;
+  ctx->used += cap;
+  return PMC_OK;
+}
+
+void release(pmc_context *ctx, DevBuf &b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    ctx->used -= b.cap;
+  }
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+void free_phase(pmc_context *ctx, PhaseRec &p) {
+  if (p.d_hu) (void)hipFree(p.d_hu);
+  if (p.d_mask) (void)hipFree(p.d_mask);
+  if (p.d_lut32) (void)hipFree(p.d_lut32);
+  if (p.d_lut64) (void)hipFree(p.d_lut64);
+  ctx->used -= p.bytes;
+  p.d_hu = nullptr;
+  p.d_mask = nullptr;
+  p.d_lut32 = p.d_lut64 = nullptr;
+  p.bytes = 0;
+}
+
+void wait_pending(pmc_context *ctx) {
+  if (ctx->pending) (void)hipStreamSynchronize(ctx->last_stream);
+  ctx->pending = false;
+}
+
+long long q_working(const pmc_context *ctx, double E) {
+  if (ctx->precision == PMC_FP32) return (long long)std::ldexp((double)(float)E, 32);
+  return std::llrint(E * kTwo32);
+}
+
+int split(const pmc_spot *spots, int64_t n_spots, const int32_t *phases, int32_t n_phases,
+          uint64_t n_hist, int64_t *per_spot) {
+  auto listed = [&](int32_t ph) {
+    for (int32_t i = 0; i < n_phases; ++i)
+      if (phases[i] == ph) return true;
+    return false;
+  };
+  double W = 0.0;
+  std::vector<int64_t> members;
+  for (int64_t s = 0; s < n_spots; ++s) {
+    per_spot[s] = 0;
+    if (listed(spots[s].phase)) {
+      W += spots[s].weight;
+      members.push_back(s);
+    }
+  }
+  if (members.empty() || !(W > 0.0)) return PMC_E_INVAL;
+  std::vector<std::pair<double, int64_t>> rem;
+  rem.reserve(members.size());
+  uint64_t given = 0;
+  for (int64_t s : members) {
+    const double share = (double)n_hist * spots[s].weight / W;
+    const double whole = std::floor(share);
+    per_spot[s] = (int64_t)whole;
+    given += (uint64_t)whole;
+    rem.emplace_back(share - whole, s);
+  }
+  std::stable_sort(rem.begin(), rem.end(), [](const std::pair<double, int64_t> &a,
+                                              const std::pair<double, int64_t> &b) {
+    return a.first > b.first || (a.first == b.first && a.second < b.second);
+  });
+  uint64_t left = n_hist > given ? n_hist - given : 0;
+  for (size_t k = 0; k < rem.size() && left > 0; ++k, --left) per_spot[rem[k].second] += 1;
+  return PMC_OK;
+}
+
+int validate_request(pmc_context *ctx, const pmc_request *req) {
+  if (!req) return fail(ctx, PMC_E_INVAL, "request is NULL");
+  if (!ctx->have_plan) return fail(ctx, PMC_E_STATE, "no plan loaded (call pmc_load_spots first)");
+  if (req->n_phases < 1 || req->n_phases > PMC_MAX_PHASES || !req->phases)
+    return fail(ctx, PMC_E_INVAL, "n_phases must be 1..%d with a phase list", PMC_MAX_PHASES);
+  for (int32_t i = 0; i < req->n_phases; ++i) {
+    if (!ctx->phases.count(req->phases[i]))
+      return fail(ctx, PMC_E_NOPHASE, "phase %d is not loaded", req->phases[i]);
+    for (int32_t j = 0; j < i; ++j)
+      if (req->phases[j] == req->phases[i])
+        return fail(ctx, PMC_E_INVAL, "phase %d listed twice", req->phases[i]);
+  }
+  if (req->n_histories == 0) return fail(ctx, PMC_E_INVAL, "n_histories must be >= 1");
+  if (req->n_histories > PMC_MAX_HISTORIES)
+    return fail(ctx, PMC_E_RANGE, "n_histories %llu exceeds %llu per tally",
+                (unsigned long long)req->n_histories, (unsigned long long)PMC_MAX_HISTORIES);
+  if (req->engine != PMC_ENGINE_PLAIN && req->engine != PMC_ENGINE_PERSISTENT)
+    return fail(ctx, PMC_E_INVAL, "unknown engine %d", req->engine);
+  if (req->block_size != 0 && (req->block_size < 64 || req->block_size > 1024 || req->block_size % 64))
+    return fail(ctx, PMC_E_INVAL, "block_size must be 0 or a multiple of 64 in [64, 1024]");
+  if (req->chunk < 0 || req->refill_min < 0 || req->refill_min > 64 || req->grid_blocks < 0)
+    return fail(ctx, PMC_E_INVAL, "chunk, refill_min (0..64) and grid_blocks must be >= 0");
+  if (req->flags & ~31u) return fail(ctx, PMC_E_INVAL, "unknown flag bits 0x%x", req->flags);
+  bool any = false;
+  for (const pmc_spot &s : ctx->spots)
+    for (int32_t i = 0; i < req->n_phases && !any; ++i) any = s.phase == req->phases[i];
+  if (!any) return fail(ctx, PMC_E_INVAL, "no spot of the plan lies on the requested phases");
+  return PMC_OK;
+}
+
+template <typename R>
+SpotDev<R> make_spot(const pmc_spot &s, const pmc_field &f, const PhaseRec &ph, int32_t target) {
+  double w[3], u[3], v[3];
+  const double nw = norm3(f.direction), nu = norm3(f.bev_u);
+  for (int k = 0; k < 3; ++k) {
+    w[k] = f.direction[k] / nw;
+    u[k] = f.bev_u[k] / nu;
+  }
+  v[0] = w[1] * u[2] - w[2] * u[1];
+  v[1] = w[2] * u[0] - w[0] * u[2];
+  v[2] = w[0] * u[1] - w[1] * u[0];
+  SpotDev<R> d;
+  for (int k = 0; k < 3; ++k) {
+    const double c = 0.1 * (f.isocentre_mm[k] - ph.org_mm[k]) + 0.1 * s.x_mm * u[k] + 0.1 * s.y_mm * v[k];
+    d.c[k] = (R)c;
+    d.u[k] = (R)u[k];
+    d.v[k] = (R)v[k];
+    d.w[k] = (R)w[k];
+  }
+  d.sigma = (R)(0.1 * s.sigma_mm);
+  d.E = (R)s.energy_MeV;
+  d.target = target;
+  d.pad = 0;
+  return d;
+}
+
+TargetDev make_target(const PhaseRec &ph, unsigned long long *tally, int32_t lut) {
+  TargetDev t;
+  t.hu = ph.d_hu;
+  t.mask = ph.d_mask;
+  t.tally = tally;
+  t.nx = ph.nx;
+  t.ny = ph.ny;
+  t.nz = ph.nz;
+  t.lut = lut;
+  for (int k = 0; k < 3; ++k) t.d[k] = 0.1 * ph.sp_mm[k];
+  return t;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int default_chunk(const pmc_request *req) { return req->chunk > 0 ? req->chunk : 256; }
+
+// Split, build and upload the request's device data (cached on the inputs).
+template <typename R>
+int prepare(pmc_context *ctx, const pmc_request *req) {
+  Prepared &P = ctx->prep;
+  std::vector<int32_t> phases(req->phases, req->phases + req->n_phases);
+  std::vector<uint64_t> versions;
+  for (int32_t ph : phases) versions.push_back(ctx->phases[ph].version);
+  const int32_t chunk = req->engine == PMC_ENGINE_PERSISTENT ? default_chunk(req) : 0;
+  if (P.valid && P.plan_version == ctx->plan_version && P.n_hist == req->n_histories &&
+      P.phases == phases && P.phase_versions == versions && P.engine == req->engine &&
+      P.chunk == chunk && P.precision == ctx->precision)
+    return PMC_OK;
+  wait_pending(ctx);
+  P = Prepared();
+  const int64_t n_spots = (int64_t)ctx->spots.size();
+  P.per_spot.assign(n_spots, 0);
+  int rc = split(ctx->spots.data(), n_spots, req->phases, req->n_phases, req->n_histories,
+                 P.per_spot.data());
+  if (rc) return fail(ctx, rc, "history split failed (weights)");
+  const int32_t n_slots = req->n_phases;
+  std::map<int32_t, int32_t> slot_of;
+  for (int32_t i = 0; i < n_slots; ++i) slot_of[phases[i]] = i;
+  // spot descriptors
+  std::vector<SpotDev<R>> sd(n_spots);
+  P.list.assign(n_slots, {});
+  P.first.assign(n_slots, {0});
+  P.slot_hist.assign(n_slots, 0);
+  for (int64_t s = 0; s < n_spots; ++s) {
+    const pmc_spot &sp = ctx->spots[s];
+    auto it = slot_of.find(sp.phase);
+    const int32_t slot = it == slot_of.end() ? -1 : it->second;
+    const PhaseRec &ph = slot >= 0 ? ctx->phases[sp.phase] : ctx->phases[phases[0]];
+    sd[s] = make_spot<R>(sp, ctx->fields[sp.field], ph, slot);
+    if (slot >= 0 && P.per_spot[s] > 0) {
+      P.list[slot].push_back((int32_t)s);
+      P.first[slot].push_back(P.first[slot].back() + P.per_spot[s]);
+      P.slot_hist[slot] += P.per_spot[s];
+      P.incident += (unsigned __int128)((unsigned long long)P.per_spot[s]) *
+                    (unsigned long long)q_working(ctx, sp.energy_MeV);
+    }
+  }
+  // work items (persistent engine): chunks of each spot's histories, spot order
+  std::vector<WorkItem> items;
+  if (req->engine == PMC_ENGINE_PERSISTENT) {
+    for (int64_t s = 0; s < n_spots; ++s) {
+      const int64_t n = P.per_spot[s];
+      for (int64_t h = 0; h < n; h += chunk) {
+        WorkItem w;
+        w.spot = (int32_t)s;
+        w.h_begin = (uint32_t)h;
+        w.h_count = (uint32_t)std::min<int64_t>(chunk, n - h);
+        w.pad = 0;
+        items.push_back(w);
+      }
+    }
+  }
+  P.n_items = (int32_t)items.size();
+  // LUTs: one if all listed phases share it, else one per slot
+  const size_t lut_elems = 2 * kLut;
+  P.same_lut = true;
+  for (int32_t i = 1; i < n_slots; ++i)
+    if (ctx->phases[phases[i]].lut64 != ctx->phases[phases[0]].lut64) P.same_lut = false;
+  const int32_t n_luts = P.same_lut ? 1 : n_slots;
+  // layout of the scratch buffer
+  size_t off = 0;
+  P.off_spots = off;
+  off = align256(off + sizeof(SpotDev<R>) * (size_t)n_spots);
+  P.off_items = off;
+  off = align256(off + sizeof(WorkItem) * items.size());
+  P.off_luts = off;
+  off = align256(off + sizeof(R) * lut_elems * (size_t)n_luts);
+  P.off_targets = off;
+  off = align256(off + sizeof(TargetDev) * (size_t)n_slots);
+  P.off_ids.resize(n_slots);
+  P.off_first.resize(n_slots);
+  for (int32_t i = 0; i < n_slots; ++i) {
+    P.off_ids[i] = off;
+    off = align256(off + sizeof(int32_t) * (P.list[i].size() + 1));
+    P.off_first[i] = off;
+    off = align256(off + sizeof(long long) * P.first[i].size());
+  }
+  P.staging.assign(off, 0);
+  auto put = [&](size_t o, const void *src, size_t n) {
+    if (n) std::memcpy(P.staging.data() + o, src, n);
+  };
+  put(P.off_spots, sd.data(), sizeof(SpotDev<R>) * sd.size());
+  put(P.off_items, items.data(), sizeof(WorkItem) * items.size());
+  for (int32_t l = 0; l < n_luts; ++l) {
+    const PhaseRec &ph = ctx->phases[phases[l]];
+    const void *src = sizeof(R) == 4 ? (const void *)ph.lut32.data() : (const void *)ph.lut64.data();
+    put(P.off_luts + sizeof(R) * lut_elems * l, src, sizeof(R) * lut_elems);
+  }
+  for (int32_t i = 0; i < n_slots; ++i) {
+    put(P.off_ids[i], P.list[i].data(), sizeof(int32_t) * P.list[i].size());
+    put(P.off_first[i], P.first[i].data(), sizeof(long long) * P.first[i].size());
+  }
+  rc = ensure(ctx, ctx->scratch, off, "request scratch");
+  if (rc) return rc;
+  HIP_TRY(ctx, hipMemcpy(ctx->scratch.p, P.staging.data(), off, hipMemcpyHostToDevice),
+          "upload request data");
+  P.valid = true;
+  P.plan_version = ctx->plan_version;
+  P.n_hist = req->n_histories;
+  P.phases = phases;
+  P.phase_versions = versions;
+  P.engine = req->engine;
+  P.chunk = chunk;
+  P.precision = ctx->precision;
+  return PMC_OK;
+}
+
+unsigned char *scratch_at(pmc_context *ctx, size_t off) {
+  return static_cast<unsigned char *>(ctx->scratch.p) + off;
+}
+
+template <typename R>
+int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
+            unsigned long long *const *tally, unsigned long long *counters) {
+  int rc = prepare<R>(ctx, req);
+  if (rc) return rc;
+  Prepared &P = ctx->prep;
+  const bool fp64 = sizeof(R) == 8;
+  const uint32_t k0 = (uint32_t)(ctx->seed & 0xffffffffu), k1 = req->request_id;
+  const double inv_dl2 = 1.0 / ctx->tabs.dl2;
+  if (req->engine == PMC_ENGINE_PLAIN) {
+    for (int32_t i = 0; i < req->n_phases; ++i) {
+      if (P.slot_hist[i] == 0) continue;
+      const PhaseRec &ph = ctx->phases[req->phases[i]];
+      pmc::PlainLaunch a;
+      a.spots = scratch_at(ctx, P.off_spots);
+      a.spot_ids = reinterpret_cast<const int32_t *>(scratch_at(ctx, P.off_ids[i]));
+      a.first = reinterpret_cast<const long long *>(scratch_at(ctx, P.off_first[i]));
+      a.n_list = (int32_t)P.list[i].size();
+      a.n_hist = P.slot_hist[i];
+      a.target = make_target(ph, tally[i], 0);
+      a.lut = fp64 ? ph.d_lut64 : ph.d_lut32;
+      a.tab = ctx->d_tab;
+      a.l2e0 = ctx->tabs.l2e0;
+      a.inv_dl2 = inv_dl2;
+      a.dl2 = ctx->tabs.dl2;
+      a.k0 = k0;
+      a.k1 = k1;
+      a.flags = req->flags;
+      a.block = req->block_size ? req->block_size : 256;
+      a.lut_lds = !fp64;
+      a.counters = counters;
+      HIP_TRY(ctx, pmc::launch_plain(a, fp64, st), "transport_plain launch");
+    }
+  } else {
+    // targets carry this call's tally pointers: rebuilt and uploaded per call
+    std::vector<TargetDev> tg(req->n_phases);
+    for (int32_t i = 0; i < req->n_phases; ++i)
+      tg[i] = make_target(ctx->phases[req->phases[i]], tally[i], P.same_lut ? 0 : i);
+    HIP_TRY(ctx, hipMemcpyAsync(scratch_at(ctx, P.off_targets), tg.data(),
+                                sizeof(TargetDev) * tg.size(), hipMemcpyHostToDevice, st),
+            "upload targets");
+    rc = ensure(ctx, ctx->cursor, 256, "work-queue cursor");
+    if (rc) return rc;
+    HIP_TRY(ctx, pmc::launch_fill_u64((unsigned long long *)ctx->cursor.p, 1, 0ull, st), "cursor reset");
+    pmc::PersistentLaunch a;
+    a.spots = scratch_at(ctx, P.off_spots);
+    a.items = reinterpret_cast<const WorkItem *>(scratch_at(ctx, P.off_items));
+    a.n_items = P.n_items;
+    a.targets = reinterpret_cast<const TargetDev *>(scratch_at(ctx, P.off_targets));
+    a.n_targets = req->n_phases;
+    a.luts = scratch_at(ctx, P.off_luts);
+    a.tab = ctx->d_tab;
+    a.l2e0 = ctx->tabs.l2e0;
+    a.inv_dl2 = inv_dl2;
+    a.dl2 = ctx->tabs.dl2;
+    a.k0 = k0;
+    a.k1 = k1;
+    a.flags = req->flags;
+    a.refill_min = req->refill_min ? req->refill_min : 16;
+    a.block = req->block_size ? req->block_size : 256;
+    a.lut_lds = !fp64 && P.same_lut;
+    a.cursor = (unsigned long long *)ctx->cursor.p;
+    a.counters = counters;
+    unsigned grid = (unsigned)req->grid_blocks;
+    if (grid == 0) {
+      int per_cu = pmc::persistent_blocks_per_cu(a, fp64);
+      if (per_cu < 1) per_cu = 1;
+      grid = (unsigned)(ctx->n_cu * per_cu);
+    }
+    a.grid = grid;
+    HIP_TRY(ctx, pmc::launch_persistent(a, fp64, st), "transport_persistent launch");
+  }
+  ctx->last_stream = st;
+  ctx->pending = true;
+  return PMC_OK;
+}
+
+void to128(unsigned __int128 v, uint64_t out[2]) {
+  out[0] = (uint64_t)v;
+  out[1] = (uint64_t)(v >> 64);
+}
+
+unsigned __int128 from128(const uint64_t v[2]) {
+  return ((unsigned __int128)v[1] << 64) | v[0];
+}
+
+void fill_balance(const pmc_context *ctx, const uint64_t *c, unsigned __int128 deposited,
+                  pmc_balance *b) {
+  to128(ctx->prep.incident, b->incident);
+  to128(deposited, b->deposited);
+  b->escaped[0] = c[0];
+  b->escaped[1] = c[1];
+  b->nuclear[0] = c[2];
+  b->nuclear[1] = c[3];
+  b->cutoff[0] = c[4];
+  b->cutoff[1] = c[5];
+  b->histories = c[6];
+  b->steps = c[7];
+  b->delta_events = c[8];
+  b->nuclear_events = c[9];
+  b->escapes = c[10];
+  b->misses = c[11];
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported C ABI
+// ===========================================================================
+extern "C" {
+
+int pmc_create(const pmc_config *cfg, pmc_context **out) {
+  if (!cfg || !out) return fail(nullptr, PMC_E_INVAL, "pmc_create: NULL argument");
+  if (cfg->precision != PMC_FP32 && cfg->precision != PMC_FP64)
+    return fail(nullptr, PMC_E_INVAL, "precision must be PMC_FP32 or PMC_FP64");
+  if (cfg->device < -1) return fail(nullptr, PMC_E_INVAL, "device must be >= -1");
+  pmc_context *ctx = new pmc_context();
+  ctx->device = cfg->device;
+  ctx->precision = cfg->precision;
+  ctx->seed = cfg->seed;
+  pmc::build_tables(&ctx->tabs);
+  if (cfg->device == -1) {  // validation-only context
+    ctx->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : ~0ull;
+    *out = ctx;
+    return PMC_OK;
+  }
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= cfg->device) {
+    delete ctx;
+    return fail(nullptr, PMC_E_DEVICE, "no HIP device %d (%s)", cfg->device,
+                e != hipSuccess ? hipGetErrorString(e) : "device count too small");
+  }
+  auto bail = [&](hipError_t err, const char *what) {
+    const int rc = fail(nullptr, PMC_E_DEVICE, "%s: %s", what, hipGetErrorString(err));
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->d_tab) (void)hipFree(ctx->d_tab);
+    delete ctx;
+    return rc;
+  };
+  if ((e = hipSetDevice(cfg->device)) != hipSuccess) return bail(e, "hipSetDevice");
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, cfg->device)) != hipSuccess) return bail(e, "hipGetDeviceProperties");
+  ctx->n_cu = prop.multiProcessorCount;
+  size_t free_b = 0, total_b = 0;
+  if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) return bail(e, "hipMemGetInfo");
+  ctx->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+  if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess)
+    return bail(e, "hipStreamCreate");
+  // tables in the working precision: (R, mu_delta, omega^2, 0) per node
+  const int n = pmc::kTableNodes;
+  if (ctx->precision == PMC_FP32) {
+    std::vector<float> t(4 * n);
+    for (int i = 0; i < n; ++i) {
+      t[4 * i + 0] = (float)ctx->tabs.range[i];
+      t[4 * i + 1] = (float)ctx->tabs.mu_delta[i];
+      t[4 * i + 2] = (float)ctx->tabs.omega2[i];
+      t[4 * i + 3] = 0.0f;
+    }
+    ctx->tab_bytes = t.size() * sizeof(float);
+    if ((e = hipMalloc(&ctx->d_tab, ctx->tab_bytes)) != hipSuccess) return bail(e, "hipMalloc tables");
+    if ((e = hipMemcpy(ctx->d_tab, t.data(), ctx->tab_bytes, hipMemcpyHostToDevice)) != hipSuccess)
+      return bail(e, "upload tables");
+  } else {
+    std::vector<double> t(4 * n);
+    for (int i = 0; i < n; ++i) {
+      t[4 * i + 0] = ctx->tabs.range[i];
+      t[4 * i + 1] = ctx->tabs.mu_delta[i];
+      t[4 * i + 2] = ctx->tabs.omega2[i];
+      t[4 * i + 3] = 0.0;
+    }
+    ctx->tab_bytes = t.size() * sizeof(double);
+    if ((e = hipMalloc(&ctx->d_tab, ctx->tab_bytes)) != hipSuccess) return bail(e, "hipMalloc tables");
+    if ((e = hipMemcpy(ctx->d_tab, t.data(), ctx->tab_bytes, hipMemcpyHostToDevice)) != hipSuccess)
+      return bail(e, "upload tables");
+  }
+  ctx->used = ctx->tab_bytes;
+  ctx->has_device = true;
+  *out = ctx;
+  return PMC_OK;
+}
+
+void pmc_destroy(pmc_context *ctx) {
+  if (!ctx) return;
+  if (ctx->has_device) {
+    (void)hipSetDevice(ctx->device);
+    wait_pending(ctx);
+    for (auto &kv : ctx->phases) free_phase(ctx, kv.second);
+    release(ctx, ctx->scratch);
+    release(ctx, ctx->cursor);
+    release(ctx, ctx->counters);
+    if (ctx->d_tab) (void)hipFree(ctx->d_tab);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  }
+  delete ctx;
+}
+
+const char *pmc_last_error(const pmc_context *ctx) {
+  return ctx ? ctx->err.c_str() : g_error.c_str();
+}
+
+int pmc_load_phase(pmc_context *ctx, int32_t phase, const int16_t *hu, int32_t nx, int32_t ny,
+                   int32_t nz, const double spacing_mm[3], const double origin_mm[3],
+                   const double *calib_hu, const double *calib_density, const double *calib_rsp,
+                   int32_t n_nodes, const uint8_t *external_mask) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (phase < 0 || phase > kMaxPhaseId) return fail(ctx, PMC_E_INVAL, "phase id must be 0..%d", kMaxPhaseId);
+  if (!hu || !spacing_mm || !origin_mm || !calib_hu || !calib_density || !calib_rsp)
+    return fail(ctx, PMC_E_INVAL, "NULL input array");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(ctx, PMC_E_INVAL, "grid dims must be >= 1");
+  const long long nvox = (long long)nx * ny * nz;
+  if (nvox > 0x7fffffffLL) return fail(ctx, PMC_E_INVAL, "grid has more than 2^31-1 voxels");
+  for (int k = 0; k < 3; ++k)
+    if (!(std::isfinite(spacing_mm[k]) && spacing_mm[k] > 0.0))
+      return fail(ctx, PMC_E_INVAL, "spacing must be finite and > 0");
+  if (!finite3(origin_mm)) return fail(ctx, PMC_E_INVAL, "origin must be finite");
+  if (n_nodes < 2) return fail(ctx, PMC_E_INVAL, "calibration needs >= 2 nodes");
+  for (int i = 0; i < n_nodes; ++i) {
+    if (!std::isfinite(calib_hu[i]) || !std::isfinite(calib_density[i]) || !std::isfinite(calib_rsp[i]))
+      return fail(ctx, PMC_E_INVAL, "calibration node %d is not finite", i);
+    if (calib_density[i] < 0.0 || calib_rsp[i] < 0.0)
+      return fail(ctx, PMC_E_INVAL, "calibration node %d has a negative value", i);
+    if (i > 0 && !(calib_hu[i] > calib_hu[i - 1]))
+      return fail(ctx, PMC_E_INVAL, "calibration HU must be strictly increasing (node %d)", i);
+  }
+  PhaseRec rec;
+  rec.nx = nx;
+  rec.ny = ny;
+  rec.nz = nz;
+  for (int k = 0; k < 3; ++k) {
+    rec.sp_mm[k] = spacing_mm[k];
+    rec.org_mm[k] = origin_mm[k];
+  }
+  rec.lut32.resize(2 * kLut);
+  rec.lut64.resize(2 * kLut);
+  for (int h = kHuLo; h <= kHuHi; ++h) {
+    const int i = h - kHuLo;
+    const double rho = calib_at(calib_hu, calib_density, n_nodes, (double)h);
+    const double rsp = calib_at(calib_hu, calib_rsp, n_nodes, (double)h);
+    rec.lut64[2 * i] = rho;
+    rec.lut64[2 * i + 1] = rsp;
+    rec.lut32[2 * i] = (float)rho;
+    rec.lut32[2 * i + 1] = (float)rsp;
+  }
+  rec.has_mask = external_mask != nullptr;
+  rec.version = ++ctx->phase_counter;
+  if (!ctx->has_device) {
+    auto it = ctx->phases.find(phase);
+    if (it != ctx->phases.end()) ctx->phases.erase(it);
+    ctx->phases[phase] = std::move(rec);
+    return PMC_OK;
+  }
+  const size_t bytes = (size_t)nvox * 2 + (rec.has_mask ? (size_t)nvox : 0) +
+                       rec.lut32.size() * sizeof(float) + rec.lut64.size() * sizeof(double);
+  const size_t old = ctx->phases.count(phase) ? ctx->phases[phase].bytes : 0;
+  if (ctx->used - old + bytes > ctx->budget)
+    return fail(ctx, PMC_E_BUDGET, "phase %d needs %zu bytes: over the device-memory budget", phase, bytes);
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  wait_pending(ctx);
+  auto cleanup = [&](hipError_t e, const char *what) {
+    free_phase(ctx, rec);
+    return hip_fail(ctx, e, what);
+  };
+  hipError_t e;
+  if ((e = hipMalloc((void **)&rec.d_hu, (size_t)nvox * 2)) != hipSuccess) return cleanup(e, "hipMalloc hu");
+  rec.bytes += (size_t)nvox * 2;
+  ctx->used += (size_t)nvox * 2;
+  if (rec.has_mask) {
+    if ((e = hipMalloc((void **)&rec.d_mask, (size_t)nvox)) != hipSuccess) return cleanup(e, "hipMalloc mask");
+    rec.bytes += (size_t)nvox;
+    ctx->used += (size_t)nvox;
+  }
+  const size_t l32 = rec.lut32.size() * sizeof(float), l64 = rec.lut64.size() * sizeof(double);
+  if ((e = hipMalloc(&rec.d_lut32, l32)) != hipSuccess) return cleanup(e, "hipMalloc lut");
+  rec.bytes += l32;
+  ctx->used += l32;
+  if ((e = hipMalloc(&rec.d_lut64, l64)) != hipSuccess) return cleanup(e, "hipMalloc lut");
+  rec.bytes += l64;
+  ctx->used += l64;
+  if ((e = hipMemcpy(rec.d_hu, hu, (size_t)nvox * 2, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(e, "upload hu");
+  if (rec.has_mask &&
+      (e = hipMemcpy(rec.d_mask, external_mask, (size_t)nvox, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(e, "upload mask");
+  if ((e = hipMemcpy(rec.d_lut32, rec.lut32.data(), l32, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(e, "upload lut");
+  if ((e = hipMemcpy(rec.d_lut64, rec.lut64.data(), l64, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(e, "upload lut");
+  auto it = ctx->phases.find(phase);
+  if (it != ctx->phases.end()) {
+    free_phase(ctx, it->second);
+    ctx->phases.erase(it);
+  }
+  ctx->phases[phase] = std::move(rec);
+  return PMC_OK;
+}
+
+int pmc_unload_phase(pmc_context *ctx, int32_t phase) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  auto it = ctx->phases.find(phase);
+  if (it == ctx->phases.end()) return fail(ctx, PMC_E_NOPHASE, "phase %d is not loaded", phase);
+  if (ctx->has_device) {
+    (void)hipSetDevice(ctx->device);
+    wait_pending(ctx);
+    free_phase(ctx, it->second);
+  }
+  ctx->phases.erase(it);
+  ctx->prep.valid = false;
+  return PMC_OK;
+}
+
+int pmc_load_spots(pmc_context *ctx, const pmc_field *fields, int32_t n_fields,
+                   const pmc_spot *spots, int64_t n_spots) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (!fields || n_fields < 1) return fail(ctx, PMC_E_INVAL, "need at least one field");
+  if (!spots || n_spots < 1 || n_spots > 0x7fffffffLL)
+    return fail(ctx, PMC_E_INVAL, "need 1..2^31-1 spots");
+  for (int32_t f = 0; f < n_fields; ++f) {
+    const pmc_field &F = fields[f];
+    if (!finite3(F.isocentre_mm) || !finite3(F.direction) || !finite3(F.bev_u))
+      return fail(ctx, PMC_E_INVAL, "field %d: non-finite vector", f);
+    const double nd = norm3(F.direction), nu = norm3(F.bev_u);
+    const double dot = F.direction[0] * F.bev_u[0] + F.direction[1] * F.bev_u[1] + F.direction[2] * F.bev_u[2];
+    if (std::fabs(nd - 1.0) > 1e-6 || std::fabs(nu - 1.0) > 1e-6 || std::fabs(dot) > 1e-6)
+      return fail(ctx, PMC_E_INVAL, "field %d: direction and bev_u must be orthogonal unit vectors", f);
+  }
+  for (int64_t s = 0; s < n_spots; ++s) {
+    const pmc_spot &S = spots[s];
+    if (!(S.energy_MeV >= PMC_E_MIN_MEV && S.energy_MeV <= PMC_E_MAX_MEV))
+      return fail(ctx, PMC_E_INVAL, "spot %lld: energy %g MeV outside [1, 300]", (long long)s, S.energy_MeV);
+    if (!std::isfinite(S.x_mm) || !std::isfinite(S.y_mm) || !(S.sigma_mm >= 0.0) || !std::isfinite(S.sigma_mm))
+      return fail(ctx, PMC_E_INVAL, "spot %lld: bad position or sigma", (long long)s);
+    if (!(S.weight > 0.0) || !std::isfinite(S.weight))
+      return fail(ctx, PMC_E_INVAL, "spot %lld: weight must be finite and > 0", (long long)s);
+    if (S.field < 0 || S.field >= n_fields)
+      return fail(ctx, PMC_E_INVAL, "spot %lld: field %d out of range", (long long)s, S.field);
+    if (S.phase < 0 || S.phase > kMaxPhaseId)
+      return fail(ctx, PMC_E_INVAL, "spot %lld: phase %d outside 0..%d", (long long)s, S.phase, kMaxPhaseId);
+  }
+  ctx->fields.assign(fields, fields + n_fields);
+  ctx->spots.assign(spots, spots + n_spots);
+  ctx->have_plan = true;
+  ++ctx->plan_version;
+  return PMC_OK;
+}
+
+int pmc_dose_device(pmc_context *ctx, const pmc_request *req, void *stream,
+                    int64_t *const *dev_tally, uint64_t *dev_counters) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  int rc = validate_request(ctx, req);
+  if (rc) return rc;
+  if (!dev_tally) return fail(ctx, PMC_E_INVAL, "dev_tally is NULL");
+  for (int32_t i = 0; i < req->n_phases; ++i)
+    if (!dev_tally[i]) return fail(ctx, PMC_E_INVAL, "dev_tally[%d] is NULL", i);
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  unsigned long long *counters = (unsigned long long *)dev_counters;
+  hipStream_t st = (hipStream_t)stream;
+  if (!counters) {
+    rc = ensure(ctx, ctx->counters, sizeof(uint64_t) * PMC_COUNTERS, "counters");
+    if (rc) return rc;
+    counters = (unsigned long long *)ctx->counters.p;
+    HIP_TRY(ctx, pmc::launch_fill_u64(counters, PMC_COUNTERS, 0ull, st), "counter reset");
+  }
+  unsigned long long *const *t = reinterpret_cast<unsigned long long *const *>(dev_tally);
+  return ctx->precision == PMC_FP64 ? enqueue<double>(ctx, req, st, t, counters)
+                                    : enqueue<float>(ctx, req, st, t, counters);
+}
+
+int pmc_balance_from_counters(pmc_context *ctx, const pmc_request *req, const uint64_t *counters,
+                              const uint64_t deposited[2], pmc_balance *out) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (!counters || !deposited || !out) return fail(ctx, PMC_E_INVAL, "NULL argument");
+  int rc = validate_request(ctx, req);
+  if (rc) return rc;
+  // the incident total depends only on the split: recompute it on the host
+  std::vector<int64_t> per(ctx->spots.size());
+  rc = split(ctx->spots.data(), (int64_t)ctx->spots.size(), req->phases, req->n_phases,
+             req->n_histories, per.data());
+  if (rc) return fail(ctx, rc, "history split failed");
+  unsigned __int128 inc = 0;
+  for (size_t s = 0; s < per.size(); ++s)
+    if (per[s] > 0)
+      inc += (unsigned __int128)(unsigned long long)per[s] *
+             (unsigned long long)q_working(ctx, ctx->spots[s].energy_MeV);
+  fill_balance(ctx, counters, from128(deposited), out);
+  to128(inc, out->incident);
+  return PMC_OK;
+}
+
+int pmc_convert_device(pmc_context *ctx, int32_t phase, const int64_t *dev_tally,
+                       uint64_t n_histories, void *stream, double *dev_dose, double *dev_density) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  auto it = ctx->phases.find(phase);
+  if (it == ctx->phases.end()) return fail(ctx, PMC_E_NOPHASE, "phase %d is not loaded", phase);
+  if (!dev_tally || n_histories == 0) return fail(ctx, PMC_E_INVAL, "need a tally and n_histories >= 1");
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  const PhaseRec &ph = it->second;
+  const double vol = (0.1 * ph.sp_mm[0]) * (0.1 * ph.sp_mm[1]) * (0.1 * ph.sp_mm[2]);
+  HIP_TRY(ctx, pmc::launch_convert((const long long *)dev_tally, ph.d_hu, ph.d_mask, ph.d_lut64,
+                                   ph.nvox(), vol, (double)n_histories, dev_dose, dev_density,
+                                   (hipStream_t)stream),
+          "convert launch");
+  return PMC_OK;
+}
+
+int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
+             int64_t *const *tally_out, double *const *density_out, pmc_balance *balance_out) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  int rc = validate_request(ctx, req);
+  if (rc) return rc;
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  const int32_t n = req->n_phases;
+  // per-call tallies and one dose/density staging buffer
+  size_t tally_bytes = 0, max_vox = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const long long nv = ctx->phases[req->phases[i]].nvox();
+    tally_bytes += (size_t)nv * 8;
+    max_vox = std::max(max_vox, (size_t)nv);
+  }
+  const size_t conv_bytes = max_vox * 8 * 2;
+  if (ctx->used + tally_bytes + conv_bytes > ctx->budget)
+    return fail(ctx, PMC_E_BUDGET, "tallies need %zu bytes: over the device-memory budget",
+                tally_bytes + conv_bytes);
+  void *d_t = nullptr, *d_conv = nullptr;
+  HIP_TRY(ctx, hipMalloc(&d_t, tally_bytes), "hipMalloc tallies");
+  ctx->used += tally_bytes;
+  struct Guard {
+    pmc_context *c;
+    void *a, *b;
+    size_t na, nb;
+    ~Guard() {
+      if (c->pending) (void)hipStreamSynchronize(c->last_stream);
+      c->pending = false;
+      if (a) { (void)hipFree(a); c->used -= na; }
+      if (b) { (void)hipFree(b); c->used -= nb; }
+    }
+  } guard{ctx, d_t, nullptr, tally_bytes, 0};
+  HIP_TRY(ctx, hipMalloc(&d_conv, conv_bytes), "hipMalloc dose buffer");
+  guard.b = d_conv;
+  guard.nb = conv_bytes;
+  ctx->used += conv_bytes;
+  hipStream_t st = ctx->stream;
+  HIP_TRY(ctx, hipMemsetAsync(d_t, 0, tally_bytes, st), "zero tallies");
+  std::vector<int64_t *> tp(n);
+  size_t off = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    tp[i] = reinterpret_cast<int64_t *>(static_cast<unsigned char *>(d_t) + off);
+    off += (size_t)ctx->phases[req->phases[i]].nvox() * 8;
+  }
+  rc = ensure(ctx, ctx->counters, sizeof(uint64_t) * PMC_COUNTERS, "counters");
+  if (rc) return rc;
+  HIP_TRY(ctx, hipMemsetAsync(ctx->counters.p, 0, sizeof(uint64_t) * PMC_COUNTERS, st), "zero counters");
+  rc = pmc_dose_device(ctx, req, st, tp.data(), (uint64_t *)ctx->counters.p);
+  if (rc) return rc;
+  // conversion and copies back
+  unsigned __int128 deposited = 0;
+  std::vector<int64_t> host_tally;
+  for (int32_t i = 0; i < n; ++i) {
+    const PhaseRec &ph = ctx->phases[req->phases[i]];
+    const long long nv = ph.nvox();
+    double *d_dose = static_cast<double *>(d_conv);
+    double *d_dens = d_dose + nv;
+    const bool want_dose = dose_out && dose_out[i];
+    const bool want_dens = density_out && density_out[i];
+    if (want_dose || want_dens) {
+      rc = pmc_convert_device(ctx, req->phases[i], tp[i], req->n_histories, st,
+                              want_dose ? d_dose : nullptr, want_dens ? d_dens : nullptr);
+      if (rc) return rc;
+    }
+    int64_t *tdst = (tally_out && tally_out[i]) ? tally_out[i] : nullptr;
+    if (!tdst) {
+      host_tally.resize((size_t)nv);
+      tdst = host_tally.data();
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(tdst, tp[i], (size_t)nv * 8, hipMemcpyDeviceToHost, st), "copy tally");
+    if (want_dose)
+      HIP_TRY(ctx, hipMemcpyAsync(dose_out[i], d_dose, (size_t)nv * 8, hipMemcpyDeviceToHost, st), "copy dose");
+    if (want_dens)
+      HIP_TRY(ctx, hipMemcpyAsync(density_out[i], d_dens, (size_t)nv * 8, hipMemcpyDeviceToHost, st),
+              "copy density");
+    HIP_TRY(ctx, hipStreamSynchronize(st), "transport / conversion");
+    for (long long v = 0; v < nv; ++v) deposited += (unsigned __int128)(uint64_t)tdst[v];
+  }
+  ctx->pending = false;
+  if (balance_out) {
+    uint64_t c[PMC_COUNTERS];
+    HIP_TRY(ctx, hipMemcpy(c, ctx->counters.p, sizeof c, hipMemcpyDeviceToHost), "copy counters");
+    fill_balance(ctx, c, deposited, balance_out);
+  }
+  return PMC_OK;
+}
+
+int pmc_trace(pmc_context *ctx, int32_t phase, int64_t spot, uint32_t history, uint32_t request_id,
+              uint32_t flags, pmc_trace_rec *out, int32_t max_rec, int32_t *n_rec) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (!out || max_rec < 1 || !n_rec) return fail(ctx, PMC_E_INVAL, "need an output buffer");
+  if (!ctx->have_plan) return fail(ctx, PMC_E_STATE, "no plan loaded");
+  if (spot < 0 || spot >= (int64_t)ctx->spots.size()) return fail(ctx, PMC_E_INVAL, "spot out of range");
+  auto it = ctx->phases.find(phase);
+  if (it == ctx->phases.end()) return fail(ctx, PMC_E_NOPHASE, "phase %d is not loaded", phase);
+  if (flags & ~31u) return fail(ctx, PMC_E_INVAL, "unknown flag bits");
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  wait_pending(ctx);
+  const PhaseRec &ph = it->second;
+  const pmc_spot &sp = ctx->spots[spot];
+  const bool fp64 = ctx->precision == PMC_FP64;
+  SpotDev<double> s64 = make_spot<double>(sp, ctx->fields[sp.field], ph, 0);
+  SpotDev<float> s32 = make_spot<float>(sp, ctx->fields[sp.field], ph, 0);
+  const size_t rec_bytes = sizeof(pmc_trace_rec) * (size_t)max_rec;
+  const size_t tally_bytes = (size_t)ph.nvox() * 8;
+  void *d = nullptr;
+  HIP_TRY(ctx, hipMalloc(&d, rec_bytes + tally_bytes + 256), "hipMalloc trace");
+  struct Free { void *p; ~Free() { (void)hipFree(p); } } fr{d};
+  unsigned char *base = static_cast<unsigned char *>(d);
+  int32_t *d_n = reinterpret_cast<int32_t *>(base);
+  void *d_rec = base + 256;
+  void *d_tally = base + 256 + rec_bytes;
+  HIP_TRY(ctx, hipMemset(d_tally, 0, tally_bytes), "zero tally");
+  pmc::TraceLaunch a;
+  a.spot = fp64 ? (const void *)&s64 : (const void *)&s32;
+  a.spot_index = (int32_t)spot;
+  a.h = history;
+  a.target = make_target(ph, (unsigned long long *)d_tally, 0);
+  a.lut = fp64 ? ph.d_lut64 : ph.d_lut32;
+  a.tab = ctx->d_tab;
+  a.l2e0 = ctx->tabs.l2e0;
+  a.inv_dl2 = 1.0 / ctx->tabs.dl2;
+  a.dl2 = ctx->tabs.dl2;
+  a.k0 = (uint32_t)(ctx->seed & 0xffffffffu);
+  a.k1 = request_id;
+  a.flags = flags;
+  a.rec = d_rec;
+  a.max_rec = max_rec;
+  a.n_rec = d_n;
+  HIP_TRY(ctx, pmc::launch_trace(a, fp64, ctx->stream), "trace launch");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "trace kernel");
+  int32_t n = 0;
+  HIP_TRY(ctx, hipMemcpy(&n, d_n, sizeof n, hipMemcpyDeviceToHost), "copy trace length");
+  const int32_t m = std::min(n, max_rec);
+  HIP_TRY(ctx, hipMemcpy(out, d_rec, sizeof(pmc_trace_rec) * (size_t)m, hipMemcpyDeviceToHost), "copy trace");
+  *n_rec = n;
+  return PMC_OK;
+}
+
+int pmc_split_histories(const pmc_spot *spots, int64_t n_spots, const int32_t *phases,
+                        int32_t n_phases, uint64_t n_histories, int64_t *per_spot) {
+  if (!spots || n_spots < 1 || !phases || n_phases < 1 || !per_spot)
+    return fail(nullptr, PMC_E_INVAL, "pmc_split_histories: bad arguments");
+  for (int64_t s = 0; s < n_spots; ++s)
+    if (!(spots[s].weight > 0.0) || !std::isfinite(spots[s].weight))
+      return fail(nullptr, PMC_E_INVAL, "spot %lld: weight must be finite and > 0", (long long)s);
+  const int rc = split(spots, n_spots, phases, n_phases, n_histories, per_spot);
+  if (rc) return fail(nullptr, rc, "no spot lies on the listed phases");
+  return PMC_OK;
+}
+
+uint64_t pmc_bytes_in_use(const pmc_context *ctx) { return ctx ? ctx->used : 0; }
+
+}  // extern "C"

@@ -1,0 +1,287 @@
+"""Thin ctypes binding of libpmc (include/pmc.h), with the same names.
+
+Argument marshalling only: every step of the transport runs in libpmc's HIP
+kernels.  Importing this module loads the in-tree libpmc.so and fails loudly
+if it has not been built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from .workloads import FIELD_DTYPE, SPOT_DTYPE
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmc.so")
+
+PMC_OK = 0
+PMC_E_INVAL, PMC_E_NOPHASE, PMC_E_BUDGET, PMC_E_DEVICE, PMC_E_RANGE, PMC_E_STATE = -1, -2, -3, -4, -5, -6
+PMC_MAX_HISTORIES = 50_000_000
+PMC_MAX_PHASES = 64
+PMC_FP32, PMC_FP64 = 0, 1
+PMC_NO_STRAGGLING, PMC_NO_MCS, PMC_NO_DELTA, PMC_NO_NUCLEAR, PMC_FROZEN = 1, 2, 4, 8, 16
+PMC_ENGINE_PLAIN, PMC_ENGINE_PERSISTENT = 0, 1
+PMC_COUNTERS = 16
+
+ERROR_NAMES = {0: "PMC_OK", -1: "PMC_E_INVAL", -2: "PMC_E_NOPHASE", -3: "PMC_E_BUDGET",
+               -4: "PMC_E_DEVICE", -5: "PMC_E_RANGE", -6: "PMC_E_STATE"}
+
+# every symbol declared in include/pmc.h
+EXPORTS = ["pmc_create", "pmc_destroy", "pmc_last_error", "pmc_load_phase", "pmc_unload_phase",
+           "pmc_load_spots", "pmc_dose", "pmc_dose_device", "pmc_balance_from_counters",
+           "pmc_convert_device", "pmc_trace", "pmc_split_histories", "pmc_bytes_in_use"]
+
+
+class pmc_config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
+                ("hbm_budget_bytes", C.c_uint64)]
+
+
+class pmc_request(C.Structure):
+    _fields_ = [("request_id", C.c_uint32), ("flags", C.c_uint32), ("n_histories", C.c_uint64),
+                ("phases", C.POINTER(C.c_int32)), ("n_phases", C.c_int32), ("engine", C.c_int32),
+                ("block_size", C.c_int32), ("chunk", C.c_int32), ("refill_min", C.c_int32),
+                ("grid_blocks", C.c_int32)]
+
+
+class pmc_balance(C.Structure):
+    _fields_ = [("incident", C.c_uint64 * 2), ("deposited", C.c_uint64 * 2),
+                ("escaped", C.c_uint64 * 2), ("nuclear", C.c_uint64 * 2), ("cutoff", C.c_uint64 * 2),
+                ("histories", C.c_uint64), ("steps", C.c_uint64), ("delta_events", C.c_uint64),
+                ("nuclear_events", C.c_uint64), ("escapes", C.c_uint64), ("misses", C.c_uint64)]
+
+    def as_dict(self):
+        def w(x):
+            return int(x[0]) + (int(x[1]) << 64)
+        return {"incident": w(self.incident), "deposited": w(self.deposited),
+                "escaped": w(self.escaped), "nuclear": w(self.nuclear), "cutoff": w(self.cutoff),
+                "histories": int(self.histories), "steps": int(self.steps),
+                "delta_events": int(self.delta_events), "nuclear_events": int(self.nuclear_events),
+                "escapes": int(self.escapes), "misses": int(self.misses)}
+
+
+TRACE_DTYPE = np.dtype([
+    ("cause", "<i4"), ("voxel", "<i4"), ("fate", "<i4"), ("block", "<u4"),
+    ("s", "<f8"), ("E", "<f8"), ("r", "<f8", 3), ("w", "<f8", 3),
+    ("n_delta", "<f8"), ("n_nuc", "<f8"), ("l_acc", "<f8"), ("dep", "<i8"), ("t_delta", "<f8"),
+])
+assert TRACE_DTYPE.itemsize == 120
+
+
+class PmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1809_03927_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u32, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
+        L.pmc_create.argtypes = [C.POINTER(pmc_config), C.POINTER(vp)]
+        L.pmc_destroy.argtypes = [vp]
+        L.pmc_destroy.restype = None
+        L.pmc_last_error.argtypes = [vp]
+        L.pmc_last_error.restype = C.c_char_p
+        L.pmc_load_phase.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp]
+        L.pmc_unload_phase.argtypes = [vp, i32]
+        L.pmc_load_spots.argtypes = [vp, vp, i32, vp, i64]
+        L.pmc_dose.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, C.POINTER(pmc_balance)]
+        L.pmc_dose_device.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp]
+        L.pmc_balance_from_counters.argtypes = [vp, C.POINTER(pmc_request), vp, vp,
+                                                C.POINTER(pmc_balance)]
+        L.pmc_convert_device.argtypes = [vp, i32, vp, u64, vp, vp, vp]
+        L.pmc_trace.argtypes = [vp, i32, i64, u32, u32, u32, vp, i32, C.POINTER(C.c_int32)]
+        L.pmc_split_histories.argtypes = [vp, i64, vp, i32, u64, vp]
+        L.pmc_bytes_in_use.argtypes = [vp]
+        L.pmc_bytes_in_use.restype = u64
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, ctx=None):
+    if rc != PMC_OK:
+        msg = lib().pmc_last_error(ctx).decode(errors="replace")
+        raise PmcError(rc, msg)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+# ----------------------------------------------------------------------------
+# same names as the C ABI
+# ----------------------------------------------------------------------------
+
+def pmc_create(device=0, precision=PMC_FP32, seed=0, hbm_budget_bytes=0):
+    cfg = pmc_config(device, precision, seed, hbm_budget_bytes)
+    h = C.c_void_p()
+    _check(lib().pmc_create(C.byref(cfg), C.byref(h)))
+    return h
+
+
+def pmc_destroy(ctx):
+    lib().pmc_destroy(ctx)
+
+
+def pmc_last_error(ctx=None) -> str:
+    return lib().pmc_last_error(ctx).decode(errors="replace")
+
+
+def pmc_load_phase(ctx, phase_id: int, ph) -> None:
+    hu = np.ascontiguousarray(ph.hu, dtype=np.int16)
+    nz, ny, nx = hu.shape
+    sp = np.ascontiguousarray(ph.spacing_mm, dtype=np.float64)
+    org = np.ascontiguousarray(ph.origin_mm, dtype=np.float64)
+    ch = np.ascontiguousarray(ph.calib_hu, dtype=np.float64)
+    cr = np.ascontiguousarray(ph.calib_rho, dtype=np.float64)
+    cs = np.ascontiguousarray(ph.calib_rsp, dtype=np.float64)
+    mask = None if ph.mask is None else np.ascontiguousarray(ph.mask, dtype=np.uint8)
+    if not (len(ch) == len(cr) == len(cs)):
+        raise ValueError("calibration arrays differ in length")
+    _check(lib().pmc_load_phase(ctx, phase_id, _ptr(hu), nx, ny, nz, _ptr(sp), _ptr(org), _ptr(ch),
+                                _ptr(cr), _ptr(cs), len(ch), _ptr(mask)), ctx)
+
+
+def pmc_unload_phase(ctx, phase_id: int) -> None:
+    _check(lib().pmc_unload_phase(ctx, phase_id), ctx)
+
+
+def pmc_load_spots(ctx, fields: np.ndarray, spots: np.ndarray) -> None:
+    f = np.ascontiguousarray(fields, dtype=FIELD_DTYPE)
+    s = np.ascontiguousarray(spots, dtype=SPOT_DTYPE)
+    _check(lib().pmc_load_spots(ctx, _ptr(f), len(f), _ptr(s), len(s)), ctx)
+
+
+class Request:
+    """A pmc_request that keeps its phase list alive."""
+
+    def __init__(self, n_histories: int, phases: Sequence[int], request_id=0, flags=0,
+                 engine=PMC_ENGINE_PLAIN, block_size=0, chunk=0, refill_min=0, grid_blocks=0):
+        self.phase_arr = np.ascontiguousarray(phases, dtype=np.int32)
+        self.c = pmc_request(request_id, flags, n_histories,
+                             self.phase_arr.ctypes.data_as(C.POINTER(C.c_int32)),
+                             len(self.phase_arr), engine, block_size, chunk, refill_min, grid_blocks)
+
+    @property
+    def n_phases(self):
+        return len(self.phase_arr)
+
+
+def pmc_dose(ctx, req: Request, nvox: Sequence[int], want_dose=True, want_tally=True,
+             want_density=False):
+    """Returns (doses, tallies, densities, balance dict); lists per phase."""
+    n = req.n_phases
+    doses = [np.zeros(v, dtype=np.float64) for v in nvox] if want_dose else None
+    tallies = [np.zeros(v, dtype=np.int64) for v in nvox] if want_tally else None
+    dens = [np.zeros(v, dtype=np.float64) for v in nvox] if want_density else None
+    dp = (C.c_void_p * n)(*[d.ctypes.data for d in doses]) if want_dose else None
+    tp = (C.c_void_p * n)(*[t.ctypes.data for t in tallies]) if want_tally else None
+    rp = (C.c_void_p * n)(*[d.ctypes.data for d in dens]) if want_density else None
+    bal = pmc_balance()
+    _check(lib().pmc_dose(ctx, C.byref(req.c), dp, tp, rp, C.byref(bal)), ctx)
+    return doses, tallies, dens, bal.as_dict()
+
+
+def pmc_dose_device(ctx, req: Request, stream: int, dev_tallies: Sequence[int],
+                    dev_counters: Optional[int]) -> None:
+    tp = (C.c_void_p * req.n_phases)(*[int(p) for p in dev_tallies])
+    _check(lib().pmc_dose_device(ctx, C.byref(req.c), C.c_void_p(stream), tp,
+                                 None if dev_counters is None else C.c_void_p(dev_counters)), ctx)
+
+
+def pmc_balance_from_counters(ctx, req: Request, counters: np.ndarray, deposited: int) -> dict:
+    c = np.ascontiguousarray(counters, dtype=np.uint64)
+    d = np.array([deposited & (2**64 - 1), deposited >> 64], dtype=np.uint64)
+    bal = pmc_balance()
+    _check(lib().pmc_balance_from_counters(ctx, C.byref(req.c), _ptr(c), _ptr(d), C.byref(bal)), ctx)
+    return bal.as_dict()
+
+
+def pmc_convert_device(ctx, phase_id: int, dev_tally: int, n_histories: int, stream: int,
+                       dev_dose: Optional[int], dev_density: Optional[int]) -> None:
+    _check(lib().pmc_convert_device(ctx, phase_id, C.c_void_p(dev_tally), n_histories,
+                                    C.c_void_p(stream), None if dev_dose is None else C.c_void_p(dev_dose),
+                                    None if dev_density is None else C.c_void_p(dev_density)), ctx)
+
+
+def pmc_trace(ctx, phase_id: int, spot: int, history: int, request_id=0, flags=0,
+              max_rec=100_000) -> np.ndarray:
+    rec = np.zeros(max_rec, dtype=TRACE_DTYPE)
+    n = C.c_int32(0)
+    _check(lib().pmc_trace(ctx, phase_id, spot, history, request_id, flags, _ptr(rec), max_rec,
+                           C.byref(n)), ctx)
+    if n.value > max_rec:
+        raise ValueError(f"trace longer than {max_rec} records")
+    return rec[: n.value].copy()
+
+
+def pmc_split_histories(spots: np.ndarray, phases: Sequence[int], n_histories: int) -> np.ndarray:
+    s = np.ascontiguousarray(spots, dtype=SPOT_DTYPE)
+    ph = np.ascontiguousarray(phases, dtype=np.int32)
+    out = np.zeros(len(s), dtype=np.int64)
+    _check(lib().pmc_split_histories(_ptr(s), len(s), _ptr(ph), len(ph), n_histories, _ptr(out)))
+    return out
+
+
+def pmc_bytes_in_use(ctx) -> int:
+    return int(lib().pmc_bytes_in_use(ctx))
+
+
+# ----------------------------------------------------------------------------
+# convenience wrapper
+# ----------------------------------------------------------------------------
+
+class Engine:
+    """Owns a context; loads a Workload's phases and plan."""
+
+    def __init__(self, device=0, precision=PMC_FP32, seed=0, hbm_budget_bytes=0):
+        self.ctx = pmc_create(device, precision, seed, hbm_budget_bytes)
+        self.nvox = {}
+
+    def close(self):
+        if self.ctx:
+            pmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_phase(self, phase_id: int, ph):
+        pmc_load_phase(self.ctx, phase_id, ph)
+        self.nvox[phase_id] = ph.nvox
+
+    def load_plan(self, plan):
+        pmc_load_spots(self.ctx, plan.fields, plan.spots)
+
+    def load_workload(self, wl):
+        for i, ph in enumerate(wl.phases):
+            self.load_phase(i, ph)
+        self.load_plan(wl.plan)
+
+    def dose(self, n_histories: int, phases: Sequence[int], request_id=0, flags=0,
+             engine=PMC_ENGINE_PLAIN, want_density=False, **launch):
+        req = Request(n_histories, phases, request_id, flags, engine, **launch)
+        return pmc_dose(self.ctx, req, [self.nvox[p] for p in phases], want_density=want_density)
+
+    def trace(self, phase_id, spot, history, request_id=0, flags=0, max_rec=100_000):
+        return pmc_trace(self.ctx, phase_id, spot, history, request_id, flags, max_rec)

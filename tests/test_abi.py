@@ -1,0 +1,156 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates arguments before any device work (using a
+validation-only context, device = -1) and computes the history split exactly
+as the oracle does."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1809_03927_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1809_03927_amd import pmc
+    if not os.path.exists(pmc.LIB_PATH):
+        from paper_1809_03927_amd import build
+        build.build()
+    return pmc
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "pmc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(pmc_[a-z_]+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_header_symbol(P):
+    names = header_functions()
+    assert len(names) >= 13
+    lib = C.CDLL(P.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(P.EXPORTS) == names
+
+
+def test_struct_layouts_match_header(P):
+    assert C.sizeof(P.pmc_config) == 24
+    assert C.sizeof(P.pmc_request) == 48
+    assert C.sizeof(P.pmc_balance) == 8 * 16
+    assert W.SPOT_DTYPE.itemsize == 48 and W.FIELD_DTYPE.itemsize == 72
+    assert P.TRACE_DTYPE.itemsize == 120
+
+
+@pytest.fixture()
+def vctx(P):
+    ctx = P.pmc_create(device=-1)
+    yield ctx
+    P.pmc_destroy(ctx)
+
+
+def test_create_rejects_bad_config(P):
+    with pytest.raises(P.PmcError) as e:
+        P.pmc_create(device=-1, precision=7)
+    assert e.value.code == P.PMC_E_INVAL
+    assert "precision" in P.pmc_last_error(None)
+    P.pmc_destroy(None)  # NULL-safe
+
+
+def test_load_phase_validation(P, vctx):
+    ph = W.make_water(8, 2.0)
+    P.pmc_load_phase(vctx, 0, ph)  # valid
+    bad = W.make_water(8, 2.0)
+    bad.calib_hu = np.array([0.0, 0.0])
+    bad.calib_rho = np.array([1.0, 1.0])
+    bad.calib_rsp = np.array([1.0, 1.0])
+    with pytest.raises(P.PmcError) as e:
+        P.pmc_load_phase(vctx, 1, bad)
+    assert e.value.code == P.PMC_E_INVAL and "increasing" in str(e.value)
+    bad = W.make_water(8, 2.0)
+    bad.spacing_mm = (2.0, 0.0, 2.0)
+    with pytest.raises(P.PmcError):
+        P.pmc_load_phase(vctx, 1, bad)
+    bad = W.make_water(8, 2.0)
+    bad.calib_rho = bad.calib_rho.copy()
+    bad.calib_rho[0] = np.nan
+    with pytest.raises(P.PmcError):
+        P.pmc_load_phase(vctx, 1, bad)
+    with pytest.raises(P.PmcError):
+        P.pmc_load_phase(vctx, 5000, ph)
+
+
+def test_load_spots_validation(P, vctx):
+    plan = W.plan_single(150.0, 5.0)
+    P.pmc_load_spots(vctx, plan.fields, plan.spots)
+    for field, val in [("energy_MeV", 0.5), ("energy_MeV", 301.0), ("weight", 0.0),
+                       ("sigma_mm", -1.0), ("field", 3), ("energy_MeV", np.nan)]:
+        s = plan.spots.copy()
+        s[field] = val
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_load_spots(vctx, plan.fields, s)
+        assert e.value.code == P.PMC_E_INVAL
+    f = plan.fields.copy()
+    f["bev_u"] = (0.0, 0.0, 1.0)  # parallel to the beam
+    with pytest.raises(P.PmcError):
+        P.pmc_load_spots(vctx, f, plan.spots)
+
+
+def test_dose_validation_order(P, vctx):
+    req = P.Request(1000, [0])
+    with pytest.raises(P.PmcError) as e:
+        P.pmc_dose(vctx, req, [8 ** 3])
+    assert e.value.code == P.PMC_E_STATE  # no plan yet
+    plan = W.plan_single(150.0, 5.0)
+    P.pmc_load_spots(vctx, plan.fields, plan.spots)
+    with pytest.raises(P.PmcError) as e:
+        P.pmc_dose(vctx, req, [8 ** 3])
+    assert e.value.code == P.PMC_E_NOPHASE
+    P.pmc_load_phase(vctx, 0, W.make_water(8, 2.0))
+    with pytest.raises(P.PmcError) as e:
+        P.pmc_dose(vctx, P.Request(P.PMC_MAX_HISTORIES + 1, [0]), [8 ** 3])
+    assert e.value.code == P.PMC_E_RANGE
+    with pytest.raises(P.PmcError) as e:
+        P.pmc_dose(vctx, P.Request(0, [0]), [8 ** 3])
+    assert e.value.code == P.PMC_E_INVAL
+    with pytest.raises(P.PmcError) as e:
+        P.pmc_dose(vctx, P.Request(10, [0, 0]), [8 ** 3, 8 ** 3])
+    assert e.value.code == P.PMC_E_INVAL
+    with pytest.raises(P.PmcError) as e:
+        P.pmc_dose(vctx, P.Request(10, [0], block_size=100), [8 ** 3])
+    assert e.value.code == P.PMC_E_INVAL
+    # all arguments valid: the validation-only context reports the missing device
+    with pytest.raises(P.PmcError) as e:
+        P.pmc_dose(vctx, req, [8 ** 3])
+    assert e.value.code == P.PMC_E_DEVICE
+    P.pmc_unload_phase(vctx, 0)
+    with pytest.raises(P.PmcError) as e:
+        P.pmc_unload_phase(vctx, 0)
+    assert e.value.code == P.PMC_E_NOPHASE
+
+
+@pytest.mark.parametrize("wl_name", ["slabs", "thorax"])
+def test_split_matches_oracle(P, orc, wl_name):
+    plan = W.plan_slabs(2) if wl_name == "slabs" else W.plan_thorax(3)
+    phases = sorted(set(plan.spots["phase"].tolist()))
+    for n in (1, 7, 12345, 10_000_000, 50_000_000):
+        a = P.pmc_split_histories(plan.spots, phases, n)
+        b = orc.split_histories(plan.spots, phases, n)
+        assert np.array_equal(a, b) and a.sum() == n
+    sub = phases[:3]
+    assert np.array_equal(P.pmc_split_histories(plan.spots, sub, 99_999),
+                          orc.split_histories(plan.spots, sub, 99_999))
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1809_03927_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "pmc_oracle" not in txt and "liboracle" not in txt, f
