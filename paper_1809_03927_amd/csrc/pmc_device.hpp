@@ -66,8 +66,15 @@ template <> struct M<float> {
   static __device__ __forceinline__ float uni(uint32_t x) {
     return ((float)(x >> 8) + 0.5f) * 0x1p-24f;
   }
-  // fixed-point energy: E * 2^32 is an integer for any float E >= 2^-9
-  static __device__ __forceinline__ long long q(float E) { return (long long)(E * 4294967296.0f); }
+  // fixed-point energy Q(E) = E * 2^32, exact for float E >= 2^-9: with
+  // E = m 2^(e-23) (m the 24-bit significand) it is m << (e + 9).  Transport
+  // only asks for E >= 1 MeV (or exactly 0).
+  static __device__ __forceinline__ long long q(float E) {
+    const uint32_t b = __float_as_uint(E);
+    const int sh = (int)(b >> 23) - 127 + 9;
+    const unsigned long long m = (unsigned long long)((b & 0x7FFFFFu) | 0x800000u);
+    return E == 0.0f ? 0ll : (long long)(m << sh);
+  }
   static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
   static __device__ __forceinline__ float fmax(float a, float b) { return __builtin_fmaxf(a, b); }
   static __device__ __forceinline__ float fmin(float a, float b) { return __builtin_fminf(a, b); }
@@ -101,10 +108,12 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
                                         uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    // 32 x 32 -> 64-bit products: one multiply-add instruction each
+    const unsigned long long p0 = (unsigned long long)c0 * 0xD2511F53u;
+    const unsigned long long p1 = (unsigned long long)c2 * 0xCD9E8D57u;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -120,6 +129,7 @@ template <typename R> struct Lane {
   R E;            // kinetic energy, MeV
   R nd, nn;       // remaining delta / nuclear interaction lengths (mean free paths)
   R lacc;         // accumulated mass path for scattering, g/cm^2
+  R lg;           // log2(lacc) (unused while lacc == 0)
   int32_t ix, iy, iz;
   int32_t v;      // linear voxel index
   int32_t hu;     // HU of the current voxel (clamped LUT index)
@@ -147,6 +157,7 @@ template <typename R> struct Geo {
   int32_t n[3];
   int32_t nxy;
   R d[3];
+  int32_t lut;  // index of the phase's LUT in the launch's LUT array
 };
 
 // physics tables: (R, mu_delta, omega^2, 0) per node, linear in log2 E
@@ -204,34 +215,50 @@ __device__ __forceinline__ R range_inverse(const Tab<R> &T, R Rn, int i) {
     rlo = T.t[lo].x;
   }
   const R rhi = T.t[lo + 1].x;
-  const R f = (Rn - rlo) / (rhi - rlo);
+  const R f = M<R>::div(Rn - rlo, rhi - rlo);
   return M<R>::exp2(T.l2e0 + T.dl2 * ((R)lo + f));
 }
 
-template <typename R> struct Kin { R beta2, tmax, pbc; };
+template <typename R> struct Kin { R beta2, pbc, b2g2, g; };
 
 template <typename R>
 __device__ __forceinline__ Kin<R> kinematics(R E) {
+  using MM = M<R>;
   const R tau = E * (R)(1.0 / kMp);
-  const R g = (R)1 + tau;
-  const R b2g2 = tau * (tau + (R)2);
-  const R r = (R)(kMe / kMp);
   Kin<R> k;
-  k.beta2 = b2g2 / (g * g);
-  k.tmax = (R)(2.0 * kMe) * b2g2 / ((R)1 + (R)2 * g * r + r * r);
-  k.pbc = E * (E + (R)(2.0 * kMp)) / (E + (R)kMp);
+  k.g = (R)1 + tau;
+  k.b2g2 = tau * (tau + (R)2);  // (beta gamma)^2
+  const R ig = MM::rcp(k.g);
+  k.beta2 = k.b2g2 * ig * ig;
+  k.pbc = (R)kMp * k.b2g2 * ig;  // p beta c = (pc)^2 / E_total
   return k;
 }
 
-// Highland projected-angle variance for mass path L at the given kinematics
 template <typename R>
-__device__ __forceinline__ R highland2(const Kin<R> &k, R L) {
+__device__ __forceinline__ R tmax_of(const Kin<R> &k) {
+  const R r = (R)(kMe / kMp);
+  return M<R>::div((R)(2.0 * kMe) * k.b2g2, (R)1 + (R)2 * k.g * r + r * r);
+}
+
+// Highland projected-angle variance: theta^2(L) = A L c(L)^2 with
+// A = (13.6 / p beta c)^2 / X0 and c(L) = 1 + 0.038 ln(L / (X0 beta^2)).
+// ln L is carried from step to step (lg = log2 L of the accumulated path).
+template <typename R> struct Highland { R A, lb; };
+
+template <typename R>
+__device__ __forceinline__ Highland<R> highland_at(const Kin<R> &k) {
+  Highland<R> h;
+  const R a = (R)13.6 * M<R>::rcp(k.pbc);
+  h.A = a * a * (R)(1.0 / kX0);
+  h.lb = M<R>::log2((R)kX0 * k.beta2);
+  return h;
+}
+
+template <typename R>
+__device__ __forceinline__ R highland2(const Highland<R> &h, R L, R lg) {
   if (!(L > (R)0)) return (R)0;
-  const R x = L * (R)(1.0 / kX0);
-  // ln(x / beta^2) via log2
-  const R c = (R)1 + (R)(0.038 * 0.69314718055994530942) * M<R>::log2(x / k.beta2);
-  const R a = (R)13.6 / k.pbc;
-  return a * a * x * c * c;
+  const R c = (R)1 + (R)(0.038 * 0.69314718055994530942) * (lg - h.lb);
+  return h.A * L * c * c;
 }
 
 // polar rotation of the unit direction w by (theta, phi = 2 pi u_phi)
@@ -299,6 +326,7 @@ __device__ __forceinline__ void start_history(Lane<R> &L, const SpotDev<R> &sp, 
   L.spot = spot;
   L.b = 1u;
   L.lacc = (R)0;
+  L.lg = (R)0;
   L.nsteps = 0;
   L.acc_v = -1;
   L.acc = 0;
@@ -318,7 +346,8 @@ __device__ __forceinline__ void start_history(Lane<R> &L, const SpotDev<R> &sp, 
   for (int k = 0; k < 3; ++k) {
     const R ext = (R)G.n[k] * G.d[k];
     if (L.w[k] != (R)0) {
-      const R t1 = ((R)0 - p[k]) / L.w[k], t2 = (ext - p[k]) / L.w[k];
+      const R iw = M<R>::div((R)1, L.w[k]);
+      const R t1 = ((R)0 - p[k]) * iw, t2 = (ext - p[k]) * iw;
       const R lo = t1 < t2 ? t1 : t2, hi = t1 < t2 ? t2 : t1;
       if (lo > tn) { tn = lo; an = k; }
       if (hi < tf) tf = hi;
@@ -338,7 +367,7 @@ __device__ __forceinline__ void start_history(Lane<R> &L, const SpotDev<R> &sp, 
       i = L.w[k] > (R)0 ? 0 : G.n[k] - 1;
       l = L.w[k] > (R)0 ? (R)0 : G.d[k];
     } else {
-      i = (int)floor(r[k] / G.d[k]);
+      i = (int)floor(M<R>::div(r[k], G.d[k]));
       i = i < 0 ? 0 : (i > G.n[k] - 1 ? G.n[k] - 1 : i);
       l = r[k] - (R)i * G.d[k];
     }
@@ -506,11 +535,13 @@ __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &
     if (cause == kDelta) L.nd = (R)0;
     if (cause == kNuc) L.nn = (R)0;
     // 8. telescoping Highland at the pre-step energy
-    const Kin<R> kp = kinematics(E_pre);
+    const Highland<R> hp = highland_at(kinematics(E_pre));
     const R l_new = L.lacc + rho * s;
-    R th2 = highland2(kp, l_new) - highland2(kp, L.lacc);
+    const R lg_new = l_new > (R)0 ? MM::log2(l_new) : (R)0;
+    R th2 = highland2(hp, l_new, lg_new) - highland2(hp, L.lacc, L.lg);
     th2 = th2 < (R)0 ? (R)0 : th2;
     L.lacc = l_new;
+    L.lg = lg_new;
     if (L.fate == kAlive && !(flags & kNoMcs) && th2 > (R)0) {
       const R theta = MM::sqrt(th2) * MM::sqrt((R)-2 * (LN2 * MM::log2(MM::uni(x.z))));
       rotate(L.w, theta, MM::uni(x.w));
@@ -525,9 +556,10 @@ __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &
     // 10. events at the step end
     if (L.fate == kAlive && cause == kDelta) {
       const Kin<R> k = kinematics(L.E);
-      if (k.tmax > (R)kTcut) {
-        const R a = (R)(1.0 / kTcut), bt = (R)(1.0 / kTcut) - MM::div((R)1, k.tmax);
-        const R cb = MM::div(k.beta2, k.tmax);
+      const R tmax = tmax_of(k);
+      if (tmax > (R)kTcut) {
+        const R a = (R)(1.0 / kTcut), bt = (R)(1.0 / kTcut) - MM::div((R)1, tmax);
+        const R cb = MM::div(k.beta2, tmax);
         R T_d = (R)kTcut;
         // acceptance is >= 1/2 per trial; the bound only guarantees termination
         for (int trial = 0; trial < 4096; ++trial) {

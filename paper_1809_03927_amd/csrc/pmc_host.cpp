@@ -476,7 +476,7 @@ int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
     a.k0 = k0;
     a.k1 = k1;
     a.flags = req->flags;
-    a.refill_min = req->refill_min ? req->refill_min : 16;
+    a.refill_min = req->refill_min ? req->refill_min : 64;
     a.block = req->block_size ? req->block_size : 256;
     a.lut_lds = !fp64 && P.same_lut;
     a.cursor = (unsigned long long *)ctx->cursor.p;

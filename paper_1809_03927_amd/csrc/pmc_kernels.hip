@@ -78,6 +78,7 @@ __device__ __forceinline__ Geo<R> geo_of(const TargetDev &t) {
   g.n[0] = t.nx; g.n[1] = t.ny; g.n[2] = t.nz;
   g.nxy = t.nx * t.ny;
   g.d[0] = (R)t.d[0]; g.d[1] = (R)t.d[1]; g.d[2] = (R)t.d[2];
+  g.lut = t.lut;
   return g;
 }
 
@@ -149,13 +150,14 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
   using R4 = typename M<R>::R4;
   R4 *tab_s = reinterpret_cast<R4 *>(smem);
   R2 *lut_s = reinterpret_cast<R2 *>(smem + Smem<R>::tab_bytes);
-  TargetDev *tg_s = reinterpret_cast<TargetDev *>(smem + Smem<R>::tab_bytes +
-                                                  (LUT_LDS ? Smem<R>::lut_bytes : 0));
-  unsigned long long *red = reinterpret_cast<unsigned long long *>(tg_s + n_targets);
+  // per-target geometry in the working precision, converted once per block
+  Geo<R> *geo_s = reinterpret_cast<Geo<R> *>(smem + Smem<R>::tab_bytes +
+                                             (LUT_LDS ? Smem<R>::lut_bytes : 0));
+  unsigned long long *red = reinterpret_cast<unsigned long long *>(geo_s + n_targets);
   for (int i = threadIdx.x; i < kNtab; i += blockDim.x) tab_s[i] = tab_g[i];
   if constexpr (LUT_LDS)
     for (int i = threadIdx.x; i < kLutSize; i += blockDim.x) lut_s[i] = luts_g[i];
-  for (int i = threadIdx.x; i < n_targets; i += blockDim.x) tg_s[i] = targets[i];
+  for (int i = threadIdx.x; i < n_targets; i += blockDim.x) geo_s[i] = geo_of<R>(targets[i]);
   __syncthreads();
 
   Tab<R> T;
@@ -194,8 +196,7 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
         if (mine) {
           const SpotDev<R> &sp = spots[it_spot];
           tgt = sp.target;
-          const Geo<R> G = geo_of<R>(tg_s[tgt]);
-          start_history(L, sp, it_spot, it_next + rank, G, k0, k1, C);
+          start_history(L, sp, it_spot, it_next + rank, geo_s[tgt], k0, k1, C);
         }
         it_next += take;
         idle = __ballot(me_idle && !mine);
@@ -207,9 +208,8 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
       continue;
     }
     if (alive) {
-      const TargetDev &td = tg_s[tgt];
-      const Geo<R> G = geo_of<R>(td);
-      const R2 *lut = LUT_LDS ? lut_s : luts_g + (size_t)td.lut * kLutSize;
+      const Geo<R> G = geo_s[tgt];
+      const R2 *lut = LUT_LDS ? lut_s : luts_g + (size_t)G.lut * kLutSize;
       step<R, false>(L, G, T, lut, k0, k1, flags, C, nullptr, 0);
       if (L.fate != kAlive) flush_tally(L, G);
     }
@@ -313,7 +313,7 @@ static hipError_t launch_persistent_t(const PersistentLaunch &a, hipStream_t st)
 template <typename R>
 static size_t persistent_lds(const PersistentLaunch &a) {
   return Smem<R>::tab_bytes + (a.lut_lds ? Smem<R>::lut_bytes : 0) +
-         sizeof(TargetDev) * (size_t)a.n_targets + sizeof(unsigned long long) * 12 * (a.block / 64 + 1);
+         sizeof(Geo<R>) * (size_t)a.n_targets + sizeof(unsigned long long) * 12 * (a.block / 64 + 1);
 }
 
 template <typename R>
