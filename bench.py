@@ -2,19 +2,22 @@
 
 One step = one full 4D dose calculation of the thorax workload (10 breathing
 phases of 256x256x160 voxels, 3000 spots assigned to phases by the delivery
-clock, 5e7 histories): zero the int64 tallies, run the transport of all
-phases (one persistent launch: work queue + lane refill; or, for the plain
-engine, one launch per phase), and convert every phase's tally to dose.
-Inputs (phantoms, tables, plan) are resident on the device before timing.
+clock, 5e7 histories): zero the int64 tallies, transport all phases, convert
+every phase's tally to dose.  Inputs (phantoms, tables, plan) are resident on
+the device before timing.
 
-Prints one JSON line.  `value` is histories/s of the batched (persistent)
-engine; the plain engine's rate on the same workload is reported beside it.
+Batched engine (the reported value): one persistent launch over a work queue
+of all phases with an autotuned launch shape, the whole step captured in a
+HIP graph and replayed.  Plain engine (reported beside it): one launch per
+phase, one history per thread, no refill, no graph.  Both give identical
+integer tallies (checked).
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -27,12 +30,18 @@ if ROOT not in sys.path:
 # VALU instruction occupies a SIMD for 4 cycles, so the chip issues at most
 # 256 * 4 * 16 * 2.4e9 = 3.93e13 full-rate lane operations per second.
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-HBM_PEAK_GBS = 8000.0
 
-# VALU instructions one lane executes per transport step, measured with the
-# SQ_INSTS_VALU counter on single-history launches of the FP32 kernel (see
-# profiles/transport_valu_per_step.md).
-VALU_PER_STEP = float(os.environ.get("PMC_VALU_PER_STEP", "0") or 0) or None
+# VALU instructions one lane executes per transport step of the FP32 kernel:
+# SQ_INSTS_VALU of single-history launches (one active lane) divided by their
+# step count (profiles/transport_valu_per_step_thorax.md).
+VALU_PER_STEP = 448.0
+
+# HBM-side bytes of one full-size transport launch (5e7 histories of the
+# thorax 4D workload), from FETCH_SIZE and WRITE_SIZE scaled by a 4 GiB copy
+# calibration (profiles/transport_thorax4d_counters.md).  Valid only for the
+# kernel sources they were measured on (hash below); otherwise reported null.
+PROFILED_TRAFFIC_BYTES = 282.3e9
+PROFILED_KERNEL_HASH = "633caf8f6a1719c7"
 
 
 def log(*a):
@@ -47,26 +56,40 @@ def parse():
     p.add_argument("--plain-steps", type=int, default=2)
     p.add_argument("--histories", type=int, default=50_000_000)
     p.add_argument("--grid", type=str, default="256,256,160")
-    p.add_argument("--chunk", type=int, default=0)
-    p.add_argument("--block", type=int, default=0)
-    p.add_argument("--refill", type=int, default=0)
+    p.add_argument("--no-tune", action="store_true", help="library default launch shape")
+    p.add_argument("--tune-cache", type=str, default=None)
+    p.add_argument("--no-graph", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-atomic-probe", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
-    p.add_argument("--mode", choices=["bench", "single-history"], default="bench")
+    p.add_argument("--mode", choices=["bench", "single-history", "copy-calibration"], default="bench")
     return p.parse_args()
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this engine runs on one GPU; multi-GPU sharding is a design "
-                                   "note only (see DESIGN.md)", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "this engine runs on one GPU; sharding over several GPUs is a "
+                                   "design note only", "n_gpus": a.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_1809_03927_amd import pmc
+    from paper_1809_03927_amd import autotune, pmc
     from paper_1809_03927_amd import workloads as W
+
+    if a.mode == "copy-calibration":
+        # plain device-to-device copies of 4 GiB (far larger than the 256 MB
+        # last-level cache): the HBM counters of these dispatches calibrate
+        # FETCH_SIZE / WRITE_SIZE (expected 4 GiB read and 4 GiB written each)
+        n = 1 << 29
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy-calibration", "bytes_per_copy": n * 8, "copies": 3}))
+        return
 
     grid = tuple(int(x) for x in a.grid.split(","))
     t0 = time.time()
@@ -83,131 +106,185 @@ def main():
     doses = [torch.zeros(nvox, dtype=torch.float64, device=dev) for _ in phases]
     counters = torch.zeros(pmc.PMC_COUNTERS, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
+    tptr = [t.data_ptr() for t in tallies]
 
     if a.mode == "single-history":
-        # one history per launch: VALU instructions per step of one lane
-        req = pmc.Request(1, [0], engine=pmc.PMC_ENGINE_PLAIN, block_size=64)
+        # one history per launch (one active lane): VALU instructions per step
         one = W.workload_thorax4d(1, shape_xyz=grid)
         one.plan.spots = one.plan.spots[:1].copy()
         one.plan.spots["phase"] = 0
         eng.load_plan(one.plan)
+        req = pmc.Request(1, [0], engine=pmc.PMC_ENGINE_PLAIN, block_size=64)
         for _ in range(20):
             counters.zero_()
-            pmc.pmc_dose_device(eng.ctx, req, stream.cuda_stream, [tallies[0].data_ptr()],
-                                counters.data_ptr())
+            pmc.pmc_dose_device(eng.ctx, req, stream.cuda_stream, [tptr[0]], counters.data_ptr())
         torch.cuda.synchronize()
-        c = counters.cpu().numpy().astype(np.uint64)
-        log(f"single-history launches: steps/launch {int(c[7])}")
+        c = counters.cpu().numpy()
         print(json.dumps({"mode": "single-history", "steps_per_launch": int(c[7]), "launches": 20}))
         return
 
+    # ---- launch shape ----------------------------------------------------
+    tuned = {"block_size": 0, "chunk": 0, "refill_min": 0}
+    if not a.no_tune:
+        e = wl.plan.spots["energy_MeV"]
+        key = autotune.shape_key(torch.cuda.get_device_name(0), [grid] * len(phases),
+                                 len(wl.plan.spots), wl.n_histories, (float(e.min()), float(e.max())))
+        t1 = time.time()
+        tuned = autotune.tune(eng.ctx, phases, key, tptr, counters.data_ptr(), stream.cuda_stream,
+                              torch.cuda.synchronize, max(wl.n_histories // 10, 100_000),
+                              request_id=wl.request_id,
+                              cache_path=a.tune_cache or autotune.DEFAULT_CACHE)
+        log(f"autotune ({time.time() - t1:.1f} s): block {tuned['block_size']} chunk "
+            f"{tuned['chunk']} refill {tuned['refill_min']}")
+
     def make_req(engine):
-        return pmc.Request(wl.n_histories, phases, request_id=wl.request_id, engine=engine,
-                           block_size=a.block, chunk=a.chunk, refill_min=a.refill)
+        kw = {}
+        if engine == pmc.PMC_ENGINE_PERSISTENT:
+            kw = dict(block_size=tuned["block_size"], chunk=tuned["chunk"],
+                      refill_min=tuned["refill_min"])
+        return pmc.Request(wl.n_histories, phases, request_id=wl.request_id, engine=engine, **kw)
 
-    ev_a = torch.cuda.Event(enable_timing=True)
-    ev_b = torch.cuda.Event(enable_timing=True)
-
-    def one_step(req, kernel_ms):
+    def eager_step(req):
         for t in tallies:
             t.zero_()
         counters.zero_()
-        ev_a.record(stream)
-        pmc.pmc_dose_device(eng.ctx, req, stream.cuda_stream, [t.data_ptr() for t in tallies],
-                            counters.data_ptr())
-        ev_b.record(stream)
+        pmc.pmc_dose_device(eng.ctx, req, stream.cuda_stream, tptr, counters.data_ptr())
         for i, p in enumerate(phases):
-            pmc.pmc_convert_device(eng.ctx, p, tallies[i].data_ptr(), wl.n_histories,
-                                   stream.cuda_stream, doses[i].data_ptr(), None)
-        kernel_ms.append((ev_a, ev_b))
-
-    def run(engine, steps, warmup):
-        req = make_req(engine)
-        scratch = []
-        for _ in range(warmup):
-            one_step(req, scratch)
-        torch.cuda.synchronize()
-        spans = []
-        ts = time.perf_counter()
-        for _ in range(steps):
-            k = []
-            one_step(req, k)
-            torch.cuda.synchronize()  # events are reused: read them per step
-            spans.append(k[0][0].elapsed_time(k[0][1]))
-        torch.cuda.synchronize()
-        te = time.perf_counter()
-        return req, (te - ts) / steps, spans
+            pmc.pmc_convert_device(eng.ctx, p, tptr[i], wl.n_histories, stream.cuda_stream,
+                                   doses[i].data_ptr(), None)
 
     def balance(req):
         c = counters.cpu().numpy().astype(np.uint64)
         dep = 0
         for t in tallies:
-            lo = int((t & 0xFFFFFFFF).sum().item())
-            hi = int((t >> 32).sum().item())
-            dep += (hi << 32) + lo
-        return pmc.pmc_balance_from_counters(eng.ctx, req, c, dep)
+            dep += (int((t >> 32).sum().item()) << 32) + int((t & 0xFFFFFFFF).sum().item())
+        b = pmc.pmc_balance_from_counters(eng.ctx, req, c, dep)
+        b["atomics"] = int(c[12])
+        return b
 
-    log(f"batched engine: warmup {a.warmup}, steps {a.steps}")
-    req_b, sec_b, spans_b = run(pmc.PMC_ENGINE_PERSISTENT, a.steps, a.warmup)
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        ts = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        return (te - ts) / steps, [e0.elapsed_time(e1) for e0, e1 in ev]
+
+    # ---- batched engine: graph replay of the whole step --------------------
+    req_b = make_req(pmc.PMC_ENGINE_PERSISTENT)
+    graph = None
+    if not a.no_graph:
+        eager_step(req_b)  # builds the request data once
+        torch.cuda.synchronize()
+        graph = pmc.pmc_graph_create(eng.ctx, req_b, tptr, counters.data_ptr(),
+                                     [d.data_ptr() for d in doses])
+        step_b = lambda: pmc.pmc_graph_launch(graph, stream.cuda_stream, eng.ctx)
+    else:
+        step_b = lambda: eager_step(req_b)
+    log(f"batched engine ({'graph' if graph else 'eager'}): warmup {a.warmup}, steps {a.steps}")
+    sec_b, spans_b = timed(step_b, a.steps, a.warmup)
     bal = balance(req_b)
     assert bal["deposited"] + bal["escaped"] + bal["nuclear"] == bal["incident"], bal
     assert bal["histories"] == wl.n_histories
-    steps_per_run = bal["steps"]
-    kern_ms = float(np.mean(spans_b))
-    log(f"batched: {sec_b * 1e3:.1f} ms/step, transport kernel {kern_ms:.1f} ms, "
-        f"{steps_per_run / wl.n_histories:.1f} steps/history, balance exact")
-    value = wl.n_histories / sec_b
+    tal_b = [t.clone() for t in tallies]
+    log(f"batched: {sec_b * 1e3:.1f} ms/step (GPU {np.mean(spans_b):.1f} ms), "
+        f"{bal['steps'] / wl.n_histories:.1f} steps/history, balance exact")
+
+    # transport kernel alone, same launch shape, timed with events on its stream
+    def transport_only():
+        pmc.pmc_dose_device(eng.ctx, req_b, stream.cuda_stream, tptr, counters.data_ptr())
+    _, spans_k = timed(transport_only, max(2, min(a.steps, 3)), 0)
+    kern_ms = float(np.mean(spans_k))
 
     plain = None
     if not a.no_plain and a.plain_steps > 0:
+        req_p = make_req(pmc.PMC_ENGINE_PLAIN)
         log(f"plain engine: steps {a.plain_steps}")
-        req_p, sec_p, spans_p = run(pmc.PMC_ENGINE_PLAIN, a.plain_steps, 1)
+        sec_p, spans_p = timed(lambda: eager_step(req_p), a.plain_steps, 1)
         balp = balance(req_p)
-        assert balp == bal, (balp, bal)  # same keys: the integer results are identical
+        same = all(torch.equal(x, y) for x, y in zip(tal_b, tallies))
+        assert same and balp["deposited"] == bal["deposited"], "plain and batched tallies differ"
         plain = {"value": wl.n_histories / sec_p, "ms_per_step": sec_p * 1e3,
-                 "transport_ms": float(np.mean(spans_p)),
-                 "speedup_batched_vs_plain": (wl.n_histories / sec_b) / (wl.n_histories / sec_p)}
-        log(f"plain: {sec_p * 1e3:.1f} ms/step (x{plain['speedup_batched_vs_plain']:.2f} batched)")
+                 "speedup_batched_vs_plain": sec_p / sec_b, "tallies_identical": same}
+        log(f"plain: {sec_p * 1e3:.1f} ms/step -> batched is x{sec_p / sec_b:.3f}")
 
-    lane_steps_per_s = steps_per_run / (kern_ms * 1e-3)
-    if VALU_PER_STEP:
-        achieved = lane_steps_per_s * VALU_PER_STEP
-        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                    "unit": "T lane-VALU-instr/s", "frac": achieved / PEAK_LANE_OPS,
-                    "traffic": None, "valu_per_step": VALU_PER_STEP,
-                    "lane_steps_per_s": lane_steps_per_s, "kernel": "transport_persistent",
-                    "kernel_ms": kern_ms}
-    else:
-        roofline = {"bound": "alu", "achieved": None, "peak": PEAK_LANE_OPS / 1e12,
-                    "unit": "T lane-VALU-instr/s", "frac": None, "traffic": None,
-                    "lane_steps_per_s": lane_steps_per_s, "kernel": "transport_persistent",
-                    "kernel_ms": kern_ms}
+    atomic_peak = None
+    if not a.no_atomic_probe:
+        atomic_peak = atomic_probe(torch, nvox)
+        log(f"int64 atomic probe (torch index_add_, random voxels): {atomic_peak / 1e9:.1f} G/s")
 
-    cpu = None
-    if not a.no_cpu_baseline:
-        cpu = cpu_baseline(wl, a.cpu_seconds)
-
+    lane_steps_s = bal["steps"] / (kern_ms * 1e-3)
+    achieved = lane_steps_s * VALU_PER_STEP
+    default_cfg = wl.n_histories == 50_000_000 and grid == (256, 256, 160)
+    traffic = (PROFILED_TRAFFIC_BYTES if default_cfg and kernel_hash() == PROFILED_KERNEL_HASH
+               else None)
+    roofline = {
+        "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+        "unit": "T lane-VALU-instr/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+        "traffic_unit": "bytes per launch (HBM side: fetches + 32 B per memory-side atomic)",
+        "kernel": "transport_persistent<float>", "kernel_ms": kern_ms,
+        "valu_per_step": VALU_PER_STEP, "lane_steps_per_s": lane_steps_s,
+        "atomics_per_s": bal["atomics"] / (kern_ms * 1e-3),
+        "atomic_probe_per_s": atomic_peak,
+        "atomic_frac": (bal["atomics"] / (kern_ms * 1e-3) / atomic_peak) if atomic_peak else None,
+    }
+    cpu = None if a.no_cpu_baseline else cpu_baseline(wl, a.cpu_seconds)
     out = {
-        "metric": "proton histories/s (batched 4D dose, one persistent launch over 10 phases)",
-        "value": value, "unit": "histories/s", "n_gpus": 1, "steps": a.steps,
+        "metric": "proton histories/s (batched 4D dose: 10 phases in one persistent launch, graph replay)",
+        "value": wl.n_histories / sec_b, "unit": "histories/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": sec_b * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 transport, int64 tally",
         "data": "synthetic (seeded thorax phantom and plan; no patient data)",
-        "config": {"workload": "thorax4d 10 phases x 256x256x160 @1.5x1.5x2 mm, 3000 spots, "
-                               f"{wl.n_histories:.0e} histories",
+        "config": {"workload": f"thorax4d: 10 phases x {grid[0]}x{grid[1]}x{grid[2]} @1.5x1.5x2 mm, "
+                               f"3000 spots, {wl.n_histories:.0e} histories",
                    "phases": len(phases), "grid": list(grid), "spots": int(len(wl.plan.spots)),
-                   "histories": wl.n_histories, "steps_per_history": steps_per_run / wl.n_histories},
+                   "histories": wl.n_histories, "steps_per_history": bal["steps"] / wl.n_histories,
+                   "launch": tuned, "graph": graph is not None},
         "plain": plain,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+    if graph is not None:
+        pmc.pmc_graph_destroy(graph)
     eng.close()
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pmc_device.hpp", "pmc_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1809_03927_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def atomic_probe(torch, nvox, n=200_000_000):
+    """Throughput of int64 atomic adds to random voxels of one tally."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    dst = torch.zeros(nvox, dtype=torch.int64, device="cuda")
+    idx = torch.randint(0, nvox, (n,), device="cuda", generator=g)
+    val = torch.ones(n, dtype=torch.int64, device="cuda")
+    dst.index_add_(0, idx, val)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    dst.index_add_(0, idx, val)
+    e1.record()
+    torch.cuda.synchronize()
+    return n / (e0.elapsed_time(e1) * 1e-3)
 
 
 def cpu_baseline(wl, target_s):
     """The FP64 oracle on the host, on the first K histories of every spot."""
-    import numpy as np
     import oracle
     oracle.build()
     cores = os.cpu_count() or 1
@@ -215,8 +292,7 @@ def cpu_baseline(wl, target_s):
     t = time.perf_counter()
     _, b = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k, n_threads=cores)
     dt = time.perf_counter() - t
-    k2 = max(k, int(k * target_s / max(dt, 1e-3)))
-    k2 = min(k2, 4096)
+    k2 = min(4096, max(k, int(k * target_s / max(dt, 1e-3))))
     log(f"cpu baseline: calibration {b['histories']} histories in {dt:.2f} s; sample k={k2}/spot")
     t = time.perf_counter()
     _, b = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k2, n_threads=cores)

@@ -118,7 +118,11 @@ typedef struct {
   double t_delta;
 } pmc_trace_rec;
 
-/* Number of uint64 words of the device counter block used by pmc_dose_device. */
+/* Number of uint64 words of the device counter block used by pmc_dose_device.
+ * Layout: [0,1] escaped, [2,3] nuclear-removed, [4,5] cutoff energy as 128-bit
+ * (lo, hi) pairs in 2^-32 MeV; [6] histories, [7] steps, [8] delta events,
+ * [9] nuclear events, [10] escapes, [11] misses, [12] global tally atomics
+ * issued; [13..15] reserved. */
 #define PMC_COUNTERS 16
 
 /* ---- context ------------------------------------------------------------ */
@@ -186,6 +190,27 @@ int pmc_balance_from_counters(pmc_context *ctx, const pmc_request *req, const ui
  * on `stream` (dev_dose / dev_density: nx*ny*nz doubles, nullable). */
 int pmc_convert_device(pmc_context *ctx, int32_t phase, const int64_t *dev_tally,
                        uint64_t n_histories, void *stream, double *dev_dose, double *dev_density);
+
+/* ---- captured graphs -------------------------------------------------------- */
+
+typedef struct pmc_graph pmc_graph;
+
+/* Capture one complete dose calculation of `req` into a HIP graph bound to
+ * the given device buffers: zero dev_tally[i] and dev_counters, transport
+ * all listed phases, and (where dev_dose[i] is not NULL) convert each tally
+ * into Gy per history.  The graph owns a private copy of the request's
+ * device data, so later calls on the context do not affect it; it must be
+ * destroyed before its context.  dev_counters is required (the balance of a
+ * replay is read from it).  Every reset inside the graph is a kernel, not a
+ * memset.  Replays on one graph must not overlap in time. */
+int pmc_graph_create(pmc_context *ctx, const pmc_request *req, int64_t *const *dev_tally,
+                     uint64_t *dev_counters, double *const *dev_dose, pmc_graph **out);
+
+/* Replay a captured graph on `stream` (a hipStream_t; NULL = default stream). */
+int pmc_graph_launch(pmc_graph *g, void *stream);
+
+/* Free a graph and its device data.  NULL-safe. */
+void pmc_graph_destroy(pmc_graph *g);
 
 /* ---- validation hooks ------------------------------------------------------ */
 

@@ -1,0 +1,91 @@
+"""Launch-shape autotuner for the persistent transport engine.
+
+For a request shape (phase grids, number of phases and spots, history count
+bucket, energy range) it times candidate launch shapes -- threads per block,
+histories per work item and the lane-refill threshold -- on a probe request
+with fewer histories over the same plan, and keeps the fastest.  Every
+candidate produces bit-identical tallies (integer fixed-point deposits,
+histories keyed by (request, spot, history)), so the choice only affects
+speed.  Choices are cached in a JSON file keyed by device and shape.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import time
+from typing import Dict, Optional, Sequence
+
+from . import pmc
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pmc", "autotune.json")
+
+BLOCKS = (256, 512, 1024)
+CHUNKS = (64, 256, 1024)
+REFILLS = (32, 48, 64)
+
+
+def shape_key(device_name: str, grids: Sequence[Sequence[int]], n_spots: int, n_hist: int,
+              e_range: Sequence[float], engine: int = pmc.PMC_ENGINE_PERSISTENT) -> str:
+    g = "+".join("x".join(str(int(v)) for v in grid) for grid in grids)
+    bucket = int(round(math.log10(max(n_hist, 1)) * 2))  # half-decade buckets
+    return (f"{device_name}|engine{engine}|{len(grids)}ph|{g}|spots{n_spots}|h{bucket}|"
+            f"E{e_range[0]:.0f}-{e_range[1]:.0f}")
+
+
+def _load(path: str) -> Dict[str, dict]:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path: str, data: Dict[str, dict]) -> None:
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(ctx, phases: Sequence[int], key: str, dev_tallies: Sequence[int], dev_counters: int,
+         stream: int, sync, probe_histories: int, request_id: int = 0, flags: int = 0,
+         cache_path: Optional[str] = DEFAULT_CACHE, candidates=None, repeats: int = 2,
+         log=None) -> dict:
+    """Return {"block_size", "chunk", "refill_min", "probe_ms"} for `key`.
+
+    dev_tallies / dev_counters are caller-owned device buffers (they are
+    overwritten by the probes; the engine adds into them, so the caller
+    zeroes them before real use).  `sync` waits for `stream`.
+    """
+    cache = _load(cache_path) if cache_path else {}
+    if key in cache:
+        return cache[key]
+    if candidates is None:
+        candidates = list(itertools.product(BLOCKS, CHUNKS, REFILLS))
+    best = None
+    for block, chunk, refill in candidates:
+        req = pmc.Request(probe_histories, phases, request_id=request_id, flags=flags,
+                          engine=pmc.PMC_ENGINE_PERSISTENT, block_size=block, chunk=chunk,
+                          refill_min=refill)
+        times = []
+        for r in range(repeats + 1):
+            sync()
+            t0 = time.perf_counter()
+            pmc.pmc_dose_device(ctx, req, stream, dev_tallies, dev_counters)
+            sync()
+            if r:  # the first run of a shape also rebuilds the request data
+                times.append(time.perf_counter() - t0)
+        ms = 1e3 * min(times)
+        if log:
+            log(f"autotune {block=} {chunk=} {refill=}: {ms:.2f} ms")
+        if best is None or ms < best["probe_ms"]:
+            best = {"block_size": block, "chunk": chunk, "refill_min": refill, "probe_ms": ms,
+                    "probe_histories": probe_histories}
+    if cache_path:
+        cache = _load(cache_path)
+        cache[key] = best
+        _store(cache_path, cache)
+    return best

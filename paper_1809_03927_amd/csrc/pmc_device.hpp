@@ -44,7 +44,7 @@ enum : int { kAlive = 0, kStopped = 1, kEscaped = 2, kNuclear = 3, kMissed = 4 }
 // counter block layout (uint64 words)
 enum : int {
   kCEscLo = 0, kCEscHi, kCNucLo, kCNucHi, kCCutLo, kCCutHi,
-  kCHist, kCSteps, kCDelta, kCNucEv, kCEscapes, kCMisses, kCCursor, kCSpare0, kCSpare1, kCSpare2
+  kCHist, kCSteps, kCDelta, kCNucEv, kCEscapes, kCMisses, kCAtomics, kCSpare0, kCSpare1, kCSpare2
 };
 
 // ---------------------------------------------------------------------------
@@ -146,7 +146,7 @@ template <typename R> struct Lane {
 // per-lane totals reduced at kernel end
 struct LaneCounters {
   unsigned long long esc, nuc, cut;
-  uint32_t hist, steps, delta, nuc_ev, escapes, misses;
+  uint32_t hist, steps, delta, nuc_ev, escapes, misses, atomics;
 };
 
 // geometry of the phase a lane is in
@@ -390,17 +390,26 @@ __device__ __forceinline__ void start_history(Lane<R> &L, const SpotDev<R> &sp, 
 }
 
 template <typename R>
-__device__ __forceinline__ void flush_tally(Lane<R> &L, const Geo<R> &G) {
-  if (L.acc != 0) atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
+__device__ __forceinline__ void flush_tally(Lane<R> &L, const Geo<R> &G, LaneCounters &C) {
+  if (L.acc != 0) {
+    atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
+    C.atomics += 1;
+  }
   L.acc = 0;
   L.acc_v = -1;
 }
 
+// consecutive deposits into the same voxel are merged in registers: at most
+// one global atomic per voxel visit
 template <typename R>
-__device__ __forceinline__ void add_tally(Lane<R> &L, const Geo<R> &G, int32_t v, long long dep) {
+__device__ __forceinline__ void add_tally(Lane<R> &L, const Geo<R> &G, int32_t v, long long dep,
+                                          LaneCounters &C) {
   if (dep == 0) return;
   if (v != L.acc_v) {
-    if (L.acc != 0) atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
+    if (L.acc != 0) {
+      atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
+      C.atomics += 1;
+    }
     L.acc_v = v;
     L.acc = dep;
   } else {
@@ -593,7 +602,7 @@ __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &
       C.nuc_ev += 1;
       L.fate = kNuclear;
     }
-    add_tally(L, G, v_step, dep);
+    add_tally(L, G, v_step, dep, C);
   }
   C.steps += 1;
   L.nsteps += 1;

@@ -72,10 +72,20 @@ struct Prepared {
   // device offsets into the request scratch buffer
   size_t off_spots = 0, off_items = 0, off_luts = 0, off_targets = 0;
   std::vector<size_t> off_ids, off_first;
-  std::vector<unsigned char> staging;  // pinned copy uploaded into the scratch
+  std::vector<unsigned char> staging;  // host image uploaded into the scratch
+  std::vector<TargetDev> targets;      // last uploaded target table (kept alive for the copy)
+  size_t bytes = 0;                    // size of the request data
 };
 
 }  // namespace
+
+struct pmc_graph {
+  pmc_context *ctx = nullptr;
+  void *data = nullptr;  // private copy of the request data + work-queue cursor
+  size_t bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 struct pmc_context {
   int device = -1;
@@ -404,6 +414,7 @@ int prepare(pmc_context *ctx, const pmc_request *req) {
   HIP_TRY(ctx, hipMemcpy(ctx->scratch.p, P.staging.data(), off, hipMemcpyHostToDevice),
           "upload request data");
   P.valid = true;
+  P.bytes = off;
   P.plan_version = ctx->plan_version;
   P.n_hist = req->n_histories;
   P.phases = phases;
@@ -414,16 +425,16 @@ int prepare(pmc_context *ctx, const pmc_request *req) {
   return PMC_OK;
 }
 
-unsigned char *scratch_at(pmc_context *ctx, size_t off) {
-  return static_cast<unsigned char *>(ctx->scratch.p) + off;
-}
-
+// Enqueue the transport of a prepared request.  `base` holds the request
+// data laid out by prepare() (the context's scratch, or a graph's own copy);
+// `cursor` is the work-queue cursor.  With upload_targets false the target
+// table at base + off_targets must already hold this call's tally pointers.
 template <typename R>
-int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
-            unsigned long long *const *tally, unsigned long long *counters) {
-  int rc = prepare<R>(ctx, req);
-  if (rc) return rc;
+int enqueue_prepared(pmc_context *ctx, const pmc_request *req, hipStream_t st,
+                     unsigned long long *const *tally, unsigned long long *counters,
+                     unsigned char *base, unsigned long long *cursor, bool upload_targets) {
   Prepared &P = ctx->prep;
+  auto scratch_at = [&](size_t off) { return base + off; };
   const bool fp64 = sizeof(R) == 8;
   const uint32_t k0 = (uint32_t)(ctx->seed & 0xffffffffu), k1 = req->request_id;
   const double inv_dl2 = 1.0 / ctx->tabs.dl2;
@@ -432,9 +443,9 @@ int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
       if (P.slot_hist[i] == 0) continue;
       const PhaseRec &ph = ctx->phases[req->phases[i]];
       pmc::PlainLaunch a;
-      a.spots = scratch_at(ctx, P.off_spots);
-      a.spot_ids = reinterpret_cast<const int32_t *>(scratch_at(ctx, P.off_ids[i]));
-      a.first = reinterpret_cast<const long long *>(scratch_at(ctx, P.off_first[i]));
+      a.spots = scratch_at(P.off_spots);
+      a.spot_ids = reinterpret_cast<const int32_t *>(scratch_at(P.off_ids[i]));
+      a.first = reinterpret_cast<const long long *>(scratch_at(P.off_first[i]));
       a.n_list = (int32_t)P.list[i].size();
       a.n_hist = P.slot_hist[i];
       a.target = make_target(ph, tally[i], 0);
@@ -452,23 +463,30 @@ int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
       HIP_TRY(ctx, pmc::launch_plain(a, fp64, st), "transport_plain launch");
     }
   } else {
-    // targets carry this call's tally pointers: rebuilt and uploaded per call
-    std::vector<TargetDev> tg(req->n_phases);
-    for (int32_t i = 0; i < req->n_phases; ++i)
-      tg[i] = make_target(ctx->phases[req->phases[i]], tally[i], P.same_lut ? 0 : i);
-    HIP_TRY(ctx, hipMemcpyAsync(scratch_at(ctx, P.off_targets), tg.data(),
-                                sizeof(TargetDev) * tg.size(), hipMemcpyHostToDevice, st),
-            "upload targets");
-    rc = ensure(ctx, ctx->cursor, 256, "work-queue cursor");
-    if (rc) return rc;
-    HIP_TRY(ctx, pmc::launch_fill_u64((unsigned long long *)ctx->cursor.p, 1, 0ull, st), "cursor reset");
+    if (upload_targets) {
+      // targets carry this call's tally pointers; uploaded only when they
+      // change (after the previous user of the table has finished)
+      std::vector<TargetDev> tg(req->n_phases);
+      for (int32_t i = 0; i < req->n_phases; ++i)
+        tg[i] = make_target(ctx->phases[req->phases[i]], tally[i], P.same_lut ? 0 : i);
+      const bool same = P.targets.size() == tg.size() &&
+                        std::memcmp(P.targets.data(), tg.data(), sizeof(TargetDev) * tg.size()) == 0;
+      if (!same) {
+        wait_pending(ctx);
+        P.targets = tg;
+        HIP_TRY(ctx, hipMemcpy(scratch_at(P.off_targets), P.targets.data(),
+                               sizeof(TargetDev) * P.targets.size(), hipMemcpyHostToDevice),
+                "upload targets");
+      }
+    }
+    HIP_TRY(ctx, pmc::launch_fill_u64(cursor, 1, 0ull, st), "cursor reset");
     pmc::PersistentLaunch a;
-    a.spots = scratch_at(ctx, P.off_spots);
-    a.items = reinterpret_cast<const WorkItem *>(scratch_at(ctx, P.off_items));
+    a.spots = scratch_at(P.off_spots);
+    a.items = reinterpret_cast<const WorkItem *>(scratch_at(P.off_items));
     a.n_items = P.n_items;
-    a.targets = reinterpret_cast<const TargetDev *>(scratch_at(ctx, P.off_targets));
+    a.targets = reinterpret_cast<const TargetDev *>(scratch_at(P.off_targets));
     a.n_targets = req->n_phases;
-    a.luts = scratch_at(ctx, P.off_luts);
+    a.luts = scratch_at(P.off_luts);
     a.tab = ctx->d_tab;
     a.l2e0 = ctx->tabs.l2e0;
     a.inv_dl2 = inv_dl2;
@@ -479,7 +497,7 @@ int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
     a.refill_min = req->refill_min ? req->refill_min : 64;
     a.block = req->block_size ? req->block_size : 256;
     a.lut_lds = !fp64 && P.same_lut;
-    a.cursor = (unsigned long long *)ctx->cursor.p;
+    a.cursor = cursor;
     a.counters = counters;
     unsigned grid = (unsigned)req->grid_blocks;
     if (grid == 0) {
@@ -493,6 +511,18 @@ int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
   ctx->last_stream = st;
   ctx->pending = true;
   return PMC_OK;
+}
+
+template <typename R>
+int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
+            unsigned long long *const *tally, unsigned long long *counters) {
+  int rc = prepare<R>(ctx, req);
+  if (rc) return rc;
+  rc = ensure(ctx, ctx->cursor, 256, "work-queue cursor");
+  if (rc) return rc;
+  return enqueue_prepared<R>(ctx, req, st, tally, counters,
+                             static_cast<unsigned char *>(ctx->scratch.p),
+                             static_cast<unsigned long long *>(ctx->cursor.p), true);
 }
 
 void to128(unsigned __int128 v, uint64_t out[2]) {
@@ -987,5 +1017,109 @@ int pmc_split_histories(const pmc_spot *spots, int64_t n_spots, const int32_t *p
 }
 
 uint64_t pmc_bytes_in_use(const pmc_context *ctx) { return ctx ? ctx->used : 0; }
+
+int pmc_graph_create(pmc_context *ctx, const pmc_request *req, int64_t *const *dev_tally,
+                     uint64_t *dev_counters, double *const *dev_dose, pmc_graph **out) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (!out) return fail(ctx, PMC_E_INVAL, "out is NULL");
+  int rc = validate_request(ctx, req);
+  if (rc) return rc;
+  if (!dev_tally || !dev_counters) return fail(ctx, PMC_E_INVAL, "dev_tally and dev_counters are required");
+  for (int32_t i = 0; i < req->n_phases; ++i)
+    if (!dev_tally[i]) return fail(ctx, PMC_E_INVAL, "dev_tally[%d] is NULL", i);
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  const bool fp64 = ctx->precision == PMC_FP64;
+  rc = fp64 ? prepare<double>(ctx, req) : prepare<float>(ctx, req);
+  if (rc) return rc;
+  wait_pending(ctx);
+  Prepared &P = ctx->prep;
+  const size_t bytes = align256(P.bytes) + 256;  // request data + cursor
+  if (ctx->used + bytes > ctx->budget)
+    return fail(ctx, PMC_E_BUDGET, "graph data needs %zu bytes: over the device-memory budget", bytes);
+  pmc_graph *g = new pmc_graph();
+  g->ctx = ctx;
+  g->bytes = bytes;
+  auto bail = [&](hipError_t e, const char *what) {
+    const int code = hip_fail(ctx, e, what);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->data) { (void)hipFree(g->data); ctx->used -= g->bytes; }
+    delete g;
+    return code;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&g->data, bytes)) != hipSuccess) { delete g; return hip_fail(ctx, e, "hipMalloc graph data"); }
+  ctx->used += bytes;
+  unsigned char *base = static_cast<unsigned char *>(g->data);
+  auto *cursor = reinterpret_cast<unsigned long long *>(base + align256(P.bytes));
+  // private image of the request data with this graph's tally pointers
+  std::vector<unsigned char> image = P.staging;
+  std::vector<TargetDev> tg(req->n_phases);
+  for (int32_t i = 0; i < req->n_phases; ++i)
+    tg[i] = make_target(ctx->phases[req->phases[i]], reinterpret_cast<unsigned long long *>(dev_tally[i]),
+                        P.same_lut ? 0 : i);
+  std::memcpy(image.data() + P.off_targets, tg.data(), sizeof(TargetDev) * tg.size());
+  if ((e = hipMemcpy(base, image.data(), P.bytes, hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(e, "upload graph data");
+  hipStream_t st = ctx->stream;
+  if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return bail(e, "hipStreamBeginCapture");
+  auto *counters = reinterpret_cast<unsigned long long *>(dev_counters);
+  bool ok = true;
+  for (int32_t i = 0; i < req->n_phases && ok; ++i)
+    ok = pmc::launch_fill_u64(reinterpret_cast<unsigned long long *>(dev_tally[i]),
+                              ctx->phases[req->phases[i]].nvox(), 0ull, st) == hipSuccess;
+  ok = ok && pmc::launch_fill_u64(counters, PMC_COUNTERS, 0ull, st) == hipSuccess;
+  auto *const *tp = reinterpret_cast<unsigned long long *const *>(dev_tally);
+  if (ok)
+    rc = fp64 ? enqueue_prepared<double>(ctx, req, st, tp, counters, base, cursor, false)
+              : enqueue_prepared<float>(ctx, req, st, tp, counters, base, cursor, false);
+  ok = ok && rc == PMC_OK;
+  for (int32_t i = 0; i < req->n_phases && ok && dev_dose; ++i) {
+    if (!dev_dose[i]) continue;
+    const PhaseRec &ph = ctx->phases[req->phases[i]];
+    const double vol = (0.1 * ph.sp_mm[0]) * (0.1 * ph.sp_mm[1]) * (0.1 * ph.sp_mm[2]);
+    ok = pmc::launch_convert(reinterpret_cast<const long long *>(dev_tally[i]), ph.d_hu, ph.d_mask,
+                             ph.d_lut64, ph.nvox(), vol, (double)req->n_histories, dev_dose[i],
+                             nullptr, st) == hipSuccess;
+  }
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(st, &graph);
+  ctx->pending = false;
+  g->graph = graph;
+  if (!ok) {
+    const std::string msg = ctx->err.empty() ? "launch failed during capture" : ctx->err;
+    bail(hipErrorUnknown, "graph capture");
+    return fail(ctx, rc ? rc : PMC_E_DEVICE, "graph capture: %s", msg.c_str());
+  }
+  if (e != hipSuccess) return bail(e, "hipStreamEndCapture");
+  if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return bail(e, "hipGraphInstantiate");
+  *out = g;
+  return PMC_OK;
+}
+
+int pmc_graph_launch(pmc_graph *g, void *stream) {
+  if (!g) return fail(nullptr, PMC_E_INVAL, "graph is NULL");
+  pmc_context *ctx = g->ctx;
+  ctx->err.clear();
+  HIP_TRY(ctx, hipGraphLaunch(g->exec, (hipStream_t)stream), "hipGraphLaunch");
+  return PMC_OK;
+}
+
+void pmc_graph_destroy(pmc_graph *g) {
+  if (!g) return;
+  (void)hipSetDevice(g->ctx->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->data) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g->data);
+    g->ctx->used -= g->bytes;
+  }
+  delete g;
+}
 
 }  // extern "C"

@@ -32,27 +32,30 @@ __device__ __forceinline__ void add128(unsigned long long *p, unsigned long long
 }
 
 // Every thread of the block must call this (it synchronises the block).
-// `red` is LDS of 12 * (waves + 1) words.
+// `red` is LDS of kNc * (waves + 1) words.
+constexpr int kNc = 13;  // 3 energies as (lo32, hi32) sums + 7 event counts
+
 __device__ void commit_counters(const LaneCounters &C, unsigned long long *counters,
                                 unsigned long long *red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  unsigned long long v[12];
+  unsigned long long v[kNc];
   v[0] = C.esc & 0xffffffffull; v[1] = C.esc >> 32;
   v[2] = C.nuc & 0xffffffffull; v[3] = C.nuc >> 32;
   v[4] = C.cut & 0xffffffffull; v[5] = C.cut >> 32;
-  v[6] = C.hist; v[7] = C.steps; v[8] = C.delta; v[9] = C.nuc_ev; v[10] = C.escapes; v[11] = C.misses;
+  v[6] = C.hist; v[7] = C.steps; v[8] = C.delta; v[9] = C.nuc_ev; v[10] = C.escapes;
+  v[11] = C.misses; v[12] = C.atomics;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) v[k] = wave_sum(v[k]);
+  for (int k = 0; k < kNc; ++k) v[k] = wave_sum(v[k]);
   __syncthreads();
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) red[wave * 12 + k] = v[k];
+    for (int k = 0; k < kNc; ++k) red[wave * kNc + k] = v[k];
   }
   __syncthreads();
-  unsigned long long *tot = red + 12 * nw;
-  if (threadIdx.x < 12) {
+  unsigned long long *tot = red + kNc * nw;
+  if (threadIdx.x < kNc) {
     unsigned long long s = 0;
-    for (int w = 0; w < nw; ++w) s += red[w * 12 + threadIdx.x];
+    for (int w = 0; w < nw; ++w) s += red[w * kNc + threadIdx.x];
     tot[threadIdx.x] = s;
   }
   __syncthreads();
@@ -63,7 +66,7 @@ __device__ void commit_counters(const LaneCounters &C, unsigned long long *count
     const unsigned long long lo = lo32 + (hi32 << 32);
     const unsigned long long hi = (hi32 >> 32) + (lo < lo32 ? 1ull : 0ull);
     if (lo | hi) add128(counters + 2 * t, lo, hi);
-  } else if (t >= 6 && t < 12) {
+  } else if (t >= 6 && t < kNc) {
     if (tot[t]) __hip_atomic_fetch_add(counters + kCHist + (t - 6), tot[t], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -129,7 +132,7 @@ transport_plain(const SpotDev<R> *__restrict__ spots, const int32_t *__restrict_
     Lane<R> L;
     start_history(L, spots[s], s, (uint32_t)(g - first[lo]), G, k0, k1, C);
     while (L.fate == kAlive) step<R, false>(L, G, T, lut, k0, k1, flags, C, nullptr, 0);
-    flush_tally(L, G);
+    flush_tally(L, G, C);
   }
   commit_counters(C, counters, red);
 }
@@ -211,7 +214,7 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
       const Geo<R> G = geo_s[tgt];
       const R2 *lut = LUT_LDS ? lut_s : luts_g + (size_t)G.lut * kLutSize;
       step<R, false>(L, G, T, lut, k0, k1, flags, C, nullptr, 0);
-      if (L.fate != kAlive) flush_tally(L, G);
+      if (L.fate != kAlive) flush_tally(L, G, C);
     }
   }
   commit_counters(C, counters, red);
@@ -235,7 +238,7 @@ __global__ void __launch_bounds__(64) trace_kernel(SpotDev<R> sp, int32_t spot, 
   L.nsteps = 0;
   trace_out(rec, 0, max_rec, -1, L.v, L, G, (R)0, 0ll, (R)0);
   while (L.fate == kAlive) step<R, true>(L, G, T, lut_g, k0, k1, flags, C, rec, max_rec);
-  flush_tally(L, G);
+  flush_tally(L, G, C);
   *n_rec = (int32_t)L.nsteps + 1;
 }
 
@@ -275,7 +278,7 @@ template <typename R>
 static hipError_t launch_plain_t(const PlainLaunch &a, hipStream_t st) {
   using R2 = typename M<R>::R2;
   using R4 = typename M<R>::R4;
-  const size_t red_bytes = sizeof(unsigned long long) * 12 * (a.block / 64 + 1);
+  const size_t red_bytes = sizeof(unsigned long long) * kNc * (a.block / 64 + 1);
   const size_t lds = Smem<R>::tab_bytes + (a.lut_lds ? Smem<R>::lut_bytes : 0) + red_bytes;
   const long long nb = (a.n_hist + a.block - 1) / a.block;
   if (nb <= 0) return hipSuccess;
@@ -313,7 +316,7 @@ static hipError_t launch_persistent_t(const PersistentLaunch &a, hipStream_t st)
 template <typename R>
 static size_t persistent_lds(const PersistentLaunch &a) {
   return Smem<R>::tab_bytes + (a.lut_lds ? Smem<R>::lut_bytes : 0) +
-         sizeof(Geo<R>) * (size_t)a.n_targets + sizeof(unsigned long long) * 12 * (a.block / 64 + 1);
+         sizeof(Geo<R>) * (size_t)a.n_targets + sizeof(unsigned long long) * kNc * (a.block / 64 + 1);
 }
 
 template <typename R>

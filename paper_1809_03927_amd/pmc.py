@@ -32,7 +32,8 @@ ERROR_NAMES = {0: "PMC_OK", -1: "PMC_E_INVAL", -2: "PMC_E_NOPHASE", -3: "PMC_E_B
 # every symbol declared in include/pmc.h
 EXPORTS = ["pmc_create", "pmc_destroy", "pmc_last_error", "pmc_load_phase", "pmc_unload_phase",
            "pmc_load_spots", "pmc_dose", "pmc_dose_device", "pmc_balance_from_counters",
-           "pmc_convert_device", "pmc_trace", "pmc_split_histories", "pmc_bytes_in_use"]
+           "pmc_convert_device", "pmc_trace", "pmc_split_histories", "pmc_bytes_in_use",
+           "pmc_graph_create", "pmc_graph_launch", "pmc_graph_destroy"]
 
 
 class pmc_config(C.Structure):
@@ -105,6 +106,10 @@ def lib():
         L.pmc_split_histories.argtypes = [vp, i64, vp, i32, u64, vp]
         L.pmc_bytes_in_use.argtypes = [vp]
         L.pmc_bytes_in_use.restype = u64
+        L.pmc_graph_create.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, C.POINTER(vp)]
+        L.pmc_graph_launch.argtypes = [vp, vp]
+        L.pmc_graph_destroy.argtypes = [vp]
+        L.pmc_graph_destroy.restype = None
         _lib = L
     return _lib
 
@@ -236,6 +241,26 @@ def pmc_split_histories(spots: np.ndarray, phases: Sequence[int], n_histories: i
 
 def pmc_bytes_in_use(ctx) -> int:
     return int(lib().pmc_bytes_in_use(ctx))
+
+
+def pmc_graph_create(ctx, req: Request, dev_tallies: Sequence[int], dev_counters: int,
+                     dev_doses: Optional[Sequence[Optional[int]]] = None):
+    tp = (C.c_void_p * req.n_phases)(*[int(p) for p in dev_tallies])
+    dp = None
+    if dev_doses is not None:
+        dp = (C.c_void_p * req.n_phases)(*[None if p is None else int(p) for p in dev_doses])
+    g = C.c_void_p()
+    _check(lib().pmc_graph_create(ctx, C.byref(req.c), tp, C.c_void_p(dev_counters), dp,
+                                  C.byref(g)), ctx)
+    return g
+
+
+def pmc_graph_launch(g, stream: int, ctx=None) -> None:
+    _check(lib().pmc_graph_launch(g, C.c_void_p(stream)), ctx)
+
+
+def pmc_graph_destroy(g) -> None:
+    lib().pmc_graph_destroy(g)
 
 
 # ----------------------------------------------------------------------------
