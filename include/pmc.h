@@ -98,6 +98,10 @@ typedef struct {
   int32_t chunk;          /* persistent engine: histories per work item; 0 = default */
   int32_t refill_min;     /* persistent engine: refill when >= this many lanes of a wave are idle (1..64); 0 = default */
   int32_t grid_blocks;    /* persistent engine: blocks; 0 = enough to fill the device */
+  int32_t plan;           /* plan id (pmc_load_plan; pmc_load_spots loads plan 0) */
+  int32_t reserved;       /* must be 0 */
+  uint64_t item_begin;    /* persistent engine: run only work items [item_begin, item_end) */
+  uint64_t item_end;      /*   of the request (0, 0 = all); see pmc_request_items */
 } pmc_request;
 
 /* Energy balance of a run.  128-bit unsigned totals as (lo, hi) words, in
@@ -156,9 +160,24 @@ int pmc_load_phase(pmc_context *ctx, int32_t phase, const int16_t *hu, int32_t n
 /* Free the device copy of a loaded phase. */
 int pmc_unload_phase(pmc_context *ctx, int32_t phase);
 
-/* Replace the plan: fields and spots (with their phase indices). */
+/* Load (or replace) plan `plan` (0..1023): fields and spots with their phase
+ * indices.  A context holds several plans; a request names the one it uses. */
+int pmc_load_plan(pmc_context *ctx, int32_t plan, const pmc_field *fields, int32_t n_fields,
+                  const pmc_spot *spots, int64_t n_spots);
+
+/* pmc_load_plan for plan 0. */
 int pmc_load_spots(pmc_context *ctx, const pmc_field *fields, int32_t n_fields,
                    const pmc_spot *spots, int64_t n_spots);
+
+/* Forget a plan and free the device data prepared for it. */
+int pmc_unload_plan(pmc_context *ctx, int32_t plan);
+
+/* Number of work items of a persistent-engine request (its histories cut
+ * into runs of `chunk` histories of one spot, in spot order).  A request may
+ * be run as several calls over consecutive item slices adding into the same
+ * tallies and counters; together they equal one call over all items.
+ * Prepares (and caches) the request's device data. */
+int pmc_request_items(pmc_context *ctx, const pmc_request *req, uint64_t *n_items);
 
 /* ---- dose ------------------------------------------------------------------ */
 
@@ -215,10 +234,10 @@ void pmc_graph_destroy(pmc_graph *g);
 /* ---- validation hooks ------------------------------------------------------ */
 
 /* Per-step trace of one history (spot index, history index within the spot)
- * of the loaded plan on one phase, computed by the GPU transport in the
+ * of plan `plan` on one phase, computed by the GPU transport in the
  * context's precision.  Writes at most max_rec records and sets *n_rec to the
  * full length. */
-int pmc_trace(pmc_context *ctx, int32_t phase, int64_t spot, uint32_t history,
+int pmc_trace(pmc_context *ctx, int32_t plan, int32_t phase, int64_t spot, uint32_t history,
               uint32_t request_id, uint32_t flags, pmc_trace_rec *out, int32_t max_rec,
               int32_t *n_rec);
 

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -52,11 +53,17 @@ struct PhaseRec {
   long long nvox() const { return (long long)nx * ny * nz; }
 };
 
+struct PlanRec {
+  std::vector<pmc_field> fields;
+  std::vector<pmc_spot> spots;
+  uint64_t version = 0;
+};
+
 // Device-side data of a request that depends only on its inputs (plan,
-// phases, split); rebuilt when any of them changes.
+// phases, split, engine); kept in a small LRU cache of such entries.
 struct Prepared {
-  bool valid = false;
   // signature
+  int32_t plan_id = -1;
   uint64_t plan_version = 0, n_hist = 0;
   std::vector<int32_t> phases;
   std::vector<uint64_t> phase_versions;
@@ -73,8 +80,10 @@ struct Prepared {
   size_t off_spots = 0, off_items = 0, off_luts = 0, off_targets = 0;
   std::vector<size_t> off_ids, off_first;
   std::vector<unsigned char> staging;  // host image uploaded into the scratch
-  std::vector<TargetDev> targets;      // last uploaded target table (kept alive for the copy)
+  std::vector<TargetDev> targets;      // last uploaded target table
   size_t bytes = 0;                    // size of the request data
+  DevBuf buf;                          // device copy of the request data
+  uint64_t last_use = 0;
 };
 
 }  // namespace
@@ -101,17 +110,15 @@ struct pmc_context {
   size_t tab_bytes = 0;
   std::map<int32_t, PhaseRec> phases;
   uint64_t phase_counter = 0;
-  std::vector<pmc_field> fields;
-  std::vector<pmc_spot> spots;
-  bool have_plan = false;
-  uint64_t plan_version = 0;
+  std::map<int32_t, PlanRec> plans;
+  uint64_t plan_counter = 0;
   hipStream_t stream = nullptr;
   hipStream_t last_stream = nullptr;
   bool pending = false;
-  DevBuf scratch;    // request data (spots, items, lists, targets, LUTs)
+  std::vector<std::unique_ptr<Prepared>> cache;  // prepared request data (LRU)
+  uint64_t use_counter = 0;
   DevBuf cursor;     // work-queue cursor (one uint64)
   DevBuf counters;   // internal counter block
-  Prepared prep;
 };
 
 namespace {
@@ -242,7 +249,10 @@ int split(const pmc_spot *spots, int64_t n_spots, const int32_t *phases, int32_t
 
 int validate_request(pmc_context *ctx, const pmc_request *req) {
   if (!req) return fail(ctx, PMC_E_INVAL, "request is NULL");
-  if (!ctx->have_plan) return fail(ctx, PMC_E_STATE, "no plan loaded (call pmc_load_spots first)");
+  auto pit = ctx->plans.find(req->plan);
+  if (pit == ctx->plans.end())
+    return fail(ctx, PMC_E_STATE, "plan %d is not loaded (call pmc_load_plan / pmc_load_spots first)",
+                req->plan);
   if (req->n_phases < 1 || req->n_phases > PMC_MAX_PHASES || !req->phases)
     return fail(ctx, PMC_E_INVAL, "n_phases must be 1..%d with a phase list", PMC_MAX_PHASES);
   for (int32_t i = 0; i < req->n_phases; ++i) {
@@ -263,8 +273,13 @@ int validate_request(pmc_context *ctx, const pmc_request *req) {
   if (req->chunk < 0 || req->refill_min < 0 || req->refill_min > 64 || req->grid_blocks < 0)
     return fail(ctx, PMC_E_INVAL, "chunk, refill_min (0..64) and grid_blocks must be >= 0");
   if (req->flags & ~31u) return fail(ctx, PMC_E_INVAL, "unknown flag bits 0x%x", req->flags);
+  if (req->reserved != 0) return fail(ctx, PMC_E_INVAL, "reserved field must be 0");
+  if (req->engine == PMC_ENGINE_PLAIN && (req->item_begin || req->item_end))
+    return fail(ctx, PMC_E_INVAL, "work-item slices need the persistent engine");
+  if (req->item_end && req->item_end < req->item_begin)
+    return fail(ctx, PMC_E_INVAL, "item_end < item_begin");
   bool any = false;
-  for (const pmc_spot &s : ctx->spots)
+  for (const pmc_spot &s : pit->second.spots)
     for (int32_t i = 0; i < req->n_phases && !any; ++i) any = s.phase == req->phases[i];
   if (!any) return fail(ctx, PMC_E_INVAL, "no spot of the plan lies on the requested phases");
   return PMC_OK;
@@ -313,23 +328,40 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int default_chunk(const pmc_request *req) { return req->chunk > 0 ? req->chunk : 256; }
 
-// Split, build and upload the request's device data (cached on the inputs).
+constexpr size_t kMaxPrepared = 32;
+
+void evict_lru(pmc_context *ctx) {
+  size_t lru = 0;
+  for (size_t i = 1; i < ctx->cache.size(); ++i)
+    if (ctx->cache[i]->last_use < ctx->cache[lru]->last_use) lru = i;
+  wait_pending(ctx);
+  release(ctx, ctx->cache[lru]->buf);
+  ctx->cache.erase(ctx->cache.begin() + (long)lru);
+}
+
+// Split, build and upload the request's device data; cached on the inputs.
 template <typename R>
-int prepare(pmc_context *ctx, const pmc_request *req) {
-  Prepared &P = ctx->prep;
+int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
+  const PlanRec &plan = ctx->plans[req->plan];
   std::vector<int32_t> phases(req->phases, req->phases + req->n_phases);
   std::vector<uint64_t> versions;
   for (int32_t ph : phases) versions.push_back(ctx->phases[ph].version);
   const int32_t chunk = req->engine == PMC_ENGINE_PERSISTENT ? default_chunk(req) : 0;
-  if (P.valid && P.plan_version == ctx->plan_version && P.n_hist == req->n_histories &&
-      P.phases == phases && P.phase_versions == versions && P.engine == req->engine &&
-      P.chunk == chunk && P.precision == ctx->precision)
-    return PMC_OK;
-  wait_pending(ctx);
-  P = Prepared();
-  const int64_t n_spots = (int64_t)ctx->spots.size();
+  for (auto &e : ctx->cache) {
+    Prepared &C = *e;
+    if (C.plan_id == req->plan && C.plan_version == plan.version && C.n_hist == req->n_histories &&
+        C.phases == phases && C.phase_versions == versions && C.engine == req->engine &&
+        C.chunk == chunk && C.precision == ctx->precision) {
+      C.last_use = ++ctx->use_counter;
+      *out = &C;
+      return PMC_OK;
+    }
+  }
+  auto entry = std::make_unique<Prepared>();
+  Prepared &P = *entry;
+  const int64_t n_spots = (int64_t)plan.spots.size();
   P.per_spot.assign(n_spots, 0);
-  int rc = split(ctx->spots.data(), n_spots, req->phases, req->n_phases, req->n_histories,
+  int rc = split(plan.spots.data(), n_spots, req->phases, req->n_phases, req->n_histories,
                  P.per_spot.data());
   if (rc) return fail(ctx, rc, "history split failed (weights)");
   const int32_t n_slots = req->n_phases;
@@ -341,11 +373,11 @@ int prepare(pmc_context *ctx, const pmc_request *req) {
   P.first.assign(n_slots, {0});
   P.slot_hist.assign(n_slots, 0);
   for (int64_t s = 0; s < n_spots; ++s) {
-    const pmc_spot &sp = ctx->spots[s];
+    const pmc_spot &sp = plan.spots[s];
     auto it = slot_of.find(sp.phase);
     const int32_t slot = it == slot_of.end() ? -1 : it->second;
     const PhaseRec &ph = slot >= 0 ? ctx->phases[sp.phase] : ctx->phases[phases[0]];
-    sd[s] = make_spot<R>(sp, ctx->fields[sp.field], ph, slot);
+    sd[s] = make_spot<R>(sp, plan.fields[sp.field], ph, slot);
     if (slot >= 0 && P.per_spot[s] > 0) {
       P.list[slot].push_back((int32_t)s);
       P.first[slot].push_back(P.first[slot].back() + P.per_spot[s]);
@@ -376,7 +408,7 @@ int prepare(pmc_context *ctx, const pmc_request *req) {
   for (int32_t i = 1; i < n_slots; ++i)
     if (ctx->phases[phases[i]].lut64 != ctx->phases[phases[0]].lut64) P.same_lut = false;
   const int32_t n_luts = P.same_lut ? 1 : n_slots;
-  // layout of the scratch buffer
+  // layout of the request data
   size_t off = 0;
   P.off_spots = off;
   off = align256(off + sizeof(SpotDev<R>) * (size_t)n_spots);
@@ -409,19 +441,26 @@ int prepare(pmc_context *ctx, const pmc_request *req) {
     put(P.off_ids[i], P.list[i].data(), sizeof(int32_t) * P.list[i].size());
     put(P.off_first[i], P.first[i].data(), sizeof(long long) * P.first[i].size());
   }
-  rc = ensure(ctx, ctx->scratch, off, "request scratch");
+  // room in the cache and in the budget (older entries are evicted first)
+  while (!ctx->cache.empty() &&
+         (ctx->cache.size() >= kMaxPrepared || ctx->used + align256(off) > ctx->budget))
+    evict_lru(ctx);
+  rc = ensure(ctx, P.buf, std::max<size_t>(off, 256), "request data");
   if (rc) return rc;
-  HIP_TRY(ctx, hipMemcpy(ctx->scratch.p, P.staging.data(), off, hipMemcpyHostToDevice),
+  HIP_TRY(ctx, hipMemcpy(P.buf.p, P.staging.data(), off, hipMemcpyHostToDevice),
           "upload request data");
-  P.valid = true;
   P.bytes = off;
-  P.plan_version = ctx->plan_version;
+  P.plan_id = req->plan;
+  P.plan_version = plan.version;
   P.n_hist = req->n_histories;
   P.phases = phases;
   P.phase_versions = versions;
   P.engine = req->engine;
   P.chunk = chunk;
   P.precision = ctx->precision;
+  P.last_use = ++ctx->use_counter;
+  ctx->cache.push_back(std::move(entry));
+  *out = ctx->cache.back().get();
   return PMC_OK;
 }
 
@@ -430,10 +469,9 @@ int prepare(pmc_context *ctx, const pmc_request *req) {
 // `cursor` is the work-queue cursor.  With upload_targets false the target
 // table at base + off_targets must already hold this call's tally pointers.
 template <typename R>
-int enqueue_prepared(pmc_context *ctx, const pmc_request *req, hipStream_t st,
+int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipStream_t st,
                      unsigned long long *const *tally, unsigned long long *counters,
                      unsigned char *base, unsigned long long *cursor, bool upload_targets) {
-  Prepared &P = ctx->prep;
   auto scratch_at = [&](size_t off) { return base + off; };
   const bool fp64 = sizeof(R) == 8;
   const uint32_t k0 = (uint32_t)(ctx->seed & 0xffffffffu), k1 = req->request_id;
@@ -482,8 +520,10 @@ int enqueue_prepared(pmc_context *ctx, const pmc_request *req, hipStream_t st,
     HIP_TRY(ctx, pmc::launch_fill_u64(cursor, 1, 0ull, st), "cursor reset");
     pmc::PersistentLaunch a;
     a.spots = scratch_at(P.off_spots);
-    a.items = reinterpret_cast<const WorkItem *>(scratch_at(P.off_items));
-    a.n_items = P.n_items;
+    // the slice [item_begin, item_end) of the request's work items
+    const uint64_t i_end = req->item_end ? req->item_end : (uint64_t)P.n_items;
+    a.items = reinterpret_cast<const WorkItem *>(scratch_at(P.off_items)) + req->item_begin;
+    a.n_items = (int32_t)(i_end - req->item_begin);
     a.targets = reinterpret_cast<const TargetDev *>(scratch_at(P.off_targets));
     a.n_targets = req->n_phases;
     a.luts = scratch_at(P.off_luts);
@@ -516,13 +556,33 @@ int enqueue_prepared(pmc_context *ctx, const pmc_request *req, hipStream_t st,
 template <typename R>
 int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
             unsigned long long *const *tally, unsigned long long *counters) {
-  int rc = prepare<R>(ctx, req);
+  Prepared *P = nullptr;
+  int rc = prepare<R>(ctx, req, &P);
   if (rc) return rc;
+  if (req->item_end > (uint64_t)P->n_items || req->item_begin > (uint64_t)P->n_items)
+    return fail(ctx, PMC_E_INVAL, "work-item slice [%llu, %llu) beyond the request's %d items",
+                (unsigned long long)req->item_begin, (unsigned long long)req->item_end, P->n_items);
   rc = ensure(ctx, ctx->cursor, 256, "work-queue cursor");
   if (rc) return rc;
-  return enqueue_prepared<R>(ctx, req, st, tally, counters,
-                             static_cast<unsigned char *>(ctx->scratch.p),
+  return enqueue_prepared<R>(ctx, *P, req, st, tally, counters,
+                             static_cast<unsigned char *>(P->buf.p),
                              static_cast<unsigned long long *>(ctx->cursor.p), true);
+}
+
+// Incident energy of a request (depends only on the split): 128-bit sum.
+int incident_of(pmc_context *ctx, const pmc_request *req, unsigned __int128 *out) {
+  const PlanRec &plan = ctx->plans[req->plan];
+  std::vector<int64_t> per(plan.spots.size());
+  const int rc = split(plan.spots.data(), (int64_t)plan.spots.size(), req->phases, req->n_phases,
+                       req->n_histories, per.data());
+  if (rc) return fail(ctx, rc, "history split failed");
+  unsigned __int128 inc = 0;
+  for (size_t s = 0; s < per.size(); ++s)
+    if (per[s] > 0)
+      inc += (unsigned __int128)(unsigned long long)per[s] *
+             (unsigned long long)q_working(ctx, plan.spots[s].energy_MeV);
+  *out = inc;
+  return PMC_OK;
 }
 
 void to128(unsigned __int128 v, uint64_t out[2]) {
@@ -534,9 +594,9 @@ unsigned __int128 from128(const uint64_t v[2]) {
   return ((unsigned __int128)v[1] << 64) | v[0];
 }
 
-void fill_balance(const pmc_context *ctx, const uint64_t *c, unsigned __int128 deposited,
+void fill_balance(unsigned __int128 incident, const uint64_t *c, unsigned __int128 deposited,
                   pmc_balance *b) {
-  to128(ctx->prep.incident, b->incident);
+  to128(incident, b->incident);
   to128(deposited, b->deposited);
   b->escaped[0] = c[0];
   b->escaped[1] = c[1];
@@ -636,7 +696,8 @@ void pmc_destroy(pmc_context *ctx) {
     (void)hipSetDevice(ctx->device);
     wait_pending(ctx);
     for (auto &kv : ctx->phases) free_phase(ctx, kv.second);
-    release(ctx, ctx->scratch);
+    for (auto &e : ctx->cache) release(ctx, e->buf);
+    ctx->cache.clear();
     release(ctx, ctx->cursor);
     release(ctx, ctx->counters);
     if (ctx->d_tab) (void)hipFree(ctx->d_tab);
@@ -757,14 +818,14 @@ int pmc_unload_phase(pmc_context *ctx, int32_t phase) {
     free_phase(ctx, it->second);
   }
   ctx->phases.erase(it);
-  ctx->prep.valid = false;
   return PMC_OK;
 }
 
-int pmc_load_spots(pmc_context *ctx, const pmc_field *fields, int32_t n_fields,
-                   const pmc_spot *spots, int64_t n_spots) {
+int pmc_load_plan(pmc_context *ctx, int32_t plan, const pmc_field *fields, int32_t n_fields,
+                  const pmc_spot *spots, int64_t n_spots) {
   if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
   ctx->err.clear();
+  if (plan < 0 || plan > kMaxPhaseId) return fail(ctx, PMC_E_INVAL, "plan id must be 0..%d", kMaxPhaseId);
   if (!fields || n_fields < 1) return fail(ctx, PMC_E_INVAL, "need at least one field");
   if (!spots || n_spots < 1 || n_spots > 0x7fffffffLL)
     return fail(ctx, PMC_E_INVAL, "need 1..2^31-1 spots");
@@ -790,10 +851,51 @@ int pmc_load_spots(pmc_context *ctx, const pmc_field *fields, int32_t n_fields,
     if (S.phase < 0 || S.phase > kMaxPhaseId)
       return fail(ctx, PMC_E_INVAL, "spot %lld: phase %d outside 0..%d", (long long)s, S.phase, kMaxPhaseId);
   }
-  ctx->fields.assign(fields, fields + n_fields);
-  ctx->spots.assign(spots, spots + n_spots);
-  ctx->have_plan = true;
-  ++ctx->plan_version;
+  PlanRec &P = ctx->plans[plan];
+  P.fields.assign(fields, fields + n_fields);
+  P.spots.assign(spots, spots + n_spots);
+  P.version = ++ctx->plan_counter;
+  return PMC_OK;
+}
+
+int pmc_load_spots(pmc_context *ctx, const pmc_field *fields, int32_t n_fields,
+                   const pmc_spot *spots, int64_t n_spots) {
+  return pmc_load_plan(ctx, 0, fields, n_fields, spots, n_spots);
+}
+
+int pmc_unload_plan(pmc_context *ctx, int32_t plan) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  auto it = ctx->plans.find(plan);
+  if (it == ctx->plans.end()) return fail(ctx, PMC_E_STATE, "plan %d is not loaded", plan);
+  ctx->plans.erase(it);
+  // drop the plan's prepared data
+  for (size_t i = 0; i < ctx->cache.size();) {
+    if (ctx->cache[i]->plan_id == plan) {
+      wait_pending(ctx);
+      release(ctx, ctx->cache[i]->buf);
+      ctx->cache.erase(ctx->cache.begin() + (long)i);
+    } else {
+      ++i;
+    }
+  }
+  return PMC_OK;
+}
+
+int pmc_request_items(pmc_context *ctx, const pmc_request *req, uint64_t *n_items) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  int rc = validate_request(ctx, req);
+  if (rc) return rc;
+  if (!n_items) return fail(ctx, PMC_E_INVAL, "n_items is NULL");
+  if (req->engine != PMC_ENGINE_PERSISTENT)
+    return fail(ctx, PMC_E_INVAL, "work items belong to the persistent engine");
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  Prepared *P = nullptr;
+  rc = ctx->precision == PMC_FP64 ? prepare<double>(ctx, req, &P) : prepare<float>(ctx, req, &P);
+  if (rc) return rc;
+  *n_items = (uint64_t)P->n_items;
   return PMC_OK;
 }
 
@@ -828,18 +930,10 @@ int pmc_balance_from_counters(pmc_context *ctx, const pmc_request *req, const ui
   if (!counters || !deposited || !out) return fail(ctx, PMC_E_INVAL, "NULL argument");
   int rc = validate_request(ctx, req);
   if (rc) return rc;
-  // the incident total depends only on the split: recompute it on the host
-  std::vector<int64_t> per(ctx->spots.size());
-  rc = split(ctx->spots.data(), (int64_t)ctx->spots.size(), req->phases, req->n_phases,
-             req->n_histories, per.data());
-  if (rc) return fail(ctx, rc, "history split failed");
   unsigned __int128 inc = 0;
-  for (size_t s = 0; s < per.size(); ++s)
-    if (per[s] > 0)
-      inc += (unsigned __int128)(unsigned long long)per[s] *
-             (unsigned long long)q_working(ctx, ctx->spots[s].energy_MeV);
-  fill_balance(ctx, counters, from128(deposited), out);
-  to128(inc, out->incident);
+  rc = incident_of(ctx, req, &inc);
+  if (rc) return rc;
+  fill_balance(inc, counters, from128(deposited), out);
   return PMC_OK;
 }
 
@@ -945,18 +1039,24 @@ int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
   if (balance_out) {
     uint64_t c[PMC_COUNTERS];
     HIP_TRY(ctx, hipMemcpy(c, ctx->counters.p, sizeof c, hipMemcpyDeviceToHost), "copy counters");
-    fill_balance(ctx, c, deposited, balance_out);
+    unsigned __int128 inc = 0;
+    rc = incident_of(ctx, req, &inc);
+    if (rc) return rc;
+    fill_balance(inc, c, deposited, balance_out);
   }
   return PMC_OK;
 }
 
-int pmc_trace(pmc_context *ctx, int32_t phase, int64_t spot, uint32_t history, uint32_t request_id,
-              uint32_t flags, pmc_trace_rec *out, int32_t max_rec, int32_t *n_rec) {
+int pmc_trace(pmc_context *ctx, int32_t plan, int32_t phase, int64_t spot, uint32_t history,
+              uint32_t request_id, uint32_t flags, pmc_trace_rec *out, int32_t max_rec,
+              int32_t *n_rec) {
   if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
   ctx->err.clear();
   if (!out || max_rec < 1 || !n_rec) return fail(ctx, PMC_E_INVAL, "need an output buffer");
-  if (!ctx->have_plan) return fail(ctx, PMC_E_STATE, "no plan loaded");
-  if (spot < 0 || spot >= (int64_t)ctx->spots.size()) return fail(ctx, PMC_E_INVAL, "spot out of range");
+  auto pit = ctx->plans.find(plan);
+  if (pit == ctx->plans.end()) return fail(ctx, PMC_E_STATE, "plan %d is not loaded", plan);
+  const PlanRec &PL = pit->second;
+  if (spot < 0 || spot >= (int64_t)PL.spots.size()) return fail(ctx, PMC_E_INVAL, "spot out of range");
   auto it = ctx->phases.find(phase);
   if (it == ctx->phases.end()) return fail(ctx, PMC_E_NOPHASE, "phase %d is not loaded", phase);
   if (flags & ~31u) return fail(ctx, PMC_E_INVAL, "unknown flag bits");
@@ -964,10 +1064,10 @@ int pmc_trace(pmc_context *ctx, int32_t phase, int64_t spot, uint32_t history, u
   HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   wait_pending(ctx);
   const PhaseRec &ph = it->second;
-  const pmc_spot &sp = ctx->spots[spot];
+  const pmc_spot &sp = PL.spots[spot];
   const bool fp64 = ctx->precision == PMC_FP64;
-  SpotDev<double> s64 = make_spot<double>(sp, ctx->fields[sp.field], ph, 0);
-  SpotDev<float> s32 = make_spot<float>(sp, ctx->fields[sp.field], ph, 0);
+  SpotDev<double> s64 = make_spot<double>(sp, PL.fields[sp.field], ph, 0);
+  SpotDev<float> s32 = make_spot<float>(sp, PL.fields[sp.field], ph, 0);
   const size_t rec_bytes = sizeof(pmc_trace_rec) * (size_t)max_rec;
   const size_t tally_bytes = (size_t)ph.nvox() * 8;
   void *d = nullptr;
@@ -1031,10 +1131,13 @@ int pmc_graph_create(pmc_context *ctx, const pmc_request *req, int64_t *const *d
   if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
   HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   const bool fp64 = ctx->precision == PMC_FP64;
-  rc = fp64 ? prepare<double>(ctx, req) : prepare<float>(ctx, req);
+  Prepared *PP = nullptr;
+  rc = fp64 ? prepare<double>(ctx, req, &PP) : prepare<float>(ctx, req, &PP);
   if (rc) return rc;
+  if (req->item_end > (uint64_t)PP->n_items || req->item_begin > (uint64_t)PP->n_items)
+    return fail(ctx, PMC_E_INVAL, "work-item slice beyond the request's items");
   wait_pending(ctx);
-  Prepared &P = ctx->prep;
+  Prepared &P = *PP;
   const size_t bytes = align256(P.bytes) + 256;  // request data + cursor
   if (ctx->used + bytes > ctx->budget)
     return fail(ctx, PMC_E_BUDGET, "graph data needs %zu bytes: over the device-memory budget", bytes);
@@ -1074,8 +1177,8 @@ int pmc_graph_create(pmc_context *ctx, const pmc_request *req, int64_t *const *d
   ok = ok && pmc::launch_fill_u64(counters, PMC_COUNTERS, 0ull, st) == hipSuccess;
   auto *const *tp = reinterpret_cast<unsigned long long *const *>(dev_tally);
   if (ok)
-    rc = fp64 ? enqueue_prepared<double>(ctx, req, st, tp, counters, base, cursor, false)
-              : enqueue_prepared<float>(ctx, req, st, tp, counters, base, cursor, false);
+    rc = fp64 ? enqueue_prepared<double>(ctx, P, req, st, tp, counters, base, cursor, false)
+              : enqueue_prepared<float>(ctx, P, req, st, tp, counters, base, cursor, false);
   ok = ok && rc == PMC_OK;
   for (int32_t i = 0; i < req->n_phases && ok && dev_dose; ++i) {
     if (!dev_dose[i]) continue;

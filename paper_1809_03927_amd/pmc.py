@@ -31,7 +31,7 @@ ERROR_NAMES = {0: "PMC_OK", -1: "PMC_E_INVAL", -2: "PMC_E_NOPHASE", -3: "PMC_E_B
 
 # every symbol declared in include/pmc.h
 EXPORTS = ["pmc_create", "pmc_destroy", "pmc_last_error", "pmc_load_phase", "pmc_unload_phase",
-           "pmc_load_spots", "pmc_dose", "pmc_dose_device", "pmc_balance_from_counters",
+           "pmc_load_spots", "pmc_load_plan", "pmc_unload_plan", "pmc_request_items", "pmc_dose", "pmc_dose_device", "pmc_balance_from_counters",
            "pmc_convert_device", "pmc_trace", "pmc_split_histories", "pmc_bytes_in_use",
            "pmc_graph_create", "pmc_graph_launch", "pmc_graph_destroy"]
 
@@ -45,7 +45,8 @@ class pmc_request(C.Structure):
     _fields_ = [("request_id", C.c_uint32), ("flags", C.c_uint32), ("n_histories", C.c_uint64),
                 ("phases", C.POINTER(C.c_int32)), ("n_phases", C.c_int32), ("engine", C.c_int32),
                 ("block_size", C.c_int32), ("chunk", C.c_int32), ("refill_min", C.c_int32),
-                ("grid_blocks", C.c_int32)]
+                ("grid_blocks", C.c_int32), ("plan", C.c_int32), ("reserved", C.c_int32),
+                ("item_begin", C.c_uint64), ("item_end", C.c_uint64)]
 
 
 class pmc_balance(C.Structure):
@@ -97,12 +98,15 @@ def lib():
         L.pmc_load_phase.argtypes = [vp, i32, vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp]
         L.pmc_unload_phase.argtypes = [vp, i32]
         L.pmc_load_spots.argtypes = [vp, vp, i32, vp, i64]
+        L.pmc_load_plan.argtypes = [vp, i32, vp, i32, vp, i64]
+        L.pmc_unload_plan.argtypes = [vp, i32]
+        L.pmc_request_items.argtypes = [vp, C.POINTER(pmc_request), C.POINTER(u64)]
         L.pmc_dose.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, C.POINTER(pmc_balance)]
         L.pmc_dose_device.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp]
         L.pmc_balance_from_counters.argtypes = [vp, C.POINTER(pmc_request), vp, vp,
                                                 C.POINTER(pmc_balance)]
         L.pmc_convert_device.argtypes = [vp, i32, vp, u64, vp, vp, vp]
-        L.pmc_trace.argtypes = [vp, i32, i64, u32, u32, u32, vp, i32, C.POINTER(C.c_int32)]
+        L.pmc_trace.argtypes = [vp, i32, i32, i64, u32, u32, u32, vp, i32, C.POINTER(C.c_int32)]
         L.pmc_split_histories.argtypes = [vp, i64, vp, i32, u64, vp]
         L.pmc_bytes_in_use.argtypes = [vp]
         L.pmc_bytes_in_use.restype = u64
@@ -168,15 +172,36 @@ def pmc_load_spots(ctx, fields: np.ndarray, spots: np.ndarray) -> None:
     _check(lib().pmc_load_spots(ctx, _ptr(f), len(f), _ptr(s), len(s)), ctx)
 
 
+def pmc_load_plan(ctx, plan_id: int, fields: np.ndarray, spots: np.ndarray) -> None:
+    f = np.ascontiguousarray(fields, dtype=FIELD_DTYPE)
+    s = np.ascontiguousarray(spots, dtype=SPOT_DTYPE)
+    _check(lib().pmc_load_plan(ctx, plan_id, _ptr(f), len(f), _ptr(s), len(s)), ctx)
+
+
+def pmc_unload_plan(ctx, plan_id: int) -> None:
+    _check(lib().pmc_unload_plan(ctx, plan_id), ctx)
+
+
 class Request:
     """A pmc_request that keeps its phase list alive."""
 
     def __init__(self, n_histories: int, phases: Sequence[int], request_id=0, flags=0,
-                 engine=PMC_ENGINE_PLAIN, block_size=0, chunk=0, refill_min=0, grid_blocks=0):
+                 engine=PMC_ENGINE_PLAIN, block_size=0, chunk=0, refill_min=0, grid_blocks=0,
+                 plan=0, item_begin=0, item_end=0):
         self.phase_arr = np.ascontiguousarray(phases, dtype=np.int32)
         self.c = pmc_request(request_id, flags, n_histories,
                              self.phase_arr.ctypes.data_as(C.POINTER(C.c_int32)),
-                             len(self.phase_arr), engine, block_size, chunk, refill_min, grid_blocks)
+                             len(self.phase_arr), engine, block_size, chunk, refill_min, grid_blocks,
+                             plan, 0, item_begin, item_end)
+
+    def slice(self, item_begin: int, item_end: int) -> "Request":
+        """The same request restricted to work items [item_begin, item_end)."""
+        r = Request.__new__(Request)
+        r.phase_arr = self.phase_arr
+        r.c = pmc_request.from_buffer_copy(self.c)
+        r.c.item_begin = item_begin
+        r.c.item_end = item_end
+        return r
 
     @property
     def n_phases(self):
@@ -220,12 +245,18 @@ def pmc_convert_device(ctx, phase_id: int, dev_tally: int, n_histories: int, str
                                     None if dev_density is None else C.c_void_p(dev_density)), ctx)
 
 
+def pmc_request_items(ctx, req: Request) -> int:
+    n = C.c_uint64(0)
+    _check(lib().pmc_request_items(ctx, C.byref(req.c), C.byref(n)), ctx)
+    return int(n.value)
+
+
 def pmc_trace(ctx, phase_id: int, spot: int, history: int, request_id=0, flags=0,
-              max_rec=100_000) -> np.ndarray:
+              max_rec=100_000, plan=0) -> np.ndarray:
     rec = np.zeros(max_rec, dtype=TRACE_DTYPE)
     n = C.c_int32(0)
-    _check(lib().pmc_trace(ctx, phase_id, spot, history, request_id, flags, _ptr(rec), max_rec,
-                           C.byref(n)), ctx)
+    _check(lib().pmc_trace(ctx, plan, phase_id, spot, history, request_id, flags, _ptr(rec),
+                           max_rec, C.byref(n)), ctx)
     if n.value > max_rec:
         raise ValueError(f"trace longer than {max_rec} records")
     return rec[: n.value].copy()

@@ -1,0 +1,604 @@
+"""Serving loop for dose requests that arrive over time (one GPU).
+
+An optimiser of 4D-robust plans, the use the paper foresees for the engine
+(Sec. 1 and Sec. 4.C), issues many dose calculations of different sizes.
+This loop takes such requests as they arrive and
+
+* admits them in arrival order while their phantom, tally, dose and request
+  data fit a device-memory budget (the head of the queue waits when it does
+  not fit, so no request starves);
+* keeps phantoms resident on the device and, when room is needed, unloads
+  those no admitted request uses, least recently used first;
+* runs admitted requests on the persistent engine in slices of their work
+  items (chunks of a spot's histories), each time choosing the request with
+  the fewest histories left (shortest remaining work first), so that a small
+  request arriving behind a large one waits for at most one slice.
+
+Slices of one request add into the same integer tally, and a history's random
+numbers depend only on (seed, request, spot, history), so the served dose of a
+request is bit-identical to the dose of one uninterrupted run, whatever the
+schedule.  The comparison engine ("plain-serial") runs every request whole,
+in arrival order, with the plain engine (one launch per phase).
+
+The scheduler does not know the device: an executor does the work and a clock
+tells time, so the policy is tested on the CPU with a simulated clock.
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import hashlib
+import json
+import math
+import sys
+import time
+from collections import OrderedDict, deque
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+from . import workloads as W
+
+
+# ----------------------------------------------------------------------------
+# jobs and clocks
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Job:
+    index: int
+    arrival_s: float
+    n_histories: int
+    phantom_key: tuple
+    nvox: int
+    cancel_s: Optional[float] = None     # the requester withdraws it at this time
+    n_items: int = 0
+    next_item: int = 0
+    item_hist: Optional[np.ndarray] = None  # histories per work item (sliced runs)
+    admitted_s: Optional[float] = None
+    first_run_s: Optional[float] = None
+    done_s: Optional[float] = None
+    cancelled: bool = False
+    slices: int = 0
+    state: Dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def remaining(self) -> int:
+        if self.item_hist is None:
+            return self.n_histories
+        return int(self.item_hist[self.next_item:].sum())
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+class WallClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def sleep_until(self, t: float) -> None:
+        d = t - self.now()
+        if d > 0:
+            time.sleep(d)
+
+
+class FakeClock:
+    """Simulated time, advanced by a simulated executor."""
+
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self) -> float:
+        return self.t
+
+    def sleep_until(self, t: float) -> None:
+        self.t = max(self.t, t)
+
+    def advance(self, dt: float) -> None:
+        self.t += dt
+
+
+class Executor:
+    """What the scheduler needs from a device."""
+
+    def phantom_bytes(self, key) -> int:
+        raise NotImplementedError
+
+    def job_bytes(self, job: Job) -> int:
+        raise NotImplementedError
+
+    def load_phantom(self, key) -> None:
+        raise NotImplementedError
+
+    def unload_phantom(self, key) -> None:
+        raise NotImplementedError
+
+    def start(self, job: Job, sliced: bool) -> None:
+        """Allocate the job's buffers; set job.n_items (and job.item_hist when sliced)."""
+        raise NotImplementedError
+
+    def run(self, job: Job, item_begin: int, item_end: int) -> None:
+        """Run work items [item_begin, item_end) of the job and wait for them."""
+        raise NotImplementedError
+
+    def finish(self, job: Job) -> None:
+        """Produce the job's dose on the host (the request is served when this returns)."""
+        raise NotImplementedError
+
+    def release(self, job: Job) -> None:
+        """Free the job's buffers (after finish, or on cancellation)."""
+        raise NotImplementedError
+
+
+# ----------------------------------------------------------------------------
+# scheduler
+# ----------------------------------------------------------------------------
+
+class Scheduler:
+    """Admission by device-memory budget, phantom residency, slice scheduling.
+
+    policy "srpt": slices of at most `slice_histories` histories (at least one
+    work item), the admitted request with the fewest histories left first.
+    policy "fifo": every request whole, in arrival order.
+    """
+
+    def __init__(self, executor: Executor, clock, budget_bytes: int, policy: str = "srpt",
+                 slice_histories: int = 4_000_000, log: Optional[Callable[[str], None]] = None,
+                 log_every: int = 25):
+        if policy not in ("srpt", "fifo"):
+            raise ValueError(f"unknown policy {policy!r}")
+        self.ex = executor
+        self.clock = clock
+        self.budget = int(budget_bytes)
+        self.policy = policy
+        self.slice_histories = int(slice_histories)
+        self.log = log
+        self.log_every = log_every
+        self.resident: "OrderedDict[tuple, int]" = OrderedDict()  # phantom -> admitted users, LRU order
+        self.admitted: List[Job] = []
+        self.used = 0
+        self.peak_used = 0
+        self.evictions = 0
+        self.phantom_loads = 0
+        self.slices = 0
+
+    # -- memory -----------------------------------------------------------------
+    def _need(self, job: Job) -> int:
+        need = self.ex.job_bytes(job)
+        if job.phantom_key not in self.resident:
+            need += self.ex.phantom_bytes(job.phantom_key)
+        return need
+
+    def _make_room(self, job: Job) -> bool:
+        need = self._need(job)
+        for key in list(self.resident):  # least recently used first
+            if self.used + need <= self.budget:
+                break
+            if self.resident[key] == 0 and key != job.phantom_key:
+                self.ex.unload_phantom(key)
+                self.used -= self.ex.phantom_bytes(key)
+                del self.resident[key]
+                self.evictions += 1
+        return self.used + need <= self.budget
+
+    def _admit(self, job: Job) -> None:
+        if job.phantom_key not in self.resident:
+            self.ex.load_phantom(job.phantom_key)
+            self.used += self.ex.phantom_bytes(job.phantom_key)
+            self.resident[job.phantom_key] = 0
+            self.phantom_loads += 1
+        self.resident[job.phantom_key] += 1
+        self.resident.move_to_end(job.phantom_key)
+        self.used += self.ex.job_bytes(job)
+        self.peak_used = max(self.peak_used, self.used)
+        job.admitted_s = self.clock.now()
+        self.ex.start(job, sliced=self.policy == "srpt")
+        self.admitted.append(job)
+
+    def _retire(self, job: Job) -> None:
+        self.ex.release(job)
+        self.used -= self.ex.job_bytes(job)
+        self.resident[job.phantom_key] -= 1
+        self.admitted.remove(job)
+
+    # -- policy -------------------------------------------------------------------
+    def _pick(self) -> Job:
+        if self.policy == "fifo":
+            return min(self.admitted, key=lambda j: (j.arrival_s, j.index))
+        return min(self.admitted, key=lambda j: (j.remaining, j.arrival_s, j.index))
+
+    def _slice_end(self, job: Job) -> int:
+        if self.policy == "fifo" or job.item_hist is None:
+            return job.n_items
+        e, acc = job.next_item, 0
+        while e < job.n_items and (acc == 0 or acc + int(job.item_hist[e]) <= self.slice_histories):
+            acc += int(job.item_hist[e])
+            e += 1
+        return e
+
+    # -- main loop ------------------------------------------------------------------
+    def run(self, jobs: List[Job]) -> List[Job]:
+        """Serve `jobs`; return the served ones in completion order."""
+        for j in jobs:
+            if self.ex.job_bytes(j) + self.ex.phantom_bytes(j.phantom_key) > self.budget:
+                raise ValueError(f"request {j.index} needs more than the whole budget")
+        waiting = deque(sorted(jobs, key=lambda j: (j.arrival_s, j.index)))
+        done: List[Job] = []
+        while waiting or self.admitted:
+            now = self.clock.now()
+            for j in [j for j in waiting if j.cancel_s is not None and j.cancel_s <= now]:
+                waiting.remove(j)
+                j.cancelled = True
+            for j in [j for j in self.admitted if j.cancel_s is not None and j.cancel_s <= now]:
+                self._retire(j)
+                j.cancelled = True
+            while waiting and waiting[0].arrival_s <= now and self._make_room(waiting[0]):
+                self._admit(waiting.popleft())
+            if not self.admitted:
+                if not waiting:
+                    break
+                if waiting[0].arrival_s <= now:
+                    raise RuntimeError("the queue head does not fit an empty device")
+                nxt = waiting[0].arrival_s
+                if waiting[0].cancel_s is not None:
+                    nxt = min(nxt, waiting[0].cancel_s)
+                self.clock.sleep_until(nxt)
+                continue
+            job = self._pick()
+            if job.first_run_s is None:
+                job.first_run_s = self.clock.now()
+            end = self._slice_end(job)
+            self.ex.run(job, job.next_item, end)
+            job.next_item = end
+            job.slices += 1
+            self.slices += 1
+            if job.next_item >= job.n_items:
+                self.ex.finish(job)
+                job.done_s = self.clock.now()
+                self._retire(job)
+                done.append(job)
+                if self.log and len(done) % self.log_every == 0:
+                    self.log(f"{self.policy}: {len(done)} served, {len(waiting)} waiting, "
+                             f"{len(self.admitted)} admitted, t={job.done_s:.2f} s")
+        return done
+
+
+def summarize(done: List[Job], label: str) -> dict:
+    lat = np.array([j.latency_s for j in done])
+    hist = sum(j.n_histories for j in done)
+    t0 = min(j.arrival_s for j in done)
+    t1 = max(j.done_s for j in done)
+    return {"engine": label, "requests": len(done), "histories": int(hist),
+            "makespan_s": t1 - t0, "throughput_hist_per_s": hist / (t1 - t0),
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_latency_s": float(lat.mean()), "max_latency_s": float(lat.max())}
+
+
+# ----------------------------------------------------------------------------
+# simulated executor (tests of the policy)
+# ----------------------------------------------------------------------------
+
+class SimExecutor(Executor):
+    """Models a device: running h histories takes overhead_s + h / rate seconds.
+
+    It checks what the scheduler must guarantee: a phantom is loaded before
+    use and never unloaded while an admitted job uses it, and every work item
+    of a job runs exactly once."""
+
+    def __init__(self, clock: FakeClock, rate_hist_per_s=1e8, overhead_s=1e-3, chunk=256,
+                 bytes_per_voxel_phantom=3, bytes_per_voxel_job=16):
+        self.clock = clock
+        self.rate = rate_hist_per_s
+        self.overhead = overhead_s
+        self.chunk = chunk
+        self.bpv_phantom = bytes_per_voxel_phantom
+        self.bpv_job = bytes_per_voxel_job
+        self.nvox: Dict[tuple, int] = {}
+        self.loaded: set = set()
+        self.live: List[Job] = []
+        self.calls: List[tuple] = []
+        self.peak = 0
+
+    def _mem(self) -> int:
+        return (sum(self.nvox[k] * self.bpv_phantom for k in self.loaded)
+                + sum(j.nvox * self.bpv_job for j in self.live))
+
+    def phantom_bytes(self, key) -> int:
+        return self.nvox[key] * self.bpv_phantom
+
+    def job_bytes(self, job: Job) -> int:
+        self.nvox.setdefault(job.phantom_key, job.nvox)
+        return job.nvox * self.bpv_job
+
+    def load_phantom(self, key) -> None:
+        assert key not in self.loaded
+        self.loaded.add(key)
+        self.calls.append(("load", key))
+
+    def unload_phantom(self, key) -> None:
+        assert key in self.loaded
+        assert all(j.phantom_key != key for j in self.live), "phantom in use unloaded"
+        self.loaded.remove(key)
+        self.calls.append(("unload", key))
+
+    def start(self, job: Job, sliced: bool) -> None:
+        assert job.phantom_key in self.loaded
+        self.live.append(job)
+        self.peak = max(self.peak, self._mem())
+        n = job.n_histories
+        h = [self.chunk] * (n // self.chunk) + ([n % self.chunk] if n % self.chunk else [])
+        job.item_hist = np.array(h, dtype=np.int64) if sliced else None
+        job.n_items = len(h)
+        job.state["covered"] = np.zeros(len(h), dtype=np.int32)
+
+    def run(self, job: Job, item_begin: int, item_end: int) -> None:
+        assert job in self.live and job.phantom_key in self.loaded
+        assert 0 <= item_begin < item_end <= job.n_items
+        job.state["covered"][item_begin:item_end] += 1
+        h = min(job.n_histories, item_end * self.chunk) - item_begin * self.chunk
+        self.calls.append(("run", job.index, item_begin, item_end))
+        self.clock.advance(self.overhead + h / self.rate)
+
+    def finish(self, job: Job) -> None:
+        assert np.all(job.state["covered"] == 1), "work items not covered exactly once"
+        self.calls.append(("finish", job.index))
+
+    def release(self, job: Job) -> None:
+        self.live = [j for j in self.live if j is not job]
+        self.calls.append(("release", job.index))
+
+
+# ----------------------------------------------------------------------------
+# GPU executor
+# ----------------------------------------------------------------------------
+
+LUT_BYTES = 4096 * 2 * (4 + 8)  # per phase: density and stopping-power-ratio tables, FP32 and FP64
+
+
+class GpuExecutor(Executor):
+    """Runs jobs through libpmc on the current device; tallies and doses are
+    torch-owned device buffers, phantoms and plans live in the context."""
+
+    def __init__(self, ctx, phantoms: Dict[tuple, W.Phase], plans: Dict[int, W.Plan],
+                 engine: int, launch: Optional[dict] = None, verify: bool = True,
+                 keep_doses: bool = False):
+        import torch
+        from . import pmc
+        self.torch, self.pmc, self.ctx = torch, pmc, ctx
+        self.phantoms = phantoms
+        self.plans = plans
+        self.engine = engine
+        self.launch = dict(launch or {})
+        self.verify = verify
+        self.keep_doses = keep_doses
+        self.slot_of: Dict[tuple, int] = {}
+        self.free_slots = list(range(1023, -1, -1))
+        self.stream = torch.cuda.current_stream()
+        self.digests: Dict[int, str] = {}
+        self.balances: Dict[int, dict] = {}
+        self.doses: Dict[int, np.ndarray] = {}
+
+    def phantom_bytes(self, key) -> int:
+        ph = self.phantoms[key]
+        return ph.nvox * (2 + (ph.mask is not None)) + LUT_BYTES
+
+    def job_bytes(self, job: Job) -> int:
+        n_spots = len(self.plans[job.index].spots)
+        items = job.n_histories // max(1, self.launch.get("chunk") or 256) + n_spots
+        # tally + dose + counters; spot descriptors, work items, LUT copy, targets
+        return job.nvox * 16 + 128 + n_spots * 96 + items * 16 + 65536
+
+    def load_phantom(self, key) -> None:
+        if not self.free_slots:
+            raise RuntimeError("all phase slots are in use")
+        slot = self.free_slots.pop()
+        self.pmc.pmc_load_phase(self.ctx, slot, self.phantoms[key])
+        self.slot_of[key] = slot
+
+    def unload_phantom(self, key) -> None:
+        slot = self.slot_of.pop(key)
+        self.pmc.pmc_unload_phase(self.ctx, slot)
+        self.free_slots.append(slot)
+
+    def start(self, job: Job, sliced: bool) -> None:
+        torch, pmc = self.torch, self.pmc
+        slot = self.slot_of[job.phantom_key]
+        plan = self.plans[job.index]
+        spots = plan.spots.copy()
+        spots["phase"] = slot
+        plan_id = job.index % 1024
+        pmc.pmc_load_plan(self.ctx, plan_id, plan.fields, spots)
+        persistent = self.engine == pmc.PMC_ENGINE_PERSISTENT
+        kw = self.launch if persistent else {}
+        req = pmc.Request(job.n_histories, [slot], request_id=job.index, engine=self.engine,
+                          plan=plan_id, **kw)
+        job.state.update(req=req, plan_id=plan_id, slot=slot,
+                         tally=torch.zeros(job.nvox, dtype=torch.int64, device="cuda"),
+                         dose=torch.empty(job.nvox, dtype=torch.float64, device="cuda"),
+                         counters=torch.zeros(pmc.PMC_COUNTERS, dtype=torch.int64, device="cuda"))
+        if persistent:
+            job.n_items = pmc.pmc_request_items(self.ctx, req)
+            chunk = kw.get("chunk") or 256
+            h: List[int] = []
+            for n in pmc.pmc_split_histories(spots, [slot], job.n_histories):
+                n = int(n)
+                h += [chunk] * (n // chunk) + ([n % chunk] if n % chunk else [])
+            if len(h) != job.n_items:
+                raise RuntimeError("work-item count differs from the library's")
+            job.item_hist = np.array(h, dtype=np.int64) if sliced else None
+        else:
+            job.n_items = 1
+
+    def run(self, job: Job, item_begin: int, item_end: int) -> None:
+        pmc, st = self.pmc, job.state
+        req = st["req"]
+        if self.engine == pmc.PMC_ENGINE_PERSISTENT and (item_begin, item_end) != (0, job.n_items):
+            req = req.slice(item_begin, item_end)
+        pmc.pmc_dose_device(self.ctx, req, self.stream.cuda_stream, [st["tally"].data_ptr()],
+                            st["counters"].data_ptr())
+        self.stream.synchronize()
+
+    def finish(self, job: Job) -> None:
+        pmc, st = self.pmc, job.state
+        pmc.pmc_convert_device(self.ctx, st["slot"], st["tally"].data_ptr(), job.n_histories,
+                               self.stream.cuda_stream, st["dose"].data_ptr(), None)
+        st["host_dose"] = st["dose"].cpu().numpy()  # served once the dose is on the host
+
+    def release(self, job: Job) -> None:
+        pmc, st = self.pmc, job.state
+        if self.verify and "host_dose" in st:
+            t = st["tally"]
+            dep = (int((t >> 32).sum().item()) << 32) + int((t & 0xFFFFFFFF).sum().item())
+            b = pmc.pmc_balance_from_counters(self.ctx, st["req"], st["counters"].cpu().numpy(), dep)
+            if b["deposited"] + b["escaped"] + b["nuclear"] != b["incident"]:
+                raise RuntimeError(f"request {job.index}: energy balance broken {b}")
+            if b["histories"] != job.n_histories:
+                raise RuntimeError(f"request {job.index}: {b['histories']} histories run")
+            self.balances[job.index] = b
+            self.digests[job.index] = hashlib.sha256(st["host_dose"].tobytes()).hexdigest()
+            if self.keep_doses:
+                self.doses[job.index] = st["host_dose"]
+        pmc.pmc_unload_plan(self.ctx, st["plan_id"])
+        st.clear()
+
+
+# ----------------------------------------------------------------------------
+# served stream
+# ----------------------------------------------------------------------------
+
+def _make_request_data(r: W.ServedRequest):
+    return W.served_phantom(r), W.served_plan(r)
+
+
+def build_stream(reqs: List[W.ServedRequest], workers: int = 0, log=None):
+    """Phantoms and plans of a served stream, generated before serving starts.
+
+    workers > 0 uses a pool of forked processes: call it before this process
+    touches the GPU."""
+    t0 = time.time()
+    if workers > 0:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            data = pool.map(_make_request_data, reqs, chunksize=1)
+    else:
+        data = [_make_request_data(r) for r in reqs]
+    phantoms: Dict[tuple, W.Phase] = {}
+    plans: Dict[int, W.Plan] = {}
+    for r, (ph, plan) in zip(reqs, data):
+        phantoms.setdefault(r.phantom_key, ph)
+        plans[r.index] = plan
+    if log:
+        log(f"generated {len(phantoms)} phantoms and {len(plans)} plans in {time.time() - t0:.1f} s")
+    return phantoms, plans
+
+
+def jobs_of(reqs: List[W.ServedRequest], phantoms) -> List[Job]:
+    return [Job(r.index, r.arrival_s, r.n_histories, r.phantom_key, phantoms[r.phantom_key].nvox)
+            for r in reqs]
+
+
+def log_uniform_mean(lo: float, hi: float) -> float:
+    return (hi - lo) / math.log(hi / lo)
+
+
+def serve_gpu(ctx, reqs, phantoms, plans, engine: int, policy: str, budget: int,
+              launch: Optional[dict] = None, slice_histories: int = 4_000_000, log=None,
+              keep_doses: bool = False):
+    """Serve `reqs` on the GPU in real time; returns (summary, executor, scheduler)."""
+    ex = GpuExecutor(ctx, phantoms, plans, engine, launch, keep_doses=keep_doses)
+    sched = Scheduler(ex, WallClock(), budget, policy=policy, slice_histories=slice_histories,
+                      log=log)
+    done = sched.run(jobs_of(reqs, phantoms))
+    s = summarize(done, policy)
+    s.update(slices=sched.slices, evictions=sched.evictions, phantom_loads=sched.phantom_loads,
+             peak_bytes=sched.peak_used, budget_bytes=budget)
+    return s, ex, sched
+
+
+def calibrate_plain(ctx, seed: int, h_lo: float, h_hi: float, log=None) -> float:
+    """Plain-engine throughput (histories/s) on a calibration set of served
+    requests drawn with another seed."""
+    import torch
+    from . import pmc
+    reqs = W.served_stream(6, rate_hz=1.0, seed=seed + 1000, h_lo=h_lo, h_hi=h_hi)
+    phantoms, plans = build_stream(reqs)
+    ex = GpuExecutor(ctx, phantoms, plans, pmc.PMC_ENGINE_PLAIN, verify=False)
+    total_h, total_t = 0, 0.0
+    for j in jobs_of(reqs, phantoms):
+        ex.load_phantom(j.phantom_key)
+        ex.start(j, sliced=False)
+        ex.run(j, 0, 1)  # the first run also prepares the request data
+        j.state["tally"].zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ex.run(j, 0, 1)
+        total_t += time.perf_counter() - t0
+        total_h += j.n_histories
+        ex.release(j)
+        ex.unload_phantom(j.phantom_key)
+    rate = total_h / total_t
+    if log:
+        log(f"plain throughput on the calibration set: {rate:.3g} histories/s")
+    return rate
+
+
+def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_hi=5e7,
+                 slice_histories=4_000_000, launch=None, workers=0, log=None):
+    """Serve one Poisson stream with the sliced shortest-remaining-first engine
+    and with the plain engine run serially.  Arrival rate = load x plain
+    throughput / mean request size.  Returns a dict of results."""
+    reqs0 = W.served_stream(n_requests, rate_hz=1.0, seed=seed, h_lo=h_lo, h_hi=h_hi)
+    phantoms, plans = build_stream(reqs0, workers, log)
+    import torch
+    from . import pmc
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(budget_bytes or 0.9 * free)
+    ctx = pmc.pmc_create(0, pmc.PMC_FP32, seed, budget)
+    try:
+        rate_plain = calibrate_plain(ctx, seed, h_lo, h_hi, log)
+        lam = load * rate_plain / log_uniform_mean(h_lo, h_hi)
+        # the same requests on the time axis of a rate-lam Poisson process
+        reqs = [dataclasses.replace(r, arrival_s=r.arrival_s / lam) for r in reqs0]
+        out = {"requests": n_requests, "load": load, "arrival_rate_hz": lam,
+               "plain_calibration_hist_per_s": rate_plain, "budget_bytes": budget}
+        execs = {}
+        for label, engine, policy in (("batched-srpt", pmc.PMC_ENGINE_PERSISTENT, "srpt"),
+                                      ("plain-serial", pmc.PMC_ENGINE_PLAIN, "fifo")):
+            s, ex, _ = serve_gpu(ctx, reqs, phantoms, plans, engine, policy, budget, launch,
+                                 slice_histories, log)
+            for key in list(ex.slot_of):
+                ex.unload_phantom(key)
+            out[label] = s
+            execs[label] = ex
+            if log:
+                log(f"{label}: p50 {s['p50_latency_s'] * 1e3:.1f} ms, p99 "
+                    f"{s['p99_latency_s'] * 1e3:.1f} ms, {s['throughput_hist_per_s']:.3g} histories/s")
+        a, b = execs["batched-srpt"].digests, execs["plain-serial"].digests
+        out["identical_doses"] = int(sum(a[k] == b.get(k) for k in a))
+        return out
+    finally:
+        pmc.pmc_destroy(ctx)
+
+
+def main():
+    p = argparse.ArgumentParser(description="Serve a Poisson stream of dose requests on one GPU.")
+    p.add_argument("--requests", type=int, default=200)
+    p.add_argument("--load", type=float, default=0.8)
+    p.add_argument("--budget-gb", type=float, default=0.0, help="0 = 0.9 x free device memory")
+    p.add_argument("--seed", type=int, default=4)
+    p.add_argument("--slice-histories", type=int, default=4_000_000)
+    p.add_argument("--workers", type=int, default=8)
+    a = p.parse_args()
+    res = run_scenario(a.requests, a.load, a.seed, int(a.budget_gb * 2**30),
+                       slice_histories=a.slice_histories, workers=a.workers,
+                       log=lambda m: print("[serve]", m, file=sys.stderr, flush=True))
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

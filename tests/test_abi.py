@@ -31,7 +31,7 @@ def header_functions():
 
 def test_library_exports_every_header_symbol(P):
     names = header_functions()
-    assert len(names) >= 13
+    assert len(names) >= 19
     lib = C.CDLL(P.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
@@ -40,7 +40,7 @@ def test_library_exports_every_header_symbol(P):
 
 def test_struct_layouts_match_header(P):
     assert C.sizeof(P.pmc_config) == 24
-    assert C.sizeof(P.pmc_request) == 48
+    assert C.sizeof(P.pmc_request) == 72
     assert C.sizeof(P.pmc_balance) == 8 * 16
     assert W.SPOT_DTYPE.itemsize == 48 and W.FIELD_DTYPE.itemsize == 72
     assert P.TRACE_DTYPE.itemsize == 120

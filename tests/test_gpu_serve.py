@@ -1,0 +1,163 @@
+"""Serving loop and request slicing on the GPU, through the C ABI.
+
+Integer tallies and per-history random streams make every schedule give the
+same dose bit for bit: slices of a request summed == the whole request, the
+sliced shortest-remaining-first server == the plain engine run serially, and
+several plans resident in one context do not disturb each other.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1809_03927_amd import serve as S
+from paper_1809_03927_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def small_stream():
+    rng = np.random.default_rng(11)
+    reqs = []
+    grids = [(64, 64, 64), (96, 96, 96), (64, 64, 64), (128, 128, 128), (64, 64, 64), (96, 96, 96)]
+    for i, g in enumerate(grids):
+        key = (g, i % 10, 1.0, 1.0, (0.0, 0.0, 0.0)) if i != 4 else reqs[0].phantom_key
+        reqs.append(W.ServedRequest(i, 0.01 * i, g, i % 10, key, int(rng.integers(50, 400)),
+                                    int(rng.integers(20_000, 300_000)), int(rng.integers(0, 2**31))))
+    return reqs
+
+
+def test_slices_sum_to_the_whole_request():
+    import torch
+    from paper_1809_03927_amd import pmc
+    wl = W.workload_thorax4d(n_histories=300_000, shape_xyz=(64, 64, 40), n_phases=10)
+    e = pmc.Engine(device=0, seed=wl.seed)
+    try:
+        e.load_workload(wl)
+        phases = list(range(10))
+        nv = wl.phases[0].nvox
+        st = torch.cuda.current_stream()
+        req = pmc.Request(wl.n_histories, phases, engine=pmc.PMC_ENGINE_PERSISTENT, chunk=64)
+        n_items = pmc.pmc_request_items(e.ctx, req)
+        assert n_items > 10
+
+        def run(cuts):
+            t = [torch.zeros(nv, dtype=torch.int64, device="cuda") for _ in phases]
+            c = torch.zeros(16, dtype=torch.int64, device="cuda")
+            for b, en in zip(cuts, cuts[1:]):
+                pmc.pmc_dose_device(e.ctx, req.slice(b, en), st.cuda_stream, [x.data_ptr() for x in t],
+                                    c.data_ptr())
+            torch.cuda.synchronize()
+            return [x.cpu().numpy() for x in t], c.cpu().numpy()
+
+        say("slices: whole")
+        ref, cref = run([0, n_items])
+        rng = np.random.default_rng(5)
+        for k in (2, 7):
+            cuts = [0] + sorted(rng.choice(np.arange(1, n_items), size=k - 1, replace=False).tolist()) + [n_items]
+            say("slices:", cuts)
+            got, c = run(cuts)
+            assert all(np.array_equal(a, b) for a, b in zip(ref, got)), cuts
+            assert np.array_equal(c[:12], cref[:12])
+        # out-of-range slices are rejected
+        t = [torch.zeros(nv, dtype=torch.int64, device="cuda") for _ in phases]
+        with pytest.raises(pmc.PmcError, match="beyond"):
+            pmc.pmc_dose_device(e.ctx, req.slice(0, n_items + 1), st.cuda_stream,
+                                [x.data_ptr() for x in t], None)
+        assert int(sum(x.abs().sum().item() for x in t)) == 0
+    finally:
+        e.close()
+
+
+def test_multiple_plans_in_one_context():
+    import torch
+    from paper_1809_03927_amd import pmc
+    reqs = small_stream()[:3]
+    phantoms, plans = S.build_stream(reqs)
+    ctx = pmc.pmc_create(0, pmc.PMC_FP32, 4, 0)
+    try:
+        st = torch.cuda.current_stream()
+        slots = {}
+        for r in reqs:
+            slots.setdefault(r.phantom_key, len(slots))
+            pmc.pmc_load_phase(ctx, slots[r.phantom_key], phantoms[r.phantom_key])
+
+        def dose(r, plan_id):
+            nv = phantoms[r.phantom_key].nvox
+            t = torch.zeros(nv, dtype=torch.int64, device="cuda")
+            q = pmc.Request(r.n_histories, [slots[r.phantom_key]], request_id=r.index,
+                            engine=pmc.PMC_ENGINE_PERSISTENT, plan=plan_id)
+            pmc.pmc_dose_device(ctx, q, st.cuda_stream, [t.data_ptr()], None)
+            torch.cuda.synchronize()
+            return t.cpu().numpy()
+
+        def load(r, plan_id):
+            sp = plans[r.index].spots.copy()
+            sp["phase"] = slots[r.phantom_key]
+            pmc.pmc_load_plan(ctx, plan_id, plans[r.index].fields, sp)
+
+        # one plan at a time in slot 0
+        alone = []
+        for r in reqs:
+            say("plan alone", r.index)
+            load(r, 0)
+            alone.append(dose(r, 0))
+        # all resident together, interleaved
+        for i, r in enumerate(reqs):
+            load(r, 10 + i)
+        for i in (2, 0, 1, 0):
+            say("plan resident", i)
+            assert np.array_equal(dose(reqs[i], 10 + i), alone[i])
+        pmc.pmc_unload_plan(ctx, 11)
+        with pytest.raises(pmc.PmcError):
+            dose(reqs[1], 11)
+        assert np.array_equal(dose(reqs[2], 12), alone[2])
+    finally:
+        pmc.pmc_destroy(ctx)
+
+
+def test_served_equals_plain_serial():
+    import torch
+    from paper_1809_03927_amd import pmc
+    reqs = small_stream()
+    phantoms, plans = S.build_stream(reqs)
+    ctx = pmc.pmc_create(0, pmc.PMC_FP32, 4, 0)
+    try:
+        # a budget that holds the largest request (3) but not also the phantoms
+        # of the requests before it, so that admitting it must evict
+        probe = S.GpuExecutor(ctx, phantoms, plans, pmc.PMC_ENGINE_PERSISTENT, {"chunk": 64})
+        j3 = S.jobs_of(reqs, phantoms)[3]
+        tight = probe.job_bytes(j3) + probe.phantom_bytes(j3.phantom_key) + 2**20
+        assert sum(probe.phantom_bytes(r.phantom_key) for r in reqs[:3]) > 2**20
+        out = {}
+        for label, engine, policy, budget in (
+                ("srpt", pmc.PMC_ENGINE_PERSISTENT, "srpt", 2 * 2**30),
+                ("srpt-tight", pmc.PMC_ENGINE_PERSISTENT, "srpt", tight),
+                ("plain", pmc.PMC_ENGINE_PLAIN, "fifo", 2 * 2**30)):
+            say("serve", label)
+            s, ex, sched = S.serve_gpu(ctx, reqs, phantoms, plans, engine, policy, budget,
+                                       launch={"chunk": 64}, slice_histories=50_000, keep_doses=True)
+            assert s["requests"] == len(reqs)
+            assert sched.peak_used <= budget
+            if label == "srpt":
+                assert sched.slices > len(reqs)  # requests were cut
+                assert sched.phantom_loads == len(reqs) - 1  # request 4 reuses request 0's phantom
+            if label == "srpt-tight":
+                assert sched.evictions > 0
+            for key in list(ex.slot_of):
+                ex.unload_phantom(key)
+            out[label] = ex
+        for r in reqs:
+            d = out["plain"].doses[r.index]
+            assert np.isfinite(d).all() and d.max() > 0
+            for label in ("srpt", "srpt-tight"):
+                assert np.array_equal(out[label].doses[r.index], d), (label, r.index)
+                assert out[label].balances[r.index] == out["plain"].balances[r.index]
+        assert pmc.pmc_bytes_in_use(ctx) >= 0
+        torch.cuda.synchronize()
+    finally:
+        pmc.pmc_destroy(ctx)

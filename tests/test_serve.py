@@ -1,0 +1,149 @@
+"""Serving-loop policy on a simulated device (CPU, simulated clock).
+
+The simulated executor asserts the scheduler's guarantees on every call
+(phantoms loaded before use and never unloaded while in use, every work item
+run exactly once); these tests add the budget, ordering, latency and
+cancellation properties.
+"""
+import numpy as np
+import pytest
+
+from paper_1809_03927_amd import serve as S
+from paper_1809_03927_amd import workloads as W
+
+
+def job(i, t, h, key=None, nvox=1000, cancel=None):
+    return S.Job(i, t, h, key if key is not None else ("p", i), nvox, cancel_s=cancel)
+
+
+def sim(**kw):
+    clock = S.FakeClock()
+    return clock, S.SimExecutor(clock, **kw)
+
+
+def test_small_request_overtakes_large_one_under_srpt():
+    for policy in ("srpt", "fifo"):
+        clock, ex = sim(rate_hist_per_s=1e8, overhead_s=1e-4)
+        big, small = job(0, 0.0, 100_000_000), job(1, 0.1, 100_000)
+        done = S.Scheduler(ex, clock, 10**9, policy=policy, slice_histories=4_000_000).run([big, small])
+        assert {j.index for j in done} == {0, 1}
+        if policy == "srpt":
+            # waits for at most one slice of the big request
+            assert small.latency_s < 0.04 + 0.001 + 2e-4 + 1e-9
+            assert done[0] is small
+            assert big.slices == 25 + 0  # 1e8 histories in slices of 4e6
+        else:
+            assert done[0] is big and small.done_s > 1.0
+            assert big.slices == 1 and small.slices == 1
+
+
+def test_slices_respect_the_history_limit():
+    clock, ex = sim(chunk=1000)
+    j = job(0, 0.0, 10_500)
+    s = S.Scheduler(ex, clock, 10**9, policy="srpt", slice_histories=3000)
+    s.run([j])
+    runs = [c for c in ex.calls if c[0] == "run"]
+    assert [(b, e) for _, _, b, e in runs] == [(0, 3), (3, 6), (6, 9), (9, 11)]
+    # a slice limit below one item still makes progress, one item at a time
+    clock, ex = sim(chunk=1000)
+    j = job(0, 0.0, 2500)
+    S.Scheduler(ex, clock, 10**9, policy="srpt", slice_histories=10).run([j])
+    assert [(c[2], c[3]) for c in ex.calls if c[0] == "run"] == [(0, 1), (1, 2), (2, 3)]
+
+
+def random_jobs(n, seed, rate_hz, n_keys=None, nvox_choices=(10_000, 50_000, 200_000)):
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate_hz)
+        h = int(np.exp(rng.uniform(np.log(1e5), np.log(5e7))))
+        key = ("p", int(rng.integers(0, n_keys))) if n_keys else ("p", i)
+        nvox = nvox_choices[hash(key) % len(nvox_choices)]
+        out.append(job(i, t, h, key, nvox))
+    return out
+
+
+@pytest.mark.parametrize("policy", ["srpt", "fifo"])
+def test_budget_is_never_exceeded_and_everything_is_served(policy):
+    jobs = random_jobs(60, 1, rate_hz=30.0, n_keys=12)
+    budget = 6_000_000  # a few jobs at a time
+    clock, ex = sim(rate_hist_per_s=2e8)
+    s = S.Scheduler(ex, clock, budget, policy=policy)
+    done = s.run(jobs)
+    assert sorted(j.index for j in done) == list(range(60))
+    assert s.peak_used <= budget and ex.peak <= budget
+    assert s.evictions > 0
+    assert s.used == sum(ex.phantom_bytes(k) for k in ex.loaded)  # only phantoms remain
+    # admission in arrival order
+    adm = sorted(jobs, key=lambda j: j.arrival_s)
+    assert all(a.admitted_s <= b.admitted_s for a, b in zip(adm, adm[1:]))
+    assert all(j.admitted_s >= j.arrival_s for j in jobs)
+
+
+def test_phantoms_are_reused_while_resident():
+    clock, ex = sim()
+    jobs = [job(i, 0.01 * i, 1_000_000, key=("same",)) for i in range(5)]
+    s = S.Scheduler(ex, clock, 10**9)
+    s.run(jobs)
+    assert s.phantom_loads == 1 and s.evictions == 0
+    assert [c for c in ex.calls if c[0] == "load"] == [("load", ("same",))]
+
+
+def test_lru_eviction_keeps_recent_phantoms():
+    clock, ex = sim(bytes_per_voxel_phantom=1, bytes_per_voxel_job=1)
+    # room for two phantoms plus one job: A, B, C (evicts A), B (resident), A (evicts C)
+    keys = ["A", "B", "C", "B", "A"]
+    jobs = [job(i, float(i), 1000, key=(k,), nvox=100) for i, k in enumerate(keys)]
+    s = S.Scheduler(ex, clock, 300)
+    s.run(jobs)
+    loads = [c[1][0] for c in ex.calls if c[0] == "load"]
+    unloads = [c[1][0] for c in ex.calls if c[0] == "unload"]
+    assert loads == ["A", "B", "C", "A"]
+    assert unloads == ["A", "C"]
+
+
+def test_request_larger_than_budget_is_rejected():
+    clock, ex = sim()
+    with pytest.raises(ValueError):
+        S.Scheduler(ex, clock, 1000).run([job(0, 0.0, 1000, nvox=10_000)])
+
+
+def test_cancellation_of_waiting_and_running_requests():
+    clock, ex = sim(rate_hist_per_s=1e8, overhead_s=0.0)
+    a = job(0, 0.0, 50_000_000)                 # runs 0.5 s
+    b = job(1, 0.1, 40_000_000, cancel=0.2)     # admitted, cancelled part-way
+    c = job(2, 0.15, 1_000_000, cancel=0.12)    # withdrawn before it arrives
+    d = job(3, 0.3, 1_000_000)
+    s = S.Scheduler(ex, clock, 10**9, policy="srpt", slice_histories=2_000_000)
+    done = s.run([a, b, c, d])
+    assert sorted(j.index for j in done) == [0, 3]
+    assert b.cancelled and c.cancelled and b.done_s is None
+    assert ("release", 1) in ex.calls and not any(x[0] == "finish" and x[1] == 1 for x in ex.calls)
+    assert not any(x[0] == "run" and x[1] == 2 for x in ex.calls)
+    assert s.used == sum(ex.phantom_bytes(k) for k in ex.loaded)
+
+
+def test_srpt_lowers_mean_latency_at_equal_throughput():
+    reqs = W.served_stream(200, rate_hz=1.0, seed=4)
+    mean_h = S.log_uniform_mean(1e5, 5e7)
+    rate = 1.3e8
+    lam = 0.8 * rate / mean_h
+    nv = {g: int(np.prod(g)) for g in W.SERVED_GRIDS}
+    res = {}
+    for policy in ("srpt", "fifo"):
+        jobs = [S.Job(r.index, r.arrival_s / lam, r.n_histories, r.phantom_key, nv[r.grid])
+                for r in reqs]
+        clock, ex = sim(rate_hist_per_s=rate, overhead_s=2e-4)
+        done = S.Scheduler(ex, clock, 200 * 2**30, policy=policy).run(jobs)
+        res[policy] = S.summarize(done, policy)
+    assert res["srpt"]["requests"] == res["fifo"]["requests"] == 200
+    assert res["srpt"]["mean_latency_s"] < res["fifo"]["mean_latency_s"]
+    assert res["srpt"]["p50_latency_s"] < 0.5 * res["fifo"]["p50_latency_s"]
+    # the device is busy the same time either way, up to per-slice overheads
+    assert res["srpt"]["makespan_s"] == pytest.approx(res["fifo"]["makespan_s"], rel=0.05)
+
+
+def test_log_uniform_mean():
+    rng = np.random.default_rng(0)
+    x = np.exp(rng.uniform(np.log(1e5), np.log(5e7), size=2_000_000))
+    assert S.log_uniform_mean(1e5, 5e7) == pytest.approx(x.mean(), rel=5e-3)
