@@ -193,9 +193,16 @@ int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
  * transport of `req` on `stream` (a hipStream_t; NULL = default stream),
  * ADDING into the caller's zero-initialised int64 tallies dev_tally[i] (one
  * per listed phase, nx*ny*nz each) and into dev_counters (PMC_COUNTERS
- * uint64 words, nullable).  Returns after enqueueing; the scratch it uses is
- * owned by the context and reused by its next call, so calls on one context
- * must not overlap in time.  Read the counters with pmc_balance_from_counters. */
+ * uint64 words, nullable).  Returns after enqueueing.  Calls on different
+ * streams may run concurrently on the device, also when they add into the
+ * same tallies (all deposits are atomic): each persistent-engine call takes
+ * one of 16 work-queue cursors in turn and waits, on the device, for the
+ * call that used that cursor before.  A NULL dev_counters means the
+ * context's own block, which concurrent calls share.  Calls that free or
+ * replace device data (unloading or replacing phases and plans, evicting
+ * prepared requests, pmc_destroy) first wait for all work the context has
+ * enqueued.  Host calls on one context must come from one thread at a time.
+ * Read the counters with pmc_balance_from_counters. */
 int pmc_dose_device(pmc_context *ctx, const pmc_request *req, void *stream,
                     int64_t *const *dev_tally, uint64_t *dev_counters);
 

@@ -34,6 +34,8 @@ constexpr int kHuLo = -1024, kHuHi = 3071, kLut = 4096;
 constexpr int kMaxPhaseId = 1023;
 constexpr double kTwo32 = 4294967296.0;
 
+constexpr int kCursorSlots = 16;
+
 struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
@@ -113,11 +115,19 @@ struct pmc_context {
   std::map<int32_t, PlanRec> plans;
   uint64_t plan_counter = 0;
   hipStream_t stream = nullptr;
-  hipStream_t last_stream = nullptr;
-  bool pending = false;
+  // Work enqueued on callers' streams: one event per stream, recorded after
+  // the stream's latest enqueue; all are waited for before device memory
+  // that such work may read is freed or overwritten.
+  std::map<hipStream_t, hipEvent_t> stream_done;
   std::vector<std::unique_ptr<Prepared>> cache;  // prepared request data (LRU)
   uint64_t use_counter = 0;
-  DevBuf cursor;     // work-queue cursor (one uint64)
+  // Work-queue cursors of persistent launches, one 256-byte line each, used
+  // round robin; a launch that reuses a cursor first waits (on the device)
+  // for the launch that used it before, so launches on different streams may
+  // run concurrently.
+  DevBuf cursor;
+  hipEvent_t cursor_done[kCursorSlots] = {};
+  int next_cursor = 0;
   DevBuf counters;   // internal counter block
 };
 
@@ -159,6 +169,8 @@ double calib_at(const double *x, const double *y, int n, double hu) {
   return y[i] + (y[i + 1] - y[i]) * t;
 }
 
+void wait_pending(pmc_context *ctx);
+
 // grow-only device buffer with budget accounting
 int ensure(pmc_context *ctx, DevBuf &b, size_t bytes, const char *what) {
   if (b.cap >= bytes) return PMC_OK;
@@ -167,8 +179,7 @@ int ensure(pmc_context *ctx, DevBuf &b, size_t bytes, const char *what) {
     return fail(ctx, PMC_E_BUDGET, "%s: %zu bytes exceed the device-memory budget (%llu in use of %llu)",
                 what, cap, (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
   if (b.p) {
-    if (ctx->pending) (void)hipStreamSynchronize(ctx->last_stream);
-    ctx->pending = false;
+    wait_pending(ctx);
     (void)hipFree(b.p);
     ctx->used -= b.cap;
     b.p = nullptr;
@@ -202,8 +213,15 @@ void free_phase(pmc_context *ctx, PhaseRec &p) {
 }
 
 void wait_pending(pmc_context *ctx) {
-  if (ctx->pending) (void)hipStreamSynchronize(ctx->last_stream);
-  ctx->pending = false;
+  for (auto &kv : ctx->stream_done) (void)hipEventSynchronize(kv.second);
+}
+
+// Record that work reading the context's device memory was enqueued on st.
+int note_pending(pmc_context *ctx, hipStream_t st) {
+  hipEvent_t &ev = ctx->stream_done[st];
+  if (!ev) HIP_TRY(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+  HIP_TRY(ctx, hipEventRecord(ev, st), "hipEventRecord");
+  return PMC_OK;
 }
 
 long long q_working(const pmc_context *ctx, double E) {
@@ -329,6 +347,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 int default_chunk(const pmc_request *req) { return req->chunk > 0 ? req->chunk : 256; }
 
 constexpr size_t kMaxPrepared = 32;
+
 
 void evict_lru(pmc_context *ctx) {
   size_t lru = 0;
@@ -548,8 +567,6 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     a.grid = grid;
     HIP_TRY(ctx, pmc::launch_persistent(a, fp64, st), "transport_persistent launch");
   }
-  ctx->last_stream = st;
-  ctx->pending = true;
   return PMC_OK;
 }
 
@@ -562,11 +579,23 @@ int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
   if (req->item_end > (uint64_t)P->n_items || req->item_begin > (uint64_t)P->n_items)
     return fail(ctx, PMC_E_INVAL, "work-item slice [%llu, %llu) beyond the request's %d items",
                 (unsigned long long)req->item_begin, (unsigned long long)req->item_end, P->n_items);
-  rc = ensure(ctx, ctx->cursor, 256, "work-queue cursor");
+  unsigned long long *cursor = nullptr;
+  hipEvent_t *cursor_done = nullptr;
+  if (req->engine == PMC_ENGINE_PERSISTENT) {
+    rc = ensure(ctx, ctx->cursor, 256 * kCursorSlots, "work-queue cursors");
+    if (rc) return rc;
+    const int slot = ctx->next_cursor;
+    ctx->next_cursor = (slot + 1) % kCursorSlots;
+    cursor_done = &ctx->cursor_done[slot];
+    if (*cursor_done) HIP_TRY(ctx, hipStreamWaitEvent(st, *cursor_done, 0), "wait for cursor");
+    else HIP_TRY(ctx, hipEventCreateWithFlags(cursor_done, hipEventDisableTiming), "hipEventCreate");
+    cursor = reinterpret_cast<unsigned long long *>(static_cast<unsigned char *>(ctx->cursor.p) + 256 * slot);
+  }
+  rc = enqueue_prepared<R>(ctx, *P, req, st, tally, counters, static_cast<unsigned char *>(P->buf.p),
+                           cursor, true);
   if (rc) return rc;
-  return enqueue_prepared<R>(ctx, *P, req, st, tally, counters,
-                             static_cast<unsigned char *>(P->buf.p),
-                             static_cast<unsigned long long *>(ctx->cursor.p), true);
+  if (cursor_done) HIP_TRY(ctx, hipEventRecord(*cursor_done, st), "hipEventRecord");
+  return note_pending(ctx, st);
 }
 
 // Incident energy of a request (depends only on the split): 128-bit sum.
@@ -700,6 +729,9 @@ void pmc_destroy(pmc_context *ctx) {
     ctx->cache.clear();
     release(ctx, ctx->cursor);
     release(ctx, ctx->counters);
+    for (hipEvent_t ev : ctx->cursor_done)
+      if (ev) (void)hipEventDestroy(ev);
+    for (auto &kv : ctx->stream_done) (void)hipEventDestroy(kv.second);
     if (ctx->d_tab) (void)hipFree(ctx->d_tab);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   }
@@ -952,7 +984,7 @@ int pmc_convert_device(pmc_context *ctx, int32_t phase, const int64_t *dev_tally
                                    ph.nvox(), vol, (double)n_histories, dev_dose, dev_density,
                                    (hipStream_t)stream),
           "convert launch");
-  return PMC_OK;
+  return note_pending(ctx, (hipStream_t)stream);
 }
 
 int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
@@ -983,8 +1015,7 @@ int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
     void *a, *b;
     size_t na, nb;
     ~Guard() {
-      if (c->pending) (void)hipStreamSynchronize(c->last_stream);
-      c->pending = false;
+      wait_pending(c);
       if (a) { (void)hipFree(a); c->used -= na; }
       if (b) { (void)hipFree(b); c->used -= nb; }
     }
@@ -1035,7 +1066,6 @@ int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
     HIP_TRY(ctx, hipStreamSynchronize(st), "transport / conversion");
     for (long long v = 0; v < nv; ++v) deposited += (unsigned __int128)(uint64_t)tdst[v];
   }
-  ctx->pending = false;
   if (balance_out) {
     uint64_t c[PMC_COUNTERS];
     HIP_TRY(ctx, hipMemcpy(c, ctx->counters.p, sizeof c, hipMemcpyDeviceToHost), "copy counters");
@@ -1190,7 +1220,6 @@ int pmc_graph_create(pmc_context *ctx, const pmc_request *req, int64_t *const *d
   }
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(st, &graph);
-  ctx->pending = false;
   g->graph = graph;
   if (!ok) {
     const std::string msg = ctx->err.empty() ? "launch failed during capture" : ctx->err;
@@ -1209,7 +1238,7 @@ int pmc_graph_launch(pmc_graph *g, void *stream) {
   pmc_context *ctx = g->ctx;
   ctx->err.clear();
   HIP_TRY(ctx, hipGraphLaunch(g->exec, (hipStream_t)stream), "hipGraphLaunch");
-  return PMC_OK;
+  return note_pending(ctx, (hipStream_t)stream);
 }
 
 void pmc_graph_destroy(pmc_graph *g) {

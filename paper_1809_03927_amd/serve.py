@@ -11,8 +11,14 @@ This loop takes such requests as they arrive and
   those no admitted request uses, least recently used first;
 * runs admitted requests on the persistent engine in slices of their work
   items (chunks of a spot's histories), each time choosing the request with
-  the fewest histories left (shortest remaining work first), so that a small
-  request arriving behind a large one waits for at most one slice.
+  the least expected slowdown, remaining run time / (time waited + c): a
+  small request arriving behind a large one waits for about one slice, as
+  under shortest-remaining-work-first, while a large request that has waited
+  long gains priority, which keeps the latency tail near that of serving in
+  arrival order;
+* keeps two slices in flight on two streams, so that the drain of one
+  persistent launch (its last histories running at falling occupancy)
+  overlaps the start of the next.
 
 Slices of one request add into the same integer tally, and a history's random
 numbers depend only on (seed, request, spot, history), so the served dose of a
@@ -53,7 +59,9 @@ class Job:
     nvox: int
     cancel_s: Optional[float] = None     # the requester withdraws it at this time
     n_items: int = 0
-    next_item: int = 0
+    next_item: int = 0                   # first work item not yet submitted
+    items_done: int = 0
+    in_flight: int = 0                   # slices submitted and not yet completed
     item_hist: Optional[np.ndarray] = None  # histories per work item (sliced runs)
     admitted_s: Optional[float] = None
     first_run_s: Optional[float] = None
@@ -121,9 +129,16 @@ class Executor:
         """Allocate the job's buffers; set job.n_items (and job.item_hist when sliced)."""
         raise NotImplementedError
 
-    def run(self, job: Job, item_begin: int, item_end: int) -> None:
-        """Run work items [item_begin, item_end) of the job and wait for them."""
+    def submit(self, job: Job, item_begin: int, item_end: int):
+        """Start work items [item_begin, item_end) of the job; return a token."""
         raise NotImplementedError
+
+    def wait(self, token) -> None:
+        """Wait until the submission of `token` has completed."""
+        raise NotImplementedError
+
+    def run(self, job: Job, item_begin: int, item_end: int) -> None:
+        self.wait(self.submit(job, item_begin, item_end))
 
     def finish(self, job: Job) -> None:
         """Produce the job's dose on the host (the request is served when this returns)."""
@@ -141,16 +156,28 @@ class Executor:
 class Scheduler:
     """Admission by device-memory budget, phantom residency, slice scheduling.
 
-    policy "srpt": slices of at most `slice_histories` histories (at least one
-    work item), the admitted request with the fewest histories left first.
+    Sliced policies cut requests into slices of at most `slice_histories`
+    histories (at least one work item) and choose, before each slice,
+      "slowdown": the least (remaining histories / rate_hist_per_s) /
+                  (time since arrival + slowdown_c_s);
+      "srpt":     the fewest remaining histories.
     policy "fifo": every request whole, in arrival order.
+    `depth` submissions are kept in flight (completed in submission order).
     """
 
-    def __init__(self, executor: Executor, clock, budget_bytes: int, policy: str = "srpt",
+    POLICIES = ("slowdown", "srpt", "fifo")
+
+    def __init__(self, executor: Executor, clock, budget_bytes: int, policy: str = "slowdown",
                  slice_histories: int = 4_000_000, log: Optional[Callable[[str], None]] = None,
-                 log_every: int = 25):
-        if policy not in ("srpt", "fifo"):
+                 log_every: int = 25, depth: int = 1, rate_hist_per_s: float = 1.3e8,
+                 slowdown_c_s: float = 0.05):
+        if policy not in self.POLICIES:
             raise ValueError(f"unknown policy {policy!r}")
+        self.rate = float(rate_hist_per_s)
+        self.slowdown_c = float(slowdown_c_s)
+        if depth < 1:
+            raise ValueError("depth must be >= 1")
+        self.depth = depth
         self.ex = executor
         self.clock = clock
         self.budget = int(budget_bytes)
@@ -196,7 +223,7 @@ class Scheduler:
         self.used += self.ex.job_bytes(job)
         self.peak_used = max(self.peak_used, self.used)
         job.admitted_s = self.clock.now()
-        self.ex.start(job, sliced=self.policy == "srpt")
+        self.ex.start(job, sliced=self.policy != "fifo")
         self.admitted.append(job)
 
     def _retire(self, job: Job) -> None:
@@ -206,10 +233,17 @@ class Scheduler:
         self.admitted.remove(job)
 
     # -- policy -------------------------------------------------------------------
-    def _pick(self) -> Job:
+    def _pick(self) -> Optional[Job]:
+        ready = [j for j in self.admitted if j.next_item < j.n_items]
+        if not ready:
+            return None
         if self.policy == "fifo":
-            return min(self.admitted, key=lambda j: (j.arrival_s, j.index))
-        return min(self.admitted, key=lambda j: (j.remaining, j.arrival_s, j.index))
+            return min(ready, key=lambda j: (j.arrival_s, j.index))
+        if self.policy == "srpt":
+            return min(ready, key=lambda j: (j.remaining, j.arrival_s, j.index))
+        now = self.clock.now()
+        return min(ready, key=lambda j: (j.remaining / self.rate / (now - j.arrival_s + self.slowdown_c),
+                                         j.arrival_s, j.index))
 
     def _slice_end(self, job: Job) -> int:
         if self.policy == "fifo" or job.item_hist is None:
@@ -227,43 +261,56 @@ class Scheduler:
             if self.ex.job_bytes(j) + self.ex.phantom_bytes(j.phantom_key) > self.budget:
                 raise ValueError(f"request {j.index} needs more than the whole budget")
         waiting = deque(sorted(jobs, key=lambda j: (j.arrival_s, j.index)))
+        inflight: deque = deque()  # (job, item_begin, item_end, token)
         done: List[Job] = []
         while waiting or self.admitted:
             now = self.clock.now()
             for j in [j for j in waiting if j.cancel_s is not None and j.cancel_s <= now]:
                 waiting.remove(j)
                 j.cancelled = True
-            for j in [j for j in self.admitted if j.cancel_s is not None and j.cancel_s <= now]:
+            for j in [j for j in self.admitted
+                      if j.cancel_s is not None and j.cancel_s <= now and j.in_flight == 0]:
                 self._retire(j)
                 j.cancelled = True
             while waiting and waiting[0].arrival_s <= now and self._make_room(waiting[0]):
                 self._admit(waiting.popleft())
-            if not self.admitted:
-                if not waiting:
+            # keep `depth` slices in flight
+            while len(inflight) < self.depth:
+                job = self._pick()
+                if job is None:
                     break
-                if waiting[0].arrival_s <= now:
-                    raise RuntimeError("the queue head does not fit an empty device")
-                nxt = waiting[0].arrival_s
-                if waiting[0].cancel_s is not None:
-                    nxt = min(nxt, waiting[0].cancel_s)
-                self.clock.sleep_until(nxt)
+                if job.first_run_s is None:
+                    job.first_run_s = self.clock.now()
+                b, e = job.next_item, self._slice_end(job)
+                inflight.append((job, b, e, self.ex.submit(job, b, e)))
+                job.next_item = e
+                job.in_flight += 1
+                job.slices += 1
+                self.slices += 1
+            if inflight:
+                job, b, e, token = inflight.popleft()
+                self.ex.wait(token)
+                job.in_flight -= 1
+                job.items_done += e - b
+                if job.items_done == job.n_items:
+                    self.ex.finish(job)
+                    job.done_s = self.clock.now()
+                    self._retire(job)
+                    done.append(job)
+                    if self.log and len(done) % self.log_every == 0:
+                        self.log(f"{self.policy}: {len(done)} served, {len(waiting)} waiting, "
+                                 f"{len(self.admitted)} admitted, t={job.done_s:.2f} s")
                 continue
-            job = self._pick()
-            if job.first_run_s is None:
-                job.first_run_s = self.clock.now()
-            end = self._slice_end(job)
-            self.ex.run(job, job.next_item, end)
-            job.next_item = end
-            job.slices += 1
-            self.slices += 1
-            if job.next_item >= job.n_items:
-                self.ex.finish(job)
-                job.done_s = self.clock.now()
-                self._retire(job)
-                done.append(job)
-                if self.log and len(done) % self.log_every == 0:
-                    self.log(f"{self.policy}: {len(done)} served, {len(waiting)} waiting, "
-                             f"{len(self.admitted)} admitted, t={job.done_s:.2f} s")
+            if self.admitted:  # only cancelled-pending work remains: nothing runs it
+                raise RuntimeError("admitted requests with no work left to submit")
+            if not waiting:
+                break
+            if waiting[0].arrival_s <= now:
+                raise RuntimeError("the queue head does not fit an empty device")
+            nxt = waiting[0].arrival_s
+            if waiting[0].cancel_s is not None:
+                nxt = min(nxt, waiting[0].cancel_s)
+            self.clock.sleep_until(nxt)
         return done
 
 
@@ -303,6 +350,7 @@ class SimExecutor(Executor):
         self.live: List[Job] = []
         self.calls: List[tuple] = []
         self.peak = 0
+        self.busy_until = 0.0
 
     def _mem(self) -> int:
         return (sum(self.nvox[k] * self.bpv_phantom for k in self.loaded)
@@ -336,16 +384,22 @@ class SimExecutor(Executor):
         job.n_items = len(h)
         job.state["covered"] = np.zeros(len(h), dtype=np.int32)
 
-    def run(self, job: Job, item_begin: int, item_end: int) -> None:
+    def submit(self, job: Job, item_begin: int, item_end: int):
         assert job in self.live and job.phantom_key in self.loaded
         assert 0 <= item_begin < item_end <= job.n_items
         job.state["covered"][item_begin:item_end] += 1
         h = min(job.n_histories, item_end * self.chunk) - item_begin * self.chunk
         self.calls.append(("run", job.index, item_begin, item_end))
-        self.clock.advance(self.overhead + h / self.rate)
+        # the device runs submissions one after another
+        self.busy_until = max(self.busy_until, self.clock.now()) + self.overhead + h / self.rate
+        return self.busy_until
+
+    def wait(self, token) -> None:
+        self.clock.sleep_until(token)
 
     def finish(self, job: Job) -> None:
         assert np.all(job.state["covered"] == 1), "work items not covered exactly once"
+        assert job.in_flight == 0
         self.calls.append(("finish", job.index))
 
     def release(self, job: Job) -> None:
@@ -366,7 +420,7 @@ class GpuExecutor(Executor):
 
     def __init__(self, ctx, phantoms: Dict[tuple, W.Phase], plans: Dict[int, W.Plan],
                  engine: int, launch: Optional[dict] = None, verify: bool = True,
-                 keep_doses: bool = False):
+                 keep_doses: bool = False, n_streams: int = 1):
         import torch
         from . import pmc
         self.torch, self.pmc, self.ctx = torch, pmc, ctx
@@ -379,6 +433,8 @@ class GpuExecutor(Executor):
         self.slot_of: Dict[tuple, int] = {}
         self.free_slots = list(range(1023, -1, -1))
         self.stream = torch.cuda.current_stream()
+        # submissions go to side streams (default priority), one per slice in flight
+        self.free_streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.digests: Dict[int, str] = {}
         self.balances: Dict[int, dict] = {}
         self.doses: Dict[int, np.ndarray] = {}
@@ -433,15 +489,24 @@ class GpuExecutor(Executor):
             job.item_hist = np.array(h, dtype=np.int64) if sliced else None
         else:
             job.n_items = 1
+        self.stream.synchronize()  # buffers are zero before a side stream adds into them
 
-    def run(self, job: Job, item_begin: int, item_end: int) -> None:
+    def submit(self, job: Job, item_begin: int, item_end: int):
         pmc, st = self.pmc, job.state
         req = st["req"]
         if self.engine == pmc.PMC_ENGINE_PERSISTENT and (item_begin, item_end) != (0, job.n_items):
             req = req.slice(item_begin, item_end)
-        pmc.pmc_dose_device(self.ctx, req, self.stream.cuda_stream, [st["tally"].data_ptr()],
+        stream = self.free_streams.pop()
+        pmc.pmc_dose_device(self.ctx, req, stream.cuda_stream, [st["tally"].data_ptr()],
                             st["counters"].data_ptr())
-        self.stream.synchronize()
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        return ev, stream
+
+    def wait(self, token) -> None:
+        ev, stream = token
+        ev.synchronize()
+        self.free_streams.append(stream)
 
     def finish(self, job: Job) -> None:
         pmc, st = self.pmc, job.state
@@ -508,15 +573,15 @@ def log_uniform_mean(lo: float, hi: float) -> float:
 
 def serve_gpu(ctx, reqs, phantoms, plans, engine: int, policy: str, budget: int,
               launch: Optional[dict] = None, slice_histories: int = 4_000_000, log=None,
-              keep_doses: bool = False):
+              keep_doses: bool = False, depth: int = 1, rate_hist_per_s: float = 1.3e8):
     """Serve `reqs` on the GPU in real time; returns (summary, executor, scheduler)."""
-    ex = GpuExecutor(ctx, phantoms, plans, engine, launch, keep_doses=keep_doses)
+    ex = GpuExecutor(ctx, phantoms, plans, engine, launch, keep_doses=keep_doses, n_streams=depth)
     sched = Scheduler(ex, WallClock(), budget, policy=policy, slice_histories=slice_histories,
-                      log=log)
+                      log=log, depth=depth, rate_hist_per_s=rate_hist_per_s)
     done = sched.run(jobs_of(reqs, phantoms))
     s = summarize(done, policy)
     s.update(slices=sched.slices, evictions=sched.evictions, phantom_loads=sched.phantom_loads,
-             peak_bytes=sched.peak_used, budget_bytes=budget)
+             peak_bytes=sched.peak_used, budget_bytes=budget, slices_in_flight=depth)
     return s, ex, sched
 
 
@@ -548,10 +613,12 @@ def calibrate_plain(ctx, seed: int, h_lo: float, h_hi: float, log=None) -> float
 
 
 def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_hi=5e7,
-                 slice_histories=4_000_000, launch=None, workers=0, log=None):
-    """Serve one Poisson stream with the sliced shortest-remaining-first engine
-    and with the plain engine run serially.  Arrival rate = load x plain
-    throughput / mean request size.  Returns a dict of results."""
+                 slice_histories=4_000_000, launch=None, workers=0, log=None, depth=2,
+                 policy="slowdown"):
+    """Serve one Poisson stream with the sliced persistent engine (`policy`,
+    `depth` slices in flight) and with the plain engine run serially in
+    arrival order.  Arrival rate = load x plain throughput / mean request
+    size.  Returns a dict of results."""
     reqs0 = W.served_stream(n_requests, rate_hz=1.0, seed=seed, h_lo=h_lo, h_hi=h_hi)
     phantoms, plans = build_stream(reqs0, workers, log)
     import torch
@@ -567,10 +634,11 @@ def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_h
         out = {"requests": n_requests, "load": load, "arrival_rate_hz": lam,
                "plain_calibration_hist_per_s": rate_plain, "budget_bytes": budget}
         execs = {}
-        for label, engine, policy in (("batched-srpt", pmc.PMC_ENGINE_PERSISTENT, "srpt"),
-                                      ("plain-serial", pmc.PMC_ENGINE_PLAIN, "fifo")):
-            s, ex, _ = serve_gpu(ctx, reqs, phantoms, plans, engine, policy, budget, launch,
-                                 slice_histories, log)
+        for label, engine, pol, d in (
+                ("batched", pmc.PMC_ENGINE_PERSISTENT, policy, depth),
+                ("plain-serial", pmc.PMC_ENGINE_PLAIN, "fifo", 1)):
+            s, ex, _ = serve_gpu(ctx, reqs, phantoms, plans, engine, pol, budget, launch,
+                                 slice_histories, log, depth=d, rate_hist_per_s=rate_plain)
             for key in list(ex.slot_of):
                 ex.unload_phantom(key)
             out[label] = s
@@ -578,7 +646,7 @@ def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_h
             if log:
                 log(f"{label}: p50 {s['p50_latency_s'] * 1e3:.1f} ms, p99 "
                     f"{s['p99_latency_s'] * 1e3:.1f} ms, {s['throughput_hist_per_s']:.3g} histories/s")
-        a, b = execs["batched-srpt"].digests, execs["plain-serial"].digests
+        a, b = execs["batched"].digests, execs["plain-serial"].digests
         out["identical_doses"] = int(sum(a[k] == b.get(k) for k in a))
         return out
     finally:
@@ -593,9 +661,12 @@ def main():
     p.add_argument("--seed", type=int, default=4)
     p.add_argument("--slice-histories", type=int, default=4_000_000)
     p.add_argument("--workers", type=int, default=8)
+    p.add_argument("--depth", type=int, default=2, help="slices in flight (streams)")
+    p.add_argument("--policy", choices=["slowdown", "srpt"], default="slowdown")
     a = p.parse_args()
     res = run_scenario(a.requests, a.load, a.seed, int(a.budget_gb * 2**30),
-                       slice_histories=a.slice_histories, workers=a.workers,
+                       slice_histories=a.slice_histories, workers=a.workers, depth=a.depth,
+                       policy=a.policy,
                        log=lambda m: print("[serve]", m, file=sys.stderr, flush=True))
     print(json.dumps(res))
 

@@ -134,16 +134,18 @@ def test_served_equals_plain_serial():
         tight = probe.job_bytes(j3) + probe.phantom_bytes(j3.phantom_key) + 2**20
         assert sum(probe.phantom_bytes(r.phantom_key) for r in reqs[:3]) > 2**20
         out = {}
-        for label, engine, policy, budget in (
-                ("srpt", pmc.PMC_ENGINE_PERSISTENT, "srpt", 2 * 2**30),
-                ("srpt-tight", pmc.PMC_ENGINE_PERSISTENT, "srpt", tight),
-                ("plain", pmc.PMC_ENGINE_PLAIN, "fifo", 2 * 2**30)):
+        for label, engine, policy, budget, depth in (
+                ("slowdown", pmc.PMC_ENGINE_PERSISTENT, "slowdown", 2 * 2**30, 2),
+                ("srpt-tight", pmc.PMC_ENGINE_PERSISTENT, "srpt", tight, 2),
+                ("srpt-depth1", pmc.PMC_ENGINE_PERSISTENT, "srpt", 2 * 2**30, 1),
+                ("plain", pmc.PMC_ENGINE_PLAIN, "fifo", 2 * 2**30, 1)):
             say("serve", label)
             s, ex, sched = S.serve_gpu(ctx, reqs, phantoms, plans, engine, policy, budget,
-                                       launch={"chunk": 64}, slice_histories=50_000, keep_doses=True)
+                                       launch={"chunk": 64}, slice_histories=50_000, keep_doses=True,
+                                       depth=depth)
             assert s["requests"] == len(reqs)
             assert sched.peak_used <= budget
-            if label == "srpt":
+            if label == "slowdown":
                 assert sched.slices > len(reqs)  # requests were cut
                 assert sched.phantom_loads == len(reqs) - 1  # request 4 reuses request 0's phantom
             if label == "srpt-tight":
@@ -154,7 +156,7 @@ def test_served_equals_plain_serial():
         for r in reqs:
             d = out["plain"].doses[r.index]
             assert np.isfinite(d).all() and d.max() > 0
-            for label in ("srpt", "srpt-tight"):
+            for label in ("slowdown", "srpt-tight", "srpt-depth1"):
                 assert np.array_equal(out[label].doses[r.index], d), (label, r.index)
                 assert out[label].balances[r.index] == out["plain"].balances[r.index]
         assert pmc.pmc_bytes_in_use(ctx) >= 0
