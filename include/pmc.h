@@ -126,7 +126,8 @@ typedef struct {
  * Layout: [0,1] escaped, [2,3] nuclear-removed, [4,5] cutoff energy as 128-bit
  * (lo, hi) pairs in 2^-32 MeV; [6] histories, [7] steps, [8] delta events,
  * [9] nuclear events, [10] escapes, [11] misses, [12] global tally atomics
- * issued; [13..15] reserved. */
+ * issued; [13,14] energy deposited outside the spots' boxes (influence
+ * calculations, 128-bit); [15] reserved. */
 #define PMC_COUNTERS 16
 
 /* ---- context ------------------------------------------------------------ */
@@ -199,9 +200,9 @@ int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
  * one of 16 work-queue cursors in turn and waits, on the device, for the
  * call that used that cursor before.  A NULL dev_counters means the
  * context's own block, which concurrent calls share.  Calls that free or
- * replace device data (unloading or replacing phases and plans, evicting
- * prepared requests, pmc_destroy) first wait for all work the context has
- * enqueued.  Host calls on one context must come from one thread at a time.
+ * rewrite device data (unloading or replacing phases and plans, evicting
+ * prepared requests, pmc_destroy) first wait for the enqueued work that
+ * reads it.  Host calls on one context must come from one thread at a time.
  * Read the counters with pmc_balance_from_counters. */
 int pmc_dose_device(pmc_context *ctx, const pmc_request *req, void *stream,
                     int64_t *const *dev_tally, uint64_t *dev_counters);
@@ -256,6 +257,56 @@ int pmc_split_histories(const pmc_spot *spots, int64_t n_spots, const int32_t *p
 
 /* Device memory held by the context (phases, tables, scratch), in bytes. */
 uint64_t pmc_bytes_in_use(const pmc_context *ctx);
+
+/* ---- influence matrix ---------------------------------------------------- */
+
+/* Voxel box [lo, hi) per axis; lo == hi on any axis means empty. */
+typedef struct {
+  int32_t lo[3], hi[3];
+} pmc_box;
+
+/* Boxes of the spots of `plan` on `phase` (n_spots = the plan's spot count;
+ * spots of other phases get empty boxes): the axis-aligned voxel box around
+ * the spot's central axis, from where it enters the grid to water-equivalent
+ * depth R(E) + 3 cm (R: the transport's range table; water-equivalent depth
+ * = path length x stopping-power ratio of the voxels crossed) or the grid
+ * exit, widened across the beam by 3 sigma_max, sigma_max^2 = sigma_spot^2 +
+ * (0.035 L)^2, L the geometric length of that axis segment.  Host
+ * computation; works on a validation-only context. */
+int pmc_influence_boxes(pmc_context *ctx, int32_t plan, int32_t phase, pmc_box *out, int64_t n_spots);
+
+/* Sparse per-spot influence matrix of a one-phase request (the dose of each
+ * spot separately, which an optimiser of spot weights needs; Sec. 4.C).
+ * Runs the request's histories (persistent engine, launch fields honoured,
+ * not sliced) with every spot tallying into its own box (`boxes`: one per
+ * plan spot, or NULL for pmc_influence_boxes), then keeps, per spot, the
+ * voxels whose tally / density is >= rel_threshold (0..1) x that spot's
+ * maximum of it, as CSR: one row per plan spot (row_ptr: n_spots + 1
+ * int64), voxel = linear index of the phase grid (int32, ascending within a
+ * row), value = dose per history of that spot (float, Gy: energy / (density
+ * x voxel volume) / the spot's histories).  Deposits outside a spot's box
+ * are not in the matrix; their energy is returned in outside[2] (128-bit
+ * (lo, hi), 2^-32 MeV; nullable).  balance (nullable): deposited = energy
+ * in the boxes, so deposited + outside + escaped + nuclear == incident.
+ * Box tallies (int64) live in context scratch of at most max_scratch_bytes
+ * (0 = half the free budget); the spots run in batches of consecutive spots
+ * whose boxes fit it (PMC_E_BUDGET if one box does not).  The result stays
+ * in the context (pmc_influence_read, pmc_influence_device) until the next
+ * pmc_influence or pmc_influence_free.  Blocks until done.  *nnz = number of
+ * entries. */
+int pmc_influence(pmc_context *ctx, const pmc_request *req, const pmc_box *boxes, double rel_threshold,
+                  uint64_t max_scratch_bytes, uint64_t *nnz, pmc_balance *balance, uint64_t outside[2]);
+
+/* Copy the last influence matrix to caller buffers (each nullable):
+ * row_ptr[n_spots + 1], voxel[nnz], value[nnz]. */
+int pmc_influence_read(pmc_context *ctx, int64_t *row_ptr, int32_t *voxel, float *value);
+
+/* Device pointers of the last influence matrix (owned by the context). */
+int pmc_influence_device(pmc_context *ctx, const int64_t **row_ptr, const int32_t **voxel,
+                         const float **value);
+
+/* Free the influence matrix and its scratch. */
+int pmc_influence_free(pmc_context *ctx);
 
 #ifdef __cplusplus
 }

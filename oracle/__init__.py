@@ -108,6 +108,11 @@ def lib():
                                       C.c_int64, C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
                                       C.c_uint64, C.c_uint32, C.c_int32, C.c_uint32, C.c_uint32,
                                       C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]
+        L.orc_dose_spots.restype = C.c_int
+        L.orc_dose_spots.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.c_int64, C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
+                                     C.c_uint64, C.c_uint32, C.c_int32, C.c_int64, C.c_int64,
+                                     C.c_void_p, C.c_void_p]
         L.orc_trace.restype = C.c_int
         L.orc_trace.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
                                 C.c_int64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -235,6 +240,89 @@ def dose_batches(phases, plan, n_hist: int, seed: int, n_batches=10, request_id=
                            n_threads, h_mod=n_batches, h_rem=b)
         out.append(t)
     return out
+
+
+def dose_spots(phases, plan, n_hist: int, seed: int, s_begin: int, s_end: int, request_id=0,
+               phase_ids=None, flags=0, n_threads=None):
+    """Tallies of only the histories of spots s_begin <= s < s_end (history
+    split of the whole request)."""
+    if phase_ids is None:
+        phase_ids = list(range(len(phases)))
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    holders, parr = _phase_array(phases)
+    ids = np.asarray(phase_ids, dtype=np.int32)
+    tallies = [np.zeros(phases[i].hu.size, dtype=np.int64) for i in phase_ids]
+    tp = (C.c_void_p * len(ids))(*[t.ctypes.data for t in tallies])
+    bal = Balance()
+    spots = np.ascontiguousarray(plan.spots)
+    fields = np.ascontiguousarray(plan.fields)
+    rc = lib().orc_dose_spots(parr, len(phases), fields.ctypes.data, len(fields), spots.ctypes.data,
+                              len(spots), ids.ctypes.data, len(ids), int(seed), int(request_id),
+                              int(n_hist), int(flags), int(n_threads), int(s_begin), int(s_end), tp,
+                              C.byref(bal))
+    if rc:
+        raise ValueError(f"orc_dose_spots failed: {rc}")
+    del holders
+    return tallies, bal.as_dict()
+
+
+MEV_TO_J = 1.602176634e-13
+
+
+def influence(phase, plan, n_hist: int, seed: int, boxes, rel_threshold: float, request_id=0,
+              flags=0, n_threads=None):
+    """Per-spot influence matrix, from its definition: for every spot, the
+    tally of that spot's histories alone (same history split and random
+    numbers as the whole request), restricted to the spot's voxel box; keep
+    the voxels whose tally / density is at least rel_threshold times the
+    spot's maximum of it; value = energy / (density x voxel volume) / the
+    spot's histories, rounded to float32.  The per-spot dose is what an
+    optimiser of spot weights needs (Sec. 1 and Sec. 4.C of the paper).
+
+    boxes: structured array with int32 fields lo[3], hi[3] (voxel index
+    ranges [lo, hi) along x, y, z), one per spot.  The plan's spots must all
+    be on `phase` (phase index 0).  Returns a dict with row_ptr, voxel,
+    value, box_deposited, outside (2^-32 MeV) and the summed balance."""
+    per_spot = split_histories(plan.spots, [0], n_hist)
+    _, rho = convert(phase, np.zeros(phase.hu.size, dtype=np.int64), 1)
+    nx, ny, nz = phase.hu.shape[2], phase.hu.shape[1], phase.hu.shape[0]
+    vol = (phase.spacing_mm[0] * 0.1) * (phase.spacing_mm[1] * 0.1) * (phase.spacing_mm[2] * 0.1)
+    rows = [0]
+    vox, val = [], []
+    box_dep, outside = 0, 0
+    bal_sum = None
+    for s in range(len(plan.spots)):
+        if per_spot[s] == 0:
+            rows.append(rows[-1])
+            continue
+        (t,), bal = dose_spots([phase], plan, n_hist, seed, s, s + 1, request_id, [0], flags,
+                               n_threads)
+        bal_sum = bal if bal_sum is None else {k: bal_sum[k] + bal[k] for k in bal}
+        t3 = t.reshape(nz, ny, nx)
+        lo, hi = boxes[s]["lo"], boxes[s]["hi"]
+        inside = np.zeros_like(t3, dtype=bool)
+        inside[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = True
+        total = int(np.sum(t, dtype=np.int64))
+        t_in = np.where(inside, t3, 0).reshape(-1)
+        kept_energy = int(np.sum(t_in, dtype=np.int64))
+        box_dep += kept_energy
+        outside += total - kept_energy
+        ok = (t_in > 0) & (rho > 0)
+        score = np.zeros(t_in.size, dtype=np.float64)
+        score[ok] = t_in[ok].astype(np.float64) / rho[ok]
+        m = score.max() if ok.any() else 0.0
+        keep = ok & (score >= rel_threshold * m)
+        idx = np.nonzero(keep)[0]  # ascending voxel index
+        e_j = t_in[idx].astype(np.float64) / Q_SCALE * MEV_TO_J
+        m_kg = rho[idx] * vol * 1e-3
+        vox.append(idx.astype(np.int32))
+        val.append((e_j / m_kg / float(per_spot[s])).astype(np.float32))
+        rows.append(rows[-1] + len(idx))
+    return {"row_ptr": np.array(rows, dtype=np.int64),
+            "voxel": np.concatenate(vox) if vox else np.zeros(0, np.int32),
+            "value": np.concatenate(val) if val else np.zeros(0, np.float32),
+            "box_deposited": box_dep, "outside": outside, "balance": bal_sum, "per_spot": per_spot}
 
 
 def trace(phase, plan, spot: int, h: int, seed: int, request_id: int = 0, flags: int = 0,

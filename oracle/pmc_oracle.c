@@ -598,6 +598,7 @@ typedef struct {
   const int64_t *offset;       /* prefix sum of per-spot histories */
   const int64_t *count;
   int64_t n_spots;
+  int64_t s_begin, s_end;       /* only spots s_begin <= s < s_end run */
   int64_t *const *tallies;
   uint64_t seed;
   uint32_t request_id, flags, h_begin, h_end, h_mod, h_rem;
@@ -619,7 +620,7 @@ static void *job_run(void *arg) {
   for (int64_t s = lo; s < j->n_spots; ++s) {
     int64_t a = j->offset[s], e = a + j->count[s];
     if (a >= j->g_end) break;
-    if (j->count[s] == 0 || j->slot_of_spot[s] < 0) continue;
+    if (j->count[s] == 0 || j->slot_of_spot[s] < 0 || s < j->s_begin || s >= j->s_end) continue;
     int32_t slot = j->slot_of_spot[s];
     if (slot != cur_slot) {
       hctx_init(&c, &j->phases[j->phase_ids[slot]], j->fields, j->spots, j->seed, j->request_id,
@@ -647,7 +648,7 @@ static int run_common(const orc_phase *phases, int32_t n_phases, const orc_field
                       const int32_t *phase_ids, int32_t n_req_phases, uint64_t seed,
                       uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
                       uint32_t h_begin, uint32_t h_end, uint32_t h_mod, uint32_t h_rem,
-                      int64_t *const *tallies, orc_balance *bal) {
+                      int64_t s_begin, int64_t s_end, int64_t *const *tallies, orc_balance *bal) {
   if (h_mod == 0 || h_rem >= h_mod) return -1;
   if (n_phases <= 0 || n_req_phases <= 0 || n_spots <= 0 || n_hist == 0) return -1;
   for (int32_t i = 0; i < n_req_phases; ++i)
@@ -674,6 +675,7 @@ static int run_common(const orc_phase *phases, int32_t n_phases, const orc_field
     j->phase_ids = phase_ids; j->offset = offset; j->count = count; j->n_spots = n_spots;
     j->tallies = tallies; j->seed = seed; j->request_id = request_id; j->flags = flags;
     j->h_begin = h_begin; j->h_end = h_end; j->h_mod = h_mod; j->h_rem = h_rem;
+    j->s_begin = s_begin; j->s_end = s_end;
     j->g_begin = total * t / n_threads;
     j->g_end = total * (t + 1) / n_threads;
   }
@@ -706,8 +708,8 @@ int orc_dose(const orc_phase *phases, int32_t n_phases, const orc_field *fields,
              uint64_t seed, uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
              int64_t *const *tallies, double *const *dose, orc_balance *bal) {
   int rc = run_common(phases, n_phases, fields, n_fields, spots, n_spots, phase_ids, n_req_phases,
-                      seed, request_id, n_hist, flags, n_threads, 0u, 0xffffffffu, 1u, 0u, tallies,
-                      bal);
+                      seed, request_id, n_hist, flags, n_threads, 0u, 0xffffffffu, 1u, 0u, 0, n_spots,
+                      tallies, bal);
   if (rc) return rc;
   if (dose)
     for (int32_t i = 0; i < n_req_phases; ++i)
@@ -722,8 +724,19 @@ int orc_dose_subset(const orc_phase *phases, int32_t n_phases, const orc_field *
                     uint32_t h_begin, uint32_t h_end, uint32_t h_mod, uint32_t h_rem,
                     int64_t *const *tallies, orc_balance *bal) {
   return run_common(phases, n_phases, fields, n_fields, spots, n_spots, phase_ids, n_req_phases,
-                    seed, request_id, n_hist, flags, n_threads, h_begin, h_end, h_mod, h_rem,
-                    tallies, bal);
+                    seed, request_id, n_hist, flags, n_threads, h_begin, h_end, h_mod, h_rem, 0,
+                    n_spots, tallies, bal);
+}
+
+int orc_dose_spots(const orc_phase *phases, int32_t n_phases, const orc_field *fields,
+                   int32_t n_fields, const orc_spot *spots, int64_t n_spots,
+                   const int32_t *phase_ids, int32_t n_req_phases, uint64_t seed,
+                   uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
+                   int64_t s_begin, int64_t s_end, int64_t *const *tallies, orc_balance *bal) {
+  if (s_begin < 0 || s_end > n_spots || s_begin > s_end) return -1;
+  return run_common(phases, n_phases, fields, n_fields, spots, n_spots, phase_ids, n_req_phases,
+                    seed, request_id, n_hist, flags, n_threads, 0u, 0xffffffffu, 1u, 0u, s_begin,
+                    s_end, tallies, bal);
 }
 
 int orc_trace(const orc_phase *phase, const orc_field *fields, int32_t n_fields,

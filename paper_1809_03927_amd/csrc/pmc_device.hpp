@@ -146,6 +146,7 @@ template <typename R> struct Lane {
 // per-lane totals reduced at kernel end
 struct LaneCounters {
   unsigned long long esc, nuc, cut;
+  unsigned long long out;  // deposits outside the spot's box (influence calculations)
   uint32_t hist, steps, delta, nuc_ev, escapes, misses, atomics;
 };
 
@@ -158,6 +159,12 @@ template <typename R> struct Geo {
   int32_t nxy;
   R d[3];
   int32_t lut;  // index of the phase's LUT in the launch's LUT array
+};
+
+// the box a lane's spot tallies into (influence calculations)
+struct BoxLane {
+  unsigned long long *base;  // entry 0 of the box
+  int32_t lo[3], n[3];
 };
 
 // physics tables: (R, mu_delta, omega^2, 0) per node, linear in log2 E
@@ -389,28 +396,54 @@ __device__ __forceinline__ void start_history(Lane<R> &L, const SpotDev<R> &sp, 
   }
 }
 
-template <typename R>
-__device__ __forceinline__ void flush_tally(Lane<R> &L, const Geo<R> &G, LaneCounters &C) {
-  if (L.acc != 0) {
-    atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
-    C.atomics += 1;
+// Tally key of a deposit: the voxel index, or with BOX the box-local entry
+// (-2 outside the box).  The lane is still in the voxel of the step.
+template <typename R, bool BOX>
+__device__ __forceinline__ int32_t tally_key(const Lane<R> &L, const BoxLane &B, int32_t v) {
+  if constexpr (!BOX) {
+    return v;
+  } else {
+    const int32_t x = L.ix - B.lo[0], y = L.iy - B.lo[1], z = L.iz - B.lo[2];
+    const bool in = (uint32_t)x < (uint32_t)B.n[0] && (uint32_t)y < (uint32_t)B.n[1] &&
+                    (uint32_t)z < (uint32_t)B.n[2];
+    return in ? x + B.n[0] * (y + B.n[1] * z) : -2;
   }
+}
+
+template <typename R, bool BOX>
+__device__ __forceinline__ void commit_acc(const Lane<R> &L, const Geo<R> &G, const BoxLane &B,
+                                           LaneCounters &C) {
+  if (L.acc == 0) return;
+  if constexpr (BOX) {
+    if (L.acc_v < 0) {
+      C.out += (unsigned long long)L.acc;
+      return;
+    }
+    atomic_add_u64(&B.base[L.acc_v], (unsigned long long)L.acc);
+  } else {
+    atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
+  }
+  C.atomics += 1;
+}
+
+template <typename R, bool BOX = false>
+__device__ __forceinline__ void flush_tally(Lane<R> &L, const Geo<R> &G, LaneCounters &C,
+                                            const BoxLane &B = BoxLane{}) {
+  commit_acc<R, BOX>(L, G, B, C);
   L.acc = 0;
   L.acc_v = -1;
 }
 
 // consecutive deposits into the same voxel are merged in registers: at most
 // one global atomic per voxel visit
-template <typename R>
-__device__ __forceinline__ void add_tally(Lane<R> &L, const Geo<R> &G, int32_t v, long long dep,
-                                          LaneCounters &C) {
+template <typename R, bool BOX>
+__device__ __forceinline__ void add_tally(Lane<R> &L, const Geo<R> &G, const BoxLane &B, int32_t v,
+                                          long long dep, LaneCounters &C) {
   if (dep == 0) return;
-  if (v != L.acc_v) {
-    if (L.acc != 0) {
-      atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
-      C.atomics += 1;
-    }
-    L.acc_v = v;
+  const int32_t key = tally_key<R, BOX>(L, B, v);
+  if (key != L.acc_v) {
+    commit_acc<R, BOX>(L, G, B, C);
+    L.acc_v = key;
     L.acc = dep;
   } else {
     L.acc += dep;
@@ -445,10 +478,11 @@ __device__ __forceinline__ void trace_out(TraceRec *rec, int n, int max_rec, int
 // ---------------------------------------------------------------------------
 // one condensed-history step
 // ---------------------------------------------------------------------------
-template <typename R, bool TRACE>
+template <typename R, bool TRACE, bool BOX = false>
 __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &T,
                                      const typename M<R>::R2 *lut, uint32_t k0, uint32_t k1,
-                                     uint32_t flags, LaneCounters &C, TraceRec *rec, int max_rec) {
+                                     uint32_t flags, LaneCounters &C, TraceRec *rec, int max_rec,
+                                     const BoxLane &B = BoxLane{}) {
   using MM = M<R>;
   const R LN2 = (R)0.69314718055994530942;
   // 1. material
@@ -602,7 +636,7 @@ __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &
       C.nuc_ev += 1;
       L.fate = kNuclear;
     }
-    add_tally(L, G, v_step, dep, C);
+    add_tally<R, BOX>(L, G, B, v_step, dep, C);
   }
   C.steps += 1;
   L.nsteps += 1;

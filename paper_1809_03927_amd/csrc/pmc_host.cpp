@@ -41,6 +41,12 @@ struct DevBuf {
   size_t cap = 0;
 };
 
+// Events recorded, per stream, after the latest enqueued work that reads a
+// resource; freeing or rewriting the resource waits for them only.
+struct UseEvents {
+  std::vector<std::pair<hipStream_t, hipEvent_t>> ev;
+};
+
 struct PhaseRec {
   int32_t nx = 0, ny = 0, nz = 0;
   double sp_mm[3] = {0, 0, 0}, org_mm[3] = {0, 0, 0};
@@ -52,6 +58,9 @@ struct PhaseRec {
   uint8_t *d_mask = nullptr;
   void *d_lut32 = nullptr, *d_lut64 = nullptr;
   size_t bytes = 0;
+  UseEvents uses;
+  std::vector<int16_t> hu_host;     // host copies for geometry queries (influence boxes)
+  std::vector<uint8_t> mask_host;
   long long nvox() const { return (long long)nx * ny * nz; }
 };
 
@@ -86,12 +95,14 @@ struct Prepared {
   size_t bytes = 0;                    // size of the request data
   DevBuf buf;                          // device copy of the request data
   uint64_t last_use = 0;
+  UseEvents uses;
 };
 
 }  // namespace
 
 struct pmc_graph {
   pmc_context *ctx = nullptr;
+  std::vector<int32_t> phases;  // phases the graph's kernels read
   void *data = nullptr;  // private copy of the request data + work-queue cursor
   size_t bytes = 0;
   hipGraph_t graph = nullptr;
@@ -129,6 +140,13 @@ struct pmc_context {
   hipEvent_t cursor_done[kCursorSlots] = {};
   int next_cursor = 0;
   DevBuf counters;   // internal counter block
+  // influence calculations: box tallies of a batch of spots, bookkeeping,
+  // and the result (CSR rows, one per plan spot)
+  DevBuf box_scratch, inf_work;
+  DevBuf inf_rows, inf_voxel, inf_value;
+  size_t inf_cap = 0;        // capacity of inf_voxel / inf_value, entries
+  int64_t inf_n_rows = -1;   // -1: no result
+  uint64_t inf_nnz = 0;
 };
 
 namespace {
@@ -200,7 +218,31 @@ void release(pmc_context *ctx, DevBuf &b) {
   b.cap = 0;
 }
 
+int note_use(pmc_context *ctx, UseEvents &u, hipStream_t st) {
+  for (auto &p : u.ev)
+    if (p.first == st) {
+      HIP_TRY(ctx, hipEventRecord(p.second, st), "hipEventRecord");
+      return PMC_OK;
+    }
+  hipEvent_t e = nullptr;
+  HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+  u.ev.emplace_back(st, e);
+  HIP_TRY(ctx, hipEventRecord(e, st), "hipEventRecord");
+  return PMC_OK;
+}
+
+void wait_use(UseEvents &u) {
+  for (auto &p : u.ev) (void)hipEventSynchronize(p.second);
+}
+
+void drop_use(UseEvents &u) {
+  for (auto &p : u.ev) (void)hipEventDestroy(p.second);
+  u.ev.clear();
+}
+
 void free_phase(pmc_context *ctx, PhaseRec &p) {
+  wait_use(p.uses);
+  drop_use(p.uses);
   if (p.d_hu) (void)hipFree(p.d_hu);
   if (p.d_mask) (void)hipFree(p.d_mask);
   if (p.d_lut32) (void)hipFree(p.d_lut32);
@@ -353,7 +395,8 @@ void evict_lru(pmc_context *ctx) {
   size_t lru = 0;
   for (size_t i = 1; i < ctx->cache.size(); ++i)
     if (ctx->cache[i]->last_use < ctx->cache[lru]->last_use) lru = i;
-  wait_pending(ctx);
+  wait_use(ctx->cache[lru]->uses);
+  drop_use(ctx->cache[lru]->uses);
   release(ctx, ctx->cache[lru]->buf);
   ctx->cache.erase(ctx->cache.begin() + (long)lru);
 }
@@ -487,10 +530,18 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
 // data laid out by prepare() (the context's scratch, or a graph's own copy);
 // `cursor` is the work-queue cursor.  With upload_targets false the target
 // table at base + off_targets must already hold this call's tally pointers.
+// Box tallies of an influence calculation (see pmc_influence).
+struct BoxArgs {
+  const pmc::BoxDev *boxes;
+  unsigned long long *tally;
+  long long bias;
+};
+
 template <typename R>
 int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipStream_t st,
                      unsigned long long *const *tally, unsigned long long *counters,
-                     unsigned char *base, unsigned long long *cursor, bool upload_targets) {
+                     unsigned char *base, unsigned long long *cursor, bool upload_targets,
+                     const BoxArgs *box = nullptr) {
   auto scratch_at = [&](size_t off) { return base + off; };
   const bool fp64 = sizeof(R) == 8;
   const uint32_t k0 = (uint32_t)(ctx->seed & 0xffffffffu), k1 = req->request_id;
@@ -529,7 +580,7 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
       const bool same = P.targets.size() == tg.size() &&
                         std::memcmp(P.targets.data(), tg.data(), sizeof(TargetDev) * tg.size()) == 0;
       if (!same) {
-        wait_pending(ctx);
+        wait_use(P.uses);  // earlier launches of this request read the table
         P.targets = tg;
         HIP_TRY(ctx, hipMemcpy(scratch_at(P.off_targets), P.targets.data(),
                                sizeof(TargetDev) * P.targets.size(), hipMemcpyHostToDevice),
@@ -558,6 +609,11 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     a.lut_lds = !fp64 && P.same_lut;
     a.cursor = cursor;
     a.counters = counters;
+    if (box) {
+      a.boxes = box->boxes;
+      a.box_tally = box->tally;
+      a.box_bias = box->bias;
+    }
     unsigned grid = (unsigned)req->grid_blocks;
     if (grid == 0) {
       int per_cu = pmc::persistent_blocks_per_cu(a, fp64);
@@ -567,6 +623,21 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     a.grid = grid;
     HIP_TRY(ctx, pmc::launch_persistent(a, fp64, st), "transport_persistent launch");
   }
+  return PMC_OK;
+}
+
+// One of the context's work-queue cursors for a launch on st: the launch
+// that used it before must have finished (a device-side wait on st).  Record
+// *done on st after the launch.
+int take_cursor(pmc_context *ctx, hipStream_t st, unsigned long long **cursor, hipEvent_t **done) {
+  int rc = ensure(ctx, ctx->cursor, 256 * kCursorSlots, "work-queue cursors");
+  if (rc) return rc;
+  const int slot = ctx->next_cursor;
+  ctx->next_cursor = (slot + 1) % kCursorSlots;
+  *done = &ctx->cursor_done[slot];
+  if (**done) HIP_TRY(ctx, hipStreamWaitEvent(st, **done, 0), "wait for cursor");
+  else HIP_TRY(ctx, hipEventCreateWithFlags(*done, hipEventDisableTiming), "hipEventCreate");
+  *cursor = reinterpret_cast<unsigned long long *>(static_cast<unsigned char *>(ctx->cursor.p) + 256 * slot);
   return PMC_OK;
 }
 
@@ -582,19 +653,16 @@ int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
   unsigned long long *cursor = nullptr;
   hipEvent_t *cursor_done = nullptr;
   if (req->engine == PMC_ENGINE_PERSISTENT) {
-    rc = ensure(ctx, ctx->cursor, 256 * kCursorSlots, "work-queue cursors");
+    rc = take_cursor(ctx, st, &cursor, &cursor_done);
     if (rc) return rc;
-    const int slot = ctx->next_cursor;
-    ctx->next_cursor = (slot + 1) % kCursorSlots;
-    cursor_done = &ctx->cursor_done[slot];
-    if (*cursor_done) HIP_TRY(ctx, hipStreamWaitEvent(st, *cursor_done, 0), "wait for cursor");
-    else HIP_TRY(ctx, hipEventCreateWithFlags(cursor_done, hipEventDisableTiming), "hipEventCreate");
-    cursor = reinterpret_cast<unsigned long long *>(static_cast<unsigned char *>(ctx->cursor.p) + 256 * slot);
   }
   rc = enqueue_prepared<R>(ctx, *P, req, st, tally, counters, static_cast<unsigned char *>(P->buf.p),
                            cursor, true);
   if (rc) return rc;
   if (cursor_done) HIP_TRY(ctx, hipEventRecord(*cursor_done, st), "hipEventRecord");
+  rc = note_use(ctx, P->uses, st);
+  for (int32_t i = 0; i < req->n_phases && !rc; ++i) rc = note_use(ctx, ctx->phases[req->phases[i]].uses, st);
+  if (rc) return rc;
   return note_pending(ctx, st);
 }
 
@@ -725,10 +793,18 @@ void pmc_destroy(pmc_context *ctx) {
     (void)hipSetDevice(ctx->device);
     wait_pending(ctx);
     for (auto &kv : ctx->phases) free_phase(ctx, kv.second);
-    for (auto &e : ctx->cache) release(ctx, e->buf);
+    for (auto &e : ctx->cache) {
+      drop_use(e->uses);
+      release(ctx, e->buf);
+    }
     ctx->cache.clear();
     release(ctx, ctx->cursor);
     release(ctx, ctx->counters);
+    release(ctx, ctx->box_scratch);
+    release(ctx, ctx->inf_work);
+    release(ctx, ctx->inf_rows);
+    release(ctx, ctx->inf_voxel);
+    release(ctx, ctx->inf_value);
     for (hipEvent_t ev : ctx->cursor_done)
       if (ev) (void)hipEventDestroy(ev);
     for (auto &kv : ctx->stream_done) (void)hipEventDestroy(kv.second);
@@ -787,6 +863,8 @@ int pmc_load_phase(pmc_context *ctx, int32_t phase, const int16_t *hu, int32_t n
     rec.lut32[2 * i + 1] = (float)rsp;
   }
   rec.has_mask = external_mask != nullptr;
+  rec.hu_host.assign(hu, hu + nvox);
+  if (rec.has_mask) rec.mask_host.assign(external_mask, external_mask + nvox);
   rec.version = ++ctx->phase_counter;
   if (!ctx->has_device) {
     auto it = ctx->phases.find(phase);
@@ -800,7 +878,6 @@ int pmc_load_phase(pmc_context *ctx, int32_t phase, const int16_t *hu, int32_t n
   if (ctx->used - old + bytes > ctx->budget)
     return fail(ctx, PMC_E_BUDGET, "phase %d needs %zu bytes: over the device-memory budget", phase, bytes);
   HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-  wait_pending(ctx);
   auto cleanup = [&](hipError_t e, const char *what) {
     free_phase(ctx, rec);
     return hip_fail(ctx, e, what);
@@ -846,8 +923,7 @@ int pmc_unload_phase(pmc_context *ctx, int32_t phase) {
   if (it == ctx->phases.end()) return fail(ctx, PMC_E_NOPHASE, "phase %d is not loaded", phase);
   if (ctx->has_device) {
     (void)hipSetDevice(ctx->device);
-    wait_pending(ctx);
-    free_phase(ctx, it->second);
+    free_phase(ctx, it->second);  // waits for the work that reads it
   }
   ctx->phases.erase(it);
   return PMC_OK;
@@ -904,7 +980,8 @@ int pmc_unload_plan(pmc_context *ctx, int32_t plan) {
   // drop the plan's prepared data
   for (size_t i = 0; i < ctx->cache.size();) {
     if (ctx->cache[i]->plan_id == plan) {
-      wait_pending(ctx);
+      wait_use(ctx->cache[i]->uses);
+      drop_use(ctx->cache[i]->uses);
       release(ctx, ctx->cache[i]->buf);
       ctx->cache.erase(ctx->cache.begin() + (long)i);
     } else {
@@ -984,6 +1061,8 @@ int pmc_convert_device(pmc_context *ctx, int32_t phase, const int64_t *dev_tally
                                    ph.nvox(), vol, (double)n_histories, dev_dose, dev_density,
                                    (hipStream_t)stream),
           "convert launch");
+  const int rc = note_use(ctx, it->second.uses, (hipStream_t)stream);
+  if (rc) return rc;
   return note_pending(ctx, (hipStream_t)stream);
 }
 
@@ -1173,6 +1252,7 @@ int pmc_graph_create(pmc_context *ctx, const pmc_request *req, int64_t *const *d
     return fail(ctx, PMC_E_BUDGET, "graph data needs %zu bytes: over the device-memory budget", bytes);
   pmc_graph *g = new pmc_graph();
   g->ctx = ctx;
+  g->phases.assign(req->phases, req->phases + req->n_phases);
   g->bytes = bytes;
   auto bail = [&](hipError_t e, const char *what) {
     const int code = hip_fail(ctx, e, what);
@@ -1238,6 +1318,12 @@ int pmc_graph_launch(pmc_graph *g, void *stream) {
   pmc_context *ctx = g->ctx;
   ctx->err.clear();
   HIP_TRY(ctx, hipGraphLaunch(g->exec, (hipStream_t)stream), "hipGraphLaunch");
+  for (int32_t ph : g->phases) {
+    auto it = ctx->phases.find(ph);
+    if (it == ctx->phases.end()) continue;
+    const int rc = note_use(ctx, it->second.uses, (hipStream_t)stream);
+    if (rc) return rc;
+  }
   return note_pending(ctx, (hipStream_t)stream);
 }
 
@@ -1252,6 +1338,421 @@ void pmc_graph_destroy(pmc_graph *g) {
     g->ctx->used -= g->bytes;
   }
   delete g;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// influence matrix
+// ---------------------------------------------------------------------------
+namespace {
+
+// Restricted CSDA range in water (g/cm^2) at E, from the transport tables.
+double table_range(const pmc::Tables &T, double E) {
+  double x = (std::log2(E) - T.l2e0) / T.dl2;
+  int i = (int)x;
+  i = i < 0 ? 0 : (i > pmc::kTableNodes - 2 ? pmc::kTableNodes - 2 : i);
+  const double f = x - i;
+  return T.range[i] + f * (T.range[i + 1] - T.range[i]);
+}
+
+double rsp_at(const PhaseRec &ph, long long v) {
+  if (ph.has_mask && ph.mask_host[(size_t)v] == 0) return 0.0;
+  int h = ph.hu_host[(size_t)v];
+  h = h < kHuLo ? kHuLo : (h > kHuHi ? kHuHi : h);
+  return ph.lut64[2 * (h - kHuLo) + 1];
+}
+
+// Voxel box of a spot: the spot's central axis from where it enters the grid
+// to water-equivalent depth R(E) + 3 cm (or the grid exit), widened by
+// 3 sigma_max across the beam, sigma_max^2 = sigma_spot^2 + (0.035 L)^2 with
+// L the geometric length of that axis segment.
+pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s) {
+  pmc_box b = {{0, 0, 0}, {0, 0, 0}};
+  double w[3], u[3], v[3], c[3], d[3], ext[3];
+  const int n[3] = {ph.nx, ph.ny, ph.nz};
+  const double nw = norm3(f.direction), nu = norm3(f.bev_u);
+  for (int k = 0; k < 3; ++k) {
+    w[k] = f.direction[k] / nw;
+    u[k] = f.bev_u[k] / nu;
+  }
+  v[0] = w[1] * u[2] - w[2] * u[1];
+  v[1] = w[2] * u[0] - w[0] * u[2];
+  v[2] = w[0] * u[1] - w[1] * u[0];
+  for (int k = 0; k < 3; ++k) {
+    c[k] = 0.1 * (f.isocentre_mm[k] - ph.org_mm[k]) + 0.1 * s.x_mm * u[k] + 0.1 * s.y_mm * v[k];
+    d[k] = 0.1 * ph.sp_mm[k];
+    ext[k] = n[k] * d[k];
+  }
+  double t_in = -HUGE_VAL, t_out = HUGE_VAL;
+  for (int k = 0; k < 3; ++k) {
+    if (w[k] != 0.0) {
+      const double t1 = (0.0 - c[k]) / w[k], t2 = (ext[k] - c[k]) / w[k];
+      t_in = std::max(t_in, std::min(t1, t2));
+      t_out = std::min(t_out, std::max(t1, t2));
+    } else if (c[k] < 0.0 || c[k] >= ext[k]) {
+      return b;
+    }
+  }
+  if (!(t_in < t_out)) return b;
+  // march the axis through the voxels, accumulating water-equivalent depth
+  const double target = table_range(ctx->tabs, s.energy_MeV) + 3.0;
+  int idx[3];
+  double t_max[3], t_step[3];
+  const double tm = 0.5 * (t_in + std::min(t_out, t_in + 1e-6));
+  for (int k = 0; k < 3; ++k) {
+    const double p = c[k] + tm * w[k];
+    idx[k] = std::min(n[k] - 1, std::max(0, (int)std::floor(p / d[k])));
+    if (w[k] > 0.0) { t_max[k] = ((idx[k] + 1) * d[k] - c[k]) / w[k]; t_step[k] = d[k] / w[k]; }
+    else if (w[k] < 0.0) { t_max[k] = (idx[k] * d[k] - c[k]) / w[k]; t_step[k] = -d[k] / w[k]; }
+    else { t_max[k] = HUGE_VAL; t_step[k] = HUGE_VAL; }
+  }
+  double t = t_in, wet = 0.0, t_end = t_out;
+  for (;;) {
+    int ax = 0;
+    if (t_max[1] < t_max[ax]) ax = 1;
+    if (t_max[2] < t_max[ax]) ax = 2;
+    const double t_next = std::min(t_max[ax], t_out);
+    const long long vx = (long long)idx[0] + (long long)n[0] * ((long long)idx[1] + (long long)n[1] * idx[2]);
+    const double r = rsp_at(ph, vx);
+    const double seg = std::max(0.0, t_next - t);
+    if (r > 0.0 && wet + r * seg >= target) {
+      t_end = t + (target - wet) / r;
+      break;
+    }
+    wet += r * seg;
+    t = t_next;
+    if (t >= t_out) break;
+    idx[ax] += w[ax] > 0.0 ? 1 : -1;
+    if (idx[ax] < 0 || idx[ax] >= n[ax]) break;
+    t_max[ax] += t_step[ax];
+  }
+  const double L = t_end - t_in;
+  const double sig = 0.1 * s.sigma_mm;
+  const double r = 3.0 * std::sqrt(sig * sig + (0.035 * L) * (0.035 * L));
+  for (int k = 0; k < 3; ++k) {
+    const double a = c[k] + t_in * w[k], e = c[k] + t_end * w[k];
+    const double half = r * (std::fabs(u[k]) + std::fabs(v[k]));
+    const double lo = std::min(a, e) - half, hi = std::max(a, e) + half;
+    long long il = (long long)std::floor(lo / d[k]), ih = (long long)std::floor(hi / d[k]) + 1;
+    il = std::max(0LL, std::min((long long)n[k], il));
+    ih = std::max(0LL, std::min((long long)n[k], ih));
+    b.lo[k] = (int32_t)il;
+    b.hi[k] = (int32_t)ih;
+  }
+  for (int k = 0; k < 3; ++k)
+    if (b.hi[k] <= b.lo[k]) return pmc_box{{0, 0, 0}, {0, 0, 0}};
+  return b;
+}
+
+long long box_entries(const pmc_box &b) {
+  long long e = 1;
+  for (int k = 0; k < 3; ++k) e *= (long long)(b.hi[k] - b.lo[k]);
+  return e;
+}
+
+int grow_csr(pmc_context *ctx, size_t need, hipStream_t st) {
+  if (need <= ctx->inf_cap) return PMC_OK;
+  const size_t cap = std::max(need, ctx->inf_cap + ctx->inf_cap / 2);
+  const size_t add = (cap - ctx->inf_cap) * (sizeof(int32_t) + sizeof(float));
+  if (ctx->used + add > ctx->budget)
+    return fail(ctx, PMC_E_BUDGET, "influence matrix: %zu entries exceed the device-memory budget", cap);
+  void *nv = nullptr, *nf = nullptr;
+  HIP_TRY(ctx, hipMalloc(&nv, cap * sizeof(int32_t)), "hipMalloc influence voxels");
+  if (hipMalloc(&nf, cap * sizeof(float)) != hipSuccess) {
+    (void)hipFree(nv);
+    return fail(ctx, PMC_E_DEVICE, "hipMalloc influence values");
+  }
+  if (ctx->inf_nnz) {
+    HIP_TRY(ctx, hipMemcpyAsync(nv, ctx->inf_voxel.p, ctx->inf_nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, st),
+            "copy influence voxels");
+    HIP_TRY(ctx, hipMemcpyAsync(nf, ctx->inf_value.p, ctx->inf_nnz * sizeof(float), hipMemcpyDeviceToDevice, st),
+            "copy influence values");
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(st), "influence copy");
+  release(ctx, ctx->inf_voxel);
+  release(ctx, ctx->inf_value);
+  ctx->inf_voxel.p = nv;
+  ctx->inf_voxel.cap = cap * sizeof(int32_t);
+  ctx->inf_value.p = nf;
+  ctx->inf_value.cap = cap * sizeof(float);
+  ctx->used += cap * (sizeof(int32_t) + sizeof(float));
+  ctx->inf_cap = cap;
+  return PMC_OK;
+}
+
+void free_influence(pmc_context *ctx) {
+  release(ctx, ctx->box_scratch);
+  release(ctx, ctx->inf_work);
+  release(ctx, ctx->inf_rows);
+  release(ctx, ctx->inf_voxel);
+  release(ctx, ctx->inf_value);
+  ctx->inf_cap = 0;
+  ctx->inf_nnz = 0;
+  ctx->inf_n_rows = -1;
+}
+
+template <typename R>
+int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_in, double thr,
+              uint64_t max_scratch, uint64_t *nnz_out, pmc_balance *bal_out, uint64_t outside_out[2]) {
+  pmc_request rq = *req_in;
+  rq.engine = PMC_ENGINE_PERSISTENT;
+  const PlanRec &plan = ctx->plans[rq.plan];
+  const int64_t n_spots = (int64_t)plan.spots.size();
+  const int32_t phase_id = rq.phases[0];
+  const PhaseRec &ph = ctx->phases[phase_id];
+  // boxes
+  std::vector<pmc_box> bx((size_t)n_spots);
+  for (int64_t s = 0; s < n_spots; ++s) {
+    if (boxes_in) {
+      bx[s] = boxes_in[s];
+      const int n[3] = {ph.nx, ph.ny, ph.nz};
+      for (int k = 0; k < 3; ++k)
+        if (bx[s].lo[k] < 0 || bx[s].hi[k] > n[k] || bx[s].lo[k] > bx[s].hi[k])
+          return fail(ctx, PMC_E_INVAL, "box of spot %lld is not inside the grid", (long long)s);
+    } else if (plan.spots[s].phase == phase_id) {
+      bx[s] = spot_box(ctx, ph, plan.fields[plan.spots[s].field], plan.spots[s]);
+    } else {
+      bx[s] = pmc_box{{0, 0, 0}, {0, 0, 0}};
+    }
+  }
+  Prepared *P = nullptr;
+  int rc = prepare<R>(ctx, &rq, &P);
+  if (rc) return rc;
+  const int64_t chunk = P->chunk;
+  // device boxes, tile layout and the work-item range of every spot
+  std::vector<pmc::BoxDev> bd((size_t)n_spots);
+  std::vector<long long> offset((size_t)n_spots + 1, 0), item_first((size_t)n_spots + 1, 0);
+  long long largest = 0;
+  for (int64_t s = 0; s < n_spots; ++s) {
+    pmc::BoxDev &d = bd[s];
+    const int64_t h = P->per_spot[s];
+    const long long ne = h > 0 ? box_entries(bx[s]) : 0;
+    for (int k = 0; k < 3; ++k) {
+      d.lo[k] = bx[s].lo[k];
+      d.n[k] = ne > 0 ? bx[s].hi[k] - bx[s].lo[k] : 0;
+    }
+    d.offset = offset[s];
+    d.n_hist = (double)h;
+    d.pad = 0.0;
+    const long long padded = (ne + pmc::kTile - 1) / pmc::kTile * pmc::kTile;
+    largest = std::max(largest, padded);
+    offset[s + 1] = offset[s] + padded;
+    item_first[s + 1] = item_first[s] + (h + chunk - 1) / chunk;
+  }
+  // batches of consecutive spots whose boxes fit the scratch
+  const size_t free_b = ctx->budget > ctx->used ? ctx->budget - ctx->used : 0;
+  const size_t scratch_b = max_scratch ? std::min<size_t>(max_scratch, free_b) : free_b / 2;
+  if ((size_t)largest * sizeof(long long) > scratch_b)
+    return fail(ctx, PMC_E_BUDGET, "a spot box of %lld voxels exceeds the scratch allowed (%zu bytes)",
+                largest, scratch_b);
+  const long long cap = (long long)(scratch_b / sizeof(long long));
+  std::vector<int64_t> cuts = {0};
+  for (int64_t s = 0; s < n_spots; ++s)
+    if (offset[s + 1] - offset[cuts.back()] > cap) cuts.push_back(s);
+  cuts.push_back(n_spots);
+  long long max_entries = 0, max_spots = 0;
+  for (size_t b = 0; b + 1 < cuts.size(); ++b) {
+    max_entries = std::max(max_entries, offset[cuts[b + 1]] - offset[cuts[b]]);
+    max_spots = std::max<long long>(max_spots, cuts[b + 1] - cuts[b]);
+  }
+  const long long max_tiles = max_entries / pmc::kTile, max_chunks = (max_tiles + 1023) / 1024;
+  // work buffer layout
+  size_t off = 0;
+  const size_t o_boxes = off; off = align256(off + sizeof(pmc::BoxDev) * (size_t)n_spots);
+  const size_t o_tfirst = off; off = align256(off + sizeof(long long) * (size_t)(max_spots + 1));
+  const size_t o_max = off; off = align256(off + sizeof(long long) * (size_t)max_spots);
+  const size_t o_dep = off; off = align256(off + 2 * sizeof(long long));
+  const size_t o_count = off; off = align256(off + sizeof(uint32_t) * (size_t)max_tiles);
+  const size_t o_toff = off; off = align256(off + sizeof(long long) * (size_t)max_tiles);
+  const size_t o_coff = off; off = align256(off + sizeof(long long) * (size_t)(max_chunks + 1));
+  ctx->inf_n_rows = -1;
+  ctx->inf_nnz = 0;
+  rc = ensure(ctx, ctx->inf_work, std::max<size_t>(off, 256), "influence work buffer");
+  if (rc) return rc;
+  rc = ensure(ctx, ctx->box_scratch, std::max<size_t>((size_t)max_entries * sizeof(long long), 256),
+              "influence box tallies");
+  if (rc) return rc;
+  rc = ensure(ctx, ctx->inf_rows, sizeof(int64_t) * (size_t)(n_spots + 1), "influence rows");
+  if (rc) return rc;
+  rc = ensure(ctx, ctx->counters, sizeof(uint64_t) * PMC_COUNTERS, "counters");
+  if (rc) return rc;
+  unsigned char *work = static_cast<unsigned char *>(ctx->inf_work.p);
+  auto *d_boxes = reinterpret_cast<pmc::BoxDev *>(work + o_boxes);
+  auto *d_tfirst = reinterpret_cast<long long *>(work + o_tfirst);
+  auto *d_max = reinterpret_cast<unsigned long long *>(work + o_max);
+  auto *d_dep = reinterpret_cast<unsigned long long *>(work + o_dep);
+  auto *scratch = static_cast<unsigned long long *>(ctx->box_scratch.p);
+  auto *counters = static_cast<unsigned long long *>(ctx->counters.p);
+  hipStream_t st = ctx->stream;
+  HIP_TRY(ctx, hipMemcpy(d_boxes, bd.data(), sizeof(pmc::BoxDev) * bd.size(), hipMemcpyHostToDevice),
+          "upload boxes");
+  HIP_TRY(ctx, pmc::launch_fill_u64(counters, PMC_COUNTERS, 0ull, st), "counter reset");
+  unsigned __int128 deposited = 0;
+  uint64_t nnz = 0;
+  std::vector<long long> tfirst((size_t)max_spots + 1);
+  unsigned long long *no_tally[1] = {nullptr};
+  for (size_t b = 0; b + 1 < cuts.size(); ++b) {
+    const int64_t s0 = cuts[b], s1 = cuts[b + 1];
+    const long long base = offset[s0], entries = offset[s1] - base;
+    const long long n_tiles = entries / pmc::kTile;
+    HIP_TRY(ctx, pmc::launch_fill_u64(scratch, entries, 0ull, st), "zero box tallies");
+    HIP_TRY(ctx, pmc::launch_fill_u64(d_max, s1 - s0, 0ull, st), "zero maxima");
+    HIP_TRY(ctx, pmc::launch_fill_u64(d_dep, 2, 0ull, st), "zero sums");
+    if (item_first[s1] > item_first[s0]) {
+      pmc_request br = rq;
+      br.item_begin = (uint64_t)item_first[s0];
+      br.item_end = (uint64_t)item_first[s1];
+      unsigned long long *cursor = nullptr;
+      hipEvent_t *cursor_done = nullptr;
+      rc = take_cursor(ctx, st, &cursor, &cursor_done);
+      if (rc) return rc;
+      const BoxArgs ba = {d_boxes, scratch, base};
+      rc = enqueue_prepared<R>(ctx, *P, &br, st, no_tally, counters, static_cast<unsigned char *>(P->buf.p),
+                               cursor, true, &ba);
+      if (rc) return rc;
+      HIP_TRY(ctx, hipEventRecord(*cursor_done, st), "hipEventRecord");
+    }
+    for (int64_t s = s0; s <= s1; ++s) tfirst[s - s0] = (offset[s] - base) / pmc::kTile;
+    HIP_TRY(ctx, hipMemcpyAsync(d_tfirst, tfirst.data(), sizeof(long long) * (size_t)(s1 - s0 + 1),
+                                hipMemcpyHostToDevice, st), "upload tile offsets");
+    pmc::InfluenceLaunch L;
+    L.box_tally = reinterpret_cast<const long long *>(scratch);
+    L.boxes = d_boxes + s0;
+    L.tile_first = d_tfirst;
+    L.n_spots = (int32_t)(s1 - s0);
+    L.n_tiles = n_tiles;
+    L.box_bias = base;
+    L.hu = ph.d_hu;
+    L.mask = ph.d_mask;
+    L.lut64 = ph.d_lut64;
+    L.nx = ph.nx;
+    L.ny = ph.ny;
+    L.vol_cm3 = (0.1 * ph.sp_mm[0]) * (0.1 * ph.sp_mm[1]) * (0.1 * ph.sp_mm[2]);
+    L.rel_threshold = thr;
+    L.spot_max = d_max;
+    L.dep_sum = d_dep;
+    L.tile_count = reinterpret_cast<uint32_t *>(work + o_count);
+    L.tile_off = reinterpret_cast<unsigned long long *>(work + o_toff);
+    L.chunk_off = reinterpret_cast<unsigned long long *>(work + o_coff);
+    L.nnz_base = (long long)nnz;
+    L.row_ptr = static_cast<int64_t *>(ctx->inf_rows.p) + s0;
+    L.voxel = nullptr;
+    L.value = nullptr;
+    HIP_TRY(ctx, pmc::launch_influence_reduce(L, st), "influence reduction");
+    const long long n_chunks = (n_tiles + 1023) / 1024;
+    uint64_t hostv[3] = {0, 0, 0};
+    HIP_TRY(ctx, hipMemcpyAsync(hostv, L.chunk_off + n_chunks, sizeof(uint64_t), hipMemcpyDeviceToHost, st),
+            "read batch size");
+    HIP_TRY(ctx, hipMemcpyAsync(hostv + 1, d_dep, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, st),
+            "read batch sum");
+    HIP_TRY(ctx, hipStreamSynchronize(st), "influence batch");
+    deposited += ((unsigned __int128)hostv[2] << 64) | hostv[1];
+    rc = grow_csr(ctx, (size_t)(nnz + hostv[0]), st);
+    if (rc) return rc;
+    L.voxel = static_cast<int32_t *>(ctx->inf_voxel.p);
+    L.value = static_cast<float *>(ctx->inf_value.p);
+    HIP_TRY(ctx, pmc::launch_influence_write(L, st), "influence write");
+    nnz += hostv[0];
+    ctx->inf_nnz = nnz;
+  }
+  const int64_t last = (int64_t)nnz;
+  HIP_TRY(ctx, hipMemcpyAsync(static_cast<int64_t *>(ctx->inf_rows.p) + n_spots, &last, sizeof last,
+                              hipMemcpyHostToDevice, st), "row end");
+  uint64_t c[PMC_COUNTERS];
+  HIP_TRY(ctx, hipMemcpyAsync(c, counters, sizeof c, hipMemcpyDeviceToHost, st), "read counters");
+  HIP_TRY(ctx, hipStreamSynchronize(st), "influence");
+  rc = note_use(ctx, P->uses, st);
+  if (rc) return rc;
+  ctx->inf_n_rows = n_spots;
+  ctx->inf_nnz = nnz;
+  *nnz_out = nnz;
+  if (bal_out) fill_balance(P->incident, c, deposited, bal_out);
+  if (outside_out) {
+    outside_out[0] = c[13];
+    outside_out[1] = c[14];
+  }
+  return PMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmc_influence_boxes(pmc_context *ctx, int32_t plan, int32_t phase, pmc_box *out, int64_t n_spots) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  auto pit = ctx->plans.find(plan);
+  if (pit == ctx->plans.end()) return fail(ctx, PMC_E_STATE, "plan %d is not loaded", plan);
+  auto hit = ctx->phases.find(phase);
+  if (hit == ctx->phases.end()) return fail(ctx, PMC_E_NOPHASE, "phase %d is not loaded", phase);
+  if (!out || n_spots != (int64_t)pit->second.spots.size())
+    return fail(ctx, PMC_E_INVAL, "need an output array of the plan's %zu spots", pit->second.spots.size());
+  const PlanRec &P = pit->second;
+  for (int64_t s = 0; s < n_spots; ++s)
+    out[s] = P.spots[s].phase == phase ? spot_box(ctx, hit->second, P.fields[P.spots[s].field], P.spots[s])
+                                       : pmc_box{{0, 0, 0}, {0, 0, 0}};
+  return PMC_OK;
+}
+
+int pmc_influence(pmc_context *ctx, const pmc_request *req, const pmc_box *boxes, double rel_threshold,
+                  uint64_t max_scratch_bytes, uint64_t *nnz, pmc_balance *balance, uint64_t outside[2]) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  int rc = validate_request(ctx, req);
+  if (rc) return rc;
+  if (!nnz) return fail(ctx, PMC_E_INVAL, "nnz is NULL");
+  if (req->n_phases != 1) return fail(ctx, PMC_E_INVAL, "an influence request has exactly one phase");
+  if (req->item_begin || req->item_end) return fail(ctx, PMC_E_INVAL, "an influence request is not sliced");
+  if (!(rel_threshold >= 0.0 && rel_threshold <= 1.0))
+    return fail(ctx, PMC_E_INVAL, "rel_threshold must be in [0, 1]");
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  rc = ctx->precision == PMC_FP64
+           ? influence<double>(ctx, req, boxes, rel_threshold, max_scratch_bytes, nnz, balance, outside)
+           : influence<float>(ctx, req, boxes, rel_threshold, max_scratch_bytes, nnz, balance, outside);
+  if (rc) {
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->inf_n_rows = -1;
+  }
+  return rc;
+}
+
+int pmc_influence_read(pmc_context *ctx, int64_t *row_ptr, int32_t *voxel, float *value) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (ctx->inf_n_rows < 0) return fail(ctx, PMC_E_STATE, "no influence matrix has been computed");
+  if (row_ptr)
+    HIP_TRY(ctx, hipMemcpy(row_ptr, ctx->inf_rows.p, sizeof(int64_t) * (size_t)(ctx->inf_n_rows + 1),
+                           hipMemcpyDeviceToHost), "copy rows");
+  if (voxel && ctx->inf_nnz)
+    HIP_TRY(ctx, hipMemcpy(voxel, ctx->inf_voxel.p, sizeof(int32_t) * ctx->inf_nnz, hipMemcpyDeviceToHost),
+            "copy voxels");
+  if (value && ctx->inf_nnz)
+    HIP_TRY(ctx, hipMemcpy(value, ctx->inf_value.p, sizeof(float) * ctx->inf_nnz, hipMemcpyDeviceToHost),
+            "copy values");
+  return PMC_OK;
+}
+
+int pmc_influence_device(pmc_context *ctx, const int64_t **row_ptr, const int32_t **voxel, const float **value) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (ctx->inf_n_rows < 0) return fail(ctx, PMC_E_STATE, "no influence matrix has been computed");
+  if (row_ptr) *row_ptr = static_cast<const int64_t *>(ctx->inf_rows.p);
+  if (voxel) *voxel = static_cast<const int32_t *>(ctx->inf_voxel.p);
+  if (value) *value = static_cast<const float *>(ctx->inf_value.p);
+  return PMC_OK;
+}
+
+int pmc_influence_free(pmc_context *ctx) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (ctx->has_device) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+  }
+  free_influence(ctx);
+  return PMC_OK;
 }
 
 }  // extern "C"

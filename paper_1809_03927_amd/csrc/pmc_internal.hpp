@@ -41,6 +41,20 @@ struct WorkItem {
   uint32_t pad;
 };
 
+// Voxel box of one spot in an influence calculation: box-local entry
+// (x, y, z) -> offset + x + n[0] (y + n[1] z) of the box scratch; n = 0 for
+// spots without histories.
+struct BoxDev {
+  int32_t lo[3];
+  int32_t n[3];
+  long long offset;  // first entry, a multiple of kTile
+  double n_hist;     // histories of the spot
+  double pad;
+};
+static_assert(sizeof(BoxDev) == 48, "BoxDev layout");
+
+constexpr int kTile = 1024;  // box entries per compaction tile (256 threads x 4)
+
 struct TraceRec {  // identical layout to pmc_trace_rec
   int32_t cause, voxel, fate;
   uint32_t block;
@@ -81,7 +95,42 @@ struct PersistentLaunch {
   bool lut_lds;
   unsigned long long *cursor;    // work-queue cursor, zero before the launch
   unsigned long long *counters;
+  // influence calculations (boxes != nullptr): each spot tallies into its
+  // box of `box_tally`, entry offset - box_bias
+  const BoxDev *boxes = nullptr;
+  unsigned long long *box_tally = nullptr;
+  long long box_bias = 0;
 };
+
+// Compaction of the box tallies of spots [0, n_spots) of a batch into CSR
+// rows (voxel, Gy per history), voxels at or above rel_threshold x the
+// spot's maximum of tally / density.
+struct InfluenceLaunch {
+  const long long *box_tally;   // batch scratch (entry 0 = box offset box_bias)
+  const BoxDev *boxes;          // the batch's spots
+  const long long *tile_first;  // n_spots + 1 tile prefix of the batch
+  int32_t n_spots;
+  long long n_tiles;
+  long long box_bias;
+  const int16_t *hu;
+  const uint8_t *mask;
+  const void *lut64;            // double2[4096]
+  int32_t nx, ny;
+  double vol_cm3;
+  double rel_threshold;
+  unsigned long long *spot_max;  // n_spots words (bits of the maximum, >= 0)
+  unsigned long long *dep_sum;   // 2 words: 128-bit sum of the batch's tallies
+  uint32_t *tile_count;          // n_tiles
+  unsigned long long *tile_off;  // n_tiles: exclusive offsets within their chunk of kTile tiles
+  unsigned long long *chunk_off; // n_chunks + 1: exclusive chunk offsets, last = batch total
+  long long nnz_base;            // CSR entries before this batch
+  int64_t *row_ptr;              // CSR row pointers of the batch's spots (n_spots entries)
+  int32_t *voxel;
+  float *value;
+};
+
+hipError_t launch_influence_reduce(const InfluenceLaunch &a, hipStream_t st);  // max, sum, count, scan
+hipError_t launch_influence_write(const InfluenceLaunch &a, hipStream_t st);   // rows and entries
 
 struct TraceLaunch {
   const void *spot;  // host pointer to one SpotDev<R> (passed by value)

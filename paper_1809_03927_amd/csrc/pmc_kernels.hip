@@ -7,6 +7,7 @@
 //  trace_kernel          one history with a record per step (validation)
 //  convert_kernel        int64 tally -> dose (Gy per history) and density
 //  fill_u64_kernel       zero-fill used instead of memset inside captured graphs
+//  influence_*           per-spot box tallies -> thresholded CSR rows
 //
 // All transport kernels run the same `pmc::step`, so for equal inputs they
 // produce bit-identical integer tallies whatever the schedule.
@@ -33,7 +34,7 @@ __device__ __forceinline__ void add128(unsigned long long *p, unsigned long long
 
 // Every thread of the block must call this (it synchronises the block).
 // `red` is LDS of kNc * (waves + 1) words.
-constexpr int kNc = 13;  // 3 energies as (lo32, hi32) sums + 7 event counts
+constexpr int kNc = 15;  // 4 energies as (lo32, hi32) sums + 7 event counts
 
 __device__ void commit_counters(const LaneCounters &C, unsigned long long *counters,
                                 unsigned long long *red) {
@@ -44,6 +45,7 @@ __device__ void commit_counters(const LaneCounters &C, unsigned long long *count
   v[4] = C.cut & 0xffffffffull; v[5] = C.cut >> 32;
   v[6] = C.hist; v[7] = C.steps; v[8] = C.delta; v[9] = C.nuc_ev; v[10] = C.escapes;
   v[11] = C.misses; v[12] = C.atomics;
+  v[13] = C.out & 0xffffffffull; v[14] = C.out >> 32;
 #pragma unroll
   for (int k = 0; k < kNc; ++k) v[k] = wave_sum(v[k]);
   __syncthreads();
@@ -60,13 +62,15 @@ __device__ void commit_counters(const LaneCounters &C, unsigned long long *count
   }
   __syncthreads();
   const int t = threadIdx.x;
-  if (t < 3) {
-    // energy e: value = hi32sum * 2^32 + lo32sum, as a 128-bit (lo, hi) pair
-    const unsigned long long lo32 = tot[2 * t], hi32 = tot[2 * t + 1];
+  if (t < 4) {
+    // energy e: value = hi32sum * 2^32 + lo32sum, as a 128-bit (lo, hi) pair;
+    // escaped, nuclear, cutoff at words 0-5, outside-box at words 13-14
+    const int src = t < 3 ? 2 * t : 13;
+    const unsigned long long lo32 = tot[src], hi32 = tot[src + 1];
     const unsigned long long lo = lo32 + (hi32 << 32);
     const unsigned long long hi = (hi32 >> 32) + (lo < lo32 ? 1ull : 0ull);
-    if (lo | hi) add128(counters + 2 * t, lo, hi);
-  } else if (t >= 6 && t < kNc) {
+    if (lo | hi) add128(counters + src, lo, hi);
+  } else if (t >= 6 && t < 13) {
     if (tot[t]) __hip_atomic_fetch_add(counters + kCHist + (t - 6), tot[t], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -140,14 +144,16 @@ transport_plain(const SpotDev<R> *__restrict__ spots, const int32_t *__restrict_
 // ---------------------------------------------------------------------------
 // persistent engine: work queue + wave-level lane refill
 // ---------------------------------------------------------------------------
-template <typename R, bool LUT_LDS>
+template <typename R, bool LUT_LDS, bool BOX>
 __global__ void __launch_bounds__(kMaxBlock<R>)
 transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict__ items,
                      int32_t n_items, const TargetDev *__restrict__ targets, int32_t n_targets,
                      const typename M<R>::R2 *__restrict__ luts_g,
                      const typename M<R>::R4 *__restrict__ tab_g, R l2e0, R inv_dl2, R dl2,
                      uint32_t k0, uint32_t k1, uint32_t flags, int32_t refill_min,
-                     unsigned long long *cursor, unsigned long long *counters) {
+                     unsigned long long *cursor, unsigned long long *counters,
+                     const BoxDev *__restrict__ boxes, unsigned long long *box_tally,
+                     long long box_bias) {
   extern __shared__ __align__(16) unsigned char smem[];
   using R2 = typename M<R>::R2;
   using R4 = typename M<R>::R4;
@@ -169,6 +175,7 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
   LaneCounters C = {};
   Lane<R> L;
   L.fate = kMissed;  // idle
+  BoxLane B = {};
   int32_t tgt = 0;
   // wave-uniform state of the work item being drained
   int32_t it_spot = 0;
@@ -200,6 +207,15 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
           const SpotDev<R> &sp = spots[it_spot];
           tgt = sp.target;
           start_history(L, sp, it_spot, it_next + rank, geo_s[tgt], k0, k1, C);
+          if constexpr (BOX) {
+            const BoxDev &bx = boxes[it_spot];
+            B.base = box_tally + (bx.offset - box_bias);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              B.lo[k] = bx.lo[k];
+              B.n[k] = bx.n[k];
+            }
+          }
         }
         it_next += take;
         idle = __ballot(me_idle && !mine);
@@ -213,8 +229,8 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
     if (alive) {
       const Geo<R> G = geo_s[tgt];
       const R2 *lut = LUT_LDS ? lut_s : luts_g + (size_t)G.lut * kLutSize;
-      step<R, false>(L, G, T, lut, k0, k1, flags, C, nullptr, 0);
-      if (L.fate != kAlive) flush_tally(L, G, C);
+      step<R, false, BOX>(L, G, T, lut, k0, k1, flags, C, nullptr, 0, B);
+      if (L.fate != kAlive) flush_tally<R, BOX>(L, G, C, B);
     }
   }
   commit_counters(C, counters, red);
@@ -272,6 +288,238 @@ __global__ void fill_u64_kernel(unsigned long long *p, long long n, unsigned lon
 }
 
 // ---------------------------------------------------------------------------
+// influence matrix: per-spot box tallies -> CSR rows, in tiles of kTile box
+// entries (no tile straddles two spots: box offsets are multiples of kTile).
+// Thread i of a tile handles entries i, i + 256, i + 512, i + 768, so loads
+// of the box tallies are coalesced and the entries of a wave are consecutive.
+// ---------------------------------------------------------------------------
+constexpr int kInfBlock = 256;
+static_assert(kTile == 4 * kInfBlock, "tile = 4 entries per thread");
+
+__device__ __forceinline__ int tile_owner(const long long *tile_first, int n_spots, long long t) {
+  int lo = 0, hi = n_spots;  // tile_first[lo] <= t < tile_first[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tile_first[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+struct InfEntry {
+  long long T;   // box tally, 2^-32 MeV
+  double rho;    // density (0 outside the external mask)
+  int32_t v;     // voxel of the phase grid
+};
+
+__device__ __forceinline__ InfEntry inf_entry(const InfluenceLaunch &a, const BoxDev &bx, long long e) {
+  InfEntry r;
+  const int32_t n0 = bx.n[0], n1 = bx.n[1];
+  const long long yz = e / n0;
+  const int32_t x = (int32_t)(e - yz * n0);
+  const int32_t z = (int32_t)(yz / n1);
+  const int32_t y = (int32_t)(yz - (long long)z * n1);
+  r.v = (bx.lo[0] + x) + a.nx * ((bx.lo[1] + y) + a.ny * (bx.lo[2] + z));
+  r.T = a.box_tally[bx.offset - a.box_bias + e];
+  const double2 *lut = static_cast<const double2 *>(a.lut64);
+  r.rho = lut[clamp_hu<double>(a.hu[r.v])].x;
+  if (a.mask && a.mask[r.v] == 0) r.rho = 0.0;
+  return r;
+}
+
+// tally / density: the dose up to factors common to the spot's voxels
+__device__ __forceinline__ double inf_score(const InfEntry &x) {
+  return (x.T > 0 && x.rho > 0.0) ? (double)x.T / x.rho : 0.0;
+}
+
+__device__ __forceinline__ bool inf_keep(const InfEntry &x, double thr) {
+  return x.T > 0 && x.rho > 0.0 && (double)x.T / x.rho >= thr;
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+__global__ void __launch_bounds__(kInfBlock) influence_max(InfluenceLaunch a) {
+  __shared__ double smax[kInfBlock / 64];
+  __shared__ unsigned long long ssum[2][kInfBlock / 64];
+  const long long t = blockIdx.x;
+  const int j = tile_owner(a.tile_first, a.n_spots, t);
+  const BoxDev bx = a.boxes[j];
+  const long long ne = (long long)bx.n[0] * bx.n[1] * bx.n[2];
+  const long long e0 = (t - a.tile_first[j]) * kTile;
+  double m = 0.0;
+  unsigned long long lo32 = 0, hi32 = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const long long e = e0 + threadIdx.x + k * kInfBlock;
+    if (e < ne) {
+      const InfEntry x = inf_entry(a, bx, e);
+      m = fmax(m, inf_score(x));
+      const unsigned long long T = (unsigned long long)x.T;  // >= 0
+      lo32 += T & 0xffffffffull;
+      hi32 += T >> 32;
+    }
+  }
+  m = wave_max(m);
+  lo32 = wave_sum(lo32);
+  hi32 = wave_sum(hi32);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    smax[w] = m;
+    ssum[0][w] = lo32;
+    ssum[1][w] = hi32;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kInfBlock / 64; ++i) {
+      m = fmax(m, smax[i]);
+      lo32 += ssum[0][i];
+      hi32 += ssum[1][i];
+    }
+    // non-negative doubles order like their bit patterns
+    if (m > 0.0)
+      __hip_atomic_fetch_max(&a.spot_max[j], (unsigned long long)__double_as_longlong(m),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long lo = lo32 + (hi32 << 32);
+    const unsigned long long hi = (hi32 >> 32) + (lo < lo32 ? 1ull : 0ull);
+    if (lo | hi) add128(a.dep_sum, lo, hi);
+  }
+}
+
+__global__ void __launch_bounds__(kInfBlock) influence_count(InfluenceLaunch a) {
+  __shared__ uint32_t scount[kInfBlock / 64];
+  const long long t = blockIdx.x;
+  const int j = tile_owner(a.tile_first, a.n_spots, t);
+  const BoxDev bx = a.boxes[j];
+  const long long ne = (long long)bx.n[0] * bx.n[1] * bx.n[2];
+  const long long e0 = (t - a.tile_first[j]) * kTile;
+  const double thr = a.rel_threshold * __longlong_as_double((long long)a.spot_max[j]);
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const long long e = e0 + threadIdx.x + k * kInfBlock;
+    if (e < ne && inf_keep(inf_entry(a, bx, e), thr)) c += 1;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) scount[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int i = 0; i < kInfBlock / 64; ++i) s += scount[i];
+    a.tile_count[t] = s;
+  }
+}
+
+// Inclusive scan of one value per thread over a block of 1024 threads;
+// every thread must call it.  Returns the inclusive prefix and the total.
+__device__ __forceinline__ unsigned long long block_scan_1024(unsigned long long x,
+                                                              unsigned long long *total) {
+  __shared__ unsigned long long wsum[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    unsigned long long s = lane < 16 ? wsum[lane] : 0ull;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const unsigned long long y = __shfl_up(s, o, 64);
+      if (lane >= o) s += y;
+    }
+    if (lane < 16) wsum[lane] = s;
+  }
+  __syncthreads();
+  const unsigned long long before = w > 0 ? wsum[w - 1] : 0ull;
+  *total = wsum[15];
+  __syncthreads();
+  return x + before;
+}
+
+// exclusive offsets of the tiles within their chunk of 1024 tiles; chunk sums
+__global__ void __launch_bounds__(1024) influence_scan_tiles(const uint32_t *tile_count, long long n_tiles,
+                                                             unsigned long long *tile_off,
+                                                             unsigned long long *chunk_sum) {
+  const long long t = (long long)blockIdx.x * 1024 + threadIdx.x;
+  const unsigned long long x = t < n_tiles ? tile_count[t] : 0ull;
+  unsigned long long total;
+  const unsigned long long incl = block_scan_1024(x, &total);
+  if (t < n_tiles) tile_off[t] = incl - x;
+  if (threadIdx.x == 0) chunk_sum[blockIdx.x] = total;
+}
+
+// chunk sums -> exclusive chunk offsets in place; chunk_off[n_chunks] = total
+__global__ void __launch_bounds__(1024) influence_scan_chunks(unsigned long long *chunk_off,
+                                                              long long n_chunks) {
+  unsigned long long carry = 0;
+  for (long long base = 0; base < n_chunks; base += 1024) {
+    const long long c = base + threadIdx.x;
+    const unsigned long long x = c < n_chunks ? chunk_off[c] : 0ull;
+    unsigned long long total;
+    const unsigned long long incl = block_scan_1024(x, &total);
+    if (c < n_chunks) chunk_off[c] = carry + incl - x;
+    carry += total;
+  }
+  if (threadIdx.x == 0) chunk_off[n_chunks] = carry;
+}
+
+__device__ __forceinline__ unsigned long long tile_offset(const InfluenceLaunch &a, long long t) {
+  const long long n_chunks = (a.n_tiles + 1023) / 1024;
+  return t < a.n_tiles ? a.chunk_off[t >> 10] + a.tile_off[t] : a.chunk_off[n_chunks];
+}
+
+__global__ void __launch_bounds__(kInfBlock) influence_write(InfluenceLaunch a) {
+  __shared__ uint32_t wcount[kInfBlock / 64];
+  const long long t = blockIdx.x;
+  const int j = tile_owner(a.tile_first, a.n_spots, t);
+  const BoxDev bx = a.boxes[j];
+  const long long ne = (long long)bx.n[0] * bx.n[1] * bx.n[2];
+  const long long e0 = (t - a.tile_first[j]) * kTile;
+  const double thr = a.rel_threshold * __longlong_as_double((long long)a.spot_max[j]);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned long long pos = (unsigned long long)a.nnz_base + tile_offset(a, t);
+  for (int k = 0; k < 4; ++k) {  // sub-tiles of 256 consecutive entries, in order
+    const long long e = e0 + threadIdx.x + k * kInfBlock;
+    InfEntry x = {};
+    bool keep = false;
+    if (e < ne) {
+      x = inf_entry(a, bx, e);
+      keep = inf_keep(x, thr);
+    }
+    const unsigned long long bal = __ballot(keep);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if (lane == 0) wcount[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = 0, sub = 0;
+    for (int i = 0; i < kInfBlock / 64; ++i) {
+      before += i < w ? wcount[i] : 0u;
+      sub += wcount[i];
+    }
+    if (keep) {
+      const unsigned long long p = pos + before + rank;
+      const double e_j = (double)x.T / 4294967296.0 * 1.602176634e-13;
+      const double m_kg = x.rho * a.vol_cm3 * 1e-3;
+      a.voxel[p] = x.v;
+      a.value[p] = (float)(e_j / m_kg / bx.n_hist);
+    }
+    pos += sub;
+    __syncthreads();
+  }
+}
+
+__global__ void influence_rows(InfluenceLaunch a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < a.n_spots) a.row_ptr[j] = a.nnz_base + (long long)tile_offset(a, a.tile_first[j]);
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 template <typename R>
@@ -295,21 +543,25 @@ static hipError_t launch_plain_t(const PlainLaunch &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename R>
-static hipError_t launch_persistent_t(const PersistentLaunch &a, hipStream_t st) {
+template <typename R, bool LUT_LDS, bool BOX>
+static void launch_persistent_v(const PersistentLaunch &a, size_t lds, hipStream_t st) {
   using R2 = typename M<R>::R2;
   using R4 = typename M<R>::R4;
+  hipLaunchKernelGGL((transport_persistent<R, LUT_LDS, BOX>), dim3(a.grid), dim3(a.block), lds, st,
+                     (const SpotDev<R> *)a.spots, a.items, a.n_items, a.targets, a.n_targets,
+                     (const R2 *)a.luts, (const R4 *)a.tab, (R)a.l2e0, (R)a.inv_dl2, (R)a.dl2,
+                     a.k0, a.k1, a.flags, a.refill_min, a.cursor, a.counters, a.boxes,
+                     a.box_tally, a.box_bias);
+}
+
+template <typename R>
+static hipError_t launch_persistent_t(const PersistentLaunch &a, hipStream_t st) {
   const size_t lds = persistent_lds<R>(a);
-  if (a.lut_lds)
-    hipLaunchKernelGGL((transport_persistent<R, true>), dim3(a.grid), dim3(a.block), lds, st,
-                       (const SpotDev<R> *)a.spots, a.items, a.n_items, a.targets, a.n_targets,
-                       (const R2 *)a.luts, (const R4 *)a.tab, (R)a.l2e0, (R)a.inv_dl2, (R)a.dl2,
-                       a.k0, a.k1, a.flags, a.refill_min, a.cursor, a.counters);
-  else
-    hipLaunchKernelGGL((transport_persistent<R, false>), dim3(a.grid), dim3(a.block), lds, st,
-                       (const SpotDev<R> *)a.spots, a.items, a.n_items, a.targets, a.n_targets,
-                       (const R2 *)a.luts, (const R4 *)a.tab, (R)a.l2e0, (R)a.inv_dl2, (R)a.dl2,
-                       a.k0, a.k1, a.flags, a.refill_min, a.cursor, a.counters);
+  const bool box = a.boxes != nullptr;
+  if (a.lut_lds && box) launch_persistent_v<R, true, true>(a, lds, st);
+  else if (a.lut_lds) launch_persistent_v<R, true, false>(a, lds, st);
+  else if (box) launch_persistent_v<R, false, true>(a, lds, st);
+  else launch_persistent_v<R, false, false>(a, lds, st);
   return hipGetLastError();
 }
 
@@ -323,12 +575,16 @@ template <typename R>
 static int blocks_per_cu_t(const PersistentLaunch &a) {
   int n = 0;
   hipError_t e;
-  if (a.lut_lds)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, transport_persistent<R, true>, a.block,
-                                                     persistent_lds<R>(a));
+  const size_t lds = persistent_lds<R>(a);
+  const bool box = a.boxes != nullptr;
+  if (a.lut_lds && box)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, transport_persistent<R, true, true>, a.block, lds);
+  else if (a.lut_lds)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, transport_persistent<R, true, false>, a.block, lds);
+  else if (box)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, transport_persistent<R, false, true>, a.block, lds);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, transport_persistent<R, false>, a.block,
-                                                     persistent_lds<R>(a));
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, transport_persistent<R, false, false>, a.block, lds);
   return e == hipSuccess ? n : 1;
 }
 
@@ -369,6 +625,26 @@ hipError_t launch_convert(const long long *tally, const int16_t *hu, const uint8
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(convert_kernel, dim3((unsigned)nb), dim3(block), 0, st, tally, hu, mask,
                      (const double2 *)lut64, nvox, vol_cm3, n_hist, dose, density);
+  return hipGetLastError();
+}
+
+hipError_t launch_influence_reduce(const InfluenceLaunch &a, hipStream_t st) {
+  const long long n_chunks = (a.n_tiles + 1023) / 1024;
+  if (a.n_tiles > 0) {
+    hipLaunchKernelGGL(influence_max, dim3((unsigned)a.n_tiles), dim3(kInfBlock), 0, st, a);
+    hipLaunchKernelGGL(influence_count, dim3((unsigned)a.n_tiles), dim3(kInfBlock), 0, st, a);
+    hipLaunchKernelGGL(influence_scan_tiles, dim3((unsigned)n_chunks), dim3(1024), 0, st,
+                       (const uint32_t *)a.tile_count, a.n_tiles, a.tile_off, a.chunk_off);
+  }
+  hipLaunchKernelGGL(influence_scan_chunks, dim3(1), dim3(1024), 0, st, a.chunk_off, n_chunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_influence_write(const InfluenceLaunch &a, hipStream_t st) {
+  if (a.n_tiles > 0)
+    hipLaunchKernelGGL(influence_write, dim3((unsigned)a.n_tiles), dim3(kInfBlock), 0, st, a);
+  if (a.n_spots > 0)
+    hipLaunchKernelGGL(influence_rows, dim3((unsigned)((a.n_spots + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -33,7 +33,8 @@ ERROR_NAMES = {0: "PMC_OK", -1: "PMC_E_INVAL", -2: "PMC_E_NOPHASE", -3: "PMC_E_B
 EXPORTS = ["pmc_create", "pmc_destroy", "pmc_last_error", "pmc_load_phase", "pmc_unload_phase",
            "pmc_load_spots", "pmc_load_plan", "pmc_unload_plan", "pmc_request_items", "pmc_dose", "pmc_dose_device", "pmc_balance_from_counters",
            "pmc_convert_device", "pmc_trace", "pmc_split_histories", "pmc_bytes_in_use",
-           "pmc_graph_create", "pmc_graph_launch", "pmc_graph_destroy"]
+           "pmc_graph_create", "pmc_graph_launch", "pmc_graph_destroy", "pmc_influence_boxes",
+           "pmc_influence", "pmc_influence_read", "pmc_influence_device", "pmc_influence_free"]
 
 
 class pmc_config(C.Structure):
@@ -71,6 +72,8 @@ TRACE_DTYPE = np.dtype([
     ("n_delta", "<f8"), ("n_nuc", "<f8"), ("l_acc", "<f8"), ("dep", "<i8"), ("t_delta", "<f8"),
 ])
 assert TRACE_DTYPE.itemsize == 120
+
+BOX_DTYPE = np.dtype([("lo", "<i4", 3), ("hi", "<i4", 3)])  # pmc_box
 
 
 class PmcError(RuntimeError):
@@ -114,6 +117,12 @@ def lib():
         L.pmc_graph_launch.argtypes = [vp, vp]
         L.pmc_graph_destroy.argtypes = [vp]
         L.pmc_graph_destroy.restype = None
+        L.pmc_influence_boxes.argtypes = [vp, i32, i32, vp, i64]
+        L.pmc_influence.argtypes = [vp, C.POINTER(pmc_request), vp, C.c_double, u64, C.POINTER(u64),
+                                    C.POINTER(pmc_balance), vp]
+        L.pmc_influence_read.argtypes = [vp, vp, vp, vp]
+        L.pmc_influence_device.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
+        L.pmc_influence_free.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -292,6 +301,44 @@ def pmc_graph_launch(g, stream: int, ctx=None) -> None:
 
 def pmc_graph_destroy(g) -> None:
     lib().pmc_graph_destroy(g)
+
+
+def pmc_influence_boxes(ctx, plan: int, phase: int, n_spots: int) -> np.ndarray:
+    out = np.zeros(n_spots, dtype=BOX_DTYPE)
+    _check(lib().pmc_influence_boxes(ctx, plan, phase, _ptr(out), n_spots), ctx)
+    return out
+
+
+def pmc_influence(ctx, req: Request, boxes: Optional[np.ndarray], rel_threshold: float,
+                  max_scratch_bytes: int = 0):
+    """Compute the influence matrix (kept in the context); returns
+    (nnz, balance dict, outside energy in 2^-32 MeV)."""
+    b = None if boxes is None else np.ascontiguousarray(boxes, dtype=BOX_DTYPE)
+    nnz = C.c_uint64(0)
+    bal = pmc_balance()
+    out = np.zeros(2, dtype=np.uint64)
+    _check(lib().pmc_influence(ctx, C.byref(req.c), _ptr(b), float(rel_threshold),
+                               int(max_scratch_bytes), C.byref(nnz), C.byref(bal), _ptr(out)), ctx)
+    return int(nnz.value), bal.as_dict(), int(out[0]) + (int(out[1]) << 64)
+
+
+def pmc_influence_read(ctx, n_spots: int, nnz: int):
+    """(row_ptr int64[n_spots + 1], voxel int32[nnz], value float32[nnz])."""
+    rows = np.zeros(n_spots + 1, dtype=np.int64)
+    vox = np.zeros(nnz, dtype=np.int32)
+    val = np.zeros(nnz, dtype=np.float32)
+    _check(lib().pmc_influence_read(ctx, _ptr(rows), _ptr(vox), _ptr(val)), ctx)
+    return rows, vox, val
+
+
+def pmc_influence_device(ctx):
+    r, v, x = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    _check(lib().pmc_influence_device(ctx, C.byref(r), C.byref(v), C.byref(x)), ctx)
+    return r.value, v.value, x.value
+
+
+def pmc_influence_free(ctx) -> None:
+    _check(lib().pmc_influence_free(ctx), ctx)
 
 
 # ----------------------------------------------------------------------------

@@ -302,6 +302,33 @@ def workload_slabs(n_histories=10_000_000) -> Workload:
     return Workload("slabs_128", [ph], plan_slabs(2), n_histories, seed=2)
 
 
+def workload_influence(n_histories=30_000) -> Workload:
+    """Small heterogeneous case for influence matrices: 48 x 48 x 64 voxels
+    of 2.5 mm (water, a lung slab at z 20-50 mm, a bone block at x > 15 mm,
+    z 60-80 mm); two fields (+z and oblique in x-z), a 3 x 3 spot grid
+    (+-15 mm) at 90 and 120 MeV on the +z field, 4 spots on the oblique
+    field, one spot that misses the grid and one spot of another phase."""
+    ph = make_box((48, 48, 64), (2.5, 2.5, 2.5), 0, origin_mm=(-60.0, -60.0, 0.0))
+    z = (np.arange(64) + 0.5) * 2.5
+    x = (np.arange(48) + 0.5) * 2.5 - 60.0
+    ph.hu[(z >= 20) & (z < 50), :, :] = -700
+    bone = ((z >= 60) & (z < 80))[:, None, None] & (x > 15.0)[None, None, :]
+    ph.hu[np.broadcast_to(bone, ph.hu.shape)] = 1000
+    c = 1.0 / math.sqrt(2.0)
+    fields = np.array([make_field((0.0, 0.0, 60.0), (0, 0, 1), (1, 0, 0)),
+                       make_field((0.0, 0.0, 60.0), (c, 0.0, c), (c, 0.0, -c))], dtype=FIELD_DTYPE)
+    rows = []
+    for e in (90.0, 120.0):
+        for yy in (-15.0, 0.0, 15.0):
+            for xx in (-15.0, 0.0, 15.0):
+                rows.append((e, xx, yy, 4.0, 1.0 + 0.1 * len(rows), 0, 0))
+    for k, (xx, yy) in enumerate(((-10.0, 0.0), (0.0, 0.0), (10.0, -10.0), (0.0, 12.0))):
+        rows.append((100.0 + 10.0 * k, xx, yy, 3.0, 1.5, 0, 1))
+    rows.append((100.0, 300.0, 0.0, 3.0, 1.0, 0, 0))  # misses the grid
+    rows.append((100.0, 0.0, 0.0, 3.0, 1.0, 1, 0))    # another phase
+    return Workload("influence_48x48x64", [ph], Plan(fields, _spots(rows)), n_histories, seed=6)
+
+
 def workload_thorax4d(n_histories=50_000_000, shape_xyz=(256, 256, 160), n_phases=10) -> Workload:
     phases = [make_thorax(shape_xyz, p, n_phases) for p in range(n_phases)]
     plan = plan_thorax(3, n_phases=n_phases)

@@ -1,0 +1,182 @@
+"""Influence matrix on the GPU, through the C ABI, against the oracle's
+per-spot definition (FP64 engine) and against the dense engine (FP32: same
+histories, same random numbers, so energy bookkeeping is exact)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1809_03927_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1809_03927_amd import pmc
+    return pmc
+
+
+def engine(P, wl, precision, budget=0):
+    e = P.Engine(device=0, precision=precision, seed=wl.seed, hbm_budget_bytes=budget)
+    e.load_workload(wl)
+    return e
+
+
+def run(P, e, wl, n, boxes=None, thr=0.01, scratch=0, **launch):
+    req = P.Request(n, [0], engine=P.PMC_ENGINE_PERSISTENT, **launch)
+    nnz, bal, out = P.pmc_influence(e.ctx, req, boxes, thr, scratch)
+    rows, vox, val = P.pmc_influence_read(e.ctx, len(wl.plan.spots), nnz)
+    return rows, vox, val, bal, out
+
+
+def full_boxes(P, wl):
+    b = np.zeros(len(wl.plan.spots), dtype=P.BOX_DTYPE)
+    nz, ny, nx = wl.phases[0].hu.shape
+    b["hi"] = (nx, ny, nz)
+    return b
+
+
+def test_fp64_influence_matches_oracle(P, orc):
+    wl = W.workload_influence(n_histories=20_000)
+    say("fp64 influence vs oracle", wl.n_histories)
+    e = engine(P, wl, P.PMC_FP64)
+    try:
+        boxes = P.pmc_influence_boxes(e.ctx, 0, 0, len(wl.plan.spots))
+        rows, vox, val, bal, out = run(P, e, wl, wl.n_histories, boxes, 0.01)
+    finally:
+        e.close()
+    ref = orc.influence(wl.phases[0], wl.plan, wl.n_histories, wl.seed, boxes, 0.01)
+    ob = ref["balance"]
+    assert bal["incident"] == ob["incident"] and bal["histories"] == ob["histories"]
+    assert bal["steps"] == ob["steps"]
+    # a unit or two of 2^-32 MeV per step from rounding order
+    assert abs(bal["deposited"] - ref["box_deposited"]) <= 2 * bal["steps"]
+    assert abs(out - ref["outside"]) <= 2 * bal["steps"]
+    assert bal["deposited"] + out + bal["escaped"] + bal["nuclear"] == bal["incident"]
+    assert ref["outside"] > 0  # the boxes do cut something
+    n_diff = 0
+    for s in range(len(wl.plan.spots)):
+        a, b = rows[s], rows[s + 1]
+        ra, rb = ref["row_ptr"][s], ref["row_ptr"][s + 1]
+        g = dict(zip(vox[a:b].tolist(), val[a:b].tolist()))
+        o = dict(zip(ref["voxel"][ra:rb].tolist(), ref["value"][ra:rb].tolist()))
+        assert np.all(np.diff(vox[a:b]) > 0)
+        if not o:
+            assert not g, s
+            continue
+        mx = max(o.values())
+        for v in set(g) ^ set(o):  # only voxels at the threshold may differ
+            x = g.get(v, o.get(v))
+            assert abs(x / mx - 0.01) < 1e-6, (s, v, x / mx)
+            n_diff += 1
+        common = sorted(set(g) & set(o))
+        gv = np.array([g[v] for v in common])
+        ov = np.array([o[v] for v in common])
+        assert np.allclose(gv, ov, rtol=1e-6, atol=0), s
+    assert n_diff <= 2
+
+
+def test_fp32_influence_energy_equals_dense_run(P):
+    wl = W.workload_influence(n_histories=200_000)
+    say("fp32 influence vs dense", wl.n_histories)
+    e = engine(P, wl, P.PMC_FP32)
+    try:
+        rows, vox, val, bal, out = run(P, e, wl, wl.n_histories, None, 0.01)
+        _, tal, _, dbal = e.dose(wl.n_histories, [0], engine=P.PMC_ENGINE_PERSISTENT)
+        # the same histories: every deposit is in a box or outside
+        assert bal["deposited"] + out == dbal["deposited"]
+        for k in ("incident", "escaped", "nuclear", "cutoff", "histories", "steps", "delta_events",
+                  "nuclear_events", "escapes", "misses"):
+            assert bal[k] == dbal[k], k
+        # threshold 0 and whole-grid boxes: the rows rebuild the dose
+        rows0, vox0, val0, bal0, out0 = run(P, e, wl, wl.n_histories, full_boxes(P, wl), 0.0)
+        assert out0 == 0 and bal0["deposited"] == dbal["deposited"]
+        per = P.pmc_split_histories(wl.plan.spots, [0], wl.n_histories)
+        acc = np.zeros(wl.phases[0].nvox)
+        for s in range(len(wl.plan.spots)):
+            a, b = rows0[s], rows0[s + 1]
+            np.add.at(acc, vox0[a:b], per[s] * val0[a:b].astype(np.float64))
+        dose, _, _, _ = e.dose(wl.n_histories, [0], engine=P.PMC_ENGINE_PERSISTENT)
+        ref = wl.n_histories * dose[0]
+        assert np.allclose(acc, ref, rtol=2e-7, atol=1e-9 * ref.max())
+        # the 1 % matrix is a subset of the full one with the same values
+        for s in range(len(wl.plan.spots)):
+            a, b = rows[s], rows[s + 1]
+            a0, b0 = rows0[s], rows0[s + 1]
+            full = dict(zip(vox0[a0:b0].tolist(), val0[a0:b0].tolist()))
+            mx = max(full.values()) if full else 0.0
+            box_only = {v for v in vox[a:b].tolist()}
+            for v in box_only:
+                assert v in full
+            for v, x in zip(vox[a:b].tolist(), val[a:b].tolist()):
+                assert x == full[v] and x >= 0.01 * mx * (1 - 1e-6)
+    finally:
+        e.close()
+
+
+def test_batches_give_the_same_matrix(P):
+    wl = W.workload_influence(n_histories=100_000)
+    e = engine(P, wl, P.PMC_FP32)
+    try:
+        boxes = P.pmc_influence_boxes(e.ctx, 0, 0, len(wl.plan.spots))
+        per = P.pmc_split_histories(wl.plan.spots, [0], wl.n_histories)
+        sizes = [int(np.prod(b["hi"] - b["lo"])) for b in boxes]
+        padded = [(-(-n // 1024)) * 1024 for n, h in zip(sizes, per) if h > 0]
+        say("influence batches", sum(padded), max(padded))
+        ref = run(P, e, wl, wl.n_histories, boxes, 0.01)
+        for scratch_entries in (max(padded), 2 * max(padded), sum(padded) // 2):
+            got = run(P, e, wl, wl.n_histories, boxes, 0.01, scratch=8 * scratch_entries)
+            for a, b in zip(ref[:3], got[:3]):
+                assert np.array_equal(a, b), scratch_entries
+            assert ref[3] == got[3] and ref[4] == got[4]
+        with pytest.raises(P.PmcError) as ex:
+            run(P, e, wl, wl.n_histories, boxes, 0.01, scratch=8 * (max(padded) - 1024))
+        assert ex.value.code == P.PMC_E_BUDGET
+        # launch shapes do not change the result
+        got = run(P, e, wl, wl.n_histories, boxes, 0.01, block_size=1024, chunk=64, refill_min=32)
+        for a, b in zip(ref[:3], got[:3]):
+            assert np.array_equal(a, b)
+    finally:
+        e.close()
+
+
+def test_influence_edge_cases(P):
+    wl = W.workload_influence(n_histories=20_000)
+    e = engine(P, wl, P.PMC_FP32)
+    try:
+        n_spots = len(wl.plan.spots)
+        per = P.pmc_split_histories(wl.plan.spots, [0], wl.n_histories)
+        say("influence threshold 1")
+        rows, vox, val, bal, out = run(P, e, wl, wl.n_histories, None, 1.0)
+        for s in range(n_spots):
+            n_row = rows[s + 1] - rows[s]
+            if per[s] == 0 or abs(wl.plan.spots[s]["x_mm"]) > 100:
+                assert n_row == 0, s  # no histories, or the spot misses the grid
+            else:
+                assert n_row >= 1, s  # the maximum itself
+        say("influence empty boxes")
+        empty = np.zeros(n_spots, dtype=P.BOX_DTYPE)
+        rows, vox, val, bal, out = run(P, e, wl, wl.n_histories, empty, 0.01)
+        assert rows[-1] == 0 and bal["deposited"] == 0
+        assert out + bal["escaped"] + bal["nuclear"] == bal["incident"]
+        bad = empty.copy()
+        bad[0]["hi"] = (49, 1, 1)
+        with pytest.raises(P.PmcError):
+            run(P, e, wl, wl.n_histories, bad, 0.01)
+        with pytest.raises(P.PmcError):
+            P.pmc_influence(e.ctx, P.Request(1000, [0], engine=P.PMC_ENGINE_PERSISTENT).slice(0, 2),
+                            None, 0.01)
+        # the result survives until freed
+        rows, vox, val, bal, out = run(P, e, wl, wl.n_histories, None, 0.01)
+        dptr = P.pmc_influence_device(e.ctx)
+        assert all(p for p in dptr)
+        P.pmc_influence_free(e.ctx)
+        with pytest.raises(P.PmcError):
+            P.pmc_influence_read(e.ctx, n_spots, 0)
+    finally:
+        e.close()

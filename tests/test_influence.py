@@ -1,0 +1,225 @@
+"""Influence matrix without a GPU: the oracle's per-spot definition against
+what fixes it (superposition of spots, the dose conversion of Eq. (4), a
+brute-force threshold), and the library's spot boxes (a host computation,
+validation-only context) against CSDA ranges and an independent numerical
+integration of the water-equivalent depth along the beam axis."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1809_03927_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BOX = np.dtype([("lo", "<i4", 3), ("hi", "<i4", 3)])
+
+
+def full_boxes(ph, n):
+    b = np.zeros(n, dtype=BOX)
+    nz, ny, nx = ph.hu.shape
+    b["hi"] = (nx, ny, nz)
+    return b
+
+
+@pytest.fixture(scope="module")
+def wl():
+    return W.workload_influence(n_histories=12_000)
+
+
+def test_spot_tallies_superpose_to_the_request(orc, wl):
+    """Every history belongs to exactly one spot: the tallies of the spots run
+    one at a time add up to the whole request's tally, unit for unit."""
+    ph = wl.phases[0]
+    (full,), bal = orc.dose_spots([ph], wl.plan, wl.n_histories, wl.seed, 0, len(wl.plan.spots), 0, [0])
+    (ref,), _, rbal = orc.dose([ph], wl.plan, wl.n_histories, wl.seed, phase_ids=[0], with_dose=False)
+    assert np.array_equal(full, ref) and bal == rbal
+    acc = np.zeros_like(ref)
+    for s in range(len(wl.plan.spots)):
+        (t,), _ = orc.dose_spots([ph], wl.plan, wl.n_histories, wl.seed, s, s + 1, 0, [0])
+        acc += t
+    assert np.array_equal(acc, ref)
+
+
+def test_influence_without_threshold_rebuilds_the_dose(orc, wl):
+    """Threshold 0 and whole-grid boxes: sum over spots of histories x
+    influence = histories x dose of the request (dose = energy / mass, Eq. 4),
+    up to the float32 rounding of the matrix entries."""
+    ph = wl.phases[0]
+    r = orc.influence(ph, wl.plan, wl.n_histories, wl.seed, full_boxes(ph, len(wl.plan.spots)), 0.0)
+    (t,), dose, bal = orc.dose([ph], wl.plan, wl.n_histories, wl.seed, phase_ids=[0])
+    acc = np.zeros(ph.hu.size)
+    for s in range(len(wl.plan.spots)):
+        a, b = r["row_ptr"][s], r["row_ptr"][s + 1]
+        np.add.at(acc, r["voxel"][a:b], r["per_spot"][s] * r["value"][a:b].astype(np.float64))
+        assert np.all(np.diff(r["voxel"][a:b]) > 0)  # ascending within a row
+    ref = wl.n_histories * dose[0]
+    assert np.allclose(acc, ref, rtol=2e-7, atol=1e-9 * ref.max())
+    assert r["outside"] == 0 and r["box_deposited"] == bal["deposited"]
+    # exactly the voxels with energy are listed
+    assert r["row_ptr"][-1] == sum(int(np.count_nonzero(
+        orc.dose_spots([ph], wl.plan, wl.n_histories, wl.seed, s, s + 1, 0, [0])[0][0]))
+        for s in range(len(wl.plan.spots)))
+    # spots without histories (missing phase) have empty rows
+    per = r["per_spot"]
+    assert per[-1] == 0 and r["row_ptr"][-1] == r["row_ptr"][-2]
+
+
+def test_threshold_and_box_by_brute_force(orc, wl):
+    """Rows of three spots recomputed voxel by voxel in plain Python."""
+    ph = wl.phases[0]
+    nz, ny, nx = ph.hu.shape
+    boxes = full_boxes(ph, len(wl.plan.spots))
+    boxes[0] = ((10, 12, 0), (40, 30, 50))
+    boxes[4] = ((16, 16, 5), (32, 32, 40))
+    thr = 0.05
+    r = orc.influence(ph, wl.plan, wl.n_histories, wl.seed, boxes, thr)
+    _, rho = orc.convert(ph, np.zeros(ph.hu.size, dtype=np.int64), 1)
+    vol = 0.25 ** 3
+    outside = 0
+    for s in range(len(wl.plan.spots)):
+        (t,), _ = orc.dose_spots([ph], wl.plan, wl.n_histories, wl.seed, s, s + 1, 0, [0])
+        lo, hi = boxes[s]["lo"], boxes[s]["hi"]
+        best, cand = 0.0, []
+        for v in np.nonzero(t)[0]:
+            x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
+            if not (lo[0] <= x < hi[0] and lo[1] <= y < hi[1] and lo[2] <= z < hi[2]):
+                outside += int(t[v])
+                continue
+            if rho[v] > 0:
+                sc = float(t[v]) / rho[v]
+                best = max(best, sc)
+                cand.append((v, sc))
+        if s not in (0, 4, 10):
+            continue
+        keep = [v for v, sc in cand if sc >= thr * best]
+        a, b = r["row_ptr"][s], r["row_ptr"][s + 1]
+        assert list(r["voxel"][a:b]) == sorted(keep), s
+        n_s = r["per_spot"][s]
+        for v, val in zip(r["voxel"][a:b], r["value"][a:b]):
+            want = np.float32(float(t[v]) / 2.0**32 * 1.602176634e-13 / (rho[v] * vol * 1e-3) / n_s)
+            assert val == want
+    assert r["outside"] == outside > 0
+    assert r["box_deposited"] + r["outside"] == r["balance"]["deposited"]
+
+
+# ----------------------------------------------------------------------------
+# spot boxes (library host code, no GPU)
+# ----------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1809_03927_amd import pmc
+    return pmc
+
+
+def boxes_of(P, ph, plan, phase=0):
+    ctx = P.pmc_create(device=-1)
+    try:
+        P.pmc_load_phase(ctx, phase, ph)
+        P.pmc_load_spots(ctx, plan.fields, plan.spots)
+        return P.pmc_influence_boxes(ctx, 0, phase, len(plan.spots))
+    finally:
+        P.pmc_destroy(ctx)
+
+
+def pstar():
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "pstar_water.txt"))
+            if l.strip() and not l.startswith("#")]
+    return {float(r[0]): float(r[2]) for r in rows}
+
+
+@pytest.mark.parametrize("E", [50.0, 100.0, 150.0, 200.0])
+def test_water_box_depth_and_width(P, orc, E):
+    ph = W.make_box((80, 80, 160), (2.5, 2.5, 2.5), 0, origin_mm=(-100.0, -100.0, 0.0))
+    sigma = 5.0
+    plan = W.plan_single(E, sigma, (0.0, 0.0, 100.0))
+    (b,) = boxes_of(P, ph, plan)
+    R = orc.f64("orc_range", E)
+    # the range table agrees with the CSDA range of PSTAR
+    assert abs(R / pstar()[E] - 1.0) < 0.06
+    depth = R + 3.0  # cm of water from the entry face z = 0
+    assert b["lo"][2] == 0
+    assert b["hi"][2] == math.floor(depth / 0.25) + 1
+    half = 3.0 * math.sqrt((0.1 * sigma) ** 2 + (0.035 * depth) ** 2)
+    for k in (0, 1):
+        assert b["lo"][k] == math.floor((10.0 - half) / 0.25)
+        assert b["hi"][k] == math.floor((10.0 + half) / 0.25) + 1
+
+
+def test_heterogeneous_box_follows_water_equivalent_depth(P, orc):
+    wl = W.workload_influence()
+    ph = wl.phases[0]
+    boxes = boxes_of(P, ph, wl.plan)
+    spots, fields = wl.plan.spots, wl.plan.fields
+    rsp_of = lambda hu: np.interp(hu, W.CALIB_HU, W.CALIB_RSP)
+    nz, ny, nx = ph.hu.shape
+    d = 0.25
+    for s, sp in enumerate(spots):
+        b = boxes[s]
+        if sp["phase"] != 0 or abs(sp["x_mm"]) > 100:
+            assert np.all(b["lo"] == b["hi"]) or np.all(b["hi"] == 0), s
+            continue
+        f = fields[sp["field"]]
+        w = np.array(f["direction"]) / np.linalg.norm(f["direction"])
+        u = np.array(f["bev_u"]) / np.linalg.norm(f["bev_u"])
+        v = np.cross(w, u)
+        c = 0.1 * (np.array(f["isocentre_mm"]) - np.array(ph.origin_mm)) + 0.1 * sp["x_mm"] * u + 0.1 * sp["y_mm"] * v
+        # dense sampling of the axis from far upstream
+        step = 1e-4
+        ts = np.arange(-40.0, 40.0, step)
+        pts = c[None, :] + ts[:, None] * w[None, :]
+        idx = np.floor(pts / d).astype(int)
+        inside = np.all((idx >= 0) & (idx < np.array([nx, ny, nz])), axis=1)
+        first = np.argmax(inside)
+        seg = inside[first:]
+        last = first + (np.argmin(seg) if not seg.all() else len(seg))
+        hu = ph.hu[idx[first:last, 2], idx[first:last, 1], idx[first:last, 0]]
+        wet = np.cumsum(rsp_of(hu)) * step
+        target = orc.f64("orc_range", float(sp["energy_MeV"])) + 3.0
+        k = np.searchsorted(wet, target)
+        end = first + min(k, last - first - 1)
+        # every axis point up to the end lies in the box (sampling error of the
+        # depth: far below 0.01 cm)
+        axis_idx = idx[first:max(first, end - 100)]
+        assert np.all(axis_idx >= b["lo"]) and np.all(axis_idx < b["hi"]), s
+        # and the box does not reach past the end by more than its lateral margin + 1 voxel
+        L = ts[end] - ts[first]
+        half = 3.0 * math.sqrt((0.1 * sp["sigma_mm"]) ** 2 + (0.035 * L) ** 2)
+        pe = pts[end]
+        for a in range(3):
+            ext = half * (abs(u[a]) + abs(v[a]))
+            lo_max = min(pts[first][a], pe[a]) - ext
+            hi_max = max(pts[first][a], pe[a]) + ext
+            assert b["lo"][a] >= max(0, math.floor(lo_max / d) - 1), (s, a)
+            assert b["hi"][a] <= min([nx, ny, nz][a], math.floor(hi_max / d) + 2), (s, a)
+    # the lung slab makes the +z boxes of 120 MeV longer than in water
+    (bw,) = boxes_of(P, W.make_box((48, 48, 64), (2.5, 2.5, 2.5), 0, origin_mm=(-60.0, -60.0, 0.0)),
+                     W.plan_single(90.0, 4.0, (0.0, 0.0, 60.0)))
+    assert boxes[4]["hi"][2] > bw["hi"][2]
+
+
+def test_box_validation(P):
+    wl = W.workload_influence()
+    ctx = P.pmc_create(device=-1)
+    try:
+        P.pmc_load_phase(ctx, 0, wl.phases[0])
+        with pytest.raises(P.PmcError):
+            P.pmc_influence_boxes(ctx, 0, 0, len(wl.plan.spots))  # no plan yet
+        P.pmc_load_spots(ctx, wl.plan.fields, wl.plan.spots)
+        with pytest.raises(P.PmcError):
+            P.pmc_influence_boxes(ctx, 0, 0, 3)  # wrong count
+        with pytest.raises(P.PmcError):
+            P.pmc_influence_boxes(ctx, 0, 5, len(wl.plan.spots))  # phase not loaded
+        req = P.Request(1000, [0])
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_influence(ctx, req, None, 0.01)
+        assert e.value.code == P.PMC_E_DEVICE
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_influence(ctx, req, None, 1.5)
+        assert e.value.code == P.PMC_E_INVAL
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_influence_read(ctx, 1, 0)
+        assert e.value.code == P.PMC_E_STATE
+    finally:
+        P.pmc_destroy(ctx)
