@@ -267,12 +267,14 @@ typedef struct {
 
 /* Boxes of the spots of `plan` on `phase` (n_spots = the plan's spot count;
  * spots of other phases get empty boxes): the axis-aligned voxel box around
- * the spot's central axis, from where it enters the grid to water-equivalent
- * depth R(E) + 3 cm (R: the transport's range table; water-equivalent depth
- * = path length x stopping-power ratio of the voxels crossed) or the grid
+ * the spot's central axis, from the first voxel on it with a stopping-power
+ * ratio >= 0.1 (air before it is left out) to water-equivalent depth
+ * R(E) + 3 cm (R: the transport's range table; water-equivalent depth =
+ * path length x stopping-power ratio of the voxels crossed) or the grid
  * exit, widened across the beam by 3 sigma_max, sigma_max^2 = sigma_spot^2 +
- * (0.035 L)^2, L the geometric length of that axis segment.  Host
- * computation; works on a validation-only context. */
+ * (0.035 L)^2, L the geometric length of that axis segment.  Empty if the
+ * axis misses the grid or meets no such voxel.  Host computation; works on
+ * a validation-only context. */
 int pmc_influence_boxes(pmc_context *ctx, int32_t plan, int32_t phase, pmc_box *out, int64_t n_spots);
 
 /* Sparse per-spot influence matrix of a one-phase request (the dose of each

@@ -1363,10 +1363,13 @@ double rsp_at(const PhaseRec &ph, long long v) {
   return ph.lut64[2 * (h - kHuLo) + 1];
 }
 
-// Voxel box of a spot: the spot's central axis from where it enters the grid
-// to water-equivalent depth R(E) + 3 cm (or the grid exit), widened by
+// Voxel box of a spot: the spot's central axis from where it first meets
+// matter (stopping-power ratio >= kBodyRsp; air before it is left out) to
+// water-equivalent depth R(E) + 3 cm (or the grid exit), widened by
 // 3 sigma_max across the beam, sigma_max^2 = sigma_spot^2 + (0.035 L)^2 with
 // L the geometric length of that axis segment.
+constexpr double kBodyRsp = 0.1;
+
 pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s) {
   pmc_box b = {{0, 0, 0}, {0, 0, 0}};
   double w[3], u[3], v[3], c[3], d[3], ext[3];
@@ -1407,7 +1410,7 @@ pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f,
     else if (w[k] < 0.0) { t_max[k] = (idx[k] * d[k] - c[k]) / w[k]; t_step[k] = -d[k] / w[k]; }
     else { t_max[k] = HUGE_VAL; t_step[k] = HUGE_VAL; }
   }
-  double t = t_in, wet = 0.0, t_end = t_out;
+  double t = t_in, wet = 0.0, t_end = t_out, t_body = -HUGE_VAL;
   for (;;) {
     int ax = 0;
     if (t_max[1] < t_max[ax]) ax = 1;
@@ -1415,6 +1418,7 @@ pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f,
     const double t_next = std::min(t_max[ax], t_out);
     const long long vx = (long long)idx[0] + (long long)n[0] * ((long long)idx[1] + (long long)n[1] * idx[2]);
     const double r = rsp_at(ph, vx);
+    if (t_body == -HUGE_VAL && r >= kBodyRsp) t_body = t;
     const double seg = std::max(0.0, t_next - t);
     if (r > 0.0 && wet + r * seg >= target) {
       t_end = t + (target - wet) / r;
@@ -1427,11 +1431,12 @@ pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f,
     if (idx[ax] < 0 || idx[ax] >= n[ax]) break;
     t_max[ax] += t_step[ax];
   }
-  const double L = t_end - t_in;
+  if (t_body == -HUGE_VAL) return b;  // no matter on the axis
+  const double L = t_end - t_body;
   const double sig = 0.1 * s.sigma_mm;
   const double r = 3.0 * std::sqrt(sig * sig + (0.035 * L) * (0.035 * L));
   for (int k = 0; k < 3; ++k) {
-    const double a = c[k] + t_in * w[k], e = c[k] + t_end * w[k];
+    const double a = c[k] + t_body * w[k], e = c[k] + t_end * w[k];
     const double half = r * (std::fabs(u[k]) + std::fabs(v[k]));
     const double lo = std::min(a, e) - half, hi = std::max(a, e) + half;
     long long il = (long long)std::floor(lo / d[k]), ih = (long long)std::floor(hi / d[k]) + 1;
@@ -1528,6 +1533,8 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
     pmc::BoxDev &d = bd[s];
     const int64_t h = P->per_spot[s];
     const long long ne = h > 0 ? box_entries(bx[s]) : 0;
+    if (ne > (1LL << 31) - 2 * pmc::kTile)
+      return fail(ctx, PMC_E_INVAL, "box of spot %lld has more than 2^31 - 2048 voxels", (long long)s);
     for (int k = 0; k < 3; ++k) {
       d.lo[k] = bx[s].lo[k];
       d.n[k] = ne > 0 ? bx[s].hi[k] - bx[s].lo[k] : 0;
@@ -1563,7 +1570,7 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
   const size_t o_tfirst = off; off = align256(off + sizeof(long long) * (size_t)(max_spots + 1));
   const size_t o_max = off; off = align256(off + sizeof(long long) * (size_t)max_spots);
   const size_t o_dep = off; off = align256(off + 2 * sizeof(long long));
-  const size_t o_count = off; off = align256(off + sizeof(uint32_t) * (size_t)max_tiles);
+  const size_t o_count = off; off = align256(off + 2 * sizeof(uint32_t) * (size_t)max_tiles);  // count, keep
   const size_t o_toff = off; off = align256(off + sizeof(long long) * (size_t)max_tiles);
   const size_t o_coff = off; off = align256(off + sizeof(long long) * (size_t)(max_chunks + 1));
   ctx->inf_n_rows = -1;
@@ -1633,6 +1640,9 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
     L.spot_max = d_max;
     L.dep_sum = d_dep;
     L.tile_count = reinterpret_cast<uint32_t *>(work + o_count);
+    L.tile_keep = L.tile_count + n_tiles;
+    HIP_TRY(ctx, pmc::launch_fill_u64(reinterpret_cast<unsigned long long *>(L.tile_count), n_tiles, 0ull, st),
+            "zero tile counts");  // 2 x n_tiles 32-bit words
     L.tile_off = reinterpret_cast<unsigned long long *>(work + o_toff);
     L.chunk_off = reinterpret_cast<unsigned long long *>(work + o_coff);
     L.nnz_base = (long long)nnz;

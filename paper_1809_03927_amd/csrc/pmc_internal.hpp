@@ -120,7 +120,8 @@ struct InfluenceLaunch {
   double rel_threshold;
   unsigned long long *spot_max;  // n_spots words (bits of the maximum, >= 0)
   unsigned long long *dep_sum;   // 2 words: 128-bit sum of the batch's tallies
-  uint32_t *tile_count;          // n_tiles
+  uint32_t *tile_count;          // n_tiles: entries with energy (zero before the passes)
+  uint32_t *tile_keep;           // n_tiles: entries kept (zero before the passes)
   unsigned long long *tile_off;  // n_tiles: exclusive offsets within their chunk of kTile tiles
   unsigned long long *chunk_off; // n_chunks + 1: exclusive chunk offsets, last = batch total
   long long nnz_base;            // CSR entries before this batch

@@ -294,6 +294,7 @@ __global__ void fill_u64_kernel(unsigned long long *p, long long n, unsigned lon
 // of the box tallies are coalesced and the entries of a wave are consecutive.
 // ---------------------------------------------------------------------------
 constexpr int kInfBlock = 256;
+constexpr int kTilesPerBlock = 8;  // consecutive tiles per block: one owner search per block
 static_assert(kTile == 4 * kInfBlock, "tile = 4 entries per thread");
 
 __device__ __forceinline__ int tile_owner(const long long *tile_first, int n_spots, long long t) {
@@ -307,22 +308,30 @@ __device__ __forceinline__ int tile_owner(const long long *tile_first, int n_spo
 
 struct InfEntry {
   long long T;   // box tally, 2^-32 MeV
-  double rho;    // density (0 outside the external mask)
-  int32_t v;     // voxel of the phase grid
+  double rho;    // density (0 outside the external mask); set only when T > 0
+  int32_t v;     // voxel of the phase grid; set only when T > 0
 };
 
-__device__ __forceinline__ InfEntry inf_entry(const InfluenceLaunch &a, const BoxDev &bx, long long e) {
+// Box entry e (< 2^31: a box is never larger than its grid) of spot box bx;
+// the voxel and its density are looked up only for entries with energy, the
+// ~90 % of empty entries cost one coalesced load.
+__device__ __forceinline__ InfEntry inf_entry(const InfluenceLaunch &a, const BoxDev &bx,
+                                              const long long *tb, int32_t e) {
   InfEntry r;
-  const int32_t n0 = bx.n[0], n1 = bx.n[1];
-  const long long yz = e / n0;
-  const int32_t x = (int32_t)(e - yz * n0);
-  const int32_t z = (int32_t)(yz / n1);
-  const int32_t y = (int32_t)(yz - (long long)z * n1);
-  r.v = (bx.lo[0] + x) + a.nx * ((bx.lo[1] + y) + a.ny * (bx.lo[2] + z));
-  r.T = a.box_tally[bx.offset - a.box_bias + e];
-  const double2 *lut = static_cast<const double2 *>(a.lut64);
-  r.rho = lut[clamp_hu<double>(a.hu[r.v])].x;
-  if (a.mask && a.mask[r.v] == 0) r.rho = 0.0;
+  r.T = tb[e];
+  r.rho = 0.0;
+  r.v = 0;
+  if (r.T > 0) {
+    const uint32_t n0 = (uint32_t)bx.n[0], n1 = (uint32_t)bx.n[1];
+    const uint32_t yz = (uint32_t)e / n0;
+    const uint32_t x = (uint32_t)e - yz * n0;
+    const uint32_t z = yz / n1;
+    const uint32_t y = yz - z * n1;
+    r.v = (bx.lo[0] + (int32_t)x) + a.nx * ((bx.lo[1] + (int32_t)y) + a.ny * (bx.lo[2] + (int32_t)z));
+    const double2 *lut = static_cast<const double2 *>(a.lut64);
+    r.rho = lut[clamp_hu<double>(a.hu[r.v])].x;
+    if (a.mask && a.mask[r.v] == 0) r.rho = 0.0;
+  }
   return r;
 }
 
@@ -335,81 +344,105 @@ __device__ __forceinline__ bool inf_keep(const InfEntry &x, double thr) {
   return x.T > 0 && x.rho > 0.0 && (double)x.T / x.rho >= thr;
 }
 
+// Owner of tile t given the owner j of an earlier tile (tile_first is
+// non-decreasing and tile_first[n_spots] = n_tiles > t).
+__device__ __forceinline__ int advance_owner(const long long *tile_first, int j, long long t) {
+  while (tile_first[j + 1] <= t) ++j;
+  return j;
+}
+
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
   return x;
 }
 
-__global__ void __launch_bounds__(kInfBlock) influence_max(InfluenceLaunch a) {
-  __shared__ double smax[kInfBlock / 64];
-  __shared__ unsigned long long ssum[2][kInfBlock / 64];
-  const long long t = blockIdx.x;
-  const int j = tile_owner(a.tile_first, a.n_spots, t);
-  const BoxDev bx = a.boxes[j];
-  const long long ne = (long long)bx.n[0] * bx.n[1] * bx.n[2];
-  const long long e0 = (t - a.tile_first[j]) * kTile;
+// Number of lanes of the wave for which `p` holds.
+__device__ __forceinline__ uint32_t wave_count(bool p) { return (uint32_t)__popcll(__ballot(p)); }
+
+// Per-thread maximum m of spot j -> the spot's maximum (atomic max on the bit
+// pattern: non-negative doubles order like their bit patterns).
+__device__ __forceinline__ void flush_spot_max(const InfluenceLaunch &a, int j, double m) {
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0 && m > 0.0)
+    __hip_atomic_fetch_max(&a.spot_max[j], (unsigned long long)__double_as_longlong(m), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Pass 1 over a run of tiles per block: per spot, the maximum of
+// tally / density; the 128-bit sum of all tallies; per tile, the number of
+// entries with energy (tile_count, zero before), so that later passes skip
+// empty tiles.  Running values stay in registers: the block issues one max
+// atomic per spot it meets and one sum atomic per wave, and no barrier.
+__global__ void __launch_bounds__(kInfBlock) influence_max(InfluenceLaunch a, long long tiles_per_block) {
+  const long long t_begin = (long long)blockIdx.x * tiles_per_block;
+  const long long t_end = t_begin + tiles_per_block < a.n_tiles ? t_begin + tiles_per_block : a.n_tiles;
+  if (t_begin >= t_end) return;
+  int j = tile_owner(a.tile_first, a.n_spots, t_begin);
   double m = 0.0;
   unsigned long long lo32 = 0, hi32 = 0;
+  for (long long t = t_begin; t < t_end; ++t) {
+    const int jt = advance_owner(a.tile_first, j, t);
+    if (jt != j) {  // block-uniform
+      flush_spot_max(a, j, m);
+      m = 0.0;
+      j = jt;
+    }
+    const BoxDev bx = a.boxes[j];
+    const int32_t ne = bx.n[0] * bx.n[1] * bx.n[2];
+    const int32_t e0 = (int32_t)((t - a.tile_first[j]) * kTile);
+    const long long *tb = a.box_tally + (bx.offset - a.box_bias);
+    uint32_t nz = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const long long e = e0 + threadIdx.x + k * kInfBlock;
-    if (e < ne) {
-      const InfEntry x = inf_entry(a, bx, e);
-      m = fmax(m, inf_score(x));
-      const unsigned long long T = (unsigned long long)x.T;  // >= 0
-      lo32 += T & 0xffffffffull;
-      hi32 += T >> 32;
+    for (int k = 0; k < 4; ++k) {
+      const int32_t e = e0 + (int32_t)threadIdx.x + k * kInfBlock;
+      double sc = 0.0;
+      if (e < ne) {
+        const InfEntry x = inf_entry(a, bx, tb, e);
+        sc = inf_score(x);
+        const unsigned long long T = (unsigned long long)x.T;  // >= 0
+        lo32 += T & 0xffffffffull;
+        hi32 += T >> 32;
+      }
+      m = fmax(m, sc);
+      nz += wave_count(sc > 0.0);
     }
+    if ((threadIdx.x & 63) == 0 && nz)
+      __hip_atomic_fetch_add(&a.tile_count[t], nz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  m = wave_max(m);
-  lo32 = wave_sum(lo32);
+  flush_spot_max(a, j, m);
+  lo32 = wave_sum(lo32);  // < 2^32 entries of < 2^32 each per wave: no overflow
   hi32 = wave_sum(hi32);
-  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    smax[w] = m;
-    ssum[0][w] = lo32;
-    ssum[1][w] = hi32;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < kInfBlock / 64; ++i) {
-      m = fmax(m, smax[i]);
-      lo32 += ssum[0][i];
-      hi32 += ssum[1][i];
-    }
-    // non-negative doubles order like their bit patterns
-    if (m > 0.0)
-      __hip_atomic_fetch_max(&a.spot_max[j], (unsigned long long)__double_as_longlong(m),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long lo = lo32 + (hi32 << 32);
     const unsigned long long hi = (hi32 >> 32) + (lo < lo32 ? 1ull : 0ull);
     if (lo | hi) add128(a.dep_sum, lo, hi);
   }
 }
 
-__global__ void __launch_bounds__(kInfBlock) influence_count(InfluenceLaunch a) {
-  __shared__ uint32_t scount[kInfBlock / 64];
-  const long long t = blockIdx.x;
-  const int j = tile_owner(a.tile_first, a.n_spots, t);
-  const BoxDev bx = a.boxes[j];
-  const long long ne = (long long)bx.n[0] * bx.n[1] * bx.n[2];
-  const long long e0 = (t - a.tile_first[j]) * kTile;
-  const double thr = a.rel_threshold * __longlong_as_double((long long)a.spot_max[j]);
-  uint32_t c = 0;
+// Pass 2: per tile, the number of entries at or above the spot's threshold
+// (tile_keep, zero before); tiles without energy are skipped.
+__global__ void __launch_bounds__(kInfBlock) influence_count(InfluenceLaunch a, long long tiles_per_block) {
+  const long long t_begin = (long long)blockIdx.x * tiles_per_block;
+  const long long t_end = t_begin + tiles_per_block < a.n_tiles ? t_begin + tiles_per_block : a.n_tiles;
+  if (t_begin >= t_end) return;
+  int j = tile_owner(a.tile_first, a.n_spots, t_begin);
+  for (long long t = t_begin; t < t_end; ++t) {
+    if (a.tile_count[t] == 0) continue;  // block-uniform: nothing in this tile
+    j = advance_owner(a.tile_first, j, t);
+    const BoxDev bx = a.boxes[j];
+    const int32_t ne = bx.n[0] * bx.n[1] * bx.n[2];
+    const int32_t e0 = (int32_t)((t - a.tile_first[j]) * kTile);
+    const long long *tb = a.box_tally + (bx.offset - a.box_bias);
+    const double thr = a.rel_threshold * __longlong_as_double((long long)a.spot_max[j]);
+    uint32_t c = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const long long e = e0 + threadIdx.x + k * kInfBlock;
-    if (e < ne && inf_keep(inf_entry(a, bx, e), thr)) c += 1;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-  if ((threadIdx.x & 63) == 0) scount[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t s = 0;
-    for (int i = 0; i < kInfBlock / 64; ++i) s += scount[i];
-    a.tile_count[t] = s;
+    for (int k = 0; k < 4; ++k) {
+      const int32_t e = e0 + (int32_t)threadIdx.x + k * kInfBlock;
+      c += wave_count(e < ne && inf_keep(inf_entry(a, bx, tb, e), thr));
+    }
+    if ((threadIdx.x & 63) == 0 && c)
+      __hip_atomic_fetch_add(&a.tile_keep[t], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -474,43 +507,51 @@ __device__ __forceinline__ unsigned long long tile_offset(const InfluenceLaunch 
   return t < a.n_tiles ? a.chunk_off[t >> 10] + a.tile_off[t] : a.chunk_off[n_chunks];
 }
 
+// Pass 4: entries of the tile at or above the threshold, in entry order, at
+// the tile's offset.
 __global__ void __launch_bounds__(kInfBlock) influence_write(InfluenceLaunch a) {
   __shared__ uint32_t wcount[kInfBlock / 64];
-  const long long t = blockIdx.x;
-  const int j = tile_owner(a.tile_first, a.n_spots, t);
-  const BoxDev bx = a.boxes[j];
-  const long long ne = (long long)bx.n[0] * bx.n[1] * bx.n[2];
-  const long long e0 = (t - a.tile_first[j]) * kTile;
-  const double thr = a.rel_threshold * __longlong_as_double((long long)a.spot_max[j]);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  unsigned long long pos = (unsigned long long)a.nnz_base + tile_offset(a, t);
-  for (int k = 0; k < 4; ++k) {  // sub-tiles of 256 consecutive entries, in order
-    const long long e = e0 + threadIdx.x + k * kInfBlock;
-    InfEntry x = {};
-    bool keep = false;
-    if (e < ne) {
-      x = inf_entry(a, bx, e);
-      keep = inf_keep(x, thr);
+  const long long t_begin = (long long)blockIdx.x * kTilesPerBlock;
+  const long long t_end = t_begin + kTilesPerBlock < a.n_tiles ? t_begin + kTilesPerBlock : a.n_tiles;
+  int j = tile_owner(a.tile_first, a.n_spots, t_begin);
+  for (long long t = t_begin; t < t_end; ++t) {
+    if (a.tile_keep[t] == 0) continue;  // block-uniform: nothing kept in this tile
+    j = advance_owner(a.tile_first, j, t);
+    const BoxDev bx = a.boxes[j];
+    const int32_t ne = bx.n[0] * bx.n[1] * bx.n[2];
+    const int32_t e0 = (int32_t)((t - a.tile_first[j]) * kTile);
+    const long long *tb = a.box_tally + (bx.offset - a.box_bias);
+    const double thr = a.rel_threshold * __longlong_as_double((long long)a.spot_max[j]);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    unsigned long long pos = (unsigned long long)a.nnz_base + tile_offset(a, t);
+    for (int k = 0; k < 4; ++k) {  // sub-tiles of 256 consecutive entries, in order
+      const int32_t e = e0 + (int32_t)threadIdx.x + k * kInfBlock;
+      InfEntry x = {};
+      bool keep = false;
+      if (e < ne) {
+        x = inf_entry(a, bx, tb, e);
+        keep = inf_keep(x, thr);
+      }
+      const unsigned long long bal = __ballot(keep);
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      if (lane == 0) wcount[w] = (uint32_t)__popcll(bal);
+      __syncthreads();
+      uint32_t before = 0, sub = 0;
+      for (int i = 0; i < kInfBlock / 64; ++i) {
+        before += i < w ? wcount[i] : 0u;
+        sub += wcount[i];
+      }
+      if (keep) {
+        const unsigned long long p = pos + before + rank;
+        const double e_j = (double)x.T / 4294967296.0 * 1.602176634e-13;
+        const double m_kg = x.rho * a.vol_cm3 * 1e-3;
+        a.voxel[p] = x.v;
+        a.value[p] = (float)(e_j / m_kg / bx.n_hist);
+      }
+      pos += sub;
+      __syncthreads();
     }
-    const unsigned long long bal = __ballot(keep);
-    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-    if (lane == 0) wcount[w] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    uint32_t before = 0, sub = 0;
-    for (int i = 0; i < kInfBlock / 64; ++i) {
-      before += i < w ? wcount[i] : 0u;
-      sub += wcount[i];
-    }
-    if (keep) {
-      const unsigned long long p = pos + before + rank;
-      const double e_j = (double)x.T / 4294967296.0 * 1.602176634e-13;
-      const double m_kg = x.rho * a.vol_cm3 * 1e-3;
-      a.voxel[p] = x.v;
-      a.value[p] = (float)(e_j / m_kg / bx.n_hist);
-    }
-    pos += sub;
-    __syncthreads();
   }
 }
 
@@ -631,18 +672,22 @@ hipError_t launch_convert(const long long *tally, const int16_t *hu, const uint8
 hipError_t launch_influence_reduce(const InfluenceLaunch &a, hipStream_t st) {
   const long long n_chunks = (a.n_tiles + 1023) / 1024;
   if (a.n_tiles > 0) {
-    hipLaunchKernelGGL(influence_max, dim3((unsigned)a.n_tiles), dim3(kInfBlock), 0, st, a);
-    hipLaunchKernelGGL(influence_count, dim3((unsigned)a.n_tiles), dim3(kInfBlock), 0, st, a);
+    // the reduction passes in a few thousand blocks of consecutive tiles
+    const long long per = (a.n_tiles + 4095) / 4096;
+    const unsigned blocks = (unsigned)((a.n_tiles + per - 1) / per);
+    hipLaunchKernelGGL(influence_max, dim3(blocks), dim3(kInfBlock), 0, st, a, per);
+    hipLaunchKernelGGL(influence_count, dim3(blocks), dim3(kInfBlock), 0, st, a, per);
     hipLaunchKernelGGL(influence_scan_tiles, dim3((unsigned)n_chunks), dim3(1024), 0, st,
-                       (const uint32_t *)a.tile_count, a.n_tiles, a.tile_off, a.chunk_off);
+                       (const uint32_t *)a.tile_keep, a.n_tiles, a.tile_off, a.chunk_off);
   }
   hipLaunchKernelGGL(influence_scan_chunks, dim3(1), dim3(1024), 0, st, a.chunk_off, n_chunks);
   return hipGetLastError();
 }
 
 hipError_t launch_influence_write(const InfluenceLaunch &a, hipStream_t st) {
+  const unsigned blocks = (unsigned)((a.n_tiles + kTilesPerBlock - 1) / kTilesPerBlock);
   if (a.n_tiles > 0)
-    hipLaunchKernelGGL(influence_write, dim3((unsigned)a.n_tiles), dim3(kInfBlock), 0, st, a);
+    hipLaunchKernelGGL(influence_write, dim3(blocks), dim3(kInfBlock), 0, st, a);
   if (a.n_spots > 0)
     hipLaunchKernelGGL(influence_rows, dim3((unsigned)((a.n_spots + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();

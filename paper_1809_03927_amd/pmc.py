@@ -91,6 +91,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_1809_03927_amd/build.py "
                               "(or __graft_entry__.build())")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 (same
+        # SONAME as the system one libpmc links).  Loading torch first makes
+        # libpmc bind to that copy; loading libpmc first would make torch load
+        # a second runtime, which then finds no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, u32, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
         L.pmc_create.argtypes = [C.POINTER(pmc_config), C.POINTER(vp)]

@@ -32,11 +32,13 @@ tells time, so the policy is tested on the CPU with a simulated clock.
 from __future__ import annotations
 
 import argparse
+import concurrent.futures
 import dataclasses
 import hashlib
 import json
 import math
 import sys
+import threading
 import time
 from collections import OrderedDict, deque
 from typing import Callable, Dict, List, Optional
@@ -433,11 +435,38 @@ class GpuExecutor(Executor):
         self.slot_of: Dict[tuple, int] = {}
         self.free_slots = list(range(1023, -1, -1))
         self.stream = torch.cuda.current_stream()
-        # submissions go to side streams (default priority), one per slice in flight
-        self.free_streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        # submissions go round robin to side streams (default priority): with
+        # one stream, slices run back to back on the device while the host
+        # prepares the next; with two, consecutive slices may overlap
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.next_stream = 0
         self.digests: Dict[int, str] = {}
         self.balances: Dict[int, dict] = {}
         self.doses: Dict[int, np.ndarray] = {}
+        # pinned host buffers for the dose copies, by voxel count; a buffer is
+        # reused once the digest of its previous dose is taken (worker thread)
+        self.pinned: Dict[int, List] = {}
+        self.pinned_lock = threading.Lock()
+        self.hasher = concurrent.futures.ThreadPoolExecutor(max_workers=2)
+        self.pending: List = []
+
+    def close(self) -> None:
+        """Wait for the digests still being computed."""
+        for f in self.pending:
+            f.result()
+        self.pending.clear()
+        self.hasher.shutdown(wait=True)
+
+    def _host_buffer(self, nvox: int):
+        with self.pinned_lock:
+            free = self.pinned.setdefault(nvox, [])
+            if free:
+                return free.pop()
+        return self.torch.empty(nvox, dtype=self.torch.float64, pin_memory=True)
+
+    def _give_back(self, buf) -> None:
+        with self.pinned_lock:
+            self.pinned[buf.numel()].append(buf)
 
     def phantom_bytes(self, key) -> int:
         ph = self.phantoms[key]
@@ -496,38 +525,50 @@ class GpuExecutor(Executor):
         req = st["req"]
         if self.engine == pmc.PMC_ENGINE_PERSISTENT and (item_begin, item_end) != (0, job.n_items):
             req = req.slice(item_begin, item_end)
-        stream = self.free_streams.pop()
+        stream = self.streams[self.next_stream]
+        self.next_stream = (self.next_stream + 1) % len(self.streams)
         pmc.pmc_dose_device(self.ctx, req, stream.cuda_stream, [st["tally"].data_ptr()],
                             st["counters"].data_ptr())
         ev = self.torch.cuda.Event()
         ev.record(stream)
-        return ev, stream
+        return ev
 
     def wait(self, token) -> None:
-        ev, stream = token
-        ev.synchronize()
-        self.free_streams.append(stream)
+        token.synchronize()
 
     def finish(self, job: Job) -> None:
         pmc, st = self.pmc, job.state
         pmc.pmc_convert_device(self.ctx, st["slot"], st["tally"].data_ptr(), job.n_histories,
                                self.stream.cuda_stream, st["dose"].data_ptr(), None)
-        st["host_dose"] = st["dose"].cpu().numpy()  # served once the dose is on the host
+        buf = self._host_buffer(job.nvox)
+        buf.copy_(st["dose"], non_blocking=True)
+        self.stream.synchronize()  # served once the dose is on the host
+        st["host_dose"] = buf
 
     def release(self, job: Job) -> None:
-        pmc, st = self.pmc, job.state
-        if self.verify and "host_dose" in st:
+        pmc, st, torch = self.pmc, job.state, self.torch
+        buf = st.get("host_dose")
+        if self.verify and buf is not None:
             t = st["tally"]
-            dep = (int((t >> 32).sum().item()) << 32) + int((t & 0xFFFFFFFF).sum().item())
-            b = pmc.pmc_balance_from_counters(self.ctx, st["req"], st["counters"].cpu().numpy(), dep)
+            words = torch.cat([torch.stack(((t >> 32).sum(), (t & 0xFFFFFFFF).sum())),
+                               st["counters"]]).cpu().numpy()
+            dep = (int(words[0]) << 32) + int(words[1])
+            b = pmc.pmc_balance_from_counters(self.ctx, st["req"], words[2:], dep)
             if b["deposited"] + b["escaped"] + b["nuclear"] != b["incident"]:
                 raise RuntimeError(f"request {job.index}: energy balance broken {b}")
             if b["histories"] != job.n_histories:
                 raise RuntimeError(f"request {job.index}: {b['histories']} histories run")
             self.balances[job.index] = b
-            self.digests[job.index] = hashlib.sha256(st["host_dose"].tobytes()).hexdigest()
             if self.keep_doses:
-                self.doses[job.index] = st["host_dose"]
+                self.doses[job.index] = buf.numpy().copy()
+
+            def digest(index=job.index, buf=buf):
+                self.digests[index] = hashlib.sha256(buf.numpy().data).hexdigest()
+                self._give_back(buf)
+
+            self.pending.append(self.hasher.submit(digest))
+        elif buf is not None:
+            self._give_back(buf)
         pmc.pmc_unload_plan(self.ctx, st["plan_id"])
         st.clear()
 
@@ -573,48 +614,51 @@ def log_uniform_mean(lo: float, hi: float) -> float:
 
 def serve_gpu(ctx, reqs, phantoms, plans, engine: int, policy: str, budget: int,
               launch: Optional[dict] = None, slice_histories: int = 4_000_000, log=None,
-              keep_doses: bool = False, depth: int = 1, rate_hist_per_s: float = 1.3e8):
+              keep_doses: bool = False, depth: int = 1, rate_hist_per_s: float = 1.3e8,
+              n_streams: int = 1):
     """Serve `reqs` on the GPU in real time; returns (summary, executor, scheduler)."""
-    ex = GpuExecutor(ctx, phantoms, plans, engine, launch, keep_doses=keep_doses, n_streams=depth)
+    ex = GpuExecutor(ctx, phantoms, plans, engine, launch, keep_doses=keep_doses, n_streams=n_streams)
     sched = Scheduler(ex, WallClock(), budget, policy=policy, slice_histories=slice_histories,
                       log=log, depth=depth, rate_hist_per_s=rate_hist_per_s)
     done = sched.run(jobs_of(reqs, phantoms))
+    ex.close()
     s = summarize(done, policy)
     s.update(slices=sched.slices, evictions=sched.evictions, phantom_loads=sched.phantom_loads,
-             peak_bytes=sched.peak_used, budget_bytes=budget, slices_in_flight=depth)
+             peak_bytes=sched.peak_used, budget_bytes=budget, slices_in_flight=depth,
+             streams=n_streams, slice_histories=slice_histories)
     return s, ex, sched
 
 
-def calibrate_plain(ctx, seed: int, h_lo: float, h_hi: float, log=None) -> float:
-    """Plain-engine throughput (histories/s) on a calibration set of served
-    requests drawn with another seed."""
-    import torch
+def calibrate_plain(ctx, seed: int, h_lo: float, h_hi: float, log=None, n: int = 12) -> float:
+    """Service rate (histories/s) of the plain engine on a calibration set of
+    served requests drawn with another seed: each request loaded, run, its
+    dose copied to the host and everything freed, one after the other."""
     from . import pmc
-    reqs = W.served_stream(6, rate_hz=1.0, seed=seed + 1000, h_lo=h_lo, h_hi=h_hi)
+    reqs = W.served_stream(n + 1, rate_hz=1.0, seed=seed + 1000, h_lo=h_lo, h_hi=h_hi)
     phantoms, plans = build_stream(reqs)
     ex = GpuExecutor(ctx, phantoms, plans, pmc.PMC_ENGINE_PLAIN, verify=False)
     total_h, total_t = 0, 0.0
-    for j in jobs_of(reqs, phantoms):
+    for k, j in enumerate(jobs_of(reqs, phantoms)):
+        t0 = time.perf_counter()
         ex.load_phantom(j.phantom_key)
         ex.start(j, sliced=False)
-        ex.run(j, 0, 1)  # the first run also prepares the request data
-        j.state["tally"].zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         ex.run(j, 0, 1)
-        total_t += time.perf_counter() - t0
-        total_h += j.n_histories
+        ex.finish(j)
         ex.release(j)
         ex.unload_phantom(j.phantom_key)
+        if k:  # the first request warms up the engine
+            total_t += time.perf_counter() - t0
+            total_h += j.n_histories
+    ex.close()
     rate = total_h / total_t
     if log:
-        log(f"plain throughput on the calibration set: {rate:.3g} histories/s")
+        log(f"plain service rate on the calibration set: {rate:.3g} histories/s")
     return rate
 
 
 def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_hi=5e7,
                  slice_histories=4_000_000, launch=None, workers=0, log=None, depth=2,
-                 policy="slowdown"):
+                 policy="slowdown", plain=True, n_streams=1):
     """Serve one Poisson stream with the sliced persistent engine (`policy`,
     `depth` slices in flight) and with the plain engine run serially in
     arrival order.  Arrival rate = load x plain throughput / mean request
@@ -634,11 +678,13 @@ def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_h
         out = {"requests": n_requests, "load": load, "arrival_rate_hz": lam,
                "plain_calibration_hist_per_s": rate_plain, "budget_bytes": budget}
         execs = {}
-        for label, engine, pol, d in (
-                ("batched", pmc.PMC_ENGINE_PERSISTENT, policy, depth),
-                ("plain-serial", pmc.PMC_ENGINE_PLAIN, "fifo", 1)):
+        engines = [("batched", pmc.PMC_ENGINE_PERSISTENT, policy, depth)]
+        if plain:
+            engines.append(("plain-serial", pmc.PMC_ENGINE_PLAIN, "fifo", 1))
+        for label, engine, pol, d in engines:
             s, ex, _ = serve_gpu(ctx, reqs, phantoms, plans, engine, pol, budget, launch,
-                                 slice_histories, log, depth=d, rate_hist_per_s=rate_plain)
+                                 slice_histories, log, depth=d, rate_hist_per_s=rate_plain,
+                                 n_streams=n_streams if engine == pmc.PMC_ENGINE_PERSISTENT else 1)
             for key in list(ex.slot_of):
                 ex.unload_phantom(key)
             out[label] = s
@@ -646,8 +692,9 @@ def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_h
             if log:
                 log(f"{label}: p50 {s['p50_latency_s'] * 1e3:.1f} ms, p99 "
                     f"{s['p99_latency_s'] * 1e3:.1f} ms, {s['throughput_hist_per_s']:.3g} histories/s")
-        a, b = execs["batched"].digests, execs["plain-serial"].digests
-        out["identical_doses"] = int(sum(a[k] == b.get(k) for k in a))
+        if plain:
+            a, b = execs["batched"].digests, execs["plain-serial"].digests
+            out["identical_doses"] = int(sum(a[k] == b.get(k) for k in a))
         return out
     finally:
         pmc.pmc_destroy(ctx)
@@ -661,12 +708,16 @@ def main():
     p.add_argument("--seed", type=int, default=4)
     p.add_argument("--slice-histories", type=int, default=4_000_000)
     p.add_argument("--workers", type=int, default=8)
-    p.add_argument("--depth", type=int, default=2, help="slices in flight (streams)")
+    p.add_argument("--depth", type=int, default=2, help="slices in flight")
+    p.add_argument("--streams", type=int, default=1, help="submission streams")
     p.add_argument("--policy", choices=["slowdown", "srpt"], default="slowdown")
+    p.add_argument("--no-plain", action="store_true", help="skip the plain-serial comparison")
+    p.add_argument("--block", type=int, default=0, help="persistent-engine block size (0 = library default)")
     a = p.parse_args()
     res = run_scenario(a.requests, a.load, a.seed, int(a.budget_gb * 2**30),
                        slice_histories=a.slice_histories, workers=a.workers, depth=a.depth,
-                       policy=a.policy,
+                       policy=a.policy, plain=not a.no_plain, n_streams=a.streams,
+                       launch={"block_size": a.block} if a.block else None,
                        log=lambda m: print("[serve]", m, file=sys.stderr, flush=True))
     print(json.dumps(res))
 

@@ -32,7 +32,7 @@ def header_functions():
 def test_library_exports_every_header_symbol(P):
     names = header_functions()
     assert len(names) >= 19
-    lib = C.CDLL(P.LIB_PATH)
+    lib = P.lib()  # loads the HIP runtime the way the binding does
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(P.EXPORTS) == names
@@ -154,3 +154,16 @@ def test_product_path_does_not_import_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "pmc_oracle" not in txt and "liboracle" not in txt, f
+
+
+def test_one_hip_runtime_in_the_process(P):
+    """libpmc and PyTorch share one HIP runtime (two copies in one process
+    leave the second without a device)."""
+    P.lib()
+    import torch  # noqa: F401
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64" in line:
+                paths.add(line.split()[-1])
+    assert len(paths) == 1, paths

@@ -134,15 +134,15 @@ def test_served_equals_plain_serial():
         tight = probe.job_bytes(j3) + probe.phantom_bytes(j3.phantom_key) + 2**20
         assert sum(probe.phantom_bytes(r.phantom_key) for r in reqs[:3]) > 2**20
         out = {}
-        for label, engine, policy, budget, depth in (
-                ("slowdown", pmc.PMC_ENGINE_PERSISTENT, "slowdown", 2 * 2**30, 2),
-                ("srpt-tight", pmc.PMC_ENGINE_PERSISTENT, "srpt", tight, 2),
-                ("srpt-depth1", pmc.PMC_ENGINE_PERSISTENT, "srpt", 2 * 2**30, 1),
-                ("plain", pmc.PMC_ENGINE_PLAIN, "fifo", 2 * 2**30, 1)):
+        for label, engine, policy, budget, depth, streams in (
+                ("slowdown", pmc.PMC_ENGINE_PERSISTENT, "slowdown", 2 * 2**30, 2, 1),
+                ("srpt-tight", pmc.PMC_ENGINE_PERSISTENT, "srpt", tight, 2, 2),
+                ("srpt-depth1", pmc.PMC_ENGINE_PERSISTENT, "srpt", 2 * 2**30, 1, 1),
+                ("plain", pmc.PMC_ENGINE_PLAIN, "fifo", 2 * 2**30, 1, 1)):
             say("serve", label)
             s, ex, sched = S.serve_gpu(ctx, reqs, phantoms, plans, engine, policy, budget,
                                        launch={"chunk": 64}, slice_histories=50_000, keep_doses=True,
-                                       depth=depth)
+                                       depth=depth, n_streams=streams)
             assert s["requests"] == len(reqs)
             assert sched.peak_used <= budget
             if label == "slowdown":
@@ -163,3 +163,18 @@ def test_served_equals_plain_serial():
         torch.cuda.synchronize()
     finally:
         pmc.pmc_destroy(ctx)
+
+
+def test_robust_workload_small():
+    """The robust-optimisation driver on a small grid: 9 scenarios x 2 phases
+    served batched and plain give identical doses; influence matrices of the
+    nominal scenario balance their energy."""
+    from paper_1809_03927_amd import robust
+    say("robust small")
+    res = robust.run(n_histories=100_000, shape_xyz=(64, 64, 40), n_phases=2)
+    assert res["calculations"] == 18
+    assert res["batched"]["requests"] == res["plain-serial"]["requests"] == 18
+    assert res["identical_doses"] == 18
+    inf = res["influence"]
+    assert len(inf["phases"]) == 2 and all(x["nnz"] > 0 for x in inf["phases"])
+    assert all(x["outside_fraction"] < 0.05 for x in inf["phases"])
