@@ -12,6 +12,12 @@ HIP graph and replayed.  Plain engine (reported beside it): one launch per
 phase, one history per thread, no refill, no graph.  Both give identical
 integer tallies (checked).
 
+Latency (reported beside it): a Poisson stream of single-phase dose requests
+of mixed grid and history counts served by the serving loop (persistent
+engine, slices, least-slowdown order) and, on the same requests, by the
+plain engine serially in arrival order; p50/p99 of arrival -> dose on the
+host, and identical doses per request (checked).
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -41,7 +47,7 @@ VALU_PER_STEP = 448.0
 # calibration (profiles/transport_thorax4d_counters.md).  Valid only for the
 # kernel sources they were measured on (hash below); otherwise reported null.
 PROFILED_TRAFFIC_BYTES = 282.3e9
-PROFILED_KERNEL_HASH = "633caf8f6a1719c7"
+PROFILED_KERNEL_HASH = "10b1a0af1734c8cb"
 
 
 def log(*a):
@@ -63,6 +69,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-atomic-probe", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--latency-requests", type=int, default=200,
+                   help="served-stream requests for the p50/p99 latency comparison (0 = skip)")
+    p.add_argument("--latency-load", type=float, default=0.8)
     p.add_argument("--mode", choices=["bench", "single-history", "copy-calibration"], default="bench")
     return p.parse_args()
 
@@ -75,8 +84,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_1809_03927_amd import autotune, pmc
+    from paper_1809_03927_amd import autotune, pmc, serve
     from paper_1809_03927_amd import workloads as W
+
+    served = None
+    if a.mode == "bench" and a.latency_requests > 0:
+        # phantoms of the served stream, generated in forked processes before
+        # this process touches the GPU
+        t0 = time.time()
+        served = serve.prebuild(a.latency_requests, workers=8)
+        log(f"served stream: {a.latency_requests} requests generated in {time.time() - t0:.1f} s")
 
     if a.mode == "copy-calibration":
         # plain device-to-device copies of 4 GiB (far larger than the 256 MB
@@ -235,9 +252,33 @@ def main():
         "atomic_probe_per_s": atomic_peak,
         "atomic_frac": (bal["atomics"] / (kern_ms * 1e-3) / atomic_peak) if atomic_peak else None,
     }
+    if graph is not None:
+        pmc.pmc_graph_destroy(graph)
+        graph = True
+    eng.close()
+    latency = None
+    if served is not None:
+        log(f"served stream: {a.latency_requests} requests at load {a.latency_load}")
+        res = serve.run_scenario(a.latency_requests, a.latency_load, prebuilt=served,
+                                 log=lambda m: log("serve:", m))
+        keys = ("p50_latency_s", "p99_latency_s", "mean_latency_s", "max_latency_s",
+                "throughput_hist_per_s", "makespan_s", "slices")
+        latency = {
+            "workload": f"served stream: {a.latency_requests} single-phase thorax requests, grids 64^3 to "
+                        f"256x256x160, 50-3000 spots, 1e5-5e7 histories (log-uniform), Poisson "
+                        f"arrivals at {a.latency_load} x the plain engine's service rate",
+            "arrival_rate_hz": res["arrival_rate_hz"],
+            "batched": {k: res["batched"][k] for k in keys},
+            "plain_serial": {k: res["plain-serial"][k] for k in keys},
+            "identical_doses": res["identical_doses"], "requests": a.latency_requests,
+        }
+        log(f"latency p50/p99: batched {latency['batched']['p50_latency_s'] * 1e3:.0f}/"
+            f"{latency['batched']['p99_latency_s'] * 1e3:.0f} ms, plain "
+            f"{latency['plain_serial']['p50_latency_s'] * 1e3:.0f}/"
+            f"{latency['plain_serial']['p99_latency_s'] * 1e3:.0f} ms")
     cpu = None if a.no_cpu_baseline else cpu_baseline(wl, a.cpu_seconds)
     out = {
-        "metric": "proton histories/s (batched 4D dose: 10 phases in one persistent launch, graph replay)",
+        "metric": "proton histories/s; p50/p99 dose-request latency, batched vs plain, 1 MI355X",
         "value": wl.n_histories / sec_b, "unit": "histories/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": sec_b * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 transport, int64 tally",
@@ -248,13 +289,11 @@ def main():
                    "histories": wl.n_histories, "steps_per_history": bal["steps"] / wl.n_histories,
                    "launch": tuned, "graph": graph is not None},
         "plain": plain,
+        "latency": latency,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
-    if graph is not None:
-        pmc.pmc_graph_destroy(graph)
-    eng.close()
 
 
 def kernel_hash():

@@ -57,6 +57,7 @@ struct PhaseRec {
   int16_t *d_hu = nullptr;
   uint8_t *d_mask = nullptr;
   void *d_lut32 = nullptr, *d_lut64 = nullptr;
+  size_t cap_hu = 0, cap_mask = 0, cap_lut32 = 0, cap_lut64 = 0;  // pool block sizes
   size_t bytes = 0;
   UseEvents uses;
   std::vector<int16_t> hu_host;     // host copies for geometry queries (influence boxes)
@@ -126,6 +127,10 @@ struct pmc_context {
   std::map<int32_t, PlanRec> plans;
   uint64_t plan_counter = 0;
   hipStream_t stream = nullptr;
+  // Freed device blocks kept for reuse, by (rounded) size: hipFree waits for
+  // the whole device, which would stall work running on other streams.
+  // Pooled blocks count as used; they are freed when the budget needs room.
+  std::multimap<size_t, void *> pool;
   // Work enqueued on callers' streams: one event per stream, recorded after
   // the stream's latest enqueue; all are waited for before device memory
   // that such work may read is freed or overwritten.
@@ -189,33 +194,80 @@ double calib_at(const double *x, const double *y, int n, double hu) {
 
 void wait_pending(pmc_context *ctx);
 
-// grow-only device buffer with budget accounting
-int ensure(pmc_context *ctx, DevBuf &b, size_t bytes, const char *what) {
-  if (b.cap >= bytes) return PMC_OK;
-  const size_t cap = std::max(bytes, b.cap + b.cap / 2);
-  if (ctx->used - b.cap + cap > ctx->budget)
-    return fail(ctx, PMC_E_BUDGET, "%s: %zu bytes exceed the device-memory budget (%llu in use of %llu)",
-                what, cap, (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
-  if (b.p) {
-    wait_pending(ctx);
-    (void)hipFree(b.p);
-    ctx->used -= b.cap;
-    b.p = nullptr;
-    b.cap = 0;
+// Sizes handed out by the pool: powers of two up to 1 MiB, then multiples
+// of 2 MiB, so that freed blocks fit later requests of similar size.
+size_t pool_round(size_t n) {
+  if (n <= (size_t(1) << 20)) {
+    size_t p = 256;
+    while (p < n) p <<= 1;
+    return p;
   }
-  HIP_TRY(ctx, hipMalloc(&b.p, cap), what);
-  b.cap = cap;
-  ctx->used += cap;
+  const size_t g = size_t(2) << 20;
+  return (n + g - 1) / g * g;
+}
+
+// Free every pooled block (hipFree: waits for the device).
+void trim_pool(pmc_context *ctx) {
+  for (auto &kv : ctx->pool) {
+    (void)hipFree(kv.second);
+    ctx->used -= kv.first;
+  }
+  ctx->pool.clear();
+}
+
+// A device block of at least n bytes (*cap = its size): a pooled block of
+// the same rounded size, or a new one within the budget.
+int pool_get(pmc_context *ctx, size_t n, void **out, size_t *cap, const char *what) {
+  const size_t r = pool_round(std::max<size_t>(n, 1));
+  auto it = ctx->pool.find(r);
+  if (it != ctx->pool.end()) {
+    *out = it->second;
+    *cap = r;
+    ctx->pool.erase(it);
+    return PMC_OK;
+  }
+  if (ctx->used + r > ctx->budget) trim_pool(ctx);
+  if (ctx->used + r > ctx->budget)
+    return fail(ctx, PMC_E_BUDGET, "%s: %zu bytes exceed the device-memory budget (%llu in use of %llu)",
+                what, r, (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
+  void *p = nullptr;
+  HIP_TRY(ctx, hipMalloc(&p, r), what);
+  ctx->used += r;
+  *out = p;
+  *cap = r;
   return PMC_OK;
 }
 
-void release(pmc_context *ctx, DevBuf &b) {
+// Return a block to the pool.  No enqueued work may still use it.
+void pool_put(pmc_context *ctx, void *p, size_t cap) {
+  if (p) ctx->pool.emplace(cap, p);
+}
+
+// grow-only device buffer with budget accounting
+int ensure(pmc_context *ctx, DevBuf &b, size_t bytes, const char *what) {
+  if (b.cap >= bytes) return PMC_OK;
   if (b.p) {
-    (void)hipFree(b.p);
-    ctx->used -= b.cap;
+    wait_pending(ctx);  // context buffers may be read by enqueued work
+    pool_put(ctx, b.p, b.cap);
+    b.p = nullptr;
+    b.cap = 0;
   }
+  return pool_get(ctx, std::max(bytes, b.cap + b.cap / 2), &b.p, &b.cap, what);
+}
+
+// Give a buffer back to the pool; the caller has waited for its users.
+void release(pmc_context *ctx, DevBuf &b) {
+  pool_put(ctx, b.p, b.cap);
   b.p = nullptr;
   b.cap = 0;
+}
+
+// Copy through the context's own stream (non-blocking with respect to every
+// other stream, unlike a synchronous copy on the null stream) and wait.
+hipError_t copy_sync(pmc_context *ctx, void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, ctx->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(ctx->stream);
 }
 
 int note_use(pmc_context *ctx, UseEvents &u, hipStream_t st) {
@@ -243,11 +295,10 @@ void drop_use(UseEvents &u) {
 void free_phase(pmc_context *ctx, PhaseRec &p) {
   wait_use(p.uses);
   drop_use(p.uses);
-  if (p.d_hu) (void)hipFree(p.d_hu);
-  if (p.d_mask) (void)hipFree(p.d_mask);
-  if (p.d_lut32) (void)hipFree(p.d_lut32);
-  if (p.d_lut64) (void)hipFree(p.d_lut64);
-  ctx->used -= p.bytes;
+  pool_put(ctx, p.d_hu, p.cap_hu);
+  pool_put(ctx, p.d_mask, p.cap_mask);
+  pool_put(ctx, p.d_lut32, p.cap_lut32);
+  pool_put(ctx, p.d_lut64, p.cap_lut64);
   p.d_hu = nullptr;
   p.d_mask = nullptr;
   p.d_lut32 = p.d_lut64 = nullptr;
@@ -509,7 +560,7 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
     evict_lru(ctx);
   rc = ensure(ctx, P.buf, std::max<size_t>(off, 256), "request data");
   if (rc) return rc;
-  HIP_TRY(ctx, hipMemcpy(P.buf.p, P.staging.data(), off, hipMemcpyHostToDevice),
+  HIP_TRY(ctx, copy_sync(ctx, P.buf.p, P.staging.data(), off, hipMemcpyHostToDevice),
           "upload request data");
   P.bytes = off;
   P.plan_id = req->plan;
@@ -582,7 +633,7 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
       if (!same) {
         wait_use(P.uses);  // earlier launches of this request read the table
         P.targets = tg;
-        HIP_TRY(ctx, hipMemcpy(scratch_at(P.off_targets), P.targets.data(),
+        HIP_TRY(ctx, copy_sync(ctx, scratch_at(P.off_targets), P.targets.data(),
                                sizeof(TargetDev) * P.targets.size(), hipMemcpyHostToDevice),
                 "upload targets");
       }
@@ -808,6 +859,7 @@ void pmc_destroy(pmc_context *ctx) {
     for (hipEvent_t ev : ctx->cursor_done)
       if (ev) (void)hipEventDestroy(ev);
     for (auto &kv : ctx->stream_done) (void)hipEventDestroy(kv.second);
+    trim_pool(ctx);
     if (ctx->d_tab) (void)hipFree(ctx->d_tab);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   }
@@ -872,41 +924,28 @@ int pmc_load_phase(pmc_context *ctx, int32_t phase, const int16_t *hu, int32_t n
     ctx->phases[phase] = std::move(rec);
     return PMC_OK;
   }
-  const size_t bytes = (size_t)nvox * 2 + (rec.has_mask ? (size_t)nvox : 0) +
-                       rec.lut32.size() * sizeof(float) + rec.lut64.size() * sizeof(double);
-  const size_t old = ctx->phases.count(phase) ? ctx->phases[phase].bytes : 0;
-  if (ctx->used - old + bytes > ctx->budget)
-    return fail(ctx, PMC_E_BUDGET, "phase %d needs %zu bytes: over the device-memory budget", phase, bytes);
   HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-  auto cleanup = [&](hipError_t e, const char *what) {
+  auto cleanup = [&](int rc) {
     free_phase(ctx, rec);
-    return hip_fail(ctx, e, what);
+    return rc;
   };
-  hipError_t e;
-  if ((e = hipMalloc((void **)&rec.d_hu, (size_t)nvox * 2)) != hipSuccess) return cleanup(e, "hipMalloc hu");
-  rec.bytes += (size_t)nvox * 2;
-  ctx->used += (size_t)nvox * 2;
-  if (rec.has_mask) {
-    if ((e = hipMalloc((void **)&rec.d_mask, (size_t)nvox)) != hipSuccess) return cleanup(e, "hipMalloc mask");
-    rec.bytes += (size_t)nvox;
-    ctx->used += (size_t)nvox;
-  }
   const size_t l32 = rec.lut32.size() * sizeof(float), l64 = rec.lut64.size() * sizeof(double);
-  if ((e = hipMalloc(&rec.d_lut32, l32)) != hipSuccess) return cleanup(e, "hipMalloc lut");
-  rec.bytes += l32;
-  ctx->used += l32;
-  if ((e = hipMalloc(&rec.d_lut64, l64)) != hipSuccess) return cleanup(e, "hipMalloc lut");
-  rec.bytes += l64;
-  ctx->used += l64;
-  if ((e = hipMemcpy(rec.d_hu, hu, (size_t)nvox * 2, hipMemcpyHostToDevice)) != hipSuccess)
-    return cleanup(e, "upload hu");
+  int rc = pool_get(ctx, (size_t)nvox * 2, (void **)&rec.d_hu, &rec.cap_hu, "phase HU grid");
+  if (!rc && rec.has_mask) rc = pool_get(ctx, (size_t)nvox, (void **)&rec.d_mask, &rec.cap_mask, "phase mask");
+  if (!rc) rc = pool_get(ctx, l32, &rec.d_lut32, &rec.cap_lut32, "phase LUT");
+  if (!rc) rc = pool_get(ctx, l64, &rec.d_lut64, &rec.cap_lut64, "phase LUT");
+  if (rc) return cleanup(rc);
+  rec.bytes = rec.cap_hu + rec.cap_mask + rec.cap_lut32 + rec.cap_lut64;
+  hipError_t e;
+  if ((e = copy_sync(ctx, rec.d_hu, hu, (size_t)nvox * 2, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(ctx, e, "upload hu"));
   if (rec.has_mask &&
-      (e = hipMemcpy(rec.d_mask, external_mask, (size_t)nvox, hipMemcpyHostToDevice)) != hipSuccess)
-    return cleanup(e, "upload mask");
-  if ((e = hipMemcpy(rec.d_lut32, rec.lut32.data(), l32, hipMemcpyHostToDevice)) != hipSuccess)
-    return cleanup(e, "upload lut");
-  if ((e = hipMemcpy(rec.d_lut64, rec.lut64.data(), l64, hipMemcpyHostToDevice)) != hipSuccess)
-    return cleanup(e, "upload lut");
+      (e = copy_sync(ctx, rec.d_mask, external_mask, (size_t)nvox, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(ctx, e, "upload mask"));
+  if ((e = copy_sync(ctx, rec.d_lut32, rec.lut32.data(), l32, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(ctx, e, "upload lut"));
+  if ((e = copy_sync(ctx, rec.d_lut64, rec.lut64.data(), l64, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(ctx, e, "upload lut"));
   auto it = ctx->phases.find(phase);
   if (it != ctx->phases.end()) {
     free_phase(ctx, it->second);
@@ -1083,26 +1122,20 @@ int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
     max_vox = std::max(max_vox, (size_t)nv);
   }
   const size_t conv_bytes = max_vox * 8 * 2;
-  if (ctx->used + tally_bytes + conv_bytes > ctx->budget)
-    return fail(ctx, PMC_E_BUDGET, "tallies need %zu bytes: over the device-memory budget",
-                tally_bytes + conv_bytes);
-  void *d_t = nullptr, *d_conv = nullptr;
-  HIP_TRY(ctx, hipMalloc(&d_t, tally_bytes), "hipMalloc tallies");
-  ctx->used += tally_bytes;
-  struct Guard {
+  struct Guard {  // per-call buffers go back to the pool once the call's work is done
     pmc_context *c;
-    void *a, *b;
-    size_t na, nb;
+    DevBuf a, b;
     ~Guard() {
       wait_pending(c);
-      if (a) { (void)hipFree(a); c->used -= na; }
-      if (b) { (void)hipFree(b); c->used -= nb; }
+      release(c, a);
+      release(c, b);
     }
-  } guard{ctx, d_t, nullptr, tally_bytes, 0};
-  HIP_TRY(ctx, hipMalloc(&d_conv, conv_bytes), "hipMalloc dose buffer");
-  guard.b = d_conv;
-  guard.nb = conv_bytes;
-  ctx->used += conv_bytes;
+  } guard{ctx, {}, {}};
+  rc = pool_get(ctx, tally_bytes, &guard.a.p, &guard.a.cap, "tallies");
+  if (rc) return rc;
+  rc = pool_get(ctx, conv_bytes, &guard.b.p, &guard.b.cap, "dose buffer");
+  if (rc) return rc;
+  void *d_t = guard.a.p, *d_conv = guard.b.p;
   hipStream_t st = ctx->stream;
   HIP_TRY(ctx, hipMemsetAsync(d_t, 0, tally_bytes, st), "zero tallies");
   std::vector<int64_t *> tp(n);
@@ -1147,7 +1180,7 @@ int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
   }
   if (balance_out) {
     uint64_t c[PMC_COUNTERS];
-    HIP_TRY(ctx, hipMemcpy(c, ctx->counters.p, sizeof c, hipMemcpyDeviceToHost), "copy counters");
+    HIP_TRY(ctx, copy_sync(ctx, c, ctx->counters.p, sizeof c, hipMemcpyDeviceToHost), "copy counters");
     unsigned __int128 inc = 0;
     rc = incident_of(ctx, req, &inc);
     if (rc) return rc;
@@ -1206,9 +1239,9 @@ int pmc_trace(pmc_context *ctx, int32_t plan, int32_t phase, int64_t spot, uint3
   HIP_TRY(ctx, pmc::launch_trace(a, fp64, ctx->stream), "trace launch");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "trace kernel");
   int32_t n = 0;
-  HIP_TRY(ctx, hipMemcpy(&n, d_n, sizeof n, hipMemcpyDeviceToHost), "copy trace length");
+  HIP_TRY(ctx, copy_sync(ctx, &n, d_n, sizeof n, hipMemcpyDeviceToHost), "copy trace length");
   const int32_t m = std::min(n, max_rec);
-  HIP_TRY(ctx, hipMemcpy(out, d_rec, sizeof(pmc_trace_rec) * (size_t)m, hipMemcpyDeviceToHost), "copy trace");
+  HIP_TRY(ctx, copy_sync(ctx, out, d_rec, sizeof(pmc_trace_rec) * (size_t)m, hipMemcpyDeviceToHost), "copy trace");
   *n_rec = n;
   return PMC_OK;
 }
@@ -1274,7 +1307,7 @@ int pmc_graph_create(pmc_context *ctx, const pmc_request *req, int64_t *const *d
     tg[i] = make_target(ctx->phases[req->phases[i]], reinterpret_cast<unsigned long long *>(dev_tally[i]),
                         P.same_lut ? 0 : i);
   std::memcpy(image.data() + P.off_targets, tg.data(), sizeof(TargetDev) * tg.size());
-  if ((e = hipMemcpy(base, image.data(), P.bytes, hipMemcpyHostToDevice)) != hipSuccess)
+  if ((e = copy_sync(ctx, base, image.data(), P.bytes, hipMemcpyHostToDevice)) != hipSuccess)
     return bail(e, "upload graph data");
   hipStream_t st = ctx->stream;
   if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess)
@@ -1592,7 +1625,7 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
   auto *scratch = static_cast<unsigned long long *>(ctx->box_scratch.p);
   auto *counters = static_cast<unsigned long long *>(ctx->counters.p);
   hipStream_t st = ctx->stream;
-  HIP_TRY(ctx, hipMemcpy(d_boxes, bd.data(), sizeof(pmc::BoxDev) * bd.size(), hipMemcpyHostToDevice),
+  HIP_TRY(ctx, copy_sync(ctx, d_boxes, bd.data(), sizeof(pmc::BoxDev) * bd.size(), hipMemcpyHostToDevice),
           "upload boxes");
   HIP_TRY(ctx, pmc::launch_fill_u64(counters, PMC_COUNTERS, 0ull, st), "counter reset");
   unsigned __int128 deposited = 0;
@@ -1733,13 +1766,13 @@ int pmc_influence_read(pmc_context *ctx, int64_t *row_ptr, int32_t *voxel, float
   ctx->err.clear();
   if (ctx->inf_n_rows < 0) return fail(ctx, PMC_E_STATE, "no influence matrix has been computed");
   if (row_ptr)
-    HIP_TRY(ctx, hipMemcpy(row_ptr, ctx->inf_rows.p, sizeof(int64_t) * (size_t)(ctx->inf_n_rows + 1),
+    HIP_TRY(ctx, copy_sync(ctx, row_ptr, ctx->inf_rows.p, sizeof(int64_t) * (size_t)(ctx->inf_n_rows + 1),
                            hipMemcpyDeviceToHost), "copy rows");
   if (voxel && ctx->inf_nnz)
-    HIP_TRY(ctx, hipMemcpy(voxel, ctx->inf_voxel.p, sizeof(int32_t) * ctx->inf_nnz, hipMemcpyDeviceToHost),
+    HIP_TRY(ctx, copy_sync(ctx, voxel, ctx->inf_voxel.p, sizeof(int32_t) * ctx->inf_nnz, hipMemcpyDeviceToHost),
             "copy voxels");
   if (value && ctx->inf_nnz)
-    HIP_TRY(ctx, hipMemcpy(value, ctx->inf_value.p, sizeof(float) * ctx->inf_nnz, hipMemcpyDeviceToHost),
+    HIP_TRY(ctx, copy_sync(ctx, value, ctx->inf_value.p, sizeof(float) * ctx->inf_nnz, hipMemcpyDeviceToHost),
             "copy values");
   return PMC_OK;
 }

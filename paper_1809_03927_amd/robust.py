@@ -87,7 +87,7 @@ def influence_nominal(ctx, phantoms, plan: W.Plan, n_phases: int, n_histories: i
     return stats
 
 
-def run(n_histories=20_000_000, shape_xyz=(256, 256, 160), n_phases=10, depth=2, policy="slowdown",
+def run(n_histories=20_000_000, shape_xyz=(256, 256, 160), n_phases=10, depth=2, policy="small-first",
         budget_bytes=0, log=None, plain=True, influence=True, slice_histories=None, n_streams=1):
     import torch
     from . import pmc

@@ -10,12 +10,13 @@ This loop takes such requests as they arrive and
 * keeps phantoms resident on the device and, when room is needed, unloads
   those no admitted request uses, least recently used first;
 * runs admitted requests on the persistent engine in slices of their work
-  items (chunks of a spot's histories), each time choosing the request with
-  the least expected slowdown, remaining run time / (time waited + c): a
-  small request arriving behind a large one waits for about one slice, as
-  under shortest-remaining-work-first, while a large request that has waited
-  long gains priority, which keeps the latency tail near that of serving in
-  arrival order;
+  items (chunks of a spot's histories); before each slice it takes the
+  oldest small request (at most `small_histories` histories, by default the
+  median request size) if there is one, else the oldest large one: a small
+  request arriving behind a large one waits for about one slice, while the
+  large requests keep their arrival order and so a latency tail close to
+  that of serving everything in arrival order (least-expected-slowdown and
+  shortest-remaining-first orders are available too);
 * keeps two slices in flight on two streams, so that the drain of one
   persistent launch (its last histories running at falling occupancy)
   overlaps the start of the next.
@@ -160,6 +161,8 @@ class Scheduler:
 
     Sliced policies cut requests into slices of at most `slice_histories`
     histories (at least one work item) and choose, before each slice,
+      "small-first": the oldest request of at most `small_histories`
+                  histories, else the oldest request;
       "slowdown": the least (remaining histories / rate_hist_per_s) /
                   (time since arrival + slowdown_c_s);
       "srpt":     the fewest remaining histories.
@@ -167,14 +170,15 @@ class Scheduler:
     `depth` submissions are kept in flight (completed in submission order).
     """
 
-    POLICIES = ("slowdown", "srpt", "fifo")
+    POLICIES = ("small-first", "slowdown", "srpt", "fifo")
 
-    def __init__(self, executor: Executor, clock, budget_bytes: int, policy: str = "slowdown",
+    def __init__(self, executor: Executor, clock, budget_bytes: int, policy: str = "small-first",
                  slice_histories: int = 4_000_000, log: Optional[Callable[[str], None]] = None,
                  log_every: int = 25, depth: int = 1, rate_hist_per_s: float = 1.3e8,
-                 slowdown_c_s: float = 0.05):
+                 slowdown_c_s: float = 0.05, small_histories: float = 2.2e6):
         if policy not in self.POLICIES:
             raise ValueError(f"unknown policy {policy!r}")
+        self.small = float(small_histories)
         self.rate = float(rate_hist_per_s)
         self.slowdown_c = float(slowdown_c_s)
         if depth < 1:
@@ -225,8 +229,7 @@ class Scheduler:
         self.used += self.ex.job_bytes(job)
         self.peak_used = max(self.peak_used, self.used)
         job.admitted_s = self.clock.now()
-        self.ex.start(job, sliced=self.policy != "fifo")
-        self.admitted.append(job)
+        self.admitted.append(job)  # its buffers are made when it first runs
 
     def _retire(self, job: Job) -> None:
         self.ex.release(job)
@@ -236,11 +239,13 @@ class Scheduler:
 
     # -- policy -------------------------------------------------------------------
     def _pick(self) -> Optional[Job]:
-        ready = [j for j in self.admitted if j.next_item < j.n_items]
+        ready = [j for j in self.admitted if j.first_run_s is None or j.next_item < j.n_items]
         if not ready:
             return None
         if self.policy == "fifo":
             return min(ready, key=lambda j: (j.arrival_s, j.index))
+        if self.policy == "small-first":
+            return min(ready, key=lambda j: (j.n_histories > self.small, j.arrival_s, j.index))
         if self.policy == "srpt":
             return min(ready, key=lambda j: (j.remaining, j.arrival_s, j.index))
         now = self.clock.now()
@@ -282,6 +287,7 @@ class Scheduler:
                 if job is None:
                     break
                 if job.first_run_s is None:
+                    self.ex.start(job, sliced=self.policy != "fifo")
                     job.first_run_s = self.clock.now()
                 b, e = job.next_item, self._slice_end(job)
                 inflight.append((job, b, e, self.ex.submit(job, b, e)))
@@ -416,6 +422,18 @@ class SimExecutor(Executor):
 LUT_BYTES = 4096 * 2 * (4 + 8)  # per phase: density and stopping-power-ratio tables, FP32 and FP64
 
 
+def item_histories(per_spot: np.ndarray, chunk: int) -> np.ndarray:
+    """Histories of each work item: every spot's histories cut into chunks of
+    `chunk`, in spot order (the library's work items)."""
+    per_spot = np.asarray(per_spot, dtype=np.int64)
+    n_items = (per_spot + chunk - 1) // chunk
+    out = np.full(int(n_items.sum()), chunk, dtype=np.int64)
+    last = np.cumsum(n_items)[n_items > 0] - 1
+    rem = per_spot[n_items > 0] - (n_items[n_items > 0] - 1) * chunk
+    out[last] = rem
+    return out
+
+
 class GpuExecutor(Executor):
     """Runs jobs through libpmc on the current device; tallies and doses are
     torch-owned device buffers, phantoms and plans live in the context."""
@@ -434,7 +452,10 @@ class GpuExecutor(Executor):
         self.keep_doses = keep_doses
         self.slot_of: Dict[tuple, int] = {}
         self.free_slots = list(range(1023, -1, -1))
-        self.stream = torch.cuda.current_stream()
+        # buffers, dose conversion and copies run on an I/O stream of their
+        # own, and the host waits on events only: work on (or a wait for) the
+        # null stream would also wait for the transport running on the others
+        self.io = torch.cuda.Stream()
         # submissions go round robin to side streams (default priority): with
         # one stream, slices run back to back on the device while the host
         # prepares the next; with two, consecutive slices may overlap
@@ -502,23 +523,24 @@ class GpuExecutor(Executor):
         kw = self.launch if persistent else {}
         req = pmc.Request(job.n_histories, [slot], request_id=job.index, engine=self.engine,
                           plan=plan_id, **kw)
-        job.state.update(req=req, plan_id=plan_id, slot=slot,
-                         tally=torch.zeros(job.nvox, dtype=torch.int64, device="cuda"),
-                         dose=torch.empty(job.nvox, dtype=torch.float64, device="cuda"),
-                         counters=torch.zeros(pmc.PMC_COUNTERS, dtype=torch.int64, device="cuda"))
+        with torch.cuda.stream(self.io):
+            job.state.update(req=req, plan_id=plan_id, slot=slot,
+                             tally=torch.zeros(job.nvox, dtype=torch.int64, device="cuda"),
+                             dose=torch.empty(job.nvox, dtype=torch.float64, device="cuda"),
+                             counters=torch.zeros(pmc.PMC_COUNTERS, dtype=torch.int64, device="cuda"))
+            zeroed = torch.cuda.Event()
+            zeroed.record(self.io)
         if persistent:
             job.n_items = pmc.pmc_request_items(self.ctx, req)
-            chunk = kw.get("chunk") or 256
-            h: List[int] = []
-            for n in pmc.pmc_split_histories(spots, [slot], job.n_histories):
-                n = int(n)
-                h += [chunk] * (n // chunk) + ([n % chunk] if n % chunk else [])
-            if len(h) != job.n_items:
-                raise RuntimeError("work-item count differs from the library's")
-            job.item_hist = np.array(h, dtype=np.int64) if sliced else None
+            if sliced:
+                job.item_hist = item_histories(pmc.pmc_split_histories(spots, [slot], job.n_histories),
+                                               kw.get("chunk") or 256)
+                if len(job.item_hist) != job.n_items:
+                    raise RuntimeError("work-item count differs from the library's")
         else:
             job.n_items = 1
-        self.stream.synchronize()  # buffers are zero before a side stream adds into them
+        for s in self.streams:  # the buffers are zero before a slice adds into them
+            s.wait_event(zeroed)
 
     def submit(self, job: Job, item_begin: int, item_end: int):
         pmc, st = self.pmc, job.state
@@ -537,21 +559,28 @@ class GpuExecutor(Executor):
         token.synchronize()
 
     def finish(self, job: Job) -> None:
-        pmc, st = self.pmc, job.state
+        # the job's slices are complete (the scheduler waited for them)
+        pmc, st, torch = self.pmc, job.state, self.torch
         pmc.pmc_convert_device(self.ctx, st["slot"], st["tally"].data_ptr(), job.n_histories,
-                               self.stream.cuda_stream, st["dose"].data_ptr(), None)
+                               self.io.cuda_stream, st["dose"].data_ptr(), None)
         buf = self._host_buffer(job.nvox)
-        buf.copy_(st["dose"], non_blocking=True)
-        self.stream.synchronize()  # served once the dose is on the host
+        with torch.cuda.stream(self.io):
+            buf.copy_(st["dose"], non_blocking=True)
+            done = torch.cuda.Event()
+            done.record(self.io)
+        done.synchronize()  # served once the dose is on the host
         st["host_dose"] = buf
 
     def release(self, job: Job) -> None:
         pmc, st, torch = self.pmc, job.state, self.torch
+        if not st:  # cancelled before it ever ran
+            return
         buf = st.get("host_dose")
         if self.verify and buf is not None:
             t = st["tally"]
-            words = torch.cat([torch.stack(((t >> 32).sum(), (t & 0xFFFFFFFF).sum())),
-                               st["counters"]]).cpu().numpy()
+            with torch.cuda.stream(self.io):  # .cpu() waits for this stream only
+                words = torch.cat([torch.stack(((t >> 32).sum(), (t & 0xFFFFFFFF).sum())),
+                                   st["counters"]]).cpu().numpy()
             dep = (int(words[0]) << 32) + int(words[1])
             b = pmc.pmc_balance_from_counters(self.ctx, st["req"], words[2:], dep)
             if b["deposited"] + b["escaped"] + b["nuclear"] != b["incident"]:
@@ -656,15 +685,25 @@ def calibrate_plain(ctx, seed: int, h_lo: float, h_hi: float, log=None, n: int =
     return rate
 
 
+def prebuild(n_requests=200, seed=4, h_lo=1e5, h_hi=5e7, workers=0, log=None):
+    """Requests (arrival times of a rate-1 Poisson process), phantoms and
+    plans of a served stream; with workers > 0 call it before this process
+    touches the GPU (forked generator processes)."""
+    reqs0 = W.served_stream(n_requests, rate_hz=1.0, seed=seed, h_lo=h_lo, h_hi=h_hi)
+    phantoms, plans = build_stream(reqs0, workers, log)
+    return reqs0, phantoms, plans
+
+
 def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_hi=5e7,
                  slice_histories=4_000_000, launch=None, workers=0, log=None, depth=2,
-                 policy="slowdown", plain=True, n_streams=1):
+                 policy="small-first", plain=True, n_streams=1, prebuilt=None):
     """Serve one Poisson stream with the sliced persistent engine (`policy`,
     `depth` slices in flight) and with the plain engine run serially in
     arrival order.  Arrival rate = load x plain throughput / mean request
     size.  Returns a dict of results."""
-    reqs0 = W.served_stream(n_requests, rate_hz=1.0, seed=seed, h_lo=h_lo, h_hi=h_hi)
-    phantoms, plans = build_stream(reqs0, workers, log)
+    if prebuilt is None:
+        prebuilt = prebuild(n_requests, seed, h_lo, h_hi, workers, log)
+    reqs0, phantoms, plans = prebuilt
     import torch
     from . import pmc
     free, _ = torch.cuda.mem_get_info()
@@ -710,7 +749,7 @@ def main():
     p.add_argument("--workers", type=int, default=8)
     p.add_argument("--depth", type=int, default=2, help="slices in flight")
     p.add_argument("--streams", type=int, default=1, help="submission streams")
-    p.add_argument("--policy", choices=["slowdown", "srpt"], default="slowdown")
+    p.add_argument("--policy", choices=["small-first", "slowdown", "srpt"], default="small-first")
     p.add_argument("--no-plain", action="store_true", help="skip the plain-serial comparison")
     p.add_argument("--block", type=int, default=0, help="persistent-engine block size (0 = library default)")
     a = p.parse_args()

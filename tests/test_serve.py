@@ -22,7 +22,7 @@ def sim(**kw):
 
 
 def test_small_request_overtakes_large_one_when_sliced():
-    for policy in ("srpt", "slowdown", "fifo"):
+    for policy in ("srpt", "slowdown", "small-first", "fifo"):
         clock, ex = sim(rate_hist_per_s=1e8, overhead_s=1e-4)
         big, small = job(0, 0.0, 100_000_000), job(1, 0.1, 100_000)
         done = S.Scheduler(ex, clock, 10**9, policy=policy, slice_histories=4_000_000,
@@ -65,7 +65,7 @@ def random_jobs(n, seed, rate_hz, n_keys=None, nvox_choices=(10_000, 50_000, 200
 
 
 @pytest.mark.parametrize("policy,depth", [("srpt", 1), ("fifo", 1), ("slowdown", 1), ("srpt", 2),
-                                          ("slowdown", 3)])
+                                          ("slowdown", 3), ("small-first", 2)])
 def test_budget_is_never_exceeded_and_everything_is_served(policy, depth):
     jobs = random_jobs(60, 1, rate_hz=30.0, n_keys=12)
     budget = 6_000_000  # a few jobs at a time
@@ -150,23 +150,24 @@ def test_cancellation_of_waiting_and_running_requests():
 @pytest.mark.parametrize("load", [0.8, 1.0])
 def test_sliced_policies_against_arrival_order(load):
     """On the served-request stream (200 requests, sizes log-uniform in
-    [1e5, 5e7] histories), both sliced policies at least halve the median
+    [1e5, 5e7] histories), the sliced policies at least halve the median
     latency of serving whole requests in arrival order.  Shortest-remaining-
     first pays for it in the tail (it starves the largest requests); the
-    slowdown rule keeps the 99th percentile within 30 % of arrival order."""
+    slowdown rule keeps the 99th percentile within 30 % of arrival order,
+    small-requests-first within 10 %."""
     reqs = W.served_stream(200, rate_hz=1.0, seed=4)
     rate = 1.3e8
     lam = load * rate / S.log_uniform_mean(1e5, 5e7)
     nv = {g: int(np.prod(g)) for g in W.SERVED_GRIDS}
     res = {}
-    for policy in ("srpt", "slowdown", "fifo"):
+    for policy in ("srpt", "slowdown", "small-first", "fifo"):
         jobs = [S.Job(r.index, r.arrival_s / lam, r.n_histories, r.phantom_key, nv[r.grid])
                 for r in reqs]
         clock, ex = sim(rate_hist_per_s=rate, overhead_s=2e-4)
         done = S.Scheduler(ex, clock, 200 * 2**30, policy=policy, rate_hist_per_s=rate).run(jobs)
         res[policy] = S.summarize(done, policy)
     f = res["fifo"]
-    for policy in ("srpt", "slowdown"):
+    for policy in ("srpt", "slowdown", "small-first"):
         r = res[policy]
         assert r["requests"] == 200
         assert r["mean_latency_s"] < f["mean_latency_s"]
@@ -175,9 +176,21 @@ def test_sliced_policies_against_arrival_order(load):
         assert r["makespan_s"] == pytest.approx(f["makespan_s"], rel=0.05)
     assert res["slowdown"]["p99_latency_s"] <= 1.3 * f["p99_latency_s"]
     assert res["srpt"]["p99_latency_s"] > res["slowdown"]["p99_latency_s"] > f["p99_latency_s"] * 0.99
+    # small requests first, large ones in arrival order: the tail stays within 10 % of it
+    assert res["small-first"]["p99_latency_s"] <= 1.1 * f["p99_latency_s"]
 
 
 def test_log_uniform_mean():
     rng = np.random.default_rng(0)
     x = np.exp(rng.uniform(np.log(1e5), np.log(5e7), size=2_000_000))
     assert S.log_uniform_mean(1e5, 5e7) == pytest.approx(x.mean(), rel=5e-3)
+
+
+def test_item_histories_match_the_library_rule():
+    per = np.array([0, 5, 256, 257, 1000, 0, 1])
+    got = S.item_histories(per, 256)
+    want = []
+    for n in per:
+        want += [256] * (n // 256) + ([n % 256] if n % 256 else [])
+    assert got.tolist() == want
+    assert S.item_histories(np.zeros(3, dtype=np.int64), 64).size == 0
