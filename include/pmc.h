@@ -207,6 +207,17 @@ int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
 int pmc_dose_device(pmc_context *ctx, const pmc_request *req, void *stream,
                     int64_t *const *dev_tally, uint64_t *dev_counters);
 
+/* pmc_dose_device for the persistent engine, with a drain signal: once every
+ * work item of the launch has been taken (its last histories may still be
+ * running), the kernel writes 1 to *host_drained.  host_drained must be host
+ * memory the device can write (pinned, e.g. hipHostMalloc); the caller sets
+ * it to 0 before the call and keeps it until the launch completes.  A caller
+ * that waits for this flag instead of the launch's end can start its next
+ * launch on another stream while this one drains (a serving loop cutting
+ * requests into slices pays no drain per slice). */
+int pmc_dose_device_notify(pmc_context *ctx, const pmc_request *req, void *stream,
+                           int64_t *const *dev_tally, uint64_t *dev_counters, uint32_t *host_drained);
+
 /* Turn a device counter block (copied to the host) plus the request into a
  * pmc_balance; the deposited total is taken from the tallies' sum, passed as
  * a 128-bit (lo, hi) pair. */

@@ -592,7 +592,7 @@ template <typename R>
 int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipStream_t st,
                      unsigned long long *const *tally, unsigned long long *counters,
                      unsigned char *base, unsigned long long *cursor, bool upload_targets,
-                     const BoxArgs *box = nullptr) {
+                     const BoxArgs *box = nullptr, unsigned int *drained = nullptr) {
   auto scratch_at = [&](size_t off) { return base + off; };
   const bool fp64 = sizeof(R) == 8;
   const uint32_t k0 = (uint32_t)(ctx->seed & 0xffffffffu), k1 = req->request_id;
@@ -665,6 +665,7 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
       a.box_tally = box->tally;
       a.box_bias = box->bias;
     }
+    a.drained = drained;
     unsigned grid = (unsigned)req->grid_blocks;
     if (grid == 0) {
       int per_cu = pmc::persistent_blocks_per_cu(a, fp64);
@@ -694,7 +695,8 @@ int take_cursor(pmc_context *ctx, hipStream_t st, unsigned long long **cursor, h
 
 template <typename R>
 int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
-            unsigned long long *const *tally, unsigned long long *counters) {
+            unsigned long long *const *tally, unsigned long long *counters,
+            unsigned int *drained = nullptr) {
   Prepared *P = nullptr;
   int rc = prepare<R>(ctx, req, &P);
   if (rc) return rc;
@@ -708,7 +710,7 @@ int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
     if (rc) return rc;
   }
   rc = enqueue_prepared<R>(ctx, *P, req, st, tally, counters, static_cast<unsigned char *>(P->buf.p),
-                           cursor, true);
+                           cursor, true, nullptr, drained);
   if (rc) return rc;
   if (cursor_done) HIP_TRY(ctx, hipEventRecord(*cursor_done, st), "hipEventRecord");
   rc = note_use(ctx, P->uses, st);
@@ -1047,8 +1049,8 @@ int pmc_request_items(pmc_context *ctx, const pmc_request *req, uint64_t *n_item
   return PMC_OK;
 }
 
-int pmc_dose_device(pmc_context *ctx, const pmc_request *req, void *stream,
-                    int64_t *const *dev_tally, uint64_t *dev_counters) {
+static int dose_device(pmc_context *ctx, const pmc_request *req, void *stream, int64_t *const *dev_tally,
+                       uint64_t *dev_counters, unsigned int *drained) {
   if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
   ctx->err.clear();
   int rc = validate_request(ctx, req);
@@ -1067,8 +1069,22 @@ int pmc_dose_device(pmc_context *ctx, const pmc_request *req, void *stream,
     HIP_TRY(ctx, pmc::launch_fill_u64(counters, PMC_COUNTERS, 0ull, st), "counter reset");
   }
   unsigned long long *const *t = reinterpret_cast<unsigned long long *const *>(dev_tally);
-  return ctx->precision == PMC_FP64 ? enqueue<double>(ctx, req, st, t, counters)
-                                    : enqueue<float>(ctx, req, st, t, counters);
+  return ctx->precision == PMC_FP64 ? enqueue<double>(ctx, req, st, t, counters, drained)
+                                    : enqueue<float>(ctx, req, st, t, counters, drained);
+}
+
+int pmc_dose_device(pmc_context *ctx, const pmc_request *req, void *stream,
+                    int64_t *const *dev_tally, uint64_t *dev_counters) {
+  return dose_device(ctx, req, stream, dev_tally, dev_counters, nullptr);
+}
+
+int pmc_dose_device_notify(pmc_context *ctx, const pmc_request *req, void *stream,
+                           int64_t *const *dev_tally, uint64_t *dev_counters, uint32_t *host_drained) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  if (!req || req->engine != PMC_ENGINE_PERSISTENT)
+    return fail(ctx, PMC_E_INVAL, "the drain signal belongs to the persistent engine");
+  if (!host_drained) return fail(ctx, PMC_E_INVAL, "host_drained is NULL");
+  return dose_device(ctx, req, stream, dev_tally, dev_counters, host_drained);
 }
 
 int pmc_balance_from_counters(pmc_context *ctx, const pmc_request *req, const uint64_t *counters,

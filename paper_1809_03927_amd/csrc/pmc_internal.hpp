@@ -100,6 +100,8 @@ struct PersistentLaunch {
   const BoxDev *boxes = nullptr;
   unsigned long long *box_tally = nullptr;
   long long box_bias = 0;
+  // host-visible flag set to 1 once every work item has been taken (nullable)
+  unsigned int *drained = nullptr;
 };
 
 // Compaction of the box tallies of spots [0, n_spots) of a batch into CSR

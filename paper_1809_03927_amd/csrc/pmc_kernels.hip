@@ -153,7 +153,7 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
                      uint32_t k0, uint32_t k1, uint32_t flags, int32_t refill_min,
                      unsigned long long *cursor, unsigned long long *counters,
                      const BoxDev *__restrict__ boxes, unsigned long long *box_tally,
-                     long long box_bias) {
+                     long long box_bias, unsigned int *drained_flag) {
   extern __shared__ __align__(16) unsigned char smem[];
   using R2 = typename M<R>::R2;
   using R4 = typename M<R>::R4;
@@ -190,7 +190,14 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
           unsigned long long k = 0;
           if (lane == 0) k = __hip_atomic_fetch_add(cursor, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           k = __shfl(k, 0, 64);
-          if (k >= (unsigned long long)n_items) { drained = true; break; }
+          if (k >= (unsigned long long)n_items) {
+            drained = true;
+            // every work item is taken: tell the host (pinned memory, vector
+            // store) so that it can start the next launch during this drain
+            if (drained_flag && lane == 0)
+              __hip_atomic_store(drained_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            break;
+          }
           const WorkItem wi = items[k];
           it_spot = __builtin_amdgcn_readfirstlane(wi.spot);
           it_next = __builtin_amdgcn_readfirstlane(wi.h_begin);
@@ -592,7 +599,7 @@ static void launch_persistent_v(const PersistentLaunch &a, size_t lds, hipStream
                      (const SpotDev<R> *)a.spots, a.items, a.n_items, a.targets, a.n_targets,
                      (const R2 *)a.luts, (const R4 *)a.tab, (R)a.l2e0, (R)a.inv_dl2, (R)a.dl2,
                      a.k0, a.k1, a.flags, a.refill_min, a.cursor, a.counters, a.boxes,
-                     a.box_tally, a.box_bias);
+                     a.box_tally, a.box_bias, a.drained);
 }
 
 template <typename R>

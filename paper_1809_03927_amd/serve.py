@@ -17,9 +17,10 @@ This loop takes such requests as they arrive and
   large requests keep their arrival order and so a latency tail close to
   that of serving everything in arrival order (least-expected-slowdown and
   shortest-remaining-first orders are available too);
-* keeps two slices in flight on two streams, so that the drain of one
-  persistent launch (its last histories running at falling occupancy)
-  overlaps the start of the next.
+* starts the next slice, on a second stream, as soon as the running one has
+  handed out its last work item (the kernel sets a pinned host flag), so
+  that the drain of one persistent launch (its last histories running at
+  falling occupancy) overlaps the start of the next instead of idling CUs.
 
 Slices of one request add into the same integer tally, and a history's random
 numbers depend only on (seed, request, spot, history), so the served dose of a
@@ -70,6 +71,7 @@ class Job:
     first_run_s: Optional[float] = None
     done_s: Optional[float] = None
     cancelled: bool = False
+    started: bool = False                # buffers made and request data prepared
     slices: int = 0
     state: Dict = dataclasses.field(default_factory=dict)
 
@@ -136,12 +138,24 @@ class Executor:
         """Start work items [item_begin, item_end) of the job; return a token."""
         raise NotImplementedError
 
-    def wait(self, token) -> None:
-        """Wait until the submission of `token` has completed."""
+    def finished(self, token) -> bool:
+        """Has the submission completed?  (Does not block.)"""
+        raise NotImplementedError
+
+    def drained(self, token) -> bool:
+        """Has the submission taken all its work, so that the next one may
+        start beside its last histories?  (Does not block.)"""
+        return self.finished(token)
+
+    def progress(self, tokens, until: Optional[float] = None) -> None:
+        """Block until a token may have drained or finished, or until time
+        `until` (a new arrival), whichever comes first."""
         raise NotImplementedError
 
     def run(self, job: Job, item_begin: int, item_end: int) -> None:
-        self.wait(self.submit(job, item_begin, item_end))
+        token = self.submit(job, item_begin, item_end)
+        while not self.finished(token):
+            self.progress([token])
 
     def finish(self, job: Job) -> None:
         """Produce the job's dose on the host (the request is served when this returns)."""
@@ -175,10 +189,11 @@ class Scheduler:
     def __init__(self, executor: Executor, clock, budget_bytes: int, policy: str = "small-first",
                  slice_histories: int = 4_000_000, log: Optional[Callable[[str], None]] = None,
                  log_every: int = 25, depth: int = 1, rate_hist_per_s: float = 1.3e8,
-                 slowdown_c_s: float = 0.05, small_histories: float = 2.2e6):
+                 slowdown_c_s: float = 0.05, small_histories: float = 2.2e6, prestart: int = 2):
         if policy not in self.POLICIES:
             raise ValueError(f"unknown policy {policy!r}")
         self.small = float(small_histories)
+        self.prestart = int(prestart)
         self.rate = float(rate_hist_per_s)
         self.slowdown_c = float(slowdown_c_s)
         if depth < 1:
@@ -238,19 +253,34 @@ class Scheduler:
         self.admitted.remove(job)
 
     # -- policy -------------------------------------------------------------------
+    def _key(self, j: Job, now: float):
+        if self.policy == "fifo":
+            return (j.arrival_s, j.index)
+        if self.policy == "small-first":
+            return (j.n_histories > self.small, j.arrival_s, j.index)
+        if self.policy == "srpt":
+            return (j.remaining, j.arrival_s, j.index)
+        return (j.remaining / self.rate / (now - j.arrival_s + self.slowdown_c), j.arrival_s, j.index)
+
+    def _ready(self) -> List[Job]:
+        return [j for j in self.admitted if not j.started or j.next_item < j.n_items]
+
     def _pick(self) -> Optional[Job]:
-        ready = [j for j in self.admitted if j.first_run_s is None or j.next_item < j.n_items]
+        ready = self._ready()
         if not ready:
             return None
-        if self.policy == "fifo":
-            return min(ready, key=lambda j: (j.arrival_s, j.index))
-        if self.policy == "small-first":
-            return min(ready, key=lambda j: (j.n_histories > self.small, j.arrival_s, j.index))
-        if self.policy == "srpt":
-            return min(ready, key=lambda j: (j.remaining, j.arrival_s, j.index))
         now = self.clock.now()
-        return min(ready, key=lambda j: (j.remaining / self.rate / (now - j.arrival_s + self.slowdown_c),
-                                         j.arrival_s, j.index))
+        return min(ready, key=lambda j: self._key(j, now))
+
+    def _prestart(self) -> None:
+        """Prepare the next requests in pick order while the device works."""
+        if self.prestart <= 0:
+            return
+        now = self.clock.now()
+        todo = sorted((j for j in self.admitted if not j.started), key=lambda j: self._key(j, now))
+        for j in todo[:self.prestart]:
+            self.ex.start(j, sliced=self.policy != "fifo")
+            j.started = True
 
     def _slice_end(self, job: Job) -> int:
         if self.policy == "fifo" or job.item_hist is None:
@@ -268,7 +298,8 @@ class Scheduler:
             if self.ex.job_bytes(j) + self.ex.phantom_bytes(j.phantom_key) > self.budget:
                 raise ValueError(f"request {j.index} needs more than the whole budget")
         waiting = deque(sorted(jobs, key=lambda j: (j.arrival_s, j.index)))
-        inflight: deque = deque()  # (job, item_begin, item_end, token)
+        inflight: deque = deque()  # (job, item_begin, item_end, token): not yet drained
+        running: List[tuple] = []  # drained, not yet finished
         done: List[Job] = []
         while waiting or self.admitted:
             now = self.clock.now()
@@ -281,13 +312,15 @@ class Scheduler:
                 j.cancelled = True
             while waiting and waiting[0].arrival_s <= now and self._make_room(waiting[0]):
                 self._admit(waiting.popleft())
-            # keep `depth` slices in flight
+            # keep `depth` slices that still have work to hand out
             while len(inflight) < self.depth:
                 job = self._pick()
                 if job is None:
                     break
-                if job.first_run_s is None:
+                if not job.started:
                     self.ex.start(job, sliced=self.policy != "fifo")
+                    job.started = True
+                if job.first_run_s is None:
                     job.first_run_s = self.clock.now()
                 b, e = job.next_item, self._slice_end(job)
                 inflight.append((job, b, e, self.ex.submit(job, b, e)))
@@ -296,8 +329,15 @@ class Scheduler:
                 job.slices += 1
                 self.slices += 1
             if inflight:
-                job, b, e, token = inflight.popleft()
-                self.ex.wait(token)
+                self._prestart()
+            moved = False
+            while inflight and self.ex.drained(inflight[0][3]):
+                running.append(inflight.popleft())
+                moved = True
+            for sub in [x for x in running if self.ex.finished(x[3])]:
+                running.remove(sub)
+                moved = True
+                job, b, e, _ = sub
                 job.in_flight -= 1
                 job.items_done += e - b
                 if job.items_done == job.n_items:
@@ -308,6 +348,16 @@ class Scheduler:
                     if self.log and len(done) % self.log_every == 0:
                         self.log(f"{self.policy}: {len(done)} served, {len(waiting)} waiting, "
                                  f"{len(self.admitted)} admitted, t={job.done_s:.2f} s")
+            if moved:
+                continue
+            nxt = None
+            if waiting:
+                nxt = waiting[0].arrival_s
+                if waiting[0].cancel_s is not None:
+                    nxt = min(nxt, waiting[0].cancel_s)
+            if inflight or running:
+                self.ex.progress([x[3] for x in inflight] + [x[3] for x in running],
+                                 until=nxt if nxt is not None and nxt > now else None)
                 continue
             if self.admitted:  # only cancelled-pending work remains: nothing runs it
                 raise RuntimeError("admitted requests with no work left to submit")
@@ -315,9 +365,6 @@ class Scheduler:
                 break
             if waiting[0].arrival_s <= now:
                 raise RuntimeError("the queue head does not fit an empty device")
-            nxt = waiting[0].arrival_s
-            if waiting[0].cancel_s is not None:
-                nxt = min(nxt, waiting[0].cancel_s)
             self.clock.sleep_until(nxt)
         return done
 
@@ -402,8 +449,14 @@ class SimExecutor(Executor):
         self.busy_until = max(self.busy_until, self.clock.now()) + self.overhead + h / self.rate
         return self.busy_until
 
-    def wait(self, token) -> None:
-        self.clock.sleep_until(token)
+    def finished(self, token) -> bool:
+        return self.clock.now() >= token
+
+    def progress(self, tokens, until: Optional[float] = None) -> None:
+        t = min(tokens)
+        if until is not None:
+            t = min(t, until)
+        self.clock.sleep_until(t)
 
     def finish(self, job: Job) -> None:
         assert np.all(job.state["covered"] == 1), "work items not covered exactly once"
@@ -461,6 +514,11 @@ class GpuExecutor(Executor):
         # prepares the next; with two, consecutive slices may overlap
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.next_stream = 0
+        # drain signals of persistent launches (pinned host words the kernel
+        # sets when every work item is taken): with two or more streams the
+        # next slice starts while the previous one drains
+        self.drain_flags = torch.zeros(64, dtype=torch.int32, pin_memory=True) if n_streams > 1 else None
+        self.free_flags = list(range(64))
         self.digests: Dict[int, str] = {}
         self.balances: Dict[int, dict] = {}
         self.doses: Dict[int, np.ndarray] = {}
@@ -545,18 +603,39 @@ class GpuExecutor(Executor):
     def submit(self, job: Job, item_begin: int, item_end: int):
         pmc, st = self.pmc, job.state
         req = st["req"]
-        if self.engine == pmc.PMC_ENGINE_PERSISTENT and (item_begin, item_end) != (0, job.n_items):
+        persistent = self.engine == pmc.PMC_ENGINE_PERSISTENT
+        if persistent and (item_begin, item_end) != (0, job.n_items):
             req = req.slice(item_begin, item_end)
         stream = self.streams[self.next_stream]
         self.next_stream = (self.next_stream + 1) % len(self.streams)
-        pmc.pmc_dose_device(self.ctx, req, stream.cuda_stream, [st["tally"].data_ptr()],
-                            st["counters"].data_ptr())
+        flag = None
+        if persistent and self.drain_flags is not None and self.free_flags:
+            flag = self.free_flags.pop()
+            self.drain_flags[flag] = 0
+            pmc.pmc_dose_device_notify(self.ctx, req, stream.cuda_stream, [st["tally"].data_ptr()],
+                                       st["counters"].data_ptr(), self.drain_flags.data_ptr() + 4 * flag)
+        else:
+            pmc.pmc_dose_device(self.ctx, req, stream.cuda_stream, [st["tally"].data_ptr()],
+                                st["counters"].data_ptr())
         ev = self.torch.cuda.Event()
         ev.record(stream)
-        return ev
+        return [ev, flag]
 
-    def wait(self, token) -> None:
-        token.synchronize()
+    def finished(self, token) -> bool:
+        if not token[0].query():
+            return False
+        if token[1] is not None:  # the launch is over: its flag is free again
+            self.free_flags.append(token[1])
+            token[1] = None
+        return True
+
+    def drained(self, token) -> bool:
+        if token[1] is not None and int(self.drain_flags[token[1]]) != 0:
+            return True
+        return self.finished(token)
+
+    def progress(self, tokens, until: Optional[float] = None) -> None:
+        time.sleep(2e-5)
 
     def finish(self, job: Job) -> None:
         # the job's slices are complete (the scheduler waited for them)
@@ -644,14 +723,16 @@ def log_uniform_mean(lo: float, hi: float) -> float:
 def serve_gpu(ctx, reqs, phantoms, plans, engine: int, policy: str, budget: int,
               launch: Optional[dict] = None, slice_histories: int = 4_000_000, log=None,
               keep_doses: bool = False, depth: int = 1, rate_hist_per_s: float = 1.3e8,
-              n_streams: int = 1):
+              n_streams: int = 1, small_histories: float = 2.2e6):
     """Serve `reqs` on the GPU in real time; returns (summary, executor, scheduler)."""
     ex = GpuExecutor(ctx, phantoms, plans, engine, launch, keep_doses=keep_doses, n_streams=n_streams)
     sched = Scheduler(ex, WallClock(), budget, policy=policy, slice_histories=slice_histories,
-                      log=log, depth=depth, rate_hist_per_s=rate_hist_per_s)
+                      log=log, depth=depth, rate_hist_per_s=rate_hist_per_s,
+                      small_histories=small_histories)
     done = sched.run(jobs_of(reqs, phantoms))
     ex.close()
     s = summarize(done, policy)
+    s["per_request"] = [[j.index, j.n_histories, j.arrival_s, j.first_run_s, j.done_s] for j in done]
     s.update(slices=sched.slices, evictions=sched.evictions, phantom_loads=sched.phantom_loads,
              peak_bytes=sched.peak_used, budget_bytes=budget, slices_in_flight=depth,
              streams=n_streams, slice_histories=slice_histories)
@@ -695,8 +776,8 @@ def prebuild(n_requests=200, seed=4, h_lo=1e5, h_hi=5e7, workers=0, log=None):
 
 
 def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_hi=5e7,
-                 slice_histories=4_000_000, launch=None, workers=0, log=None, depth=2,
-                 policy="small-first", plain=True, n_streams=1, prebuilt=None):
+                 slice_histories=4_000_000, launch=None, workers=0, log=None, depth=1,
+                 policy="small-first", plain=True, n_streams=2, prebuilt=None, small=2.2e6):
     """Serve one Poisson stream with the sliced persistent engine (`policy`,
     `depth` slices in flight) and with the plain engine run serially in
     arrival order.  Arrival rate = load x plain throughput / mean request
@@ -723,7 +804,8 @@ def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_h
         for label, engine, pol, d in engines:
             s, ex, _ = serve_gpu(ctx, reqs, phantoms, plans, engine, pol, budget, launch,
                                  slice_histories, log, depth=d, rate_hist_per_s=rate_plain,
-                                 n_streams=n_streams if engine == pmc.PMC_ENGINE_PERSISTENT else 1)
+                                 n_streams=n_streams if engine == pmc.PMC_ENGINE_PERSISTENT else 1,
+                                 small_histories=small)
             for key in list(ex.slot_of):
                 ex.unload_phantom(key)
             out[label] = s
@@ -747,17 +829,24 @@ def main():
     p.add_argument("--seed", type=int, default=4)
     p.add_argument("--slice-histories", type=int, default=4_000_000)
     p.add_argument("--workers", type=int, default=8)
-    p.add_argument("--depth", type=int, default=2, help="slices in flight")
-    p.add_argument("--streams", type=int, default=1, help="submission streams")
-    p.add_argument("--policy", choices=["small-first", "slowdown", "srpt"], default="small-first")
+    p.add_argument("--depth", type=int, default=1, help="slices handing out work at once")
+    p.add_argument("--streams", type=int, default=2,
+                   help="submission streams (>= 2: the next slice starts while the previous drains)")
+    p.add_argument("--policy", choices=["small-first", "slowdown", "srpt", "fifo"], default="small-first")
+    p.add_argument("--small", type=float, default=2.2e6, help="small-first: largest small request")
     p.add_argument("--no-plain", action="store_true", help="skip the plain-serial comparison")
     p.add_argument("--block", type=int, default=0, help="persistent-engine block size (0 = library default)")
+    p.add_argument("--per-request", action="store_true", help="keep per-request times in the output")
     a = p.parse_args()
     res = run_scenario(a.requests, a.load, a.seed, int(a.budget_gb * 2**30),
                        slice_histories=a.slice_histories, workers=a.workers, depth=a.depth,
-                       policy=a.policy, plain=not a.no_plain, n_streams=a.streams,
+                       policy=a.policy, plain=not a.no_plain, n_streams=a.streams, small=a.small,
                        launch={"block_size": a.block} if a.block else None,
                        log=lambda m: print("[serve]", m, file=sys.stderr, flush=True))
+    if not a.per_request:
+        for k in ("batched", "plain-serial"):
+            if k in res:
+                res[k].pop("per_request", None)
     print(json.dumps(res))
 
 

@@ -136,6 +136,7 @@ def test_served_equals_plain_serial():
         out = {}
         for label, engine, policy, budget, depth, streams in (
                 ("slowdown", pmc.PMC_ENGINE_PERSISTENT, "slowdown", 2 * 2**30, 2, 1),
+                ("small-first-drain", pmc.PMC_ENGINE_PERSISTENT, "small-first", 2 * 2**30, 1, 2),
                 ("srpt-tight", pmc.PMC_ENGINE_PERSISTENT, "srpt", tight, 2, 2),
                 ("srpt-depth1", pmc.PMC_ENGINE_PERSISTENT, "srpt", 2 * 2**30, 1, 1),
                 ("plain", pmc.PMC_ENGINE_PLAIN, "fifo", 2 * 2**30, 1, 1)):
@@ -156,7 +157,7 @@ def test_served_equals_plain_serial():
         for r in reqs:
             d = out["plain"].doses[r.index]
             assert np.isfinite(d).all() and d.max() > 0
-            for label in ("slowdown", "srpt-tight", "srpt-depth1"):
+            for label in ("slowdown", "small-first-drain", "srpt-tight", "srpt-depth1"):
                 assert np.array_equal(out[label].doses[r.index], d), (label, r.index)
                 assert out[label].balances[r.index] == out["plain"].balances[r.index]
         assert pmc.pmc_bytes_in_use(ctx) >= 0
@@ -178,3 +179,34 @@ def test_robust_workload_small():
     inf = res["influence"]
     assert len(inf["phases"]) == 2 and all(x["nnz"] > 0 for x in inf["phases"])
     assert all(x["outside_fraction"] < 0.05 for x in inf["phases"])
+
+
+def test_drain_signal():
+    """pmc_dose_device_notify: the pinned flag is set by the time the launch
+    has completed, the tally equals pmc_dose_device's, and the plain engine
+    is rejected."""
+    import torch
+    from paper_1809_03927_amd import pmc
+    wl = W.workload_thorax4d(n_histories=200_000, shape_xyz=(64, 64, 40), n_phases=10)
+    e = pmc.Engine(device=0, seed=wl.seed)
+    try:
+        e.load_workload(wl)
+        phases = list(range(10))
+        nv = wl.phases[0].nvox
+        st = torch.cuda.current_stream()
+        flag = torch.zeros(4, dtype=torch.int32, pin_memory=True)
+        req = pmc.Request(wl.n_histories, phases, engine=pmc.PMC_ENGINE_PERSISTENT)
+        ref = [torch.zeros(nv, dtype=torch.int64, device="cuda") for _ in phases]
+        got = [torch.zeros(nv, dtype=torch.int64, device="cuda") for _ in phases]
+        pmc.pmc_dose_device(e.ctx, req, st.cuda_stream, [t.data_ptr() for t in ref], None)
+        say("drain signal")
+        pmc.pmc_dose_device_notify(e.ctx, req, st.cuda_stream, [t.data_ptr() for t in got], None,
+                                   flag.data_ptr() + 4)
+        torch.cuda.synchronize()
+        assert int(flag[1]) == 1 and int(flag[0]) == 0 and int(flag[2]) == 0
+        assert all(torch.equal(a, b) for a, b in zip(ref, got))
+        with pytest.raises(pmc.PmcError):
+            pmc.pmc_dose_device_notify(e.ctx, pmc.Request(1000, [0], engine=pmc.PMC_ENGINE_PLAIN),
+                                       st.cuda_stream, [got[0].data_ptr()], None, flag.data_ptr())
+    finally:
+        e.close()

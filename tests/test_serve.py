@@ -85,23 +85,53 @@ def test_budget_is_never_exceeded_and_everything_is_served(policy, depth):
 
 def test_slices_in_flight_never_exceed_depth():
     class Counting(S.SimExecutor):
-        outstanding = 0
         most = 0
 
         def submit(self, job, b, e):
-            Counting.outstanding += 1
-            Counting.most = max(Counting.most, Counting.outstanding)
-            return super().submit(job, b, e)
-
-        def wait(self, token):
-            Counting.outstanding -= 1
-            super().wait(token)
+            token = super().submit(job, b, e)
+            self.tokens = getattr(self, "tokens", []) + [token]
+            busy = sum(1 for t in self.tokens if self.clock.now() < t)
+            Counting.most = max(Counting.most, busy)
+            return token
 
     clock = S.FakeClock()
     ex = Counting(clock, rate_hist_per_s=1e8)
     jobs = random_jobs(20, 3, rate_hz=50.0)
     done = S.Scheduler(ex, clock, 10**9, depth=2, slice_histories=2_000_000).run(jobs)
-    assert len(done) == 20 and Counting.most == 2 and Counting.outstanding == 0
+    assert len(done) == 20 and Counting.most == 2
+
+
+def test_drained_slices_free_their_slot_before_they_finish():
+    """A submission that has handed out all its work (drained) lets the next
+    one start while its last histories still run."""
+    class Draining(S.SimExecutor):
+        lead = 0.005  # drained this long before finishing
+        overlaps = 0
+
+        def submit(self, job, b, e):
+            token = super().submit(job, b, e)
+            self.tokens = getattr(self, "tokens", []) + [token]
+            if sum(1 for t in self.tokens if self.clock.now() < t) > 1:
+                Draining.overlaps += 1
+            return token
+
+        def drained(self, token):
+            return self.clock.now() >= token - self.lead
+
+        def progress(self, tokens, until=None):
+            ts = [t - self.lead for t in tokens if self.clock.now() < t - self.lead] + \
+                 [t for t in tokens if self.clock.now() < t]
+            t = min(ts) if ts else self.clock.now()
+            if until is not None:
+                t = min(t, until)
+            self.clock.sleep_until(t)
+
+    clock = S.FakeClock()
+    ex = Draining(clock, rate_hist_per_s=1e8)
+    jobs = [job(0, 0.0, 20_000_000)]
+    done = S.Scheduler(ex, clock, 10**9, depth=1, slice_histories=2_000_000).run(jobs)
+    assert len(done) == 1 and jobs[0].slices >= 10 and Draining.overlaps >= jobs[0].slices - 1
+    assert np.all(jobs[0].state["covered"] == 1)
 
 
 def test_phantoms_are_reused_while_resident():
