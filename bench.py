@@ -299,7 +299,7 @@ def main():
 def kernel_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("pmc_device.hpp", "pmc_kernels.hip"):
+    for f in ("pmc_device.hpp", "pmc_kernels.hip", "pmc_host.cpp"):
         with open(os.path.join(ROOT, "paper_1809_03927_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

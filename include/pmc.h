@@ -94,7 +94,8 @@ typedef struct {
   const int32_t *phases;  /* phase ids to simulate (spots of other phases are skipped) */
   int32_t n_phases;       /* 1..PMC_MAX_PHASES, distinct, all loaded */
   int32_t engine;         /* PMC_ENGINE_* */
-  int32_t block_size;     /* threads per block; 0 = library default (64..1024, multiple of 64) */
+  int32_t block_size;     /* threads per block, multiple of 64 in 64..1024 (FP64: ..256);
+                             0 = default (see pmc_launch_shape) */
   int32_t chunk;          /* persistent engine: histories per work item; 0 = default */
   int32_t refill_min;     /* persistent engine: refill when >= this many lanes of a wave are idle (1..64); 0 = default */
   int32_t grid_blocks;    /* persistent engine: blocks; 0 = enough to fill the device */
@@ -173,12 +174,36 @@ int pmc_load_spots(pmc_context *ctx, const pmc_field *fields, int32_t n_fields,
 /* Forget a plan and free the device data prepared for it. */
 int pmc_unload_plan(pmc_context *ctx, int32_t plan);
 
-/* Number of work items of a persistent-engine request (its histories cut
- * into runs of `chunk` histories of one spot, in spot order).  A request may
- * be run as several calls over consecutive item slices adding into the same
- * tallies and counters; together they equal one call over all items.
- * Prepares (and caches) the request's device data. */
+/* Number of work items of a persistent-engine request.  Each spot's
+ * histories are cut into runs of `chunk` (pmc_launch_shape); the work queue
+ * holds the first run of every spot in plan order, then the second run of
+ * every spot that has one, and so on, so that waves running together carry
+ * histories of many spots.  A request may be run as several calls over
+ * consecutive item slices adding into the same tallies and counters;
+ * together they equal one call over all items.  Prepares (and caches) the
+ * request's device data. */
 int pmc_request_items(pmc_context *ctx, const pmc_request *req, uint64_t *n_items);
+
+/* Work items of a persistent-engine request without preparing it: *n_items
+ * receives their number (as pmc_request_items) and, if histories is not
+ * NULL, histories[i] the number of histories of item i in queue order
+ * (PMC_E_INVAL if capacity is smaller than the count).  Lets a caller cut
+ * slices of a chosen number of histories.  Host-only (works on
+ * validation-only contexts, which assume 256 compute units for the default
+ * chunk). */
+int pmc_request_item_histories(pmc_context *ctx, const pmc_request *req, uint32_t *histories,
+                               uint64_t capacity, uint64_t *n_items);
+
+/* Launch shape the library uses for req: the request's own block_size,
+ * chunk and refill_min where nonzero, else the defaults.  Defaults: 1024
+ * threads per block for the FP32 persistent engine, 256 for FP64 and for the
+ * plain engine; histories per work item the largest of 256, 128, 64 for which
+ * the request still has about four work items per resident wave (16 waves per
+ * compute unit); refill at 64 idle lanes.  Plain engine: *chunk and
+ * *refill_min are 0.  Host-only (works on validation-only contexts, which
+ * assume 256 compute units).  NULL outputs are skipped. */
+int pmc_launch_shape(pmc_context *ctx, const pmc_request *req, int32_t *block_size, int32_t *chunk,
+                     int32_t *refill_min);
 
 /* ---- dose ------------------------------------------------------------------ */
 

@@ -381,6 +381,8 @@ int validate_request(pmc_context *ctx, const pmc_request *req) {
     return fail(ctx, PMC_E_INVAL, "unknown engine %d", req->engine);
   if (req->block_size != 0 && (req->block_size < 64 || req->block_size > 1024 || req->block_size % 64))
     return fail(ctx, PMC_E_INVAL, "block_size must be 0 or a multiple of 64 in [64, 1024]");
+  if (ctx->precision == PMC_FP64 && req->block_size > 256)
+    return fail(ctx, PMC_E_INVAL, "FP64 kernels take at most 256 threads per block");
   if (req->chunk < 0 || req->refill_min < 0 || req->refill_min > 64 || req->grid_blocks < 0)
     return fail(ctx, PMC_E_INVAL, "chunk, refill_min (0..64) and grid_blocks must be >= 0");
   if (req->flags & ~31u) return fail(ctx, PMC_E_INVAL, "unknown flag bits 0x%x", req->flags);
@@ -437,9 +439,66 @@ TargetDev make_target(const PhaseRec &ph, unsigned long long *tally, int32_t lut
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int default_chunk(const pmc_request *req) { return req->chunk > 0 ? req->chunk : 256; }
+// Launch shape of a request: its own values where set, else the defaults.
+// Threads per block: 1024 for the FP32 persistent engine (one block fills a
+// CU's wave slots that the LDS tables and registers allow: 16 waves), the
+// launch bound 256 for FP64 and for the plain engine.  Histories per work
+// item: the largest of 256, 128, 64 that still hands each resident wave about
+// four items, so that a small request spreads over the whole device instead of
+// running several histories in a row on the lanes of a few waves.
+struct LaunchShape {
+  int32_t block, chunk, refill;
+};
+
+LaunchShape launch_shape(const pmc_context *ctx, const pmc_request *req) {
+  const bool persistent = req->engine == PMC_ENGINE_PERSISTENT;
+  LaunchShape s;
+  s.block = req->block_size ? req->block_size
+                            : (persistent && ctx->precision != PMC_FP64 ? 1024 : 256);
+  s.refill = persistent ? (req->refill_min ? req->refill_min : 64) : 0;
+  s.chunk = 0;
+  if (persistent) {
+    if (req->chunk > 0) {
+      s.chunk = req->chunk;
+    } else {
+      const uint64_t waves = 16ull * (uint64_t)(ctx->n_cu > 0 ? ctx->n_cu : 256);
+      s.chunk = 256;
+      while (s.chunk > 64 && req->n_histories < 4ull * waves * (uint64_t)s.chunk) s.chunk >>= 1;
+    }
+  }
+  return s;
+}
+
+int default_chunk(const pmc_context *ctx, const pmc_request *req) { return launch_shape(ctx, req).chunk; }
 
 constexpr size_t kMaxPrepared = 32;
+
+// Work items of spots [s0, s1) in queue order.  Each spot's histories are cut
+// into runs of `chunk`; the queue holds the first run of every spot (plan
+// order), then the second run of every spot that has one, and so on.  Waves
+// running at the same time then carry histories of many spots, which spreads
+// their tally atomics over many voxels; in plan order every resident wave
+// would deposit around the same spot's Bragg peak, and the memory-side atomics
+// on those few addresses would serialise.
+void build_items(const std::vector<int64_t> &per_spot, int64_t s0, int64_t s1, int64_t chunk,
+                 std::vector<WorkItem> &out) {
+  std::vector<int32_t> active;
+  for (int64_t s = s0; s < s1; ++s)
+    if (per_spot[s] > 0) active.push_back((int32_t)s);
+  for (int64_t h = 0; !active.empty(); h += chunk) {
+    size_t keep = 0;
+    for (int32_t s : active) {
+      WorkItem w;
+      w.spot = s;
+      w.h_begin = (uint32_t)h;
+      w.h_count = (uint32_t)std::min<int64_t>(chunk, per_spot[s] - h);
+      w.pad = 0;
+      out.push_back(w);
+      if (per_spot[s] > h + chunk) active[keep++] = s;
+    }
+    active.resize(keep);
+  }
+}
 
 
 void evict_lru(pmc_context *ctx) {
@@ -459,7 +518,7 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
   std::vector<int32_t> phases(req->phases, req->phases + req->n_phases);
   std::vector<uint64_t> versions;
   for (int32_t ph : phases) versions.push_back(ctx->phases[ph].version);
-  const int32_t chunk = req->engine == PMC_ENGINE_PERSISTENT ? default_chunk(req) : 0;
+  const int32_t chunk = req->engine == PMC_ENGINE_PERSISTENT ? default_chunk(ctx, req) : 0;
   for (auto &e : ctx->cache) {
     Prepared &C = *e;
     if (C.plan_id == req->plan && C.plan_version == plan.version && C.n_hist == req->n_histories &&
@@ -499,21 +558,9 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
                     (unsigned long long)q_working(ctx, sp.energy_MeV);
     }
   }
-  // work items (persistent engine): chunks of each spot's histories, spot order
+  // work items (persistent engine), in queue order
   std::vector<WorkItem> items;
-  if (req->engine == PMC_ENGINE_PERSISTENT) {
-    for (int64_t s = 0; s < n_spots; ++s) {
-      const int64_t n = P.per_spot[s];
-      for (int64_t h = 0; h < n; h += chunk) {
-        WorkItem w;
-        w.spot = (int32_t)s;
-        w.h_begin = (uint32_t)h;
-        w.h_count = (uint32_t)std::min<int64_t>(chunk, n - h);
-        w.pad = 0;
-        items.push_back(w);
-      }
-    }
-  }
+  if (req->engine == PMC_ENGINE_PERSISTENT) build_items(P.per_spot, 0, n_spots, chunk, items);
   P.n_items = (int32_t)items.size();
   // LUTs: one if all listed phases share it, else one per slot
   const size_t lut_elems = 2 * kLut;
@@ -586,6 +633,8 @@ struct BoxArgs {
   const pmc::BoxDev *boxes;
   unsigned long long *tally;
   long long bias;
+  const WorkItem *items;  // the batch's own work items (the spots whose boxes are in tally)
+  int32_t n_items;
 };
 
 template <typename R>
@@ -616,7 +665,7 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
       a.k0 = k0;
       a.k1 = k1;
       a.flags = req->flags;
-      a.block = req->block_size ? req->block_size : 256;
+      a.block = launch_shape(ctx, req).block;
       a.lut_lds = !fp64;
       a.counters = counters;
       HIP_TRY(ctx, pmc::launch_plain(a, fp64, st), "transport_plain launch");
@@ -645,6 +694,10 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     const uint64_t i_end = req->item_end ? req->item_end : (uint64_t)P.n_items;
     a.items = reinterpret_cast<const WorkItem *>(scratch_at(P.off_items)) + req->item_begin;
     a.n_items = (int32_t)(i_end - req->item_begin);
+    if (box) {
+      a.items = box->items;
+      a.n_items = box->n_items;
+    }
     a.targets = reinterpret_cast<const TargetDev *>(scratch_at(P.off_targets));
     a.n_targets = req->n_phases;
     a.luts = scratch_at(P.off_luts);
@@ -655,8 +708,9 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     a.k0 = k0;
     a.k1 = k1;
     a.flags = req->flags;
-    a.refill_min = req->refill_min ? req->refill_min : 64;
-    a.block = req->block_size ? req->block_size : 256;
+    const LaunchShape shape = launch_shape(ctx, req);
+    a.refill_min = shape.refill;
+    a.block = shape.block;
     a.lut_lds = !fp64 && P.same_lut;
     a.cursor = cursor;
     a.counters = counters;
@@ -1046,6 +1100,44 @@ int pmc_request_items(pmc_context *ctx, const pmc_request *req, uint64_t *n_item
   rc = ctx->precision == PMC_FP64 ? prepare<double>(ctx, req, &P) : prepare<float>(ctx, req, &P);
   if (rc) return rc;
   *n_items = (uint64_t)P->n_items;
+  return PMC_OK;
+}
+
+int pmc_launch_shape(pmc_context *ctx, const pmc_request *req, int32_t *block_size, int32_t *chunk,
+                     int32_t *refill_min) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  int rc = validate_request(ctx, req);
+  if (rc) return rc;
+  const LaunchShape s = launch_shape(ctx, req);
+  if (block_size) *block_size = s.block;
+  if (chunk) *chunk = s.chunk;
+  if (refill_min) *refill_min = s.refill;
+  return PMC_OK;
+}
+
+int pmc_request_item_histories(pmc_context *ctx, const pmc_request *req, uint32_t *histories,
+                               uint64_t capacity, uint64_t *n_items) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  int rc = validate_request(ctx, req);
+  if (rc) return rc;
+  if (req->engine != PMC_ENGINE_PERSISTENT)
+    return fail(ctx, PMC_E_INVAL, "work items belong to the persistent engine");
+  if (!n_items) return fail(ctx, PMC_E_INVAL, "n_items is NULL");
+  const PlanRec &plan = ctx->plans[req->plan];
+  const int64_t n_spots = (int64_t)plan.spots.size();
+  std::vector<int64_t> per_spot((size_t)n_spots, 0);
+  rc = split(plan.spots.data(), n_spots, req->phases, req->n_phases, req->n_histories, per_spot.data());
+  if (rc) return fail(ctx, rc, "history split failed (weights)");
+  std::vector<WorkItem> items;
+  build_items(per_spot, 0, n_spots, default_chunk(ctx, req), items);
+  *n_items = (uint64_t)items.size();
+  if (!histories) return PMC_OK;
+  if (capacity < (uint64_t)items.size())
+    return fail(ctx, PMC_E_INVAL, "the request has %zu work items, capacity is %llu", items.size(),
+                (unsigned long long)capacity);
+  for (size_t i = 0; i < items.size(); ++i) histories[i] = items[i].h_count;
   return PMC_OK;
 }
 
@@ -1576,7 +1668,7 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
   const int64_t chunk = P->chunk;
   // device boxes, tile layout and the work-item range of every spot
   std::vector<pmc::BoxDev> bd((size_t)n_spots);
-  std::vector<long long> offset((size_t)n_spots + 1, 0), item_first((size_t)n_spots + 1, 0);
+  std::vector<long long> offset((size_t)n_spots + 1, 0);
   long long largest = 0;
   for (int64_t s = 0; s < n_spots; ++s) {
     pmc::BoxDev &d = bd[s];
@@ -1594,7 +1686,6 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
     const long long padded = (ne + pmc::kTile - 1) / pmc::kTile * pmc::kTile;
     largest = std::max(largest, padded);
     offset[s + 1] = offset[s] + padded;
-    item_first[s + 1] = item_first[s] + (h + chunk - 1) / chunk;
   }
   // batches of consecutive spots whose boxes fit the scratch
   const size_t free_b = ctx->budget > ctx->used ? ctx->budget - ctx->used : 0;
@@ -1613,6 +1704,13 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
     max_spots = std::max<long long>(max_spots, cuts[b + 1] - cuts[b]);
   }
   const long long max_tiles = max_entries / pmc::kTile, max_chunks = (max_tiles + 1023) / 1024;
+  // each batch's work items, in queue order over its spots
+  std::vector<WorkItem> bitems;
+  std::vector<size_t> batch_first = {0};
+  for (size_t b = 0; b + 1 < cuts.size(); ++b) {
+    build_items(P->per_spot, cuts[b], cuts[b + 1], chunk, bitems);
+    batch_first.push_back(bitems.size());
+  }
   // work buffer layout
   size_t off = 0;
   const size_t o_boxes = off; off = align256(off + sizeof(pmc::BoxDev) * (size_t)n_spots);
@@ -1622,6 +1720,7 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
   const size_t o_count = off; off = align256(off + 2 * sizeof(uint32_t) * (size_t)max_tiles);  // count, keep
   const size_t o_toff = off; off = align256(off + sizeof(long long) * (size_t)max_tiles);
   const size_t o_coff = off; off = align256(off + sizeof(long long) * (size_t)(max_chunks + 1));
+  const size_t o_items = off; off = align256(off + sizeof(WorkItem) * bitems.size());
   ctx->inf_n_rows = -1;
   ctx->inf_nnz = 0;
   rc = ensure(ctx, ctx->inf_work, std::max<size_t>(off, 256), "influence work buffer");
@@ -1643,6 +1742,10 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
   hipStream_t st = ctx->stream;
   HIP_TRY(ctx, copy_sync(ctx, d_boxes, bd.data(), sizeof(pmc::BoxDev) * bd.size(), hipMemcpyHostToDevice),
           "upload boxes");
+  auto *d_items = reinterpret_cast<WorkItem *>(work + o_items);
+  if (!bitems.empty())
+    HIP_TRY(ctx, copy_sync(ctx, d_items, bitems.data(), sizeof(WorkItem) * bitems.size(),
+                           hipMemcpyHostToDevice), "upload batch work items");
   HIP_TRY(ctx, pmc::launch_fill_u64(counters, PMC_COUNTERS, 0ull, st), "counter reset");
   unsigned __int128 deposited = 0;
   uint64_t nnz = 0;
@@ -1655,15 +1758,14 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
     HIP_TRY(ctx, pmc::launch_fill_u64(scratch, entries, 0ull, st), "zero box tallies");
     HIP_TRY(ctx, pmc::launch_fill_u64(d_max, s1 - s0, 0ull, st), "zero maxima");
     HIP_TRY(ctx, pmc::launch_fill_u64(d_dep, 2, 0ull, st), "zero sums");
-    if (item_first[s1] > item_first[s0]) {
+    if (batch_first[b + 1] > batch_first[b]) {
       pmc_request br = rq;
-      br.item_begin = (uint64_t)item_first[s0];
-      br.item_end = (uint64_t)item_first[s1];
       unsigned long long *cursor = nullptr;
       hipEvent_t *cursor_done = nullptr;
       rc = take_cursor(ctx, st, &cursor, &cursor_done);
       if (rc) return rc;
-      const BoxArgs ba = {d_boxes, scratch, base};
+      const BoxArgs ba = {d_boxes, scratch, base, d_items + batch_first[b],
+                          (int32_t)(batch_first[b + 1] - batch_first[b])};
       rc = enqueue_prepared<R>(ctx, *P, &br, st, no_tally, counters, static_cast<unsigned char *>(P->buf.p),
                                cursor, true, &ba);
       if (rc) return rc;

@@ -31,7 +31,7 @@ ERROR_NAMES = {0: "PMC_OK", -1: "PMC_E_INVAL", -2: "PMC_E_NOPHASE", -3: "PMC_E_B
 
 # every symbol declared in include/pmc.h
 EXPORTS = ["pmc_create", "pmc_destroy", "pmc_last_error", "pmc_load_phase", "pmc_unload_phase",
-           "pmc_load_spots", "pmc_load_plan", "pmc_unload_plan", "pmc_request_items", "pmc_dose",
+           "pmc_load_spots", "pmc_load_plan", "pmc_unload_plan", "pmc_request_items", "pmc_request_item_histories", "pmc_launch_shape", "pmc_dose",
            "pmc_dose_device", "pmc_dose_device_notify", "pmc_balance_from_counters",
            "pmc_convert_device", "pmc_trace", "pmc_split_histories", "pmc_bytes_in_use",
            "pmc_graph_create", "pmc_graph_launch", "pmc_graph_destroy", "pmc_influence_boxes",
@@ -113,6 +113,9 @@ def lib():
         L.pmc_load_plan.argtypes = [vp, i32, vp, i32, vp, i64]
         L.pmc_unload_plan.argtypes = [vp, i32]
         L.pmc_request_items.argtypes = [vp, C.POINTER(pmc_request), C.POINTER(u64)]
+        L.pmc_request_item_histories.argtypes = [vp, C.POINTER(pmc_request), vp, u64, C.POINTER(u64)]
+        L.pmc_launch_shape.argtypes = [vp, C.POINTER(pmc_request), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.pmc_dose.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, C.POINTER(pmc_balance)]
         L.pmc_dose_device.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp]
         L.pmc_dose_device_notify.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, vp]
@@ -277,6 +280,21 @@ def pmc_request_items(ctx, req: Request) -> int:
     n = C.c_uint64(0)
     _check(lib().pmc_request_items(ctx, C.byref(req.c), C.byref(n)), ctx)
     return int(n.value)
+
+
+def pmc_request_item_histories(ctx, req: Request) -> np.ndarray:
+    """Histories of each work item of a persistent-engine request, queue order."""
+    n = C.c_uint64(0)
+    _check(lib().pmc_request_item_histories(ctx, C.byref(req.c), None, 0, C.byref(n)), ctx)
+    out = np.zeros(n.value, dtype=np.uint32)
+    _check(lib().pmc_request_item_histories(ctx, C.byref(req.c), _ptr(out), n.value, C.byref(n)), ctx)
+    return out
+
+
+def pmc_launch_shape(ctx, req: Request) -> dict:
+    b, c, r = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    _check(lib().pmc_launch_shape(ctx, C.byref(req.c), C.byref(b), C.byref(c), C.byref(r)), ctx)
+    return {"block_size": b.value, "chunk": c.value, "refill_min": r.value}
 
 
 def pmc_trace(ctx, phase_id: int, spot: int, history: int, request_id=0, flags=0,

@@ -88,7 +88,7 @@ def influence_nominal(ctx, phantoms, plan: W.Plan, n_phases: int, n_histories: i
 
 
 def run(n_histories=20_000_000, shape_xyz=(256, 256, 160), n_phases=10, depth=1, policy="small-first",
-        budget_bytes=0, log=None, plain=True, influence=True, slice_histories=None, n_streams=2):
+        budget_bytes=0, log=None, plain=True, influence=True, slice_histories=None, n_streams=1):
     import torch
     from . import pmc
     t0 = time.time()
@@ -147,7 +147,7 @@ def main():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-influence", action="store_true")
     p.add_argument("--slice-histories", type=int, default=0, help="0 = whole calculations")
-    p.add_argument("--streams", type=int, default=2)
+    p.add_argument("--streams", type=int, default=1)
     a = p.parse_args()
     res = run(a.histories, tuple(int(x) for x in a.grid.split(",")), a.phases, plain=not a.no_plain,
               influence=not a.no_influence, slice_histories=a.slice_histories or None,

@@ -17,10 +17,13 @@ This loop takes such requests as they arrive and
   large requests keep their arrival order and so a latency tail close to
   that of serving everything in arrival order (least-expected-slowdown and
   shortest-remaining-first orders are available too);
-* starts the next slice, on a second stream, as soon as the running one has
-  handed out its last work item (the kernel sets a pinned host flag), so
+* submits the next slice as soon as the running one has handed out its last
+  work item (the kernel sets a pinned host flag), on a second stream, so
   that the drain of one persistent launch (its last histories running at
-  falling occupancy) overlaps the start of the next instead of idling CUs.
+  falling occupancy) overlaps the start of the next instead of idling CUs,
+  while the choice of what runs next is made as late as possible (a request
+  arriving during a slice can still run next).  With one stream the next
+  slice waits for the running one to end.
 
 Slices of one request add into the same integer tally, and a history's random
 numbers depend only on (seed, request, spot, history), so the served dose of a
@@ -475,25 +478,13 @@ class SimExecutor(Executor):
 LUT_BYTES = 4096 * 2 * (4 + 8)  # per phase: density and stopping-power-ratio tables, FP32 and FP64
 
 
-def item_histories(per_spot: np.ndarray, chunk: int) -> np.ndarray:
-    """Histories of each work item: every spot's histories cut into chunks of
-    `chunk`, in spot order (the library's work items)."""
-    per_spot = np.asarray(per_spot, dtype=np.int64)
-    n_items = (per_spot + chunk - 1) // chunk
-    out = np.full(int(n_items.sum()), chunk, dtype=np.int64)
-    last = np.cumsum(n_items)[n_items > 0] - 1
-    rem = per_spot[n_items > 0] - (n_items[n_items > 0] - 1) * chunk
-    out[last] = rem
-    return out
-
-
 class GpuExecutor(Executor):
     """Runs jobs through libpmc on the current device; tallies and doses are
     torch-owned device buffers, phantoms and plans live in the context."""
 
     def __init__(self, ctx, phantoms: Dict[tuple, W.Phase], plans: Dict[int, W.Plan],
                  engine: int, launch: Optional[dict] = None, verify: bool = True,
-                 keep_doses: bool = False, n_streams: int = 1):
+                 keep_doses: bool = False, n_streams: int = 1, drain_signal: bool = True):
         import torch
         from . import pmc
         self.torch, self.pmc, self.ctx = torch, pmc, ctx
@@ -515,9 +506,11 @@ class GpuExecutor(Executor):
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.next_stream = 0
         # drain signals of persistent launches (pinned host words the kernel
-        # sets when every work item is taken): with two or more streams the
-        # next slice starts while the previous one drains
-        self.drain_flags = torch.zeros(64, dtype=torch.int32, pin_memory=True) if n_streams > 1 else None
+        # sets when every work item is taken): the scheduler then submits the
+        # next slice, which waits on its stream for the running one to end
+        persistent = engine == pmc.PMC_ENGINE_PERSISTENT
+        self.drain_flags = (torch.zeros(64, dtype=torch.int32, pin_memory=True)
+                            if drain_signal and persistent else None)
         self.free_flags = list(range(64))
         self.digests: Dict[int, str] = {}
         self.balances: Dict[int, dict] = {}
@@ -553,7 +546,8 @@ class GpuExecutor(Executor):
 
     def job_bytes(self, job: Job) -> int:
         n_spots = len(self.plans[job.index].spots)
-        items = job.n_histories // max(1, self.launch.get("chunk") or 256) + n_spots
+        # the library's default work item holds 64 to 256 histories
+        items = job.n_histories // max(1, self.launch.get("chunk") or 64) + n_spots
         # tally + dose + counters; spot descriptors, work items, LUT copy, targets
         return job.nvox * 16 + 128 + n_spots * 96 + items * 16 + 65536
 
@@ -591,8 +585,7 @@ class GpuExecutor(Executor):
         if persistent:
             job.n_items = pmc.pmc_request_items(self.ctx, req)
             if sliced:
-                job.item_hist = item_histories(pmc.pmc_split_histories(spots, [slot], job.n_histories),
-                                               kw.get("chunk") or 256)
+                job.item_hist = pmc.pmc_request_item_histories(self.ctx, req)
                 if len(job.item_hist) != job.n_items:
                     raise RuntimeError("work-item count differs from the library's")
         else:
@@ -723,9 +716,10 @@ def log_uniform_mean(lo: float, hi: float) -> float:
 def serve_gpu(ctx, reqs, phantoms, plans, engine: int, policy: str, budget: int,
               launch: Optional[dict] = None, slice_histories: int = 4_000_000, log=None,
               keep_doses: bool = False, depth: int = 1, rate_hist_per_s: float = 1.3e8,
-              n_streams: int = 1, small_histories: float = 2.2e6):
+              n_streams: int = 1, small_histories: float = 2.2e6, drain_signal: bool = True):
     """Serve `reqs` on the GPU in real time; returns (summary, executor, scheduler)."""
-    ex = GpuExecutor(ctx, phantoms, plans, engine, launch, keep_doses=keep_doses, n_streams=n_streams)
+    ex = GpuExecutor(ctx, phantoms, plans, engine, launch, keep_doses=keep_doses, n_streams=n_streams,
+                     drain_signal=drain_signal)
     sched = Scheduler(ex, WallClock(), budget, policy=policy, slice_histories=slice_histories,
                       log=log, depth=depth, rate_hist_per_s=rate_hist_per_s,
                       small_histories=small_histories)
@@ -735,7 +729,8 @@ def serve_gpu(ctx, reqs, phantoms, plans, engine: int, policy: str, budget: int,
     s["per_request"] = [[j.index, j.n_histories, j.arrival_s, j.first_run_s, j.done_s] for j in done]
     s.update(slices=sched.slices, evictions=sched.evictions, phantom_loads=sched.phantom_loads,
              peak_bytes=sched.peak_used, budget_bytes=budget, slices_in_flight=depth,
-             streams=n_streams, slice_histories=slice_histories)
+             streams=n_streams, drain_signal=ex.drain_flags is not None,
+             slice_histories=slice_histories)
     return s, ex, sched
 
 
@@ -777,7 +772,8 @@ def prebuild(n_requests=200, seed=4, h_lo=1e5, h_hi=5e7, workers=0, log=None):
 
 def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_hi=5e7,
                  slice_histories=4_000_000, launch=None, workers=0, log=None, depth=1,
-                 policy="small-first", plain=True, n_streams=2, prebuilt=None, small=2.2e6):
+                 policy="small-first", plain=True, n_streams=2, prebuilt=None, small=2.2e6,
+                 drain_signal=True):
     """Serve one Poisson stream with the sliced persistent engine (`policy`,
     `depth` slices in flight) and with the plain engine run serially in
     arrival order.  Arrival rate = load x plain throughput / mean request
@@ -805,7 +801,7 @@ def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_h
             s, ex, _ = serve_gpu(ctx, reqs, phantoms, plans, engine, pol, budget, launch,
                                  slice_histories, log, depth=d, rate_hist_per_s=rate_plain,
                                  n_streams=n_streams if engine == pmc.PMC_ENGINE_PERSISTENT else 1,
-                                 small_histories=small)
+                                 small_histories=small, drain_signal=drain_signal)
             for key in list(ex.slot_of):
                 ex.unload_phantom(key)
             out[label] = s
@@ -830,6 +826,8 @@ def main():
     p.add_argument("--slice-histories", type=int, default=4_000_000)
     p.add_argument("--workers", type=int, default=8)
     p.add_argument("--depth", type=int, default=1, help="slices handing out work at once")
+    p.add_argument("--no-drain-signal", action="store_true",
+                   help="submit the next slice only when the running one has finished")
     p.add_argument("--streams", type=int, default=2,
                    help="submission streams (>= 2: the next slice starts while the previous drains)")
     p.add_argument("--policy", choices=["small-first", "slowdown", "srpt", "fifo"], default="small-first")
@@ -841,6 +839,7 @@ def main():
     res = run_scenario(a.requests, a.load, a.seed, int(a.budget_gb * 2**30),
                        slice_histories=a.slice_histories, workers=a.workers, depth=a.depth,
                        policy=a.policy, plain=not a.no_plain, n_streams=a.streams, small=a.small,
+                       drain_signal=not a.no_drain_signal,
                        launch={"block_size": a.block} if a.block else None,
                        log=lambda m: print("[serve]", m, file=sys.stderr, flush=True))
     if not a.per_request:

@@ -133,6 +133,44 @@ def test_dose_validation_order(P, vctx):
     assert e.value.code == P.PMC_E_NOPHASE
 
 
+def test_launch_shape_defaults(P):
+    """Default work items shrink for small requests so that every resident
+    wave (16 per compute unit, 256 units assumed without a device) gets about
+    four of them; explicit values pass through."""
+    ctx = P.pmc_create(device=-1)
+    try:
+        plan = W.plan_single(150.0, 5.0)
+        P.pmc_load_spots(ctx, plan.fields, plan.spots)
+        P.pmc_load_phase(ctx, 0, W.make_water(8, 2.0))
+        waves = 16 * 256
+        pers = P.PMC_ENGINE_PERSISTENT
+        for n, chunk in [(1, 64), (4 * waves * 128 - 1, 64), (4 * waves * 128, 128),
+                         (4 * waves * 256 - 1, 128), (4 * waves * 256, 256), (P.PMC_MAX_HISTORIES, 256)]:
+            got = P.pmc_launch_shape(ctx, P.Request(n, [0], engine=pers))
+            assert got == {"block_size": 1024, "chunk": chunk, "refill_min": 64}, n
+        got = P.pmc_launch_shape(ctx, P.Request(10, [0], engine=pers, block_size=512, chunk=7,
+                                                refill_min=3))
+        assert got == {"block_size": 512, "chunk": 7, "refill_min": 3}
+        assert P.pmc_launch_shape(ctx, P.Request(10, [0])) == {"block_size": 256, "chunk": 0,
+                                                               "refill_min": 0}
+        with pytest.raises(P.PmcError):
+            P.pmc_launch_shape(ctx, P.Request(10, [0], block_size=100))
+    finally:
+        P.pmc_destroy(ctx)
+    ctx = P.pmc_create(device=-1, precision=P.PMC_FP64)
+    try:
+        plan = W.plan_single(150.0, 5.0)
+        P.pmc_load_spots(ctx, plan.fields, plan.spots)
+        P.pmc_load_phase(ctx, 0, W.make_water(8, 2.0))
+        assert P.pmc_launch_shape(ctx, P.Request(10 ** 7, [0], engine=P.PMC_ENGINE_PERSISTENT)) == {
+            "block_size": 256, "chunk": 256, "refill_min": 64}
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_launch_shape(ctx, P.Request(10, [0], block_size=512))
+        assert e.value.code == P.PMC_E_INVAL
+    finally:
+        P.pmc_destroy(ctx)
+
+
 @pytest.mark.parametrize("wl_name", ["slabs", "thorax"])
 def test_split_matches_oracle(P, orc, wl_name):
     plan = W.plan_slabs(2) if wl_name == "slabs" else W.plan_thorax(3)

@@ -134,16 +134,17 @@ def test_served_equals_plain_serial():
         tight = probe.job_bytes(j3) + probe.phantom_bytes(j3.phantom_key) + 2**20
         assert sum(probe.phantom_bytes(r.phantom_key) for r in reqs[:3]) > 2**20
         out = {}
-        for label, engine, policy, budget, depth, streams in (
-                ("slowdown", pmc.PMC_ENGINE_PERSISTENT, "slowdown", 2 * 2**30, 2, 1),
-                ("small-first-drain", pmc.PMC_ENGINE_PERSISTENT, "small-first", 2 * 2**30, 1, 2),
-                ("srpt-tight", pmc.PMC_ENGINE_PERSISTENT, "srpt", tight, 2, 2),
-                ("srpt-depth1", pmc.PMC_ENGINE_PERSISTENT, "srpt", 2 * 2**30, 1, 1),
-                ("plain", pmc.PMC_ENGINE_PLAIN, "fifo", 2 * 2**30, 1, 1)):
+        for label, engine, policy, budget, depth, streams, drain in (
+                ("slowdown", pmc.PMC_ENGINE_PERSISTENT, "slowdown", 2 * 2**30, 2, 1, False),
+                ("small-first", pmc.PMC_ENGINE_PERSISTENT, "small-first", 2 * 2**30, 1, 1, True),
+                ("small-first-2", pmc.PMC_ENGINE_PERSISTENT, "small-first", 2 * 2**30, 1, 2, True),
+                ("srpt-tight", pmc.PMC_ENGINE_PERSISTENT, "srpt", tight, 2, 2, False),
+                ("srpt-depth1", pmc.PMC_ENGINE_PERSISTENT, "srpt", 2 * 2**30, 1, 1, True),
+                ("plain", pmc.PMC_ENGINE_PLAIN, "fifo", 2 * 2**30, 1, 1, False)):
             say("serve", label)
             s, ex, sched = S.serve_gpu(ctx, reqs, phantoms, plans, engine, policy, budget,
                                        launch={"chunk": 64}, slice_histories=50_000, keep_doses=True,
-                                       depth=depth, n_streams=streams)
+                                       depth=depth, n_streams=streams, drain_signal=drain)
             assert s["requests"] == len(reqs)
             assert sched.peak_used <= budget
             if label == "slowdown":
@@ -157,7 +158,7 @@ def test_served_equals_plain_serial():
         for r in reqs:
             d = out["plain"].doses[r.index]
             assert np.isfinite(d).all() and d.max() > 0
-            for label in ("slowdown", "small-first-drain", "srpt-tight", "srpt-depth1"):
+            for label in ("slowdown", "small-first", "small-first-2", "srpt-tight", "srpt-depth1"):
                 assert np.array_equal(out[label].doses[r.index], d), (label, r.index)
                 assert out[label].balances[r.index] == out["plain"].balances[r.index]
         assert pmc.pmc_bytes_in_use(ctx) >= 0

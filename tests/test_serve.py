@@ -216,11 +216,27 @@ def test_log_uniform_mean():
     assert S.log_uniform_mean(1e5, 5e7) == pytest.approx(x.mean(), rel=5e-3)
 
 
-def test_item_histories_match_the_library_rule():
-    per = np.array([0, 5, 256, 257, 1000, 0, 1])
-    got = S.item_histories(per, 256)
-    want = []
-    for n in per:
-        want += [256] * (n // 256) + ([n % 256] if n % 256 else [])
-    assert got.tolist() == want
-    assert S.item_histories(np.zeros(3, dtype=np.int64), 64).size == 0
+def test_library_work_items_round_robin_over_spots():
+    """The work queue (validation-only context): each spot's histories in runs
+    of `chunk`, first runs of all spots in plan order, then second runs, ..."""
+    from paper_1809_03927_amd import pmc
+    ctx = pmc.pmc_create(device=-1)
+    try:
+        plan = W.plan_thorax(3, n_layers=2, grid=(3, 2))
+        pmc.pmc_load_phase(ctx, 0, W.make_water(8, 2.0))
+        sp = plan.spots.copy()
+        sp["phase"] = 0
+        sp["phase"][4] = 1  # on a phase the request does not list: no histories
+        pmc.pmc_load_plan(ctx, 0, plan.fields, sp)
+        for n, chunk in [(2000, 64), (5000, 128), (7, 0)]:
+            req = pmc.Request(n, [0], engine=pmc.PMC_ENGINE_PERSISTENT, chunk=chunk)
+            c = pmc.pmc_launch_shape(ctx, req)["chunk"]
+            per = pmc.pmc_split_histories(sp, [0], n)
+            want, r = [], 0
+            while any(h > r * c for h in per):
+                want += [min(c, h - r * c) for h in per if h > r * c]
+                r += 1
+            got = pmc.pmc_request_item_histories(ctx, req)
+            assert got.tolist() == want and got.sum() == n
+    finally:
+        pmc.pmc_destroy(ctx)
