@@ -58,6 +58,19 @@ extern "C" {
 #define PMC_ENGINE_PLAIN 0      /* one launch per phase, one history per thread */
 #define PMC_ENGINE_PERSISTENT 1 /* one launch for all phases: work queue + lane refill */
 
+/* Where the persistent engine adds deposits (pmc_request.tally_mode).
+ * LANE: each lane adds a voxel visit's deposit into the phase tally (one
+ *   device-wide atomic per visit); waves take work items on their own.
+ * CORE: a block of 1024 threads runs one work item at a time; deposits inside
+ *   the spot's core box (the central part of the voxel box around its beam
+ *   axis that fits the block's LDS) add into LDS, the block adds each nonzero
+ *   core voxel into the phase tally once the item is done, and the other
+ *   deposits go to the phase tally directly.  Fewer device-wide atomics; the
+ *   integer tallies are identical.  FP32 only. */
+#define PMC_TALLY_AUTO 0
+#define PMC_TALLY_LANE 1
+#define PMC_TALLY_CORE 2
+
 typedef struct pmc_context pmc_context;
 
 typedef struct {
@@ -100,7 +113,7 @@ typedef struct {
   int32_t refill_min;     /* persistent engine: refill when >= this many lanes of a wave are idle (1..64); 0 = default */
   int32_t grid_blocks;    /* persistent engine: blocks; 0 = enough to fill the device */
   int32_t plan;           /* plan id (pmc_load_plan; pmc_load_spots loads plan 0) */
-  int32_t reserved;       /* must be 0 */
+  int32_t tally_mode;     /* persistent engine: PMC_TALLY_*; 0 = library's choice */
   uint64_t item_begin;    /* persistent engine: run only work items [item_begin, item_end) */
   uint64_t item_end;      /*   of the request (0, 0 = all); see pmc_request_items */
 } pmc_request;
@@ -194,16 +207,31 @@ int pmc_request_items(pmc_context *ctx, const pmc_request *req, uint64_t *n_item
 int pmc_request_item_histories(pmc_context *ctx, const pmc_request *req, uint32_t *histories,
                                uint64_t capacity, uint64_t *n_items);
 
-/* Launch shape the library uses for req: the request's own block_size,
- * chunk and refill_min where nonzero, else the defaults.  Defaults: 1024
- * threads per block for the FP32 persistent engine, 256 for FP64 and for the
- * plain engine; histories per work item the largest of 256, 128, 64 for which
- * the request still has about four work items per resident wave (16 waves per
- * compute unit); refill at 64 idle lanes.  Plain engine: *chunk and
- * *refill_min are 0.  Host-only (works on validation-only contexts, which
- * assume 256 compute units).  NULL outputs are skipped. */
-int pmc_launch_shape(pmc_context *ctx, const pmc_request *req, int32_t *block_size, int32_t *chunk,
-                     int32_t *refill_min);
+/* Launch shape the library uses for req (pmc_launch_shape). */
+typedef struct {
+  int32_t block_size;    /* threads per block */
+  int32_t chunk;         /* histories per work item (persistent engine) */
+  int32_t refill_min;    /* lane refill threshold (persistent engine) */
+  int32_t tally_mode;    /* PMC_TALLY_LANE or PMC_TALLY_CORE (persistent engine), else 0 */
+  int32_t core_capacity; /* PMC_TALLY_CORE: LDS tally entries per block, else 0 */
+  int32_t reserved[3];
+} pmc_shape;
+
+/* Launch shape the library uses for req: the request's own values where
+ * set, else the defaults.
+ *  - tally_mode: PMC_TALLY_CORE when the FP32 persistent engine runs a large
+ *    request whose spots have many histories each (work items of `chunk`
+ *    histories averaging at least 4096, at least 4 per compute unit, and room
+ *    for 4096 core entries in LDS), else PMC_TALLY_LANE.
+ *  - block_size: 1024 for the FP32 persistent engine (PMC_TALLY_CORE takes
+ *    only 1024), 256 for FP64 and for the plain engine.
+ *  - chunk: PMC_TALLY_CORE 8192; PMC_TALLY_LANE the largest of 256, 128, 64
+ *    for which the request still has about four work items per resident wave
+ *    (16 waves per compute unit).
+ *  - refill_min: 64.
+ * Host-only (works on validation-only contexts, which assume 256 compute
+ * units and 160 KiB of LDS per block). */
+int pmc_launch_shape(pmc_context *ctx, const pmc_request *req, pmc_shape *out);
 
 /* ---- dose ------------------------------------------------------------------ */
 

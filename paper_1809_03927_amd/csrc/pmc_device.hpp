@@ -161,7 +161,16 @@ template <typename R> struct Geo {
   int32_t lut;  // index of the phase's LUT in the launch's LUT array
 };
 
-// the box a lane's spot tallies into (influence calculations)
+// Where a lane's deposits go:
+//   kTallyGrid  the phase tally (one global atomic per voxel visit)
+//   kTallyBox   the spot's box tally (influence calculations); deposits
+//               outside the box are only counted
+//   kTallyCore  inside the spot's core box: the block's LDS copy of the core
+//               (flushed into the phase tally when the block is done with the
+//               spot); outside it: the phase tally
+constexpr int kTallyGrid = 0, kTallyBox = 1, kTallyCore = 2;
+
+// the box a lane's spot tallies into (kTallyBox: global, kTallyCore: LDS)
 struct BoxLane {
   unsigned long long *base;  // entry 0 of the box
   int32_t lo[3], n[3];
@@ -186,8 +195,18 @@ __device__ __forceinline__ void set3(T &x0, T &x1, T &x2, int k, T v) {
   x2 = k == 2 ? v : x2;
 }
 
+// Pointers that reach a kernel through device memory (tables of targets,
+// geometry in LDS) are generic to the compiler, which then emits flat
+// instructions; on CDNA those also count against the LDS wait counter, so an
+// LDS table read after a tally atomic would wait for the atomic to complete.
+// Tallies, HU grids and masks live in device memory: address them as global.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+
 __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned long long v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(as_global(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,9 +405,9 @@ __device__ __forceinline__ void start_history(Lane<R> &L, const SpotDev<R> &sp, 
   L.iz = idx[2];
   const int v = idx[0] + G.n[0] * (idx[1] + G.n[1] * idx[2]);
   L.v = missed ? -1 : v;
-  const int hu = G.hu[v];  // v is in range in both cases (0 when missed)
+  const int hu = as_global(G.hu)[v];  // v is in range in both cases (0 when missed)
   L.hu = clamp_hu<R>(hu);
-  L.vac = (G.mask && !missed) ? (G.mask[v] == 0) : 0;
+  L.vac = (G.mask && !missed) ? (as_global(G.mask)[v] == 0) : 0;
   L.fate = missed ? kMissed : kAlive;
   if (missed) {
     C.esc += (unsigned long long)M<R>::q(L.E);
@@ -396,53 +415,64 @@ __device__ __forceinline__ void start_history(Lane<R> &L, const SpotDev<R> &sp, 
   }
 }
 
-// Tally key of a deposit: the voxel index, or with BOX the box-local entry
-// (-2 outside the box).  The lane is still in the voxel of the step.
-template <typename R, bool BOX>
+// Tally key of a deposit.  kTallyGrid: the voxel index; kTallyBox: the
+// box-local entry, -2 outside the box; kTallyCore: -3 - (core-local entry)
+// inside the core, else the voxel index.  The lane is still in the voxel of
+// the step.
+template <typename R, int TM>
 __device__ __forceinline__ int32_t tally_key(const Lane<R> &L, const BoxLane &B, int32_t v) {
-  if constexpr (!BOX) {
+  if constexpr (TM == kTallyGrid) {
     return v;
   } else {
     const int32_t x = L.ix - B.lo[0], y = L.iy - B.lo[1], z = L.iz - B.lo[2];
     const bool in = (uint32_t)x < (uint32_t)B.n[0] && (uint32_t)y < (uint32_t)B.n[1] &&
                     (uint32_t)z < (uint32_t)B.n[2];
-    return in ? x + B.n[0] * (y + B.n[1] * z) : -2;
+    const int32_t e = x + B.n[0] * (y + B.n[1] * z);
+    if constexpr (TM == kTallyBox) return in ? e : -2;
+    else return in ? -3 - e : v;
   }
 }
 
-template <typename R, bool BOX>
+template <typename R, int TM>
 __device__ __forceinline__ void commit_acc(const Lane<R> &L, const Geo<R> &G, const BoxLane &B,
                                            LaneCounters &C) {
   if (L.acc == 0) return;
-  if constexpr (BOX) {
+  if constexpr (TM == kTallyBox) {
     if (L.acc_v < 0) {
       C.out += (unsigned long long)L.acc;
       return;
     }
     atomic_add_u64(&B.base[L.acc_v], (unsigned long long)L.acc);
+  } else if constexpr (TM == kTallyCore) {
+    if (L.acc_v <= -3) {  // LDS: the block's copy of the core
+      __hip_atomic_fetch_add(&B.base[-3 - L.acc_v], (unsigned long long)L.acc, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+      return;
+    }
+    atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
   } else {
     atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
   }
   C.atomics += 1;
 }
 
-template <typename R, bool BOX = false>
+template <typename R, int TM = kTallyGrid>
 __device__ __forceinline__ void flush_tally(Lane<R> &L, const Geo<R> &G, LaneCounters &C,
                                             const BoxLane &B = BoxLane{}) {
-  commit_acc<R, BOX>(L, G, B, C);
+  commit_acc<R, TM>(L, G, B, C);
   L.acc = 0;
   L.acc_v = -1;
 }
 
 // consecutive deposits into the same voxel are merged in registers: at most
-// one global atomic per voxel visit
-template <typename R, bool BOX>
+// one atomic per voxel visit
+template <typename R, int TM>
 __device__ __forceinline__ void add_tally(Lane<R> &L, const Geo<R> &G, const BoxLane &B, int32_t v,
                                           long long dep, LaneCounters &C) {
   if (dep == 0) return;
-  const int32_t key = tally_key<R, BOX>(L, B, v);
+  const int32_t key = tally_key<R, TM>(L, B, v);
   if (key != L.acc_v) {
-    commit_acc<R, BOX>(L, G, B, C);
+    commit_acc<R, TM>(L, G, B, C);
     L.acc_v = key;
     L.acc = dep;
   } else {
@@ -478,7 +508,7 @@ __device__ __forceinline__ void trace_out(TraceRec *rec, int n, int max_rec, int
 // ---------------------------------------------------------------------------
 // one condensed-history step
 // ---------------------------------------------------------------------------
-template <typename R, bool TRACE, bool BOX = false>
+template <typename R, bool TRACE, int TM = kTallyGrid>
 __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &T,
                                      const typename M<R>::R2 *lut, uint32_t k0, uint32_t k1,
                                      uint32_t flags, LaneCounters &C, TraceRec *rec, int max_rec,
@@ -511,8 +541,8 @@ __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &
   const int v_nb = L.v + (ax_pos ? stride : -stride);
   int hu_nb = 0, mask_nb = 1;
   if (nb_in) {
-    hu_nb = G.hu[v_nb];
-    if (G.mask) mask_nb = G.mask[v_nb];
+    hu_nb = as_global(G.hu)[v_nb];
+    if (G.mask) mask_nb = as_global(G.mask)[v_nb];
   }
 
   // 3-4. physics limits; priority on ties stop > geo > delta > nuclear > phys
@@ -636,7 +666,7 @@ __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &
       C.nuc_ev += 1;
       L.fate = kNuclear;
     }
-    add_tally<R, BOX>(L, G, B, v_step, dep, C);
+    add_tally<R, TM>(L, G, B, v_step, dep, C);
   }
   C.steps += 1;
   L.nsteps += 1;

@@ -79,7 +79,7 @@ struct Prepared {
   uint64_t plan_version = 0, n_hist = 0;
   std::vector<int32_t> phases;
   std::vector<uint64_t> phase_versions;
-  int32_t engine = -1, chunk = -1, precision = -1;
+  int32_t engine = -1, chunk = -1, precision = -1, mode = 0;
   // host side
   std::vector<int64_t> per_spot;
   std::vector<std::vector<int32_t>> list;      // per slot: spots with histories
@@ -89,7 +89,8 @@ struct Prepared {
   bool same_lut = true;
   unsigned __int128 incident = 0;
   // device offsets into the request scratch buffer
-  size_t off_spots = 0, off_items = 0, off_luts = 0, off_targets = 0;
+  size_t off_spots = 0, off_items = 0, off_luts = 0, off_targets = 0, off_cores = 0;
+  int32_t core_cap = 0;  // PMC_TALLY_CORE: LDS tally entries per block
   std::vector<size_t> off_ids, off_first;
   std::vector<unsigned char> staging;  // host image uploaded into the scratch
   std::vector<TargetDev> targets;      // last uploaded target table
@@ -118,6 +119,7 @@ struct pmc_context {
   uint64_t used = 0;
   bool has_device = false;
   int n_cu = 0;
+  size_t lds_max = 160 * 1024;  // LDS bytes a block may use (device property)
   std::string err;
   pmc::Tables tabs;
   void *d_tab = nullptr;
@@ -386,7 +388,14 @@ int validate_request(pmc_context *ctx, const pmc_request *req) {
   if (req->chunk < 0 || req->refill_min < 0 || req->refill_min > 64 || req->grid_blocks < 0)
     return fail(ctx, PMC_E_INVAL, "chunk, refill_min (0..64) and grid_blocks must be >= 0");
   if (req->flags & ~31u) return fail(ctx, PMC_E_INVAL, "unknown flag bits 0x%x", req->flags);
-  if (req->reserved != 0) return fail(ctx, PMC_E_INVAL, "reserved field must be 0");
+  if (req->tally_mode < PMC_TALLY_AUTO || req->tally_mode > PMC_TALLY_CORE)
+    return fail(ctx, PMC_E_INVAL, "unknown tally_mode %d", req->tally_mode);
+  if (req->tally_mode == PMC_TALLY_CORE) {
+    if (req->engine != PMC_ENGINE_PERSISTENT || ctx->precision != PMC_FP32)
+      return fail(ctx, PMC_E_INVAL, "PMC_TALLY_CORE needs the FP32 persistent engine");
+    if (req->block_size != 0 && req->block_size != pmc::kCoreBlock)
+      return fail(ctx, PMC_E_INVAL, "PMC_TALLY_CORE runs %d threads per block", pmc::kCoreBlock);
+  }
   if (req->engine == PMC_ENGINE_PLAIN && (req->item_begin || req->item_end))
     return fail(ctx, PMC_E_INVAL, "work-item slices need the persistent engine");
   if (req->item_end && req->item_end < req->item_begin)
@@ -443,25 +452,67 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Threads per block: 1024 for the FP32 persistent engine (one block fills a
 // CU's wave slots that the LDS tables and registers allow: 16 waves), the
 // launch bound 256 for FP64 and for the plain engine.  Histories per work
-// item: the largest of 256, 128, 64 that still hands each resident wave about
-// four items, so that a small request spreads over the whole device instead of
-// running several histories in a row on the lanes of a few waves.
+// item (lane mode): the largest of 256, 128, 64 that still hands each
+// resident wave about four items, so that a small request spreads over the
+// whole device instead of running several histories in a row on the lanes of
+// a few waves.  Core mode: items of 8192 histories (8 per lane of a block),
+// so that the wait of a block's waves for its item's last history, and the
+// flush of the core, are small against the item.
 struct LaunchShape {
-  int32_t block, chunk, refill;
+  int32_t block, chunk, refill, mode, core_cap;
 };
 
+constexpr int32_t kCoreChunk = 8192;
+constexpr int32_t kCoreMinEntries = 4096;
+
+bool same_lut(const pmc_context *ctx, const pmc_request *req) {
+  for (int32_t i = 1; i < req->n_phases; ++i)
+    if (ctx->phases.at(req->phases[i]).lut64 != ctx->phases.at(req->phases[0]).lut64) return false;
+  return true;
+}
+
+int32_t core_capacity(const pmc_context *ctx, bool lut_lds) {
+  const size_t fixed = pmc::core_fixed_lds(lut_lds);
+  if (ctx->lds_max <= fixed) return 0;
+  return (int32_t)std::min<size_t>((ctx->lds_max - fixed) / sizeof(unsigned long long), 1u << 30);
+}
+
+// Requires a validated request.
 LaunchShape launch_shape(const pmc_context *ctx, const pmc_request *req) {
   const bool persistent = req->engine == PMC_ENGINE_PERSISTENT;
+  const bool fp32 = ctx->precision != PMC_FP64;
   LaunchShape s;
-  s.block = req->block_size ? req->block_size
-                            : (persistent && ctx->precision != PMC_FP64 ? 1024 : 256);
   s.refill = persistent ? (req->refill_min ? req->refill_min : 64) : 0;
+  s.mode = persistent ? req->tally_mode : 0;
+  s.core_cap = 0;
+  const int64_t n_cu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+  if (persistent && s.mode == PMC_TALLY_AUTO) {
+    s.mode = PMC_TALLY_LANE;
+    const int32_t cap = fp32 ? core_capacity(ctx, same_lut(ctx, req)) : 0;
+    if (cap >= kCoreMinEntries && (req->block_size == 0 || req->block_size == pmc::kCoreBlock)) {
+      const int64_t chunk = req->chunk > 0 ? req->chunk : kCoreChunk;
+      const std::vector<pmc_spot> &sp = ctx->plans.at(req->plan).spots;
+      std::vector<int64_t> per(sp.size(), 0);
+      if (split(sp.data(), (int64_t)sp.size(), req->phases, req->n_phases, req->n_histories, per.data()) == 0) {
+        int64_t items = 0;
+        for (int64_t h : per) items += (h + chunk - 1) / chunk;
+        if (items >= 4 * n_cu && (int64_t)req->n_histories >= 4096 * items) s.mode = PMC_TALLY_CORE;
+      }
+    }
+  }
+  if (s.mode == PMC_TALLY_CORE) {
+    s.block = pmc::kCoreBlock;
+    s.chunk = req->chunk > 0 ? req->chunk : kCoreChunk;
+    s.core_cap = core_capacity(ctx, same_lut(ctx, req));
+    return s;
+  }
+  s.block = req->block_size ? req->block_size : (persistent && fp32 ? 1024 : 256);
   s.chunk = 0;
   if (persistent) {
     if (req->chunk > 0) {
       s.chunk = req->chunk;
     } else {
-      const uint64_t waves = 16ull * (uint64_t)(ctx->n_cu > 0 ? ctx->n_cu : 256);
+      const uint64_t waves = 16ull * (uint64_t)n_cu;
       s.chunk = 256;
       while (s.chunk > 64 && req->n_histories < 4ull * waves * (uint64_t)s.chunk) s.chunk >>= 1;
     }
@@ -470,6 +521,39 @@ LaunchShape launch_shape(const pmc_context *ctx, const pmc_request *req) {
 }
 
 int default_chunk(const pmc_context *ctx, const pmc_request *req) { return launch_shape(ctx, req).chunk; }
+
+pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s);
+
+// Core box of a spot: its voxel box if that fits `cap` entries, else the box's
+// full extent along the beam's main axis and a window across it, centred in
+// the box, with the box's aspect ratio and at most `cap` entries in all.
+pmc::CoreDev core_of(const pmc_box &b, const pmc_field &f, int32_t cap) {
+  pmc::CoreDev c = {};
+  int64_t n[3];
+  for (int k = 0; k < 3; ++k) {
+    c.lo[k] = b.lo[k];
+    n[k] = b.hi[k] > b.lo[k] ? b.hi[k] - b.lo[k] : 0;
+  }
+  if (n[0] * n[1] * n[2] == 0 || cap <= 0) return c;
+  if (n[0] * n[1] * n[2] > cap) {
+    int d = 0;
+    for (int k = 1; k < 3; ++k)
+      if (std::fabs(f.direction[k]) > std::fabs(f.direction[d])) d = k;
+    const int a = (d + 1) % 3, e = (d + 2) % 3;
+    const int64_t cells = cap / n[d];
+    if (cells < 1) return c;  // not even the axis fits: no core
+    int64_t wa = (int64_t)std::floor(std::sqrt((double)cells * (double)n[a] / (double)n[e]));
+    wa = std::max<int64_t>(1, std::min(wa, n[a]));
+    int64_t we = std::max<int64_t>(1, std::min(cells / wa, n[e]));
+    wa = std::max<int64_t>(1, std::min(cells / we, n[a]));
+    c.lo[a] = (int32_t)(b.lo[a] + (n[a] - wa) / 2);
+    c.lo[e] = (int32_t)(b.lo[e] + (n[e] - we) / 2);
+    n[a] = wa;
+    n[e] = we;
+  }
+  for (int k = 0; k < 3; ++k) c.n[k] = (int32_t)n[k];
+  return c;
+}
 
 constexpr size_t kMaxPrepared = 32;
 
@@ -518,12 +602,14 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
   std::vector<int32_t> phases(req->phases, req->phases + req->n_phases);
   std::vector<uint64_t> versions;
   for (int32_t ph : phases) versions.push_back(ctx->phases[ph].version);
-  const int32_t chunk = req->engine == PMC_ENGINE_PERSISTENT ? default_chunk(ctx, req) : 0;
+  const LaunchShape shape = launch_shape(ctx, req);
+  const int32_t chunk = req->engine == PMC_ENGINE_PERSISTENT ? shape.chunk : 0;
+  const int32_t mode = req->engine == PMC_ENGINE_PERSISTENT ? shape.mode : 0;
   for (auto &e : ctx->cache) {
     Prepared &C = *e;
     if (C.plan_id == req->plan && C.plan_version == plan.version && C.n_hist == req->n_histories &&
         C.phases == phases && C.phase_versions == versions && C.engine == req->engine &&
-        C.chunk == chunk && C.precision == ctx->precision) {
+        C.chunk == chunk && C.mode == mode && C.precision == ctx->precision) {
       C.last_use = ++ctx->use_counter;
       *out = &C;
       return PMC_OK;
@@ -574,6 +660,26 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
   off = align256(off + sizeof(SpotDev<R>) * (size_t)n_spots);
   P.off_items = off;
   off = align256(off + sizeof(WorkItem) * items.size());
+  // core boxes (block engine), by spot, inside the grid of the spot's phase
+  std::vector<pmc::CoreDev> cores;
+  if (mode == PMC_TALLY_CORE) {
+    P.core_cap = shape.core_cap;
+    cores.assign(n_spots, pmc::CoreDev{});
+    for (int64_t s = 0; s < n_spots; ++s) {
+      const pmc_spot &sp = plan.spots[s];
+      if (P.per_spot[s] == 0 || slot_of.find(sp.phase) == slot_of.end()) continue;
+      const PhaseRec &ph = ctx->phases[sp.phase];
+      const pmc_field &f = plan.fields[sp.field];
+      pmc::CoreDev c = core_of(spot_box(ctx, ph, f, sp), f, P.core_cap);
+      const int n[3] = {ph.nx, ph.ny, ph.nz};
+      bool ok = (long long)c.n[0] * c.n[1] * c.n[2] <= (long long)P.core_cap;
+      for (int k = 0; k < 3; ++k) ok = ok && c.lo[k] >= 0 && c.n[k] >= 0 && c.lo[k] + c.n[k] <= n[k];
+      if (!ok) return fail(ctx, PMC_E_STATE, "internal: core box of spot %lld out of range", (long long)s);
+      cores[s] = c;
+    }
+  }
+  P.off_cores = off;
+  off = align256(off + sizeof(pmc::CoreDev) * cores.size());
   P.off_luts = off;
   off = align256(off + sizeof(R) * lut_elems * (size_t)n_luts);
   P.off_targets = off;
@@ -592,6 +698,7 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
   };
   put(P.off_spots, sd.data(), sizeof(SpotDev<R>) * sd.size());
   put(P.off_items, items.data(), sizeof(WorkItem) * items.size());
+  put(P.off_cores, cores.data(), sizeof(pmc::CoreDev) * cores.size());
   for (int32_t l = 0; l < n_luts; ++l) {
     const PhaseRec &ph = ctx->phases[phases[l]];
     const void *src = sizeof(R) == 4 ? (const void *)ph.lut32.data() : (const void *)ph.lut64.data();
@@ -617,6 +724,7 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
   P.phase_versions = versions;
   P.engine = req->engine;
   P.chunk = chunk;
+  P.mode = mode;
   P.precision = ctx->precision;
   P.last_use = ++ctx->use_counter;
   ctx->cache.push_back(std::move(entry));
@@ -711,6 +819,11 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     const LaunchShape shape = launch_shape(ctx, req);
     a.refill_min = shape.refill;
     a.block = shape.block;
+    if (P.mode == PMC_TALLY_CORE && !box) {
+      a.cores = reinterpret_cast<const pmc::CoreDev *>(scratch_at(P.off_cores));
+      a.core_cap = P.core_cap;
+      a.block = pmc::kCoreBlock;
+    }
     a.lut_lds = !fp64 && P.same_lut;
     a.cursor = cursor;
     a.counters = counters;
@@ -721,7 +834,9 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     }
     a.drained = drained;
     unsigned grid = (unsigned)req->grid_blocks;
-    if (grid == 0) {
+    if (grid == 0 && a.cores) {
+      grid = (unsigned)ctx->n_cu;  // one block per CU: the core takes the LDS
+    } else if (grid == 0) {
       int per_cu = pmc::persistent_blocks_per_cu(a, fp64);
       if (per_cu < 1) per_cu = 1;
       grid = (unsigned)(ctx->n_cu * per_cu);
@@ -856,6 +971,7 @@ int pmc_create(const pmc_config *cfg, pmc_context **out) {
   hipDeviceProp_t prop;
   if ((e = hipGetDeviceProperties(&prop, cfg->device)) != hipSuccess) return bail(e, "hipGetDeviceProperties");
   ctx->n_cu = prop.multiProcessorCount;
+  if (prop.sharedMemPerBlock > 0) ctx->lds_max = prop.sharedMemPerBlock;
   size_t free_b = 0, total_b = 0;
   if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) return bail(e, "hipMemGetInfo");
   ctx->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
@@ -1103,16 +1219,19 @@ int pmc_request_items(pmc_context *ctx, const pmc_request *req, uint64_t *n_item
   return PMC_OK;
 }
 
-int pmc_launch_shape(pmc_context *ctx, const pmc_request *req, int32_t *block_size, int32_t *chunk,
-                     int32_t *refill_min) {
+int pmc_launch_shape(pmc_context *ctx, const pmc_request *req, pmc_shape *out) {
   if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
   ctx->err.clear();
+  if (!out) return fail(ctx, PMC_E_INVAL, "out is NULL");
   int rc = validate_request(ctx, req);
   if (rc) return rc;
   const LaunchShape s = launch_shape(ctx, req);
-  if (block_size) *block_size = s.block;
-  if (chunk) *chunk = s.chunk;
-  if (refill_min) *refill_min = s.refill;
+  *out = pmc_shape{};
+  out->block_size = s.block;
+  out->chunk = s.chunk;
+  out->refill_min = s.refill;
+  out->tally_mode = s.mode;
+  out->core_capacity = s.core_cap;
   return PMC_OK;
 }
 
@@ -1643,6 +1762,7 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
               uint64_t max_scratch, uint64_t *nnz_out, pmc_balance *bal_out, uint64_t outside_out[2]) {
   pmc_request rq = *req_in;
   rq.engine = PMC_ENGINE_PERSISTENT;
+  rq.tally_mode = PMC_TALLY_LANE;  // per-spot box tallies
   const PlanRec &plan = ctx->plans[rq.plan];
   const int64_t n_spots = (int64_t)plan.spots.size();
   const int32_t phase_id = rq.phases[0];

@@ -53,6 +53,16 @@ struct BoxDev {
 };
 static_assert(sizeof(BoxDev) == 48, "BoxDev layout");
 
+// Core box of one spot for the block engine: voxels lo + [0, n) of the
+// spot's phase grid, whose deposits a block accumulates in LDS while it runs
+// the spot's histories; n[0] n[1] n[2] <= the launch's core capacity (n = 0:
+// no core, every deposit goes to the phase tally).
+struct CoreDev {
+  int32_t lo[3];
+  int32_t n[3];
+  int32_t pad[2];
+};
+
 constexpr int kTile = 1024;  // box entries per compaction tile (256 threads x 4)
 
 struct TraceRec {  // identical layout to pmc_trace_rec
@@ -102,7 +112,16 @@ struct PersistentLaunch {
   long long box_bias = 0;
   // host-visible flag set to 1 once every work item has been taken (nullable)
   unsigned int *drained = nullptr;
+  // block engine (cores != nullptr): one block per work item, core boxes by
+  // spot, LDS room for core_cap tally entries per block
+  const CoreDev *cores = nullptr;
+  int32_t core_cap = 0;
 };
+
+// Fixed LDS of a block-engine block (tables, the LUT when it is in LDS,
+// counter reduction, item state); the core tally follows it.
+size_t core_fixed_lds(bool lut_lds);
+constexpr int kCoreBlock = 1024;  // threads per block-engine block
 
 // Compaction of the box tallies of spots [0, n_spots) of a batch into CSR
 // rows (voxel, Gy per history), voxels at or above rel_threshold x the

@@ -236,8 +236,134 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
     if (alive) {
       const Geo<R> G = geo_s[tgt];
       const R2 *lut = LUT_LDS ? lut_s : luts_g + (size_t)G.lut * kLutSize;
-      step<R, false, BOX>(L, G, T, lut, k0, k1, flags, C, nullptr, 0, B);
-      if (L.fate != kAlive) flush_tally<R, BOX>(L, G, C, B);
+      constexpr int TM = BOX ? kTallyBox : kTallyGrid;
+      step<R, false, TM>(L, G, T, lut, k0, k1, flags, C, nullptr, 0, B);
+      if (L.fate != kAlive) flush_tally<R, TM>(L, G, C, B);
+    }
+  }
+  commit_counters(C, counters, red);
+}
+
+// ---------------------------------------------------------------------------
+// block engine: a block runs one work item (a run of one spot's histories)
+// at a time with all of its waves.  Deposits inside the spot's core box add
+// into the block's LDS copy of the core, the others into the phase tally;
+// when every history of the item has ended, the block adds each nonzero core
+// entry into the tally: one global atomic per voxel instead of one per voxel
+// visit.  Waves refill idle lanes from the item through an LDS counter.
+// ---------------------------------------------------------------------------
+size_t core_fixed_lds(bool lut_lds) {
+  return Smem<float>::tab_bytes + (lut_lds ? Smem<float>::lut_bytes : 0) +
+         sizeof(unsigned long long) * kNc * (kCoreBlock / 64 + 1) + 16;
+}
+
+template <typename R, bool LUT_LDS>
+__global__ void __launch_bounds__(kCoreBlock)
+transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict__ items,
+               int32_t n_items, const TargetDev *__restrict__ targets,
+               const typename M<R>::R2 *__restrict__ luts_g,
+               const typename M<R>::R4 *__restrict__ tab_g, R l2e0, R inv_dl2, R dl2,
+               uint32_t k0, uint32_t k1, uint32_t flags, int32_t refill_min,
+               unsigned long long *cursor, unsigned long long *counters,
+               const CoreDev *__restrict__ cores, int32_t core_cap, unsigned int *drained_flag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using R2 = typename M<R>::R2;
+  using R4 = typename M<R>::R4;
+  // LDS layout: [tables][lut (optional)][reduction][item state][core tally]
+  R4 *tab_s = reinterpret_cast<R4 *>(smem);
+  R2 *lut_s = reinterpret_cast<R2 *>(smem + Smem<R>::tab_bytes);
+  unsigned long long *red = reinterpret_cast<unsigned long long *>(
+      smem + Smem<R>::tab_bytes + (LUT_LDS ? Smem<R>::lut_bytes : 0));
+  int32_t *state = reinterpret_cast<int32_t *>(red + kNc * (kCoreBlock / 64 + 1));  // item, next
+  unsigned long long *core = reinterpret_cast<unsigned long long *>(state + 4);
+  for (int i = threadIdx.x; i < kNtab; i += blockDim.x) tab_s[i] = tab_g[i];
+  if constexpr (LUT_LDS)
+    for (int i = threadIdx.x; i < kLutSize; i += blockDim.x) lut_s[i] = luts_g[i];
+  for (int i = threadIdx.x; i < core_cap; i += blockDim.x) core[i] = 0ull;
+
+  Tab<R> T;
+  T.t = tab_s; T.l2e0 = l2e0; T.inv_dl2 = inv_dl2; T.dl2 = dl2;
+  const int lane = threadIdx.x & 63;
+  LaneCounters C = {};
+  Lane<R> L;
+  L.fate = kMissed;  // idle
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const unsigned long long k = __hip_atomic_fetch_add(cursor, 1ull, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+      state[0] = k < (unsigned long long)n_items ? (int32_t)k : -1;
+      state[1] = 0;
+      // every work item is taken: tell the host (pinned memory, vector store)
+      if (k >= (unsigned long long)n_items && drained_flag)
+        __hip_atomic_store(drained_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    // the item is published; tables, the zeroed core and the previous flush are complete
+    __syncthreads();
+    const int32_t k = __builtin_amdgcn_readfirstlane(state[0]);
+    if (k < 0) break;
+    const int32_t spot = __builtin_amdgcn_readfirstlane(items[k].spot);
+    const uint32_t h_begin = __builtin_amdgcn_readfirstlane(items[k].h_begin);
+    const uint32_t count = __builtin_amdgcn_readfirstlane(items[k].h_count);
+    const SpotDev<R> &sp = spots[spot];
+    const int32_t tgt = __builtin_amdgcn_readfirstlane(sp.target);
+    const Geo<R> G = geo_of<R>(targets[tgt]);
+    const R2 *lut = LUT_LDS ? lut_s : luts_g + (size_t)G.lut * kLutSize;
+    int32_t cn[3], clo[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      clo[a] = __builtin_amdgcn_readfirstlane(cores[spot].lo[a]);
+      cn[a] = __builtin_amdgcn_readfirstlane(cores[spot].n[a]);
+    }
+    const long long n_core = (long long)cn[0] * cn[1] * cn[2];
+    const bool use_core = n_core > 0 && n_core <= (long long)core_cap;
+    BoxLane B;
+    B.base = core;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      B.lo[a] = clo[a];
+      B.n[a] = use_core ? cn[a] : 0;  // no core: every deposit goes to the tally
+    }
+    bool taken_all = false;
+    for (;;) {
+      const unsigned long long idle = __ballot(L.fate != kAlive);
+      if (!taken_all && (int)__popcll(idle) >= refill_min) {
+        const uint32_t n_idle = (uint32_t)__popcll(idle);
+        uint32_t h0 = 0;
+        if (lane == 0)
+          h0 = __hip_atomic_fetch_add(reinterpret_cast<uint32_t *>(state + 1), n_idle, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+        h0 = __shfl(h0, 0, 64);
+        const uint32_t avail = h0 < count ? count - h0 : 0u;
+        const uint32_t take = avail < n_idle ? avail : n_idle;
+        if (h0 + n_idle >= count) taken_all = true;
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+        const bool mine = ((idle >> lane) & 1ull) && rank < take;
+        if (mine) start_history(L, sp, spot, h_begin + h0 + rank, G, k0, k1, C);
+      }
+      const bool alive = L.fate == kAlive;
+      if (!__any(alive)) {
+        if (taken_all) break;
+        continue;
+      }
+      if (alive) {
+        step<R, false, kTallyCore>(L, G, T, lut, k0, k1, flags, C, nullptr, 0, B);
+        if (L.fate != kAlive) flush_tally<R, kTallyCore>(L, G, C, B);
+      }
+    }
+    __syncthreads();  // every history of the item has ended: the core is complete
+    if (use_core) {
+      const int32_t nxy = cn[0] * cn[1];
+      for (int e = threadIdx.x; e < (int)n_core; e += blockDim.x) {
+        const unsigned long long v = core[e];
+        if (v) {
+          core[e] = 0ull;
+          const int32_t z = e / nxy, r = e - z * nxy, y = r / cn[0], x = r - y * cn[0];
+          const int32_t vox = (clo[0] + x) + G.n[0] * ((clo[1] + y) + G.n[1] * (clo[2] + z));
+          atomic_add_u64(&G.tally[vox], v);
+          C.atomics += 1;
+        }
+      }
     }
   }
   commit_counters(C, counters, red);
@@ -603,7 +729,28 @@ static void launch_persistent_v(const PersistentLaunch &a, size_t lds, hipStream
 }
 
 template <typename R>
+static hipError_t launch_core_t(const PersistentLaunch &a, hipStream_t st) {
+  if constexpr (sizeof(R) != sizeof(float)) {
+    return hipErrorInvalidValue;  // the block engine runs in FP32 only
+  } else {
+    using R2 = typename M<R>::R2;
+    using R4 = typename M<R>::R4;
+    const size_t lds = core_fixed_lds(a.lut_lds) + sizeof(unsigned long long) * (size_t)a.core_cap;
+    auto kern = a.lut_lds ? transport_core<R, true> : transport_core<R, false>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(a.grid), dim3(kCoreBlock), lds, st, (const SpotDev<R> *)a.spots,
+                       a.items, a.n_items, a.targets, (const R2 *)a.luts, (const R4 *)a.tab,
+                       (R)a.l2e0, (R)a.inv_dl2, (R)a.dl2, a.k0, a.k1, a.flags, a.refill_min, a.cursor,
+                       a.counters, a.cores, a.core_cap, a.drained);
+    return hipGetLastError();
+  }
+}
+
+template <typename R>
 static hipError_t launch_persistent_t(const PersistentLaunch &a, hipStream_t st) {
+  if (a.cores) return launch_core_t<R>(a, st);
   const size_t lds = persistent_lds<R>(a);
   const bool box = a.boxes != nullptr;
   if (a.lut_lds && box) launch_persistent_v<R, true, true>(a, lds, st);

@@ -24,6 +24,7 @@ PMC_MAX_PHASES = 64
 PMC_FP32, PMC_FP64 = 0, 1
 PMC_NO_STRAGGLING, PMC_NO_MCS, PMC_NO_DELTA, PMC_NO_NUCLEAR, PMC_FROZEN = 1, 2, 4, 8, 16
 PMC_ENGINE_PLAIN, PMC_ENGINE_PERSISTENT = 0, 1
+PMC_TALLY_AUTO, PMC_TALLY_LANE, PMC_TALLY_CORE = 0, 1, 2
 PMC_COUNTERS = 16
 
 ERROR_NAMES = {0: "PMC_OK", -1: "PMC_E_INVAL", -2: "PMC_E_NOPHASE", -3: "PMC_E_BUDGET",
@@ -43,11 +44,16 @@ class pmc_config(C.Structure):
                 ("hbm_budget_bytes", C.c_uint64)]
 
 
+class pmc_shape(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("chunk", C.c_int32), ("refill_min", C.c_int32),
+                ("tally_mode", C.c_int32), ("core_capacity", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
 class pmc_request(C.Structure):
     _fields_ = [("request_id", C.c_uint32), ("flags", C.c_uint32), ("n_histories", C.c_uint64),
                 ("phases", C.POINTER(C.c_int32)), ("n_phases", C.c_int32), ("engine", C.c_int32),
                 ("block_size", C.c_int32), ("chunk", C.c_int32), ("refill_min", C.c_int32),
-                ("grid_blocks", C.c_int32), ("plan", C.c_int32), ("reserved", C.c_int32),
+                ("grid_blocks", C.c_int32), ("plan", C.c_int32), ("tally_mode", C.c_int32),
                 ("item_begin", C.c_uint64), ("item_end", C.c_uint64)]
 
 
@@ -114,8 +120,7 @@ def lib():
         L.pmc_unload_plan.argtypes = [vp, i32]
         L.pmc_request_items.argtypes = [vp, C.POINTER(pmc_request), C.POINTER(u64)]
         L.pmc_request_item_histories.argtypes = [vp, C.POINTER(pmc_request), vp, u64, C.POINTER(u64)]
-        L.pmc_launch_shape.argtypes = [vp, C.POINTER(pmc_request), C.POINTER(C.c_int32),
-                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.pmc_launch_shape.argtypes = [vp, C.POINTER(pmc_request), C.POINTER(pmc_shape)]
         L.pmc_dose.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, C.POINTER(pmc_balance)]
         L.pmc_dose_device.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp]
         L.pmc_dose_device_notify.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, vp]
@@ -209,12 +214,12 @@ class Request:
 
     def __init__(self, n_histories: int, phases: Sequence[int], request_id=0, flags=0,
                  engine=PMC_ENGINE_PLAIN, block_size=0, chunk=0, refill_min=0, grid_blocks=0,
-                 plan=0, item_begin=0, item_end=0):
+                 plan=0, item_begin=0, item_end=0, tally_mode=PMC_TALLY_AUTO):
         self.phase_arr = np.ascontiguousarray(phases, dtype=np.int32)
         self.c = pmc_request(request_id, flags, n_histories,
                              self.phase_arr.ctypes.data_as(C.POINTER(C.c_int32)),
                              len(self.phase_arr), engine, block_size, chunk, refill_min, grid_blocks,
-                             plan, 0, item_begin, item_end)
+                             plan, tally_mode, item_begin, item_end)
 
     def slice(self, item_begin: int, item_end: int) -> "Request":
         """The same request restricted to work items [item_begin, item_end)."""
@@ -292,9 +297,10 @@ def pmc_request_item_histories(ctx, req: Request) -> np.ndarray:
 
 
 def pmc_launch_shape(ctx, req: Request) -> dict:
-    b, c, r = C.c_int32(0), C.c_int32(0), C.c_int32(0)
-    _check(lib().pmc_launch_shape(ctx, C.byref(req.c), C.byref(b), C.byref(c), C.byref(r)), ctx)
-    return {"block_size": b.value, "chunk": c.value, "refill_min": r.value}
+    out = pmc_shape()
+    _check(lib().pmc_launch_shape(ctx, C.byref(req.c), C.byref(out)), ctx)
+    return {k: getattr(out, k) for k in ("block_size", "chunk", "refill_min", "tally_mode",
+                                          "core_capacity")}
 
 
 def pmc_trace(ctx, phase_id: int, spot: int, history: int, request_id=0, flags=0,

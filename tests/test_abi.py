@@ -41,6 +41,7 @@ def test_library_exports_every_header_symbol(P):
 def test_struct_layouts_match_header(P):
     assert C.sizeof(P.pmc_config) == 24
     assert C.sizeof(P.pmc_request) == 72
+    assert C.sizeof(P.pmc_shape) == 32
     assert C.sizeof(P.pmc_balance) == 8 * 16
     assert W.SPOT_DTYPE.itemsize == 48 and W.FIELD_DTYPE.itemsize == 72
     assert P.TRACE_DTYPE.itemsize == 120
@@ -134,27 +135,44 @@ def test_dose_validation_order(P, vctx):
 
 
 def test_launch_shape_defaults(P):
-    """Default work items shrink for small requests so that every resident
+    """Lane mode: work items shrink for small requests so that every resident
     wave (16 per compute unit, 256 units assumed without a device) gets about
-    four of them; explicit values pass through."""
+    four of them.  Core mode for large requests with many histories per spot
+    (items of 8192 averaging >= 4096 histories, >= 4 per compute unit).
+    Explicit values pass through."""
     ctx = P.pmc_create(device=-1)
+    pers, lane, core = P.PMC_ENGINE_PERSISTENT, P.PMC_TALLY_LANE, P.PMC_TALLY_CORE
     try:
         plan = W.plan_single(150.0, 5.0)
         P.pmc_load_spots(ctx, plan.fields, plan.spots)
         P.pmc_load_phase(ctx, 0, W.make_water(8, 2.0))
         waves = 16 * 256
-        pers = P.PMC_ENGINE_PERSISTENT
         for n, chunk in [(1, 64), (4 * waves * 128 - 1, 64), (4 * waves * 128, 128),
-                         (4 * waves * 256 - 1, 128), (4 * waves * 256, 256), (P.PMC_MAX_HISTORIES, 256)]:
+                         (4 * waves * 256 - 1, 128), (4 * waves * 256, 256)]:
             got = P.pmc_launch_shape(ctx, P.Request(n, [0], engine=pers))
-            assert got == {"block_size": 1024, "chunk": chunk, "refill_min": 64}, n
+            assert got == {"block_size": 1024, "chunk": chunk, "refill_min": 64, "tally_mode": lane,
+                           "core_capacity": 0}, n
+        # one spot: items of 8192, enough of them from 4 x 256 x 8192 histories on
+        cap = P.pmc_launch_shape(ctx, P.Request(4 * 256 * 8192, [0], engine=pers))
+        assert cap["tally_mode"] == core and cap["chunk"] == 8192 and cap["block_size"] == 1024
+        assert cap["core_capacity"] > 4096
+        assert P.pmc_launch_shape(ctx, P.Request(1023 * 8192, [0], engine=pers))["tally_mode"] == lane
+        # forced modes, explicit shapes
+        assert P.pmc_launch_shape(ctx, P.Request(10, [0], engine=pers, tally_mode=core))["chunk"] == 8192
+        assert P.pmc_launch_shape(ctx, P.Request(P.PMC_MAX_HISTORIES, [0], engine=pers,
+                                                 tally_mode=lane))["tally_mode"] == lane
+        assert P.pmc_launch_shape(ctx, P.Request(P.PMC_MAX_HISTORIES, [0], engine=pers,
+                                                 block_size=512))["tally_mode"] == lane
         got = P.pmc_launch_shape(ctx, P.Request(10, [0], engine=pers, block_size=512, chunk=7,
                                                 refill_min=3))
-        assert got == {"block_size": 512, "chunk": 7, "refill_min": 3}
-        assert P.pmc_launch_shape(ctx, P.Request(10, [0])) == {"block_size": 256, "chunk": 0,
-                                                               "refill_min": 0}
-        with pytest.raises(P.PmcError):
-            P.pmc_launch_shape(ctx, P.Request(10, [0], block_size=100))
+        assert (got["block_size"], got["chunk"], got["refill_min"]) == (512, 7, 3)
+        assert P.pmc_launch_shape(ctx, P.Request(10, [0])) == {
+            "block_size": 256, "chunk": 0, "refill_min": 0, "tally_mode": 0, "core_capacity": 0}
+        for bad in (dict(block_size=100), dict(engine=pers, tally_mode=3),
+                    dict(engine=pers, tally_mode=core, block_size=512), dict(tally_mode=core)):
+            with pytest.raises(P.PmcError) as e:
+                P.pmc_launch_shape(ctx, P.Request(10, [0], **bad))
+            assert e.value.code == P.PMC_E_INVAL, bad
     finally:
         P.pmc_destroy(ctx)
     ctx = P.pmc_create(device=-1, precision=P.PMC_FP64)
@@ -162,11 +180,12 @@ def test_launch_shape_defaults(P):
         plan = W.plan_single(150.0, 5.0)
         P.pmc_load_spots(ctx, plan.fields, plan.spots)
         P.pmc_load_phase(ctx, 0, W.make_water(8, 2.0))
-        assert P.pmc_launch_shape(ctx, P.Request(10 ** 7, [0], engine=P.PMC_ENGINE_PERSISTENT)) == {
-            "block_size": 256, "chunk": 256, "refill_min": 64}
-        with pytest.raises(P.PmcError) as e:
-            P.pmc_launch_shape(ctx, P.Request(10, [0], block_size=512))
-        assert e.value.code == P.PMC_E_INVAL
+        assert P.pmc_launch_shape(ctx, P.Request(P.PMC_MAX_HISTORIES, [0], engine=pers)) == {
+            "block_size": 256, "chunk": 256, "refill_min": 64, "tally_mode": lane, "core_capacity": 0}
+        for bad in (dict(block_size=512), dict(engine=pers, tally_mode=core)):
+            with pytest.raises(P.PmcError) as e:
+                P.pmc_launch_shape(ctx, P.Request(10, [0], **bad))
+            assert e.value.code == P.PMC_E_INVAL
     finally:
         P.pmc_destroy(ctx)
 
