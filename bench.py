@@ -32,10 +32,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs, 4 SIMD16 units each, 2.4 GHz peak engine clock.  A wave64
-# VALU instruction occupies a SIMD for 4 cycles, so the chip issues at most
-# 256 * 4 * 16 * 2.4e9 = 3.93e13 full-rate lane operations per second.
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# MI355X: 256 CUs at 2.4 GHz; FP32 vector peak 157.3 TFLOP/s = 256 x 2.4e9 x
+# 128 lanes x 2 flops (FMA), i.e. 128 lanes of ordinary (non-packed) VALU work
+# per CU per clock: 7.86e13 lane operations per second.  (The counters agree:
+# the block engine issues 1.07 wave64 VALU instructions per CU per clock, more
+# than a 64-lane-per-clock CU could.)
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
 
 # VALU instructions one lane executes per transport step of the FP32 kernel:
 # SQ_INSTS_VALU of single-history launches (one active lane) divided by their
@@ -43,11 +45,12 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 VALU_PER_STEP = 448.0
 
 # HBM-side bytes of one full-size transport launch (5e7 histories of the
-# thorax 4D workload), from FETCH_SIZE and WRITE_SIZE scaled by a 4 GiB copy
-# calibration (profiles/transport_thorax4d_counters.md).  Valid only for the
-# kernel sources they were measured on (hash below); otherwise reported null.
-PROFILED_TRAFFIC_BYTES = 282.3e9
-PROFILED_KERNEL_HASH = "10b1a0af1734c8cb"
+# thorax 4D workload, block engine, chunk 8192), from FETCH_SIZE and
+# WRITE_SIZE scaled by a 4 GiB copy calibration
+# (profiles/transport_core_thorax4d_counters.md).  Valid only for the sources
+# they were measured on (hash below) and that launch shape; otherwise null.
+PROFILED_TRAFFIC_BYTES = 180.0e9
+PROFILED_KERNEL_HASH = "2d52edc9a7a70231"
 
 
 def log(*a):
@@ -141,24 +144,26 @@ def main():
         return
 
     # ---- launch shape ----------------------------------------------------
-    tuned = {"block_size": 0, "chunk": 0, "refill_min": 0}
+    tuned = {"block_size": 0, "chunk": 0, "refill_min": 0, "tally_mode": 0}
     if not a.no_tune:
         e = wl.plan.spots["energy_MeV"]
         key = autotune.shape_key(torch.cuda.get_device_name(0), [grid] * len(phases),
                                  len(wl.plan.spots), wl.n_histories, (float(e.min()), float(e.max())))
         t1 = time.time()
+        # full-size probes over a short candidate list (block-engine items are
+        # runs of one spot's histories: a smaller probe would shorten them)
         tuned = autotune.tune(eng.ctx, phases, key, tptr, counters.data_ptr(), stream.cuda_stream,
-                              torch.cuda.synchronize, max(wl.n_histories // 10, 100_000),
-                              request_id=wl.request_id,
-                              cache_path=a.tune_cache or autotune.DEFAULT_CACHE)
-        log(f"autotune ({time.time() - t1:.1f} s): block {tuned['block_size']} chunk "
-            f"{tuned['chunk']} refill {tuned['refill_min']}")
+                              torch.cuda.synchronize, wl.n_histories, request_id=wl.request_id,
+                              cache_path=a.tune_cache or autotune.DEFAULT_CACHE,
+                              candidates=autotune.FULL_SIZE_CANDIDATES, repeats=1)
+        log(f"autotune ({time.time() - t1:.1f} s): tally mode {tuned['tally_mode']} block "
+            f"{tuned['block_size']} chunk {tuned['chunk']} refill {tuned['refill_min']}")
 
     def make_req(engine):
         kw = {}
         if engine == pmc.PMC_ENGINE_PERSISTENT:
             kw = dict(block_size=tuned["block_size"], chunk=tuned["chunk"],
-                      refill_min=tuned["refill_min"])
+                      refill_min=tuned["refill_min"], tally_mode=tuned.get("tally_mode", 0))
         return pmc.Request(wl.n_histories, phases, request_id=wl.request_id, engine=engine, **kw)
 
     def eager_step(req):
@@ -219,6 +224,9 @@ def main():
         pmc.pmc_dose_device(eng.ctx, req_b, stream.cuda_stream, tptr, counters.data_ptr())
     _, spans_k = timed(transport_only, max(2, min(a.steps, 3)), 0)
     kern_ms = float(np.mean(spans_k))
+    shape_b = pmc.pmc_launch_shape(eng.ctx, req_b)
+    kernel_name = ("transport_core<float>" if shape_b["tally_mode"] == pmc.PMC_TALLY_CORE
+                   else "transport_persistent<float>")
 
     plain = None
     if not a.no_plain and a.plain_steps > 0:
@@ -241,12 +249,12 @@ def main():
     achieved = lane_steps_s * VALU_PER_STEP
     default_cfg = wl.n_histories == 50_000_000 and grid == (256, 256, 160)
     traffic = (PROFILED_TRAFFIC_BYTES if default_cfg and kernel_hash() == PROFILED_KERNEL_HASH
-               else None)
+               and shape_b["tally_mode"] == pmc.PMC_TALLY_CORE and shape_b["chunk"] == 8192 else None)
     roofline = {
         "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
         "unit": "T lane-VALU-instr/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
         "traffic_unit": "bytes per launch (HBM side: fetches + 32 B per memory-side atomic)",
-        "kernel": "transport_persistent<float>", "kernel_ms": kern_ms,
+        "kernel": kernel_name, "kernel_ms": kern_ms,
         "valu_per_step": VALU_PER_STEP, "lane_steps_per_s": lane_steps_s,
         "atomics_per_s": bal["atomics"] / (kern_ms * 1e-3),
         "atomic_probe_per_s": atomic_peak,
