@@ -219,10 +219,10 @@ typedef struct {
 
 /* Launch shape the library uses for req: the request's own values where
  * set, else the defaults.
- *  - tally_mode: PMC_TALLY_CORE when the FP32 persistent engine runs a large
- *    request whose spots have many histories each (work items of `chunk`
- *    histories averaging at least 4096, at least 4 per compute unit, and room
- *    for 4096 core entries in LDS), else PMC_TALLY_LANE.
+ *  - tally_mode: PMC_TALLY_CORE for the FP32 persistent engine when its work
+ *    items of `chunk` histories average at least 1024 (one per lane of a
+ *    block), the request has at least 1024 histories per compute unit and
+ *    the LDS holds at least 4096 core entries; else PMC_TALLY_LANE.
  *  - block_size: 1024 for the FP32 persistent engine (PMC_TALLY_CORE takes
  *    only 1024), 256 for FP64 and for the plain engine.
  *  - chunk: PMC_TALLY_CORE 8192; PMC_TALLY_LANE the largest of 256, 128, 64

@@ -496,7 +496,11 @@ LaunchShape launch_shape(const pmc_context *ctx, const pmc_request *req) {
       if (split(sp.data(), (int64_t)sp.size(), req->phases, req->n_phases, req->n_histories, per.data()) == 0) {
         int64_t items = 0;
         for (int64_t h : per) items += (h + chunk - 1) / chunk;
-        if (items >= 4 * n_cu && (int64_t)req->n_histories >= 4096 * items) s.mode = PMC_TALLY_CORE;
+        // at least one history per lane of a block per item, and per lane of
+        // the device: smaller requests spread better over lanes of many waves
+        if ((int64_t)req->n_histories >= (int64_t)pmc::kCoreBlock * items &&
+            (int64_t)req->n_histories >= (int64_t)pmc::kCoreBlock * n_cu)
+          s.mode = PMC_TALLY_CORE;
       }
     }
   }

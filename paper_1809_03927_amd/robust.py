@@ -88,7 +88,8 @@ def influence_nominal(ctx, phantoms, plan: W.Plan, n_phases: int, n_histories: i
 
 
 def run(n_histories=20_000_000, shape_xyz=(256, 256, 160), n_phases=10, depth=1, policy="small-first",
-        budget_bytes=0, log=None, plain=True, influence=True, slice_histories=None, n_streams=1):
+        budget_bytes=0, log=None, plain=True, influence=True, slice_histories=None, n_streams=1,
+        launch=None):
     import torch
     from . import pmc
     t0 = time.time()
@@ -107,8 +108,9 @@ def run(n_histories=20_000_000, shape_xyz=(256, 256, 160), n_phases=10, depth=1,
             engines.append(("plain-serial", pmc.PMC_ENGINE_PLAIN, "fifo", 1))
         digests = {}
         for label, engine, pol, d in engines:
-            ex = S.GpuExecutor(ctx, phantoms, per_job, engine, {},
-                               n_streams=n_streams if engine == pmc.PMC_ENGINE_PERSISTENT else 1)
+            persistent = engine == pmc.PMC_ENGINE_PERSISTENT
+            ex = S.GpuExecutor(ctx, phantoms, per_job, engine, launch if persistent else {},
+                               n_streams=n_streams if persistent else 1)
             # every calculation arrives at once and has the same size: no
             # request gains from being cut, so by default each runs whole
             sched = S.Scheduler(ex, S.WallClock(), budget, policy=pol, depth=d, log=log,
@@ -148,10 +150,12 @@ def main():
     p.add_argument("--no-influence", action="store_true")
     p.add_argument("--slice-histories", type=int, default=0, help="0 = whole calculations")
     p.add_argument("--streams", type=int, default=1)
+    p.add_argument("--tally-mode", choices=["auto", "lane", "core"], default="auto",
+                   help="persistent-engine tally mode (auto: the library's choice)")
     a = p.parse_args()
     res = run(a.histories, tuple(int(x) for x in a.grid.split(",")), a.phases, plain=not a.no_plain,
               influence=not a.no_influence, slice_histories=a.slice_histories or None,
-              n_streams=a.streams,
+              n_streams=a.streams, launch={"tally_mode": ["auto", "lane", "core"].index(a.tally_mode)},
               log=lambda m: print("[robust]", m, file=sys.stderr, flush=True))
     print(json.dumps(res))
 

@@ -548,8 +548,8 @@ class GpuExecutor(Executor):
         n_spots = len(self.plans[job.index].spots)
         # the library's default work item holds 64 to 256 histories
         items = job.n_histories // max(1, self.launch.get("chunk") or 64) + n_spots
-        # tally + dose + counters; spot descriptors, work items, LUT copy, targets
-        return job.nvox * 16 + 128 + n_spots * 96 + items * 16 + 65536
+        # tally + dose + counters; spot descriptors and core boxes, work items, LUT copy, targets
+        return job.nvox * 16 + 128 + n_spots * 128 + items * 16 + 65536
 
     def load_phantom(self, key) -> None:
         if not self.free_slots:
@@ -834,13 +834,16 @@ def main():
     p.add_argument("--small", type=float, default=2.2e6, help="small-first: largest small request")
     p.add_argument("--no-plain", action="store_true", help="skip the plain-serial comparison")
     p.add_argument("--block", type=int, default=0, help="persistent-engine block size (0 = library default)")
+    p.add_argument("--tally-mode", choices=["auto", "lane", "core"], default="auto",
+                   help="persistent-engine tally mode (auto: the library's choice)")
     p.add_argument("--per-request", action="store_true", help="keep per-request times in the output")
     a = p.parse_args()
     res = run_scenario(a.requests, a.load, a.seed, int(a.budget_gb * 2**30),
                        slice_histories=a.slice_histories, workers=a.workers, depth=a.depth,
                        policy=a.policy, plain=not a.no_plain, n_streams=a.streams, small=a.small,
                        drain_signal=not a.no_drain_signal,
-                       launch={"block_size": a.block} if a.block else None,
+                       launch=dict({"block_size": a.block} if a.block else {},
+                                   tally_mode=["auto", "lane", "core"].index(a.tally_mode)),
                        log=lambda m: print("[serve]", m, file=sys.stderr, flush=True))
     if not a.per_request:
         for k in ("batched", "plain-serial"):

@@ -149,14 +149,14 @@ def test_launch_shape_defaults(P):
         waves = 16 * 256
         for n, chunk in [(1, 64), (4 * waves * 128 - 1, 64), (4 * waves * 128, 128),
                          (4 * waves * 256 - 1, 128), (4 * waves * 256, 256)]:
-            got = P.pmc_launch_shape(ctx, P.Request(n, [0], engine=pers))
+            got = P.pmc_launch_shape(ctx, P.Request(n, [0], engine=pers, tally_mode=lane))
             assert got == {"block_size": 1024, "chunk": chunk, "refill_min": 64, "tally_mode": lane,
                            "core_capacity": 0}, n
-        # one spot: items of 8192, enough of them from 4 x 256 x 8192 histories on
-        cap = P.pmc_launch_shape(ctx, P.Request(4 * 256 * 8192, [0], engine=pers))
+        # core mode from 1024 histories per lane of the device on (items average >= 1024)
+        cap = P.pmc_launch_shape(ctx, P.Request(1024 * 256, [0], engine=pers))
         assert cap["tally_mode"] == core and cap["chunk"] == 8192 and cap["block_size"] == 1024
         assert cap["core_capacity"] > 4096
-        assert P.pmc_launch_shape(ctx, P.Request(1023 * 8192, [0], engine=pers))["tally_mode"] == lane
+        assert P.pmc_launch_shape(ctx, P.Request(1024 * 256 - 1, [0], engine=pers))["tally_mode"] == lane
         # forced modes, explicit shapes
         assert P.pmc_launch_shape(ctx, P.Request(10, [0], engine=pers, tally_mode=core))["chunk"] == 8192
         assert P.pmc_launch_shape(ctx, P.Request(P.PMC_MAX_HISTORIES, [0], engine=pers,
@@ -173,6 +173,12 @@ def test_launch_shape_defaults(P):
             with pytest.raises(P.PmcError) as e:
                 P.pmc_launch_shape(ctx, P.Request(10, [0], **bad))
             assert e.value.code == P.PMC_E_INVAL, bad
+        # many spots: items are whole spots here, core mode once they average 1024 histories
+        plan = W.plan_thorax(3, n_layers=4, grid=(15, 10), n_phases=1)
+        assert len(plan.spots) == 600
+        P.pmc_load_spots(ctx, plan.fields, plan.spots)
+        assert P.pmc_launch_shape(ctx, P.Request(600 * 1024 - 1, [0], engine=pers))["tally_mode"] == lane
+        assert P.pmc_launch_shape(ctx, P.Request(600 * 1024, [0], engine=pers))["tally_mode"] == core
     finally:
         P.pmc_destroy(ctx)
     ctx = P.pmc_create(device=-1, precision=P.PMC_FP64)
