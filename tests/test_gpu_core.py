@@ -148,3 +148,31 @@ def test_auto_mode_picks_core_for_large_requests(P):
         assert np.array_equal(t_auto[0], t_lane[0]) and b_auto == b_lane
     finally:
         e.close()
+
+
+def test_core_mode_mixed_calibrations_and_mask(P):
+    """Two phases with different HU calibrations in one request (the LUTs stay
+    in global memory) and an external mask (vacuum outside the body)."""
+    import dataclasses
+    base = W.make_thorax((96, 96, 60), 0, 10)
+    body = (base.hu > -900).astype(np.uint8)
+    ph0 = dataclasses.replace(base, mask=body)
+    ph1 = W.scaled_calibration(W.make_thorax((96, 96, 60), 5, 10), 1.035)
+    plan = W.plan_thorax(3, n_phases=10)
+    plan.spots["phase"] = np.arange(len(plan.spots)) % 2
+    wl = W.Workload("mixed", [ph0, ph1], plan, 400_000, seed=9)
+    e = engine(P, wl)
+    try:
+        say("core mode, two calibrations + mask")
+        _, tp, _, bp = e.dose(wl.n_histories, [0, 1], engine=P.PMC_ENGINE_PLAIN)
+        assert bp["deposited"] + bp["escaped"] + bp["nuclear"] == bp["incident"]
+        for mode in (P.PMC_TALLY_LANE, P.PMC_TALLY_CORE):
+            _, tc, _, bc = e.dose(wl.n_histories, [0, 1], engine=P.PMC_ENGINE_PERSISTENT,
+                                  tally_mode=mode, chunk=300)
+            assert bc == bp, mode
+            for a, b in zip(tp, tc):
+                assert np.array_equal(a, b), mode
+        # nothing is deposited outside the mask of phase 0
+        assert not tp[0][body.reshape(-1) == 0].any()
+    finally:
+        e.close()
