@@ -345,7 +345,9 @@ int pmc_influence_boxes(pmc_context *ctx, int32_t plan, int32_t phase, pmc_box *
  * spot separately, which an optimiser of spot weights needs; Sec. 4.C).
  * Runs the request's histories (persistent engine, launch fields honoured,
  * not sliced) with every spot tallying into its own box (`boxes`: one per
- * plan spot, or NULL for pmc_influence_boxes), then keeps, per spot, the
+ * plan spot, or NULL for pmc_influence_boxes); with PMC_TALLY_CORE (picked
+ * by the rule of pmc_launch_shape when tally_mode is 0) a block keeps a
+ * window of its spot's box in LDS.  Then it keeps, per spot, the
  * voxels whose tally / density is >= rel_threshold (0..1) x that spot's
  * maximum of it, as CSR: one row per plan spot (row_ptr: n_spots + 1
  * int64), voxel = linear index of the phase grid (int32, ascending within a

@@ -168,12 +168,17 @@ template <typename R> struct Geo {
 //   kTallyCore  inside the spot's core box: the block's LDS copy of the core
 //               (flushed into the phase tally when the block is done with the
 //               spot); outside it: the phase tally
-constexpr int kTallyGrid = 0, kTallyBox = 1, kTallyCore = 2;
+//   kTallyBoxCore  kTallyBox whose core window (inside the box) adds into
+//               the block's LDS copy (flushed into the box tally)
+constexpr int kTallyGrid = 0, kTallyBox = 1, kTallyCore = 2, kTallyBoxCore = 3;
 
-// the box a lane's spot tallies into (kTallyBox: global, kTallyCore: LDS)
+// the box a lane's spot tallies into (kTallyBox: global, kTallyCore: LDS);
+// kTallyBoxCore: the box (global) and its core window (LDS)
 struct BoxLane {
   unsigned long long *base;  // entry 0 of the box
   int32_t lo[3], n[3];
+  unsigned long long *core;  // kTallyBoxCore: entry 0 of the core window
+  int32_t clo[3], cn[3];     // kTallyBoxCore: window corner (grid voxels) and size
 };
 
 // physics tables: (R, mu_delta, omega^2, 0) per node, linear in log2 E
@@ -417,12 +422,22 @@ __device__ __forceinline__ void start_history(Lane<R> &L, const SpotDev<R> &sp, 
 
 // Tally key of a deposit.  kTallyGrid: the voxel index; kTallyBox: the
 // box-local entry, -2 outside the box; kTallyCore: -3 - (core-local entry)
-// inside the core, else the voxel index.  The lane is still in the voxel of
-// the step.
+// inside the core, else the voxel index; kTallyBoxCore: -2 outside the box,
+// -3 - (window-local entry) inside the window, else the box-local entry.  The
+// lane is still in the voxel of the step.
 template <typename R, int TM>
 __device__ __forceinline__ int32_t tally_key(const Lane<R> &L, const BoxLane &B, int32_t v) {
   if constexpr (TM == kTallyGrid) {
     return v;
+  } else if constexpr (TM == kTallyBoxCore) {
+    const int32_t x = L.ix - B.lo[0], y = L.iy - B.lo[1], z = L.iz - B.lo[2];
+    if (!((uint32_t)x < (uint32_t)B.n[0] && (uint32_t)y < (uint32_t)B.n[1] &&
+          (uint32_t)z < (uint32_t)B.n[2]))
+      return -2;
+    const int32_t cx = L.ix - B.clo[0], cy = L.iy - B.clo[1], cz = L.iz - B.clo[2];
+    const bool in_core = (uint32_t)cx < (uint32_t)B.cn[0] && (uint32_t)cy < (uint32_t)B.cn[1] &&
+                         (uint32_t)cz < (uint32_t)B.cn[2];
+    return in_core ? -3 - (cx + B.cn[0] * (cy + B.cn[1] * cz)) : x + B.n[0] * (y + B.n[1] * z);
   } else {
     const int32_t x = L.ix - B.lo[0], y = L.iy - B.lo[1], z = L.iz - B.lo[2];
     const bool in = (uint32_t)x < (uint32_t)B.n[0] && (uint32_t)y < (uint32_t)B.n[1] &&
@@ -450,6 +465,17 @@ __device__ __forceinline__ void commit_acc(const Lane<R> &L, const Geo<R> &G, co
       return;
     }
     atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
+  } else if constexpr (TM == kTallyBoxCore) {
+    if (L.acc_v <= -3) {  // LDS: the block's copy of the core window
+      __hip_atomic_fetch_add(&B.core[-3 - L.acc_v], (unsigned long long)L.acc, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+      return;
+    }
+    if (L.acc_v == -2) {
+      C.out += (unsigned long long)L.acc;
+      return;
+    }
+    atomic_add_u64(&B.base[L.acc_v], (unsigned long long)L.acc);
   } else {
     atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
   }

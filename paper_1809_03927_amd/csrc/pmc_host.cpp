@@ -747,6 +747,8 @@ struct BoxArgs {
   long long bias;
   const WorkItem *items;  // the batch's own work items (the spots whose boxes are in tally)
   int32_t n_items;
+  const pmc::CoreDev *cores;  // block engine: core window of every spot's box (else null)
+  int32_t core_cap;
 };
 
 template <typename R>
@@ -826,6 +828,10 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     if (P.mode == PMC_TALLY_CORE && !box) {
       a.cores = reinterpret_cast<const pmc::CoreDev *>(scratch_at(P.off_cores));
       a.core_cap = P.core_cap;
+      a.block = pmc::kCoreBlock;
+    } else if (box && box->cores) {
+      a.cores = box->cores;
+      a.core_cap = box->core_cap;
       a.block = pmc::kCoreBlock;
     }
     a.lut_lds = !fp64 && P.same_lut;
@@ -1828,11 +1834,44 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
     max_spots = std::max<long long>(max_spots, cuts[b + 1] - cuts[b]);
   }
   const long long max_tiles = max_entries / pmc::kTile, max_chunks = (max_tiles + 1023) / 1024;
+  // Block engine (FP32, room in LDS, items of kCoreChunk averaging one
+  // history per lane, as for dense requests): every spot's box keeps a core
+  // window in LDS.  Else the lane engine with the request's chunk.
+  // The request's tally_mode forces either engine.
+  int32_t core_cap = 0;
+  int64_t item_chunk = chunk;
+  if (ctx->precision == PMC_FP32 && req_in->tally_mode != PMC_TALLY_LANE) {
+    const int32_t cap = core_capacity(ctx, P->same_lut);
+    const int64_t core_chunk = req_in->chunk > 0 ? req_in->chunk : kCoreChunk;
+    int64_t items = 0;
+    for (int64_t h : P->per_spot) items += (h + core_chunk - 1) / core_chunk;
+    const int64_t n_cu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+    const bool pick = req_in->tally_mode == PMC_TALLY_CORE ||
+                      (cap >= kCoreMinEntries && (int64_t)rq.n_histories >= (int64_t)pmc::kCoreBlock * items &&
+                       (int64_t)rq.n_histories >= (int64_t)pmc::kCoreBlock * n_cu);
+    if (pick && cap > 0) {
+      core_cap = cap;
+      item_chunk = core_chunk;
+    }
+  }
+  std::vector<pmc::CoreDev> cores;
+  if (core_cap > 0) {
+    cores.assign((size_t)n_spots, pmc::CoreDev{});
+    for (int64_t s = 0; s < n_spots; ++s) {
+      if (P->per_spot[s] == 0) continue;
+      pmc::CoreDev c = core_of(bx[s], plan.fields[plan.spots[s].field], core_cap);
+      bool ok = (long long)c.n[0] * c.n[1] * c.n[2] <= (long long)core_cap;
+      for (int k = 0; k < 3; ++k)
+        ok = ok && c.n[k] >= 0 && c.lo[k] >= bx[s].lo[k] && c.lo[k] + c.n[k] <= bx[s].hi[k];
+      if (!ok) return fail(ctx, PMC_E_STATE, "internal: core window of spot %lld outside its box", (long long)s);
+      cores[s] = c;
+    }
+  }
   // each batch's work items, in queue order over its spots
   std::vector<WorkItem> bitems;
   std::vector<size_t> batch_first = {0};
   for (size_t b = 0; b + 1 < cuts.size(); ++b) {
-    build_items(P->per_spot, cuts[b], cuts[b + 1], chunk, bitems);
+    build_items(P->per_spot, cuts[b], cuts[b + 1], item_chunk, bitems);
     batch_first.push_back(bitems.size());
   }
   // work buffer layout
@@ -1845,6 +1884,7 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
   const size_t o_toff = off; off = align256(off + sizeof(long long) * (size_t)max_tiles);
   const size_t o_coff = off; off = align256(off + sizeof(long long) * (size_t)(max_chunks + 1));
   const size_t o_items = off; off = align256(off + sizeof(WorkItem) * bitems.size());
+  const size_t o_cores = off; off = align256(off + sizeof(pmc::CoreDev) * cores.size());
   ctx->inf_n_rows = -1;
   ctx->inf_nnz = 0;
   rc = ensure(ctx, ctx->inf_work, std::max<size_t>(off, 256), "influence work buffer");
@@ -1870,6 +1910,10 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
   if (!bitems.empty())
     HIP_TRY(ctx, copy_sync(ctx, d_items, bitems.data(), sizeof(WorkItem) * bitems.size(),
                            hipMemcpyHostToDevice), "upload batch work items");
+  auto *d_cores = reinterpret_cast<pmc::CoreDev *>(work + o_cores);
+  if (!cores.empty())
+    HIP_TRY(ctx, copy_sync(ctx, d_cores, cores.data(), sizeof(pmc::CoreDev) * cores.size(),
+                           hipMemcpyHostToDevice), "upload core windows");
   HIP_TRY(ctx, pmc::launch_fill_u64(counters, PMC_COUNTERS, 0ull, st), "counter reset");
   unsigned __int128 deposited = 0;
   uint64_t nnz = 0;
@@ -1889,7 +1933,8 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
       rc = take_cursor(ctx, st, &cursor, &cursor_done);
       if (rc) return rc;
       const BoxArgs ba = {d_boxes, scratch, base, d_items + batch_first[b],
-                          (int32_t)(batch_first[b + 1] - batch_first[b])};
+                          (int32_t)(batch_first[b + 1] - batch_first[b]),
+                          core_cap > 0 ? d_cores : nullptr, core_cap};
       rc = enqueue_prepared<R>(ctx, *P, &br, st, no_tally, counters, static_cast<unsigned char *>(P->buf.p),
                                cursor, true, &ba);
       if (rc) return rc;

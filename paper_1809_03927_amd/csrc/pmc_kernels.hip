@@ -251,13 +251,16 @@ transport_persistent(const SpotDev<R> *__restrict__ spots, const WorkItem *__res
 // when every history of the item has ended, the block adds each nonzero core
 // entry into the tally: one global atomic per voxel instead of one per voxel
 // visit.  Waves refill idle lanes from the item through an LDS counter.
+// With BOX (influence calculations) the lanes tally into their spot's box as
+// in transport_persistent, and the core is a window of that box whose entries
+// are flushed into the box tally.
 // ---------------------------------------------------------------------------
 size_t core_fixed_lds(bool lut_lds) {
   return Smem<float>::tab_bytes + (lut_lds ? Smem<float>::lut_bytes : 0) +
          sizeof(unsigned long long) * kNc * (kCoreBlock / 64 + 1) + 16;
 }
 
-template <typename R, bool LUT_LDS>
+template <typename R, bool LUT_LDS, bool BOX>
 __global__ void __launch_bounds__(kCoreBlock)
 transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict__ items,
                int32_t n_items, const TargetDev *__restrict__ targets,
@@ -265,7 +268,9 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
                const typename M<R>::R4 *__restrict__ tab_g, R l2e0, R inv_dl2, R dl2,
                uint32_t k0, uint32_t k1, uint32_t flags, int32_t refill_min,
                unsigned long long *cursor, unsigned long long *counters,
-               const CoreDev *__restrict__ cores, int32_t core_cap, unsigned int *drained_flag) {
+               const CoreDev *__restrict__ cores, int32_t core_cap, const BoxDev *__restrict__ boxes,
+               unsigned long long *box_tally, long long box_bias, unsigned int *drained_flag) {
+  constexpr int TM = BOX ? kTallyBoxCore : kTallyCore;
   extern __shared__ __align__(16) unsigned char smem[];
   using R2 = typename M<R>::R2;
   using R4 = typename M<R>::R4;
@@ -317,11 +322,27 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
     const long long n_core = (long long)cn[0] * cn[1] * cn[2];
     const bool use_core = n_core > 0 && n_core <= (long long)core_cap;
     BoxLane B;
-    B.base = core;
+    if constexpr (BOX) {
+      // the box's first entry relative to this batch's scratch (64-bit)
+      const unsigned long long rel = (unsigned long long)(boxes[spot].offset - box_bias);
+      const uint32_t rel_lo = __builtin_amdgcn_readfirstlane((uint32_t)rel);
+      const uint32_t rel_hi = __builtin_amdgcn_readfirstlane((uint32_t)(rel >> 32));
+      B.base = box_tally + (long long)(((unsigned long long)rel_hi << 32) | rel_lo);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      B.lo[a] = clo[a];
-      B.n[a] = use_core ? cn[a] : 0;  // no core: every deposit goes to the tally
+      for (int a = 0; a < 3; ++a) {
+        B.lo[a] = __builtin_amdgcn_readfirstlane(boxes[spot].lo[a]);
+        B.n[a] = __builtin_amdgcn_readfirstlane(boxes[spot].n[a]);
+        B.clo[a] = clo[a];
+        B.cn[a] = use_core ? cn[a] : 0;  // no core: the box tally takes every deposit
+      }
+      B.core = core;
+    } else {
+      B.base = core;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        B.lo[a] = clo[a];
+        B.n[a] = use_core ? cn[a] : 0;  // no core: every deposit goes to the tally
+      }
     }
     bool taken_all = false;
     for (;;) {
@@ -347,8 +368,8 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
         continue;
       }
       if (alive) {
-        step<R, false, kTallyCore>(L, G, T, lut, k0, k1, flags, C, nullptr, 0, B);
-        if (L.fate != kAlive) flush_tally<R, kTallyCore>(L, G, C, B);
+        step<R, false, TM>(L, G, T, lut, k0, k1, flags, C, nullptr, 0, B);
+        if (L.fate != kAlive) flush_tally<R, TM>(L, G, C, B);
       }
     }
     __syncthreads();  // every history of the item has ended: the core is complete
@@ -359,8 +380,13 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
         if (v) {
           core[e] = 0ull;
           const int32_t z = e / nxy, r = e - z * nxy, y = r / cn[0], x = r - y * cn[0];
-          const int32_t vox = (clo[0] + x) + G.n[0] * ((clo[1] + y) + G.n[1] * (clo[2] + z));
-          atomic_add_u64(&G.tally[vox], v);
+          if constexpr (BOX) {
+            const int32_t bx = clo[0] - B.lo[0] + x, by = clo[1] - B.lo[1] + y, bz = clo[2] - B.lo[2] + z;
+            atomic_add_u64(&B.base[bx + B.n[0] * (by + B.n[1] * bz)], v);
+          } else {
+            const int32_t vox = (clo[0] + x) + G.n[0] * ((clo[1] + y) + G.n[1] * (clo[2] + z));
+            atomic_add_u64(&G.tally[vox], v);
+          }
           C.atomics += 1;
         }
       }
@@ -736,14 +762,16 @@ static hipError_t launch_core_t(const PersistentLaunch &a, hipStream_t st) {
     using R2 = typename M<R>::R2;
     using R4 = typename M<R>::R4;
     const size_t lds = core_fixed_lds(a.lut_lds) + sizeof(unsigned long long) * (size_t)a.core_cap;
-    auto kern = a.lut_lds ? transport_core<R, true> : transport_core<R, false>;
+    const bool box = a.boxes != nullptr;
+    auto kern = a.lut_lds ? (box ? transport_core<R, true, true> : transport_core<R, true, false>)
+                          : (box ? transport_core<R, false, true> : transport_core<R, false, false>);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(a.grid), dim3(kCoreBlock), lds, st, (const SpotDev<R> *)a.spots,
                        a.items, a.n_items, a.targets, (const R2 *)a.luts, (const R4 *)a.tab,
                        (R)a.l2e0, (R)a.inv_dl2, (R)a.dl2, a.k0, a.k1, a.flags, a.refill_min, a.cursor,
-                       a.counters, a.cores, a.core_cap, a.drained);
+                       a.counters, a.cores, a.core_cap, a.boxes, a.box_tally, a.box_bias, a.drained);
     return hipGetLastError();
   }
 }

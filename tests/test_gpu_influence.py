@@ -180,3 +180,31 @@ def test_influence_edge_cases(P):
             P.pmc_influence_read(e.ctx, n_spots, 0)
     finally:
         e.close()
+
+
+def test_block_engine_influence_equals_lane(P):
+    """Box tallies with core windows in LDS (block engine) give the same matrix,
+    balance and outside energy as the lane engine, also in scratch batches."""
+    wl = W.workload_influence(n_histories=300_000)
+    e = engine(P, wl, P.PMC_FP32)
+    try:
+        boxes = P.pmc_influence_boxes(e.ctx, 0, 0, len(wl.plan.spots))
+        say("influence lane vs block engine")
+        ref = run(P, e, wl, wl.n_histories, boxes, 0.01, tally_mode=P.PMC_TALLY_LANE)
+        per = P.pmc_split_histories(wl.plan.spots, [0], wl.n_histories)
+        sizes = [int(np.prod(b["hi"] - b["lo"])) for b in boxes]
+        padded = [(-(-n // 1024)) * 1024 for n, h in zip(sizes, per) if h > 0]
+        for kw in (dict(), dict(chunk=700), dict(scratch=8 * 2 * max(padded))):
+            got = run(P, e, wl, wl.n_histories, boxes, 0.01, tally_mode=P.PMC_TALLY_CORE, **kw)
+            for a, b in zip(ref[:3], got[:3]):
+                assert np.array_equal(a, b), kw
+            assert ref[3] == got[3] and ref[4] == got[4], kw
+        # whole-grid boxes: the core windows are windows of a large box
+        full = full_boxes(P, wl)
+        ref = run(P, e, wl, wl.n_histories, full, 0.0, tally_mode=P.PMC_TALLY_LANE)
+        got = run(P, e, wl, wl.n_histories, full, 0.0, tally_mode=P.PMC_TALLY_CORE)
+        for a, b in zip(ref[:3], got[:3]):
+            assert np.array_equal(a, b)
+        assert ref[3] == got[3] and got[4] == 0
+    finally:
+        e.close()
