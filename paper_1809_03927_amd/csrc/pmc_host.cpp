@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -17,6 +18,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pmc.h"
@@ -448,6 +450,31 @@ TargetDev make_target(const PhaseRec &ph, unsigned long long *tally, int32_t lut
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// f(i) for i in [0, n) on up to 16 host threads (f must be safe to run
+// concurrently for different i); small n runs inline.
+template <typename F>
+void parallel_for(int64_t n, F &&f) {
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int64_t nt = std::min<int64_t>(hw ? hw : 1, 16);
+  if (n < 512 || nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const int64_t i0 = next.fetch_add(64);
+      if (i0 >= n) return;
+      const int64_t i1 = std::min<int64_t>(n, i0 + 64);
+      for (int64_t i = i0; i < i1; ++i) f(i);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int64_t t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto &t : pool) t.join();
+}
+
 // Launch shape of a request: its own values where set, else the defaults.
 // Threads per block: 1024 for the FP32 persistent engine (one block fills a
 // CU's wave slots that the LDS tables and registers allow: 16 waves), the
@@ -669,12 +696,19 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
   if (mode == PMC_TALLY_CORE) {
     P.core_cap = shape.core_cap;
     cores.assign(n_spots, pmc::CoreDev{});
+    // the voxel boxes (a host march along every spot axis), on host threads
+    std::vector<pmc_box> sbox((size_t)n_spots, pmc_box{{0, 0, 0}, {0, 0, 0}});
+    parallel_for(n_spots, [&](int64_t s) {
+      const pmc_spot &sp = plan.spots[s];
+      if (P.per_spot[s] == 0 || slot_of.find(sp.phase) == slot_of.end()) return;
+      sbox[s] = spot_box(ctx, ctx->phases.at(sp.phase), plan.fields[sp.field], sp);
+    });
     for (int64_t s = 0; s < n_spots; ++s) {
       const pmc_spot &sp = plan.spots[s];
       if (P.per_spot[s] == 0 || slot_of.find(sp.phase) == slot_of.end()) continue;
-      const PhaseRec &ph = ctx->phases[sp.phase];
+      const PhaseRec &ph = ctx->phases.at(sp.phase);
       const pmc_field &f = plan.fields[sp.field];
-      pmc::CoreDev c = core_of(spot_box(ctx, ph, f, sp), f, P.core_cap);
+      pmc::CoreDev c = core_of(sbox[s], f, P.core_cap);
       const int n[3] = {ph.nx, ph.ny, ph.nz};
       bool ok = (long long)c.n[0] * c.n[1] * c.n[2] <= (long long)P.core_cap;
       for (int k = 0; k < 3; ++k) ok = ok && c.lo[k] >= 0 && c.n[k] >= 0 && c.lo[k] + c.n[k] <= n[k];
@@ -1778,19 +1812,20 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
   const int32_t phase_id = rq.phases[0];
   const PhaseRec &ph = ctx->phases[phase_id];
   // boxes
-  std::vector<pmc_box> bx((size_t)n_spots);
-  for (int64_t s = 0; s < n_spots; ++s) {
-    if (boxes_in) {
+  std::vector<pmc_box> bx((size_t)n_spots, pmc_box{{0, 0, 0}, {0, 0, 0}});
+  if (boxes_in) {
+    for (int64_t s = 0; s < n_spots; ++s) {
       bx[s] = boxes_in[s];
       const int n[3] = {ph.nx, ph.ny, ph.nz};
       for (int k = 0; k < 3; ++k)
         if (bx[s].lo[k] < 0 || bx[s].hi[k] > n[k] || bx[s].lo[k] > bx[s].hi[k])
           return fail(ctx, PMC_E_INVAL, "box of spot %lld is not inside the grid", (long long)s);
-    } else if (plan.spots[s].phase == phase_id) {
-      bx[s] = spot_box(ctx, ph, plan.fields[plan.spots[s].field], plan.spots[s]);
-    } else {
-      bx[s] = pmc_box{{0, 0, 0}, {0, 0, 0}};
     }
+  } else {
+    parallel_for(n_spots, [&](int64_t s) {
+      if (plan.spots[s].phase == phase_id)
+        bx[s] = spot_box(ctx, ph, plan.fields[plan.spots[s].field], plan.spots[s]);
+    });
   }
   Prepared *P = nullptr;
   int rc = prepare<R>(ctx, &rq, &P);
@@ -2019,9 +2054,10 @@ int pmc_influence_boxes(pmc_context *ctx, int32_t plan, int32_t phase, pmc_box *
   if (!out || n_spots != (int64_t)pit->second.spots.size())
     return fail(ctx, PMC_E_INVAL, "need an output array of the plan's %zu spots", pit->second.spots.size());
   const PlanRec &P = pit->second;
-  for (int64_t s = 0; s < n_spots; ++s)
+  parallel_for(n_spots, [&](int64_t s) {
     out[s] = P.spots[s].phase == phase ? spot_box(ctx, hit->second, P.fields[P.spots[s].field], P.spots[s])
                                        : pmc_box{{0, 0, 0}, {0, 0, 0}};
+  });
   return PMC_OK;
 }
 

@@ -274,6 +274,17 @@ def pmc_balance_from_counters(ctx, req: Request, counters: np.ndarray, deposited
     return bal.as_dict()
 
 
+def balance_from_words(counters: np.ndarray, deposited: int, incident: int) -> dict:
+    """The dict of pmc_balance_from_counters from a counter block read back
+    earlier (layout of PMC_COUNTERS in pmc.h) and the request's incident
+    energy (pmc_balance_from_counters with the request still loaded)."""
+    c = [int(x) for x in np.asarray(counters, dtype=np.uint64)]
+    return {"incident": int(incident), "deposited": int(deposited),
+            "escaped": c[0] + (c[1] << 64), "nuclear": c[2] + (c[3] << 64),
+            "cutoff": c[4] + (c[5] << 64), "histories": c[6], "steps": c[7],
+            "delta_events": c[8], "nuclear_events": c[9], "escapes": c[10], "misses": c[11]}
+
+
 def pmc_convert_device(ctx, phase_id: int, dev_tally: int, n_histories: int, stream: int,
                        dev_dose: Optional[int], dev_density: Optional[int]) -> None:
     _check(lib().pmc_convert_device(ctx, phase_id, C.c_void_p(dev_tally), n_histories,

@@ -276,12 +276,16 @@ class Scheduler:
         return min(ready, key=lambda j: self._key(j, now))
 
     def _prestart(self) -> None:
-        """Prepare the next requests in pick order while the device works."""
-        if self.prestart <= 0:
+        """Prepare the next requests in pick order while the device works:
+        at most `prestart` prepared requests wait for their first slice (each
+        preparation takes host time the loop cannot spend on submissions)."""
+        ahead = sum(1 for j in self.admitted if j.started and j.first_run_s is None)
+        room = self.prestart - ahead
+        if room <= 0:
             return
         now = self.clock.now()
         todo = sorted((j for j in self.admitted if not j.started), key=lambda j: self._key(j, now))
-        for j in todo[:self.prestart]:
+        for j in todo[:room]:
             self.ex.start(j, sliced=self.policy != "fifo")
             j.started = True
 
@@ -521,9 +525,11 @@ class GpuExecutor(Executor):
         self.pinned_lock = threading.Lock()
         self.hasher = concurrent.futures.ThreadPoolExecutor(max_workers=2)
         self.pending: List = []
+        self.checks: List[tuple] = []  # balance checks waiting for their sums
 
     def close(self) -> None:
-        """Wait for the digests still being computed."""
+        """Finish the pending balance checks and digests."""
+        self._check_balances(wait=True)
         for f in self.pending:
             f.result()
         self.pending.clear()
@@ -628,6 +634,8 @@ class GpuExecutor(Executor):
         return self.finished(token)
 
     def progress(self, tokens, until: Optional[float] = None) -> None:
+        if self.checks:
+            self._check_balances()
         time.sleep(2e-5)
 
     def finish(self, job: Job) -> None:
@@ -649,29 +657,50 @@ class GpuExecutor(Executor):
             return
         buf = st.get("host_dose")
         if self.verify and buf is not None:
-            t = st["tally"]
-            with torch.cuda.stream(self.io):  # .cpu() waits for this stream only
-                words = torch.cat([torch.stack(((t >> 32).sum(), (t & 0xFFFFFFFF).sum())),
-                                   st["counters"]]).cpu().numpy()
-            dep = (int(words[0]) << 32) + int(words[1])
-            b = pmc.pmc_balance_from_counters(self.ctx, st["req"], words[2:], dep)
-            if b["deposited"] + b["escaped"] + b["nuclear"] != b["incident"]:
-                raise RuntimeError(f"request {job.index}: energy balance broken {b}")
-            if b["histories"] != job.n_histories:
-                raise RuntimeError(f"request {job.index}: {b['histories']} histories run")
-            self.balances[job.index] = b
-            if self.keep_doses:
-                self.doses[job.index] = buf.numpy().copy()
-
-            def digest(index=job.index, buf=buf):
-                self.digests[index] = hashlib.sha256(buf.numpy().data).hexdigest()
-                self._give_back(buf)
-
-            self.pending.append(self.hasher.submit(digest))
+            # exact energy balance of the served tally, checked once the sums
+            # arrive: the reduction may wait for CUs held by the next launch,
+            # and the loop must not wait with it
+            incident = pmc.pmc_balance_from_counters(self.ctx, st["req"], np.zeros(pmc.PMC_COUNTERS),
+                                                     0)["incident"]
+            t, counters = st["tally"], st["counters"]
+            words = torch.empty(2 + pmc.PMC_COUNTERS, dtype=torch.int64, pin_memory=True)
+            with torch.cuda.stream(self.io):
+                dev = torch.cat([torch.stack(((t >> 32).sum(), (t & 0xFFFFFFFF).sum())), counters])
+                words.copy_(dev, non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(self.io)
+            self.checks.append((job.index, job.n_histories, incident, words, ev, buf, (t, counters, dev)))
         elif buf is not None:
             self._give_back(buf)
         pmc.pmc_unload_plan(self.ctx, st["plan_id"])
         st.clear()
+        self._check_balances()
+
+    def _check_balances(self, wait: bool = False) -> None:
+        """Energy balances whose sums have arrived (all of them with wait)."""
+        keep = []
+        for chk in self.checks:
+            index, n_hist, incident, words, ev, buf, _ = chk
+            if not wait and not ev.query():
+                keep.append(chk)
+                continue
+            ev.synchronize()
+            w = words.numpy().astype(np.uint64)
+            b = self.pmc.balance_from_words(w[2:], (int(w[0]) << 32) + int(w[1]), incident)
+            if b["deposited"] + b["escaped"] + b["nuclear"] != b["incident"]:
+                raise RuntimeError(f"request {index}: energy balance broken {b}")
+            if b["histories"] != n_hist:
+                raise RuntimeError(f"request {index}: {b['histories']} histories run")
+            self.balances[index] = b
+            if self.keep_doses:
+                self.doses[index] = buf.numpy().copy()
+
+            def digest(index=index, buf=buf):
+                self.digests[index] = hashlib.sha256(buf.numpy().data).hexdigest()
+                self._give_back(buf)
+
+            self.pending.append(self.hasher.submit(digest))
+        self.checks = keep
 
 
 # ----------------------------------------------------------------------------

@@ -230,3 +230,23 @@ def test_one_hip_runtime_in_the_process(P):
             if "libamdhip64" in line:
                 paths.add(line.split()[-1])
     assert len(paths) == 1, paths
+
+
+def test_balance_from_words_matches_library(P):
+    """The binding's decoding of a counter block read back earlier equals the
+    library's pmc_balance_from_counters."""
+    ctx = P.pmc_create(device=-1)
+    try:
+        plan = W.plan_single(150.0, 5.0)
+        P.pmc_load_spots(ctx, plan.fields, plan.spots)
+        P.pmc_load_phase(ctx, 0, W.make_water(8, 2.0))
+        req = P.Request(12345, [0], engine=P.PMC_ENGINE_PERSISTENT)
+        rng = np.random.default_rng(3)
+        c = rng.integers(0, 2**63, size=P.PMC_COUNTERS, dtype=np.uint64)
+        c[[1, 3, 5]] = [0, 7, 1]
+        dep = (5 << 64) + 99
+        ref = P.pmc_balance_from_counters(ctx, req, c, dep)
+        inc = P.pmc_balance_from_counters(ctx, req, np.zeros(P.PMC_COUNTERS), 0)["incident"]
+        assert P.balance_from_words(c, dep, inc) == ref
+    finally:
+        P.pmc_destroy(ctx)

@@ -240,3 +240,23 @@ def test_library_work_items_round_robin_over_spots():
             assert got.tolist() == want and got.sum() == n
     finally:
         pmc.pmc_destroy(ctx)
+
+
+def test_prestart_prepares_a_bounded_number_ahead():
+    """With many queued requests, at most `prestart` are prepared and waiting
+    for their first slice at any time; every request is still served."""
+    class Counting(S.SimExecutor):
+        most = 0
+
+        def start(self, job, sliced):
+            super().start(job, sliced)
+            waiting = sum(1 for j in self.sched_ref.admitted if j.started and j.first_run_s is None)
+            Counting.most = max(Counting.most, waiting + 1)
+
+    clock = S.FakeClock()
+    ex = Counting(clock, rate_hist_per_s=1e8)
+    jobs = [job(i, 0.0, 3_000_000) for i in range(12)]
+    sched = S.Scheduler(ex, clock, 10**9, depth=1, slice_histories=1_000_000, prestart=2)
+    ex.sched_ref = sched
+    done = sched.run(jobs)
+    assert len(done) == 12 and Counting.most <= 2
