@@ -263,6 +263,22 @@ def main():
     if graph is not None:
         pmc.pmc_graph_destroy(graph)
         graph = True
+    # the GPU's share of the accuracy check: the histories the oracle sample
+    # runs (the first k of every spot = the first round of work items of k)
+    gpu_sample = None
+    k_sample = None
+    if not a.no_cpu_baseline:
+        k_sample = cpu_sample_size(wl, a.cpu_seconds)
+        per = pmc.pmc_split_histories(wl.plan.spots, phases, wl.n_histories)
+        req_s = pmc.Request(wl.n_histories, phases, request_id=wl.request_id,
+                            engine=pmc.PMC_ENGINE_PERSISTENT, chunk=k_sample,
+                            tally_mode=tuned.get("tally_mode", 0), item_begin=0,
+                            item_end=int(np.count_nonzero(per)))
+        for t in tallies:
+            t.zero_()
+        pmc.pmc_dose_device(eng.ctx, req_s, stream.cuda_stream, tptr, counters.data_ptr())
+        torch.cuda.synchronize()
+        gpu_sample = [t.cpu().numpy() for t in tallies]
     eng.close()
     latency = None
     if served is not None:
@@ -284,7 +300,7 @@ def main():
             f"{latency['batched']['p99_latency_s'] * 1e3:.0f} ms, plain "
             f"{latency['plain_serial']['p50_latency_s'] * 1e3:.0f}/"
             f"{latency['plain_serial']['p99_latency_s'] * 1e3:.0f} ms")
-    cpu = None if a.no_cpu_baseline else cpu_baseline(wl, a.cpu_seconds)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(wl, k_sample, gpu_sample)
     out = {
         "metric": "proton histories/s; p50/p99 dose-request latency, batched vs plain, 1 MI355X",
         "value": wl.n_histories / sec_b, "unit": "histories/s", "n_gpus": 1, "steps": a.steps,
@@ -330,24 +346,74 @@ def atomic_probe(torch, nvox, n=200_000_000):
     return n / (e0.elapsed_time(e1) * 1e-3)
 
 
-def cpu_baseline(wl, target_s):
-    """The FP64 oracle on the host, on the first K histories of every spot."""
+def cpu_sample_size(wl, target_s):
+    """Histories per spot (first k of every spot) for about target_s seconds
+    of the FP64 oracle on this host."""
     import oracle
     oracle.build()
-    cores = os.cpu_count() or 1
     k = 2
     t = time.perf_counter()
-    _, b = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k, n_threads=cores)
+    _, b = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k,
+                              n_threads=os.cpu_count() or 1)
     dt = time.perf_counter() - t
     k2 = min(4096, max(k, int(k * target_s / max(dt, 1e-3))))
     log(f"cpu baseline: calibration {b['histories']} histories in {dt:.2f} s; sample k={k2}/spot")
+    return k2
+
+
+def cpu_baseline(wl, k, gpu_sample):
+    """The FP64 oracle on the host, on the first k histories of every spot,
+    timed; then the C.8 accuracy check of the GPU's tallies of the same
+    histories against it: voxels above 10 % of the phase's maximum dose pass
+    if |dD| <= 1 % of that maximum or <= 3 sigma_diff (sqrt 2 x the oracle's
+    sigma from 10 history batches); total energy within 0.1 %."""
+    import numpy as np
+    import oracle
+    cores = os.cpu_count() or 1
     t = time.perf_counter()
-    _, b = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k2, n_threads=cores)
+    _, b = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k, n_threads=cores)
     dt = time.perf_counter() - t
-    return {"value": b["histories"] / dt, "unit": "histories/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {k2} histories of every spot of the thorax4d plan "
-                      f"({b['histories']} histories, {b['steps']} steps, {dt:.1f} s, FP64)",
-            "steps_per_history": b["steps"] / max(b["histories"], 1)}
+    out = {"value": b["histories"] / dt, "unit": "histories/s", "cores": cores, "kind": "oracle",
+           "sample": f"first {k} histories of every spot of the thorax4d plan "
+                     f"({b['histories']} histories, {b['steps']} steps, {dt:.1f} s, FP64)",
+           "steps_per_history": b["steps"] / max(b["histories"], 1)}
+    if gpu_sample is None:
+        return out
+    nb = 10
+    s1 = [np.zeros(ph.hu.size) for ph in wl.phases]
+    s2 = [np.zeros(ph.hu.size) for ph in wl.phases]
+    for r in range(nb):
+        tb, _ = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k, n_threads=cores,
+                                   h_mod=nb, h_rem=r)
+        for i, x in enumerate(tb):
+            x = x.astype(np.float64)
+            s1[i] += x
+            s2[i] += x * x
+    n_sel = n_ok = 0
+    e_gpu = e_orc = 0.0
+    for i, ph in enumerate(wl.phases):
+        _, rho = oracle.convert(ph, np.zeros(ph.hu.size, dtype=np.int64), 1)
+        inv = np.where(rho > 0, 1.0 / np.where(rho > 0, rho, 1.0), 0.0)
+        mean_b = s1[i] / nb
+        var_b = np.maximum((s2[i] - nb * mean_b * mean_b) / (nb - 1), 0.0)
+        d_o = s1[i] * inv
+        d_g = gpu_sample[i].astype(np.float64) * inv
+        sig = np.sqrt(2.0 * nb * var_b) * inv
+        dmax = d_o.max()
+        if dmax > 0:
+            sel = d_o > 0.1 * dmax
+            dd = np.abs(d_g[sel] - d_o[sel])
+            n_sel += int(sel.sum())
+            n_ok += int(((dd <= 0.01 * dmax) | (dd <= 3.0 * sig[sel])).sum())
+        e_gpu += float(gpu_sample[i].sum(dtype=np.float64))
+        e_orc += float(s1[i].sum())
+    frac = n_ok / max(n_sel, 1)
+    e_rel = abs(e_gpu - e_orc) / max(e_orc, 1)
+    out["accuracy"] = {"check": "GPU (FP32, same histories) vs oracle (FP64) on the sample, C.8",
+                       "voxels": n_sel, "pass_frac": frac, "energy_rel": e_rel,
+                       "passed": bool(frac >= 0.99 and e_rel <= 1e-3)}
+    log(f"accuracy on the sample: {n_sel} voxels above 10 % Dmax, pass {frac:.4f}, dE {e_rel:.2e}")
+    return out
 
 
 if __name__ == "__main__":
