@@ -178,6 +178,49 @@ def make_thorax(shape_xyz=(256, 256, 160), phase=0, n_phases=10, period=4.0,
     return Phase(hu, sp, org, CALIB_HU.copy(), CALIB_RHO.copy(), CALIB_RSP.copy())
 
 
+@dataclasses.dataclass
+class Dvf:
+    """A deformation vector field as a DICOM deformable registration stores
+    it (App. B): a grid of points (i, j, k), 0 <= i < n[0] along the row
+    direction, ..., at start_mm + i spacing[0] row + j spacing[1] col +
+    k spacing[2] (row x col), each with a translation delta_mm (mm, the
+    pre/post rigid matrices are the identity between 4DCT phases)."""
+    n: Tuple[int, int, int]
+    start_mm: Tuple[float, float, float]
+    spacing_mm: Tuple[float, float, float]
+    row: Tuple[float, float, float]
+    col: Tuple[float, float, float]
+    delta_mm: np.ndarray  # float64 (n[2], n[1], n[0], 3), i fastest
+
+
+def thorax_dvf(phase: int, ref_phase: int = 0, n_phases=10, period=4.0, spacing_mm=(2.5, 2.5, 2.5),
+               half_extent_mm=(170.0, 120.0, 150.0), taper_mm=15.0, lung_scale=1.0) -> Dvf:
+    """Source-to-reference DVF of the synthetic thorax (make_thorax): points
+    of the lungs (and the tumour in them) on `phase` move back by the
+    breathing shift between the two phases along z; the weight falls from 1
+    on the lung surface to 0 taper_mm outside it (cosine), so the field is
+    smooth; the body, spine and air stay.  The grid covers the body, not the
+    whole CT (like a registration's grid)."""
+    d_src = breathing_shift_mm(period * phase / n_phases, period=period)
+    d_ref = breathing_shift_mm(period * ref_phase / n_phases, period=period)
+    n = tuple(int(2 * h / s) + 1 for h, s in zip(half_extent_mm, spacing_mm))
+    start = tuple(-h for h in half_extent_mm)
+    x = start[0] + np.arange(n[0]) * spacing_mm[0]
+    y = start[1] + np.arange(n[1]) * spacing_mm[1]
+    z = start[2] + np.arange(n[2]) * spacing_mm[2]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    la = np.array([55.0, 70.0, 100.0]) * lung_scale
+    w = np.zeros(Z.shape)
+    for cx in (-80.0, 80.0):
+        q = np.sqrt(((X - cx) / la[0]) ** 2 + ((Y - 10.0) / la[1]) ** 2 + ((Z - (-20.0 + d_src)) / la[2]) ** 2)
+        # distance outside the surface, in mm, along the ellipsoid's smallest axis
+        out_mm = np.maximum(q - 1.0, 0.0) * la.min()
+        w = np.maximum(w, np.where(out_mm < taper_mm, 0.5 * (1.0 + np.cos(np.pi * out_mm / taper_mm)), 0.0))
+    delta = np.zeros(Z.shape + (3,))
+    delta[..., 2] = -(d_src - d_ref) * w
+    return Dvf(n, start, tuple(spacing_mm), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), delta)
+
+
 # ----------------------------------------------------------------------------
 # Plans and the simplified delivery clock
 # ----------------------------------------------------------------------------
