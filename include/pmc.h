@@ -376,6 +376,54 @@ int pmc_influence_device(pmc_context *ctx, const int64_t **row_ptr, const int32_
 /* Free the influence matrix and its scratch. */
 int pmc_influence_free(pmc_context *ctx);
 
+/* ---- deformable dose accumulation (Sec. 2.D) ------------------------------ */
+
+/* A deformation vector field as a DICOM deformable registration stores it
+ * (App. B, Eqs. (7)-(8)): grid point (i, j, k), 0 <= i < n[0] ..., sits at
+ * start_mm + i spacing_mm[0] row + j spacing_mm[1] col + k spacing_mm[2]
+ * (row x col) and maps to that position plus its translation (the pre/post
+ * rigid matrices are the identity between phases of one 4DCT).  A point
+ * between grid points maps to the trilinear interpolation of the mapped
+ * points around it; points outside the box of grid points are not mapped.
+ * For accumulation the field maps a source phase onto the reference phase. */
+typedef struct {
+  int32_t n[3];            /* grid points along row, column, depth; each >= 2 */
+  double start_mm[3];      /* position of grid point (0, 0, 0), scanner frame */
+  double spacing_mm[3];    /* > 0 */
+  double row[3], col[3];   /* unit, orthogonal direction cosines (within 1e-6) */
+  const double *delta_mm;  /* translations (x, y, z) per grid point, i fastest, then j, k */
+} pmc_dvf;
+
+/* Copy a DVF to the device as `dvf` (0..1023), replacing one of that id. */
+int pmc_load_dvf(pmc_context *ctx, int32_t dvf, const pmc_dvf *d);
+int pmc_unload_dvf(pmc_context *ctx, int32_t dvf);
+
+/* Accumulated dose on the reference phase's grid by energy/mass transfer
+ * (Sec. 2.D.2, Eqs. (2), (4)-(6)), Gy per history of a run of n_histories:
+ *   D_i = D_i^R + sum over sources S (in list order) of D_i^S,
+ * D^R the reference phase's own dose (ref_tally, as pmc_convert_device), and
+ * D_i^S = sum E / sum M over the subvoxels of S mapped into reference voxel i:
+ * every voxel of S is cut into n_sub^3 equal subvoxels, each centre mapped by
+ * the source's DVF; a subvoxel carries mass rho v and energy rho v D, i.e.
+ * 1/n_sub^3 of its voxel's tally, and rho is the density the transport uses
+ * (0 outside an external mask).  Sums are exact integers (tally units, and
+ * round-half-even(rho 2^32) per subvoxel), so the result does not depend on
+ * the schedule.  Reported (else 0) where the reference voxel centre lies in
+ * the grid box of every source DVF; mask_out (nullable, one byte per voxel)
+ * receives that mask.  Tallies in the units of pmc_dose (2^-32 MeV) on each
+ * phase's own grid.  n_sub 1..16, n_src 0..PMC_MAX_PHASES.
+ * pmc_accumulate: host buffers, blocks until done.
+ * pmc_accumulate_device: device buffers, enqueued on `stream` (the call is
+ * ordered after earlier accumulations on other streams; their accumulator
+ * memory is shared). */
+int pmc_accumulate(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
+                   const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
+                   int32_t n_sub, uint64_t n_histories, double *dose_out, uint8_t *mask_out);
+int pmc_accumulate_device(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
+                          const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
+                          int32_t n_sub, uint64_t n_histories, void *stream, double *dev_dose,
+                          uint8_t *dev_mask);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,15 @@ struct PhaseRec {
   long long nvox() const { return (long long)nx * ny * nz; }
 };
 
+// A resident deformation vector field (App. B).
+struct DvfRec {
+  pmc::DvfDev dev = {};   // geometry; dev.delta points into d_delta
+  void *d_delta = nullptr;
+  size_t cap = 0;
+  size_t bytes = 0;
+  UseEvents uses;
+};
+
 struct PlanRec {
   std::vector<pmc_field> fields;
   std::vector<pmc_spot> spots;
@@ -156,6 +165,11 @@ struct pmc_context {
   size_t inf_cap = 0;        // capacity of inf_voxel / inf_value, entries
   int64_t inf_n_rows = -1;   // -1: no result
   uint64_t inf_nnz = 0;
+  // dose accumulation: resident DVFs and the energy/mass accumulators of the
+  // reference grid (3 x uint64 per voxel), last used on the streams in acc_uses
+  std::map<int32_t, DvfRec> dvfs;
+  DevBuf acc;
+  UseEvents acc_uses;
 };
 
 namespace {
@@ -1072,6 +1086,13 @@ void pmc_destroy(pmc_context *ctx) {
     release(ctx, ctx->inf_rows);
     release(ctx, ctx->inf_voxel);
     release(ctx, ctx->inf_value);
+    for (auto &kv : ctx->dvfs) {
+      drop_use(kv.second.uses);
+      pool_put(ctx, kv.second.d_delta, kv.second.cap);
+    }
+    ctx->dvfs.clear();
+    drop_use(ctx->acc_uses);
+    release(ctx, ctx->acc);
     for (hipEvent_t ev : ctx->cursor_done)
       if (ev) (void)hipEventDestroy(ev);
     for (auto &kv : ctx->stream_done) (void)hipEventDestroy(kv.second);
@@ -2122,3 +2143,249 @@ int pmc_influence_free(pmc_context *ctx) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// deformable dose accumulation (Sec. 2.D.2, energy/mass transfer; App. B)
+// ===========================================================================
+
+int pmc_load_dvf(pmc_context *ctx, int32_t dvf, const pmc_dvf *d) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (dvf < 0 || dvf > kMaxPhaseId) return fail(ctx, PMC_E_INVAL, "dvf id must be 0..%d", kMaxPhaseId);
+  if (!d || !d->delta_mm) return fail(ctx, PMC_E_INVAL, "NULL DVF");
+  for (int k = 0; k < 3; ++k) {
+    if (d->n[k] < 2) return fail(ctx, PMC_E_INVAL, "a DVF grid needs >= 2 points along every axis");
+    if (!(std::isfinite(d->spacing_mm[k]) && d->spacing_mm[k] > 0.0))
+      return fail(ctx, PMC_E_INVAL, "DVF spacing must be finite and > 0");
+  }
+  if (!finite3(d->start_mm) || !finite3(d->row) || !finite3(d->col))
+    return fail(ctx, PMC_E_INVAL, "DVF start and directions must be finite");
+  const double nr = norm3(d->row), nc = norm3(d->col);
+  const double dot = d->row[0] * d->col[0] + d->row[1] * d->col[1] + d->row[2] * d->col[2];
+  if (std::fabs(nr - 1.0) > 1e-6 || std::fabs(nc - 1.0) > 1e-6 || std::fabs(dot) > 1e-6)
+    return fail(ctx, PMC_E_INVAL, "DVF row and column directions must be orthonormal");
+  const long long pts = (long long)d->n[0] * d->n[1] * d->n[2];
+  if (pts > (1LL << 31)) return fail(ctx, PMC_E_INVAL, "DVF grid has more than 2^31 points");
+  for (long long i = 0; i < 3 * pts; ++i)
+    if (!std::isfinite(d->delta_mm[i])) return fail(ctx, PMC_E_INVAL, "DVF translation %lld is not finite", i / 3);
+  DvfRec rec;
+  pmc::DvfDev &g = rec.dev;
+  for (int k = 0; k < 3; ++k) {
+    g.n[k] = d->n[k];
+    g.start[k] = d->start_mm[k];
+    g.sp[k] = d->spacing_mm[k];
+    g.u[k] = d->row[k];
+    g.v[k] = d->col[k];
+  }
+  // depth direction W = U x V (Eq. (8))
+  g.w[0] = g.u[1] * g.v[2] - g.u[2] * g.v[1];
+  g.w[1] = g.u[2] * g.v[0] - g.u[0] * g.v[2];
+  g.w[2] = g.u[0] * g.v[1] - g.u[1] * g.v[0];
+  rec.bytes = sizeof(double) * 3 * (size_t)pts;
+  if (ctx->has_device) {
+    HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    int rc = pool_get(ctx, rec.bytes, &rec.d_delta, &rec.cap, "DVF translations");
+    if (rc) return rc;
+    hipError_t e = copy_sync(ctx, rec.d_delta, d->delta_mm, rec.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      pool_put(ctx, rec.d_delta, rec.cap);
+      return hip_fail(ctx, e, "upload DVF");
+    }
+    g.delta = static_cast<const double *>(rec.d_delta);
+  }
+  auto it = ctx->dvfs.find(dvf);
+  if (it != ctx->dvfs.end()) {
+    wait_use(it->second.uses);
+    drop_use(it->second.uses);
+    pool_put(ctx, it->second.d_delta, it->second.cap);
+    ctx->dvfs.erase(it);
+  }
+  ctx->dvfs[dvf] = std::move(rec);
+  return PMC_OK;
+}
+
+int pmc_unload_dvf(pmc_context *ctx, int32_t dvf) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  auto it = ctx->dvfs.find(dvf);
+  if (it == ctx->dvfs.end()) return fail(ctx, PMC_E_STATE, "dvf %d is not loaded", dvf);
+  wait_use(it->second.uses);
+  drop_use(it->second.uses);
+  pool_put(ctx, it->second.d_delta, it->second.cap);
+  ctx->dvfs.erase(it);
+  return PMC_OK;
+}
+
+namespace {
+
+int validate_accumulate(pmc_context *ctx, int32_t ref_phase, int32_t n_src, const int32_t *src_phases,
+                        const int32_t *src_dvfs, int32_t n_sub, uint64_t n_histories) {
+  if (ctx->phases.find(ref_phase) == ctx->phases.end())
+    return fail(ctx, PMC_E_NOPHASE, "reference phase %d is not loaded", ref_phase);
+  if (n_src < 0 || n_src > PMC_MAX_PHASES) return fail(ctx, PMC_E_INVAL, "n_src must be 0..%d", PMC_MAX_PHASES);
+  if (n_src > 0 && (!src_phases || !src_dvfs)) return fail(ctx, PMC_E_INVAL, "NULL source list");
+  for (int32_t s = 0; s < n_src; ++s) {
+    if (ctx->phases.find(src_phases[s]) == ctx->phases.end())
+      return fail(ctx, PMC_E_NOPHASE, "source phase %d is not loaded", src_phases[s]);
+    if (ctx->dvfs.find(src_dvfs[s]) == ctx->dvfs.end())
+      return fail(ctx, PMC_E_STATE, "dvf %d is not loaded", src_dvfs[s]);
+  }
+  if (n_sub < 1 || n_sub > 16) return fail(ctx, PMC_E_INVAL, "n_sub must be 1..16");
+  if (n_histories == 0) return fail(ctx, PMC_E_INVAL, "n_histories must be >= 1");
+  return PMC_OK;
+}
+
+}  // namespace
+
+int pmc_accumulate_device(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
+                          const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
+                          int32_t n_sub, uint64_t n_histories, void *stream, double *dev_dose,
+                          uint8_t *dev_mask) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  int rc = validate_accumulate(ctx, ref_phase, n_src, src_phases, src_dvfs, n_sub, n_histories);
+  if (rc) return rc;
+  if (!ref_tally || !dev_dose) return fail(ctx, PMC_E_INVAL, "need the reference tally and a dose buffer");
+  if (n_src > 0 && !src_tallies) return fail(ctx, PMC_E_INVAL, "NULL source tallies");
+  for (int32_t s = 0; s < n_src; ++s)
+    if (!src_tallies[s]) return fail(ctx, PMC_E_INVAL, "source tally %d is NULL", s);
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  PhaseRec &ref = ctx->phases[ref_phase];
+  const long long nvox = ref.nvox();
+  const double vol_ref = (0.1 * ref.sp_mm[0]) * (0.1 * ref.sp_mm[1]) * (0.1 * ref.sp_mm[2]);
+  const double nh = (double)n_histories;
+  // D^R: the reference phase's own dose (Eq. (2), first term)
+  HIP_TRY(ctx, pmc::launch_convert((const long long *)ref_tally, ref.d_hu, ref.d_mask, ref.d_lut64, nvox,
+                                   vol_ref, nh, dev_dose, nullptr, st),
+          "reference dose");
+  if (n_src > 0) {
+    // accumulators: wait (on this stream) for the calls that used them before
+    rc = ensure(ctx, ctx->acc, 3 * sizeof(unsigned long long) * (size_t)nvox, "accumulators");
+    if (rc) return rc;
+    for (auto &p : ctx->acc_uses.ev) HIP_TRY(ctx, hipStreamWaitEvent(st, p.second, 0), "wait accumulators");
+    auto *e_hi = static_cast<unsigned long long *>(ctx->acc.p);
+    auto *e_lo = e_hi + nvox, *mass = e_lo + nvox;
+    for (int32_t s = 0; s < n_src; ++s) {
+      const PhaseRec &src = ctx->phases[src_phases[s]];
+      const DvfRec &dv = ctx->dvfs[src_dvfs[s]];
+      HIP_TRY(ctx, pmc::launch_fill_u64(e_hi, 3 * nvox, 0ull, st), "zero accumulators");
+      pmc::EmtmPush a = {};
+      a.hu = src.d_hu;
+      a.mask = src.d_mask;
+      a.lut64 = static_cast<const double *>(src.d_lut64);
+      a.tally = (const long long *)src_tallies[s];
+      a.nx = src.nx;
+      a.ny = src.ny;
+      a.nz = src.nz;
+      a.dvf = dv.dev;
+      a.rnx = ref.nx;
+      a.rny = ref.ny;
+      a.rnz = ref.nz;
+      for (int k = 0; k < 3; ++k) {
+        a.org[k] = src.org_mm[k];
+        a.sp[k] = src.sp_mm[k];
+        a.rorg[k] = ref.org_mm[k];
+        a.rsp[k] = ref.sp_mm[k];
+      }
+      a.n_sub = n_sub;
+      a.e_hi = e_hi;
+      a.e_lo = e_lo;
+      a.mass = mass;
+      HIP_TRY(ctx, pmc::launch_emtm_push(a, st), "emtm_push launch");
+      pmc::EmtmRatio r = {};
+      r.e_hi = e_hi;
+      r.e_lo = e_lo;
+      r.mass = mass;
+      r.dose = dev_dose;
+      r.nvox = nvox;
+      r.vol_cm3 = (0.1 * src.sp_mm[0]) * (0.1 * src.sp_mm[1]) * (0.1 * src.sp_mm[2]);
+      r.n_hist = nh;
+      HIP_TRY(ctx, pmc::launch_emtm_ratio(r, st), "emtm_ratio launch");
+    }
+  }
+  // report mask: the reference voxel centres inside every DVF's grid box
+  for (int32_t s0 = 0; s0 < n_src || (s0 == 0 && dev_mask); s0 += pmc::kMaskDvfs) {
+    pmc::EmtmMask m = {};
+    m.n_dvf = std::min<int32_t>(pmc::kMaskDvfs, n_src - s0);
+    for (int32_t k = 0; k < m.n_dvf; ++k) m.dvfs[k] = ctx->dvfs[src_dvfs[s0 + k]].dev;
+    m.first = s0 == 0;
+    m.nx = ref.nx;
+    m.ny = ref.ny;
+    m.nz = ref.nz;
+    for (int k = 0; k < 3; ++k) {
+      m.org[k] = ref.org_mm[k];
+      m.sp[k] = ref.sp_mm[k];
+    }
+    m.dose = dev_dose;
+    m.mask_out = dev_mask;
+    HIP_TRY(ctx, pmc::launch_emtm_mask(m, st), "emtm_mask launch");
+    if (n_src == 0) break;
+  }
+  // the inputs read by this call stay alive until it has run
+  rc = note_use(ctx, ref.uses, st);
+  for (int32_t s = 0; s < n_src && !rc; ++s) {
+    rc = note_use(ctx, ctx->phases[src_phases[s]].uses, st);
+    if (!rc) rc = note_use(ctx, ctx->dvfs[src_dvfs[s]].uses, st);
+  }
+  if (!rc && n_src > 0) rc = note_use(ctx, ctx->acc_uses, st);
+  if (rc) return rc;
+  return note_pending(ctx, st);
+}
+
+int pmc_accumulate(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
+                   const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
+                   int32_t n_sub, uint64_t n_histories, double *dose_out, uint8_t *mask_out) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  int rc = validate_accumulate(ctx, ref_phase, n_src, src_phases, src_dvfs, n_sub, n_histories);
+  if (rc) return rc;
+  if (!ref_tally || !dose_out) return fail(ctx, PMC_E_INVAL, "need the reference tally and a dose buffer");
+  if (n_src > 0 && !src_tallies) return fail(ctx, PMC_E_INVAL, "NULL source tallies");
+  for (int32_t s = 0; s < n_src; ++s)
+    if (!src_tallies[s]) return fail(ctx, PMC_E_INVAL, "source tally %d is NULL", s);
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  // device copies of the tallies (source grids may differ from the reference)
+  struct Block { void *p = nullptr; size_t cap = 0; };
+  std::vector<Block> blocks;
+  auto cleanup = [&](int code) {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &b : blocks) pool_put(ctx, b.p, b.cap);
+    return code;
+  };
+  auto upload = [&](const void *src, size_t bytes, void **dst) -> int {
+    Block b;
+    int r = pool_get(ctx, std::max<size_t>(bytes, 256), &b.p, &b.cap, "accumulation inputs");
+    if (r) return r;
+    blocks.push_back(b);
+    *dst = b.p;
+    if (src) {
+      hipError_t e = copy_sync(ctx, b.p, src, bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(ctx, e, "upload tally");
+    }
+    return PMC_OK;
+  };
+  const PhaseRec &ref = ctx->phases[ref_phase];
+  const long long nvox = ref.nvox();
+  void *d_ref = nullptr, *d_dose = nullptr, *d_mask = nullptr;
+  rc = upload(ref_tally, sizeof(int64_t) * (size_t)nvox, &d_ref);
+  std::vector<const int64_t *> d_src((size_t)n_src, nullptr);
+  for (int32_t s = 0; s < n_src && !rc; ++s) {
+    void *p = nullptr;
+    rc = upload(src_tallies[s], sizeof(int64_t) * (size_t)ctx->phases[src_phases[s]].nvox(), &p);
+    d_src[s] = static_cast<const int64_t *>(p);
+  }
+  if (!rc) rc = upload(nullptr, sizeof(double) * (size_t)nvox, &d_dose);
+  if (!rc && mask_out) rc = upload(nullptr, (size_t)nvox, &d_mask);
+  if (rc) return cleanup(rc);
+  rc = pmc_accumulate_device(ctx, ref_phase, static_cast<const int64_t *>(d_ref), n_src, src_phases, src_dvfs,
+                             d_src.data(), n_sub, n_histories, ctx->stream, static_cast<double *>(d_dose),
+                             static_cast<uint8_t *>(d_mask));
+  if (rc) return cleanup(rc);
+  hipError_t e = copy_sync(ctx, dose_out, d_dose, sizeof(double) * (size_t)nvox, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && mask_out) e = copy_sync(ctx, mask_out, d_mask, (size_t)nvox, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "download accumulated dose"));
+  return cleanup(PMC_OK);
+}

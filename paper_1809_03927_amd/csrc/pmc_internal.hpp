@@ -151,6 +151,56 @@ struct InfluenceLaunch {
   float *value;
 };
 
+// Deformation vector field on the device (App. B): grid points i + n[0] (j +
+// n[1] k) at start + i sp[0] u + j sp[1] v + k sp[2] w, translations delta
+// (3 doubles per point, same order).
+struct DvfDev {
+  int32_t n[3];
+  double start[3], sp[3];
+  double u[3], v[3], w[3];
+  const double *delta;
+};
+
+// Energy/mass push of one source phase into the reference accumulators.
+struct EmtmPush {
+  const int16_t *hu;
+  const uint8_t *mask;       // nullable
+  const double *lut64;       // (rho, rsp) per HU -1024..3071
+  const long long *tally;
+  int32_t nx, ny, nz;
+  double org[3], sp[3];      // source grid, mm
+  DvfDev dvf;                // source -> reference
+  int32_t rnx, rny, rnz;
+  double rorg[3], rsp[3];    // reference grid, mm
+  int32_t n_sub;
+  unsigned long long *e_hi, *e_lo, *mass;  // per reference voxel
+};
+
+// dose_i += (e_hi 2^32 + e_lo) MeV_to_J / (mass vol 1e-3 n_hist) where mass > 0.
+struct EmtmRatio {
+  const unsigned long long *e_hi, *e_lo, *mass;
+  double *dose;
+  long long nvox;
+  double vol_cm3, n_hist;
+};
+
+// Zero the dose (and clear the mask) outside the grid box of any of up to
+// kMaskDvfs DVFs; `first` writes the mask, later passes only clear it.
+constexpr int kMaskDvfs = 16;
+struct EmtmMask {
+  DvfDev dvfs[kMaskDvfs];
+  int32_t n_dvf;
+  int32_t first;
+  int32_t nx, ny, nz;
+  double org[3], sp[3];
+  double *dose;
+  uint8_t *mask_out;  // nullable
+};
+
+hipError_t launch_emtm_push(const EmtmPush &a, hipStream_t st);
+hipError_t launch_emtm_ratio(const EmtmRatio &a, hipStream_t st);
+hipError_t launch_emtm_mask(const EmtmMask &a, hipStream_t st);
+
 hipError_t launch_influence_reduce(const InfluenceLaunch &a, hipStream_t st);  // max, sum, count, scan
 hipError_t launch_influence_write(const InfluenceLaunch &a, hipStream_t st);   // rows and entries
 

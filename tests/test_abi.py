@@ -250,3 +250,44 @@ def test_balance_from_words_matches_library(P):
         assert P.balance_from_words(c, dep, inc) == ref
     finally:
         P.pmc_destroy(ctx)
+
+
+def test_dvf_and_accumulation_validation(P):
+    ctx = P.pmc_create(device=-1)
+    try:
+        ph = W.make_water(8, 2.0)
+        P.pmc_load_phase(ctx, 0, ph)
+        P.pmc_load_phase(ctx, 1, ph)
+        n = (3, 3, 3)
+        good = W.Dvf(n, (0.0, 0.0, 0.0), (4.0, 4.0, 4.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0),
+                     np.zeros((3, 3, 3, 3)))
+        for bad in (W.Dvf((1, 3, 3), good.start_mm, good.spacing_mm, good.row, good.col, np.zeros((3, 3, 1, 3))),
+                    W.Dvf(n, good.start_mm, (4.0, 0.0, 4.0), good.row, good.col, good.delta_mm),
+                    W.Dvf(n, good.start_mm, good.spacing_mm, good.row, (1.0, 0.0, 0.0), good.delta_mm),
+                    W.Dvf(n, good.start_mm, good.spacing_mm, good.row, good.col,
+                          np.full((3, 3, 3, 3), np.nan))):
+            with pytest.raises(P.PmcError) as e:
+                P.pmc_load_dvf(ctx, 0, bad)
+            assert e.value.code == P.PMC_E_INVAL
+        P.pmc_load_dvf(ctx, 4, good)
+        t = np.zeros(8 ** 3, dtype=np.int64)
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_accumulate(ctx, 0, t, [1], [5], [t], 2, 10, 8 ** 3)
+        assert e.value.code == P.PMC_E_STATE  # dvf 5 not loaded
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_accumulate(ctx, 0, t, [2], [4], [t], 2, 10, 8 ** 3)
+        assert e.value.code == P.PMC_E_NOPHASE
+        for kw in (dict(n_sub=0), dict(n_sub=17), dict(n_histories=0)):
+            args = dict(n_sub=2, n_histories=10)
+            args.update(kw)
+            with pytest.raises(P.PmcError) as e:
+                P.pmc_accumulate(ctx, 0, t, [1], [4], [t], args["n_sub"], args["n_histories"], 8 ** 3)
+            assert e.value.code == P.PMC_E_INVAL, kw
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_accumulate(ctx, 0, t, [1], [4], [t], 2, 10, 8 ** 3)
+        assert e.value.code == P.PMC_E_DEVICE  # all arguments valid
+        P.pmc_unload_dvf(ctx, 4)
+        with pytest.raises(P.PmcError):
+            P.pmc_unload_dvf(ctx, 4)
+    finally:
+        P.pmc_destroy(ctx)

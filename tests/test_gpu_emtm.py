@@ -1,0 +1,137 @@
+"""Energy/mass-transfer dose accumulation on the GPU (pmc_accumulate, through
+the C ABI) against the oracle's plain FP64 evaluation of Eqs. (2), (4)-(6)
+with the App. B DVFs: same integer sums, same mapping decisions, so the doses
+agree to the rounding of the mass units (the two sides compute the densities
+independently) and the report masks are identical."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1809_03927_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1809_03927_amd import pmc
+    return pmc
+
+
+@pytest.fixture(scope="module")
+def E():
+    import oracle.emtm as emtm
+    return emtm
+
+
+def densities(orc, phases):
+    return [orc.convert(ph, np.zeros(ph.hu.size, dtype=np.int64), 1)[1] for ph in phases]
+
+
+def compare(got, want, mask_got, mask_want):
+    assert np.array_equal(mask_got.astype(bool), mask_want)
+    exact = np.mean(got == want)
+    assert np.allclose(got, want, rtol=1e-9, atol=0), np.max(np.abs(got - want) / np.maximum(want, 1e-300))
+    assert exact > 0.999, exact
+
+
+@pytest.mark.parametrize("n_sub", [1, 3])
+def test_accumulation_matches_oracle_random_tallies(P, E, orc, n_sub):
+    """Thorax phases 3, 5, 8 accumulated onto phase 0 with the breathing DVFs;
+    random integer tallies exercise both 32-bit halves of the energy sums."""
+    shape = (64, 64, 40)
+    ids = [0, 3, 5, 8]
+    phases = [W.make_thorax(shape, p, 10) for p in ids]
+    dvfs = [None] + [W.thorax_dvf(p, 0) for p in ids[1:]]
+    rng = np.random.default_rng(7)
+    tallies = [rng.integers(0, 2**45, size=ph.hu.size) * (ph.hu.ravel() > -1000) for ph in phases]
+    rho = densities(orc, phases)
+    ctx = P.pmc_create(0, P.PMC_FP32, 1, 0)
+    try:
+        for k, ph in enumerate(phases):
+            P.pmc_load_phase(ctx, k, ph)
+        for k in range(1, len(ids)):
+            P.pmc_load_dvf(ctx, 10 + k, dvfs[k])
+        say("emtm random tallies", shape, "n_sub", n_sub)
+        dose, mask = P.pmc_accumulate(ctx, 0, tallies[0], [1, 2, 3], [11, 12, 13], tallies[1:], n_sub,
+                                      1000, phases[0].hu.size, want_mask=True)
+    finally:
+        P.pmc_destroy(ctx)
+    ref = E.emtm(phases, tallies, rho, 0, dvfs, n_sub, 1000)
+    assert ref["mask"].sum() < ref["mask"].size  # the DVF grids do not cover the whole CT
+    compare(dose, ref["dose"], mask, ref["mask"])
+
+
+def test_accumulation_of_a_4d_transport_run(P, E, orc):
+    """Per-phase tallies of a 4D thorax run on the GPU, phases 2, 5 and 7
+    accumulated onto phase 0 (n_sub 2), host and device entry points, against
+    the oracle."""
+    import torch
+    wl = W.workload_thorax4d(n_histories=300_000, shape_xyz=(64, 64, 40))
+    phases = list(range(10))
+    e = P.Engine(device=0, precision=P.PMC_FP32, seed=wl.seed)
+    try:
+        e.load_workload(wl)
+        say("4D run for accumulation")
+        _, tallies, _, _ = e.dose(wl.n_histories, phases, engine=P.PMC_ENGINE_PERSISTENT)
+        src = [2, 5, 7]
+        dvfs = {p: W.thorax_dvf(p, 0) for p in src}
+        for p in src:
+            P.pmc_load_dvf(e.ctx, 100 + p, dvfs[p])
+        nv = wl.phases[0].hu.size
+        dose, mask = P.pmc_accumulate(e.ctx, 0, tallies[0], src, [100 + p for p in src],
+                                      [tallies[p] for p in src], 2, wl.n_histories, nv, want_mask=True)
+        # device entry point on torch buffers and stream: identical result
+        st = torch.cuda.Stream()
+        dt = [torch.from_numpy(t).cuda() for t in tallies]
+        dd = torch.empty(nv, dtype=torch.float64, device="cuda")
+        dm = torch.empty(nv, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        P.pmc_accumulate_device(e.ctx, 0, dt[0].data_ptr(), src, [100 + p for p in src],
+                                [dt[p].data_ptr() for p in src], 2, wl.n_histories, st.cuda_stream,
+                                dd.data_ptr(), dm.data_ptr())
+        st.synchronize()
+        assert np.array_equal(dd.cpu().numpy(), dose) and np.array_equal(dm.cpu().numpy(), mask)
+    finally:
+        e.close()
+    sel = [0] + src
+    rho = densities(orc, [wl.phases[p] for p in sel])
+    ref = E.emtm([wl.phases[p] for p in sel], [tallies[p] for p in sel], rho, 0,
+                 [None] + [dvfs[p] for p in src], 2, wl.n_histories)
+    compare(dose, ref["dose"], mask, ref["mask"])
+    # the energy the DVFs move stays on the grid: the accumulated dose carries
+    # (to the mask and the mass-weighting) the run's energy
+    assert dose.max() > 0
+
+
+def test_identity_dvfs_sum_the_phase_doses(P, orc):
+    """Identity DVFs covering the grid: each source voxel lands in itself, so
+    the accumulated dose is the sum of the phases' own doses (Sec. 2.E's
+    first test, with the MC doses of a 4D run)."""
+    wl = W.workload_thorax4d(n_histories=200_000, shape_xyz=(64, 64, 40), n_phases=3)
+    e = P.Engine(device=0, precision=P.PMC_FP32, seed=wl.seed)
+    try:
+        e.load_workload(wl)
+        doses, tallies, _, _ = e.dose(wl.n_histories, [0, 1, 2], engine=P.PMC_ENGINE_PERSISTENT)
+        ph = wl.phases[0]
+        nz, ny, nx = ph.hu.shape
+        sp = np.asarray(ph.spacing_mm)
+        o = np.asarray(ph.origin_mm) - sp
+        ident = W.Dvf((nx + 2, ny + 2, nz + 2), tuple(o), tuple(sp), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0),
+                      np.zeros((nz + 2, ny + 2, nx + 2, 3)))
+        P.pmc_load_dvf(e.ctx, 7, ident)
+        for n_sub in (1, 4):
+            dose, mask = P.pmc_accumulate(e.ctx, 0, tallies[0], [1, 2], [7, 7], tallies[1:], n_sub,
+                                          wl.n_histories, ph.hu.size, want_mask=True)
+            assert mask.all()
+            want = doses[0] + doses[1] + doses[2]
+            # mass counts in units of 2^-32 g/cm^3 per subvoxel: relative
+            # rounding up to 0.5 / (rho 2^32), 1e-7 in air
+            assert np.allclose(dose, want, rtol=2e-7, atol=0), n_sub
+    finally:
+        e.close()
