@@ -6,18 +6,28 @@
 //               DVF translations, FP64); the voxel's energy (tally, as two
 //               32-bit halves) and mass units (round(rho 2^32)) are added,
 //               once per subvoxel, to the reference voxel each centre lands
-//               in.  A thread merges its subvoxels by target (up to 8 targets
-//               in registers) before its atomics: a voxel usually maps into
-//               few reference voxels.
+//               in.  The thread counts its subvoxels per reference voxel in a
+//               private LDS window of 4x4x4 voxels (16-bit counts) around the
+//               first one, and adds count x energy and count x mass with one
+//               set of device atomics per voxel it reached.
 //  emtm_ratio   dose_i += sum E / sum M (Eq. (5)) per reference voxel, in
 //               Gy per history, added in source order (Eq. (2)).
 //  emtm_mask    keeps the dose where the reference voxel centre lies in the
 //               grid box of every DVF.
 //
 // Every floating-point decision (which reference voxel a centre lands in)
-// uses the same FP64 operations in the same order as a plain evaluation of
-// the formulas (no contraction), and every sum is an integer sum, so the
-// result does not depend on the schedule.
+// equals that of a plain FP64 evaluation of the formulas in their written
+// order (no contraction), and every sum is an integer sum, so the result does
+// not depend on the schedule.
+//
+// Axis-aligned DVF grids (row (1,0,0), column (0,1,0), so depth (0,0,1)):
+// the grid coordinate along an axis is then the point's own coordinate minus
+// the start over the spacing, exactly (x*1 = x, the other terms are signed
+// zeros, which change no decision below), so each axis is evaluated once per
+// subvoxel row (z: once per voxel, kept in LDS).  With z innermost, the
+// x- and y-interpolated translations of a DVF cell are reused while the
+// subvoxels stay in that cell; a wave's lanes share z, so the reload is
+// wave-uniform.
 #include <hip/hip_runtime.h>
 
 #include "pmc_internal.hpp"
@@ -26,7 +36,14 @@ namespace pmc {
 
 namespace {
 
-constexpr int kTargets = 8;
+constexpr int kBlock = 256;
+constexpr int kMaxSub = 16;
+constexpr int kWin = 4;                              // window offsets -1..+2 per axis
+constexpr int kWinCells = kWin * kWin * kWin;
+
+// log2 of the counts per 32-bit window word: four 8-bit counts while a voxel
+// has at most 255 subvoxels (n <= 6), else two 16-bit counts (n^3 <= 4096).
+__host__ __device__ __forceinline__ int win_lg(int n) { return n * n * n <= 255 ? 2 : 1; }
 
 __device__ __forceinline__ bool dvf_coords(const DvfDev &d, double px, double py, double pz, double g[3]) {
   const double rx = px - d.start[0], ry = py - d.start[1], rz = pz - d.start[2];
@@ -77,10 +94,134 @@ __device__ __forceinline__ void add_u64(unsigned long long *p, unsigned long lon
                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(256) emtm_push(EmtmPush a) {
-  const long long nvox = (long long)a.nx * a.ny * a.nz;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < nvox; j += stride) {
+struct Deposit {
+  unsigned long long t_hi, t_lo, mq;
+};
+
+__device__ __forceinline__ void deposit(const EmtmPush &a, const Deposit &d, int i, unsigned long long c) {
+  if (d.t_hi) add_u64(a.e_hi + i, c * d.t_hi);
+  if (d.t_lo) add_u64(a.e_lo + i, c * d.t_lo);
+  add_u64(a.mass + i, c * d.mq);
+}
+
+// This thread's subvoxel counts per reference voxel: word k of the window at
+// w[k * kBlock] holds the counts of window cells k 2^lg .. (k + 1) 2^lg - 1.
+struct Window {
+  uint32_t *w;
+  int lg;
+  int b[3];
+  uint32_t touched;  // words holding counts
+  bool set;
+};
+
+// Reference voxel of a mapped point q (Eq. (6): the voxel containing it);
+// false outside the reference grid.  Along each axis the index is
+// floor(RN(t / r)), t = q - origin, as a plain division gives it.  With
+// a = t * rinv (rinv = RN(1/r)): |a - t/r| <= |t/r| (2^-52 + 2^-106) and
+// |RN(t/r) - t/r| <= |t/r| 2^-53, so |a - RN(t/r)| < |a| 2^-50, below 2^-30
+// while |a| < 2^20.  Then if a - floor(a) lies in [2^-30, 1 - 2^-30],
+// RN(t/r) has the floor of a.  (That difference is exact except for
+// -1/2 < a < 0, where floor(RN(t/r)) = -1 = floor(a) anyway.)  For
+// |a| >= 2^20 both floors lie outside a grid of fewer than 2^20 voxels per
+// axis.  Otherwise, a within 2^-30 of an integer (rare), the divisions
+// decide.  Coordinates in mm give no subnormal quotients.
+__device__ __forceinline__ bool ref_voxel(const EmtmPush &a, double qx, double qy, double qz, int t[3]) {
+  const double tx = qx - a.rorg[0], ty = qy - a.rorg[1], tz = qz - a.rorg[2];
+  const double ax = tx * a.rinv[0], ay = ty * a.rinv[1], az = tz * a.rinv[2];
+  double kx = floor(ax), ky = floor(ay), kz = floor(az);
+  const double ex = ax - kx, ey = ay - ky, ez = az - kz;
+  constexpr double lo = 0x1p-30, hi = 1.0 - 0x1p-30;
+  const bool sure = (ex >= lo) & (ex <= hi) & (ey >= lo) & (ey <= hi) & (ez >= lo) & (ez <= hi);
+  if (!sure) {
+    kx = floor(tx / a.rsp[0]);
+    ky = floor(ty / a.rsp[1]);
+    kz = floor(tz / a.rsp[2]);
+  }
+  if (!((kx >= 0.0) & (kx < (double)a.rnx) & (ky >= 0.0) & (ky < (double)a.rny) & (kz >= 0.0) &
+        (kz < (double)a.rnz)))
+    return false;
+  t[0] = (int)kx;
+  t[1] = (int)ky;
+  t[2] = (int)kz;
+  return true;
+}
+
+__device__ __forceinline__ void count(const EmtmPush &a, Window &win, const Deposit &d, const int t[3]) {
+  if (a.n_sub == 1) {
+    deposit(a, d, t[0] + a.rnx * (t[1] + a.rny * t[2]), 1);
+    return;
+  }
+  const bool first = !win.set;
+  win.b[0] = first ? t[0] - 1 : win.b[0];
+  win.b[1] = first ? t[1] - 1 : win.b[1];
+  win.b[2] = first ? t[2] - 1 : win.b[2];
+  win.set = true;
+  const unsigned dx = (unsigned)(t[0] - win.b[0]), dy = (unsigned)(t[1] - win.b[1]),
+                 dz = (unsigned)(t[2] - win.b[2]);
+  if (dx < kWin && dy < kWin && dz < kWin) {
+    const unsigned c = dx + kWin * (dy + kWin * dz);
+    const unsigned lg = (unsigned)win.lg;
+    win.touched |= 1u << (c >> lg);
+    __hip_atomic_fetch_add(win.w + (c >> lg) * kBlock, 1u << ((c & ((1u << lg) - 1u)) << (5u - lg)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else {
+    deposit(a, d, t[0] + a.rnx * (t[1] + a.rny * t[2]), 1);
+  }
+}
+
+__device__ __forceinline__ void flush(const EmtmPush &a, Window &win, const Deposit &d) {
+  const int per = 1 << win.lg, bits = 32 >> win.lg;
+  const uint32_t field = (1u << bits) - 1u;
+  while (win.touched) {
+    const int k = __builtin_ctz(win.touched);
+    win.touched &= win.touched - 1u;
+    const uint32_t v = win.w[k * kBlock];
+    win.w[k * kBlock] = 0;
+    for (int h = 0; h < per; ++h) {
+      const uint32_t c = (v >> (bits * h)) & field;
+      if (!c) continue;
+      const int e = per * k + h;
+      const int x = win.b[0] + (e & 3), y = win.b[1] + ((e >> 2) & 3), z = win.b[2] + (e >> 4);
+      deposit(a, d, x + a.rnx * (y + a.rny * z), c);
+    }
+  }
+  win.set = false;
+}
+
+// Grid cell and fraction along one axis of the DVF grid (inside already checked).
+__device__ __forceinline__ int cell(double g, int n, double &f) {
+  int i = (int)floor(g);
+  if (i > n - 2) i = n - 2;
+  f = g - (double)i;
+  return i;
+}
+
+template <bool ALIGNED>
+__global__ void __launch_bounds__(kBlock) emtm_push(EmtmPush a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double off[kMaxSub];
+  const int n = a.n_sub;
+  const int tid = threadIdx.x;
+  const int lg = win_lg(n);
+  const int words = kWinCells >> lg;
+  uint32_t *win_words = reinterpret_cast<uint32_t *>(smem);
+  double *zf = reinterpret_cast<double *>(smem + sizeof(uint32_t) * words * kBlock);
+  double *zp = zf + (size_t)n * kBlock;
+  int *zb = reinterpret_cast<int *>(zp + (size_t)n * kBlock);
+  // subvoxel centre offsets (s + 1/2) / n, in voxels
+  if (tid < n) off[tid] = ((double)tid + 0.5) / (double)n;
+  for (int k = 0; k < words; ++k) win_words[k * kBlock + tid] = 0;
+  __syncthreads();
+  Window win;
+  win.w = win_words + tid;
+  win.lg = lg;
+  win.touched = 0;
+  win.set = false;
+  const DvfDev &g = a.dvf;
+  // grids hold at most 2^31 - 1 voxels
+  const unsigned nvox = (unsigned)a.nx * (unsigned)a.ny * (unsigned)a.nz;
+  const unsigned stride = gridDim.x * kBlock;
+  for (unsigned j = blockIdx.x * kBlock + tid; j < nvox; j += stride) {
     double rho = 0.0;
     if (!a.mask || a.mask[j] != 0) {
       int h = a.hu[j];
@@ -90,50 +231,97 @@ __global__ void __launch_bounds__(256) emtm_push(EmtmPush a) {
     const long long mq = (long long)rint(rho * 4294967296.0);
     if (mq <= 0) continue;  // no mass: vacuum
     const unsigned long long t = (unsigned long long)a.tally[j];
-    const unsigned long long t_hi = t >> 32, t_lo = t & 0xFFFFFFFFull;
-    const int ix = (int)(j % a.nx), iy = (int)((j / a.nx) % a.ny), iz = (int)(j / ((long long)a.nx * a.ny));
-    int tgt[kTargets], cnt[kTargets];
-    int used = 0;
-    auto flush = [&]() {
-      for (int e = 0; e < used; ++e) {
-        const unsigned long long c = (unsigned long long)cnt[e];
-        if (t_hi) add_u64(a.e_hi + tgt[e], c * t_hi);
-        if (t_lo) add_u64(a.e_lo + tgt[e], c * t_lo);
-        add_u64(a.mass + tgt[e], c * (unsigned long long)mq);
+    const Deposit d = {t >> 32, t & 0xFFFFFFFFull, (unsigned long long)mq};
+    const unsigned row = j / (unsigned)a.nx;
+    const int ix = (int)(j - row * (unsigned)a.nx), iy = (int)(row % (unsigned)a.ny), iz = (int)(row / (unsigned)a.ny);
+    if (ALIGNED) {
+      // z: coordinate, DVF cell and fraction of every subvoxel plane (cell -1
+      // outside the grid)
+      for (int sc = 0; sc < n; ++sc) {
+        const double pz = a.org[2] + ((double)iz + off[sc]) * a.sp[2];
+        const double gz = (pz - g.start[2]) / g.sp[2];
+        double f = 0.0;
+        int b = -1;
+        if (gz >= 0.0 && gz <= (double)(g.n[2] - 1)) b = cell(gz, g.n[2], f);
+        zf[sc * kBlock + tid] = f;
+        zp[sc * kBlock + tid] = pz;
+        zb[sc * kBlock + tid] = b;
       }
-      used = 0;
-    };
-    const double n = (double)a.n_sub;
-    for (int sc = 0; sc < a.n_sub; ++sc) {
-      for (int sb = 0; sb < a.n_sub; ++sb) {
-        for (int sa = 0; sa < a.n_sub; ++sa) {
-          // subvoxel centre: origin + (index + (s + 0.5) / n) spacing
-          const double px = a.org[0] + ((double)ix + ((double)sa + 0.5) / n) * a.sp[0];
-          const double py = a.org[1] + ((double)iy + ((double)sb + 0.5) / n) * a.sp[1];
-          const double pz = a.org[2] + ((double)iz + ((double)sc + 0.5) / n) * a.sp[2];
-          double q[3];
-          if (!dvf_map(a.dvf, px, py, pz, q)) continue;
-          const double fx = floor((q[0] - a.rorg[0]) / a.rsp[0]);
-          const double fy = floor((q[1] - a.rorg[1]) / a.rsp[1]);
-          const double fz = floor((q[2] - a.rorg[2]) / a.rsp[2]);
-          if (!(fx >= 0.0 && fx < (double)a.rnx && fy >= 0.0 && fy < (double)a.rny && fz >= 0.0 &&
-                fz < (double)a.rnz))
-            continue;
-          const int i = (int)fx + a.rnx * ((int)fy + a.rny * (int)fz);
-          int e = 0;
-          while (e < used && tgt[e] != i) ++e;
-          if (e < used) {
-            cnt[e] += 1;
-          } else {
-            if (used == kTargets) flush();
-            tgt[used] = i;
-            cnt[used] = 1;
-            ++used;
+      const long long sy = 3LL * g.n[0], sz = 3LL * g.n[0] * g.n[1];
+      for (int sa = 0; sa < n; ++sa) {
+        const double px = a.org[0] + ((double)ix + off[sa]) * a.sp[0];
+        const double gx = (px - g.start[0]) / g.sp[0];
+        if (!(gx >= 0.0 && gx <= (double)(g.n[0] - 1))) continue;
+        double f0;
+        const int b0 = cell(gx, g.n[0], f0);
+        for (int sb = 0; sb < n; ++sb) {
+          const double py = a.org[1] + ((double)iy + off[sb]) * a.sp[1];
+          const double gy = (py - g.start[1]) / g.sp[1];
+          if (!(gy >= 0.0 && gy <= (double)(g.n[1] - 1))) continue;
+          double f1;
+          const int b1 = cell(gy, g.n[1], f1);
+          const double *col = g.delta + 3LL * b0 + sy * b1;
+          // c0, c1: translations interpolated in x then y on the lower and
+          // upper z plane of DVF cell layer cb; dc = c1 - c0
+          int cb = -1;
+          double c0[3], c1[3], dc[3];
+          for (int sc = 0; sc < n; ++sc) {
+            const int b2 = zb[sc * kBlock + tid];
+            if (b2 < 0) continue;
+            const double f2 = zf[sc * kBlock + tid];
+            if (b2 != cb) {
+              // z grows with sc, so the next layer is usually cb + 1, whose
+              // lower plane is cb's upper plane: the same corners and
+              // operations give the same c0
+              const double *c = col + sz * b2;
+              if (cb >= 0 && b2 == cb + 1) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) c0[k] = c1[k];
+              } else {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                  const double d000 = c[k], d100 = c[3 + k], d010 = c[sy + k], d110 = c[sy + 3 + k];
+                  const double c00 = d000 + f0 * (d100 - d000);
+                  const double c10 = d010 + f0 * (d110 - d010);
+                  c0[k] = c00 + f1 * (c10 - c00);
+                }
+              }
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                const double d001 = c[sz + k], d101 = c[sz + 3 + k], d011 = c[sz + sy + k],
+                             d111 = c[sz + sy + 3 + k];
+                const double c01 = d001 + f0 * (d101 - d001);
+                const double c11 = d011 + f0 * (d111 - d011);
+                c1[k] = c01 + f1 * (c11 - c01);
+                dc[k] = c1[k] - c0[k];
+              }
+              cb = b2;
+            }
+            const double pz = zp[sc * kBlock + tid];
+            const double qx = px + (c0[0] + f2 * dc[0]);
+            const double qy = py + (c0[1] + f2 * dc[1]);
+            const double qz = pz + (c0[2] + f2 * dc[2]);
+            int tv[3];
+            if (ref_voxel(a, qx, qy, qz, tv)) count(a, win, d, tv);
+          }
+        }
+      }
+    } else {
+      for (int sa = 0; sa < n; ++sa) {
+        const double px = a.org[0] + ((double)ix + off[sa]) * a.sp[0];
+        for (int sb = 0; sb < n; ++sb) {
+          const double py = a.org[1] + ((double)iy + off[sb]) * a.sp[1];
+          for (int sc = 0; sc < n; ++sc) {
+            const double pz = a.org[2] + ((double)iz + off[sc]) * a.sp[2];
+            double q[3];
+            if (!dvf_map(g, px, py, pz, q)) continue;
+            int tv[3];
+            if (ref_voxel(a, q[0], q[1], q[2], tv)) count(a, win, d, tv);
           }
         }
       }
     }
-    flush();
+    flush(a, win, d);
   }
 }
 
@@ -176,7 +364,20 @@ unsigned grid_for(long long n) {
 
 hipError_t launch_emtm_push(const EmtmPush &a, hipStream_t st) {
   const long long n = (long long)a.nx * a.ny * a.nz;
-  hipLaunchKernelGGL(emtm_push, dim3(grid_for(n)), dim3(256), 0, st, a);
+  const size_t lds = sizeof(uint32_t) * (kWinCells >> win_lg(a.n_sub)) * kBlock +
+                     (a.aligned ? (2 * sizeof(double) + sizeof(int)) * (size_t)a.n_sub * kBlock : 0);
+  if (a.n_sub < 1 || a.n_sub > kMaxSub) return hipErrorInvalidValue;
+  if (a.aligned) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&emtm_push<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(emtm_push<true>, dim3(grid_for(n)), dim3(kBlock), lds, st, a);
+  } else {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&emtm_push<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(emtm_push<false>, dim3(grid_for(n)), dim3(kBlock), lds, st, a);
+  }
   return hipGetLastError();
 }
 

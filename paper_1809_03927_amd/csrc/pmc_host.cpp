@@ -2232,6 +2232,9 @@ int validate_accumulate(pmc_context *ctx, int32_t ref_phase, int32_t n_src, cons
   }
   if (n_sub < 1 || n_sub > 16) return fail(ctx, PMC_E_INVAL, "n_sub must be 1..16");
   if (n_histories == 0) return fail(ctx, PMC_E_INVAL, "n_histories must be >= 1");
+  const PhaseRec &ref = ctx->phases[ref_phase];
+  if (ref.nx >= (1 << 20) - 1 || ref.ny >= (1 << 20) - 1 || ref.nz >= (1 << 20) - 1)
+    return fail(ctx, PMC_E_INVAL, "reference grid needs fewer than 2^20 - 1 voxels per axis");
   return PMC_OK;
 }
 
@@ -2288,8 +2291,12 @@ int pmc_accumulate_device(pmc_context *ctx, int32_t ref_phase, const int64_t *re
         a.sp[k] = src.sp_mm[k];
         a.rorg[k] = ref.org_mm[k];
         a.rsp[k] = ref.sp_mm[k];
+        a.rinv[k] = 1.0 / ref.sp_mm[k];
       }
       a.n_sub = n_sub;
+      const pmc::DvfDev &g = dv.dev;
+      a.aligned = g.u[0] == 1.0 && g.u[1] == 0.0 && g.u[2] == 0.0 && g.v[0] == 0.0 && g.v[1] == 1.0 &&
+                  g.v[2] == 0.0;
       a.e_hi = e_hi;
       a.e_lo = e_lo;
       a.mass = mass;

@@ -172,7 +172,9 @@ struct EmtmPush {
   DvfDev dvf;                // source -> reference
   int32_t rnx, rny, rnz;
   double rorg[3], rsp[3];    // reference grid, mm
+  double rinv[3];            // 1 / rsp, rounded to nearest
   int32_t n_sub;
+  int32_t aligned;           // DVF row (1,0,0) and column (0,1,0): per-axis grid coordinates
   unsigned long long *e_hi, *e_lo, *mass;  // per reference voxel
 };
 
