@@ -49,8 +49,30 @@ VALU_PER_STEP = 448.0
 # WRITE_SIZE scaled by a 4 GiB copy calibration
 # (profiles/transport_core_thorax4d_counters.md).  Valid only for the sources
 # they were measured on (hash below) and that launch shape; otherwise null.
-PROFILED_TRAFFIC_BYTES = 180.0e9
-PROFILED_KERNEL_HASH = "2d52edc9a7a70231"
+PROFILED_TRAFFIC_BYTES = 180.4e9
+PROFILED_KERNEL_HASH = "710bdd01123ff18f"
+
+# Deformable accumulation (energy/mass transfer, Sec. 2.D.2): the per-phase
+# tallies of the 4D run accumulated onto one reference phase with n^3
+# subvoxels per voxel.  FP64 operations the plain definition spends on one
+# subvoxel whose centre lies inside the DVF grid: centre 9 (3 x add, multiply,
+# add), DVF grid coordinates 21 (3 subtractions, then per axis 3 multiplies,
+# 2 adds, 1 divide), cell fractions 3, trilinear interpolation of the three
+# translations 63 (7 lerps of 3 operations each) plus 3 adds, reference voxel
+# 6 (3 subtractions, 3 divides).  Floors and comparisons are not counted.
+ACC_REF_PHASE = 5
+ACC_N_SUB = 5
+ACC_OPS_PER_SUBVOXEL = 105
+# These are unfused FP64 operations: one per lane per clock, 256 CUs x 64
+# FP64 lanes x 2.4 GHz (the 78.6 TFLOP/s FP64 vector figure counts an FMA as
+# two operations).
+PEAK_FP64_OPS = 256 * 64 * 2.4e9
+# HBM-side bytes of one accumulation call (9 sources of the thorax 4D
+# workload onto phase 5, n_sub 5), FETCH_SIZE and WRITE_SIZE of emtm_push
+# scaled like the transport's (profiles/emtm_push_thorax4d_counters.md);
+# valid for the source it was measured on (hash of pmc_accumulate.hip).
+PROFILED_ACC_TRAFFIC_BYTES = 3.13e9
+PROFILED_ACC_HASH = "df93c254057989c0"
 
 
 def log(*a):
@@ -72,6 +94,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-atomic-probe", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-accumulation", action="store_true")
+    p.add_argument("--acc-cpu-seconds", type=float, default=10.0)
     p.add_argument("--latency-requests", type=int, default=200,
                    help="served-stream requests for the p50/p99 latency comparison (0 = skip)")
     p.add_argument("--latency-load", type=float, default=0.8)
@@ -224,6 +248,11 @@ def main():
         pmc.pmc_dose_device(eng.ctx, req_b, stream.cuda_stream, tptr, counters.data_ptr())
     _, spans_k = timed(transport_only, max(2, min(a.steps, 3)), 0)
     kern_ms = float(np.mean(spans_k))
+
+    accumulation = None
+    if not a.no_accumulation:
+        accumulation = accumulation_bench(eng, wl, tal_b, stream, timed, max(2, min(a.steps, 5)),
+                                          None if a.no_cpu_baseline else a.acc_cpu_seconds)
     shape_b = pmc.pmc_launch_shape(eng.ctx, req_b)
     kernel_name = ("transport_core<float>" if shape_b["tally_mode"] == pmc.PMC_TALLY_CORE
                    else "transport_persistent<float>")
@@ -316,17 +345,22 @@ def main():
         "latency": latency,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "accumulation": accumulation,
     }
     print(json.dumps(out))
 
 
-def kernel_hash():
+def source_hash(files):
     import hashlib
     h = hashlib.sha256()
-    for f in ("pmc_device.hpp", "pmc_kernels.hip", "pmc_host.cpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1809_03927_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def kernel_hash():
+    return source_hash(("pmc_device.hpp", "pmc_kernels.hip", "pmc_host.cpp"))
 
 
 def atomic_probe(torch, nvox, n=200_000_000):
@@ -344,6 +378,139 @@ def atomic_probe(torch, nvox, n=200_000_000):
     e1.record()
     torch.cuda.synchronize()
     return n / (e0.elapsed_time(e1) * 1e-3)
+
+
+def mapped_subvoxels(ph, dvf, n):
+    """Subvoxel centres of the phase's voxels with mass that lie inside the
+    grid box of an axis-aligned DVF (the subvoxels that are mapped)."""
+    import numpy as np
+    assert tuple(dvf.row) == (1.0, 0.0, 0.0) and tuple(dvf.col) == (0.0, 1.0, 0.0)
+    nz, ny, nx = ph.hu.shape
+    cnt = []
+    for axis, m in enumerate((nx, ny, nz)):
+        c = (np.arange(m)[:, None] + (np.arange(n)[None, :] + 0.5) / n) * ph.spacing_mm[axis]
+        g = (ph.origin_mm[axis] + c - dvf.start_mm[axis]) / dvf.spacing_mm[axis]
+        cnt.append(((g >= 0.0) & (g <= dvf.n[axis] - 1)).sum(axis=1).astype(np.float64))
+    hu = np.clip(ph.hu, -1024, 3071).astype(np.float64)
+    has_mass = np.interp(hu, np.asarray(ph.calib_hu, float), np.asarray(ph.calib_rho, float)) > 0
+    if ph.mask is not None:
+        has_mass &= ph.mask.astype(bool)
+    return float(np.einsum("zyx,x,y,z->", has_mass.astype(np.float64), cnt[0], cnt[1], cnt[2]))
+
+
+def accumulation_bench(eng, wl, tallies, stream, timed, steps, cpu_seconds):
+    """All other phases' tallies accumulated onto the reference phase by
+    energy/mass transfer (pmc_accumulate_device on the stream the events are
+    recorded on), with the FP64-operation roofline; then the oracle on a
+    z-slab of one source phase, timed, and the GPU's result for the same
+    slab checked against it."""
+    import numpy as np
+    import torch
+    from paper_1809_03927_amd import pmc
+    from paper_1809_03927_amd import workloads as W
+    ref = ACC_REF_PHASE
+    n = ACC_N_SUB
+    src = [p for p in range(len(wl.phases)) if p != ref]
+    t0 = time.time()
+    dvfs = {p: W.thorax_dvf(p, ref, n_phases=len(wl.phases)) for p in src}
+    for p in src:
+        pmc.pmc_load_dvf(eng.ctx, 100 + p, dvfs[p])
+    log(f"accumulation: {len(src)} DVFs {dvfs[src[0]].n} built and loaded in {time.time() - t0:.1f} s")
+    nv = wl.phases[ref].nvox
+    dose = torch.empty(nv, dtype=torch.float64, device="cuda")
+    mask = torch.empty(nv, dtype=torch.uint8, device="cuda")
+
+    def run():
+        pmc.pmc_accumulate_device(eng.ctx, ref, tallies[ref].data_ptr(), src, [100 + p for p in src],
+                                  [tallies[p].data_ptr() for p in src], n, wl.n_histories,
+                                  stream.cuda_stream, dose.data_ptr(), mask.data_ptr())
+    _, spans = timed(run, steps, 1)
+    ms = float(np.mean(spans))
+    mapped = sum(mapped_subvoxels(wl.phases[p], dvfs[p], n) for p in src)
+    achieved = ACC_OPS_PER_SUBVOXEL * mapped / (ms * 1e-3)
+    default_size = wl.phases[ref].hu.shape == (160, 256, 256) and len(wl.phases) == 10
+    log(f"accumulation: {ms:.2f} ms for {len(src)} source phases (n_sub {n}), "
+        f"{mapped / (ms * 1e-3) / 1e9:.1f} G subvoxels/s")
+    out = {
+        "workload": f"EMTM: phases {src} of the thorax4d run accumulated onto phase {ref}, n_sub {n}, "
+                    f"DVFs {dvfs[src[0]].n[0]}x{dvfs[src[0]].n[1]}x{dvfs[src[0]].n[2]} @2.5 mm",
+        "value": mapped / (ms * 1e-3), "unit": "mapped subvoxels/s", "ms_per_accumulation": ms,
+        "ms_per_source_phase": ms / len(src), "mapped_subvoxels": mapped, "dtype": "f64 mapping, int64 sums",
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
+                     "unit": "T FP64 op/s (unfused)", "frac": achieved / PEAK_FP64_OPS,
+                     "traffic": (PROFILED_ACC_TRAFFIC_BYTES if default_size and
+                                 source_hash(["pmc_accumulate.hip"]) == PROFILED_ACC_HASH else None),
+                     "traffic_unit": "bytes per accumulation call (HBM side)",
+                     "ops_per_subvoxel": ACC_OPS_PER_SUBVOXEL,
+                     "kernel": "emtm_push (with the reference dose, per-source fill and ratio, mask)"},
+        "cpu_baseline": None,
+    }
+    if cpu_seconds:
+        out["cpu_baseline"] = accumulation_cpu(eng, wl, tallies, dvfs, src[0], ref, n, cpu_seconds)
+    return out
+
+
+def accumulation_cpu(eng, wl, tallies, dvfs, sp, ref, n, target_s):
+    """The oracle's energy/mass push of a z-slab of source phase sp (through
+    the middle of the grid) onto the reference, timed; then the GPU's
+    accumulation of the same slab (as a phase of its own, with a zero
+    reference tally) against it: masks identical, doses within 1e-9."""
+    import dataclasses
+    import numpy as np
+    import torch
+    import oracle
+    import oracle.emtm as E
+    from paper_1809_03927_amd import pmc
+    ph, rph, dvf = wl.phases[sp], wl.phases[ref], dvfs[sp]
+    nz = ph.hu.shape[0]
+    tal = tallies[sp].cpu().numpy().reshape(ph.hu.shape)
+
+    def slab(k):
+        z0 = nz // 2 - k // 2
+        o = (ph.origin_mm[0], ph.origin_mm[1], ph.origin_mm[2] + z0 * ph.spacing_mm[2])
+        c = dataclasses.replace(ph, hu=np.ascontiguousarray(ph.hu[z0:z0 + k]), origin_mm=o,
+                                mask=None if ph.mask is None else np.ascontiguousarray(ph.mask[z0:z0 + k]))
+        return c, np.ascontiguousarray(tal[z0:z0 + k]).ravel()
+
+    def push(k):
+        c, t = slab(k)
+        rho = oracle.convert(c, np.zeros(c.hu.size, dtype=np.int64), 1)[1]
+        t1 = time.perf_counter()
+        sums = E.push(c, t, rho, rph, dvf, n)
+        return c, t, sums, time.perf_counter() - t1
+
+    _, _, _, dt1 = push(1)
+    k = int(min(nz, max(1, target_s / max(dt1, 1e-3))))
+    c, t, sums, dt = push(k)
+    mapped = mapped_subvoxels(c, dvf, n)
+    v_src = float(np.prod(np.asarray(c.spacing_mm) * 0.1))
+    want_mask = E.report_mask(rph, [dvf])
+    want = np.where(want_mask, E.dose_from_sums(sums, v_src, wl.n_histories), 0.0)
+    out = {"value": mapped / dt, "unit": "mapped subvoxels/s", "cores": 1, "kind": "oracle",
+           "sample": f"{k} z-slices of phase {sp} ({c.hu.size} voxels, {mapped:.3g} mapped subvoxels, "
+                     f"n_sub {n}) pushed onto phase {ref} by the numpy oracle in {dt:.1f} s"}
+    pmc.pmc_load_phase(eng.ctx, 200, c)
+    zero = torch.zeros(rph.nvox, dtype=torch.int64, device="cuda")
+    ts = torch.from_numpy(t).cuda()
+    dose = torch.empty(rph.nvox, dtype=torch.float64, device="cuda")
+    mask = torch.empty(rph.nvox, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    pmc.pmc_accumulate_device(eng.ctx, ref, zero.data_ptr(), [200], [100 + sp], [ts.data_ptr()], n,
+                              wl.n_histories, 0, dose.data_ptr(), mask.data_ptr())
+    torch.cuda.synchronize()
+    pmc.pmc_unload_phase(eng.ctx, 200)
+    got, gmask = dose.cpu().numpy(), mask.cpu().numpy().astype(bool)
+    sel = want > 0
+    rel = float(np.max(np.abs(got[sel] - want[sel]) / want[sel])) if sel.any() else 0.0
+    same_mask = bool(np.array_equal(gmask, want_mask))
+    out["accuracy"] = {"check": "GPU vs oracle on the sample: report masks identical, doses within 1e-9 "
+                                "relative (identical binning of every subvoxel)",
+                       "voxels": int(sel.sum()), "max_rel": rel,
+                       "bit_identical_frac": float(np.mean(got == want)),
+                       "passed": bool(same_mask and np.allclose(got, want, rtol=1e-9, atol=0) and sel.any())}
+    log(f"accumulation oracle: {k} slices in {dt:.1f} s; GPU check max rel {rel:.2e}, "
+        f"mask identical {same_mask}")
+    return out
 
 
 def cpu_sample_size(wl, target_s):
