@@ -9,11 +9,12 @@ documentation of pmc_accumulate (integer accumulators, points outside a DVF
 grid, the report mask).
 
 * DVF (App. B): grid point (i, j, k) sits at x0 = start + i dX U + j dY V +
-  k dZ W with W = U x V (Eq. (8)) and maps to x0 + delta (Eq. (7), identity
-  pre/post matrices).  A point r between grid points maps to the trilinear
-  interpolation of the mapped grid points around it, which is r plus the
-  trilinear interpolation of their translations.  Points outside the box of
-  grid-point centres are not mapped.
+  k dZ W with W = U x V (Eq. (8)) and maps to M_post (M_pre x0 + delta)
+  (Eq. (7); the rigid matrices are the identity between 4DCT phases, None
+  here).  A point r between grid points maps to M_post (M_pre r + delta(r)),
+  delta(r) the trilinear interpolation of the translations of the grid points
+  around it (with identity matrices: r plus that interpolation).  Points
+  outside the box of grid-point centres are not mapped.
 * EMTM (Eqs. (4)-(6)): every voxel j of a source phase is split into n^3
   subvoxels of volume v = V/n^3; subvoxel k carries mass M = rho_j v and
   energy E = M D_j, which for the Monte Carlo dose D_j = E_j / (rho_j V) is
@@ -45,6 +46,35 @@ def dvf_axes(dvf):
     return u, v, w
 
 
+def affine(m, pts: np.ndarray) -> np.ndarray:
+    """A 4x4 rigid matrix applied to points (..., 3): output axis a is
+    m[a,0] x + m[a,1] y + m[a,2] z + m[a,3], summed in that order."""
+    m = np.asarray(m, dtype=np.float64)
+    out = np.empty_like(pts)
+    for a in range(3):
+        out[..., a] = m[a, 0] * pts[..., 0] + m[a, 1] * pts[..., 1] + m[a, 2] * pts[..., 2] + m[a, 3]
+    return out
+
+
+def dvf_points(dvf):
+    """Eqs. (8) and (7) at every grid point: x0 (the matrix product written
+    out per axis: (U_a dX) i + (V_a dY) j + (W_a dZ) k + start_a) and
+    r_f = M_post (M_pre x0 + delta); both (n[2], n[1], n[0], 3)."""
+    u, v, w = dvf_axes(dvf)
+    n = dvf.n
+    k, j, i = np.meshgrid(np.arange(n[2], dtype=np.float64), np.arange(n[1], dtype=np.float64),
+                          np.arange(n[0], dtype=np.float64), indexing="ij")
+    x0 = np.empty(k.shape + (3,))
+    for a in range(3):
+        x0[..., a] = ((u[a] * dvf.spacing_mm[0]) * i + (v[a] * dvf.spacing_mm[1]) * j
+                      + (w[a] * dvf.spacing_mm[2]) * k + dvf.start_mm[a])
+    m = x0 if dvf.pre is None else affine(dvf.pre, x0)
+    rf = m + np.asarray(dvf.delta_mm, dtype=np.float64)
+    if dvf.post is not None:
+        rf = affine(dvf.post, rf)
+    return x0, rf
+
+
 def dvf_grid_coords(dvf, pts: np.ndarray) -> np.ndarray:
     """Grid coordinates (i, j, k) of points (mm): projections of r - start
     on U, V, W divided by the grid spacings (the inverse of Eq. (8))."""
@@ -68,7 +98,7 @@ def dvf_inside(dvf, pts: np.ndarray) -> np.ndarray:
 def dvf_map(dvf, pts: np.ndarray) -> np.ndarray:
     """T(r) of Eq. (1) for points pts (..., 3) in mm; NaN where r is outside
     the grid.  Trilinear interpolation of the translations, x first, then y,
-    then z."""
+    then z; then the rigid matrices of Eq. (7), if any."""
     g = dvf_grid_coords(dvf, pts)
     inside = dvf_inside(dvf, pts)
     out = np.full(pts.shape, np.nan)
@@ -95,7 +125,11 @@ def dvf_map(dvf, pts: np.ndarray) -> np.ndarray:
     c11 = corner(0, 1, 1) + fx * (corner(1, 1, 1) - corner(0, 1, 1))
     c0 = c00 + fy * (c10 - c00)
     c1 = c01 + fy * (c11 - c01)
-    out[inside] = p + (c0 + fz * (c1 - c0))
+    base = p if getattr(dvf, "pre", None) is None else affine(dvf.pre, p)
+    q = base + (c0 + fz * (c1 - c0))
+    if getattr(dvf, "post", None) is not None:
+        q = affine(dvf.post, q)
+    out[inside] = q
     return out
 
 

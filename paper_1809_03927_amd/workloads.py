@@ -191,6 +191,10 @@ class Dvf:
     row: Tuple[float, float, float]
     col: Tuple[float, float, float]
     delta_mm: np.ndarray  # float64 (n[2], n[1], n[0], 3), i fastest
+    # rigid 4x4 matrices applied before and after the translation (Eq. (7));
+    # None is the identity (registrations between 4DCT phases)
+    pre: Optional[np.ndarray] = None
+    post: Optional[np.ndarray] = None
 
 
 def thorax_dvf(phase: int, ref_phase: int = 0, n_phases=10, period=4.0, spacing_mm=(2.5, 2.5, 2.5),
