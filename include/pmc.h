@@ -380,23 +380,37 @@ int pmc_influence_free(pmc_context *ctx);
 
 /* A deformation vector field as a DICOM deformable registration stores it
  * (App. B, Eqs. (7)-(8)): grid point (i, j, k), 0 <= i < n[0] ..., sits at
- * start_mm + i spacing_mm[0] row + j spacing_mm[1] col + k spacing_mm[2]
- * (row x col) and maps to that position plus its translation (the pre/post
- * rigid matrices are the identity between phases of one 4DCT).  A point
- * between grid points maps to the trilinear interpolation of the mapped
- * points around it; points outside the box of grid points are not mapped.
- * For accumulation the field maps a source phase onto the reference phase. */
+ * x0 = start_mm + i spacing_mm[0] row + j spacing_mm[1] col + k spacing_mm[2]
+ * (row x col) (Eq. (8)) and maps to M_post (M_pre x0 + delta) (Eq. (7); the
+ * rigid matrices are the identity between phases of one 4DCT, pass NULL).
+ * A point r between grid points maps to M_post (M_pre r + delta(r)), delta(r)
+ * the trilinear interpolation (x, then y, then z) of the translations of the
+ * grid points around it, in FP64; points outside the box of grid points are
+ * not mapped.  For pmc_accumulate the field maps a source phase onto the
+ * reference phase; for pmc_accumulate_dim the reference phase onto a source. */
 typedef struct {
   int32_t n[3];            /* grid points along row, column, depth; each >= 2 */
   double start_mm[3];      /* position of grid point (0, 0, 0), scanner frame */
   double spacing_mm[3];    /* > 0 */
   double row[3], col[3];   /* unit, orthogonal direction cosines (within 1e-6) */
   const double *delta_mm;  /* translations (x, y, z) per grid point, i fastest, then j, k */
+  const double *pre;       /* nullable: M_pre, 4x4 row-major rigid matrix (rotation part
+                              orthonormal within 1e-6, last row 0 0 0 1); NULL = identity */
+  const double *post;      /* nullable: M_post, same form */
 } pmc_dvf;
 
 /* Copy a DVF to the device as `dvf` (0..1023), replacing one of that id. */
 int pmc_load_dvf(pmc_context *ctx, int32_t dvf, const pmc_dvf *d);
 int pmc_unload_dvf(pmc_context *ctx, int32_t dvf);
+
+/* The full field of a loaded DVF (App. B): Eq. (8) and Eq. (7) evaluated on
+ * the device, one thread per grid point.  x0_out receives the grid points'
+ * positions, rf_out the mapped positions M_post (M_pre x0 + delta); 3 doubles
+ * (x, y, z) per point in grid order (i fastest), mm; either may be NULL.
+ * Eq. (8) is the matrix product written out per axis:
+ *   x0_a = (row_a dX) i + (col_a dY) j + (dep_a dZ) k + start_a.
+ * Host buffers; blocks until done. */
+int pmc_dvf_points(pmc_context *ctx, int32_t dvf, double *x0_out, double *rf_out);
 
 /* Accumulated dose on the reference phase's grid by energy/mass transfer
  * (Sec. 2.D.2, Eqs. (2), (4)-(6)), Gy per history of a run of n_histories:
@@ -423,6 +437,30 @@ int pmc_accumulate_device(pmc_context *ctx, int32_t ref_phase, const int64_t *re
                           const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
                           int32_t n_sub, uint64_t n_histories, void *stream, double *dev_dose,
                           uint8_t *dev_mask);
+
+/* Accumulated dose on the reference phase's grid by dose interpolation
+ * (Sec. 2.D.2, Eqs. (2), (3)), Gy per history: D_i = D_i^R + sum over
+ * sources (list order) of D_i^S with
+ *   D_i^S = (1 / n_sub^3) sum over the n_sub^3 subvoxel centres r_k of
+ *           reference voxel i of Dt^S(T^{R->S}(r_k)),
+ * where each source's DVF maps the reference phase onto that source (the
+ * opposite direction to pmc_accumulate), subvoxel centres are at origin +
+ * (i + (s + 1/2) / n_sub) spacing per axis, and Dt^S is the source phase's
+ * dose (its tally converted as pmc_convert_device) interpolated trilinearly
+ * between its voxel centres (x, then y, then z) at the position clamped to
+ * the box of voxel centres, as a 3D texture with clamp-to-edge addressing
+ * does.  A centre outside the DVF grid contributes 0.  The sum runs over the
+ * subvoxels with x outermost, then y, then z, in FP64.  Reported (else 0)
+ * where the reference voxel centre lies in the grid box of every DVF; other
+ * arguments, buffers and streams as pmc_accumulate / pmc_accumulate_device
+ * (the two share the context's scratch memory). */
+int pmc_accumulate_dim(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
+                       const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
+                       int32_t n_sub, uint64_t n_histories, double *dose_out, uint8_t *mask_out);
+int pmc_accumulate_dim_device(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
+                              const int32_t *src_phases, const int32_t *src_dvfs,
+                              const int64_t *const *src_tallies, int32_t n_sub, uint64_t n_histories,
+                              void *stream, double *dev_dose, uint8_t *dev_mask);
 
 #ifdef __cplusplus
 }

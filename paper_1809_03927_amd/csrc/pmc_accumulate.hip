@@ -14,6 +14,11 @@
 //               Gy per history, added in source order (Eq. (2)).
 //  emtm_mask    keeps the dose where the reference voxel centre lies in the
 //               grid box of every DVF.
+//  dim_pull     dose interpolation (Eq. (3)): one thread per reference voxel
+//               maps its n^3 subvoxel centres to the source phase and adds
+//               the average of the source dose sampled there.
+//  dvf_points   the full field of App. B (Eqs. (8), (7)), one thread per grid
+//               point.
 //
 // Every floating-point decision (which reference voxel a centre lands in)
 // equals that of a plain FP64 evaluation of the formulas in their written
@@ -45,7 +50,8 @@ constexpr int kWinCells = kWin * kWin * kWin;
 // has at most 255 subvoxels (n <= 6), else two 16-bit counts (n^3 <= 4096).
 __host__ __device__ __forceinline__ int win_lg(int n) { return n * n * n <= 255 ? 2 : 1; }
 
-__device__ __forceinline__ bool dvf_coords(const DvfDev &d, double px, double py, double pz, double g[3]) {
+template <class G>
+__device__ __forceinline__ bool dvf_coords(const G &d, double px, double py, double pz, double g[3]) {
   const double rx = px - d.start[0], ry = py - d.start[1], rz = pz - d.start[2];
   const double ax[3][3] = {{d.u[0], d.u[1], d.u[2]}, {d.v[0], d.v[1], d.v[2]}, {d.w[0], d.w[1], d.w[2]}};
   bool inside = true;
@@ -57,8 +63,16 @@ __device__ __forceinline__ bool dvf_coords(const DvfDev &d, double px, double py
   return inside;
 }
 
-// T(r) of Eq. (1): r plus the trilinear interpolation (x, then y, then z) of
-// the translations of the 8 grid points around r.  False outside the grid.
+// A rigid 4x4 matrix (rows 0..2) applied to a point: m[a][0] x + m[a][1] y +
+// m[a][2] z + m[a][3], summed in that order.
+__device__ __forceinline__ void rigid(const double m[12], const double p[3], double out[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[a] = m[4 * a] * p[0] + m[4 * a + 1] * p[1] + m[4 * a + 2] * p[2] + m[4 * a + 3];
+}
+
+// T(r) of Eq. (1): M_post (M_pre r + the trilinear interpolation (x, then y,
+// then z) of the translations of the 8 grid points around r); without the
+// rigid matrices r plus that interpolation.  False outside the grid.
 __device__ __forceinline__ bool dvf_map(const DvfDev &d, double px, double py, double pz, double q[3]) {
   double g[3];
   if (!dvf_coords(d, px, py, pz, g)) return false;
@@ -74,6 +88,8 @@ __device__ __forceinline__ bool dvf_map(const DvfDev &d, double px, double py, d
   const long long sx = 3, sy = 3LL * d.n[0], sz = 3LL * d.n[0] * d.n[1];
   const double *c = d.delta + b[0] * sx + b[1] * sy + b[2] * sz;
   const double p[3] = {px, py, pz};
+  double base[3] = {px, py, pz};
+  if (d.has_pre) rigid(d.pre, p, base);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double d000 = c[k], d100 = c[sx + k], d010 = c[sy + k], d110 = c[sx + sy + k];
@@ -84,7 +100,11 @@ __device__ __forceinline__ bool dvf_map(const DvfDev &d, double px, double py, d
     const double c11 = d011 + f[0] * (d111 - d011);
     const double c0 = c00 + f[1] * (c10 - c00);
     const double c1 = c01 + f[1] * (c11 - c01);
-    q[k] = p[k] + (c0 + f[2] * (c1 - c0));
+    q[k] = base[k] + (c0 + f[2] * (c1 - c0));
+  }
+  if (d.has_post) {
+    const double r[3] = {q[0], q[1], q[2]};
+    rigid(d.post, r, q);
   }
   return true;
 }
@@ -196,6 +216,105 @@ __device__ __forceinline__ int cell(double g, int n, double &f) {
   return i;
 }
 
+// The n^3 subvoxel centres of voxel (ix, iy, iz) of a grid (origin org,
+// spacing sp, mm) mapped by the DVF g: visit(qx, qy, qz) for every centre
+// inside the DVF grid, x outermost, then y, then z.  ALIGNED (identity
+// directions, no rigid matrices): the grid coordinate along an axis is exactly
+// (coordinate - start) / spacing, so z is tabulated per voxel in this thread's
+// LDS table (zf: fraction, zp: coordinate, zb: cell or -1 outside; n entries,
+// stride kBlock) and the x- then y-interpolated translations of a DVF cell are
+// kept while the centres stay in it.
+template <bool ALIGNED, class Visit>
+__device__ __forceinline__ void map_subvoxels(const DvfDev &g, const double *org, const double *sp, int n, int ix,
+                                              int iy, int iz, const double *off, double *zf, double *zp, int *zb,
+                                              int tid, Visit &&visit) {
+  if (ALIGNED) {
+    // z: coordinate, DVF cell and fraction of every subvoxel plane (cell -1
+    // outside the grid)
+    for (int sc = 0; sc < n; ++sc) {
+      const double pz = org[2] + ((double)iz + off[sc]) * sp[2];
+      const double gz = (pz - g.start[2]) / g.sp[2];
+      double f = 0.0;
+      int b = -1;
+      if (gz >= 0.0 && gz <= (double)(g.n[2] - 1)) b = cell(gz, g.n[2], f);
+      zf[sc * kBlock + tid] = f;
+      zp[sc * kBlock + tid] = pz;
+      zb[sc * kBlock + tid] = b;
+    }
+    const long long sy = 3LL * g.n[0], sz = 3LL * g.n[0] * g.n[1];
+    for (int sa = 0; sa < n; ++sa) {
+      const double px = org[0] + ((double)ix + off[sa]) * sp[0];
+      const double gx = (px - g.start[0]) / g.sp[0];
+      if (!(gx >= 0.0 && gx <= (double)(g.n[0] - 1))) continue;
+      double f0;
+      const int b0 = cell(gx, g.n[0], f0);
+      for (int sb = 0; sb < n; ++sb) {
+        const double py = org[1] + ((double)iy + off[sb]) * sp[1];
+        const double gy = (py - g.start[1]) / g.sp[1];
+        if (!(gy >= 0.0 && gy <= (double)(g.n[1] - 1))) continue;
+        double f1;
+        const int b1 = cell(gy, g.n[1], f1);
+        const double *col = g.delta + 3LL * b0 + sy * b1;
+        // c0, c1: translations interpolated in x then y on the lower and
+        // upper z plane of DVF cell layer cb; dc = c1 - c0
+        int cb = -1;
+        double c0[3], c1[3], dc[3];
+        for (int sc = 0; sc < n; ++sc) {
+          const int b2 = zb[sc * kBlock + tid];
+          if (b2 < 0) continue;
+          const double f2 = zf[sc * kBlock + tid];
+          if (b2 != cb) {
+            // z grows with sc, so the next layer is usually cb + 1, whose
+            // lower plane is cb's upper plane: the same corners and
+            // operations give the same c0
+            const double *c = col + sz * b2;
+            if (cb >= 0 && b2 == cb + 1) {
+#pragma unroll
+              for (int k = 0; k < 3; ++k) c0[k] = c1[k];
+            } else {
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                const double d000 = c[k], d100 = c[3 + k], d010 = c[sy + k], d110 = c[sy + 3 + k];
+                const double c00 = d000 + f0 * (d100 - d000);
+                const double c10 = d010 + f0 * (d110 - d010);
+                c0[k] = c00 + f1 * (c10 - c00);
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              const double d001 = c[sz + k], d101 = c[sz + 3 + k], d011 = c[sz + sy + k],
+                           d111 = c[sz + sy + 3 + k];
+              const double c01 = d001 + f0 * (d101 - d001);
+              const double c11 = d011 + f0 * (d111 - d011);
+              c1[k] = c01 + f1 * (c11 - c01);
+              dc[k] = c1[k] - c0[k];
+            }
+            cb = b2;
+          }
+          const double pz = zp[sc * kBlock + tid];
+          const double qx = px + (c0[0] + f2 * dc[0]);
+          const double qy = py + (c0[1] + f2 * dc[1]);
+          const double qz = pz + (c0[2] + f2 * dc[2]);
+          visit(qx, qy, qz);
+        }
+      }
+    }
+  } else {
+    for (int sa = 0; sa < n; ++sa) {
+      const double px = org[0] + ((double)ix + off[sa]) * sp[0];
+      for (int sb = 0; sb < n; ++sb) {
+        const double py = org[1] + ((double)iy + off[sb]) * sp[1];
+        for (int sc = 0; sc < n; ++sc) {
+          const double pz = org[2] + ((double)iz + off[sc]) * sp[2];
+          double q[3];
+          if (!dvf_map(g, px, py, pz, q)) continue;
+          visit(q[0], q[1], q[2]);
+        }
+      }
+    }
+  }
+}
+
 template <bool ALIGNED>
 __global__ void __launch_bounds__(kBlock) emtm_push(EmtmPush a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -234,94 +353,103 @@ __global__ void __launch_bounds__(kBlock) emtm_push(EmtmPush a) {
     const Deposit d = {t >> 32, t & 0xFFFFFFFFull, (unsigned long long)mq};
     const unsigned row = j / (unsigned)a.nx;
     const int ix = (int)(j - row * (unsigned)a.nx), iy = (int)(row % (unsigned)a.ny), iz = (int)(row / (unsigned)a.ny);
-    if (ALIGNED) {
-      // z: coordinate, DVF cell and fraction of every subvoxel plane (cell -1
-      // outside the grid)
-      for (int sc = 0; sc < n; ++sc) {
-        const double pz = a.org[2] + ((double)iz + off[sc]) * a.sp[2];
-        const double gz = (pz - g.start[2]) / g.sp[2];
-        double f = 0.0;
-        int b = -1;
-        if (gz >= 0.0 && gz <= (double)(g.n[2] - 1)) b = cell(gz, g.n[2], f);
-        zf[sc * kBlock + tid] = f;
-        zp[sc * kBlock + tid] = pz;
-        zb[sc * kBlock + tid] = b;
-      }
-      const long long sy = 3LL * g.n[0], sz = 3LL * g.n[0] * g.n[1];
-      for (int sa = 0; sa < n; ++sa) {
-        const double px = a.org[0] + ((double)ix + off[sa]) * a.sp[0];
-        const double gx = (px - g.start[0]) / g.sp[0];
-        if (!(gx >= 0.0 && gx <= (double)(g.n[0] - 1))) continue;
-        double f0;
-        const int b0 = cell(gx, g.n[0], f0);
-        for (int sb = 0; sb < n; ++sb) {
-          const double py = a.org[1] + ((double)iy + off[sb]) * a.sp[1];
-          const double gy = (py - g.start[1]) / g.sp[1];
-          if (!(gy >= 0.0 && gy <= (double)(g.n[1] - 1))) continue;
-          double f1;
-          const int b1 = cell(gy, g.n[1], f1);
-          const double *col = g.delta + 3LL * b0 + sy * b1;
-          // c0, c1: translations interpolated in x then y on the lower and
-          // upper z plane of DVF cell layer cb; dc = c1 - c0
-          int cb = -1;
-          double c0[3], c1[3], dc[3];
-          for (int sc = 0; sc < n; ++sc) {
-            const int b2 = zb[sc * kBlock + tid];
-            if (b2 < 0) continue;
-            const double f2 = zf[sc * kBlock + tid];
-            if (b2 != cb) {
-              // z grows with sc, so the next layer is usually cb + 1, whose
-              // lower plane is cb's upper plane: the same corners and
-              // operations give the same c0
-              const double *c = col + sz * b2;
-              if (cb >= 0 && b2 == cb + 1) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) c0[k] = c1[k];
-              } else {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                  const double d000 = c[k], d100 = c[3 + k], d010 = c[sy + k], d110 = c[sy + 3 + k];
-                  const double c00 = d000 + f0 * (d100 - d000);
-                  const double c10 = d010 + f0 * (d110 - d010);
-                  c0[k] = c00 + f1 * (c10 - c00);
-                }
-              }
-#pragma unroll
-              for (int k = 0; k < 3; ++k) {
-                const double d001 = c[sz + k], d101 = c[sz + 3 + k], d011 = c[sz + sy + k],
-                             d111 = c[sz + sy + 3 + k];
-                const double c01 = d001 + f0 * (d101 - d001);
-                const double c11 = d011 + f0 * (d111 - d011);
-                c1[k] = c01 + f1 * (c11 - c01);
-                dc[k] = c1[k] - c0[k];
-              }
-              cb = b2;
-            }
-            const double pz = zp[sc * kBlock + tid];
-            const double qx = px + (c0[0] + f2 * dc[0]);
-            const double qy = py + (c0[1] + f2 * dc[1]);
-            const double qz = pz + (c0[2] + f2 * dc[2]);
-            int tv[3];
-            if (ref_voxel(a, qx, qy, qz, tv)) count(a, win, d, tv);
-          }
-        }
-      }
-    } else {
-      for (int sa = 0; sa < n; ++sa) {
-        const double px = a.org[0] + ((double)ix + off[sa]) * a.sp[0];
-        for (int sb = 0; sb < n; ++sb) {
-          const double py = a.org[1] + ((double)iy + off[sb]) * a.sp[1];
-          for (int sc = 0; sc < n; ++sc) {
-            const double pz = a.org[2] + ((double)iz + off[sc]) * a.sp[2];
-            double q[3];
-            if (!dvf_map(g, px, py, pz, q)) continue;
-            int tv[3];
-            if (ref_voxel(a, q[0], q[1], q[2], tv)) count(a, win, d, tv);
-          }
-        }
-      }
-    }
+    map_subvoxels<ALIGNED>(g, a.org, a.sp, n, ix, iy, iz, off, zf, zp, zb, tid,
+                           [&](double qx, double qy, double qz) {
+                             int tv[3];
+                             if (ref_voxel(a, qx, qy, qz, tv)) count(a, win, d, tv);
+                           });
     flush(a, win, d);
+  }
+}
+
+// Source dose at q (mm): trilinear interpolation between voxel centres
+// (x, then y, then z), the voxel-centre coordinate (q - origin) / spacing -
+// 1/2 clamped to [0, n - 1] per axis; on the last plane both corners are the
+// last voxel.
+__device__ __forceinline__ double dose_sample(const DimPull &a, double qx, double qy, double qz) {
+  const double q[3] = {qx, qy, qz};
+  const int dims[3] = {a.snx, a.sny, a.snz};
+  int lo[3], hi[3];
+  double f[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double u = (q[k] - a.sorg[k]) / a.ssp[k] - 0.5;
+    u = fmin(fmax(u, 0.0), (double)(dims[k] - 1));
+    const int i = (int)floor(u);
+    lo[k] = i;
+    hi[k] = i + 1 < dims[k] ? i + 1 : dims[k] - 1;
+    f[k] = u - (double)i;
+  }
+  const long long nx = a.snx, nxy = (long long)a.snx * a.sny;
+  const double *d = a.sdose;
+  const long long z0 = lo[2] * nxy, z1 = hi[2] * nxy, y0 = lo[1] * nx, y1 = hi[1] * nx;
+  const double d000 = d[z0 + y0 + lo[0]], d100 = d[z0 + y0 + hi[0]];
+  const double d010 = d[z0 + y1 + lo[0]], d110 = d[z0 + y1 + hi[0]];
+  const double d001 = d[z1 + y0 + lo[0]], d101 = d[z1 + y0 + hi[0]];
+  const double d011 = d[z1 + y1 + lo[0]], d111 = d[z1 + y1 + hi[0]];
+  const double c00 = d000 + f[0] * (d100 - d000);
+  const double c10 = d010 + f[0] * (d110 - d010);
+  const double c01 = d001 + f[0] * (d101 - d001);
+  const double c11 = d011 + f[0] * (d111 - d011);
+  const double c0 = c00 + f[1] * (c10 - c00);
+  const double c1 = c01 + f[1] * (c11 - c01);
+  return c0 + f[2] * (c1 - c0);
+}
+
+template <bool ALIGNED>
+__global__ void __launch_bounds__(kBlock) dim_pull(DimPull a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double off[kMaxSub];
+  const int n = a.n_sub;
+  const int tid = threadIdx.x;
+  double *zf = reinterpret_cast<double *>(smem);
+  double *zp = zf + (size_t)n * kBlock;
+  int *zb = reinterpret_cast<int *>(zp + (size_t)n * kBlock);
+  if (tid < n) off[tid] = ((double)tid + 0.5) / (double)n;
+  __syncthreads();
+  const double count = (double)(n * n * n);
+  const unsigned nvox = (unsigned)a.nx * (unsigned)a.ny * (unsigned)a.nz;
+  const unsigned stride = gridDim.x * kBlock;
+  for (unsigned j = blockIdx.x * kBlock + tid; j < nvox; j += stride) {
+    const unsigned row = j / (unsigned)a.nx;
+    const int ix = (int)(j - row * (unsigned)a.nx), iy = (int)(row % (unsigned)a.ny), iz = (int)(row / (unsigned)a.ny);
+    // Eq. (3): the subvoxel samples summed in order (a centre outside the DVF
+    // grid adds nothing), then divided by n^3
+    double acc = 0.0;
+    map_subvoxels<ALIGNED>(a.dvf, a.org, a.sp, n, ix, iy, iz, off, zf, zp, zb, tid,
+                           [&](double qx, double qy, double qz) { acc = acc + dose_sample(a, qx, qy, qz); });
+    a.dose[j] = a.dose[j] + acc / count;
+  }
+}
+
+__global__ void __launch_bounds__(256) dvf_points_kernel(DvfDev d, double *x0, double *rf) {
+  const long long np = (long long)d.n[0] * d.n[1] * d.n[2];
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+    const double i = (double)(p % d.n[0]), j = (double)((p / d.n[0]) % d.n[1]),
+                 k = (double)(p / ((long long)d.n[0] * d.n[1]));
+    double x[3], m[3], r[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      x[a] = (d.u[a] * d.sp[0]) * i + (d.v[a] * d.sp[1]) * j + (d.w[a] * d.sp[2]) * k + d.start[a];
+    m[0] = x[0];
+    m[1] = x[1];
+    m[2] = x[2];
+    if (d.has_pre) rigid(d.pre, x, m);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r[a] = m[a] + d.delta[3 * p + a];
+    if (d.has_post) {
+      const double t[3] = {r[0], r[1], r[2]};
+      rigid(d.post, t, r);
+    }
+    if (x0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) x0[3 * p + a] = x[a];
+    }
+    if (rf) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) rf[3 * p + a] = r[a];
+    }
   }
 }
 
@@ -378,6 +506,27 @@ hipError_t launch_emtm_push(const EmtmPush &a, hipStream_t st) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(emtm_push<false>, dim3(grid_for(n)), dim3(kBlock), lds, st, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_dim_pull(const DimPull &a, hipStream_t st) {
+  const long long n = (long long)a.nx * a.ny * a.nz;
+  if (a.n_sub < 1 || a.n_sub > kMaxSub) return hipErrorInvalidValue;
+  const size_t lds = a.aligned ? (2 * sizeof(double) + sizeof(int)) * (size_t)a.n_sub * kBlock : 0;
+  if (a.aligned) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&dim_pull<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(dim_pull<true>, dim3(grid_for(n)), dim3(kBlock), lds, st, a);
+  } else {
+    hipLaunchKernelGGL(dim_pull<false>, dim3(grid_for(n)), dim3(kBlock), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dvf_points(const DvfDev &d, double *x0, double *rf, hipStream_t st) {
+  const long long n = (long long)d.n[0] * d.n[1] * d.n[2];
+  hipLaunchKernelGGL(dvf_points_kernel, dim3(grid_for(n)), dim3(256), 0, st, d, x0, rf);
   return hipGetLastError();
 }
 

@@ -2164,6 +2164,28 @@ int pmc_load_dvf(pmc_context *ctx, int32_t dvf, const pmc_dvf *d) {
   const double dot = d->row[0] * d->col[0] + d->row[1] * d->col[1] + d->row[2] * d->col[2];
   if (std::fabs(nr - 1.0) > 1e-6 || std::fabs(nc - 1.0) > 1e-6 || std::fabs(dot) > 1e-6)
     return fail(ctx, PMC_E_INVAL, "DVF row and column directions must be orthonormal");
+  // rigid 4x4 matrices of Eq. (7): rotation part orthonormal, last row 0 0 0 1
+  auto check_rigid = [&](const double *m, const char *name) -> int {
+    for (int i = 0; i < 16; ++i)
+      if (!std::isfinite(m[i])) return fail(ctx, PMC_E_INVAL, "%s has a non-finite entry", name);
+    if (m[12] != 0.0 || m[13] != 0.0 || m[14] != 0.0 || m[15] != 1.0)
+      return fail(ctx, PMC_E_INVAL, "%s must have the last row 0 0 0 1", name);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        const double dot = m[4 * r] * m[4 * c] + m[4 * r + 1] * m[4 * c + 1] + m[4 * r + 2] * m[4 * c + 2];
+        if (std::fabs(dot - (r == c ? 1.0 : 0.0)) > 1e-6)
+          return fail(ctx, PMC_E_INVAL, "%s must be rigid (orthonormal rotation part)", name);
+      }
+    return PMC_OK;
+  };
+  if (d->pre) {
+    int rc = check_rigid(d->pre, "M_pre");
+    if (rc) return rc;
+  }
+  if (d->post) {
+    int rc = check_rigid(d->post, "M_post");
+    if (rc) return rc;
+  }
   const long long pts = (long long)d->n[0] * d->n[1] * d->n[2];
   if (pts > (1LL << 31)) return fail(ctx, PMC_E_INVAL, "DVF grid has more than 2^31 points");
   for (long long i = 0; i < 3 * pts; ++i)
@@ -2181,6 +2203,12 @@ int pmc_load_dvf(pmc_context *ctx, int32_t dvf, const pmc_dvf *d) {
   g.w[0] = g.u[1] * g.v[2] - g.u[2] * g.v[1];
   g.w[1] = g.u[2] * g.v[0] - g.u[0] * g.v[2];
   g.w[2] = g.u[0] * g.v[1] - g.u[1] * g.v[0];
+  g.has_pre = d->pre != nullptr;
+  g.has_post = d->post != nullptr;
+  for (int i = 0; i < 12; ++i) {
+    g.pre[i] = d->pre ? d->pre[i] : 0.0;
+    g.post[i] = d->post ? d->post[i] : 0.0;
+  }
   rec.bytes = sizeof(double) * 3 * (size_t)pts;
   if (ctx->has_device) {
     HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
@@ -2216,6 +2244,35 @@ int pmc_unload_dvf(pmc_context *ctx, int32_t dvf) {
   return PMC_OK;
 }
 
+int pmc_dvf_points(pmc_context *ctx, int32_t dvf, double *x0_out, double *rf_out) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  auto it = ctx->dvfs.find(dvf);
+  if (it == ctx->dvfs.end()) return fail(ctx, PMC_E_STATE, "dvf %d is not loaded", dvf);
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  if (!x0_out && !rf_out) return PMC_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  const pmc::DvfDev &g = it->second.dev;
+  const size_t bytes = sizeof(double) * 3 * (size_t)g.n[0] * g.n[1] * g.n[2];
+  void *d_x0 = nullptr, *d_rf = nullptr;
+  size_t c_x0 = 0, c_rf = 0;
+  auto cleanup = [&](int code) {
+    (void)hipStreamSynchronize(ctx->stream);
+    if (d_x0) pool_put(ctx, d_x0, c_x0);
+    if (d_rf) pool_put(ctx, d_rf, c_rf);
+    return code;
+  };
+  int rc = x0_out ? pool_get(ctx, bytes, &d_x0, &c_x0, "DVF points") : PMC_OK;
+  if (!rc && rf_out) rc = pool_get(ctx, bytes, &d_rf, &c_rf, "DVF points");
+  if (rc) return cleanup(rc);
+  hipError_t e = pmc::launch_dvf_points(g, static_cast<double *>(d_x0), static_cast<double *>(d_rf), ctx->stream);
+  if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "dvf_points launch"));
+  if (x0_out) e = copy_sync(ctx, x0_out, d_x0, bytes, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && rf_out) e = copy_sync(ctx, rf_out, d_rf, bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "download DVF points"));
+  return cleanup(PMC_OK);
+}
+
 namespace {
 
 int validate_accumulate(pmc_context *ctx, int32_t ref_phase, int32_t n_src, const int32_t *src_phases,
@@ -2240,10 +2297,32 @@ int validate_accumulate(pmc_context *ctx, int32_t ref_phase, int32_t n_src, cons
 
 }  // namespace
 
-int pmc_accumulate_device(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
-                          const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
-                          int32_t n_sub, uint64_t n_histories, void *stream, double *dev_dose,
-                          uint8_t *dev_mask) {
+namespace {
+
+enum AccMethod { kEmtm = 0, kDim = 1 };
+
+bool aligned_dvf(const pmc::DvfDev &g) {
+  return g.u[0] == 1.0 && g.u[1] == 0.0 && g.u[2] == 0.0 && g.v[0] == 0.0 && g.v[1] == 1.0 && g.v[2] == 0.0 &&
+         !g.has_pre && !g.has_post;
+}
+
+pmc::DvfBox box_of(const pmc::DvfDev &g) {
+  pmc::DvfBox b = {};
+  for (int k = 0; k < 3; ++k) {
+    b.n[k] = g.n[k];
+    b.start[k] = g.start[k];
+    b.sp[k] = g.sp[k];
+    b.u[k] = g.u[k];
+    b.v[k] = g.v[k];
+    b.w[k] = g.w[k];
+  }
+  return b;
+}
+
+int accumulate_device(pmc_context *ctx, AccMethod method, int32_t ref_phase, const int64_t *ref_tally,
+                      int32_t n_src, const int32_t *src_phases, const int32_t *src_dvfs,
+                      const int64_t *const *src_tallies, int32_t n_sub, uint64_t n_histories, void *stream,
+                      double *dev_dose, uint8_t *dev_mask) {
   if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
   ctx->err.clear();
   int rc = validate_accumulate(ctx, ref_phase, n_src, src_phases, src_dvfs, n_sub, n_histories);
@@ -2263,7 +2342,44 @@ int pmc_accumulate_device(pmc_context *ctx, int32_t ref_phase, const int64_t *re
   HIP_TRY(ctx, pmc::launch_convert((const long long *)ref_tally, ref.d_hu, ref.d_mask, ref.d_lut64, nvox,
                                    vol_ref, nh, dev_dose, nullptr, st),
           "reference dose");
-  if (n_src > 0) {
+  if (n_src > 0 && method == kDim) {
+    // scratch: one source dose at a time; wait (on this stream) for the calls
+    // that used the scratch before
+    size_t need = 0;
+    for (int32_t s = 0; s < n_src; ++s)
+      need = std::max(need, sizeof(double) * (size_t)ctx->phases[src_phases[s]].nvox());
+    rc = ensure(ctx, ctx->acc, need, "accumulators");
+    if (rc) return rc;
+    for (auto &p : ctx->acc_uses.ev) HIP_TRY(ctx, hipStreamWaitEvent(st, p.second, 0), "wait accumulators");
+    auto *sdose = static_cast<double *>(ctx->acc.p);
+    for (int32_t s = 0; s < n_src; ++s) {
+      const PhaseRec &src = ctx->phases[src_phases[s]];
+      const DvfRec &dv = ctx->dvfs[src_dvfs[s]];
+      const double vol_src = (0.1 * src.sp_mm[0]) * (0.1 * src.sp_mm[1]) * (0.1 * src.sp_mm[2]);
+      HIP_TRY(ctx, pmc::launch_convert((const long long *)src_tallies[s], src.d_hu, src.d_mask, src.d_lut64,
+                                       src.nvox(), vol_src, nh, sdose, nullptr, st),
+              "source dose");
+      pmc::DimPull a = {};
+      a.nx = ref.nx;
+      a.ny = ref.ny;
+      a.nz = ref.nz;
+      a.dvf = dv.dev;
+      a.snx = src.nx;
+      a.sny = src.ny;
+      a.snz = src.nz;
+      for (int k = 0; k < 3; ++k) {
+        a.org[k] = ref.org_mm[k];
+        a.sp[k] = ref.sp_mm[k];
+        a.sorg[k] = src.org_mm[k];
+        a.ssp[k] = src.sp_mm[k];
+      }
+      a.sdose = sdose;
+      a.n_sub = n_sub;
+      a.aligned = aligned_dvf(dv.dev);
+      a.dose = dev_dose;
+      HIP_TRY(ctx, pmc::launch_dim_pull(a, st), "dim_pull launch");
+    }
+  } else if (n_src > 0) {
     // accumulators: wait (on this stream) for the calls that used them before
     rc = ensure(ctx, ctx->acc, 3 * sizeof(unsigned long long) * (size_t)nvox, "accumulators");
     if (rc) return rc;
@@ -2294,9 +2410,7 @@ int pmc_accumulate_device(pmc_context *ctx, int32_t ref_phase, const int64_t *re
         a.rinv[k] = 1.0 / ref.sp_mm[k];
       }
       a.n_sub = n_sub;
-      const pmc::DvfDev &g = dv.dev;
-      a.aligned = g.u[0] == 1.0 && g.u[1] == 0.0 && g.u[2] == 0.0 && g.v[0] == 0.0 && g.v[1] == 1.0 &&
-                  g.v[2] == 0.0;
+      a.aligned = aligned_dvf(dv.dev);
       a.e_hi = e_hi;
       a.e_lo = e_lo;
       a.mass = mass;
@@ -2316,7 +2430,7 @@ int pmc_accumulate_device(pmc_context *ctx, int32_t ref_phase, const int64_t *re
   for (int32_t s0 = 0; s0 < n_src || (s0 == 0 && dev_mask); s0 += pmc::kMaskDvfs) {
     pmc::EmtmMask m = {};
     m.n_dvf = std::min<int32_t>(pmc::kMaskDvfs, n_src - s0);
-    for (int32_t k = 0; k < m.n_dvf; ++k) m.dvfs[k] = ctx->dvfs[src_dvfs[s0 + k]].dev;
+    for (int32_t k = 0; k < m.n_dvf; ++k) m.dvfs[k] = box_of(ctx->dvfs[src_dvfs[s0 + k]].dev);
     m.first = s0 == 0;
     m.nx = ref.nx;
     m.ny = ref.ny;
@@ -2341,9 +2455,10 @@ int pmc_accumulate_device(pmc_context *ctx, int32_t ref_phase, const int64_t *re
   return note_pending(ctx, st);
 }
 
-int pmc_accumulate(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
-                   const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
-                   int32_t n_sub, uint64_t n_histories, double *dose_out, uint8_t *mask_out) {
+int accumulate_host(pmc_context *ctx, AccMethod method, int32_t ref_phase, const int64_t *ref_tally,
+                    int32_t n_src, const int32_t *src_phases, const int32_t *src_dvfs,
+                    const int64_t *const *src_tallies, int32_t n_sub, uint64_t n_histories, double *dose_out,
+                    uint8_t *mask_out) {
   if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
   ctx->err.clear();
   int rc = validate_accumulate(ctx, ref_phase, n_src, src_phases, src_dvfs, n_sub, n_histories);
@@ -2387,12 +2502,44 @@ int pmc_accumulate(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally
   if (!rc) rc = upload(nullptr, sizeof(double) * (size_t)nvox, &d_dose);
   if (!rc && mask_out) rc = upload(nullptr, (size_t)nvox, &d_mask);
   if (rc) return cleanup(rc);
-  rc = pmc_accumulate_device(ctx, ref_phase, static_cast<const int64_t *>(d_ref), n_src, src_phases, src_dvfs,
-                             d_src.data(), n_sub, n_histories, ctx->stream, static_cast<double *>(d_dose),
-                             static_cast<uint8_t *>(d_mask));
+  rc = accumulate_device(ctx, method, ref_phase, static_cast<const int64_t *>(d_ref), n_src, src_phases, src_dvfs,
+                         d_src.data(), n_sub, n_histories, ctx->stream, static_cast<double *>(d_dose),
+                         static_cast<uint8_t *>(d_mask));
   if (rc) return cleanup(rc);
   hipError_t e = copy_sync(ctx, dose_out, d_dose, sizeof(double) * (size_t)nvox, hipMemcpyDeviceToHost);
   if (e == hipSuccess && mask_out) e = copy_sync(ctx, mask_out, d_mask, (size_t)nvox, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "download accumulated dose"));
   return cleanup(PMC_OK);
+}
+
+}  // namespace
+
+int pmc_accumulate_device(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
+                          const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
+                          int32_t n_sub, uint64_t n_histories, void *stream, double *dev_dose,
+                          uint8_t *dev_mask) {
+  return accumulate_device(ctx, kEmtm, ref_phase, ref_tally, n_src, src_phases, src_dvfs, src_tallies, n_sub,
+                           n_histories, stream, dev_dose, dev_mask);
+}
+
+int pmc_accumulate_dim_device(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
+                              const int32_t *src_phases, const int32_t *src_dvfs,
+                              const int64_t *const *src_tallies, int32_t n_sub, uint64_t n_histories,
+                              void *stream, double *dev_dose, uint8_t *dev_mask) {
+  return accumulate_device(ctx, kDim, ref_phase, ref_tally, n_src, src_phases, src_dvfs, src_tallies, n_sub,
+                           n_histories, stream, dev_dose, dev_mask);
+}
+
+int pmc_accumulate(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
+                   const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
+                   int32_t n_sub, uint64_t n_histories, double *dose_out, uint8_t *mask_out) {
+  return accumulate_host(ctx, kEmtm, ref_phase, ref_tally, n_src, src_phases, src_dvfs, src_tallies, n_sub,
+                         n_histories, dose_out, mask_out);
+}
+
+int pmc_accumulate_dim(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_tally, int32_t n_src,
+                       const int32_t *src_phases, const int32_t *src_dvfs, const int64_t *const *src_tallies,
+                       int32_t n_sub, uint64_t n_histories, double *dose_out, uint8_t *mask_out) {
+  return accumulate_host(ctx, kDim, ref_phase, ref_tally, n_src, src_phases, src_dvfs, src_tallies, n_sub,
+                         n_histories, dose_out, mask_out);
 }

@@ -154,11 +154,20 @@ struct InfluenceLaunch {
 // Deformation vector field on the device (App. B): grid points i + n[0] (j +
 // n[1] k) at start + i sp[0] u + j sp[1] v + k sp[2] w, translations delta
 // (3 doubles per point, same order).
+// DVF grid box (geometry only): the report mask tests points against it.
+struct DvfBox {
+  int32_t n[3];
+  double start[3], sp[3];
+  double u[3], v[3], w[3];
+};
+
 struct DvfDev {
   int32_t n[3];
   double start[3], sp[3];
   double u[3], v[3], w[3];
   const double *delta;
+  int32_t has_pre, has_post;  // rigid matrices of Eq. (7) (rows 0..2 of 4x4)
+  double pre[12], post[12];
 };
 
 // Energy/mass push of one source phase into the reference accumulators.
@@ -190,7 +199,7 @@ struct EmtmRatio {
 // kMaskDvfs DVFs; `first` writes the mask, later passes only clear it.
 constexpr int kMaskDvfs = 16;
 struct EmtmMask {
-  DvfDev dvfs[kMaskDvfs];
+  DvfBox dvfs[kMaskDvfs];
   int32_t n_dvf;
   int32_t first;
   int32_t nx, ny, nz;
@@ -199,7 +208,25 @@ struct EmtmMask {
   uint8_t *mask_out;  // nullable
 };
 
+// Dose interpolation of one source phase (Eq. (3)): dose_i += average over
+// the subvoxel centres of reference voxel i of the source dose sampled at
+// their images under the reference-to-source DVF.
+struct DimPull {
+  int32_t nx, ny, nz;
+  double org[3], sp[3];      // reference grid, mm
+  DvfDev dvf;                // reference -> source
+  int32_t snx, sny, snz;
+  double sorg[3], ssp[3];    // source grid, mm
+  const double *sdose;       // source dose per voxel (Gy per history)
+  int32_t n_sub;
+  int32_t aligned;           // as EmtmPush
+  double *dose;
+};
+
 hipError_t launch_emtm_push(const EmtmPush &a, hipStream_t st);
+hipError_t launch_dim_pull(const DimPull &a, hipStream_t st);
+// Eqs. (8), (7) at every grid point; outputs nullable (device memory)
+hipError_t launch_dvf_points(const DvfDev &d, double *x0, double *rf, hipStream_t st);
 hipError_t launch_emtm_ratio(const EmtmRatio &a, hipStream_t st);
 hipError_t launch_emtm_mask(const EmtmMask &a, hipStream_t st);
 

@@ -37,7 +37,8 @@ EXPORTS = ["pmc_create", "pmc_destroy", "pmc_last_error", "pmc_load_phase", "pmc
            "pmc_convert_device", "pmc_trace", "pmc_split_histories", "pmc_bytes_in_use",
            "pmc_graph_create", "pmc_graph_launch", "pmc_graph_destroy", "pmc_influence_boxes",
            "pmc_influence", "pmc_influence_read", "pmc_influence_device", "pmc_influence_free",
-           "pmc_load_dvf", "pmc_unload_dvf", "pmc_accumulate", "pmc_accumulate_device"]
+           "pmc_load_dvf", "pmc_unload_dvf", "pmc_dvf_points", "pmc_accumulate", "pmc_accumulate_device",
+           "pmc_accumulate_dim", "pmc_accumulate_dim_device"]
 
 
 class pmc_config(C.Structure):
@@ -47,7 +48,8 @@ class pmc_config(C.Structure):
 
 class pmc_dvf(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("start_mm", C.c_double * 3), ("spacing_mm", C.c_double * 3),
-                ("row", C.c_double * 3), ("col", C.c_double * 3), ("delta_mm", C.c_void_p)]
+                ("row", C.c_double * 3), ("col", C.c_double * 3), ("delta_mm", C.c_void_p),
+                ("pre", C.c_void_p), ("post", C.c_void_p)]
 
 
 class pmc_shape(C.Structure):
@@ -128,8 +130,11 @@ def lib():
         L.pmc_request_item_histories.argtypes = [vp, C.POINTER(pmc_request), vp, u64, C.POINTER(u64)]
         L.pmc_load_dvf.argtypes = [vp, i32, C.POINTER(pmc_dvf)]
         L.pmc_unload_dvf.argtypes = [vp, i32]
+        L.pmc_dvf_points.argtypes = [vp, i32, vp, vp]
         L.pmc_accumulate.argtypes = [vp, i32, vp, i32, vp, vp, vp, i32, u64, vp, vp]
         L.pmc_accumulate_device.argtypes = [vp, i32, vp, i32, vp, vp, vp, i32, u64, vp, vp, vp]
+        L.pmc_accumulate_dim.argtypes = [vp, i32, vp, i32, vp, vp, vp, i32, u64, vp, vp]
+        L.pmc_accumulate_dim_device.argtypes = [vp, i32, vp, i32, vp, vp, vp, i32, u64, vp, vp, vp]
         L.pmc_launch_shape.argtypes = [vp, C.POINTER(pmc_request), C.POINTER(pmc_shape)]
         L.pmc_dose.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, C.POINTER(pmc_balance)]
         L.pmc_dose_device.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp]
@@ -322,10 +327,30 @@ def pmc_load_dvf(ctx, dvf_id: int, dvf) -> None:
     delta = np.ascontiguousarray(dvf.delta_mm, dtype=np.float64)
     if delta.shape != (dvf.n[2], dvf.n[1], dvf.n[0], 3):
         raise ValueError("delta_mm must have shape (n[2], n[1], n[0], 3)")
+    mats = []
+    for m in (getattr(dvf, "pre", None), getattr(dvf, "post", None)):
+        if m is None:
+            mats.append(None)
+            continue
+        a = np.ascontiguousarray(m, dtype=np.float64)
+        if a.shape != (4, 4):
+            raise ValueError("pre/post must be 4x4 matrices")
+        mats.append(a)
     d = pmc_dvf((C.c_int32 * 3)(*dvf.n), (C.c_double * 3)(*dvf.start_mm),
                 (C.c_double * 3)(*dvf.spacing_mm), (C.c_double * 3)(*dvf.row),
-                (C.c_double * 3)(*dvf.col), delta.ctypes.data)
+                (C.c_double * 3)(*dvf.col), delta.ctypes.data,
+                None if mats[0] is None else mats[0].ctypes.data,
+                None if mats[1] is None else mats[1].ctypes.data)
     _check(lib().pmc_load_dvf(ctx, dvf_id, C.byref(d)), ctx)
+
+
+def pmc_dvf_points(ctx, dvf_id: int, n):
+    """(x0, r_f) of every grid point, each (n[2], n[1], n[0], 3), computed on
+    the device (Eqs. (8), (7))."""
+    x0 = np.zeros((n[2], n[1], n[0], 3), dtype=np.float64)
+    rf = np.zeros_like(x0)
+    _check(lib().pmc_dvf_points(ctx, dvf_id, _ptr(x0), _ptr(rf)), ctx)
+    return x0, rf
 
 
 def pmc_unload_dvf(ctx, dvf_id: int) -> None:
@@ -355,6 +380,35 @@ def pmc_accumulate_device(ctx, ref_phase: int, ref_tally: int, src_phases: Seque
     dv = np.ascontiguousarray(src_dvfs, dtype=np.int32)
     tp = (C.c_void_p * max(len(src_tallies), 1))(*[int(t) for t in src_tallies])
     _check(lib().pmc_accumulate_device(ctx, ref_phase, C.c_void_p(ref_tally), len(src_tallies), _ptr(ph),
+                                       _ptr(dv), tp, n_sub, n_histories, C.c_void_p(stream),
+                                       C.c_void_p(dev_dose), None if dev_mask is None else C.c_void_p(dev_mask)),
+           ctx)
+
+
+def pmc_accumulate_dim(ctx, ref_phase: int, ref_tally: np.ndarray, src_phases: Sequence[int],
+                   src_dvfs: Sequence[int], src_tallies: Sequence[np.ndarray], n_sub: int,
+                   n_histories: int, nvox_ref: int, want_mask: bool = False):
+    """Dose interpolation (Eq. (3)); src_dvfs map the reference phase onto each
+    source.  Returns (dose, mask or None) on the reference grid."""
+    ref = np.ascontiguousarray(ref_tally, dtype=np.int64)
+    srcs = [np.ascontiguousarray(t, dtype=np.int64) for t in src_tallies]
+    ph = np.ascontiguousarray(src_phases, dtype=np.int32)
+    dv = np.ascontiguousarray(src_dvfs, dtype=np.int32)
+    tp = (C.c_void_p * max(len(srcs), 1))(*[t.ctypes.data for t in srcs])
+    dose = np.zeros(nvox_ref, dtype=np.float64)
+    mask = np.zeros(nvox_ref, dtype=np.uint8) if want_mask else None
+    _check(lib().pmc_accumulate_dim(ctx, ref_phase, _ptr(ref), len(srcs), _ptr(ph), _ptr(dv), tp, n_sub,
+                                n_histories, _ptr(dose), _ptr(mask)), ctx)
+    return dose, mask
+
+
+def pmc_accumulate_dim_device(ctx, ref_phase: int, ref_tally: int, src_phases: Sequence[int],
+                          src_dvfs: Sequence[int], src_tallies: Sequence[int], n_sub: int,
+                          n_histories: int, stream: int, dev_dose: int, dev_mask: Optional[int] = None):
+    ph = np.ascontiguousarray(src_phases, dtype=np.int32)
+    dv = np.ascontiguousarray(src_dvfs, dtype=np.int32)
+    tp = (C.c_void_p * max(len(src_tallies), 1))(*[int(t) for t in src_tallies])
+    _check(lib().pmc_accumulate_dim_device(ctx, ref_phase, C.c_void_p(ref_tally), len(src_tallies), _ptr(ph),
                                        _ptr(dv), tp, n_sub, n_histories, C.c_void_p(stream),
                                        C.c_void_p(dev_dose), None if dev_mask is None else C.c_void_p(dev_mask)),
            ctx)

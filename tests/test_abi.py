@@ -286,6 +286,35 @@ def test_dvf_and_accumulation_validation(P):
         with pytest.raises(P.PmcError) as e:
             P.pmc_accumulate(ctx, 0, t, [1], [4], [t], 2, 10, 8 ** 3)
         assert e.value.code == P.PMC_E_DEVICE  # all arguments valid
+        # the same checks for dose interpolation
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_accumulate_dim(ctx, 0, t, [1], [5], [t], 2, 10, 8 ** 3)
+        assert e.value.code == P.PMC_E_STATE
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_accumulate_dim(ctx, 0, t, [1], [4], [t], 17, 10, 8 ** 3)
+        assert e.value.code == P.PMC_E_INVAL
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_accumulate_dim(ctx, 0, t, [1], [4], [t], 3, 10, 8 ** 3)
+        assert e.value.code == P.PMC_E_DEVICE
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_dvf_points(ctx, 4, n)
+        assert e.value.code == P.PMC_E_DEVICE
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_dvf_points(ctx, 9, n)
+        assert e.value.code == P.PMC_E_STATE
+        # rigid matrices of Eq. (7): accepted when rigid, rejected otherwise
+        rot = np.eye(4)
+        rot[:2, :2] = [[0.6, -0.8], [0.8, 0.6]]
+        rot[:3, 3] = [1.0, -2.0, 3.0]
+        P.pmc_load_dvf(ctx, 6, W.Dvf(n, good.start_mm, good.spacing_mm, good.row, good.col, good.delta_mm,
+                                     pre=rot, post=np.linalg.inv(rot)))
+        stretched = np.eye(4)
+        stretched[0, 0] = 1.1
+        for m in (stretched, np.diag([1.0, 1.0, 1.0, 2.0]), np.full((4, 4), np.nan)):
+            with pytest.raises(P.PmcError) as e:
+                P.pmc_load_dvf(ctx, 7, W.Dvf(n, good.start_mm, good.spacing_mm, good.row, good.col,
+                                             good.delta_mm, post=m))
+            assert e.value.code == P.PMC_E_INVAL
         P.pmc_unload_dvf(ctx, 4)
         with pytest.raises(P.PmcError):
             P.pmc_unload_dvf(ctx, 4)

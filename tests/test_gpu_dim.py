@@ -1,0 +1,203 @@
+"""Dose-interpolation accumulation (pmc_accumulate_dim, Eq. (3)), the DVF
+construction of App. B (pmc_dvf_points, Eqs. (7)-(8)) and rigid pre/post
+matrices in the mapping, on the GPU through the C ABI, against the oracle
+(`oracle.dim`, `oracle.emtm`).
+
+DIM values are continuous in the mapped positions and both sides evaluate the
+same FP64 operations in the same order, so the doses agree to the last bits;
+the source doses come from the same tallies through densities that the two
+sides interpolate from the calibration independently (a last-bit difference
+for some HU values), hence the 1e-12 relative tolerance."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1809_03927_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1809_03927_amd import pmc
+    return pmc
+
+
+@pytest.fixture(scope="module")
+def E():
+    import oracle.emtm as emtm
+    return emtm
+
+
+@pytest.fixture(scope="module")
+def D():
+    import oracle.dim as dim
+    return dim
+
+
+def rot(theta, axis, t):
+    c, s = math.cos(theta), math.sin(theta)
+    m = np.eye(4)
+    i, j = [(1, 2), (2, 0), (0, 1)][axis]
+    m[i, i] = c
+    m[i, j] = -s
+    m[j, i] = s
+    m[j, j] = c
+    m[:3, 3] = t
+    return m
+
+
+def densities(orc, phases):
+    return [orc.convert(ph, np.zeros(ph.hu.size, dtype=np.int64), 1)[1] for ph in phases]
+
+
+def doses_of(E, phases, tallies, rho, n_hist):
+    return [E.phase_dose(t, r, float(np.prod(np.asarray(ph.spacing_mm) * 0.1)), n_hist)
+            for ph, t, r in zip(phases, tallies, rho)]
+
+
+def compare(got, want, mask_got, mask_want, rtol=1e-12):
+    assert np.array_equal(mask_got.astype(bool), mask_want)
+    scale = max(float(np.abs(want).max()), 1e-300)
+    err = np.abs(got - want)
+    assert np.all(err <= rtol * np.maximum(np.abs(want), 1e-3 * scale)), float(
+        np.max(err / np.maximum(np.abs(want), 1e-3 * scale)))
+
+
+def test_dvf_points_match_eqs_7_and_8(P, E):
+    """A rotated grid with rigid pre/post matrices: x0 and r_f of every grid
+    point bit-identical to the oracle's evaluation of Eqs. (8) and (7)."""
+    c, s = math.cos(0.3), math.sin(0.3)
+    n = (7, 5, 4)
+    rng = np.random.default_rng(1)
+    d = W.Dvf(n, (-12.0, 4.0, 30.0), (2.5, 3.0, 2.0), (c, s, 0.0), (-s * 0.8, c * 0.8, 0.6),
+              rng.uniform(-3, 3, size=(n[2], n[1], n[0], 3)), pre=rot(0.2, 2, [1.0, 2.0, -1.0]),
+              post=rot(-0.4, 0, [0.0, -3.0, 5.0]))
+    ctx = P.pmc_create(0, P.PMC_FP32, 1, 0)
+    try:
+        P.pmc_load_dvf(ctx, 3, d)
+        say("dvf points", n)
+        x0, rf = P.pmc_dvf_points(ctx, 3, n)
+    finally:
+        P.pmc_destroy(ctx)
+    wx0, wrf = E.dvf_points(d)
+    assert np.array_equal(x0, wx0) and np.array_equal(rf, wrf)
+
+
+@pytest.mark.parametrize("n_sub,ids", [(1, [0, 2, 5, 8]), (2, [0, 2, 5, 8]), (3, [0, 2, 5, 8]), (5, [0, 5])])
+def test_dim_matches_oracle_breathing_dvfs(P, E, D, orc, n_sub, ids):
+    """Thorax phases pulled onto phase 0 through reference-to-source breathing
+    DVFs (axis-aligned: the per-axis kernel path)."""
+    shape = (64, 64, 40)
+    phases = [W.make_thorax(shape, p, 10) for p in ids]
+    dvfs = [None] + [W.thorax_dvf(0, p) for p in ids[1:]]
+    rng = np.random.default_rng(7)
+    tallies = [rng.integers(0, 2**40, size=ph.hu.size) * (ph.hu.ravel() > -1000) for ph in phases]
+    ctx = P.pmc_create(0, P.PMC_FP32, 1, 0)
+    try:
+        for k, ph in enumerate(phases):
+            P.pmc_load_phase(ctx, k, ph)
+        for k in range(1, len(ids)):
+            P.pmc_load_dvf(ctx, 10 + k, dvfs[k])
+        say("dim breathing", shape, "n_sub", n_sub)
+        src = list(range(1, len(ids)))
+        dose, mask = P.pmc_accumulate_dim(ctx, 0, tallies[0], src, [10 + k for k in src], tallies[1:], n_sub,
+                                          1000, phases[0].hu.size, want_mask=True)
+    finally:
+        P.pmc_destroy(ctx)
+    rho = densities(orc, phases)
+    ref = D.dim(phases, doses_of(E, phases, tallies, rho, 1000), 0, dvfs, n_sub)
+    assert ref["mask"].sum() < ref["mask"].size
+    compare(dose, ref["dose"], mask, ref["mask"])
+    assert np.mean(dose == ref["dose"]) > 0.999  # four HU values: identical densities
+
+
+@pytest.mark.parametrize("n_sub", [2, 5])
+def test_dim_and_emtm_with_rotated_grids_and_rigid_matrices(P, E, D, orc, n_sub):
+    """The general mapping: rotated DVF grids with rigid pre/post matrices,
+    random HU, different source and reference grids; DIM and EMTM both,
+    host and device entry points."""
+    import torch
+    ref_ph = W.make_box((20, 18, 12), (2.0, 2.5, 3.0), 0)
+    src_ph = W.make_box((16, 20, 10), (2.5, 2.0, 3.5), 0, origin_mm=(-19.0, -21.0, 1.0))
+    rng = np.random.default_rng(11)
+    for ph in (ref_ph, src_ph):
+        ph.hu[...] = rng.integers(-1000, 1500, size=ph.hu.shape).astype(np.int16)
+    c, s = math.cos(0.35), math.sin(0.35)
+
+    def field(ph, pad):
+        nz, ny, nx = ph.hu.shape
+        o = np.asarray(ph.origin_mm) + 0.5 * np.asarray(ph.spacing_mm) + pad
+        ext = np.asarray(ph.spacing_mm) * (np.array([nx, ny, nz]) - 1) - 2 * pad
+        n = tuple(int(e // 3.0) + 1 for e in ext)
+        return W.Dvf(n, tuple(o), (3.0, 3.0, 3.0), (c, s, 0.0), (-s, c, 0.0),
+                     rng.uniform(-2.0, 2.0, size=(n[2], n[1], n[0], 3)),
+                     pre=rot(0.05, 1, [0.5, -0.3, 0.2]), post=rot(-0.05, 1, [-0.4, 0.3, -0.1]))
+
+    d_rs = field(ref_ph, 3.0)  # reference -> source (DIM)
+    d_sr = field(src_ph, 3.0)  # source -> reference (EMTM)
+    tallies = [rng.integers(0, 2**38, size=ph.hu.size) for ph in (ref_ph, src_ph)]
+    ctx = P.pmc_create(0, P.PMC_FP32, 1, 0)
+    try:
+        P.pmc_load_phase(ctx, 0, ref_ph)
+        P.pmc_load_phase(ctx, 1, src_ph)
+        P.pmc_load_dvf(ctx, 1, d_rs)
+        P.pmc_load_dvf(ctx, 2, d_sr)
+        say("dim/emtm general mapping, n_sub", n_sub)
+        dim_dose, dim_mask = P.pmc_accumulate_dim(ctx, 0, tallies[0], [1], [1], [tallies[1]], n_sub, 50,
+                                                  ref_ph.hu.size, want_mask=True)
+        em_dose, em_mask = P.pmc_accumulate(ctx, 0, tallies[0], [1], [2], [tallies[1]], n_sub, 50,
+                                            ref_ph.hu.size, want_mask=True)
+        # device entry point of DIM on torch buffers and stream: identical
+        st = torch.cuda.Stream()
+        dt = [torch.from_numpy(t).cuda() for t in tallies]
+        dd = torch.empty(ref_ph.hu.size, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        P.pmc_accumulate_dim_device(ctx, 0, dt[0].data_ptr(), [1], [1], [dt[1].data_ptr()], n_sub, 50,
+                                    st.cuda_stream, dd.data_ptr(), None)
+        st.synchronize()
+        assert np.array_equal(dd.cpu().numpy(), dim_dose)
+    finally:
+        P.pmc_destroy(ctx)
+    rho = densities(orc, [ref_ph, src_ph])
+    doses = doses_of(E, [ref_ph, src_ph], tallies, rho, 50)
+    want = D.dim([ref_ph, src_ph], doses, 0, [None, d_rs], n_sub)
+    assert want["mask"].any() and not want["mask"].all()
+    compare(dim_dose, want["dose"], dim_mask, want["mask"])
+    want_e = E.emtm([ref_ph, src_ph], tallies, rho, 0, [None, d_sr], n_sub, 50)
+    assert want_e["sums"][1]["mass"].sum() > 0
+    assert np.array_equal(em_mask.astype(bool), want_e["mask"])
+    assert np.allclose(em_dose, want_e["dose"], rtol=1e-9, atol=0)
+
+
+def test_dim_identity_dvfs_sum_the_phase_doses(P):
+    """Identity reference-to-source DVFs and n = 1: every reference voxel
+    samples each source dose at its own centre, so the accumulated dose is
+    the sum of the phases' doses (Sec. 2.E's first test, with the MC doses
+    of a 4D run)."""
+    wl = W.workload_thorax4d(n_histories=200_000, shape_xyz=(64, 64, 40), n_phases=3)
+    e = P.Engine(device=0, precision=P.PMC_FP32, seed=wl.seed)
+    try:
+        e.load_workload(wl)
+        doses, tallies, _, _ = e.dose(wl.n_histories, [0, 1, 2], engine=P.PMC_ENGINE_PERSISTENT)
+        ph = wl.phases[0]
+        nz, ny, nx = ph.hu.shape
+        sp = np.asarray(ph.spacing_mm)
+        o = np.asarray(ph.origin_mm) - sp
+        ident = W.Dvf((nx + 2, ny + 2, nz + 2), tuple(o), tuple(sp), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0),
+                      np.zeros((nz + 2, ny + 2, nx + 2, 3)))
+        P.pmc_load_dvf(e.ctx, 7, ident)
+        say("dim identity")
+        dose, mask = P.pmc_accumulate_dim(e.ctx, 0, tallies[0], [1, 2], [7, 7], tallies[1:], 1,
+                                          wl.n_histories, ph.hu.size, want_mask=True)
+        assert mask.all()
+        want = doses[0] + doses[1] + doses[2]
+        assert np.allclose(dose, want, rtol=1e-12, atol=1e-12 * want.max())
+    finally:
+        e.close()
