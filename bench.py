@@ -63,6 +63,11 @@ PROFILED_KERNEL_HASH = "710bdd01123ff18f"
 ACC_REF_PHASE = 5
 ACC_N_SUB = 5
 ACC_OPS_PER_SUBVOXEL = 105
+# Dose interpolation (Eq. (3)) per mapped subvoxel of a reference voxel: the
+# same centre, grid coordinates, fractions and translation (99), then the
+# dose sample: voxel-centre coordinates 9 (3 x subtract, divide, subtract),
+# fractions 3, 7 lerps of 3 operations, and the add into the sum: 133.
+DIM_OPS_PER_SUBVOXEL = 133
 # These are unfused FP64 operations: one per lane per clock, 256 CUs x 64
 # FP64 lanes x 2.4 GHz (the 78.6 TFLOP/s FP64 vector figure counts an FMA as
 # two operations).
@@ -72,7 +77,8 @@ PEAK_FP64_OPS = 256 * 64 * 2.4e9
 # scaled like the transport's (profiles/emtm_push_thorax4d_counters.md);
 # valid for the source it was measured on (hash of pmc_accumulate.hip).
 PROFILED_ACC_TRAFFIC_BYTES = 3.13e9
-PROFILED_ACC_HASH = "df93c254057989c0"
+PROFILED_DIM_TRAFFIC_BYTES = 4.40e9
+PROFILED_ACC_HASH = "8557f93252cfdc1c"
 
 
 def log(*a):
@@ -380,9 +386,10 @@ def atomic_probe(torch, nvox, n=200_000_000):
     return n / (e0.elapsed_time(e1) * 1e-3)
 
 
-def mapped_subvoxels(ph, dvf, n):
-    """Subvoxel centres of the phase's voxels with mass that lie inside the
-    grid box of an axis-aligned DVF (the subvoxels that are mapped)."""
+def mapped_subvoxels(ph, dvf, n, with_mass=True):
+    """Subvoxel centres of the phase's voxels (with mass, if with_mass) that
+    lie inside the grid box of an axis-aligned DVF (the subvoxels that are
+    mapped)."""
     import numpy as np
     assert tuple(dvf.row) == (1.0, 0.0, 0.0) and tuple(dvf.col) == (0.0, 1.0, 0.0)
     nz, ny, nx = ph.hu.shape
@@ -395,6 +402,8 @@ def mapped_subvoxels(ph, dvf, n):
     has_mass = np.interp(hu, np.asarray(ph.calib_hu, float), np.asarray(ph.calib_rho, float)) > 0
     if ph.mask is not None:
         has_mass &= ph.mask.astype(bool)
+    if not with_mass:
+        has_mass = np.ones(ph.hu.shape, dtype=bool)
     return float(np.einsum("zyx,x,y,z->", has_mass.astype(np.float64), cnt[0], cnt[1], cnt[2]))
 
 
@@ -447,6 +456,118 @@ def accumulation_bench(eng, wl, tallies, stream, timed, steps, cpu_seconds):
     }
     if cpu_seconds:
         out["cpu_baseline"] = accumulation_cpu(eng, wl, tallies, dvfs, src[0], ref, n, cpu_seconds)
+    out["dim"] = dim_bench(eng, wl, tallies, stream, timed, steps, cpu_seconds)
+    return out
+
+
+def dim_bench(eng, wl, tallies, stream, timed, steps, cpu_seconds):
+    """The same accumulation by dose interpolation (pmc_accumulate_dim_device:
+    reference-to-source DVFs, one thread per reference voxel), with its
+    FP64-operation roofline; then the oracle's Eq. (3) on a z-slab of the
+    reference phase, timed, and the GPU's result for that slab checked
+    against it."""
+    import numpy as np
+    import torch
+    from paper_1809_03927_amd import pmc
+    from paper_1809_03927_amd import workloads as W
+    ref = ACC_REF_PHASE
+    n = ACC_N_SUB
+    src = [p for p in range(len(wl.phases)) if p != ref]
+    dvfs = {p: W.thorax_dvf(ref, p, n_phases=len(wl.phases)) for p in src}
+    for p in src:
+        pmc.pmc_load_dvf(eng.ctx, 300 + p, dvfs[p])
+    nv = wl.phases[ref].nvox
+    dose = torch.empty(nv, dtype=torch.float64, device="cuda")
+    mask = torch.empty(nv, dtype=torch.uint8, device="cuda")
+
+    def run():
+        pmc.pmc_accumulate_dim_device(eng.ctx, ref, tallies[ref].data_ptr(), src, [300 + p for p in src],
+                                      [tallies[p].data_ptr() for p in src], n, wl.n_histories,
+                                      stream.cuda_stream, dose.data_ptr(), mask.data_ptr())
+    _, spans = timed(run, steps, 1)
+    ms = float(np.mean(spans))
+    mapped = sum(mapped_subvoxels(wl.phases[ref], dvfs[p], n, with_mass=False) for p in src)
+    achieved = DIM_OPS_PER_SUBVOXEL * mapped / (ms * 1e-3)
+    log(f"dose interpolation: {ms:.2f} ms for {len(src)} source phases (n_sub {n}), "
+        f"{mapped / (ms * 1e-3) / 1e9:.1f} G subvoxels/s")
+    out = {
+        "workload": f"DIM: phases {src} of the thorax4d run pulled onto phase {ref}, n_sub {n}, "
+                    f"reference-to-source DVFs {dvfs[src[0]].n[0]}x{dvfs[src[0]].n[1]}x{dvfs[src[0]].n[2]} "
+                    f"@2.5 mm",
+        "value": mapped / (ms * 1e-3), "unit": "mapped subvoxels/s", "ms_per_accumulation": ms,
+        "ms_per_source_phase": ms / len(src), "mapped_subvoxels": mapped, "dtype": "f64",
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_OPS / 1e12,
+                     "unit": "T FP64 op/s (unfused)", "frac": achieved / PEAK_FP64_OPS,
+                     "traffic": (PROFILED_DIM_TRAFFIC_BYTES if wl.phases[ref].hu.shape == (160, 256, 256)
+                                 and len(wl.phases) == 10
+                                 and source_hash(["pmc_accumulate.hip"]) == PROFILED_ACC_HASH else None),
+                     "traffic_unit": "bytes per accumulation call (HBM side)",
+                     "ops_per_subvoxel": DIM_OPS_PER_SUBVOXEL,
+                     "kernel": "dim_pull (with the source and reference doses, mask)"},
+        "cpu_baseline": None,
+    }
+    if cpu_seconds:
+        out["cpu_baseline"] = dim_cpu(eng, wl, tallies, dvfs, src[0], ref, n, cpu_seconds)
+    return out
+
+
+def dim_cpu(eng, wl, tallies, dvfs, sp, ref, n, target_s):
+    """The oracle's Eq. (3) for a z-slab of the reference phase (through the
+    middle of the grid) from source phase sp, timed; then the GPU's pull onto
+    the same slab (as a phase of its own, zero reference tally) against it:
+    masks identical, doses within 1e-12 relative."""
+    import dataclasses
+    import numpy as np
+    import torch
+    import oracle
+    import oracle.dim as D
+    import oracle.emtm as E
+    from paper_1809_03927_amd import pmc
+    rph, sph, dvf = wl.phases[ref], wl.phases[sp], dvfs[sp]
+    nz = rph.hu.shape[0]
+    t_src = tallies[sp].cpu().numpy()
+    rho_s = oracle.convert(sph, np.zeros(sph.hu.size, dtype=np.int64), 1)[1]
+    dose_s = E.phase_dose(t_src, rho_s, float(np.prod(np.asarray(sph.spacing_mm) * 0.1)), wl.n_histories)
+
+    def slab(k):
+        z0 = nz // 2 - k // 2
+        o = (rph.origin_mm[0], rph.origin_mm[1], rph.origin_mm[2] + z0 * rph.spacing_mm[2])
+        return dataclasses.replace(rph, hu=np.ascontiguousarray(rph.hu[z0:z0 + k]), origin_mm=o, mask=None)
+
+    def pull(k):
+        c = slab(k)
+        t1 = time.perf_counter()
+        d = D.pull(c, sph, dose_s, dvf, n)
+        return c, d, time.perf_counter() - t1
+
+    _, _, dt1 = pull(1)
+    k = int(min(nz, max(1, target_s / max(dt1, 1e-3))))
+    c, term, dt = pull(k)
+    mapped = mapped_subvoxels(c, dvf, n, with_mass=False)
+    want_mask = E.report_mask(c, [dvf])
+    want = np.where(want_mask, term, 0.0)
+    out = {"value": mapped / dt, "unit": "mapped subvoxels/s", "cores": 1, "kind": "oracle",
+           "sample": f"{k} z-slices of phase {ref} ({c.hu.size} voxels, {mapped:.3g} mapped subvoxels, "
+                     f"n_sub {n}) pulled from phase {sp} by the numpy oracle in {dt:.1f} s"}
+    pmc.pmc_load_phase(eng.ctx, 201, c)
+    zero = torch.zeros(c.hu.size, dtype=torch.int64, device="cuda")
+    dose = torch.empty(c.hu.size, dtype=torch.float64, device="cuda")
+    mask = torch.empty(c.hu.size, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    pmc.pmc_accumulate_dim_device(eng.ctx, 201, zero.data_ptr(), [sp], [300 + sp], [tallies[sp].data_ptr()], n,
+                                  wl.n_histories, 0, dose.data_ptr(), mask.data_ptr())
+    torch.cuda.synchronize()
+    pmc.pmc_unload_phase(eng.ctx, 201)
+    got, gmask = dose.cpu().numpy(), mask.cpu().numpy().astype(bool)
+    sel = want > 0
+    rel = float(np.max(np.abs(got[sel] - want[sel]) / want[sel])) if sel.any() else 0.0
+    same_mask = bool(np.array_equal(gmask, want_mask))
+    out["accuracy"] = {"check": "GPU vs oracle on the sample: report masks identical, doses within 1e-12 "
+                                "relative", "voxels": int(sel.sum()), "max_rel": rel,
+                       "bit_identical_frac": float(np.mean(got == want)),
+                       "passed": bool(same_mask and rel <= 1e-12 and sel.any())}
+    log(f"dose interpolation oracle: {k} slices in {dt:.1f} s; GPU check max rel {rel:.2e}, "
+        f"mask identical {same_mask}")
     return out
 
 
