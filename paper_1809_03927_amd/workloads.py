@@ -249,6 +249,48 @@ def assign_phases(n_spots_per_layer: Sequence[int], start_phase: int, t_spot=0.0
     return np.array(phases, dtype=np.int32)
 
 
+# ----------------------------------------------------------------------------
+# Beam-delivery simulation inputs (Sec. 2.B, App. A)
+# ----------------------------------------------------------------------------
+
+# Synchrotron timing parameters, each (central value, 1-sigma uncertainty),
+# in the order the simulation draws them.  The paper takes its values from
+# its Ref. 45 (not available here); these are synthetic, of the magnitudes
+# App. A describes (layer switch ~2 s, 70 ms of discarded beam, ~8 s
+# extraction limit), and stand in for them.
+SYNC_PARAMS = ("layer_switch_s", "layer_switch_per_mev", "discard_s", "spill_rate_mu_s",
+               "spill_rate_per_mev", "spot_switch_s", "spot_switch_per_mm", "capacity_mu",
+               "extraction_max_s")
+SYNC_DEFAULT = {
+    "layer_switch_s": (1.9, 0.05),        # reset + acceleration to 70 MeV
+    "layer_switch_per_mev": (0.002, 0.0),  # s per MeV above 70 MeV
+    "discard_s": (0.070, 0.002),          # beam discarded at every extraction start
+    "spill_rate_mu_s": (8.0, 0.4),        # MU/s spilled at 70 MeV
+    "spill_rate_per_mev": (0.04, 0.0),    # MU/s per MeV above 70 MeV
+    "spot_switch_s": (0.002, 0.0002),     # beam off between spots
+    "spot_switch_per_mm": (0.0001, 0.0),  # s per mm of the larger axis move
+    "capacity_mu": (8.0, 0.3),            # MU one synchrotron fill delivers
+    "extraction_max_s": (8.0, 0.0),       # extraction time limit per fill
+}
+
+
+@dataclasses.dataclass
+class Delivery:
+    """Options of the beam-delivery simulation (Sec. 2.B)."""
+    n_phases: int = 10
+    start_phase: int = -1          # -1: U{0..N-1} per trial and field
+    period_s: float = 4.0          # breathing period mean mu
+    period_sd_s: float = 0.0       # sigma: t_ph = N(mu, sigma) / N per phase
+    period_min_s: int = 0          # 0 < min <= max: mu ~ U{min..max} s per trial and field
+    period_max_s: int = 0
+    gate_lo: int = -1              # gated delivery: phases gate_lo..gate_hi; -1: free breathing
+    gate_hi: int = -1
+    max_mu: float = 0.0            # isolayered repainting: max MU per spot delivery (0: none)
+    sync: dict = dataclasses.field(default_factory=lambda: dict(SYNC_DEFAULT))
+    seed: int = 1
+    n_trials: int = 1
+
+
 def layer_grid(nu: int, nv: int, pitch: float, serpentine=True):
     """Spot positions (u, v) of one layer on a centred nu x nv grid."""
     us = (np.arange(nu) - 0.5 * (nu - 1)) * pitch
