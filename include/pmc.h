@@ -462,6 +462,74 @@ int pmc_accumulate_dim_device(pmc_context *ctx, int32_t ref_phase, const int64_t
                               const int64_t *const *src_tallies, int32_t n_sub, uint64_t n_histories,
                               void *stream, double *dev_dose, uint8_t *dev_mask);
 
+/* ---- beam-delivery simulation (Sec. 2.B, App. A) ------------------------ */
+
+/* A parameter's central value and 1-sigma uncertainty (0: fixed). */
+typedef struct {
+  double central, sd;
+} pmc_param;
+
+/* Synchrotron timing (App. A), drawn once per trial and field as
+ * central + sd z (clipped at 0), in this order.  At energy E (MeV):
+ *   layer switch (reset, acceleration, preparation) a + b (E - 70),
+ *   spill rate (MU/s)                               c + d (E - 70),
+ *   beam off between two spots of a fill            e + f max(|dx|, |dy|) (mm). */
+typedef struct {
+  pmc_param layer_switch_s;       /* a */
+  pmc_param layer_switch_per_mev; /* b */
+  pmc_param discard_s;            /* beam discarded at every extraction start (70 ms) */
+  pmc_param spill_rate_mu_s;      /* c */
+  pmc_param spill_rate_per_mev;   /* d */
+  pmc_param spot_switch_s;        /* e */
+  pmc_param spot_switch_per_mm;   /* f */
+  pmc_param capacity_mu;          /* MU one synchrotron fill delivers */
+  pmc_param extraction_max_s;     /* extraction time limit of a fill */
+} pmc_synchrotron;
+
+typedef struct {
+  int32_t n_phases;               /* N, 1..64 */
+  int32_t start_phase;            /* 0..N-1, or -1: U{0..N-1} per trial and field */
+  double period_s;                /* breathing period mean mu, s (used unless min/max below) */
+  double period_sd_s;             /* sigma: phase k lasts max(mu + sigma z_k, mu / 20) / N */
+  int32_t period_min_s, period_max_s; /* if 0 < min <= max: mu ~ U{min..max} s per trial and field */
+  int32_t gate_lo, gate_hi;       /* gated delivery: beam on only in phases gate_lo..gate_hi
+                                     (0 <= lo <= hi < N); gate_lo = -1: free breathing */
+  double max_mu;                  /* isolayered repainting: at most max_mu per spot delivery; 0: none */
+  pmc_synchrotron sync;
+  uint64_t seed;                  /* Philox key word 0 is seed mod 2^32, word 1 the trial */
+  int32_t n_trials;               /* >= 1 */
+} pmc_delivery;
+
+/* Simulate the delivery of a plan (Sec. 2.B) in n_trials trials: which part
+ * of each spot's MU is delivered in which breathing phase.  Spots (weight =
+ * MU > 0, field 0..n_fields-1) are delivered in array order within each
+ * field; a layer is a run of consecutive spots of one field with one energy.
+ * Each (trial, field) is an independent timeline from t = 0 at the start of
+ * its first breathing phase, one GPU thread each:
+ *  - every layer starts a synchrotron fill: layer switch, then (gated) wait
+ *    for the gate, then discarded beam;
+ *  - painting r of a layer gives each spot min(MU - r max_mu, max_mu) while
+ *    positive (without repainting its whole MU once), in spot order; between
+ *    two deliveries the beam is off for the spot switch; a delivery that
+ *    would exceed the fill's charge or extraction time, and is not the fill's
+ *    first, starts a new fill at the same energy (layer switch, gate,
+ *    discard); a delivery that finds the gate closed waits for it and
+ *    discards beam again;
+ *  - a delivery lasts its MU / spill rate and belongs to the breathing phase
+ *    at its start.
+ * Random numbers: Philox4x32-10, key (seed mod 2^32, trial), counter (field,
+ * purpose, index, block); purpose 0 start phase, 1 synchrotron parameter
+ * (index = its position above), 2 breathing phase occurrence k, 3 period;
+ * a Gaussian z is the sum of the 12 words of blocks 0..2 times 2^-32, minus
+ * 6; U{0..n-1} is floor(word 0 of block 0 x n / 2^32).
+ * Outputs (host buffers, each nullable): mu_out[trial][spot][phase] (MU),
+ * time_out[trial][field] (end of the last delivery, s), fills_out
+ * [trial][field] (synchrotron fills).  PMC_E_INVAL for invalid options or
+ * spots, including spill rates that a draw within +-6 sigma could make <= 0
+ * at a spot's energy.  Blocks until done. */
+int pmc_delivery_simulate(pmc_context *ctx, const pmc_delivery *d, const pmc_spot *spots, int64_t n_spots,
+                          int32_t n_fields, double *mu_out, double *time_out, int32_t *fills_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpmc.so")
 
-SOURCES = ["pmc_host.cpp", "pmc_tables.cpp", "pmc_kernels.hip", "pmc_accumulate.hip"]
+SOURCES = ["pmc_host.cpp", "pmc_tables.cpp", "pmc_kernels.hip", "pmc_accumulate.hip", "pmc_delivery.hip"]
 
 # -ffp-contract=off: no implicit FMA, so every kernel that inlines the step
 # evaluates it with the same operations (bit-identical tallies across

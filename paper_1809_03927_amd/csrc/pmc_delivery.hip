@@ -1,0 +1,175 @@
+// Beam-delivery simulation (Sec. 2.B, App. A): which part of each spot's MU
+// is delivered in which breathing phase.  One thread walks the timeline of
+// one (trial, field): breathing phases of N(mu, sigma) / N, synchrotron fills
+// (layer switch, wait for the gate, discarded beam), spills and spot switches,
+// refills on charge or extraction time, isolayered repainting.  Every random
+// number is a Philox word keyed by (seed, trial) at counter (field, purpose,
+// index, block); a Gaussian is the sum of 12 uniforms minus 6, exact in FP64,
+// so with the FP64 operations below the result is reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "pmc_device.hpp"
+
+namespace pmc {
+
+namespace {
+
+enum : uint32_t { kPStart = 0, kPSync = 1, kPBreath = 2, kPPeriod = 3 };
+enum { kSwitch = 0, kSwitchPerMev, kDiscard, kRate, kRatePerMev, kSpotSwitch, kSpotSwitchPerMm, kCapacity,
+       kExtractionMax };
+constexpr long long kMaxAdvances = 1LL << 30;  // breathing phases per thread before giving up
+
+__device__ double gauss(uint32_t k0, uint32_t k1, uint32_t field, uint32_t purpose, uint32_t index) {
+  double total = 0.0;
+  for (uint32_t b = 0; b < 3; ++b) {
+    const uint4 x = philox(field, purpose, index, b, k0, k1);
+    total = total + (double)x.x * 0x1p-32;
+    total = total + (double)x.y * 0x1p-32;
+    total = total + (double)x.z * 0x1p-32;
+    total = total + (double)x.w * 0x1p-32;
+  }
+  return total - 6.0;
+}
+
+__device__ __forceinline__ int draw_int(uint32_t k0, uint32_t k1, uint32_t field, uint32_t purpose, uint32_t n) {
+  const uint4 x = philox(field, purpose, 0u, 0u, k0, k1);
+  return (int)(((unsigned long long)x.x * n) >> 32);
+}
+
+// The breathing timeline of one (trial, field): occurrence k of a phase is
+// phase (phi0 + k) mod N and lasts max(mu + sigma z_k, mu / 20) / N.
+struct Breathing {
+  uint32_t k0, k1, field;
+  int n, phi0, gate_lo, gate_hi;
+  double mu, sd;
+  long long k, advances;
+  double t0, t1;
+
+  __device__ double length(long long kk) const {
+    double p = mu + sd * gauss(k0, k1, field, kPBreath, (uint32_t)kk);
+    if (p < mu / 20.0) p = mu / 20.0;
+    return p / (double)n;
+  }
+  __device__ int phase(double t) {
+    while (t >= t1 && advances < kMaxAdvances) {
+      ++k;
+      ++advances;
+      t0 = t1;
+      t1 = t0 + length(k);
+    }
+    return (int)((phi0 + k) % n);
+  }
+  __device__ bool open(int ph) const { return gate_lo < 0 || (gate_lo <= ph && ph <= gate_hi); }
+  // the first time >= t at which the gate is open
+  __device__ double wait_gate(double t) {
+    int ph = phase(t);
+    while (!open(ph) && advances < kMaxAdvances) {
+      t = t1;
+      ph = phase(t);
+    }
+    return t;
+  }
+};
+
+__global__ void __launch_bounds__(64) delivery_sim(DeliveryLaunch a) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long long)a.n_trials * a.n_fields) return;
+  const int trial = (int)(gid / a.n_fields), field = (int)(gid % a.n_fields);
+  const int s0 = a.fstart[field], s1 = a.fstart[field + 1];
+  const uint32_t k0 = a.seed, k1 = (uint32_t)trial;
+  double par[kSyncParams];
+  for (int i = 0; i < kSyncParams; ++i) {
+    const double v = a.central[i] + a.sd[i] * gauss(k0, k1, (uint32_t)field, kPSync, (uint32_t)i);
+    par[i] = v > 0.0 ? v : 0.0;
+  }
+  Breathing br;
+  br.k0 = k0;
+  br.k1 = k1;
+  br.field = (uint32_t)field;
+  br.n = a.n_phases;
+  br.phi0 = a.start_phase >= 0 ? a.start_phase : draw_int(k0, k1, (uint32_t)field, kPStart, (uint32_t)a.n_phases);
+  br.gate_lo = a.gate_lo;
+  br.gate_hi = a.gate_hi;
+  br.mu = (a.period_min > 0 && a.period_min <= a.period_max)
+              ? (double)(a.period_min + draw_int(k0, k1, (uint32_t)field, kPPeriod,
+                                                 (uint32_t)(a.period_max - a.period_min + 1)))
+              : a.period_s;
+  br.sd = a.period_sd_s;
+  br.k = 0;
+  br.advances = 0;
+  br.t0 = 0.0;
+  br.t1 = br.length(0);
+  const bool gated = a.gate_lo >= 0;
+  double t = 0.0;
+  int fills = 0;
+  int i = s0;
+  while (i < s1) {
+    // a layer: consecutive spots of one energy
+    const double e = a.spots[i].e;
+    int j = i + 1;
+    while (j < s1 && a.spots[j].e == e) ++j;
+    const double sw = par[kSwitch] + par[kSwitchPerMev] * (e - 70.0);
+    const double rate = par[kRate] + par[kRatePerMev] * (e - 70.0);
+    t = t + sw;
+    t = br.wait_gate(t) + par[kDiscard];
+    double t_ext = t;
+    double q = par[kCapacity];
+    ++fills;
+    bool fresh = true, have_prev = false;
+    double px = 0.0, py = 0.0;
+    for (int r = 0;; ++r) {
+      bool any = false;
+      for (int s = i; s < j; ++s) {
+        const DeliverySpot sp = a.spots[s];
+        double m;
+        if (a.max_mu > 0.0) {
+          m = sp.mu - (double)r * a.max_mu;
+          if (m > a.max_mu) m = a.max_mu;
+        } else {
+          m = r == 0 ? sp.mu : 0.0;
+        }
+        if (m <= 0.0) continue;
+        any = true;
+        if (have_prev) {
+          const double dx = fabs(sp.x - px), dy = fabs(sp.y - py);
+          t = t + (par[kSpotSwitch] + par[kSpotSwitchPerMm] * (dx > dy ? dx : dy));
+        }
+        const double spill = m / rate;
+        if (!fresh && (m > q || (t - t_ext) + spill > par[kExtractionMax])) {
+          t = t + sw;
+          t = br.wait_gate(t) + par[kDiscard];
+          t_ext = t;
+          q = par[kCapacity];
+          ++fills;
+        }
+        if (gated && !br.open(br.phase(t))) t = br.wait_gate(t) + par[kDiscard];
+        const int ph = br.phase(t);
+        double *cell = a.mu + ((long long)trial * a.n_spots + a.index[s]) * a.n_phases + ph;
+        *cell = *cell + m;
+        t = t + spill;
+        q = q - m;
+        fresh = false;
+        have_prev = true;
+        px = sp.x;
+        py = sp.y;
+      }
+      if (!any || br.advances >= kMaxAdvances) break;
+    }
+    if (br.advances >= kMaxAdvances) break;
+    i = j;
+  }
+  if (br.advances >= kMaxAdvances) a.status[0] = 1;
+  a.time[gid] = t;
+  a.fills[gid] = fills;
+}
+
+}  // namespace
+
+hipError_t launch_delivery(const DeliveryLaunch &a, hipStream_t st) {
+  const long long n = (long long)a.n_trials * a.n_fields;
+  const unsigned blocks = (unsigned)((n + 63) / 64);
+  hipLaunchKernelGGL(delivery_sim, dim3(blocks), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace pmc

@@ -2543,3 +2543,144 @@ int pmc_accumulate_dim(pmc_context *ctx, int32_t ref_phase, const int64_t *ref_t
   return accumulate_host(ctx, kDim, ref_phase, ref_tally, n_src, src_phases, src_dvfs, src_tallies, n_sub,
                          n_histories, dose_out, mask_out);
 }
+
+// ---------------------------------------------------------------------------
+// beam-delivery simulation (Sec. 2.B, App. A)
+// ---------------------------------------------------------------------------
+
+int pmc_delivery_simulate(pmc_context *ctx, const pmc_delivery *d, const pmc_spot *spots, int64_t n_spots,
+                          int32_t n_fields, double *mu_out, double *time_out, int32_t *fills_out) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (!d || (!spots && n_spots > 0)) return fail(ctx, PMC_E_INVAL, "NULL delivery options or spots");
+  if (d->n_phases < 1 || d->n_phases > 64) return fail(ctx, PMC_E_INVAL, "n_phases must be 1..64");
+  if (d->start_phase < -1 || d->start_phase >= d->n_phases)
+    return fail(ctx, PMC_E_INVAL, "start_phase must be -1 or 0..n_phases-1");
+  const bool random_period = d->period_min_s > 0 && d->period_min_s <= d->period_max_s;
+  if (d->period_min_s < 0 || d->period_max_s < 0 || d->period_max_s > 3600)
+    return fail(ctx, PMC_E_INVAL, "period_min_s/period_max_s must be 0..3600");
+  if (!random_period && !(std::isfinite(d->period_s) && d->period_s > 0.0))
+    return fail(ctx, PMC_E_INVAL, "period_s must be finite and > 0");
+  if (!(std::isfinite(d->period_sd_s) && d->period_sd_s >= 0.0))
+    return fail(ctx, PMC_E_INVAL, "period_sd_s must be finite and >= 0");
+  if (d->gate_lo != -1 && !(d->gate_lo >= 0 && d->gate_lo <= d->gate_hi && d->gate_hi < d->n_phases))
+    return fail(ctx, PMC_E_INVAL, "gate must be -1 or 0 <= gate_lo <= gate_hi < n_phases");
+  if (!(std::isfinite(d->max_mu) && d->max_mu >= 0.0)) return fail(ctx, PMC_E_INVAL, "max_mu must be >= 0");
+  if (d->n_trials < 1 || n_fields < 1 || n_spots < 0 || n_spots > (1LL << 31))
+    return fail(ctx, PMC_E_INVAL, "need n_trials >= 1, n_fields >= 1 and 0..2^31 spots");
+  const pmc_param *par = &d->sync.layer_switch_s;
+  for (int i = 0; i < pmc::kSyncParams; ++i)
+    if (!(std::isfinite(par[i].central) && std::isfinite(par[i].sd) && par[i].sd >= 0.0))
+      return fail(ctx, PMC_E_INVAL, "synchrotron parameter %d must be finite with sd >= 0", i);
+  const double out_bytes = (double)d->n_trials * (double)n_spots * (double)d->n_phases * 8.0;
+  if (out_bytes > 64e9) return fail(ctx, PMC_E_INVAL, "trials x spots x phases too large");
+  // spots grouped by field, plan order kept within a field; spill rates
+  // positive for any draw within +-6 sigma (a 12-uniform Gaussian never leaves it)
+  std::vector<int32_t> fstart((size_t)n_fields + 1, 0);
+  for (int64_t i = 0; i < n_spots; ++i) {
+    const pmc_spot &sp = spots[i];
+    if (sp.field < 0 || sp.field >= n_fields) return fail(ctx, PMC_E_INVAL, "spot %lld: bad field", (long long)i);
+    if (!(std::isfinite(sp.energy_MeV) && sp.energy_MeV >= 1.0 && sp.energy_MeV <= 300.0) ||
+        !std::isfinite(sp.x_mm) || !std::isfinite(sp.y_mm) || !(std::isfinite(sp.weight) && sp.weight > 0.0))
+      return fail(ctx, PMC_E_INVAL, "spot %lld: energy 1..300 MeV, finite position, MU > 0", (long long)i);
+    const double de = sp.energy_MeV - 70.0;
+    const double c = par[3].central - 6.0 * par[3].sd;
+    const double s_lo = (par[4].central - 6.0 * par[4].sd) * de, s_hi = (par[4].central + 6.0 * par[4].sd) * de;
+    if (!(c + std::min(s_lo, s_hi) > 0.0))
+      return fail(ctx, PMC_E_INVAL, "spill rate can reach <= 0 at %g MeV", sp.energy_MeV);
+    ++fstart[(size_t)sp.field + 1];
+  }
+  for (int32_t f = 0; f < n_fields; ++f) fstart[(size_t)f + 1] += fstart[(size_t)f];
+  std::vector<pmc::DeliverySpot> grouped((size_t)n_spots);
+  std::vector<int64_t> index((size_t)n_spots);
+  {
+    std::vector<int32_t> fill(fstart.begin(), fstart.end() - 1);
+    for (int64_t i = 0; i < n_spots; ++i) {
+      const pmc_spot &sp = spots[i];
+      const int32_t at = fill[(size_t)sp.field]++;
+      grouped[(size_t)at] = {sp.energy_MeV, sp.x_mm, sp.y_mm, sp.weight};
+      index[(size_t)at] = i;
+    }
+  }
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  const size_t n_tf = (size_t)d->n_trials * (size_t)n_fields;
+  const size_t mu_bytes = (size_t)out_bytes;
+  struct Block { void *p = nullptr; size_t cap = 0; };
+  std::vector<Block> blocks;
+  auto cleanup = [&](int code) {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &b : blocks) pool_put(ctx, b.p, b.cap);
+    return code;
+  };
+  auto get = [&](size_t bytes, void **p) -> int {
+    Block b;
+    int r = pool_get(ctx, std::max<size_t>(bytes, 256), &b.p, &b.cap, "delivery simulation");
+    if (r) return r;
+    blocks.push_back(b);
+    *p = b.p;
+    return PMC_OK;
+  };
+  void *d_spots = nullptr, *d_fstart = nullptr, *d_index = nullptr, *d_mu = nullptr, *d_time = nullptr,
+       *d_fills = nullptr, *d_status = nullptr;
+  int rc = get(sizeof(pmc::DeliverySpot) * grouped.size(), &d_spots);
+  if (!rc) rc = get(sizeof(int32_t) * fstart.size(), &d_fstart);
+  if (!rc) rc = get(sizeof(int64_t) * index.size(), &d_index);
+  if (!rc) rc = get(mu_bytes, &d_mu);
+  if (!rc) rc = get(sizeof(double) * n_tf, &d_time);
+  if (!rc) rc = get(sizeof(int32_t) * n_tf, &d_fills);
+  if (!rc) rc = get(sizeof(int32_t), &d_status);
+  if (rc) return cleanup(rc);
+  hipError_t e = hipSuccess;
+  if (n_spots > 0) e = copy_sync(ctx, d_spots, grouped.data(), sizeof(pmc::DeliverySpot) * grouped.size(),
+                                 hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = copy_sync(ctx, d_fstart, fstart.data(), sizeof(int32_t) * fstart.size(),
+                                     hipMemcpyHostToDevice);
+  if (e == hipSuccess && n_spots > 0)
+    e = copy_sync(ctx, d_index, index.data(), sizeof(int64_t) * index.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "upload delivery inputs"));
+  if (mu_bytes >= 8)
+    HIP_TRY(ctx, pmc::launch_fill_u64(static_cast<unsigned long long *>(d_mu), (long long)(mu_bytes / 8), 0ull,
+                                      ctx->stream), "zero MU");
+  {
+    const int32_t zero = 0;
+    e = copy_sync(ctx, d_status, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "status"));
+  }
+  pmc::DeliveryLaunch a = {};
+  a.spots = static_cast<const pmc::DeliverySpot *>(d_spots);
+  a.fstart = static_cast<const int32_t *>(d_fstart);
+  a.index = static_cast<const int64_t *>(d_index);
+  a.n_spots = n_spots;
+  a.n_fields = n_fields;
+  a.n_trials = d->n_trials;
+  a.n_phases = d->n_phases;
+  a.start_phase = d->start_phase;
+  a.period_min = random_period ? d->period_min_s : 0;
+  a.period_max = random_period ? d->period_max_s : 0;
+  a.gate_lo = d->gate_lo;
+  a.gate_hi = d->gate_hi;
+  a.period_s = d->period_s;
+  a.period_sd_s = d->period_sd_s;
+  a.max_mu = d->max_mu;
+  for (int i = 0; i < pmc::kSyncParams; ++i) {
+    a.central[i] = par[i].central;
+    a.sd[i] = par[i].sd;
+  }
+  a.seed = (uint32_t)(d->seed & 0xFFFFFFFFull);
+  a.mu = static_cast<double *>(d_mu);
+  a.time = static_cast<double *>(d_time);
+  a.fills = static_cast<int32_t *>(d_fills);
+  a.status = static_cast<int32_t *>(d_status);
+  e = pmc::launch_delivery(a, ctx->stream);
+  if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "delivery_sim launch"));
+  int32_t status = 0;
+  e = copy_sync(ctx, &status, d_status, sizeof(status), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && mu_out && mu_bytes) e = copy_sync(ctx, mu_out, d_mu, mu_bytes, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && time_out) e = copy_sync(ctx, time_out, d_time, sizeof(double) * n_tf, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && fills_out)
+    e = copy_sync(ctx, fills_out, d_fills, sizeof(int32_t) * n_tf, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "download delivery results"));
+  if (status) return cleanup(fail(ctx, PMC_E_INVAL, "a delivery timeline exceeded 2^30 breathing phases"));
+  return cleanup(PMC_OK);
+}

@@ -223,6 +223,27 @@ struct DimPull {
   double *dose;
 };
 
+// Beam-delivery simulation (Sec. 2.B, App. A): one thread per (trial, field).
+constexpr int kSyncParams = 9;
+struct DeliverySpot {
+  double e, x, y, mu;        // energy (MeV), BEV position (mm), MU
+};
+struct DeliveryLaunch {
+  const DeliverySpot *spots; // grouped by field, plan order within a field
+  const int32_t *fstart;     // n_fields + 1 offsets into spots
+  const int64_t *index;      // plan index of each grouped spot
+  int64_t n_spots;
+  int32_t n_fields, n_trials, n_phases, start_phase, period_min, period_max, gate_lo, gate_hi;
+  double period_s, period_sd_s, max_mu;
+  double central[kSyncParams], sd[kSyncParams];
+  uint32_t seed;
+  double *mu;                // [trial][plan spot][phase], zeroed by the caller
+  double *time;              // [trial][field], s
+  int32_t *fills;            // [trial][field]
+  int32_t *status;           // 1 if a thread stopped at its iteration cap
+};
+hipError_t launch_delivery(const DeliveryLaunch &a, hipStream_t st);
+
 hipError_t launch_emtm_push(const EmtmPush &a, hipStream_t st);
 hipError_t launch_dim_pull(const DimPull &a, hipStream_t st);
 // Eqs. (8), (7) at every grid point; outputs nullable (device memory)

@@ -38,7 +38,7 @@ EXPORTS = ["pmc_create", "pmc_destroy", "pmc_last_error", "pmc_load_phase", "pmc
            "pmc_graph_create", "pmc_graph_launch", "pmc_graph_destroy", "pmc_influence_boxes",
            "pmc_influence", "pmc_influence_read", "pmc_influence_device", "pmc_influence_free",
            "pmc_load_dvf", "pmc_unload_dvf", "pmc_dvf_points", "pmc_accumulate", "pmc_accumulate_device",
-           "pmc_accumulate_dim", "pmc_accumulate_dim_device"]
+           "pmc_accumulate_dim", "pmc_accumulate_dim_device", "pmc_delivery_simulate"]
 
 
 class pmc_config(C.Structure):
@@ -50,6 +50,23 @@ class pmc_dvf(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("start_mm", C.c_double * 3), ("spacing_mm", C.c_double * 3),
                 ("row", C.c_double * 3), ("col", C.c_double * 3), ("delta_mm", C.c_void_p),
                 ("pre", C.c_void_p), ("post", C.c_void_p)]
+
+
+class pmc_param(C.Structure):
+    _fields_ = [("central", C.c_double), ("sd", C.c_double)]
+
+
+class pmc_synchrotron(C.Structure):
+    _fields_ = [(name, pmc_param) for name in (
+        "layer_switch_s", "layer_switch_per_mev", "discard_s", "spill_rate_mu_s", "spill_rate_per_mev",
+        "spot_switch_s", "spot_switch_per_mm", "capacity_mu", "extraction_max_s")]
+
+
+class pmc_delivery(C.Structure):
+    _fields_ = [("n_phases", C.c_int32), ("start_phase", C.c_int32), ("period_s", C.c_double),
+                ("period_sd_s", C.c_double), ("period_min_s", C.c_int32), ("period_max_s", C.c_int32),
+                ("gate_lo", C.c_int32), ("gate_hi", C.c_int32), ("max_mu", C.c_double),
+                ("sync", pmc_synchrotron), ("seed", C.c_uint64), ("n_trials", C.c_int32)]
 
 
 class pmc_shape(C.Structure):
@@ -131,6 +148,7 @@ def lib():
         L.pmc_load_dvf.argtypes = [vp, i32, C.POINTER(pmc_dvf)]
         L.pmc_unload_dvf.argtypes = [vp, i32]
         L.pmc_dvf_points.argtypes = [vp, i32, vp, vp]
+        L.pmc_delivery_simulate.argtypes = [vp, C.POINTER(pmc_delivery), vp, i64, i32, vp, vp, vp]
         L.pmc_accumulate.argtypes = [vp, i32, vp, i32, vp, vp, vp, i32, u64, vp, vp]
         L.pmc_accumulate_device.argtypes = [vp, i32, vp, i32, vp, vp, vp, i32, u64, vp, vp, vp]
         L.pmc_accumulate_dim.argtypes = [vp, i32, vp, i32, vp, vp, vp, i32, u64, vp, vp]
@@ -412,6 +430,24 @@ def pmc_accumulate_dim_device(ctx, ref_phase: int, ref_tally: int, src_phases: S
                                        _ptr(dv), tp, n_sub, n_histories, C.c_void_p(stream),
                                        C.c_void_p(dev_dose), None if dev_mask is None else C.c_void_p(dev_mask)),
            ctx)
+
+
+def pmc_delivery_simulate(ctx, d, spots: np.ndarray, n_fields: int) -> dict:
+    """d: a workloads.Delivery; spots: SPOT_DTYPE array (weight = MU, field)
+    in delivery order.  Returns {"mu": (n_trials, n_spots, N), "time":
+    (n_trials, n_fields), "fills": (n_trials, n_fields)}."""
+    sp = np.ascontiguousarray(spots)
+    if sp.dtype != SPOT_DTYPE:
+        raise ValueError("spots must use the pmc_spot layout")
+    sync = pmc_synchrotron(*[pmc_param(*d.sync[f[0]]) for f in pmc_synchrotron._fields_])
+    c = pmc_delivery(d.n_phases, d.start_phase, d.period_s, d.period_sd_s, d.period_min_s, d.period_max_s,
+                     d.gate_lo, d.gate_hi, d.max_mu, sync, d.seed, d.n_trials)
+    mu = np.zeros((d.n_trials, len(sp), d.n_phases), dtype=np.float64)
+    t = np.zeros((d.n_trials, n_fields), dtype=np.float64)
+    fills = np.zeros((d.n_trials, n_fields), dtype=np.int32)
+    _check(lib().pmc_delivery_simulate(ctx, C.byref(c), _ptr(sp), len(sp), n_fields, _ptr(mu), _ptr(t),
+                                       _ptr(fills)), ctx)
+    return {"mu": mu, "time": t, "fills": fills}
 
 
 def pmc_launch_shape(ctx, req: Request) -> dict:

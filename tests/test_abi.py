@@ -320,3 +320,40 @@ def test_dvf_and_accumulation_validation(P):
             P.pmc_unload_dvf(ctx, 4)
     finally:
         P.pmc_destroy(ctx)
+
+
+def test_delivery_validation(P):
+    """Invalid delivery options or spots are rejected before any device work;
+    valid ones reach the device check of a validation-only context."""
+    ctx = P.pmc_create(device=-1)
+    try:
+        plan = W.plan_thorax(3, n_phases=10)
+        sp = plan.spots.copy()
+        sp["weight"] = sp["weight"] / sp["weight"].sum() * 300.0
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_delivery_simulate(ctx, W.Delivery(n_trials=2), sp, len(plan.fields))
+        assert e.value.code == P.PMC_E_DEVICE
+        for bad in (dict(n_phases=0), dict(n_phases=65), dict(start_phase=10), dict(gate_lo=3, gate_hi=2),
+                    dict(gate_lo=0, gate_hi=10), dict(max_mu=-1.0), dict(n_trials=0), dict(period_s=0.0),
+                    dict(period_sd_s=-1.0), dict(period_min_s=-1)):
+            with pytest.raises(P.PmcError) as e:
+                P.pmc_delivery_simulate(ctx, W.Delivery(**bad), sp, 1)
+            assert e.value.code == P.PMC_E_INVAL, bad
+        # a spill rate that a draw within 6 sigma could make non-positive
+        sync = dict(W.SYNC_DEFAULT)
+        sync["spill_rate_mu_s"] = (1.0, 0.5)
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_delivery_simulate(ctx, W.Delivery(sync=sync), sp, 1)
+        assert e.value.code == P.PMC_E_INVAL
+        bad_sp = sp.copy()
+        bad_sp["field"][5] = 3
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_delivery_simulate(ctx, W.Delivery(), bad_sp, 1)
+        assert e.value.code == P.PMC_E_INVAL
+        bad_sp = sp.copy()
+        bad_sp["weight"][0] = 0.0
+        with pytest.raises(P.PmcError) as e:
+            P.pmc_delivery_simulate(ctx, W.Delivery(), bad_sp, 1)
+        assert e.value.code == P.PMC_E_INVAL
+    finally:
+        P.pmc_destroy(ctx)
