@@ -101,6 +101,7 @@ def parse():
     p.add_argument("--no-atomic-probe", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-accumulation", action="store_true")
+    p.add_argument("--no-delivery", action="store_true")
     p.add_argument("--acc-cpu-seconds", type=float, default=10.0)
     p.add_argument("--latency-requests", type=int, default=200,
                    help="served-stream requests for the p50/p99 latency comparison (0 = skip)")
@@ -255,6 +256,10 @@ def main():
     _, spans_k = timed(transport_only, max(2, min(a.steps, 3)), 0)
     kern_ms = float(np.mean(spans_k))
 
+    delivery = None
+    if not a.no_delivery:
+        delivery = delivery_bench(eng, None if a.no_cpu_baseline else 2)
+
     accumulation = None
     if not a.no_accumulation:
         accumulation = accumulation_bench(eng, wl, tal_b, stream, timed, max(2, min(a.steps, 5)),
@@ -352,6 +357,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accumulation": accumulation,
+        "delivery": delivery,
     }
     print(json.dumps(out))
 
@@ -384,6 +390,86 @@ def atomic_probe(torch, nvox, n=200_000_000):
     e1.record()
     torch.cuda.synchronize()
     return n / (e0.elapsed_time(e1) * 1e-3)
+
+
+DELIVERY_TRIALS = 25
+DELIVERY_SCENARIOS = {
+    "free": {},
+    "gated": {"gate_lo": 3, "gate_hi": 7},        # CT30-CT70, 50 % duty cycle
+    "repainted": {"max_mu": 0.005},               # isolayered, 0.005 MU per delivery
+}
+
+
+def delivery_bench(eng, cpu_trials):
+    """The paper's delivery-uncertainty study (Sec. 2.B): 25 trials of the
+    3-field robust plan with random start phase, breathing period U{3..7} s
+    (sigma 0.4 s) and synchrotron uncertainty, free-breathing, gated and
+    repainted; each call simulates all trials and fields (one GPU thread per
+    trial and field) and returns the MU per spot and phase.  Timed as whole
+    calls (inputs and outputs in host memory).  Then the oracle replays the
+    first trials of the repainted scenario, timed, and must match the GPU bit
+    for bit."""
+    import numpy as np
+    from paper_1809_03927_amd import pmc
+    from paper_1809_03927_amd import workloads as W
+    plan = W.plan_robust()
+    sp = plan.spots.copy()
+    sp["weight"] = sp["weight"] / sp["weight"].sum() * 600.0  # 600 MU over the three fields
+    n_f = len(plan.fields)
+    out = {"workload": f"robust plan: {n_f} fields, {len(sp)} spots, 600 MU; {DELIVERY_TRIALS} trials "
+                       "(start phase U{0..9}, period U{3..7} s with sigma 0.4 s, synchrotron uncertainty); "
+                       "synthetic synchrotron timing",
+           "unit": "spot deliveries simulated/s", "scenarios": {}}
+    results = {}
+    for name, kw in DELIVERY_SCENARIOS.items():
+        d = W.Delivery(n_trials=DELIVERY_TRIALS, period_sd_s=0.4, period_min_s=3, period_max_s=7, seed=17, **kw)
+        pmc.pmc_delivery_simulate(eng.ctx, d, sp, n_f)  # warm-up
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = pmc.pmc_delivery_simulate(eng.ctx, d, sp, n_f)
+        sec = (time.perf_counter() - t0) / reps
+        n_del = int(np.count_nonzero(res["mu"]))  # (spot, phase) cells reached; deliveries below
+        if d.max_mu > 0:
+            pieces = np.ceil(sp["weight"] / d.max_mu)
+            deliveries = float(pieces.sum()) * DELIVERY_TRIALS
+        else:
+            deliveries = float(len(sp)) * DELIVERY_TRIALS
+        results[name] = (d, res)
+        out["scenarios"][name] = {
+            "ms_per_call": sec * 1e3, "deliveries": deliveries, "value": deliveries / sec,
+            "delivery_time_s_mean": float(res["time"].mean()), "fills_mean": float(res["fills"].mean()),
+            "phase_cells_with_mu": n_del}
+        log(f"delivery {name}: {sec * 1e3:.1f} ms per call of {DELIVERY_TRIALS} trials x {n_f} fields "
+            f"({deliveries:.3g} deliveries), mean delivery time {res['time'].mean():.0f} s")
+    rp = out["scenarios"]["repainted"]
+    out["value"] = rp["value"]
+    out["ms_per_call"] = rp["ms_per_call"]
+    out["roofline"] = {
+        "bound": "latency",
+        "note": "each (trial, field) timeline is serial: 75 threads, one dependent FP64 chain each; "
+                "the figure is deliveries per second per timeline",
+        "achieved": rp["value"] / (DELIVERY_TRIALS * n_f), "unit": "deliveries/s per timeline",
+        "peak": None, "frac": None, "traffic": None}
+    if cpu_trials:
+        import oracle.delivery as DL
+        d, res = results["repainted"]
+        d1 = W.Delivery(**{**d.__dict__, "n_trials": cpu_trials})
+        t0 = time.perf_counter()
+        want = DL.simulate(sp, n_f, d1)
+        dt = time.perf_counter() - t0
+        deliveries = float(np.ceil(sp["weight"] / d.max_mu).sum()) * cpu_trials
+        same = bool(np.array_equal(want["mu"], res["mu"][:cpu_trials])
+                    and np.array_equal(want["time"], res["time"][:cpu_trials])
+                    and np.array_equal(want["fills"], res["fills"][:cpu_trials]))
+        out["cpu_baseline"] = {"value": deliveries / dt, "unit": "spot deliveries simulated/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the first {cpu_trials} trials of the repainted scenario "
+                                         f"({deliveries:.3g} deliveries) in {dt:.1f} s, pure Python",
+                               "accuracy": {"check": "GPU vs oracle: MU per spot and phase, end times and fills "
+                                                     "bit-identical", "passed": same}}
+        log(f"delivery oracle: {cpu_trials} trials in {dt:.1f} s; identical {same}")
+    return out
 
 
 def mapped_subvoxels(ph, dvf, n, with_mass=True):

@@ -2672,6 +2672,19 @@ int pmc_delivery_simulate(pmc_context *ctx, const pmc_delivery *d, const pmc_spo
   a.time = static_cast<double *>(d_time);
   a.fills = static_cast<int32_t *>(d_fills);
   a.status = static_cast<int32_t *>(d_status);
+  // longest layer, staged in LDS when it fits 64 KiB with its MU sums
+  {
+    int32_t longest = 0;
+    for (int32_t f = 0; f < n_fields; ++f)
+      for (int32_t i = fstart[(size_t)f]; i < fstart[(size_t)f + 1];) {
+        int32_t j = i + 1;
+        while (j < fstart[(size_t)f + 1] && grouped[(size_t)j].e == grouped[(size_t)i].e) ++j;
+        longest = std::max(longest, j - i);
+        i = j;
+      }
+    const int32_t per = (int32_t)(sizeof(pmc::DeliverySpot) + sizeof(double) * (size_t)d->n_phases);
+    a.layer_cap = std::min<int32_t>(longest, 65536 / per);
+  }
   e = pmc::launch_delivery(a, ctx->stream);
   if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "delivery_sim launch"));
   int32_t status = 0;

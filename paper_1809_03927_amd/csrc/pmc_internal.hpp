@@ -241,6 +241,7 @@ struct DeliveryLaunch {
   double *time;              // [trial][field], s
   int32_t *fills;            // [trial][field]
   int32_t *status;           // 1 if a thread stopped at its iteration cap
+  int32_t layer_cap;         // layers of at most this many spots are staged in LDS
 };
 hipError_t launch_delivery(const DeliveryLaunch &a, hipStream_t st);
 
