@@ -108,7 +108,8 @@ def parse():
     p.add_argument("--latency-requests", type=int, default=200,
                    help="served-stream requests for the p50/p99 latency comparison (0 = skip)")
     p.add_argument("--latency-load", type=float, default=0.8)
-    p.add_argument("--mode", choices=["bench", "single-history", "copy-calibration"], default="bench")
+    p.add_argument("--mode", choices=["bench", "single-history", "copy-calibration", "accumulation-scan"],
+                   default="bench")
     return p.parse_args()
 
 
@@ -174,6 +175,10 @@ def main():
         torch.cuda.synchronize()
         c = counters.cpu().numpy()
         print(json.dumps({"mode": "single-history", "steps_per_launch": int(c[7]), "launches": 20}))
+        return
+
+    if a.mode == "accumulation-scan":
+        accumulation_scan(eng, wl, tallies, counters, stream, torch)
         return
 
     # ---- launch shape ----------------------------------------------------
@@ -396,6 +401,64 @@ def atomic_probe(torch, nvox, n=200_000_000):
     e1.record()
     torch.cuda.synchronize()
     return n / (e0.elapsed_time(e1) * 1e-3)
+
+
+SCAN_N = (1, 2, 3, 4, 5, 6, 8, 10, 16)
+
+
+def accumulation_scan(eng, wl, tallies, counters, stream, torch):
+    """Accumulation time and tumour dose-volume histograms against the
+    voxel-subdivision scale n for both methods (the studies of the paper's
+    Figs. 3 and 4, on the synthetic thorax): one 4D transport of the
+    workload, then the nine other phases accumulated onto phase 5 with
+    EMTM and DIM for each n; DVHs of the phase-5 tumour compared with n = 16."""
+    import numpy as np
+    from paper_1809_03927_amd import fourd, pmc
+    from paper_1809_03927_amd import workloads as W
+    phases = list(range(len(wl.phases)))
+    req = pmc.Request(wl.n_histories, phases, request_id=wl.request_id, engine=pmc.PMC_ENGINE_PERSISTENT)
+    pmc.pmc_dose_device(eng.ctx, req, stream.cuda_stream, [t.data_ptr() for t in tallies], counters.data_ptr())
+    torch.cuda.synchronize()
+    ref = ACC_REF_PHASE
+    src = [p for p in phases if p != ref]
+    for p in src:
+        pmc.pmc_load_dvf(eng.ctx, 100 + p, W.thorax_dvf(p, ref, n_phases=len(phases)))
+        pmc.pmc_load_dvf(eng.ctx, 300 + p, W.thorax_dvf(ref, p, n_phases=len(phases)))
+    nv = wl.phases[ref].nvox
+    dose = torch.empty(nv, dtype=torch.float64, device="cuda")
+    roi = W.thorax_tumour_mask(tuple(wl.phases[ref].shape_xyz), ref, len(phases)).ravel()
+    out = {"mode": "accumulation-scan", "workload": f"thorax4d ({wl.n_histories:.0e} histories), phases {src} "
+                                                     f"onto phase {ref}; ROI: the phase-{ref} tumour "
+                                                     f"({int(roi.sum())} voxels)", "methods": {}}
+    for method, fn, base in (("emtm", pmc.pmc_accumulate_device, 100), ("dim", pmc.pmc_accumulate_dim_device, 300)):
+        rows, doses = [], {}
+        for n in SCAN_N:
+            def run():
+                fn(eng.ctx, ref, tallies[ref].data_ptr(), src, [base + p for p in src],
+                   [tallies[p].data_ptr() for p in src], n, wl.n_histories, stream.cuda_stream,
+                   dose.data_ptr(), None)
+            run()
+            torch.cuda.synchronize()
+            reps = 2 if n <= 10 else 1
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            doses[n] = dose.cpu().numpy()
+            rows.append({"n": n, "ms": e0.elapsed_time(e1) / reps})
+            log(f"scan {method} n={n}: {rows[-1]['ms']:.2f} ms")
+        top = doses[SCAN_N[-1]][roi]
+        bins = np.linspace(0.0, 1.1 * float(top.max()), 221)
+        dvh_ref = fourd.dvh(doses[SCAN_N[-1]], roi, bins)
+        for r in rows:
+            d = doses[r["n"]][roi]
+            r["dvh_max_diff"] = float(np.max(np.abs(fourd.dvh(doses[r["n"]], roi, bins) - dvh_ref)))
+            r["d95_rel"] = float(np.percentile(d, 5) / np.percentile(top, 5))
+            r["d50_rel"] = float(np.median(d) / np.median(top))
+        out["methods"][method] = rows
+    print(json.dumps(out))
 
 
 def fourd_bench(eng, wl, trials, tally_mode):

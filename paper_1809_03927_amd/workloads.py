@@ -178,6 +178,21 @@ def make_thorax(shape_xyz=(256, 256, 160), phase=0, n_phases=10, period=4.0,
     return Phase(hu, sp, org, CALIB_HU.copy(), CALIB_RHO.copy(), CALIB_RSP.copy())
 
 
+def thorax_tumour_mask(shape_xyz=(256, 256, 160), phase=0, n_phases=10, period=4.0,
+                       extent_mm=THORAX_EXTENT_MM) -> np.ndarray:
+    """Voxels of make_thorax's tumour sphere on that phase (bool, (nz, ny,
+    nx)): the region of interest of the dose-volume histograms."""
+    nx, ny, nz = shape_xyz
+    sp = (extent_mm[0] / nx, extent_mm[1] / ny, extent_mm[2] / nz)
+    org = (-0.5 * extent_mm[0], -0.5 * extent_mm[1], -0.5 * extent_mm[2])
+    x = org[0] + (np.arange(nx) + 0.5) * sp[0]
+    y = org[1] + (np.arange(ny) + 0.5) * sp[1]
+    z = org[2] + (np.arange(nz) + 0.5) * sp[2]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    d = breathing_shift_mm(period * phase / n_phases, period=period)
+    return (X + 80.0) ** 2 + (Y - 20.0) ** 2 + (Z - (-10.0 + d)) ** 2 <= 20.0 * 20.0
+
+
 @dataclasses.dataclass
 class Dvf:
     """A deformation vector field as a DICOM deformable registration stores
