@@ -2566,8 +2566,10 @@ int pmc_delivery_simulate(pmc_context *ctx, const pmc_delivery *d, const pmc_spo
   if (d->gate_lo != -1 && !(d->gate_lo >= 0 && d->gate_lo <= d->gate_hi && d->gate_hi < d->n_phases))
     return fail(ctx, PMC_E_INVAL, "gate must be -1 or 0 <= gate_lo <= gate_hi < n_phases");
   if (!(std::isfinite(d->max_mu) && d->max_mu >= 0.0)) return fail(ctx, PMC_E_INVAL, "max_mu must be >= 0");
-  if (d->n_trials < 1 || n_fields < 1 || n_spots < 0 || n_spots > (1LL << 31))
-    return fail(ctx, PMC_E_INVAL, "need n_trials >= 1, n_fields >= 1 and 0..2^31 spots");
+  if (d->n_trials < 1 || n_fields < 1 || n_spots < 0 || n_spots >= (1LL << 31))
+    return fail(ctx, PMC_E_INVAL, "need n_trials >= 1, n_fields >= 1 and 0..2^31-1 spots");
+  if ((long long)d->n_trials * n_fields >= (1LL << 31))
+    return fail(ctx, PMC_E_INVAL, "n_trials x n_fields must be below 2^31");
   const pmc_param *par = &d->sync.layer_switch_s;
   for (int i = 0; i < pmc::kSyncParams; ++i)
     if (!(std::isfinite(par[i].central) && std::isfinite(par[i].sd) && par[i].sd >= 0.0))

@@ -96,3 +96,30 @@ def test_three_fields(P, DL):
     say("delivery three fields")
     got = run(P, d, sp, len(plan.fields))
     same(got, DL.simulate(sp, len(plan.fields), d))
+
+
+def test_degenerate_deliveries(P, DL):
+    """A field without spots, a single breathing phase, a gate open on every
+    phase (the same as free breathing), max_MU above every spot's MU (the
+    same as no repainting), and an empty plan."""
+    plan = W.plan_thorax(3, n_phases=10)
+    sp = plan.spots.copy()[:400]
+    sp["weight"] = sp["weight"] / sp["weight"].sum() * 40.0
+    base = dict(n_trials=3, period_sd_s=0.3, seed=4)
+    say("delivery: empty second field")
+    got = run(P, W.Delivery(**base), sp, 2)
+    want = DL.simulate(sp, 2, W.Delivery(**base))
+    same(got, want)
+    assert not got["time"][:, 1].any() and not got["fills"][:, 1].any()
+    say("delivery: one phase")
+    one = run(P, W.Delivery(n_phases=1, **base), sp, 1)
+    assert np.array_equal(one["mu"][:, :, 0], np.broadcast_to(sp["weight"], (3, len(sp))))
+    say("delivery: gate on every phase, max MU above every spot")
+    free = run(P, W.Delivery(**base), sp, 1)
+    gated_all = run(P, W.Delivery(gate_lo=0, gate_hi=9, **base), sp, 1)
+    big = run(P, W.Delivery(max_mu=float(sp["weight"].max()) * 2, **base), sp, 1)
+    same(gated_all, free)
+    same(big, free)
+    say("delivery: empty plan")
+    empty = run(P, W.Delivery(**base), sp[:0], 1)
+    assert empty["mu"].shape == (3, 0, 10) and not empty["time"].any()

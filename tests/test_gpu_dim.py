@@ -201,3 +201,59 @@ def test_dim_identity_dvfs_sum_the_phase_doses(P):
         assert np.allclose(dose, want, rtol=1e-12, atol=1e-12 * want.max())
     finally:
         e.close()
+
+
+def test_edge_cases_no_sources_masks_and_many_dvfs(P, E, D, orc):
+    """No sources (the reference dose alone, everything reported); an
+    external mask on a source phase (no mass outside it: nothing pushed,
+    zero dose sampled there); 20 sources, so the report mask takes two
+    passes of at most 16 DVFs; both methods against the oracle."""
+    import dataclasses
+    ph = W.make_box((14, 12, 10), (2.0, 2.0, 2.5), 0)
+    rng = np.random.default_rng(17)
+    ph.hu[...] = rng.integers(-900, 900, size=ph.hu.shape).astype(np.int16)
+    body = np.zeros(ph.hu.shape, dtype=np.uint8)
+    body[:, 2:-2, 3:-3] = 1
+    src_ph = dataclasses.replace(ph, mask=body)
+    t_ref = rng.integers(0, 2**36, size=ph.hu.size)
+    t_src = rng.integers(0, 2**36, size=ph.hu.size)
+    n_src = 20
+    dvfs = []
+    for k in range(n_src):
+        nz, ny, nx = ph.hu.shape
+        sp = np.asarray(ph.spacing_mm)
+        pad = 0.3 * k  # shrinking grids: the mask is their intersection
+        o = np.asarray(ph.origin_mm) + 0.5 * sp + pad
+        n = tuple(int((e - 2 * pad) // s) + 1 for e, s in zip(sp * (np.array([nx, ny, nz]) - 1), sp))
+        dvfs.append(W.Dvf(n, tuple(o), tuple(sp), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0),
+                          rng.uniform(-1.0, 1.0, size=(n[2], n[1], n[0], 3))))
+    ctx = P.pmc_create(0, P.PMC_FP32, 1, 0)
+    try:
+        P.pmc_load_phase(ctx, 0, ph)
+        P.pmc_load_phase(ctx, 1, src_ph)
+        for k, d in enumerate(dvfs):
+            P.pmc_load_dvf(ctx, 40 + k, d)
+        say("edge: no sources")
+        alone, m0 = P.pmc_accumulate(ctx, 0, t_ref, [], [], [], 3, 100, ph.hu.size, want_mask=True)
+        alone_d, m0d = P.pmc_accumulate_dim(ctx, 0, t_ref, [], [], [], 3, 100, ph.hu.size, want_mask=True)
+        say("edge: 20 sources with a masked phase")
+        em, em_mask = P.pmc_accumulate(ctx, 0, t_ref, [1] * n_src, [40 + k for k in range(n_src)], [t_src] * n_src,
+                                       2, 100, ph.hu.size, want_mask=True)
+        dm, dm_mask = P.pmc_accumulate_dim(ctx, 0, t_ref, [1] * n_src, [40 + k for k in range(n_src)],
+                                           [t_src] * n_src, 2, 100, ph.hu.size, want_mask=True)
+    finally:
+        P.pmc_destroy(ctx)
+    rho = densities(orc, [ph, src_ph])
+    v = float(np.prod(np.asarray(ph.spacing_mm) * 0.1))
+    own = E.phase_dose(t_ref, rho[0], v, 100)
+    assert m0.all() and m0d.all()
+    assert np.allclose(alone, own, rtol=1e-12, atol=0) and np.allclose(alone_d, own, rtol=1e-12, atol=0)
+    assert not rho[1][body.ravel() == 0].any()  # the mask removes the mass outside it
+    phases = [ph] + [src_ph] * n_src
+    want_e = E.emtm(phases, [t_ref] + [t_src] * n_src, [rho[0]] + [rho[1]] * n_src, 0, [None] + dvfs, 2, 100)
+    assert np.array_equal(em_mask.astype(bool), want_e["mask"])
+    assert want_e["mask"].any() and not want_e["mask"].all()
+    assert np.allclose(em, want_e["dose"], rtol=1e-9, atol=0)
+    doses = [own] + [E.phase_dose(t_src, rho[1], v, 100)] * n_src
+    want_d = D.dim(phases, doses, 0, [None] + dvfs, 2)
+    compare(dm, want_d["dose"], dm_mask, want_d["mask"])
