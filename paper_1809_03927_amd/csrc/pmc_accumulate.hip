@@ -35,13 +35,14 @@
 // wave-uniform.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "pmc_internal.hpp"
 
 namespace pmc {
 
 namespace {
 
-constexpr int kBlock = 256;
 constexpr int kMaxSub = 16;
 constexpr int kWin = 4;                              // window offsets -1..+2 per axis
 constexpr int kWinCells = kWin * kWin * kWin;
@@ -125,9 +126,10 @@ __device__ __forceinline__ void deposit(const EmtmPush &a, const Deposit &d, int
 }
 
 // This thread's subvoxel counts per reference voxel: word k of the window at
-// w[k * kBlock] holds the counts of window cells k 2^lg .. (k + 1) 2^lg - 1.
+// w[k * stride] holds the counts of window cells k 2^lg .. (k + 1) 2^lg - 1.
 struct Window {
   uint32_t *w;
+  int stride;  // threads of the block: word k of this thread's window at w[k * stride]
   int lg;
   int b[3];
   uint32_t touched;  // words holding counts
@@ -182,7 +184,7 @@ __device__ __forceinline__ void count(const EmtmPush &a, Window &win, const Depo
     const unsigned c = dx + kWin * (dy + kWin * dz);
     const unsigned lg = (unsigned)win.lg;
     win.touched |= 1u << (c >> lg);
-    __hip_atomic_fetch_add(win.w + (c >> lg) * kBlock, 1u << ((c & ((1u << lg) - 1u)) << (5u - lg)),
+    __hip_atomic_fetch_add(win.w + (c >> lg) * win.stride, 1u << ((c & ((1u << lg) - 1u)) << (5u - lg)),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   } else {
     deposit(a, d, t[0] + a.rnx * (t[1] + a.rny * t[2]), 1);
@@ -195,8 +197,8 @@ __device__ __forceinline__ void flush(const EmtmPush &a, Window &win, const Depo
   while (win.touched) {
     const int k = __builtin_ctz(win.touched);
     win.touched &= win.touched - 1u;
-    const uint32_t v = win.w[k * kBlock];
-    win.w[k * kBlock] = 0;
+    const uint32_t v = win.w[k * win.stride];
+    win.w[k * win.stride] = 0;
     for (int h = 0; h < per; ++h) {
       const uint32_t c = (v >> (bits * h)) & field;
       if (!c) continue;
@@ -222,9 +224,9 @@ __device__ __forceinline__ int cell(double g, int n, double &f) {
 // directions, no rigid matrices): the grid coordinate along an axis is exactly
 // (coordinate - start) / spacing, so z is tabulated per voxel in this thread's
 // LDS table (zf: fraction, zp: coordinate, zb: cell or -1 outside; n entries,
-// stride kBlock) and the x- then y-interpolated translations of a DVF cell are
+// stride B, the block size) and the x- then y-interpolated translations of a DVF cell are
 // kept while the centres stay in it.
-template <bool ALIGNED, class Visit>
+template <bool ALIGNED, int B, class Visit>
 __device__ __forceinline__ void map_subvoxels(const DvfDev &g, const double *org, const double *sp, int n, int ix,
                                               int iy, int iz, const double *off, double *zf, double *zp, int *zb,
                                               int tid, Visit &&visit) {
@@ -237,9 +239,9 @@ __device__ __forceinline__ void map_subvoxels(const DvfDev &g, const double *org
       double f = 0.0;
       int b = -1;
       if (gz >= 0.0 && gz <= (double)(g.n[2] - 1)) b = cell(gz, g.n[2], f);
-      zf[sc * kBlock + tid] = f;
-      zp[sc * kBlock + tid] = pz;
-      zb[sc * kBlock + tid] = b;
+      zf[sc * B + tid] = f;
+      zp[sc * B + tid] = pz;
+      zb[sc * B + tid] = b;
     }
     const long long sy = 3LL * g.n[0], sz = 3LL * g.n[0] * g.n[1];
     for (int sa = 0; sa < n; ++sa) {
@@ -260,9 +262,9 @@ __device__ __forceinline__ void map_subvoxels(const DvfDev &g, const double *org
         int cb = -1;
         double c0[3], c1[3], dc[3];
         for (int sc = 0; sc < n; ++sc) {
-          const int b2 = zb[sc * kBlock + tid];
+          const int b2 = zb[sc * B + tid];
           if (b2 < 0) continue;
-          const double f2 = zf[sc * kBlock + tid];
+          const double f2 = zf[sc * B + tid];
           if (b2 != cb) {
             // z grows with sc, so the next layer is usually cb + 1, whose
             // lower plane is cb's upper plane: the same corners and
@@ -291,7 +293,7 @@ __device__ __forceinline__ void map_subvoxels(const DvfDev &g, const double *org
             }
             cb = b2;
           }
-          const double pz = zp[sc * kBlock + tid];
+          const double pz = zp[sc * B + tid];
           const double qx = px + (c0[0] + f2 * dc[0]);
           const double qy = py + (c0[1] + f2 * dc[1]);
           const double qz = pz + (c0[2] + f2 * dc[2]);
@@ -315,8 +317,8 @@ __device__ __forceinline__ void map_subvoxels(const DvfDev &g, const double *org
   }
 }
 
-template <bool ALIGNED>
-__global__ void __launch_bounds__(kBlock) emtm_push(EmtmPush a) {
+template <bool ALIGNED, int B>
+__global__ void __launch_bounds__(B) emtm_push(EmtmPush a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double off[kMaxSub];
   const int n = a.n_sub;
@@ -324,23 +326,24 @@ __global__ void __launch_bounds__(kBlock) emtm_push(EmtmPush a) {
   const int lg = win_lg(n);
   const int words = kWinCells >> lg;
   uint32_t *win_words = reinterpret_cast<uint32_t *>(smem);
-  double *zf = reinterpret_cast<double *>(smem + sizeof(uint32_t) * words * kBlock);
-  double *zp = zf + (size_t)n * kBlock;
-  int *zb = reinterpret_cast<int *>(zp + (size_t)n * kBlock);
+  double *zf = reinterpret_cast<double *>(smem + sizeof(uint32_t) * words * B);
+  double *zp = zf + (size_t)n * B;
+  int *zb = reinterpret_cast<int *>(zp + (size_t)n * B);
   // subvoxel centre offsets (s + 1/2) / n, in voxels
   if (tid < n) off[tid] = ((double)tid + 0.5) / (double)n;
-  for (int k = 0; k < words; ++k) win_words[k * kBlock + tid] = 0;
+  for (int k = 0; k < words; ++k) win_words[k * B + tid] = 0;
   __syncthreads();
   Window win;
   win.w = win_words + tid;
+  win.stride = B;
   win.lg = lg;
   win.touched = 0;
   win.set = false;
   const DvfDev &g = a.dvf;
   // grids hold at most 2^31 - 1 voxels
   const unsigned nvox = (unsigned)a.nx * (unsigned)a.ny * (unsigned)a.nz;
-  const unsigned stride = gridDim.x * kBlock;
-  for (unsigned j = blockIdx.x * kBlock + tid; j < nvox; j += stride) {
+  const unsigned stride = gridDim.x * B;
+  for (unsigned j = blockIdx.x * B + tid; j < nvox; j += stride) {
     double rho = 0.0;
     if (!a.mask || a.mask[j] != 0) {
       int h = a.hu[j];
@@ -353,7 +356,7 @@ __global__ void __launch_bounds__(kBlock) emtm_push(EmtmPush a) {
     const Deposit d = {t >> 32, t & 0xFFFFFFFFull, (unsigned long long)mq};
     const unsigned row = j / (unsigned)a.nx;
     const int ix = (int)(j - row * (unsigned)a.nx), iy = (int)(row % (unsigned)a.ny), iz = (int)(row / (unsigned)a.ny);
-    map_subvoxels<ALIGNED>(g, a.org, a.sp, n, ix, iy, iz, off, zf, zp, zb, tid,
+    map_subvoxels<ALIGNED, B>(g, a.org, a.sp, n, ix, iy, iz, off, zf, zp, zb, tid,
                            [&](double qx, double qy, double qz) {
                              int tv[3];
                              if (ref_voxel(a, qx, qy, qz, tv)) count(a, win, d, tv);
@@ -396,27 +399,27 @@ __device__ __forceinline__ double dose_sample(const DimPull &a, double qx, doubl
   return c0 + f[2] * (c1 - c0);
 }
 
-template <bool ALIGNED>
-__global__ void __launch_bounds__(kBlock) dim_pull(DimPull a) {
+template <bool ALIGNED, int B>
+__global__ void __launch_bounds__(B) dim_pull(DimPull a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double off[kMaxSub];
   const int n = a.n_sub;
   const int tid = threadIdx.x;
   double *zf = reinterpret_cast<double *>(smem);
-  double *zp = zf + (size_t)n * kBlock;
-  int *zb = reinterpret_cast<int *>(zp + (size_t)n * kBlock);
+  double *zp = zf + (size_t)n * B;
+  int *zb = reinterpret_cast<int *>(zp + (size_t)n * B);
   if (tid < n) off[tid] = ((double)tid + 0.5) / (double)n;
   __syncthreads();
   const double count = (double)(n * n * n);
   const unsigned nvox = (unsigned)a.nx * (unsigned)a.ny * (unsigned)a.nz;
-  const unsigned stride = gridDim.x * kBlock;
-  for (unsigned j = blockIdx.x * kBlock + tid; j < nvox; j += stride) {
+  const unsigned stride = gridDim.x * B;
+  for (unsigned j = blockIdx.x * B + tid; j < nvox; j += stride) {
     const unsigned row = j / (unsigned)a.nx;
     const int ix = (int)(j - row * (unsigned)a.nx), iy = (int)(row % (unsigned)a.ny), iz = (int)(row / (unsigned)a.ny);
     // Eq. (3): the subvoxel samples summed in order (a centre outside the DVF
     // grid adds nothing), then divided by n^3
     double acc = 0.0;
-    map_subvoxels<ALIGNED>(a.dvf, a.org, a.sp, n, ix, iy, iz, off, zf, zp, zb, tid,
+    map_subvoxels<ALIGNED, B>(a.dvf, a.org, a.sp, n, ix, iy, iz, off, zf, zp, zb, tid,
                            [&](double qx, double qy, double qz) { acc = acc + dose_sample(a, qx, qy, qz); });
     a.dose[j] = a.dose[j] + acc / count;
   }
@@ -481,47 +484,85 @@ __global__ void __launch_bounds__(256) emtm_mask(EmtmMask a) {
   }
 }
 
-unsigned grid_for(long long n) {
-  long long b = (n + 255) / 256;
+unsigned grid_for(long long n, int block = 256) {
+  long long b = (n + block - 1) / block;
   if (b > 65536) b = 65536;
   if (b < 1) b = 1;
   return (unsigned)b;
+}
+
+// Block size for a kernel whose threads each need `per_thread` bytes of LDS:
+// 256, unless LDS (160 KiB per CU) then leaves fewer than 512 threads (two
+// waves per SIMD) resident on a CU; then the one of 128 and 64 that keeps the
+// most threads resident (measured: above two waves per SIMD smaller blocks
+// gain nothing; below, n = 10 takes 280 instead of 425 ms).
+int pick_block(size_t per_thread) {
+  auto resident = [&](int b) -> long long {
+    const size_t per_block = per_thread * (size_t)b;
+    const long long blocks = per_block ? (long long)((160u * 1024u) / per_block) : 1280 / b;
+    return std::min<long long>(blocks * b, 1280);
+  };
+  if (resident(256) >= 512) return 256;
+  int best = 256;
+  for (int b : {128, 64})
+    if (resident(b) > resident(best)) best = b;
+  return best;
+}
+
+template <bool ALIGNED, int B>
+hipError_t launch_push_b(const EmtmPush &a, size_t per_thread, long long n, hipStream_t st) {
+  const size_t lds = per_thread * B;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&emtm_push<ALIGNED, B>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((emtm_push<ALIGNED, B>), dim3(grid_for(n, B)), dim3(B), lds, st, a);
+  return hipGetLastError();
+}
+
+template <bool ALIGNED>
+hipError_t launch_push_a(const EmtmPush &a, size_t per_thread, long long n, hipStream_t st) {
+  switch (pick_block(per_thread)) {
+    case 64: return launch_push_b<ALIGNED, 64>(a, per_thread, n, st);
+    case 128: return launch_push_b<ALIGNED, 128>(a, per_thread, n, st);
+    default: return launch_push_b<ALIGNED, 256>(a, per_thread, n, st);
+  }
+}
+
+template <bool ALIGNED, int B>
+hipError_t launch_dim_b(const DimPull &a, size_t per_thread, long long n, hipStream_t st) {
+  const size_t lds = per_thread * B;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&dim_pull<ALIGNED, B>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((dim_pull<ALIGNED, B>), dim3(grid_for(n, B)), dim3(B), lds, st, a);
+  return hipGetLastError();
+}
+
+template <bool ALIGNED>
+hipError_t launch_dim_a(const DimPull &a, size_t per_thread, long long n, hipStream_t st) {
+  switch (pick_block(per_thread)) {
+    case 64: return launch_dim_b<ALIGNED, 64>(a, per_thread, n, st);
+    case 128: return launch_dim_b<ALIGNED, 128>(a, per_thread, n, st);
+    default: return launch_dim_b<ALIGNED, 256>(a, per_thread, n, st);
+  }
 }
 
 }  // namespace
 
 hipError_t launch_emtm_push(const EmtmPush &a, hipStream_t st) {
   const long long n = (long long)a.nx * a.ny * a.nz;
-  const size_t lds = sizeof(uint32_t) * (kWinCells >> win_lg(a.n_sub)) * kBlock +
-                     (a.aligned ? (2 * sizeof(double) + sizeof(int)) * (size_t)a.n_sub * kBlock : 0);
   if (a.n_sub < 1 || a.n_sub > kMaxSub) return hipErrorInvalidValue;
-  if (a.aligned) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&emtm_push<true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(emtm_push<true>, dim3(grid_for(n)), dim3(kBlock), lds, st, a);
-  } else {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&emtm_push<false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(emtm_push<false>, dim3(grid_for(n)), dim3(kBlock), lds, st, a);
-  }
-  return hipGetLastError();
+  // per thread: the counting window, and the z table of the axis-aligned path
+  const size_t per_thread = sizeof(uint32_t) * (kWinCells >> win_lg(a.n_sub)) +
+                            (a.aligned ? (2 * sizeof(double) + sizeof(int)) * (size_t)a.n_sub : 0);
+  return a.aligned ? launch_push_a<true>(a, per_thread, n, st) : launch_push_a<false>(a, per_thread, n, st);
 }
 
 hipError_t launch_dim_pull(const DimPull &a, hipStream_t st) {
   const long long n = (long long)a.nx * a.ny * a.nz;
   if (a.n_sub < 1 || a.n_sub > kMaxSub) return hipErrorInvalidValue;
-  const size_t lds = a.aligned ? (2 * sizeof(double) + sizeof(int)) * (size_t)a.n_sub * kBlock : 0;
-  if (a.aligned) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&dim_pull<true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(dim_pull<true>, dim3(grid_for(n)), dim3(kBlock), lds, st, a);
-  } else {
-    hipLaunchKernelGGL(dim_pull<false>, dim3(grid_for(n)), dim3(kBlock), 0, st, a);
-  }
-  return hipGetLastError();
+  const size_t per_thread = a.aligned ? (2 * sizeof(double) + sizeof(int)) * (size_t)a.n_sub : 0;
+  return a.aligned ? launch_dim_a<true>(a, per_thread, n, st) : launch_dim_a<false>(a, per_thread, n, st);
 }
 
 hipError_t launch_dvf_points(const DvfDev &d, double *x0, double *rf, hipStream_t st) {

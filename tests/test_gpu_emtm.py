@@ -167,14 +167,15 @@ def random_box(shape, spacing, seed):
     return ph
 
 
-@pytest.mark.parametrize("n_sub", [2, 5, 16])
+@pytest.mark.parametrize("n_sub", [2, 5, 12, 16])
 def test_rotated_and_expanding_dvfs(P, E, orc, n_sub):
     """Rotated DVF grids (the general mapping), an aligned DVF that stretches
     the source threefold (subvoxels fall outside the 4x4x4 counting window and
-    go straight to the device sums) and n_sub up to 16 (more than 64 KiB of
-    LDS per block), all against the oracle."""
+    go straight to the device sums) and n_sub up to 16 (16-bit counts; the
+    LDS tables of n_sub 12 and 16 make the library use 128- and 64-thread
+    blocks), all against the oracle."""
     import math
-    shape = (24, 20, 16) if n_sub < 16 else (12, 10, 8)
+    shape = (24, 20, 16) if n_sub < 12 else (12, 10, 8)
     phases = [random_box(shape, (2.0, 2.5, 3.0), 20 + k) for k in range(3)]
     c, s = math.cos(0.3), math.sin(0.3)
     A1 = np.array([[0.01, -0.02, 0.005], [0.0, 0.015, 0.01], [-0.01, 0.0, 0.02]])
