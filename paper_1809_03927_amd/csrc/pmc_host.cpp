@@ -600,6 +600,22 @@ pmc::CoreDev core_of(const pmc_box &b, const pmc_field &f, int32_t cap) {
   return c;
 }
 
+// The voxel box of a spot extended along the beam's main axis back to the
+// face of the grid where the beam enters.  Every proton crosses the air in
+// front of the body one voxel per step, close to the spot axis, and each
+// crossing deposits: a core window over this extent takes those deposits into
+// LDS as well.  An empty box stays empty.
+pmc_box to_entry_face(const pmc_box &b, const pmc_field &f, const int n[3]) {
+  pmc_box e = b;
+  if (b.hi[0] <= b.lo[0] || b.hi[1] <= b.lo[1] || b.hi[2] <= b.lo[2]) return e;
+  int d = 0;
+  for (int k = 1; k < 3; ++k)
+    if (std::fabs(f.direction[k]) > std::fabs(f.direction[d])) d = k;
+  if (f.direction[d] < 0.0) e.hi[d] = n[d];
+  else e.lo[d] = 0;
+  return e;
+}
+
 constexpr size_t kMaxPrepared = 32;
 
 // Work items of spots [s0, s1) in queue order.  Each spot's histories are cut
@@ -722,8 +738,8 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
       if (P.per_spot[s] == 0 || slot_of.find(sp.phase) == slot_of.end()) continue;
       const PhaseRec &ph = ctx->phases.at(sp.phase);
       const pmc_field &f = plan.fields[sp.field];
-      pmc::CoreDev c = core_of(sbox[s], f, P.core_cap);
       const int n[3] = {ph.nx, ph.ny, ph.nz};
+      pmc::CoreDev c = core_of(to_entry_face(sbox[s], f, n), f, P.core_cap);
       bool ok = (long long)c.n[0] * c.n[1] * c.n[2] <= (long long)P.core_cap;
       for (int k = 0; k < 3; ++k) ok = ok && c.lo[k] >= 0 && c.n[k] >= 0 && c.lo[k] + c.n[k] <= n[k];
       if (!ok) return fail(ctx, PMC_E_STATE, "internal: core box of spot %lld out of range", (long long)s);
