@@ -49,8 +49,8 @@ VALU_PER_STEP = 448.0
 # WRITE_SIZE scaled by a 4 GiB copy calibration
 # (profiles/transport_core_thorax4d_counters.md).  Valid only for the sources
 # they were measured on (hash below) and that launch shape; otherwise null.
-PROFILED_TRAFFIC_BYTES = 180.4e9
-PROFILED_KERNEL_HASH = "710bdd01123ff18f"
+PROFILED_TRAFFIC_BYTES = 171.2e9
+PROFILED_KERNEL_HASH = "f91386154467cf13"
 
 # Deformable accumulation (energy/mass transfer, Sec. 2.D.2): the per-phase
 # tallies of the 4D run accumulated onto one reference phase with n^3
@@ -78,7 +78,7 @@ PEAK_FP64_OPS = 256 * 64 * 2.4e9
 # valid for the source it was measured on (hash of pmc_accumulate.hip).
 PROFILED_ACC_TRAFFIC_BYTES = 3.13e9
 PROFILED_DIM_TRAFFIC_BYTES = 4.40e9
-PROFILED_ACC_HASH = "8557f93252cfdc1c"
+PROFILED_ACC_HASH = "5c14f46b68ad05ac"
 
 
 def log(*a):
