@@ -2657,9 +2657,10 @@ int pmc_delivery_simulate(pmc_context *ctx, const pmc_delivery *d, const pmc_spo
   if (e == hipSuccess && n_spots > 0)
     e = copy_sync(ctx, d_index, index.data(), sizeof(int64_t) * index.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "upload delivery inputs"));
-  if (mu_bytes >= 8)
-    HIP_TRY(ctx, pmc::launch_fill_u64(static_cast<unsigned long long *>(d_mu), (long long)(mu_bytes / 8), 0ull,
-                                      ctx->stream), "zero MU");
+  if (mu_bytes >= 8) {
+    e = pmc::launch_fill_u64(static_cast<unsigned long long *>(d_mu), (long long)(mu_bytes / 8), 0ull, ctx->stream);
+    if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "zero MU"));
+  }
   {
     const int32_t zero = 0;
     e = copy_sync(ctx, d_status, &zero, sizeof(zero), hipMemcpyHostToDevice);
@@ -2707,11 +2708,13 @@ int pmc_delivery_simulate(pmc_context *ctx, const pmc_delivery *d, const pmc_spo
   if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "delivery_sim launch"));
   int32_t status = 0;
   e = copy_sync(ctx, &status, d_status, sizeof(status), hipMemcpyDeviceToHost);
-  if (e == hipSuccess && mu_out && mu_bytes) e = copy_sync(ctx, mu_out, d_mu, mu_bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "download delivery status"));
+  // an abandoned timeline leaves the caller's buffers untouched
+  if (status) return cleanup(fail(ctx, PMC_E_INVAL, "a delivery timeline exceeded 2^30 breathing phases"));
+  if (mu_out && mu_bytes) e = copy_sync(ctx, mu_out, d_mu, mu_bytes, hipMemcpyDeviceToHost);
   if (e == hipSuccess && time_out) e = copy_sync(ctx, time_out, d_time, sizeof(double) * n_tf, hipMemcpyDeviceToHost);
   if (e == hipSuccess && fills_out)
     e = copy_sync(ctx, fills_out, d_fills, sizeof(int32_t) * n_tf, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return cleanup(hip_fail(ctx, e, "download delivery results"));
-  if (status) return cleanup(fail(ctx, PMC_E_INVAL, "a delivery timeline exceeded 2^30 breathing phases"));
   return cleanup(PMC_OK);
 }
