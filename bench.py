@@ -852,7 +852,7 @@ def cpu_sample_size(wl, target_s):
 
 def cpu_baseline(wl, k, gpu_sample):
     """The FP64 oracle on the host, on the first k histories of every spot,
-    timed; then the C.8 accuracy check of the GPU's tallies of the same
+    timed; then the accuracy check of the GPU's tallies of the same
     histories against it: voxels above 10 % of the phase's maximum dose pass
     if |dD| <= 1 % of that maximum or <= 3 sigma_diff (sqrt 2 x the oracle's
     sigma from 10 history batches); total energy within 0.1 %."""
@@ -898,7 +898,7 @@ def cpu_baseline(wl, k, gpu_sample):
         e_orc += float(s1[i].sum())
     frac = n_ok / max(n_sel, 1)
     e_rel = abs(e_gpu - e_orc) / max(e_orc, 1)
-    out["accuracy"] = {"check": "GPU (FP32, same histories) vs oracle (FP64) on the sample, C.8",
+    out["accuracy"] = {"check": "GPU (FP32, same histories) vs oracle (FP64) on the sample: voxels above 10 % of the phase maximum within 1 % of it or 3 sigma_diff; total energy within 0.1 %",
                        "voxels": n_sel, "pass_frac": frac, "energy_rel": e_rel,
                        "passed": bool(frac >= 0.99 and e_rel <= 1e-3)}
     log(f"accuracy on the sample: {n_sel} voxels above 10 % Dmax, pass {frac:.4f}, dE {e_rel:.2e}")

@@ -273,7 +273,9 @@ int pmc_dose_device_notify(pmc_context *ctx, const pmc_request *req, void *strea
 
 /* Turn a device counter block (copied to the host) plus the request into a
  * pmc_balance; the deposited total is taken from the tallies' sum, passed as
- * a 128-bit (lo, hi) pair. */
+ * a 128-bit (lo, hi) pair.  The incident energy is that of the histories the
+ * request runs: for a slice [item_begin, item_end) of a persistent-engine
+ * request, those of its work items only (pmc_dose reports the same). */
 int pmc_balance_from_counters(pmc_context *ctx, const pmc_request *req, const uint64_t *counters,
                               const uint64_t deposited[2], pmc_balance *out);
 

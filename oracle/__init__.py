@@ -113,6 +113,11 @@ def lib():
                                      C.c_int64, C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
                                      C.c_uint64, C.c_uint32, C.c_int32, C.c_int64, C.c_int64,
                                      C.c_void_p, C.c_void_p]
+        L.orc_dose_spots_batch.restype = C.c_int
+        L.orc_dose_spots_batch.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                           C.c_int64, C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
+                                           C.c_uint64, C.c_uint32, C.c_int32, C.c_int64, C.c_int64,
+                                           C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]
         L.orc_trace.restype = C.c_int
         L.orc_trace.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
                                 C.c_int64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -243,9 +248,10 @@ def dose_batches(phases, plan, n_hist: int, seed: int, n_batches=10, request_id=
 
 
 def dose_spots(phases, plan, n_hist: int, seed: int, s_begin: int, s_end: int, request_id=0,
-               phase_ids=None, flags=0, n_threads=None):
+               phase_ids=None, flags=0, n_threads=None, h_mod: int = 1, h_rem: int = 0):
     """Tallies of only the histories of spots s_begin <= s < s_end (history
-    split of the whole request)."""
+    split of the whole request); with h_mod > 1 only the histories h of
+    those spots with h % h_mod == h_rem."""
     if phase_ids is None:
         phase_ids = list(range(len(phases)))
     if n_threads is None:
@@ -257,12 +263,12 @@ def dose_spots(phases, plan, n_hist: int, seed: int, s_begin: int, s_end: int, r
     bal = Balance()
     spots = np.ascontiguousarray(plan.spots)
     fields = np.ascontiguousarray(plan.fields)
-    rc = lib().orc_dose_spots(parr, len(phases), fields.ctypes.data, len(fields), spots.ctypes.data,
-                              len(spots), ids.ctypes.data, len(ids), int(seed), int(request_id),
-                              int(n_hist), int(flags), int(n_threads), int(s_begin), int(s_end), tp,
-                              C.byref(bal))
+    rc = lib().orc_dose_spots_batch(parr, len(phases), fields.ctypes.data, len(fields), spots.ctypes.data,
+                                    len(spots), ids.ctypes.data, len(ids), int(seed), int(request_id),
+                                    int(n_hist), int(flags), int(n_threads), int(s_begin), int(s_end),
+                                    int(h_mod), int(h_rem), tp, C.byref(bal))
     if rc:
-        raise ValueError(f"orc_dose_spots failed: {rc}")
+        raise ValueError(f"orc_dose_spots_batch failed: {rc}")
     del holders
     return tallies, bal.as_dict()
 

@@ -728,15 +728,26 @@ int orc_dose_subset(const orc_phase *phases, int32_t n_phases, const orc_field *
                     n_spots, tallies, bal);
 }
 
+int orc_dose_spots_batch(const orc_phase *phases, int32_t n_phases, const orc_field *fields,
+                         int32_t n_fields, const orc_spot *spots, int64_t n_spots,
+                         const int32_t *phase_ids, int32_t n_req_phases, uint64_t seed,
+                         uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
+                         int64_t s_begin, int64_t s_end, uint32_t h_mod, uint32_t h_rem,
+                         int64_t *const *tallies, orc_balance *bal) {
+  if (s_begin < 0 || s_end > n_spots || s_begin > s_end) return -1;
+  return run_common(phases, n_phases, fields, n_fields, spots, n_spots, phase_ids, n_req_phases,
+                    seed, request_id, n_hist, flags, n_threads, 0u, 0xffffffffu, h_mod, h_rem,
+                    s_begin, s_end, tallies, bal);
+}
+
 int orc_dose_spots(const orc_phase *phases, int32_t n_phases, const orc_field *fields,
                    int32_t n_fields, const orc_spot *spots, int64_t n_spots,
                    const int32_t *phase_ids, int32_t n_req_phases, uint64_t seed,
                    uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
                    int64_t s_begin, int64_t s_end, int64_t *const *tallies, orc_balance *bal) {
-  if (s_begin < 0 || s_end > n_spots || s_begin > s_end) return -1;
-  return run_common(phases, n_phases, fields, n_fields, spots, n_spots, phase_ids, n_req_phases,
-                    seed, request_id, n_hist, flags, n_threads, 0u, 0xffffffffu, 1u, 0u, s_begin,
-                    s_end, tallies, bal);
+  return orc_dose_spots_batch(phases, n_phases, fields, n_fields, spots, n_spots, phase_ids,
+                              n_req_phases, seed, request_id, n_hist, flags, n_threads, s_begin,
+                              s_end, 1u, 0u, tallies, bal);
 }
 
 int orc_trace(const orc_phase *phase, const orc_field *fields, int32_t n_fields,

@@ -132,6 +132,15 @@ int orc_dose_spots(const orc_phase *phases, int32_t n_phases, const orc_field *f
                    uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
                    int64_t s_begin, int64_t s_end, int64_t *const *tallies, orc_balance *bal);
 
+/* orc_dose_spots restricted further to the histories h of each spot with
+ * h % h_mod == h_rem (batches of the same histories for an error estimate). */
+int orc_dose_spots_batch(const orc_phase *phases, int32_t n_phases, const orc_field *fields,
+                         int32_t n_fields, const orc_spot *spots, int64_t n_spots,
+                         const int32_t *phase_ids, int32_t n_req_phases, uint64_t seed,
+                         uint32_t request_id, uint64_t n_hist, uint32_t flags, int32_t n_threads,
+                         int64_t s_begin, int64_t s_end, uint32_t h_mod, uint32_t h_rem,
+                         int64_t *const *tallies, orc_balance *bal);
+
 /* Per-step trace of one history (spot index, history index within spot).
  * Returns the number of records written (<= max_rec) or a negative error. */
 int orc_trace(const orc_phase *phase, const orc_field *fields, int32_t n_fields,

@@ -75,6 +75,15 @@ template <> struct M<float> {
     const unsigned long long m = (unsigned long long)((b & 0x7FFFFFu) | 0x800000u);
     return E == 0.0f ? 0ll : (long long)(m << sh);
   }
+  // 1 - 2^-y for y >= 0.  1 - exp2(-y) cancels for the small y of a step
+  // through air (its absolute error is an ulp of 1); below z = y ln 2 = 1/16
+  // the series z - z^2/2 + z^3/6 - z^4/24 is used, whose first omitted term
+  // is under 2^-23 of the result.
+  static __device__ __forceinline__ float one_minus_exp2_neg(float y) {
+    const float z = y * 0.693147180559945309f;
+    if (z < 0.0625f) return z * (1.0f - z * (0.5f - z * (1.0f / 6.0f - z * (1.0f / 24.0f))));
+    return 1.0f - __builtin_amdgcn_exp2f(-y);
+  }
   static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
   static __device__ __forceinline__ float fmax(float a, float b) { return __builtin_fmaxf(a, b); }
   static __device__ __forceinline__ float fmin(float a, float b) { return __builtin_fminf(a, b); }
@@ -96,6 +105,9 @@ template <> struct M<double> {
   }
   static __device__ __forceinline__ double uni(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
   static __device__ __forceinline__ long long q(double E) { return __double2ll_rn(E * 4294967296.0); }
+  static __device__ __forceinline__ double one_minus_exp2_neg(double y) {
+    return -::expm1(-y * 0.69314718055994530942);
+  }
   static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
   static __device__ __forceinline__ double fmax(double a, double b) { return __builtin_fmax(a, b); }
   static __device__ __forceinline__ double fmin(double a, double b) { return __builtin_fmin(a, b); }
@@ -181,7 +193,9 @@ struct BoxLane {
   int32_t clo[3], cn[3];     // kTallyBoxCore: window corner (grid voxels) and size
 };
 
-// physics tables: (R, mu_delta, omega^2, 0) per node, linear in log2 E
+// physics tables per node i: (R, mu_delta, omega^2, dl2 / (R_{i+1} - R_i)),
+// linear in log2 E between nodes; the last entry is the inverse slope of R
+// against log2 E on the interval above the node (0 at the top node)
 template <typename R> struct Tab {
   const typename M<R>::R4 *t;  // kNtab entries (LDS or global)
   R l2e0, inv_dl2, dl2;
@@ -217,7 +231,7 @@ __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned l
 // ---------------------------------------------------------------------------
 // table lookups
 // ---------------------------------------------------------------------------
-template <typename R> struct Lookup { R R_, mud, om2; int i; };
+template <typename R> struct Lookup { R R_, mud, om2, f, islope; int i; };
 
 template <typename R>
 __device__ __forceinline__ Lookup<R> lookup(const Tab<R> &T, R E) {
@@ -230,6 +244,8 @@ __device__ __forceinline__ Lookup<R> lookup(const Tab<R> &T, R E) {
   o.R_ = a.x + f * (b.x - a.x);
   o.mud = a.y + f * (b.y - a.y);
   o.om2 = a.z + f * (b.z - a.z);
+  o.f = f;
+  o.islope = a.w;
   o.i = i;
   return o;
 }
@@ -572,7 +588,7 @@ __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &
   }
 
   // 3-4. physics limits; priority on ties stop > geo > delta > nuclear > phys
-  R s = dg, Rr = 0, mud = 0, om2 = 0, mun = 0;
+  R s = dg, Rr = 0, mud = 0, om2 = 0, mun = 0, tf = 0, tis = 0;
   int ti = 0;
   int cause = kGeo;
   if (!vac) {
@@ -581,6 +597,8 @@ __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &
     mud = (flags & kNoDelta) ? (R)0 : lk.mud;
     om2 = lk.om2;
     ti = lk.i;
+    tf = lk.f;
+    tis = lk.islope;
     mun = (!(flags & kNoNuclear) && L.E >= (R)kEn) ? (R)kMuN : (R)0;
     const R inv_rsp = MM::rcp(rsp);
     const R s_stop = (flags & kFrozen) ? MM::inf() : (rsp > (R)0 ? Rr * inv_rsp : MM::inf());
@@ -621,7 +639,16 @@ __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &
         const R g = (flags & kNoStraggling)
                         ? (R)0
                         : MM::sqrt((R)-2 * (LN2 * MM::log2(MM::uni(x.x)))) * MM::cos_rev(MM::uni(x.y));
-        R dE = (L.E - range_inverse(T, Rr - sw, ti)) + MM::sqrt(om2 * sw) * g;
+        // mean loss: the exact inverse of the piecewise-linear range table.
+        // A step that ends in the log E interval it starts in moves log2 E
+        // down by y = sw dl2 / (R_{i+1} - R_i) exactly, so E' = E 2^-y; the
+        // loss is formed from y directly rather than as E - R^-1(R(E) - sw),
+        // whose working-precision rounding of the table coordinate is large
+        // against the loss of a step through air.
+        const R y = sw * tis;
+        const R d_mean = y <= T.dl2 * tf ? L.E * MM::one_minus_exp2_neg(y)
+                                         : L.E - range_inverse(T, Rr - sw, ti);
+        R dE = d_mean + MM::sqrt(om2 * sw) * g;
         dE = dE < (R)0 ? (R)0 : (dE > L.E ? L.E : dE);
         const R En = L.E - dE;
         if (En <= (R)kElo) L.fate = kStopped;

@@ -962,7 +962,8 @@ int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
   return note_pending(ctx, st);
 }
 
-// Incident energy of a request (depends only on the split): 128-bit sum.
+// Incident energy of a request (depends only on the split and, for a slice
+// of a persistent-engine request, on its work items): 128-bit sum.
 int incident_of(pmc_context *ctx, const pmc_request *req, unsigned __int128 *out) {
   const PlanRec &plan = ctx->plans[req->plan];
   std::vector<int64_t> per(plan.spots.size());
@@ -970,10 +971,20 @@ int incident_of(pmc_context *ctx, const pmc_request *req, unsigned __int128 *out
                        req->n_histories, per.data());
   if (rc) return fail(ctx, rc, "history split failed");
   unsigned __int128 inc = 0;
-  for (size_t s = 0; s < per.size(); ++s)
-    if (per[s] > 0)
-      inc += (unsigned __int128)(unsigned long long)per[s] *
-             (unsigned long long)q_working(ctx, plan.spots[s].energy_MeV);
+  if (req->engine == PMC_ENGINE_PERSISTENT && (req->item_begin || req->item_end)) {
+    // the items of the launch (same chunk, same queue order), then the slice
+    std::vector<WorkItem> items;
+    build_items(per, 0, (int64_t)per.size(), launch_shape(ctx, req).chunk, items);
+    const uint64_t e = req->item_end ? std::min<uint64_t>(req->item_end, items.size()) : items.size();
+    for (uint64_t k = req->item_begin; k < e; ++k)
+      inc += (unsigned __int128)items[k].h_count *
+             (unsigned long long)q_working(ctx, plan.spots[items[k].spot].energy_MeV);
+  } else {
+    for (size_t s = 0; s < per.size(); ++s)
+      if (per[s] > 0)
+        inc += (unsigned __int128)(unsigned long long)per[s] *
+               (unsigned long long)q_working(ctx, plan.spots[s].energy_MeV);
+  }
   *out = inc;
   return PMC_OK;
 }
@@ -1051,15 +1062,18 @@ int pmc_create(const pmc_config *cfg, pmc_context **out) {
   ctx->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
   if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess)
     return bail(e, "hipStreamCreate");
-  // tables in the working precision: (R, mu_delta, omega^2, 0) per node
+  // tables in the working precision, per node: (R, mu_delta, omega^2, inverse
+  // slope dl2 / (R_{i+1} - R_i) of the interval above the node, 0 at the top)
   const int n = pmc::kTableNodes;
+  std::vector<double> islope(n, 0.0);
+  for (int i = 0; i + 1 < n; ++i) islope[i] = ctx->tabs.dl2 / (ctx->tabs.range[i + 1] - ctx->tabs.range[i]);
   if (ctx->precision == PMC_FP32) {
     std::vector<float> t(4 * n);
     for (int i = 0; i < n; ++i) {
       t[4 * i + 0] = (float)ctx->tabs.range[i];
       t[4 * i + 1] = (float)ctx->tabs.mu_delta[i];
       t[4 * i + 2] = (float)ctx->tabs.omega2[i];
-      t[4 * i + 3] = 0.0f;
+      t[4 * i + 3] = (float)islope[i];
     }
     ctx->tab_bytes = t.size() * sizeof(float);
     if ((e = hipMalloc(&ctx->d_tab, ctx->tab_bytes)) != hipSuccess) return bail(e, "hipMalloc tables");
@@ -1071,7 +1085,7 @@ int pmc_create(const pmc_config *cfg, pmc_context **out) {
       t[4 * i + 0] = ctx->tabs.range[i];
       t[4 * i + 1] = ctx->tabs.mu_delta[i];
       t[4 * i + 2] = ctx->tabs.omega2[i];
-      t[4 * i + 3] = 0.0;
+      t[4 * i + 3] = islope[i];
     }
     ctx->tab_bytes = t.size() * sizeof(double);
     if ((e = hipMalloc(&ctx->d_tab, ctx->tab_bytes)) != hipSuccess) return bail(e, "hipMalloc tables");

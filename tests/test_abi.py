@@ -252,6 +252,39 @@ def test_balance_from_words_matches_library(P):
         P.pmc_destroy(ctx)
 
 
+def test_slice_incident_energy_is_the_slices(P):
+    """The incident energy of a slice of a persistent-engine request counts
+    only its work items: the slices of a partition add up to the whole, and a
+    slice of one spot's items is that spot's share.  Host-only (a
+    validation-only context)."""
+    ctx = P.pmc_create(device=-1)
+    try:
+        wl = W.workload_slabs()
+        P.pmc_load_spots(ctx, wl.plan.fields, wl.plan.spots)
+        P.pmc_load_phase(ctx, 0, wl.phases[0])
+        n = 1_000_003
+        req = P.Request(n, [0], engine=P.PMC_ENGINE_PERSISTENT, chunk=700)
+        zero = np.zeros(P.PMC_COUNTERS)
+        whole = P.pmc_balance_from_counters(ctx, req, zero, 0)["incident"]
+        sizes = P.pmc_request_item_histories(ctx, req)
+        m = len(sizes)
+        cuts = [0, 1, 37, m // 2, m - 1, m]
+        parts = [P.pmc_balance_from_counters(ctx, req.slice(a, b), zero, 0)["incident"]
+                 for a, b in zip(cuts, cuts[1:])]
+        assert all(x > 0 for x in parts) and sum(parts) == whole
+        # open-ended slice [k, end) and the whole request as (0, 0)
+        tail = P.pmc_balance_from_counters(ctx, req.slice(m // 2, 0), zero, 0)["incident"]
+        assert tail == sum(parts[3:])
+        # one item: its histories times the spot's incident energy per history
+        per = P.pmc_split_histories(wl.plan.spots, [0], n)
+        first = P.pmc_balance_from_counters(ctx, req.slice(0, 1), zero, 0)["incident"]
+        s0 = int(np.nonzero(per)[0][0])
+        assert first % int(sizes[0]) == 0 and first // int(sizes[0]) > 0
+        assert int(sizes[0]) == min(700, int(per[s0]))
+    finally:
+        P.pmc_destroy(ctx)
+
+
 def test_dvf_and_accumulation_validation(P):
     ctx = P.pmc_create(device=-1)
     try:

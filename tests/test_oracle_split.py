@@ -53,3 +53,20 @@ def test_split_only_listed_phases_and_ties(orc):
     # three equal spots share 4: the extra one goes to the lowest index
     assert list(got) == [2, 1, 1, 0]
     assert list(orc.split_histories(s, [2], 3)) == [0, 0, 0, 3]
+
+
+def test_spot_selection_and_batches_partition_the_histories(orc):
+    """The per-spot selection takes exactly the spots' histories of the whole
+    request's split, and its h % h_mod batches partition them."""
+    wl = W.workload_slabs()
+    n = 20_000
+    whole, b_all = orc.dose(wl.phases, wl.plan, n, wl.seed)[0::2]
+    per = orc.split_histories(wl.plan.spots, [0], n)
+    parts = [orc.dose_spots(wl.phases, wl.plan, n, wl.seed, a, b) for a, b in ((0, 7), (7, 300), (300, 500))]
+    assert sum(p[1]["histories"] for p in parts) == n
+    assert np.array_equal(sum(p[0][0] for p in parts), whole[0])
+    t, b = orc.dose_spots(wl.phases, wl.plan, n, wl.seed, 3, 5)
+    assert b["histories"] == int(per[3] + per[4])
+    batches = [orc.dose_spots(wl.phases, wl.plan, n, wl.seed, 3, 5, h_mod=3, h_rem=r) for r in range(3)]
+    assert np.array_equal(sum(x[0][0] for x in batches), t[0])
+    assert sum(x[1]["incident"] for x in batches) == b["incident"]
