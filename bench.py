@@ -716,7 +716,9 @@ def dim_cpu(eng, wl, tallies, dvfs, sp, ref, n, target_s):
     """The oracle's Eq. (3) for a z-slab of the reference phase (through the
     middle of the grid) from source phase sp, timed; then the GPU's pull onto
     the same slab (as a phase of its own, zero reference tally) against it:
-    masks identical, doses within 1e-12 relative."""
+    masks identical, doses within 1e-12 relative.  The source tally is a
+    seeded synthetic one (workloads.random_tally), not the run's: no input of
+    the comparison comes from the library."""
     import dataclasses
     import numpy as np
     import torch
@@ -726,7 +728,8 @@ def dim_cpu(eng, wl, tallies, dvfs, sp, ref, n, target_s):
     from paper_1809_03927_amd import pmc
     rph, sph, dvf = wl.phases[ref], wl.phases[sp], dvfs[sp]
     nz = rph.hu.shape[0]
-    t_src = tallies[sp].cpu().numpy()
+    from paper_1809_03927_amd import workloads as W
+    t_src = W.random_tally(sph, 11)
     rho_s = oracle.convert(sph, np.zeros(sph.hu.size, dtype=np.int64), 1)[1]
     dose_s = E.phase_dose(t_src, rho_s, float(np.prod(np.asarray(sph.spacing_mm) * 0.1)), wl.n_histories)
 
@@ -755,7 +758,9 @@ def dim_cpu(eng, wl, tallies, dvfs, sp, ref, n, target_s):
     dose = torch.empty(c.hu.size, dtype=torch.float64, device="cuda")
     mask = torch.empty(c.hu.size, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
-    pmc.pmc_accumulate_dim_device(eng.ctx, 201, zero.data_ptr(), [sp], [300 + sp], [tallies[sp].data_ptr()], n,
+    ts = torch.from_numpy(t_src).cuda()
+    torch.cuda.synchronize()
+    pmc.pmc_accumulate_dim_device(eng.ctx, 201, zero.data_ptr(), [sp], [300 + sp], [ts.data_ptr()], n,
                                   wl.n_histories, 0, dose.data_ptr(), mask.data_ptr())
     torch.cuda.synchronize()
     pmc.pmc_unload_phase(eng.ctx, 201)
@@ -776,7 +781,9 @@ def accumulation_cpu(eng, wl, tallies, dvfs, sp, ref, n, target_s):
     """The oracle's energy/mass push of a z-slab of source phase sp (through
     the middle of the grid) onto the reference, timed; then the GPU's
     accumulation of the same slab (as a phase of its own, with a zero
-    reference tally) against it: masks identical, doses within 1e-9."""
+    reference tally) against it: masks identical, doses within 1e-9.  The
+    slab's tally is a seeded synthetic one (workloads.random_tally), not the
+    run's: no input of the comparison comes from the library."""
     import dataclasses
     import numpy as np
     import torch
@@ -785,7 +792,8 @@ def accumulation_cpu(eng, wl, tallies, dvfs, sp, ref, n, target_s):
     from paper_1809_03927_amd import pmc
     ph, rph, dvf = wl.phases[sp], wl.phases[ref], dvfs[sp]
     nz = ph.hu.shape[0]
-    tal = tallies[sp].cpu().numpy().reshape(ph.hu.shape)
+    from paper_1809_03927_amd import workloads as W
+    tal = W.random_tally(ph, 7).reshape(ph.hu.shape)
 
     def slab(k):
         z0 = nz // 2 - k // 2

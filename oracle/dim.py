@@ -58,12 +58,17 @@ def dose_sample(dose: np.ndarray, ph, pts: np.ndarray) -> np.ndarray:
     return c0 + fz * (c1 - c0)
 
 
-def pull(ref, src, dose_src: np.ndarray, dvf, n: int) -> np.ndarray:
+def pull(ref, src, dose_src: np.ndarray, dvf, n: int, voxels: Optional[np.ndarray] = None) -> np.ndarray:
     """Eq. (3): D^S on the reference grid (flat, x fastest) from the source
-    phase's dose through the reference-to-source DVF."""
+    phase's dose through the reference-to-source DVF; with `voxels` (flat
+    indices) only those reference voxels, in that order."""
     nz, ny, nx = ref.hu.shape
-    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    idx = np.stack([xx, yy, zz], axis=-1).reshape(-1, 3).astype(np.float64)
+    if voxels is None:
+        zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        idx = np.stack([xx, yy, zz], axis=-1).reshape(-1, 3).astype(np.float64)
+    else:
+        v = np.asarray(voxels, dtype=np.int64)
+        idx = np.stack([v % nx, (v // nx) % ny, v // (nx * ny)], axis=-1).astype(np.float64)
     o, s = np.asarray(ref.origin_mm, dtype=np.float64), np.asarray(ref.spacing_mm, dtype=np.float64)
     acc = np.zeros(idx.shape[0])
     for a in range(n):

@@ -138,6 +138,16 @@ def make_slabs() -> Phase:
     return p
 
 
+def random_tally(ph: Phase, seed: int, bits: int = 40) -> np.ndarray:
+    """Seeded int64 tally (units of 2^-32 MeV) on a phase's grid, for checks
+    of the accumulation that must not take their input from the transport
+    under test: uniform in [0, 2^bits) on voxels with matter (HU > -1000),
+    0 in air."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = rng.integers(0, 2**bits, size=ph.hu.size, dtype=np.int64)
+    return np.where(ph.hu.ravel() > -1000, t, 0).astype(np.int64)
+
+
 THORAX_EXTENT_MM = (384.0, 384.0, 320.0)
 
 

@@ -168,6 +168,17 @@ def test_rigid_shift_of_an_affine_dose(n):
     assert np.allclose(term[inner.ravel()], want[inner.ravel()], rtol=1e-12)
 
 
+def test_pull_of_selected_voxels_equals_the_whole():
+    """The voxel selection only picks which reference voxels are evaluated:
+    any subset, in any order, equals the same entries of the whole pull."""
+    ph = box((9, 8, 7), (2.0, 2.0, 2.0), (0.0, 0.0, 0.0))
+    dvf = cover(ph, lambda x: np.broadcast_to(np.array([1.3, -0.7, 0.45]), x.shape))
+    dose = affine_dose(ph) + np.random.default_rng(5).random(ph.hu.size)
+    whole = D.pull(ph, ph, dose, dvf, 2)
+    pick = np.random.default_rng(6).permutation(ph.hu.size)[:100]
+    assert np.array_equal(D.pull(ph, ph, dose, dvf, 2, voxels=pick), whole[pick])
+
+
 def test_brute_force_tiny_grid():
     """Pure-Python loops with weighted-sum trilinear interpolation of the DVF
     and of the dose (clamped), centres outside the DVF grid contributing 0."""

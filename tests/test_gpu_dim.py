@@ -176,16 +176,16 @@ def test_dim_and_emtm_with_rotated_grids_and_rigid_matrices(P, E, D, orc, n_sub)
     assert np.allclose(em_dose, want_e["dose"], rtol=1e-9, atol=0)
 
 
-def test_dim_identity_dvfs_sum_the_phase_doses(P):
+def test_dim_identity_dvfs_sum_the_phase_doses(P, orc):
     """Identity reference-to-source DVFs and n = 1: every reference voxel
     samples each source dose at its own centre, so the accumulated dose is
-    the sum of the phases' doses (Sec. 2.E's first test, with the MC doses
-    of a 4D run)."""
+    the sum of the phases' doses (Sec. 2.E's first test, with the MC tallies
+    and doses of a 4D run by the oracle)."""
     wl = W.workload_thorax4d(n_histories=200_000, shape_xyz=(64, 64, 40), n_phases=3)
+    tallies, doses, _ = orc.dose(wl.phases, wl.plan, wl.n_histories, wl.seed, phase_ids=[0, 1, 2])
     e = P.Engine(device=0, precision=P.PMC_FP32, seed=wl.seed)
     try:
         e.load_workload(wl)
-        doses, tallies, _, _ = e.dose(wl.n_histories, [0, 1, 2], engine=P.PMC_ENGINE_PERSISTENT)
         ph = wl.phases[0]
         nz, ny, nx = ph.hu.shape
         sp = np.asarray(ph.spacing_mm)

@@ -74,17 +74,18 @@ def test_accumulation_matches_oracle_random_tallies(P, E, orc, n_sub):
 
 
 def test_accumulation_of_a_4d_transport_run(P, E, orc):
-    """Per-phase tallies of a 4D thorax run on the GPU, phases 2, 5 and 7
+    """Per-phase tallies of a 4D thorax run (the oracle's transport, so that
+    no input of the comparison comes from the library), phases 2, 5 and 7
     accumulated onto phase 0 (n_sub 2), host and device entry points, against
     the oracle."""
     import torch
     wl = W.workload_thorax4d(n_histories=300_000, shape_xyz=(64, 64, 40))
     phases = list(range(10))
+    say("oracle 4D run for accumulation")
+    tallies = orc.dose(wl.phases, wl.plan, wl.n_histories, wl.seed, phase_ids=phases)[0]
     e = P.Engine(device=0, precision=P.PMC_FP32, seed=wl.seed)
     try:
         e.load_workload(wl)
-        say("4D run for accumulation")
-        _, tallies, _, _ = e.dose(wl.n_histories, phases, engine=P.PMC_ENGINE_PERSISTENT)
         src = [2, 5, 7]
         dvfs = {p: W.thorax_dvf(p, 0) for p in src}
         for p in src:
@@ -118,12 +119,12 @@ def test_accumulation_of_a_4d_transport_run(P, E, orc):
 def test_identity_dvfs_sum_the_phase_doses(P, orc):
     """Identity DVFs covering the grid: each source voxel lands in itself, so
     the accumulated dose is the sum of the phases' own doses (Sec. 2.E's
-    first test, with the MC doses of a 4D run)."""
+    first test, with the MC tallies and doses of a 4D run by the oracle)."""
     wl = W.workload_thorax4d(n_histories=200_000, shape_xyz=(64, 64, 40), n_phases=3)
+    tallies, doses, _ = orc.dose(wl.phases, wl.plan, wl.n_histories, wl.seed, phase_ids=[0, 1, 2])
     e = P.Engine(device=0, precision=P.PMC_FP32, seed=wl.seed)
     try:
         e.load_workload(wl)
-        doses, tallies, _, _ = e.dose(wl.n_histories, [0, 1, 2], engine=P.PMC_ENGINE_PERSISTENT)
         ph = wl.phases[0]
         nz, ny, nx = ph.hu.shape
         sp = np.asarray(ph.spacing_mm)

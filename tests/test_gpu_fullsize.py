@@ -189,3 +189,132 @@ def test_full_size_sampled_spots_against_oracle(full):
         e_rel = abs(float(t_g.sum()) - float(o_t[ph].sum())) / float(o_t[ph].sum())
         say(f"spot {s}: {int(sel.sum())} voxels above 10 %, pass {frac:.4f}, dE {e_rel:.2e}")
         assert sel.sum() > 100 and frac >= 0.99 and e_rel <= 1e-3 and math.isfinite(e_rel)
+
+
+def test_full_size_dim_sampled_voxels(full):
+    """Dose interpolation (Eq. (3)) at the benchmark's size and shape: nine
+    source phases pulled onto phase 5 through reference-to-source DVFs
+    (137 x 97 x 121 points at 2.5 mm), n = 5, by the device entry point.
+    Every reference voxel is computed on its own, so the oracle evaluates
+    3000 sampled ones (a third of them where the dose is highest) one by one:
+    masks identical, doses within 1e-12 relative.  The tallies are seeded
+    synthetic ones, so that no input comes from the library."""
+    import torch
+    import oracle
+    import oracle.dim as D
+    import oracle.emtm as E
+    pmc, wl, e = full
+    ref, n = 5, 5
+    src = [p for p in range(10) if p != ref]
+    tal = [W.random_tally(ph, 100 + i) for i, ph in enumerate(wl.phases)]
+    dvfs = {p: W.thorax_dvf(ref, p, n_phases=10) for p in src}
+    for p in src:
+        pmc.pmc_load_dvf(e.ctx, 300 + p, dvfs[p])
+    nv = wl.phases[ref].nvox
+    dt = [torch.from_numpy(t).cuda() for t in tal]
+    dose = torch.empty(nv, dtype=torch.float64, device="cuda")
+    mask = torch.empty(nv, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    say("full-size DIM, 9 sources, n = 5")
+    pmc.pmc_accumulate_dim_device(e.ctx, ref, dt[ref].data_ptr(), src, [300 + p for p in src],
+                                  [dt[p].data_ptr() for p in src], n, wl.n_histories, 0, dose.data_ptr(),
+                                  mask.data_ptr())
+    torch.cuda.synchronize()
+    got, gmask = dose.cpu().numpy(), mask.cpu().numpy().astype(bool)
+    rph = wl.phases[ref]
+    want_mask = E.report_mask(rph, [dvfs[p] for p in src])
+    assert np.array_equal(gmask, want_mask)
+    rho = [oracle.convert(ph, np.zeros(ph.hu.size, dtype=np.int64), 1)[1] for ph in wl.phases]
+    doses = [E.phase_dose(t, r, float(np.prod(np.asarray(ph.spacing_mm) * 0.1)), wl.n_histories)
+             for ph, t, r in zip(wl.phases, tal, rho)]
+    rng = np.random.Generator(np.random.PCG64(17))
+    inside = np.nonzero(want_mask)[0]
+    top = np.argsort(got)[-1000:]
+    pick = np.unique(np.concatenate([rng.choice(inside, 2000, replace=False), top]))
+    want = doses[ref][pick].copy()
+    for p in src:
+        want = want + D.pull(rph, wl.phases[p], doses[p], dvfs[p], n, voxels=pick)
+    want = np.where(want_mask[pick], want, 0.0)
+    g = got[pick]
+    scale = max(float(np.abs(want).max()), 1e-300)
+    rel = np.abs(g - want) / np.maximum(np.abs(want), 1e-3 * scale)
+    say(f"DIM sampled voxels {len(pick)}: max rel {rel.max():.2e}, identical {np.mean(g == want):.4f}")
+    assert rel.max() <= 1e-12
+    for p in src:
+        pmc.pmc_unload_dvf(e.ctx, 300 + p)
+
+
+def test_full_size_emtm_separable_and_slab(full):
+    """Energy/mass transfer (Eqs. (2), (4)-(6)) at the benchmark's size and
+    shape: nine source phases onto phase 5 (source-to-reference DVFs), n = 5,
+    device entry point.  Eq. (2) sums independent per-source terms, so the
+    nine-source call equals, bit for bit inside its report mask, the
+    reference dose plus nine single-source calls added on the host in source
+    order; and a 3-slice slab of one source phase (its own phase, zero
+    reference tally) against the oracle's push at the full reference size:
+    masks identical, doses within 1e-9 relative.  Seeded synthetic tallies."""
+    import dataclasses
+    import torch
+    import oracle
+    import oracle.emtm as E
+    pmc, wl, e = full
+    ref, n = 5, 5
+    src = [p for p in range(10) if p != ref]
+    tal = [W.random_tally(ph, 200 + i) for i, ph in enumerate(wl.phases)]
+    dvfs = {p: W.thorax_dvf(p, ref, n_phases=10) for p in src}
+    for p in src:
+        pmc.pmc_load_dvf(e.ctx, 100 + p, dvfs[p])
+    nv = wl.phases[ref].nvox
+    dt = [torch.from_numpy(t).cuda() for t in tal]
+    zero = torch.zeros(nv, dtype=torch.int64, device="cuda")
+    dose = torch.empty(nv, dtype=torch.float64, device="cuda")
+    mask = torch.empty(nv, dtype=torch.uint8, device="cuda")
+
+    def acc(ref_t, sources, tallies):
+        pmc.pmc_accumulate_device(e.ctx, ref, ref_t.data_ptr(), sources, [100 + p for p in sources],
+                                  [t.data_ptr() for t in tallies], n, wl.n_histories, 0, dose.data_ptr(),
+                                  mask.data_ptr())
+        torch.cuda.synchronize()
+        return dose.cpu().numpy(), mask.cpu().numpy().astype(bool)
+
+    say("full-size EMTM, 9 sources, n = 5")
+    full_d, full_m = acc(dt[ref], src, [dt[p] for p in src])
+    assert np.array_equal(full_m, E.report_mask(wl.phases[ref], [dvfs[p] for p in src]))
+    total, _ = acc(dt[ref], [], [])
+    for p in src:
+        say("single source", p)
+        term, m = acc(zero, [p], [dt[p]])
+        assert np.all(m[full_m])
+        total = total + term
+    assert np.array_equal(full_d[full_m], total[full_m]) and not full_d[~full_m].any()
+    # slab of source phase 0 against the oracle
+    sp, k = 0, 3
+    ph, rph = wl.phases[sp], wl.phases[ref]
+    z0 = ph.hu.shape[0] // 2 - 1
+    o = (ph.origin_mm[0], ph.origin_mm[1], ph.origin_mm[2] + z0 * ph.spacing_mm[2])
+    c = dataclasses.replace(ph, hu=np.ascontiguousarray(ph.hu[z0:z0 + k]), origin_mm=o, mask=None)
+    t = np.ascontiguousarray(tal[sp].reshape(ph.hu.shape)[z0:z0 + k]).ravel()
+    rho = oracle.convert(c, np.zeros(c.hu.size, dtype=np.int64), 1)[1]
+    say("oracle push of a 3-slice slab")
+    sums = E.push(c, t, rho, rph, dvfs[sp], n)
+    want_mask = E.report_mask(rph, [dvfs[sp]])
+    want = np.where(want_mask, E.dose_from_sums(sums, float(np.prod(np.asarray(c.spacing_mm) * 0.1)),
+                                                wl.n_histories), 0.0)
+    pmc.pmc_load_phase(e.ctx, 200, c)
+    try:
+        pmc.pmc_load_dvf(e.ctx, 300, dvfs[sp])
+        ts = torch.from_numpy(t).cuda()
+        pmc.pmc_accumulate_device(e.ctx, ref, zero.data_ptr(), [200], [300], [ts.data_ptr()], n,
+                                  wl.n_histories, 0, dose.data_ptr(), mask.data_ptr())
+        torch.cuda.synchronize()
+        got, gmask = dose.cpu().numpy(), mask.cpu().numpy().astype(bool)
+    finally:
+        pmc.pmc_unload_phase(e.ctx, 200)
+        pmc.pmc_unload_dvf(e.ctx, 300)
+    assert np.array_equal(gmask, want_mask)
+    sel = want > 0
+    rel = np.abs(got[sel] - want[sel]) / want[sel]
+    say(f"EMTM slab: {int(sel.sum())} voxels, max rel {rel.max():.2e}, identical {np.mean(got == want):.4f}")
+    assert sel.sum() > 1000 and rel.max() <= 1e-9 and not got[~sel].any()
+    for p in src:
+        pmc.pmc_unload_dvf(e.ctx, 100 + p)
