@@ -42,15 +42,15 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # VALU instructions one lane executes per transport step of the FP32 kernel:
 # SQ_INSTS_VALU of single-history launches (one active lane) divided by their
 # step count (profiles/transport_valu_per_step_thorax.md).
-VALU_PER_STEP = 446.7
+VALU_PER_STEP = 448.6
 
 # HBM-side bytes of one full-size transport launch (5e7 histories of the
 # thorax 4D workload, block engine, chunk 8192), from FETCH_SIZE and
 # WRITE_SIZE scaled by a 4 GiB copy calibration
 # (profiles/transport_core_thorax4d_counters.md).  Valid only for the sources
 # they were measured on (hash below) and that launch shape; otherwise null.
-PROFILED_TRAFFIC_BYTES = 170.4e9
-PROFILED_KERNEL_HASH = "b3a64e36d96427b3"
+PROFILED_TRAFFIC_BYTES = 172.2e9
+PROFILED_KERNEL_HASH = "698bebd8d8e87ae1"
 
 # Deformable accumulation (energy/mass transfer, Sec. 2.D.2): the per-phase
 # tallies of the 4D run accumulated onto one reference phase with n^3

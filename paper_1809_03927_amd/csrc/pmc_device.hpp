@@ -719,8 +719,17 @@ __device__ __forceinline__ void step(Lane<R> &L, const Geo<R> &G, const Tab<R> &
       C.nuc_ev += 1;
       L.fate = kNuclear;
     }
-    add_tally<R, TM>(L, G, B, v_step, dep, C);
   }
+  // Take the prefetched neighbour (HU, mask) here, on every path and before
+  // this step's tally atomic.  Vector memory operations complete in order, so
+  // a wait for the prefetch placed after the atomic (the compiler puts it
+  // before the first use, in the crossing below) also waited for the atomic's
+  // round trip to the memory side; here it covers only the previous step's
+  // atomic, issued a whole step earlier.  The empty asm emits nothing; its
+  // register operands make the value needed at this point.  (dep is 0 in
+  // vacuum, where add_tally does nothing.)
+  asm volatile("" ::"v"(hu_nb), "v"(mask_nb));
+  add_tally<R, TM>(L, G, B, v_step, dep, C);
   C.steps += 1;
   L.nsteps += 1;
   // 11. boundary crossing
