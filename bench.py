@@ -190,10 +190,13 @@ def main():
         t1 = time.time()
         # full-size probes over a short candidate list (block-engine items are
         # runs of one spot's histories: a smaller probe would shorten them)
+        dflt = pmc.pmc_launch_shape(eng.ctx, pmc.Request(wl.n_histories, phases, request_id=wl.request_id,
+                                                         engine=pmc.PMC_ENGINE_PERSISTENT))
         tuned = autotune.tune(eng.ctx, phases, key, tptr, counters.data_ptr(), stream.cuda_stream,
                               torch.cuda.synchronize, wl.n_histories, request_id=wl.request_id,
                               cache_path=a.tune_cache or autotune.DEFAULT_CACHE,
-                              candidates=autotune.FULL_SIZE_CANDIDATES, repeats=1)
+                              candidates=autotune.FULL_SIZE_CANDIDATES, repeats=1,
+                              prefer=(dflt["block_size"], dflt["chunk"], dflt["refill_min"], dflt["tally_mode"]))
         log(f"autotune ({time.time() - t1:.1f} s): tally mode {tuned['tally_mode']} block "
             f"{tuned['block_size']} chunk {tuned['chunk']} refill {tuned['refill_min']}")
 

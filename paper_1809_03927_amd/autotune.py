@@ -63,11 +63,15 @@ def _store(path: str, data: Dict[str, dict]) -> None:
 def tune(ctx, phases: Sequence[int], key: str, dev_tallies: Sequence[int], dev_counters: int,
          stream: int, sync, probe_histories: int, request_id: int = 0, flags: int = 0,
          cache_path: Optional[str] = DEFAULT_CACHE, candidates=None, repeats: int = 2,
-         log=None) -> dict:
+         log=None, prefer=None, tolerance: float = 0.01) -> dict:
     """Return {"block_size", "chunk", "refill_min", "tally_mode", "probe_ms"} for `key`.
 
     candidates: (block, chunk, refill[, tally mode]) tuples; the default is
     every lane-mode combination of BLOCKS x CHUNKS x REFILLS.
+
+    prefer: a candidate (usually the library's own default shape) kept unless
+    another one is faster by more than `tolerance`: shapes within the timing
+    noise of each other would otherwise be picked at random from run to run.
 
     dev_tallies / dev_counters are caller-owned device buffers (they are
     overwritten by the probes; the engine adds into them, so the caller
@@ -79,6 +83,7 @@ def tune(ctx, phases: Sequence[int], key: str, dev_tallies: Sequence[int], dev_c
     if candidates is None:
         candidates = LANE_CANDIDATES
     best = None
+    preferred = None
     for cand in candidates:
         block, chunk, refill = cand[:3]
         mode = cand[3] if len(cand) > 3 else pmc.PMC_TALLY_LANE
@@ -96,9 +101,14 @@ def tune(ctx, phases: Sequence[int], key: str, dev_tallies: Sequence[int], dev_c
         ms = 1e3 * min(times)
         if log:
             log(f"autotune {block=} {chunk=} {refill=} {mode=}: {ms:.2f} ms")
+        this = {"block_size": block, "chunk": chunk, "refill_min": refill, "tally_mode": mode,
+                "probe_ms": ms, "probe_histories": probe_histories}
         if best is None or ms < best["probe_ms"]:
-            best = {"block_size": block, "chunk": chunk, "refill_min": refill, "tally_mode": mode,
-                    "probe_ms": ms, "probe_histories": probe_histories}
+            best = this
+        if prefer is not None and (block, chunk, refill, mode) == tuple(prefer):
+            preferred = this
+    if preferred is not None and preferred["probe_ms"] <= best["probe_ms"] * (1.0 + tolerance):
+        best = preferred
     if cache_path:
         cache = _load(cache_path)
         cache[key] = best
