@@ -318,3 +318,27 @@ def test_full_size_emtm_separable_and_slab(full):
     assert sel.sum() > 1000 and rel.max() <= 1e-9 and not got[~sel].any()
     for p in src:
         pmc.pmc_unload_dvf(e.ctx, 100 + p)
+
+
+@pytest.mark.parametrize("scenario", ["free", "gated", "repainted"])
+def test_full_size_delivery(full, scenario):
+    """The delivery simulation (Sec. 2.B, App. A) at the benchmark's size:
+    the robust plan's three fields (8000 spots, 600 MU), 25 trials with
+    random start phase, breathing period and synchrotron parameters, free,
+    gated (phases 3-7) and repainted (0.005 MU per delivery).  Every trial is
+    independent, and the oracle replays all 25: MU per spot and phase, end
+    times and fill counts bit-identical."""
+    from oracle import delivery as OD
+    pmc, _, e = full
+    plan = W.plan_robust()
+    sp = plan.spots.copy()
+    sp["weight"] = sp["weight"] / sp["weight"].sum() * 600.0
+    kw = {"free": {}, "gated": {"gate_lo": 3, "gate_hi": 7}, "repainted": {"max_mu": 0.005}}[scenario]
+    d = W.Delivery(n_trials=25, period_sd_s=0.4, period_min_s=3, period_max_s=7, seed=17, **kw)
+    say("full-size delivery", scenario)
+    got = pmc.pmc_delivery_simulate(e.ctx, d, sp, len(plan.fields))
+    want = OD.simulate(sp, len(plan.fields), d)
+    assert np.array_equal(got["mu"], want["mu"])
+    assert np.array_equal(got["time"], want["time"]) and np.array_equal(got["fills"], want["fills"])
+    # MU conserved per spot and trial
+    assert np.allclose(got["mu"].sum(axis=2), sp["weight"][None, :], rtol=1e-12, atol=0)
