@@ -80,6 +80,10 @@ PROFILED_ACC_TRAFFIC_BYTES = 3.13e9
 PROFILED_DIM_TRAFFIC_BYTES = 4.40e9
 PROFILED_ACC_HASH = "5c14f46b68ad05ac"
 
+# Least pass fraction of the voxel criterion for a comparison with the oracle
+# that shares its random numbers (FP32 and FP64 runs of the same histories).
+SAME_SEED_MIN_PASS = 0.995
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -525,8 +529,8 @@ def delivery_bench(eng, cpu_trials):
     repainted; each call simulates all trials and fields (one GPU thread per
     trial and field) and returns the MU per spot and phase.  Timed as whole
     calls (inputs and outputs in host memory).  Then the oracle replays the
-    first trials of the repainted scenario, timed, and must match the GPU bit
-    for bit."""
+    first trials of the repainted scenario, timed, and must match the GPU:
+    MU and fills identical, end times within 1e-12, per timeline."""
     import numpy as np
     from paper_1809_03927_amd import pmc
     from paper_1809_03927_amd import workloads as W
@@ -577,16 +581,34 @@ def delivery_bench(eng, cpu_trials):
         want = DL.simulate(sp, n_f, d1)
         dt = time.perf_counter() - t0
         deliveries = float(np.ceil(sp["weight"] / d.max_mu).sum()) * cpu_trials
-        same = bool(np.array_equal(want["mu"], res["mu"][:cpu_trials])
-                    and np.array_equal(want["time"], res["time"][:cpu_trials])
-                    and np.array_equal(want["fills"], res["fills"][:cpu_trials]))
+        # per (trial, field): MU per (spot, phase) and fills identical, end
+        # time within 1e-12; a timeline that differs must hold a decision at
+        # a near tie in the oracle's log (the Box-Muller logarithm and cosine
+        # of host and device may differ in the last bit)
+        identical, flipped, bad, t_rel = 0, 0, 0, 0.0
+        for f in range(n_f):
+            idx = np.flatnonzero(sp["field"] == f)
+            for t in range(cpu_trials):
+                if (np.array_equal(want["mu"][t, idx], res["mu"][t, idx])
+                        and want["fills"][t, f] == res["fills"][t, f]):
+                    identical += 1
+                    t_rel = max(t_rel, abs(res["time"][t, f] - want["time"][t, f]) / max(want["time"][t, f], 1.0))
+                elif want["margin"][t, f] < 1e-10:
+                    flipped += 1
+                else:
+                    bad += 1
+        ok = bad == 0 and flipped <= 1 and t_rel <= 1e-12
         out["cpu_baseline"] = {"value": deliveries / dt, "unit": "spot deliveries simulated/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"the first {cpu_trials} trials of the repainted scenario "
                                          f"({deliveries:.3g} deliveries) in {dt:.1f} s, pure Python",
-                               "accuracy": {"check": "GPU vs oracle: MU per spot and phase, end times and fills "
-                                                     "bit-identical", "passed": same}}
-        log(f"delivery oracle: {cpu_trials} trials in {dt:.1f} s; identical {same}")
+                               "accuracy": {"check": "GPU vs oracle per (trial, field) timeline: MU per spot and "
+                                                     "phase and fills identical, end time within 1e-12 relative, "
+                                                     "or a logged near-tie decision (at most one timeline)",
+                                            "timelines_identical": identical, "timelines_flipped_at_tie": flipped,
+                                            "end_time_max_rel": t_rel, "passed": bool(ok)}}
+        log(f"delivery oracle: {cpu_trials} trials in {dt:.1f} s; {identical} timelines identical, "
+            f"{flipped} flipped at a near tie, {bad} differing, end time max rel {t_rel:.1e}")
     return out
 
 
@@ -909,9 +931,11 @@ def cpu_baseline(wl, k, gpu_sample):
         e_orc += float(s1[i].sum())
     frac = n_ok / max(n_sel, 1)
     e_rel = abs(e_gpu - e_orc) / max(e_orc, 1)
-    out["accuracy"] = {"check": "GPU (FP32, same histories) vs oracle (FP64) on the sample: voxels above 10 % of the phase maximum within 1 % of it or 3 sigma_diff; total energy within 0.1 %",
+    out["accuracy"] = {"check": "GPU (FP32, same histories and random numbers) vs oracle (FP64) on the sample: "
+                                "voxels above 10 % of the phase maximum within 1 % of it or 3 sigma_diff in at "
+                                "least 99.5 % of them; total energy within 0.1 %",
                        "voxels": n_sel, "pass_frac": frac, "energy_rel": e_rel,
-                       "passed": bool(frac >= 0.99 and e_rel <= 1e-3)}
+                       "passed": bool(frac >= SAME_SEED_MIN_PASS and e_rel <= 1e-3)}
     log(f"accuracy on the sample: {n_sel} voxels above 10 % Dmax, pass {frac:.4f}, dE {e_rel:.2e}")
     return out
 

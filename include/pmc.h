@@ -289,17 +289,22 @@ int pmc_convert_device(pmc_context *ctx, int32_t phase, const int64_t *dev_tally
 typedef struct pmc_graph pmc_graph;
 
 /* Capture one complete dose calculation of `req` into a HIP graph bound to
- * the given device buffers: zero dev_tally[i] and dev_counters, transport
- * all listed phases, and (where dev_dose[i] is not NULL) convert each tally
- * into Gy per history.  The graph owns a private copy of the request's
- * device data, so later calls on the context do not affect it; it must be
- * destroyed before its context.  dev_counters is required (the balance of a
- * replay is read from it).  Every reset inside the graph is a kernel, not a
- * memset.  Replays on one graph must not overlap in time. */
+ * the given device buffers (the batching of Sec. 2.C's N_g runs into one
+ * replayable launch): zero dev_tally[i] and dev_counters, transport all
+ * listed phases, and (where dev_dose[i] is not NULL) convert each tally into
+ * Gy per history.  The graph owns a private copy of the request's device
+ * data (plan, work items), so later plan loads do not affect it; it reads
+ * the listed phases' device grids in place, so it must be destroyed before
+ * its context.  dev_counters is required (the balance of a replay is read
+ * from it).  Every reset inside the graph is a kernel, not a memset.
+ * Replays on one graph must not overlap in time. */
 int pmc_graph_create(pmc_context *ctx, const pmc_request *req, int64_t *const *dev_tally,
                      uint64_t *dev_counters, double *const *dev_dose, pmc_graph **out);
 
-/* Replay a captured graph on `stream` (a hipStream_t; NULL = default stream). */
+/* Replay a captured graph on `stream` (a hipStream_t; NULL = default stream).
+ * PMC_E_STATE, with nothing launched, if a phase the graph reads was unloaded
+ * or replaced (pmc_load_phase on its id) since the capture: the graph is
+ * stale and can only be destroyed. */
 int pmc_graph_launch(pmc_graph *g, void *stream);
 
 /* Free a graph and its device data.  NULL-safe. */
@@ -522,12 +527,14 @@ typedef struct {
  * Random numbers: Philox4x32-10, key (seed mod 2^32, trial), counter (field,
  * purpose, index, block); purpose 0 start phase, 1 synchrotron parameter
  * (index = its position above), 2 breathing phase occurrence k, 3 period;
- * a Gaussian z is the sum of the 12 words of blocks 0..2 times 2^-32, minus
- * 6; U{0..n-1} is floor(word 0 of block 0 x n / 2^32).
+ * a Gaussian z ~ N(0, 1) (the N(mu, sigma) draws of Sec. 2.B and App. A)
+ * is sqrt(-2 ln u_a) cos(2 pi u_b) in FP64 with u = (x + 1/2) 2^-32 of words
+ * 0 and 1 of block 0 (|z| <= 6.77); U{0..n-1} is floor(word 0 of block 0 x
+ * n / 2^32).
  * Outputs (host buffers, each nullable): mu_out[trial][spot][phase] (MU),
  * time_out[trial][field] (end of the last delivery, s), fills_out
  * [trial][field] (synchrotron fills).  PMC_E_INVAL for invalid options or
- * spots, including spill rates that a draw within +-6 sigma could make <= 0
+ * spots, including spill rates that a draw within +-6.8 sigma could make <= 0
  * at a spot's energy.  Blocks until done. */
 int pmc_delivery_simulate(pmc_context *ctx, const pmc_delivery *d, const pmc_spot *spots, int64_t n_spots,
                           int32_t n_fields, double *mu_out, double *time_out, int32_t *fills_out);

@@ -65,6 +65,7 @@ TRACE_DTYPE = np.dtype([
     ("cause", "<i4"), ("voxel", "<i4"), ("fate", "<i4"), ("block", "<u4"),
     ("s", "<f8"), ("E", "<f8"), ("r", "<f8", 3), ("w", "<f8", 3),
     ("n_delta", "<f8"), ("n_nuc", "<f8"), ("l_acc", "<f8"), ("dep", "<i8"), ("t_delta", "<f8"),
+    ("margin", "<f8"),
 ])
 
 

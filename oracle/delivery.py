@@ -13,9 +13,10 @@ those of the library's documentation of pmc_delivery_simulate:
   given or U{min..max} seconds per trial and field;
 * synchrotron parameters are drawn once per trial and field as
   central + sd z, clipped at 0;
-* z is the sum of 12 uniforms minus 6 (each uniform x 2^-32 of a Philox word,
-  key (seed mod 2^32, trial), counter (field, purpose, index, block)), exact
-  in FP64;
+* z ~ N(0, 1) (the paper's N(mu, sigma) draws, Sec. 2.B and App. A) by the
+  Box-Muller transform in FP64, z = sqrt(-2 ln u_a) cos(2 pi u_b), from the
+  first two words of one Philox block, key (seed mod 2^32, trial), counter
+  (field, purpose, index, 0), each word x as u = (x + 1/2) 2^-32;
 * a layer is the run of consecutive spots of one field with one energy; each
   layer costs a layer switch a + b (E - 70 MeV); every fill of the synchrotron
   starts by waiting for the gate (gated delivery) and discarding beam;
@@ -27,9 +28,19 @@ those of the library's documentation of pmc_delivery_simulate:
   discard); a delivery that finds the gate closed waits for it and discards
   beam again; the delivery belongs wholly to the breathing phase at its start
   and lasts MU / (c + d (E - 70 MeV)).
+
+The logarithm and cosine are the host's libm, so another implementation of
+the same definition (the device's) may differ in the last bit of z.  Every
+decision that such a difference could flip is a comparison of two FP64
+values; `simulate` records, per (trial, field), the smallest relative gap
+|a - b| / max(|a|, |b|) among them (phase boundaries against delivery
+times, the fill's charge against the next delivery's MU, the extraction
+time against its limit), so that a comparison can tell a last-bit flip at a
+near tie from a real difference.
 """
 from __future__ import annotations
 
+import math
 from typing import Dict
 
 import numpy as np
@@ -38,6 +49,7 @@ import oracle
 from paper_1809_03927_amd.workloads import SYNC_PARAMS
 
 TWO_M32 = 2.0 ** -32
+TWO_PI = 2.0 * math.pi
 P_START, P_SYNC, P_BREATH, P_PERIOD = 0, 1, 2, 3
 
 
@@ -46,12 +58,18 @@ def words(key, field, purpose, index, block):
 
 
 def gauss(key, field, purpose, index) -> float:
-    """Sum of 12 uniforms x 2^-32 minus 6 (mean 0, variance 1)."""
-    total = 0.0
-    for block in range(3):
-        for x in words(key, field, purpose, index, block):
-            total = total + x * TWO_M32
-    return total - 6.0
+    """A standard normal deviate by Box-Muller: u = (x + 1/2) 2^-32 of the
+    first two words of block 0, z = sqrt(-2 ln u_a) cos(2 pi u_b)."""
+    w = words(key, field, purpose, index, 0)
+    ua = (w[0] + 0.5) * TWO_M32
+    ub = (w[1] + 0.5) * TWO_M32
+    return math.sqrt(-2.0 * math.log(ua)) * math.cos(TWO_PI * ub)
+
+
+def gap(a, b) -> float:
+    """Relative gap of a comparison of a with b."""
+    m = max(abs(a), abs(b))
+    return abs(a - b) / m if m > 0.0 else 0.0
 
 
 def draw_int(key, field, purpose, n) -> int:
@@ -67,6 +85,7 @@ class Breathing:
         self.k = 0
         self.t0 = 0.0
         self.t1 = self.length(0)
+        self.margin = math.inf
 
     def length(self, k):
         p = self.mu + self.d.period_sd_s * gauss(self.key, self.field, P_BREATH, k)
@@ -74,11 +93,20 @@ class Breathing:
             p = self.mu / 20.0
         return p / self.d.n_phases
 
-    def phase(self, t):
+    def phase(self, t, log=True):
+        """Phase at time t (t never decreases).  With log, the gaps of the
+        comparisons with the boundaries go into the margin; without, t is a
+        boundary itself (the gate's opening), an exact comparison."""
+        moved = False
         while t >= self.t1:
+            if log:
+                self.margin = min(self.margin, gap(t, self.t1))
             self.k += 1
             self.t0 = self.t1
             self.t1 = self.t0 + self.length(self.k)
+            moved = True
+        if log or moved:
+            self.margin = min(self.margin, gap(t, self.t1))
         return (self.phi0 + self.k) % self.d.n_phases
 
     def gated_open(self, ph):
@@ -89,19 +117,21 @@ class Breathing:
         ph = self.phase(t)
         while not self.gated_open(ph):
             t = self.t1
-            ph = self.phase(t)
+            ph = self.phase(t, log=False)
         return t
 
 
 def simulate(spots: np.ndarray, n_fields: int, d) -> Dict[str, np.ndarray]:
     """spots: structured array (energy_MeV, x_mm, y_mm, weight = MU, field) in
     delivery order within each field.  Returns mu (n_trials, n_spots, N), the
-    end time (n_trials, n_fields) in s and the number of synchrotron fills."""
+    end time (n_trials, n_fields) in s, the number of synchrotron fills and
+    the smallest relative gap of a decision per (trial, field) ("margin")."""
     n = len(spots)
     N = d.n_phases
     mu_out = np.zeros((d.n_trials, n, N))
     t_out = np.zeros((d.n_trials, n_fields))
     fills_out = np.zeros((d.n_trials, n_fields), dtype=np.int64)
+    margin_out = np.full((d.n_trials, n_fields), np.inf)
     gated = d.gate_lo >= 0
     for trial in range(d.n_trials):
         key = [d.seed & 0xFFFFFFFF, trial]
@@ -159,6 +189,9 @@ def simulate(spots: np.ndarray, n_fields: int, d) -> Dict[str, np.ndarray]:
                             dx, dy = abs(x - prev[0]), abs(y - prev[1])
                             t = t + (par["spot_switch_s"] + par["spot_switch_per_mm"] * (dx if dx > dy else dy))
                         spill = m / rate
+                        if not fresh:
+                            br.margin = min(br.margin, gap(m, q),
+                                            gap((t - t_ext) + spill, par["extraction_max_s"]))
                         if not fresh and (m > q or (t - t_ext) + spill > par["extraction_max_s"]):
                             t = t + switch
                             t = br.wait_gate(t) + par["discard_s"]
@@ -178,4 +211,5 @@ def simulate(spots: np.ndarray, n_fields: int, d) -> Dict[str, np.ndarray]:
                     r += 1
             t_out[trial, field] = t
             fills_out[trial, field] = fills
-    return {"mu": mu_out, "time": t_out, "fills": fills_out}
+            margin_out[trial, field] = br.margin
+    return {"mu": mu_out, "time": t_out, "fills": fills_out, "margin": margin_out}

@@ -298,27 +298,52 @@ static void rotate(double w[3], double theta, double phi) {
 
 static void trace_put(orc_trace_rec *rec, int32_t max_rec, int32_t *nrec, int cause, int64_t v,
                       int fate, uint32_t block, double s, double E, const double r[3],
-                      const double w[3], double nd, double nn, double la, int64_t dep, double td) {
+                      const double w[3], double nd, double nn, double la, int64_t dep, double td,
+                      double margin) {
   if (!rec || *nrec >= max_rec) { if (rec) ++*nrec; return; }
   orc_trace_rec *p = &rec[*nrec];
   p->cause = cause; p->voxel = (int32_t)v; p->fate = fate; p->block = block;
   p->s = s; p->E = E;
   for (int k = 0; k < 3; ++k) { p->r[k] = r[k]; p->w[k] = w[k]; }
   p->n_delta = nd; p->n_nuc = nn; p->l_acc = la; p->dep = dep; p->t_delta = td;
+  p->margin = margin;
   ++*nrec;
+}
+
+/* Decision margins (traces only): the relative gap |a - b| / max(|a|, |b|)
+ * of a comparison of a with b, folded into *m by min.  Infinite operands
+ * (a zero coefficient) decide nothing. */
+static inline void gap(double *m, double a, double b) {
+  if (!m || isinf(a) || isinf(b)) return;
+  double x = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+  double g = x > 0.0 ? fabs(a - b) / x : 0.0;
+  if (g < *m) *m = g;
+}
+
+/* the gap of the smallest of n values to the next smallest */
+static void gap_min2(double *m, const double *x, int n) {
+  if (!m) return;
+  double a = HUGE_VAL, b = HUGE_VAL;
+  for (int i = 0; i < n; ++i) {
+    if (x[i] < a) { b = a; a = x[i]; }
+    else if (x[i] < b) b = x[i];
+  }
+  gap(m, a, b);
 }
 
 /* Hard delta-ray energy: T from the 1/T^2 part of the free-electron spectrum
  * on [T_cut, Tmax] by inversion, accepted with probability 1 - beta^2 T/Tmax.
  * Each block gives two trials, (u0,u1) and (u2,u3). */
 static double sample_delta(const uint32_t key[2], uint32_t *block, uint32_t h, uint32_t s,
-                           kin_t k) {
+                           kin_t k, double *m) {
   for (;;) {
     double q[4];
     draw4(key, (*block)++, h, s, q);
     double t1 = 1.0 / (1.0 / T_CUT - q[0] * (1.0 / T_CUT - 1.0 / k.tmax));
+    gap(m, q[1], 1.0 - k.beta2 * t1 / k.tmax);
     if (q[1] < 1.0 - k.beta2 * t1 / k.tmax) return t1;
     double t2 = 1.0 / (1.0 / T_CUT - q[2] * (1.0 / T_CUT - 1.0 / k.tmax));
+    gap(m, q[3], 1.0 - k.beta2 * t2 / k.tmax);
     if (q[3] < 1.0 - k.beta2 * t2 / k.tmax) return t2;
   }
 }
@@ -355,24 +380,34 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
   for (int k = 0; k < 3; ++k)
     p[k] = 0.1 * (f->isocentre_mm[k] - ph->origin_mm[k]) + a * bu[k] + b * bv[k];
 
+  /* decision margin of the step being traced (NULL: not tracing) */
+  double mg_val = HUGE_VAL, *mg = rec ? &mg_val : NULL;
   /* entry into the grid box [0, ext) along the line p + t w (slab method) */
   double tn = -HUGE_VAL, tf = HUGE_VAL;
+  double t_lo[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
   int an = -1, missed = 0;
   for (int k = 0; k < 3; ++k) {
     if (w[k] != 0.0) {
       double t1 = (0.0 - p[k]) / w[k], t2 = (c->ext[k] - p[k]) / w[k];
       double lo = t1 < t2 ? t1 : t2, hi = t1 < t2 ? t2 : t1;
+      t_lo[k] = lo;
       if (lo > tn) { tn = lo; an = k; }
       if (hi < tf) tf = hi;
     } else if (p[k] < 0.0 || p[k] >= c->ext[k]) {
       missed = 1;
     }
   }
+  if (mg) { /* which face is entered, and whether the box is hit at all */
+    double neg[3] = {-t_lo[0], -t_lo[1], -t_lo[2]};
+    gap_min2(mg, neg, 3);
+    gap(mg, tn, tf);
+  }
   if (an < 0 || !(tn < tf)) missed = 1;
   if (missed) {
     acc->escaped += (u128)Qe(E);
     acc->misses++;
-    trace_put(rec, max_rec, nrec, -1, -1, ORC_FATE_MISSED, 1u, 0.0, E, p, w, n_delta, n_nuc, 0.0, 0, 0.0);
+    trace_put(rec, max_rec, nrec, -1, -1, ORC_FATE_MISSED, 1u, 0.0, E, p, w, n_delta, n_nuc, 0.0, 0, 0.0,
+              HUGE_VAL);
     return;
   }
   int idx[3];
@@ -382,7 +417,9 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
     if (k == an) {
       idx[k] = w[k] > 0.0 ? 0 : c->n[k] - 1;
     } else {
-      int i = (int)floor(r[k] / c->d[k]);
+      double q = r[k] / c->d[k];
+      int i = (int)floor(q);
+      gap(mg, q, floor(q + 0.5)); /* a coordinate on a voxel face */
       if (i < 0) i = 0;
       if (i > c->n[k] - 1) i = c->n[k] - 1;
       idx[k] = i;
@@ -391,7 +428,8 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
   int64_t v = (int64_t)idx[0] + (int64_t)c->n[0] * ((int64_t)idx[1] + (int64_t)c->n[1] * idx[2]);
   uint32_t block = 1u;
   double l_acc = 0.0;
-  trace_put(rec, max_rec, nrec, -1, v, ORC_FATE_ALIVE, block, 0.0, E, r, w, n_delta, n_nuc, l_acc, 0, 0.0);
+  trace_put(rec, max_rec, nrec, -1, v, ORC_FATE_ALIVE, block, 0.0, E, r, w, n_delta, n_nuc, l_acc, 0, 0.0,
+            mg_val);
 
   int fate = ORC_FATE_ALIVE;
   uint64_t steps = 0;
@@ -401,6 +439,7 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
       acc->escapes++;
       break;
     }
+    mg_val = HUGE_VAL;
     /* 1. material of the current voxel */
     double rho, rsp;
     material(ph, ph->hu[v], &rho, &rsp);
@@ -409,14 +448,17 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
     /* 2. distance to the voxel boundary; lowest axis wins ties */
     double dgeo = HUGE_VAL;
     int ax = -1;
+    double t_ax[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL};
     for (int k = 0; k < 3; ++k) {
       double t;
       if (w[k] > 0.0) t = ((double)(idx[k] + 1) * c->d[k] - r[k]) / w[k];
       else if (w[k] < 0.0) t = ((double)idx[k] * c->d[k] - r[k]) / w[k];
       else continue;
       if (t < 0.0) t = 0.0;
+      t_ax[k] = t;
       if (t < dgeo) { dgeo = t; ax = k; }
     }
+    gap_min2(mg, t_ax, 3); /* which face is reached first */
 
     /* 3-4. physics limits and the step; priority on ties:
      * stop > geo > delta > nuclear > phys */
@@ -433,6 +475,11 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
       double d_nuc = dist(n_nuc, mun * rho);
       if (d_del < 0.0) d_del = 0.0; /* rounding can leave a counter a hair below 0 */
       if (d_nuc < 0.0) d_nuc = 0.0;
+      if (mg) { /* which limit is the shortest; the nuclear switch at E_N */
+        double cand[5] = {s_stop, dgeo, d_del, d_nuc, s_phys};
+        gap_min2(mg, cand, 5);
+        if (!(flags & ORC_NO_NUCLEAR)) gap(mg, E, E_N);
+      }
       s = s_stop;
       cause = ORC_CAUSE_STOP;
       if (dgeo < s) { s = dgeo; cause = ORC_CAUSE_GEO; }
@@ -461,9 +508,12 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
           double sw = rsp * s;
           double g = (flags & ORC_NO_STRAGGLING) ? 0.0 : sqrt(-2.0 * log(u[0])) * cos(TWO_PI * u[1]);
           double dE = (E - rinv_t(T, R - sw)) + sqrt(om2 * sw) * g;
+          gap(mg, dE + E, E); /* the clamps of the loss to [0, E], and the cutoff */
+          gap(mg, dE, E);
           if (dE < 0.0) dE = 0.0;
           if (dE > E) dE = E;
           double En = E - dE;
+          gap(mg, En, E_LO);
           if (En <= E_LO) fate = ORC_FATE_STOPPED;
           else E = En;
         }
@@ -492,8 +542,10 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
       /* 10. events at the step end */
       if (fate == ORC_FATE_ALIVE && cause == ORC_CAUSE_DELTA) {
         kin_t k = kinematics(E);
+        gap(mg, k.tmax, T_CUT);
         if (k.tmax > T_CUT) {
-          double T_d = sample_delta(c->key, &block, h, s32, k);
+          double T_d = sample_delta(c->key, &block, h, s32, k, mg);
+          gap(mg, T_d, E - E_LO);
           if (T_d > E - E_LO) T_d = E - E_LO;
           t_delta = T_d;
           acc->delta_events++;
@@ -501,6 +553,7 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
             double En = E - T_d;
             dep += Qe(E) - Qe(En);
             E = En;
+            gap(mg, E, E_LO);
             if (E <= E_LO) {
               dep += Qe(E);
               acc->cutoff += (u128)Qe(E);
@@ -534,7 +587,7 @@ static void transport(const hctx *c, int64_t spot, uint32_t h, int64_t *tally, a
     }
     double E_rec = (fate == ORC_FATE_STOPPED) ? 0.0 : E;
     trace_put(rec, max_rec, nrec, cause, v_step, fate, block, s, E_rec, r, w, n_delta, n_nuc, l_acc,
-              dep, t_delta);
+              dep, t_delta, mg_val);
   }
 }
 
@@ -770,7 +823,7 @@ int orc_sample_delta(double E, uint32_t seed, uint32_t request_id, uint32_t h, u
   if (!(k.tmax > T_CUT)) return -1;
   uint32_t key[2] = {seed, request_id};
   uint32_t block = 0;
-  for (int32_t i = 0; i < n; ++i) T_out[i] = sample_delta(key, &block, h, s, k);
+  for (int32_t i = 0; i < n; ++i) T_out[i] = sample_delta(key, &block, h, s, k, NULL);
   return 0;
 }
 

@@ -70,6 +70,10 @@ typedef struct {
   double n_delta, n_nuc, l_acc;
   int64_t dep;     /* energy tallied in `voxel` by this step, 2^-32 MeV units */
   double t_delta;  /* energy of the delta ray produced at the step end (0 if none) */
+  double margin;   /* smallest relative gap of a decision taken in this step (which
+                      axis or cause limits it, clamps, cutoffs, delta acceptance):
+                      where another implementation, equal to rounding, may decide
+                      otherwise */
 } orc_trace_rec;
 
 typedef struct {

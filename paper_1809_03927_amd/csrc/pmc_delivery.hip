@@ -4,8 +4,9 @@
 // (layer switch, wait for the gate, discarded beam), spills and spot switches,
 // refills on charge or extraction time, isolayered repainting.  Every random
 // number is a Philox word keyed by (seed, trial) at counter (field, purpose,
-// index, block); a Gaussian is the sum of 12 uniforms minus 6, exact in FP64,
-// so with the FP64 operations below the result is reproducible bit for bit.
+// index, block); a Gaussian N(0, 1) is the Box-Muller transform of the first
+// two words of one block, in FP64.  The walk itself is the same sequence of
+// FP64 operations on every run, so the result is reproducible bit for bit.
 #include <hip/hip_runtime.h>
 
 #include "pmc_device.hpp"
@@ -19,16 +20,13 @@ enum { kSwitch = 0, kSwitchPerMev, kDiscard, kRate, kRatePerMev, kSpotSwitch, kS
        kExtractionMax };
 constexpr long long kMaxAdvances = 1LL << 30;  // breathing phases per thread before giving up
 
+// z = sqrt(-2 ln u_a) cos(2 pi u_b), u = (x + 1/2) 2^-32 of the words x, y of
+// block 0: |z| <= sqrt(66 ln 2) = 6.77 (the smallest u is 2^-33).
 __device__ double gauss(uint32_t k0, uint32_t k1, uint32_t field, uint32_t purpose, uint32_t index) {
-  double total = 0.0;
-  for (uint32_t b = 0; b < 3; ++b) {
-    const uint4 x = philox(field, purpose, index, b, k0, k1);
-    total = total + (double)x.x * 0x1p-32;
-    total = total + (double)x.y * 0x1p-32;
-    total = total + (double)x.z * 0x1p-32;
-    total = total + (double)x.w * 0x1p-32;
-  }
-  return total - 6.0;
+  const uint4 x = philox(field, purpose, index, 0u, k0, k1);
+  const double ua = ((double)x.x + 0.5) * 0x1p-32;
+  const double ub = ((double)x.y + 0.5) * 0x1p-32;
+  return sqrt(-2.0 * log(ua)) * cos(6.283185307179586 * ub);
 }
 
 __device__ __forceinline__ int draw_int(uint32_t k0, uint32_t k1, uint32_t field, uint32_t purpose, uint32_t n) {

@@ -116,6 +116,7 @@ struct Prepared {
 struct pmc_graph {
   pmc_context *ctx = nullptr;
   std::vector<int32_t> phases;  // phases the graph's kernels read
+  std::vector<uint64_t> versions;  // their versions at capture: the graph holds their device pointers
   void *data = nullptr;  // private copy of the request data + work-queue cursor
   size_t bytes = 0;
   hipGraph_t graph = nullptr;
@@ -1608,6 +1609,7 @@ int pmc_graph_create(pmc_context *ctx, const pmc_request *req, int64_t *const *d
   pmc_graph *g = new pmc_graph();
   g->ctx = ctx;
   g->phases.assign(req->phases, req->phases + req->n_phases);
+  for (int32_t ph : g->phases) g->versions.push_back(ctx->phases[ph].version);
   g->bytes = bytes;
   auto bail = [&](hipError_t e, const char *what) {
     const int code = hip_fail(ctx, e, what);
@@ -1672,11 +1674,18 @@ int pmc_graph_launch(pmc_graph *g, void *stream) {
   if (!g) return fail(nullptr, PMC_E_INVAL, "graph is NULL");
   pmc_context *ctx = g->ctx;
   ctx->err.clear();
+  // the captured kernels read the phases' HU grids, masks and LUTs by
+  // address: a phase unloaded or replaced since the capture has returned
+  // that memory to the pool, so the graph must not run
+  for (size_t i = 0; i < g->phases.size(); ++i) {
+    auto it = ctx->phases.find(g->phases[i]);
+    if (it == ctx->phases.end() || it->second.version != g->versions[i])
+      return fail(ctx, PMC_E_STATE, "phase %d was unloaded or replaced since the graph was captured",
+                  g->phases[i]);
+  }
   HIP_TRY(ctx, hipGraphLaunch(g->exec, (hipStream_t)stream), "hipGraphLaunch");
   for (int32_t ph : g->phases) {
-    auto it = ctx->phases.find(ph);
-    if (it == ctx->phases.end()) continue;
-    const int rc = note_use(ctx, it->second.uses, (hipStream_t)stream);
+    const int rc = note_use(ctx, ctx->phases[ph].uses, (hipStream_t)stream);
     if (rc) return rc;
   }
   return note_pending(ctx, (hipStream_t)stream);
@@ -2607,7 +2616,8 @@ int pmc_delivery_simulate(pmc_context *ctx, const pmc_delivery *d, const pmc_spo
   const double out_bytes = (double)d->n_trials * (double)n_spots * (double)d->n_phases * 8.0;
   if (out_bytes > 64e9) return fail(ctx, PMC_E_INVAL, "trials x spots x phases too large");
   // spots grouped by field, plan order kept within a field; spill rates
-  // positive for any draw within +-6 sigma (a 12-uniform Gaussian never leaves it)
+  // positive for any draw within +-6.8 sigma (the Box-Muller deviate of two
+  // 32-bit uniforms never leaves +-6.77)
   std::vector<int32_t> fstart((size_t)n_fields + 1, 0);
   for (int64_t i = 0; i < n_spots; ++i) {
     const pmc_spot &sp = spots[i];
@@ -2616,8 +2626,8 @@ int pmc_delivery_simulate(pmc_context *ctx, const pmc_delivery *d, const pmc_spo
         !std::isfinite(sp.x_mm) || !std::isfinite(sp.y_mm) || !(std::isfinite(sp.weight) && sp.weight > 0.0))
       return fail(ctx, PMC_E_INVAL, "spot %lld: energy 1..300 MeV, finite position, MU > 0", (long long)i);
     const double de = sp.energy_MeV - 70.0;
-    const double c = par[3].central - 6.0 * par[3].sd;
-    const double s_lo = (par[4].central - 6.0 * par[4].sd) * de, s_hi = (par[4].central + 6.0 * par[4].sd) * de;
+    const double c = par[3].central - 6.8 * par[3].sd;
+    const double s_lo = (par[4].central - 6.8 * par[4].sd) * de, s_hi = (par[4].central + 6.8 * par[4].sd) * de;
     if (!(c + std::min(s_lo, s_hi) > 0.0))
       return fail(ctx, PMC_E_INVAL, "spill rate can reach <= 0 at %g MeV", sp.energy_MeV);
     ++fstart[(size_t)sp.field + 1];

@@ -117,11 +117,44 @@ def test_random_trials_conserve_mu_and_respect_the_gate():
 
 
 def test_draws():
+    """The delivery Gaussians are N(0, 1) (Sec. 2.B, App. A: N(mu, sigma)):
+    Kolmogorov-Smirnov against scipy's normal CDF, the fourth moment (3 for a
+    normal; the 12-uniform sum this replaced has 2.9, six standard errors
+    away at this sample size) and the tail beyond 3 sigma; |z| <= 6.77 (the
+    smallest uniform is 2^-33).  Start phases and periods cover their ranges."""
+    from scipy import stats
     key = [5, 2]
-    z = np.array([DL.gauss(key, 0, 2, k) for k in range(3000)])
-    assert abs(z.mean()) < 0.06 and abs(z.var() - 1.0) < 0.08
-    assert z.min() >= -6.0 and z.max() <= 6.0
+    z = np.array([DL.gauss(key, f, 2, k) for f in range(4) for k in range(25000)])
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 0.02 and abs(z.var() - 1.0) < 0.02
+    kurt = np.mean(z ** 4) / np.mean(z ** 2) ** 2
+    assert abs(kurt - 3.0) < 0.06, kurt
+    tail = np.mean(np.abs(z) > 3.0)
+    assert abs(tail - 2 * stats.norm.sf(3.0)) < 4 * np.sqrt(2.7e-3 / len(z)), tail
+    assert np.abs(z).max() <= np.sqrt(66 * np.log(2.0))
     starts = {DL.draw_int([s, 0], 0, DL.P_START, 10) for s in range(200)}
     assert starts == set(range(10))
     periods = {3 + DL.draw_int([s, 0], 0, DL.P_PERIOD, 5) for s in range(200)}
     assert periods == {3, 4, 5, 6, 7}
+
+
+def test_margin_logs_near_ties():
+    """The oracle's margin is the smallest relative gap of a decision a
+    last-bit difference could flip.  Hand timeline with a 2.05 s layer
+    switch (phases of 0.4 s from phase 0): the first fill's gate check at
+    2.05, starts 2.12, 2.23, 2.44 (phase 6), end 2.74; the second layer's
+    check at 4.79, 0.01 s before the boundary at 4.8 -- the smallest gap,
+    0.01 / 4.8 -- then starts 4.86 and 4.97.  A switch that ends exactly on
+    a boundary logs 0, one that ends 1e-13 s before it logs below 1e-12."""
+    sp = spots([(70.0, 0, 0, 1.0, 0), (70.0, 5, 0, 2.0, 0), (70.0, 10, 0, 3.0, 0),
+                (100.0, 0, 0, 1.0, 0), (100.0, 5, 0, 1.0, 0)])
+    d = W.Delivery(n_phases=10, start_phase=0, period_s=4.0, sync=fixed(switch=2.05))
+    out = DL.simulate(sp, 1, d)
+    assert phases_of(out["mu"][0]) == [5, 5, 6, 2, 2]
+    assert out["time"][0, 0] == pytest.approx(5.07, abs=1e-12)
+    assert out["margin"][0, 0] == pytest.approx(0.01 / 4.8, rel=1e-9)
+    on = DL.simulate(sp[:1], 1, W.Delivery(n_phases=10, start_phase=0, period_s=4.0, sync=fixed(switch=2.0)))
+    assert on["margin"][0, 0] < 1e-15
+    near = DL.simulate(sp[:1], 1, W.Delivery(n_phases=10, start_phase=0, period_s=4.0,
+                                             sync=fixed(switch=2.0 - 1e-13)))
+    assert 0 < near["margin"][0, 0] < 1e-12

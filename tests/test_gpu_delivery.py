@@ -1,12 +1,15 @@
 """Beam-delivery simulation on the GPU (pmc_delivery_simulate, through the C
 ABI) against the oracle (`oracle.delivery`): the same Philox draws and the
-same FP64 operations in the same order, so MU per phase, end times and fill
-counts are bit-identical."""
+same FP64 operations in the same order; the Box-Muller logarithm and cosine
+are the device's and the host's, so MU per phase and fill counts are
+identical and end times agree to 1e-12 except in a timeline with a decision
+at a near tie (logged by the oracle; see `delivery_check`)."""
 import sys
 
 import numpy as np
 import pytest
 
+from delivery_check import compare, same
 from paper_1809_03927_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -36,12 +39,6 @@ def run(P, d, sp, n_fields):
         P.pmc_destroy(ctx)
 
 
-def same(got, want):
-    assert np.array_equal(got["fills"], want["fills"])
-    assert np.array_equal(got["time"], want["time"])
-    assert np.array_equal(got["mu"], want["mu"])
-
-
 def test_hand_computed_timeline(P, DL):
     sp = np.zeros(5, dtype=W.SPOT_DTYPE)
     sp["energy_MeV"] = [70.0, 70.0, 70.0, 100.0, 100.0]
@@ -56,7 +53,8 @@ def test_hand_computed_timeline(P, DL):
     got = run(P, d, sp, 1)
     assert got["time"][0, 0] == pytest.approx(4.97, abs=1e-12)
     assert [int(np.flatnonzero(r)[0]) for r in got["mu"][0]] == [5, 5, 5, 1, 2]
-    same(got, DL.simulate(sp, 1, d))
+    # every standard deviation is 0: no draw reaches the timeline
+    same(got, {k: v for k, v in DL.simulate(sp, 1, d).items() if k != "margin"})
 
 
 @pytest.mark.parametrize("mode", ["free", "gated", "repainted"])
@@ -77,7 +75,7 @@ def test_random_trials_match_oracle(P, DL, mode):
     say("delivery random trials", mode)
     got = run(P, d, sp, len(plan.fields))
     want = DL.simulate(sp, len(plan.fields), d)
-    same(got, want)
+    compare(got, want, sp, len(plan.fields), max_flips=1)
     assert np.allclose(got["mu"].sum(axis=2), np.broadcast_to(sp["weight"], (6, len(sp))), rtol=1e-12)
 
 
@@ -95,7 +93,7 @@ def test_three_fields(P, DL):
     d = W.Delivery(n_trials=4, period_sd_s=0.3, gate_lo=2, gate_hi=6, max_mu=0.02, seed=5)
     say("delivery three fields")
     got = run(P, d, sp, len(plan.fields))
-    same(got, DL.simulate(sp, len(plan.fields), d))
+    compare(got, DL.simulate(sp, len(plan.fields), d), sp, len(plan.fields), max_flips=1)
 
 
 def test_degenerate_deliveries(P, DL):
@@ -109,7 +107,7 @@ def test_degenerate_deliveries(P, DL):
     say("delivery: empty second field")
     got = run(P, W.Delivery(**base), sp, 2)
     want = DL.simulate(sp, 2, W.Delivery(**base))
-    same(got, want)
+    compare(got, want, sp, 2, max_flips=1)
     assert not got["time"][:, 1].any() and not got["fills"][:, 1].any()
     say("delivery: one phase")
     one = run(P, W.Delivery(n_phases=1, **base), sp, 1)

@@ -12,8 +12,8 @@ are compared with the oracle's tallies of exactly those histories (same
 keys) -- the history count and incident energy exactly (the FP32 engine's
 at the spot energy rounded to FP32), the dose voxel by voxel (voxels above
 10 % of the maximum pass if the difference is within 1 % of the maximum or
-3 sigma of the difference, sigma = sqrt 2 x the oracle's), the total
-deposited energy within 0.1 %.  The oracle's sigma comes from 50 batches of
+3 sigma of the difference, sigma = sqrt 2 x the oracle's; same seed, so at
+least 99.5 % of them), the total deposited energy within 0.1 %.  The oracle's sigma comes from 50 batches of
 the same histories rather than the 10 of the plan-wide check: with 9 degrees
 of freedom per voxel a 3-sigma bound alone fails about 1.5 % of the voxels
 of two results that agree in distribution (Student's t), with 49 about
@@ -28,6 +28,7 @@ import sys
 import numpy as np
 import pytest
 
+from parity import SAME_SEED_MIN_PASS
 from paper_1809_03927_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -188,7 +189,7 @@ def test_full_size_sampled_spots_against_oracle(full):
         frac = float(((dd <= 0.01 * dmax) | (dd <= 3.0 * sig[sel])).mean())
         e_rel = abs(float(t_g.sum()) - float(o_t[ph].sum())) / float(o_t[ph].sum())
         say(f"spot {s}: {int(sel.sum())} voxels above 10 %, pass {frac:.4f}, dE {e_rel:.2e}")
-        assert sel.sum() > 100 and frac >= 0.99 and e_rel <= 1e-3 and math.isfinite(e_rel)
+        assert sel.sum() > 100 and frac >= SAME_SEED_MIN_PASS and e_rel <= 1e-3 and math.isfinite(e_rel)
 
 
 def test_full_size_dim_sampled_voxels(full):
@@ -326,8 +327,10 @@ def test_full_size_delivery(full, scenario):
     the robust plan's three fields (8000 spots, 600 MU), 25 trials with
     random start phase, breathing period and synchrotron parameters, free,
     gated (phases 3-7) and repainted (0.005 MU per delivery).  Every trial is
-    independent, and the oracle replays all 25: MU per spot and phase, end
-    times and fill counts bit-identical."""
+    independent, and the oracle replays all 25: MU per spot and phase and
+    fill counts identical, end times within 1e-12, except in a timeline with
+    a logged near-tie decision (at most one of the 75)."""
+    from delivery_check import compare
     from oracle import delivery as OD
     pmc, _, e = full
     plan = W.plan_robust()
@@ -338,7 +341,7 @@ def test_full_size_delivery(full, scenario):
     say("full-size delivery", scenario)
     got = pmc.pmc_delivery_simulate(e.ctx, d, sp, len(plan.fields))
     want = OD.simulate(sp, len(plan.fields), d)
-    assert np.array_equal(got["mu"], want["mu"])
-    assert np.array_equal(got["time"], want["time"]) and np.array_equal(got["fills"], want["fills"])
+    flips = compare(got, want, sp, len(plan.fields), max_flips=1)
+    say(f"full-size delivery {scenario}: {flips} timelines with a flipped near-tie decision")
     # MU conserved per spot and trial
     assert np.allclose(got["mu"].sum(axis=2), sp["weight"][None, :], rtol=1e-12, atol=0)

@@ -74,6 +74,46 @@ def test_graph_replays_equal_eager(setup):
     pmc.pmc_graph_destroy(g)
 
 
+def test_graph_refuses_a_replaced_phase(setup):
+    """A graph reads its phases' device grids by address: after one of them
+    is replaced (pmc_load_phase on its id) or unloaded, the replay is
+    refused with PMC_E_STATE and nothing runs (the tallies keep the marker
+    the replay would have cleared); a graph captured afterwards runs."""
+    torch, pmc, wl, e = setup
+    st = torch.cuda.current_stream()
+    req = pmc.Request(50_000, [2, 3], engine=pmc.PMC_ENGINE_PERSISTENT)
+    t_g, d_g, c_g = buffers(torch, wl)
+    g = pmc.pmc_graph_create(e.ctx, req, [t_g[0].data_ptr(), t_g[1].data_ptr()], c_g.data_ptr(), None)
+    try:
+        pmc.pmc_graph_launch(g, st.cuda_stream, e.ctx)
+        torch.cuda.synchronize()
+        first = t_g[1].clone()
+        say("graph after a phase reload")
+        pmc.pmc_load_phase(e.ctx, 3, wl.phases[3])  # same content, new device memory
+        t_g[0].fill_(777)
+        t_g[1].fill_(777)
+        with pytest.raises(pmc.PmcError) as ex:
+            pmc.pmc_graph_launch(g, st.cuda_stream, e.ctx)
+        assert ex.value.code == pmc.PMC_E_STATE
+        torch.cuda.synchronize()
+        assert bool((t_g[0] == 777).all()) and bool((t_g[1] == 777).all())
+    finally:
+        pmc.pmc_graph_destroy(g)
+    g = pmc.pmc_graph_create(e.ctx, req, [t_g[0].data_ptr(), t_g[1].data_ptr()], c_g.data_ptr(), None)
+    try:
+        pmc.pmc_graph_launch(g, st.cuda_stream, e.ctx)
+        torch.cuda.synchronize()
+        assert torch.equal(t_g[1], first)
+        say("graph after unloading a phase")
+        pmc.pmc_unload_phase(e.ctx, 2)
+        with pytest.raises(pmc.PmcError) as ex:
+            pmc.pmc_graph_launch(g, st.cuda_stream, e.ctx)
+        assert ex.value.code == pmc.PMC_E_STATE
+    finally:
+        pmc.pmc_graph_destroy(g)
+        pmc.pmc_load_phase(e.ctx, 2, wl.phases[2])
+
+
 def test_autotune_candidates_identical(setup, tmp_path):
     torch, pmc, wl, e = setup
     from paper_1809_03927_amd import autotune

@@ -2,8 +2,10 @@
 
   * FP64 transport: per-step traces equal the oracle's to 1e-9 (relative),
     and the integer tallies agree to rounding of the last fixed-point unit.
-  * FP32 transport: per-voxel dose within 1 % of Dmax or 3 sigma in every
-    voxel above 10 % of Dmax, integral energy within 0.1 %.
+  * FP32 transport: the voxel criterion (above 10 % of Dmax: within 1 % of
+    Dmax or 3 sigma) in at least the fraction of voxels two oracle runs with
+    independent seeds reach, less 3 standard errors (and at least 0.995 with
+    the oracle's seed); integral energy within 0.1 % (tests/parity.py).
   * Integer invariants, bit-exact: plain == persistent engine for any launch
     shape, run-to-run identity, exact energy balance, and the paper's two 3D
     comparison tests (Sec. 2.E).
@@ -14,6 +16,7 @@ import sys
 import numpy as np
 import pytest
 
+from parity import SAME_SEED_MIN_PASS, calibration, dose_parity, independent_bar, oracle_with_sigma
 from paper_1809_03927_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -52,26 +55,50 @@ def compare_traces(gt, ot, rtol=1e-9, length_scale=30.0):
     lengths relative to max(1, |n|).  Step lengths are not compared relative
     to themselves: a boundary distance travelled almost parallel to a face is
     a tiny difference divided by a tiny direction cosine and carries the
-    last-bit differences of two coordinate representations."""
-    if len(gt) != len(ot):
-        return False, f"length {len(gt)} vs {len(ot)}"
+    last-bit differences of two coordinate representations.
+
+    Returns (ok, message, k) with k the first record that differs (None if
+    none does)."""
     E0 = float(ot[0]["E"])
     for k, (g, o) in enumerate(zip(gt, ot)):
         if g["cause"] != o["cause"] or g["fate"] != o["fate"] or g["voxel"] != o["voxel"] \
                 or g["block"] != o["block"]:
-            return False, f"step {k}: discrete state differs {g} vs {o}"
+            return False, f"step {k}: discrete state differs {g} vs {o}", k
         checks = [("E", E0), ("t_delta", E0), ("s", length_scale),
                   ("n_delta", max(1.0, abs(float(o["n_delta"])))),
                   ("n_nuc", max(1.0, abs(float(o["n_nuc"])))),
                   ("l_acc", max(1.0, abs(float(o["l_acc"]))))]
         for f, scale in checks:
             if abs(float(g[f]) - float(o[f])) > rtol * scale:
-                return False, f"step {k}: {f} {float(g[f])!r} vs {float(o[f])!r}"
+                return False, f"step {k}: {f} {float(g[f])!r} vs {float(o[f])!r}", k
         if np.max(np.abs(g["r"] - o["r"])) > rtol * length_scale or np.max(np.abs(g["w"] - o["w"])) > rtol:
-            return False, f"step {k}: r/w {g['r']} {o['r']} {g['w']} {o['w']}"
+            return False, f"step {k}: r/w {g['r']} {o['r']} {g['w']} {o['w']}", k
         if abs(int(g["dep"]) - int(o["dep"])) > max(2, int(rtol * E0 * Q)):
-            return False, f"step {k}: dep {g['dep']} vs {o['dep']}"
-    return True, ""
+            return False, f"step {k}: dep {g['dep']} vs {o['dep']}", k
+    if len(gt) != len(ot):
+        k = min(len(gt), len(ot))
+        return False, f"length {len(gt)} vs {len(ot)}", k
+    return True, "", None
+
+
+# A decision whose operands differ by less than this (relative) may go the
+# other way in an implementation equal to the oracle to rounding; traces
+# agree to 1e-9, so that is the level at which a decision can flip.
+TIE = 1e-9
+
+
+def check_trace(gt, ot, label):
+    """True if the traces agree; False if they differ only from a record whose
+    decisions the oracle logged at a near tie (traces equal to 1e-9 up to
+    it); an assertion error otherwise."""
+    ok, msg, k = compare_traces(gt, ot)
+    if ok:
+        return True
+    # the first differing record must hold a decision at a near tie
+    margin = float(ot[min(k, len(ot) - 1)]["margin"])
+    assert margin < TIE, f"{label}: {msg}; the oracle's decisions there have margin {margin:.3e}"
+    say(label, f"flipped at a near tie (margin {margin:.2e}): {msg}")
+    return False
 
 
 @pytest.mark.parametrize("name", ["tiny", "slabs", "hetero3"])
@@ -95,14 +122,11 @@ def test_fp64_trace_parity(P, orc, name):
         for h in range(40):
             gt = e.trace(0, s, h)
             ot = orc.trace(wl.phases[0], wl.plan, s, h, seed=wl.seed)
-            ok, msg = compare_traces(gt, ot)
             n += 1
-            n_ok += ok
-            if not ok:
-                msgs.append(f"spot {s} h {h}: {msg}")
+            n_ok += check_trace(gt, ot, f"spot {s} h {h}")
     e.close()
-    # a mismatch may only come from a discrete decision flipped by the last bit
-    assert n_ok >= n - max(1, n // 50), msgs[:3]
+    # every mismatch is a decision flipped at a near tie; such ties are rare
+    assert n_ok >= n - max(1, n // 50), (n_ok, n)
 
 
 def test_fp64_trace_parity_with_switches(P, orc):
@@ -111,8 +135,8 @@ def test_fp64_trace_parity_with_switches(P, orc):
     for flags in (1, 2, 4, 8, 16 | 1 | 4 | 8, 1 | 2 | 4 | 8):
         say("fp64 trace parity flags", flags)
         for h in range(5):
-            ok, msg = compare_traces(e.trace(0, 77, h, flags=flags),
-                                     orc.trace(wl.phases[0], wl.plan, 77, h, seed=wl.seed, flags=flags))
+            ok, msg, _ = compare_traces(e.trace(0, 77, h, flags=flags),
+                                        orc.trace(wl.phases[0], wl.plan, 77, h, seed=wl.seed, flags=flags))
             assert ok, (flags, h, msg)
     e.close()
 
@@ -137,70 +161,45 @@ def test_fp64_tally_matches_oracle(P, orc):
 # FP32 dose parity (statistical)
 # ----------------------------------------------------------------------------
 
-def oracle_with_sigma(orc, wl, n, n_batches=100):
-    """Oracle tally, its per-voxel standard deviation and the standard
-    deviation of its total, from history batches (history index mod
-    n_batches), accumulated one batch at a time."""
-    tot = None
-    sq = None
-    totals = []
-    for b in range(n_batches):
-        t, _ = orc.dose_subset(wl.phases, wl.plan, n, wl.seed, 0, 2**32 - 1, h_mod=n_batches, h_rem=b)
-        t = np.array(t, dtype=np.float64)
-        totals.append(t.sum())
-        tot = t if tot is None else tot + t
-        sq = t * t if sq is None else sq + t * t
-    mean = tot / n_batches
-    var_b = (sq - n_batches * mean * mean) / (n_batches - 1)
-    sigma_total = math.sqrt(n_batches * np.var(totals, ddof=1))
-    return tot, np.sqrt(np.maximum(var_b, 0.0) * n_batches), sigma_total
+def thorax128():
+    ph = W.make_thorax((128, 128, 80), 0)
+    plan = W.plan_thorax(3)
+    plan.spots["phase"] = 0
+    return W.Workload("thorax128", [ph], plan, 200_000, seed=3)
 
 
-def dose_parity(gpu_tally, orc_tally, orc_sigma, label):
-    """Voxels above 10 % of Dmax pass if |dD| <= 1 % Dmax or <= 3 sigma_diff
-    (sigma_diff = sqrt(2) sigma_oracle).  Tallies of equal history counts are
-    compared: dose is a per-voxel scaling of the tally.  Also returns the mean
-    and RMS of dD / sigma_diff over those voxels (bias and spread)."""
-    g = np.asarray(gpu_tally, dtype=np.float64)
-    o = np.asarray(orc_tally, dtype=np.float64)
-    dmax = o.max()
-    sel = o > 0.1 * dmax
-    d = g[sel] - o[sel]
-    sig = math.sqrt(2.0) * orc_sigma[sel]
-    ok = (np.abs(d) <= 0.01 * dmax) | (np.abs(d) <= 3.0 * sig)
-    frac = ok.mean()
-    z = d / np.maximum(sig, 1e-30)
-    e_rel = abs(g.sum() - o.sum()) / o.sum()
-    say(label, f"voxels>0.1Dmax={sel.sum()} pass={frac:.5f} dE={e_rel:.2e} "
-               f"mean z={z.mean():+.3f} rms z={np.sqrt(np.mean(z * z)):.3f}")
-    return frac, e_rel, float(z.mean()), float(np.sqrt(np.mean(z * z)))
+CASES = {"tiny": (W.workload_tiny, 100_000, "tiny_1e5"), "slabs": (W.workload_slabs, 300_000, "slabs_3e5"),
+         "thorax128": (thorax128, 200_000, "thorax128_2e5")}
 
 
-@pytest.mark.parametrize("name,n,seed_gpu", [("tiny", 100_000, None), ("tiny", 100_000, 99),
-                                             ("slabs", 300_000, None), ("slabs", 300_000, 77)])
-def test_fp32_dose_parity(P, orc, name, n, seed_gpu):
-    """Voxel criterion: above 10 % of the maximum, within 1 % of it or
-    3 sigma_diff.  With the oracle's own seed the FP32 and FP64
-    streams share their random numbers (to 2^-24) and must agree closely;
-    with an independent seed the comparison is purely statistical, and even
-    two oracle runs pass only ~97-99.7 % of voxels (coherent fluctuations,
-    e.g. in the number of nuclear removals), so the bar is set accordingly and
-    backed by bias and spread checks."""
-    wl = W.workload_tiny() if name == "tiny" else W.workload_slabs()
+@pytest.mark.parametrize("name,seed_gpu", [("tiny", None), ("tiny", 99), ("slabs", None), ("slabs", 77),
+                                           ("thorax128", None), ("thorax128", 33)])
+def test_fp32_dose_parity(P, orc, name, seed_gpu):
+    """The voxel criterion of `parity` (above 10 % of the maximum: within 1 %
+    of it or 3 sigma_diff, sigma from 100 oracle batches).  With an
+    independent seed the comparison is purely statistical and the GPU must
+    reach the pass fraction two oracle runs reach at the same counts, less 3
+    standard errors.  With the oracle's seed the FP32 and FP64 streams share
+    their random numbers, so the GPU must do at least that well and reach
+    0.995; the total energy must then agree within 0.1 %."""
+    make, n, cal = CASES[name]
+    wl = make()
     say("fp32 dose parity", name, n, "gpu seed", seed_gpu)
     e = engine(P, wl, P.PMC_FP32, seed=seed_gpu)
     _, tal, _, bal = e.dose(n, [0])
     e.close()
     check_balance(bal)
     ot, osig, sig_tot = oracle_with_sigma(orc, wl, n)
-    frac, e_rel, zmean, zrms = dose_parity(tal[0], ot[0], osig[0], f"{name} seed {seed_gpu}")
+    frac, e_rel, zmean, zrms, _ = dose_parity(tal[0], ot, osig, f"{name} seed {seed_gpu}")
     same_seed = seed_gpu is None
-    assert frac >= (0.99 if same_seed else 0.97), frac
+    bar = max(SAME_SEED_MIN_PASS, independent_bar(cal)) if same_seed else independent_bar(cal)
+    say(name, f"bar {bar:.5f} (oracle vs oracle {calibration(cal)['mean']:.5f})")
+    assert frac >= bar, (frac, bar)
     if same_seed:
         assert e_rel <= 1e-3, e_rel
     else:
-        assert e_rel * ot[0].sum() <= max(1e-3 * ot[0].sum(), 3 * math.sqrt(2) * sig_tot), e_rel
-        assert 0.8 < zrms < 1.3, zrms
+        assert e_rel * ot.sum() <= max(1e-3 * ot.sum(), 3 * math.sqrt(2) * sig_tot), e_rel
+        assert 0.6 < zrms < 1.3, zrms
     assert abs(zmean) < 0.2, zmean
 
 
@@ -264,21 +263,6 @@ def test_fp32_air_deposits_match_fp64(P):
         rel = a[sl].sum() / b[sl].sum() - 1.0
         say(name, f"FP32/FP64 - 1 = {rel:+.5f}")
         assert abs(rel) < 3e-3, (name, rel)
-
-
-def test_fp32_dose_parity_thorax_phase(P, orc):
-    ph = W.make_thorax((128, 128, 80), 0)
-    plan = W.plan_thorax(3)
-    plan.spots["phase"] = 0
-    wl = W.Workload("thorax128", [ph], plan, 200_000, seed=3)
-    say("fp32 dose parity thorax 128x128x80", wl.n_histories)
-    e = engine(P, wl, P.PMC_FP32)
-    _, tal, _, bal = e.dose(wl.n_histories, [0])
-    e.close()
-    check_balance(bal)
-    ot, osig, _ = oracle_with_sigma(orc, wl, wl.n_histories)
-    frac, e_rel, zmean, zrms = dose_parity(tal[0], ot[0], osig[0], "thorax")
-    assert frac >= 0.99 and e_rel <= 1e-3 and abs(zmean) < 0.2, (frac, e_rel, zmean)
 
 
 # ----------------------------------------------------------------------------
@@ -368,3 +352,36 @@ def test_conversion_is_the_oracle_definition(P, orc):
     # same definition; the two calibration interpolations round differently
     assert np.allclose(dens[0], orho, rtol=4e-16, atol=0)
     assert np.allclose(dose[0], od, rtol=1e-15, atol=0)
+
+
+@pytest.mark.timeout(900)
+def test_slabs_full_run_against_oracle(P, orc):
+    """The heterogeneous slab case in full: 500 spots, 1e7 histories, FP32 on
+    the persistent engine's default launch, against the oracle's 1e7
+    histories of the same keys (sigma from 10 batches of 1e6): the voxel
+    criterion in at least 99.5 % of the voxels above 10 % of the maximum,
+    total energy within 0.1 %, no bias (mean dD / sigma_diff within 0.2)."""
+    import os
+    wl = W.workload_slabs()
+    n = wl.n_histories
+    assert n == 10_000_000
+    say("slabs full run on the GPU", n)
+    e = engine(P, wl, P.PMC_FP32)
+    _, tal, _, bal = e.dose(n, [0], engine=P.PMC_ENGINE_PERSISTENT)
+    e.close()
+    check_balance(bal)
+    assert bal["histories"] == n
+    threads = min(16, os.cpu_count() or 1)
+    nb = 10
+    tot = sq = None
+    for b in range(nb):
+        say(f"oracle batch {b + 1}/{nb} ({threads} threads)")
+        t, _ = orc.dose_subset(wl.phases, wl.plan, n, wl.seed, 0, 2**32 - 1, n_threads=threads,
+                               h_mod=nb, h_rem=b)
+        t = np.asarray(t[0], dtype=np.float64)
+        tot = t if tot is None else tot + t
+        sq = t * t if sq is None else sq + t * t
+    sig = np.sqrt(np.maximum((sq - tot * tot / nb) / (nb - 1), 0.0) * nb)
+    frac, e_rel, zmean, zrms, nv = dose_parity(tal[0], tot, sig, "slabs 1e7 same seed")
+    assert nv > 10_000 and frac >= SAME_SEED_MIN_PASS and e_rel <= 1e-3 and abs(zmean) < 0.2, \
+        (frac, e_rel, zmean)

@@ -223,3 +223,46 @@ def test_box_validation(P):
         assert e.value.code == P.PMC_E_STATE
     finally:
         P.pmc_destroy(ctx)
+
+
+def box_differences(lib_boxes, orc_boxes, real):
+    """Bounds where the library's boxes differ from the oracle's: each must
+    be a bound whose real value lo/d or hi/d sits on an integer (a beam
+    entering on a voxel face: floor of an exact tie), off by one."""
+    ties = 0
+    for s in range(len(orc_boxes)):
+        for key, which in (("lo", 0), ("hi", 1)):
+            for k in range(3):
+                a, b = int(lib_boxes[s][key][k]), int(orc_boxes[s][key][k])
+                if a == b:
+                    continue
+                assert real[s] is not None, (s, key, k, a, b)
+                x = real[s][which][k]
+                assert abs(a - b) == 1 and abs(x - round(x)) < 1e-9, (s, key, k, a, b, x)
+                ties += 1
+    return ties
+
+
+def test_library_boxes_equal_the_oracle_boxes(P):
+    """The library's spot boxes (voxel-stepping walk along the axis) against
+    the oracle's (`oracle.boxes`: every plane crossing of the axis, sorted)
+    on the influence test case (a +z and an oblique field, lung and bone, a
+    spot off the grid, one of another phase) and on a thorax phase with a
+    sample of the robust plan's three fields: equal, except a bound that
+    sits exactly on a voxel face, where the floor may go either way."""
+    from oracle import boxes as OB
+    wl = W.workload_influence()
+    ob, real = OB.spot_boxes(wl.phases[0], wl.plan, 0)
+    lb = boxes_of(P, wl.phases[0], wl.plan)
+    assert box_differences(lb, ob, real) == 0
+    assert sum(r is not None for r in real) >= 20
+    ph = W.make_thorax((256, 256, 160), phase=4)
+    plan = W.plan_robust()
+    sub = W.Plan(plan.fields, plan.spots[::23].copy())
+    sub.spots["phase"] = 0
+    ob, real = OB.spot_boxes(ph, sub, 0)
+    lb = boxes_of(P, ph, sub)
+    ties = box_differences(lb, ob, real)
+    assert all(r is not None for r in real)
+    # the -y field enters the body on a voxel face along y
+    assert ties <= len(sub.spots)

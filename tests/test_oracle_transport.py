@@ -389,3 +389,36 @@ def test_dose_conversion_definition(orc):
     r = float(np.interp(hu, W.CALIB_HU, W.CALIB_RHO))
     assert rho[k] == pytest.approx(r, rel=1e-15)
     assert dose[k] == pytest.approx(t[k] / Q * 1.602176634e-13 / (r * V * 1e-3) / 1000, rel=1e-14)
+
+
+def test_interaction_distances_never_negative(orc):
+    """Step 7 lowers the interaction counters by the pre-step coefficient
+    times the step; a step that another limit ends within rounding of the
+    event's own distance can leave a counter a hair below 0, and its next
+    distance is then read as 0 (the event is due where the proton is; a
+    negative step would move it backwards).  Over thousands of steps of the
+    slab workload no counter goes below -1e-12, so the reading only guards
+    rounding."""
+    wl = W.workload_slabs()
+    lo = 0.0
+    n = 0
+    for s in range(0, 500, 50):
+        for h in range(10):
+            tr = orc.trace(wl.phases[0], wl.plan, s, h, seed=wl.seed)
+            n += len(tr)
+            lo = min(lo, float(tr["n_delta"][1:].min()), float(tr["n_nuc"][1:].min()))
+    assert n > 10_000 and lo >= -1e-12, (n, lo)
+
+
+def test_trace_margins_log_near_ties(orc):
+    """The trace's decision margin (the smallest relative gap of a decision
+    taken in a step) is 0 where a decision is an exact tie -- a beam entering
+    on a voxel face (x = 0 on an even grid) -- and positive, well away from
+    0, on an ordinary trace."""
+    ph = W.make_box((8, 8, 8), (2.5, 2.5, 2.5), 0, origin_mm=(-10.0, -10.0, 0.0))
+    plan = W.plan_single(100.0, 0.0, (0.0, 0.0, 10.0))
+    tr = orc.trace(ph, plan, 0, 0, seed=3)
+    assert tr[0]["margin"] == 0.0  # the entry point's x and y sit on voxel faces
+    wl = W.workload_slabs()
+    tr = orc.trace(wl.phases[0], wl.plan, 200, 1, seed=wl.seed)
+    assert len(tr) > 50 and np.median(tr["margin"][1:]) > 1e-4
