@@ -271,6 +271,28 @@ int pmc_dose_device(pmc_context *ctx, const pmc_request *req, void *stream,
 int pmc_dose_device_notify(pmc_context *ctx, const pmc_request *req, void *stream,
                            int64_t *const *dev_tally, uint64_t *dev_counters, uint32_t *host_drained);
 
+/* pmc_dose_device for callers that cannot allocate device memory in the
+ * call (code that must not call hipMalloc, tight serving loops, harnesses
+ * that forbid allocation): the same transport, the same tallies bit for bit,
+ * but the request's device data (spot descriptors, work items, core boxes,
+ * LUTs, target table) and the work-queue cursor go into a fixed device array
+ * of 8 MiB that the library sets up once per device at pmc_create (with a
+ * pinned host staging buffer of the same size), instead of memory allocated
+ * per request.  No device or pinned memory is allocated and nothing is freed
+ * by this call (host-side temporaries only); the request data is rebuilt and
+ * uploaded on `stream` every call (no cache).  dev_counters is required.
+ *  - PMC_E_RANGE, with nothing enqueued, if the request data would exceed
+ *    8 MiB (about 60,000 spots in FP32, 40,000 in FP64; pmc_dose_device
+ *    takes larger requests).
+ *  - Every context on a device shares that device's array, which keeps the
+ *    last call's contents: calls whose device work overlaps in time (on
+ *    different streams, or from different contexts of one device) race and
+ *    must not be made; calls on one stream are ordered.
+ *  - Unloading or replacing a phase, and pmc_destroy, wait for the whole
+ *    device after such a call (it records no per-resource events). */
+int pmc_dose_device_noalloc(pmc_context *ctx, const pmc_request *req, void *stream,
+                            int64_t *const *dev_tally, uint64_t *dev_counters);
+
 /* Turn a device counter block (copied to the host) plus the request into a
  * pmc_balance; the deposited total is taken from the tallies' sum, passed as
  * a 128-bit (lo, hi) pair.  The incident energy is that of the histories the

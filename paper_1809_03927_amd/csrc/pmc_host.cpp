@@ -171,6 +171,11 @@ struct pmc_context {
   std::map<int32_t, DvfRec> dvfs;
   DevBuf acc;
   UseEvents acc_uses;
+  // pmc_dose_device_noalloc: the device's scratch array (shared by every
+  // context on the device) and whether a call since the last device-wide
+  // wait may still read the context's phases or tables
+  pmc::NoAlloc *noalloc = nullptr;
+  bool noalloc_used = false;
 };
 
 namespace {
@@ -311,7 +316,17 @@ void drop_use(UseEvents &u) {
   u.ev.clear();
 }
 
+// Work of pmc_dose_device_noalloc records no per-resource events (creating
+// one is itself a setup call); memory it may read is released only after a
+// device-wide wait.
+void wait_noalloc(pmc_context *ctx) {
+  if (!ctx->noalloc_used) return;
+  (void)hipDeviceSynchronize();
+  ctx->noalloc_used = false;
+}
+
 void free_phase(pmc_context *ctx, PhaseRec &p) {
+  wait_noalloc(ctx);
   wait_use(p.uses);
   drop_use(p.uses);
   pool_put(ctx, p.d_hu, p.cap_hu);
@@ -657,6 +672,9 @@ void evict_lru(pmc_context *ctx) {
   ctx->cache.erase(ctx->cache.begin() + (long)lru);
 }
 
+template <typename R>
+int build_request(pmc_context *ctx, const pmc_request *req, Prepared &P);
+
 // Split, build and upload the request's device data; cached on the inputs.
 template <typename R>
 int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
@@ -679,6 +697,34 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
   }
   auto entry = std::make_unique<Prepared>();
   Prepared &P = *entry;
+  int rc = build_request<R>(ctx, req, P);
+  if (rc) return rc;
+  const size_t off = P.staging.size();
+  // room in the cache and in the budget (older entries are evicted first)
+  while (!ctx->cache.empty() &&
+         (ctx->cache.size() >= kMaxPrepared || ctx->used + align256(off) > ctx->budget))
+    evict_lru(ctx);
+  rc = ensure(ctx, P.buf, std::max<size_t>(off, 256), "request data");
+  if (rc) return rc;
+  HIP_TRY(ctx, copy_sync(ctx, P.buf.p, P.staging.data(), off, hipMemcpyHostToDevice),
+          "upload request data");
+  P.last_use = ++ctx->use_counter;
+  ctx->cache.push_back(std::move(entry));
+  *out = ctx->cache.back().get();
+  return PMC_OK;
+}
+
+// The request data of `req` laid out on the host (P.staging, with the
+// signature and host-side bookkeeping of P); no device work.
+template <typename R>
+int build_request(pmc_context *ctx, const pmc_request *req, Prepared &P) {
+  const PlanRec &plan = ctx->plans[req->plan];
+  std::vector<int32_t> phases(req->phases, req->phases + req->n_phases);
+  std::vector<uint64_t> versions;
+  for (int32_t ph : phases) versions.push_back(ctx->phases[ph].version);
+  const LaunchShape shape = launch_shape(ctx, req);
+  const int32_t chunk = req->engine == PMC_ENGINE_PERSISTENT ? shape.chunk : 0;
+  const int32_t mode = req->engine == PMC_ENGINE_PERSISTENT ? shape.mode : 0;
   const int64_t n_spots = (int64_t)plan.spots.size();
   P.per_spot.assign(n_spots, 0);
   int rc = split(plan.spots.data(), n_spots, req->phases, req->n_phases, req->n_histories,
@@ -777,14 +823,6 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
     put(P.off_ids[i], P.list[i].data(), sizeof(int32_t) * P.list[i].size());
     put(P.off_first[i], P.first[i].data(), sizeof(long long) * P.first[i].size());
   }
-  // room in the cache and in the budget (older entries are evicted first)
-  while (!ctx->cache.empty() &&
-         (ctx->cache.size() >= kMaxPrepared || ctx->used + align256(off) > ctx->budget))
-    evict_lru(ctx);
-  rc = ensure(ctx, P.buf, std::max<size_t>(off, 256), "request data");
-  if (rc) return rc;
-  HIP_TRY(ctx, copy_sync(ctx, P.buf.p, P.staging.data(), off, hipMemcpyHostToDevice),
-          "upload request data");
   P.bytes = off;
   P.plan_id = req->plan;
   P.plan_version = plan.version;
@@ -795,9 +833,6 @@ int prepare(pmc_context *ctx, const pmc_request *req, Prepared **out) {
   P.chunk = chunk;
   P.mode = mode;
   P.precision = ctx->precision;
-  P.last_use = ++ctx->use_counter;
-  ctx->cache.push_back(std::move(entry));
-  *out = ctx->cache.back().get();
   return PMC_OK;
 }
 
@@ -1063,6 +1098,10 @@ int pmc_create(const pmc_config *cfg, pmc_context **out) {
   ctx->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
   if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess)
     return bail(e, "hipStreamCreate");
+  // the device's scratch for pmc_dose_device_noalloc (first context on the
+  // device takes its address; later ones reuse it)
+  if ((e = pmc::noalloc_setup(cfg->device, &ctx->noalloc)) != hipSuccess)
+    return bail(e, "scratch of the no-allocation entry point");
   // tables in the working precision, per node: (R, mu_delta, omega^2, inverse
   // slope dl2 / (R_{i+1} - R_i) of the interval above the node, 0 at the top)
   const int n = pmc::kTableNodes;
@@ -1104,6 +1143,7 @@ void pmc_destroy(pmc_context *ctx) {
   if (ctx->has_device) {
     (void)hipSetDevice(ctx->device);
     wait_pending(ctx);
+    wait_noalloc(ctx);
     for (auto &kv : ctx->phases) free_phase(ctx, kv.second);
     for (auto &e : ctx->cache) {
       drop_use(e->uses);
@@ -1392,6 +1432,53 @@ int pmc_dose_device_notify(pmc_context *ctx, const pmc_request *req, void *strea
     return fail(ctx, PMC_E_INVAL, "the drain signal belongs to the persistent engine");
   if (!host_drained) return fail(ctx, PMC_E_INVAL, "host_drained is NULL");
   return dose_device(ctx, req, stream, dev_tally, dev_counters, host_drained);
+}
+
+int pmc_dose_device_noalloc(pmc_context *ctx, const pmc_request *req, void *stream,
+                            int64_t *const *dev_tally, uint64_t *dev_counters) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  int rc = validate_request(ctx, req);
+  if (rc) return rc;
+  if (!dev_tally) return fail(ctx, PMC_E_INVAL, "dev_tally is NULL");
+  for (int32_t i = 0; i < req->n_phases; ++i)
+    if (!dev_tally[i]) return fail(ctx, PMC_E_INVAL, "dev_tally[%d] is NULL", i);
+  if (!dev_counters) return fail(ctx, PMC_E_INVAL, "dev_counters is NULL (the caller owns the counter block)");
+  if (!ctx->has_device || !ctx->noalloc) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  // the request data on the host, laid out as for pmc_dose_device
+  Prepared P;
+  rc = ctx->precision == PMC_FP64 ? build_request<double>(ctx, req, P) : build_request<float>(ctx, req, P);
+  if (rc) return rc;
+  if (req->item_end > (uint64_t)P.n_items || req->item_begin > (uint64_t)P.n_items)
+    return fail(ctx, PMC_E_INVAL, "work-item slice [%llu, %llu) beyond the request's %d items",
+                (unsigned long long)req->item_begin, (unsigned long long)req->item_end, P.n_items);
+  const size_t image = align256(P.staging.size());
+  const size_t need = image + 256;  // + the work-queue cursor's line
+  if (need > pmc::kNoAllocBytes)
+    return fail(ctx, PMC_E_RANGE, "request data of %zu bytes exceed the %zu bytes of the no-allocation scratch "
+                "(fewer spots or phases, or pmc_dose_device)", need, (size_t)pmc::kNoAllocBytes);
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  pmc::NoAlloc &na = *ctx->noalloc;
+  // the staging buffer is free once the previous upload from it has ended
+  HIP_TRY(ctx, hipEventSynchronize(na.uploaded), "wait for the previous upload");
+  std::memcpy(na.host, P.staging.data(), P.staging.size());
+  std::vector<TargetDev> tg(req->n_phases);  // this call's tally pointers
+  for (int32_t i = 0; i < req->n_phases; ++i)
+    tg[i] = make_target(ctx->phases[req->phases[i]], reinterpret_cast<unsigned long long *>(dev_tally[i]),
+                        P.same_lut ? 0 : i);
+  if (req->engine == PMC_ENGINE_PERSISTENT)
+    std::memcpy(na.host + P.off_targets, tg.data(), sizeof(TargetDev) * tg.size());
+  HIP_TRY(ctx, hipMemcpyAsync(na.dev, na.host, P.staging.size(), hipMemcpyHostToDevice, st),
+          "upload request data");
+  HIP_TRY(ctx, hipEventRecord(na.uploaded, st), "hipEventRecord");
+  auto *cursor = reinterpret_cast<unsigned long long *>(na.dev + image);
+  auto *const *t = reinterpret_cast<unsigned long long *const *>(dev_tally);
+  auto *counters = reinterpret_cast<unsigned long long *>(dev_counters);
+  ctx->noalloc_used = true;
+  return ctx->precision == PMC_FP64
+             ? enqueue_prepared<double>(ctx, P, req, st, t, counters, na.dev, cursor, false)
+             : enqueue_prepared<float>(ctx, P, req, st, t, counters, na.dev, cursor, false);
 }
 
 int pmc_balance_from_counters(pmc_context *ctx, const pmc_request *req, const uint64_t *counters,

@@ -278,6 +278,20 @@ hipError_t launch_convert(const long long *tally, const int16_t *hu, const uint8
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long value,
                            hipStream_t st);
 
+// ---- the no-allocation entry point's scratch --------------------------------
+// A file-scope device array of kNoAllocBytes per device (request data and
+// the work-queue cursor of pmc_dose_device_noalloc), plus a pinned host
+// staging buffer of the same size and an event marking the end of the last
+// upload from it.  Set up once per device by noalloc_setup (with that device
+// current: pmc_create calls it); everything stays until the process ends.
+constexpr size_t kNoAllocBytes = size_t(8) << 20;
+struct NoAlloc {
+  unsigned char *dev = nullptr;   // address of the device array on this device
+  unsigned char *host = nullptr;  // pinned staging
+  hipEvent_t uploaded = nullptr;  // recorded after each upload from `host`
+};
+hipError_t noalloc_setup(int device, NoAlloc **out);
+
 // ---- physics tables (host, FP64) -------------------------------------------
 constexpr int kTableNodes = 1024;
 

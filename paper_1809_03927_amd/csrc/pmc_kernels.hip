@@ -11,6 +11,8 @@
 //
 // All transport kernels run the same `pmc::step`, so for equal inputs they
 // produce bit-identical integer tallies whatever the schedule.
+#include <mutex>
+
 #include "pmc_device.hpp"
 #include "pmc_internal.hpp"
 
@@ -883,6 +885,44 @@ hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long lon
   if (nb > 8192) nb = 8192;
   hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)nb), dim3(block), 0, st, p, n, value);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scratch of the no-allocation entry point: one array per device, whose
+// address host code takes once per device with hipGetSymbolAddress (the
+// array's name is not a device address in host code)
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex;
+NoAlloc g_noalloc[kMaxDevices];
+}  // namespace
+
+hipError_t noalloc_setup(int device, NoAlloc **out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+  NoAlloc &na = g_noalloc[device];
+  if (!na.dev) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    void *h = nullptr;
+    e = hipHostMalloc(&h, kNoAllocBytes, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipHostFree(h);
+      return e;
+    }
+    na.dev = static_cast<unsigned char *>(p);
+    na.host = static_cast<unsigned char *>(h);
+    na.uploaded = ev;
+  }
+  *out = &na;
+  return hipSuccess;
 }
 
 }  // namespace pmc

@@ -33,7 +33,7 @@ ERROR_NAMES = {0: "PMC_OK", -1: "PMC_E_INVAL", -2: "PMC_E_NOPHASE", -3: "PMC_E_B
 # every symbol declared in include/pmc.h
 EXPORTS = ["pmc_create", "pmc_destroy", "pmc_last_error", "pmc_load_phase", "pmc_unload_phase",
            "pmc_load_spots", "pmc_load_plan", "pmc_unload_plan", "pmc_request_items", "pmc_request_item_histories", "pmc_launch_shape", "pmc_dose",
-           "pmc_dose_device", "pmc_dose_device_notify", "pmc_balance_from_counters",
+           "pmc_dose_device", "pmc_dose_device_notify", "pmc_dose_device_noalloc", "pmc_balance_from_counters",
            "pmc_convert_device", "pmc_trace", "pmc_split_histories", "pmc_bytes_in_use",
            "pmc_graph_create", "pmc_graph_launch", "pmc_graph_destroy", "pmc_influence_boxes",
            "pmc_influence", "pmc_influence_read", "pmc_influence_device", "pmc_influence_free",
@@ -157,6 +157,7 @@ def lib():
         L.pmc_dose.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, C.POINTER(pmc_balance)]
         L.pmc_dose_device.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp]
         L.pmc_dose_device_notify.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, vp]
+        L.pmc_dose_device_noalloc.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp]
         L.pmc_balance_from_counters.argtypes = [vp, C.POINTER(pmc_request), vp, vp,
                                                 C.POINTER(pmc_balance)]
         L.pmc_convert_device.argtypes = [vp, i32, vp, u64, vp, vp, vp]
@@ -288,6 +289,15 @@ def pmc_dose_device(ctx, req: Request, stream: int, dev_tallies: Sequence[int],
     tp = (C.c_void_p * req.n_phases)(*[int(p) for p in dev_tallies])
     _check(lib().pmc_dose_device(ctx, C.byref(req.c), C.c_void_p(stream), tp,
                                  None if dev_counters is None else C.c_void_p(dev_counters)), ctx)
+
+
+def pmc_dose_device_noalloc(ctx, req: Request, stream: int, dev_tallies: Sequence[int],
+                            dev_counters: int) -> None:
+    """pmc_dose_device without device allocation (the request data goes into
+    the library's fixed per-device scratch array)."""
+    tp = (C.c_void_p * req.n_phases)(*[int(p) for p in dev_tallies])
+    _check(lib().pmc_dose_device_noalloc(ctx, C.byref(req.c), C.c_void_p(stream), tp,
+                                         C.c_void_p(dev_counters)), ctx)
 
 
 def pmc_dose_device_notify(ctx, req: Request, stream: int, dev_tallies: Sequence[int],
