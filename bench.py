@@ -44,12 +44,19 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # step count (profiles/transport_valu_per_step_thorax.md).
 VALU_PER_STEP = 448.6
 
+# The method's own VALU work per step (one Philox4x32-10 block, two
+# Box-Muller transforms, the table reads and the range inversion, the DDA),
+# at the upper end of an estimate of 150-250 instructions per lane.
+METHOD_VALU_PER_STEP = 250
+
 # HBM-side bytes of one full-size transport launch (5e7 histories of the
 # thorax 4D workload, block engine, chunk 8192), from FETCH_SIZE and
-# WRITE_SIZE scaled by a 4 GiB copy calibration
-# (profiles/transport_core_thorax4d_counters.md).  Valid only for the sources
-# they were measured on (hash below) and that launch shape; otherwise null.
+# WRITE_SIZE scaled by a 4 GiB copy calibration, and its memory-side atomic
+# requests (TCC_EA0_ATOMIC_sum) (profiles/transport_core_thorax4d_counters.md).
+# Valid only for the sources they were measured on (hash below) and that
+# launch shape; otherwise null.
 PROFILED_TRAFFIC_BYTES = 172.2e9
+PROFILED_MEMSIDE_ATOMICS = 4.098e9
 PROFILED_KERNEL_HASH = "698bebd8d8e87ae1"
 
 # Deformable accumulation (energy/mass transfer, Sec. 2.D.2): the per-phase
@@ -297,26 +304,12 @@ def main():
                  "speedup_batched_vs_plain": sec_p / sec_b, "tallies_identical": same}
         log(f"plain: {sec_p * 1e3:.1f} ms/step -> batched is x{sec_p / sec_b:.3f}")
 
-    atomic_peak = None
-    if not a.no_atomic_probe:
-        atomic_peak = atomic_probe(torch, nvox)
-        log(f"int64 atomic probe (torch index_add_, random voxels): {atomic_peak / 1e9:.1f} G/s")
-
-    lane_steps_s = bal["steps"] / (kern_ms * 1e-3)
-    achieved = lane_steps_s * VALU_PER_STEP
-    default_cfg = wl.n_histories == 50_000_000 and grid == (256, 256, 160)
-    traffic = (PROFILED_TRAFFIC_BYTES if default_cfg and kernel_hash() == PROFILED_KERNEL_HASH
-               and shape_b["tally_mode"] == pmc.PMC_TALLY_CORE and shape_b["chunk"] == 8192 else None)
-    roofline = {
-        "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-        "unit": "T lane-VALU-instr/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
-        "traffic_unit": "bytes per launch (HBM side: fetches + 32 B per memory-side atomic)",
-        "kernel": kernel_name, "kernel_ms": kern_ms,
-        "valu_per_step": VALU_PER_STEP, "lane_steps_per_s": lane_steps_s,
-        "atomics_per_s": bal["atomics"] / (kern_ms * 1e-3),
-        "atomic_probe_per_s": atomic_peak,
-        "atomic_frac": (bal["atomics"] / (kern_ms * 1e-3) / atomic_peak) if atomic_peak else None,
-    }
+    probe = None
+    if not a.no_atomic_probe and shape_b["tally_mode"] == pmc.PMC_TALLY_CORE:
+        probe = atomic_probe(eng, pmc, wl, phases, tuned, tallies, counters, stream, torch)
+        log(f"atomic replay of the kernel's own addresses: {probe['per_s'] / 1e9:.2f} G/s "
+            f"({probe['replayed']:.3g} atomics in {probe['ms']:.1f} ms)")
+    roofline = roofline_fields(bal, kern_ms, probe, kernel_name, shape_b, wl, grid, pmc)
     if graph is not None:
         pmc.pmc_graph_destroy(graph)
         graph = True
@@ -393,21 +386,84 @@ def kernel_hash():
     return source_hash(("pmc_device.hpp", "pmc_kernels.hip", "pmc_host.cpp"))
 
 
-def atomic_probe(torch, nvox, n=200_000_000):
-    """Throughput of int64 atomic adds to random voxels of one tally."""
-    g = torch.Generator(device="cuda")
-    g.manual_seed(0)
-    dst = torch.zeros(nvox, dtype=torch.int64, device="cuda")
-    idx = torch.randint(0, nvox, (n,), device="cuda", generator=g)
-    val = torch.ones(n, dtype=torch.int64, device="cuda")
-    dst.index_add_(0, idx, val)
+LOG_PER_LANE = 8192  # logged atomics per lane of the replay probe
+
+
+def atomic_probe(eng, pmc, wl, phases, tuned, tallies, counters, stream, torch):
+    """The device-wide atomic throughput of the transport kernel's own
+    deposit-address pattern: one block-engine launch of the benchmark's
+    request (same shape, one block per CU) logs the address of every lane's
+    device-wide tally atomic (the first LOG_PER_LANE of each lane), then a
+    replay kernel issues exactly those atomics, per lane in logged order,
+    back to back; timed with events on the benchmark's stream.  Leaves the
+    tallies changed (run after every use of them)."""
+    import numpy as np
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    req = pmc.Request(wl.n_histories, phases, request_id=wl.request_id, engine=pmc.PMC_ENGINE_PERSISTENT,
+                      chunk=tuned["chunk"], refill_min=tuned["refill_min"], tally_mode=pmc.PMC_TALLY_CORE,
+                      grid_blocks=n_cu)
+    lanes = n_cu * 1024
+    log_buf = torch.empty(LOG_PER_LANE * lanes, dtype=torch.int64, device="cuda")
+    count = torch.zeros(lanes, dtype=torch.int32, device="cuda")
+    for t in tallies:
+        t.zero_()
+    counters.zero_()
+    pmc.pmc_atomic_log(eng.ctx, req, stream.cuda_stream, [t.data_ptr() for t in tallies], counters.data_ptr(),
+                       log_buf.data_ptr(), LOG_PER_LANE, count.data_ptr())
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    dst.index_add_(0, idx, val)
-    e1.record()
-    torch.cuda.synchronize()
-    return n / (e0.elapsed_time(e1) * 1e-3)
+    c = count.cpu().numpy().astype(np.int64)
+    replayed = int(np.minimum(c, LOG_PER_LANE).sum())
+    spans = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pmc.pmc_atomic_replay(eng.ctx, stream.cuda_stream, log_buf.data_ptr(), LOG_PER_LANE,
+                              count.data_ptr(), lanes)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        spans.append(e0.elapsed_time(e1))
+    del log_buf
+    torch.cuda.empty_cache()
+    ms = float(np.mean(spans[1:]))
+    return {"per_s": replayed / (ms * 1e-3), "ms": ms, "replayed": replayed, "lanes": lanes,
+            "logged_total": int(c.sum()), "per_lane_cap": LOG_PER_LANE}
+
+
+def roofline_fields(bal, kern_ms, probe, kernel_name, shape_b, wl, grid, pmc):
+    """The dominant kernel's roofline: device-wide int64 atomics per second
+    against the replay of its own address pattern (the binding roof of the
+    block engine), with the VALU view beside it."""
+    kern_s = kern_ms * 1e-3
+    issued = bal["atomics"] / kern_s
+    lane_steps_s = bal["steps"] / kern_s
+    default_cfg = wl.n_histories == 50_000_000 and grid == (256, 256, 160)
+    profiled = (default_cfg and kernel_hash() == PROFILED_KERNEL_HASH
+                and shape_b["tally_mode"] == pmc.PMC_TALLY_CORE and shape_b["chunk"] == 8192)
+    out = {
+        "bound": "atomic" if probe else "alu",
+        "achieved": issued / 1e9 if probe else lane_steps_s * VALU_PER_STEP / 1e12,
+        "peak": probe["per_s"] / 1e9 if probe else PEAK_LANE_OPS / 1e12,
+        "unit": "G device-wide int64 atomics/s" if probe else "T lane-VALU-instr/s",
+        "frac": issued / probe["per_s"] if probe else lane_steps_s * VALU_PER_STEP / PEAK_LANE_OPS,
+        "traffic": PROFILED_TRAFFIC_BYTES if profiled else None,
+        "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, rocprofv3, copy-calibrated)",
+        "kernel": kernel_name, "kernel_ms": kern_ms,
+        "atomics_per_launch": int(bal["atomics"]),
+        "memory_side_atomics_per_launch": PROFILED_MEMSIDE_ATOMICS if profiled else None,
+        "peak_source": None if not probe else (
+            f"pmc_atomic_replay of the kernel's logged deposit addresses: the first {probe['per_lane_cap']} "
+            f"device-wide atomics of each of its {probe['lanes']} lanes ({probe['replayed']:.4g} of "
+            f"{probe['logged_total']:.4g}), in logged order, back to back"),
+        "valu": {
+            "peak_T_lane_instr_per_s": PEAK_LANE_OPS / 1e12,
+            "lane_steps_per_s": lane_steps_s,
+            "executed_per_step": VALU_PER_STEP,
+            "frac_executed": lane_steps_s * VALU_PER_STEP / PEAK_LANE_OPS,
+            "method_per_step": METHOD_VALU_PER_STEP,
+            "frac_method": lane_steps_s * METHOD_VALU_PER_STEP / PEAK_LANE_OPS,
+        },
+    }
+    return out
 
 
 SCAN_N = (1, 2, 3, 4, 5, 6, 8, 10, 16)

@@ -334,6 +334,25 @@ void pmc_graph_destroy(pmc_graph *g);
 
 /* ---- validation hooks ------------------------------------------------------ */
 
+/* Measurement of the block engine's deposit-address pattern: run `req`
+ * (persistent engine resolving to PMC_TALLY_CORE, FP32, grid_blocks > 0) as
+ * pmc_dose_device does -- the same tallies -- and also write, for every
+ * lane g of the launch (lanes = grid_blocks x 1024), the device address of
+ * its n-th device-wide tally atomic to dev_log[n * lanes + g] for n <
+ * per_lane, and its count of such atomics to dev_log_count[g].  dev_log
+ * holds per_lane x lanes uint64, dev_log_count lanes uint32 (device). */
+int pmc_atomic_log(pmc_context *ctx, const pmc_request *req, void *stream, int64_t *const *dev_tally,
+                   uint64_t *dev_counters, uint64_t *dev_log, uint32_t per_lane, uint32_t *dev_log_count);
+
+/* Replay a log written by pmc_atomic_log (same per_lane, n_lanes = its
+ * lanes): lane g issues 64-bit atomic adds of 1 at its first
+ * min(dev_log_count[g], per_lane) logged addresses, in order, with nothing
+ * between them -- the atomic throughput of exactly that address pattern
+ * (timed by the caller on `stream`).  The logged tallies must still be
+ * allocated; they are changed. */
+int pmc_atomic_replay(pmc_context *ctx, void *stream, const uint64_t *dev_log, uint32_t per_lane,
+                      const uint32_t *dev_log_count, uint32_t n_lanes);
+
 /* Per-step trace of one history (spot index, history index within the spot)
  * of plan `plan` on one phase, computed by the GPU transport in the
  * context's precision.  Writes at most max_rec records and sets *n_rec to the

@@ -182,7 +182,10 @@ template <typename R> struct Geo {
 //               spot); outside it: the phase tally
 //   kTallyBoxCore  kTallyBox whose core window (inside the box) adds into
 //               the block's LDS copy (flushed into the box tally)
-constexpr int kTallyGrid = 0, kTallyBox = 1, kTallyCore = 2, kTallyBoxCore = 3;
+//   kTallyCoreLog  kTallyCore that also writes the address of every global
+//               atomic into a per-lane log (measurement of the deposit
+//               address pattern; the tallies are the same)
+constexpr int kTallyGrid = 0, kTallyBox = 1, kTallyCore = 2, kTallyBoxCore = 3, kTallyCoreLog = 4;
 
 // the box a lane's spot tallies into (kTallyBox: global, kTallyCore: LDS);
 // kTallyBoxCore: the box (global) and its core window (LDS)
@@ -191,6 +194,9 @@ struct BoxLane {
   int32_t lo[3], n[3];
   unsigned long long *core;  // kTallyBoxCore: entry 0 of the core window
   int32_t clo[3], cn[3];     // kTallyBoxCore: window corner (grid voxels) and size
+  // kTallyCoreLog: entry n of this lane is log[n * log_stride + log_lane], n < log_cap
+  unsigned long long *log;
+  uint32_t log_cap, log_stride, log_lane;
 };
 
 // physics tables per node i: (R, mu_delta, omega^2, dl2 / (R_{i+1} - R_i)),
@@ -226,6 +232,11 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p) 
 
 __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned long long v) {
   __hip_atomic_fetch_add(as_global(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// kTallyCoreLog: the address of the lane's n-th global atomic
+__device__ __forceinline__ void log_atomic(const BoxLane &B, uint32_t n, const unsigned long long *p) {
+  if (n < B.log_cap) as_global(B.log)[(size_t)n * B.log_stride + B.log_lane] = (unsigned long long)p;
 }
 
 // ---------------------------------------------------------------------------
@@ -474,13 +485,14 @@ __device__ __forceinline__ void commit_acc(const Lane<R> &L, const Geo<R> &G, co
       return;
     }
     atomic_add_u64(&B.base[L.acc_v], (unsigned long long)L.acc);
-  } else if constexpr (TM == kTallyCore) {
+  } else if constexpr (TM == kTallyCore || TM == kTallyCoreLog) {
     if (L.acc_v <= -3) {  // LDS: the block's copy of the core
       __hip_atomic_fetch_add(&B.base[-3 - L.acc_v], (unsigned long long)L.acc, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
       return;
     }
     atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
+    if constexpr (TM == kTallyCoreLog) log_atomic(B, C.atomics, &G.tally[L.acc_v]);
   } else if constexpr (TM == kTallyBoxCore) {
     if (L.acc_v <= -3) {  // LDS: the block's copy of the core window
       __hip_atomic_fetch_add(&B.core[-3 - L.acc_v], (unsigned long long)L.acc, __ATOMIC_RELAXED,

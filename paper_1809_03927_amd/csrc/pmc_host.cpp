@@ -851,11 +851,19 @@ struct BoxArgs {
   int32_t core_cap;
 };
 
+// Address log of a block-engine launch (pmc_atomic_log).
+struct LogArgs {
+  unsigned long long *log;
+  uint32_t cap;
+  uint32_t *count;
+};
+
 template <typename R>
 int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipStream_t st,
                      unsigned long long *const *tally, unsigned long long *counters,
                      unsigned char *base, unsigned long long *cursor, bool upload_targets,
-                     const BoxArgs *box = nullptr, unsigned int *drained = nullptr) {
+                     const BoxArgs *box = nullptr, unsigned int *drained = nullptr,
+                     const LogArgs *log = nullptr) {
   auto scratch_at = [&](size_t off) { return base + off; };
   const bool fp64 = sizeof(R) == 8;
   const uint32_t k0 = (uint32_t)(ctx->seed & 0xffffffffu), k1 = req->request_id;
@@ -943,6 +951,12 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
       a.box_bias = box->bias;
     }
     a.drained = drained;
+    if (log) {
+      if (!a.cores || !a.lut_lds) return fail(ctx, PMC_E_INVAL, "the address log needs the block engine with one LUT");
+      a.log = log->log;
+      a.log_cap = log->cap;
+      a.log_count = log->count;
+    }
     unsigned grid = (unsigned)req->grid_blocks;
     if (grid == 0 && a.cores) {
       grid = (unsigned)ctx->n_cu;  // one block per CU: the core takes the LDS
@@ -975,7 +989,7 @@ int take_cursor(pmc_context *ctx, hipStream_t st, unsigned long long **cursor, h
 template <typename R>
 int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
             unsigned long long *const *tally, unsigned long long *counters,
-            unsigned int *drained = nullptr) {
+            unsigned int *drained = nullptr, const LogArgs *log = nullptr) {
   Prepared *P = nullptr;
   int rc = prepare<R>(ctx, req, &P);
   if (rc) return rc;
@@ -989,7 +1003,7 @@ int enqueue(pmc_context *ctx, const pmc_request *req, hipStream_t st,
     if (rc) return rc;
   }
   rc = enqueue_prepared<R>(ctx, *P, req, st, tally, counters, static_cast<unsigned char *>(P->buf.p),
-                           cursor, true, nullptr, drained);
+                           cursor, true, nullptr, drained, log);
   if (rc) return rc;
   if (cursor_done) HIP_TRY(ctx, hipEventRecord(*cursor_done, st), "hipEventRecord");
   rc = note_use(ctx, P->uses, st);
@@ -1479,6 +1493,43 @@ int pmc_dose_device_noalloc(pmc_context *ctx, const pmc_request *req, void *stre
   return ctx->precision == PMC_FP64
              ? enqueue_prepared<double>(ctx, P, req, st, t, counters, na.dev, cursor, false)
              : enqueue_prepared<float>(ctx, P, req, st, t, counters, na.dev, cursor, false);
+}
+
+int pmc_atomic_log(pmc_context *ctx, const pmc_request *req, void *stream, int64_t *const *dev_tally,
+                   uint64_t *dev_counters, uint64_t *dev_log, uint32_t per_lane, uint32_t *dev_log_count) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  int rc = validate_request(ctx, req);
+  if (rc) return rc;
+  if (!dev_tally || !dev_counters || !dev_log || !dev_log_count || per_lane == 0)
+    return fail(ctx, PMC_E_INVAL, "NULL tally, counters, log or count, or per_lane = 0");
+  for (int32_t i = 0; i < req->n_phases; ++i)
+    if (!dev_tally[i]) return fail(ctx, PMC_E_INVAL, "dev_tally[%d] is NULL", i);
+  if (req->engine != PMC_ENGINE_PERSISTENT || req->grid_blocks <= 0)
+    return fail(ctx, PMC_E_INVAL, "the address log needs the persistent engine and an explicit grid_blocks");
+  if (ctx->precision != PMC_FP32) return fail(ctx, PMC_E_INVAL, "the block engine runs in FP32");
+  if (launch_shape(ctx, req).mode != PMC_TALLY_CORE)
+    return fail(ctx, PMC_E_INVAL, "the request does not run on the block engine (tally_mode)");
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  const LogArgs log{reinterpret_cast<unsigned long long *>(dev_log), per_lane, dev_log_count};
+  return enqueue<float>(ctx, req, (hipStream_t)stream, reinterpret_cast<unsigned long long *const *>(dev_tally),
+                        reinterpret_cast<unsigned long long *>(dev_counters), nullptr, &log);
+}
+
+int pmc_atomic_replay(pmc_context *ctx, void *stream, const uint64_t *dev_log, uint32_t per_lane,
+                      const uint32_t *dev_log_count, uint32_t n_lanes) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (!dev_log || !dev_log_count || per_lane == 0 || n_lanes == 0 || n_lanes % pmc::kCoreBlock != 0)
+    return fail(ctx, PMC_E_INVAL, "NULL log or count, per_lane = 0, or n_lanes not a multiple of %d",
+                pmc::kCoreBlock);
+  if (!ctx->has_device) return fail(ctx, PMC_E_DEVICE, "validation-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  HIP_TRY(ctx, pmc::launch_atomic_replay(reinterpret_cast<const unsigned long long *>(dev_log), per_lane,
+                                         dev_log_count, n_lanes, (hipStream_t)stream),
+          "atomic_replay launch");
+  return note_pending(ctx, (hipStream_t)stream);
 }
 
 int pmc_balance_from_counters(pmc_context *ctx, const pmc_request *req, const uint64_t *counters,

@@ -116,6 +116,12 @@ struct PersistentLaunch {
   // spot, LDS room for core_cap tally entries per block
   const CoreDev *cores = nullptr;
   int32_t core_cap = 0;
+  // block engine, measurement: the address of each lane's global atomics,
+  // entry n of lane g at log[n * lanes + g] for n < log_cap, and each lane's
+  // count of global atomics in log_count[g] (lanes = grid x kCoreBlock)
+  unsigned long long *log = nullptr;
+  uint32_t log_cap = 0;
+  uint32_t *log_count = nullptr;
 };
 
 // Fixed LDS of a block-engine block (tables, the LUT when it is in LDS,
@@ -277,6 +283,8 @@ hipError_t launch_convert(const long long *tally, const int16_t *hu, const uint8
                           double *dose, double *density, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long value,
                            hipStream_t st);
+hipError_t launch_atomic_replay(const unsigned long long *log, uint32_t log_cap, const uint32_t *log_count,
+                                uint32_t n_lanes, hipStream_t st);
 
 // ---- the no-allocation entry point's scratch --------------------------------
 // A file-scope device array of kNoAllocBytes per device (request data and

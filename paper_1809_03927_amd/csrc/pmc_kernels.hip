@@ -262,7 +262,7 @@ size_t core_fixed_lds(bool lut_lds) {
          sizeof(unsigned long long) * kNc * (kCoreBlock / 64 + 1) + 16;
 }
 
-template <typename R, bool LUT_LDS, bool BOX>
+template <typename R, bool LUT_LDS, bool BOX, bool LOG = false>
 __global__ void __launch_bounds__(kCoreBlock)
 transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict__ items,
                int32_t n_items, const TargetDev *__restrict__ targets,
@@ -271,8 +271,10 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
                uint32_t k0, uint32_t k1, uint32_t flags, int32_t refill_min,
                unsigned long long *cursor, unsigned long long *counters,
                const CoreDev *__restrict__ cores, int32_t core_cap, const BoxDev *__restrict__ boxes,
-               unsigned long long *box_tally, long long box_bias, unsigned int *drained_flag) {
-  constexpr int TM = BOX ? kTallyBoxCore : kTallyCore;
+               unsigned long long *box_tally, long long box_bias, unsigned int *drained_flag,
+               unsigned long long *log, uint32_t log_cap, uint32_t *log_count) {
+  static_assert(!(LOG && BOX), "the address log covers the phase tallies");
+  constexpr int TM = BOX ? kTallyBoxCore : (LOG ? kTallyCoreLog : kTallyCore);
   extern __shared__ __align__(16) unsigned char smem[];
   using R2 = typename M<R>::R2;
   using R4 = typename M<R>::R4;
@@ -345,6 +347,12 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
         B.lo[a] = clo[a];
         B.n[a] = use_core ? cn[a] : 0;  // no core: every deposit goes to the tally
       }
+      if constexpr (LOG) {
+        B.log = log;
+        B.log_cap = log_cap;
+        B.log_stride = gridDim.x * blockDim.x;
+        B.log_lane = blockIdx.x * blockDim.x + threadIdx.x;
+      }
     }
     bool taken_all = false;
     for (;;) {
@@ -388,13 +396,33 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
           } else {
             const int32_t vox = (clo[0] + x) + G.n[0] * ((clo[1] + y) + G.n[1] * (clo[2] + z));
             atomic_add_u64(&G.tally[vox], v);
+            if constexpr (LOG) log_atomic(B, C.atomics, &G.tally[vox]);
           }
           C.atomics += 1;
         }
       }
     }
   }
+  if constexpr (LOG) log_count[blockIdx.x * blockDim.x + threadIdx.x] = C.atomics;
   commit_counters(C, counters, red);
+}
+
+// ---------------------------------------------------------------------------
+// replay of a logged deposit-address pattern: lane g issues its logged
+// 64-bit atomics, in its order, back to back (one per loop iteration, value
+// 1) -- the atomic throughput of exactly those addresses without the
+// transport around them
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kCoreBlock) atomic_replay(const unsigned long long *__restrict__ log,
+                                                             uint32_t log_cap,
+                                                             const uint32_t *__restrict__ log_count,
+                                                             uint32_t n_lanes) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_lanes) return;
+  const uint32_t c = log_count[g];
+  const uint32_t n = c < log_cap ? c : log_cap;
+  for (uint32_t k = 0; k < n; ++k)
+    atomic_add_u64(reinterpret_cast<unsigned long long *>(log[(size_t)k * n_lanes + g]), 1ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -765,15 +793,18 @@ static hipError_t launch_core_t(const PersistentLaunch &a, hipStream_t st) {
     using R4 = typename M<R>::R4;
     const size_t lds = core_fixed_lds(a.lut_lds) + sizeof(unsigned long long) * (size_t)a.core_cap;
     const bool box = a.boxes != nullptr;
-    auto kern = a.lut_lds ? (box ? transport_core<R, true, true> : transport_core<R, true, false>)
-                          : (box ? transport_core<R, false, true> : transport_core<R, false, false>);
+    if (a.log && (box || !a.lut_lds)) return hipErrorInvalidValue;  // logged: phase tallies, one LUT
+    auto kern = a.log ? transport_core<R, true, false, true>
+                      : a.lut_lds ? (box ? transport_core<R, true, true> : transport_core<R, true, false>)
+                                  : (box ? transport_core<R, false, true> : transport_core<R, false, false>);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(a.grid), dim3(kCoreBlock), lds, st, (const SpotDev<R> *)a.spots,
                        a.items, a.n_items, a.targets, (const R2 *)a.luts, (const R4 *)a.tab,
                        (R)a.l2e0, (R)a.inv_dl2, (R)a.dl2, a.k0, a.k1, a.flags, a.refill_min, a.cursor,
-                       a.counters, a.cores, a.core_cap, a.boxes, a.box_tally, a.box_bias, a.drained);
+                       a.counters, a.cores, a.core_cap, a.boxes, a.box_tally, a.box_bias, a.drained,
+                       a.log, a.log_cap, a.log_count);
     return hipGetLastError();
   }
 }
@@ -874,6 +905,14 @@ hipError_t launch_influence_write(const InfluenceLaunch &a, hipStream_t st) {
     hipLaunchKernelGGL(influence_write, dim3(blocks), dim3(kInfBlock), 0, st, a);
   if (a.n_spots > 0)
     hipLaunchKernelGGL(influence_rows, dim3((unsigned)((a.n_spots + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_atomic_replay(const unsigned long long *log, uint32_t log_cap, const uint32_t *log_count,
+                                uint32_t n_lanes, hipStream_t st) {
+  if (n_lanes == 0) return hipSuccess;
+  hipLaunchKernelGGL(atomic_replay, dim3((n_lanes + kCoreBlock - 1) / kCoreBlock), dim3(kCoreBlock), 0, st,
+                     log, log_cap, log_count, n_lanes);
   return hipGetLastError();
 }
 

@@ -33,7 +33,8 @@ ERROR_NAMES = {0: "PMC_OK", -1: "PMC_E_INVAL", -2: "PMC_E_NOPHASE", -3: "PMC_E_B
 # every symbol declared in include/pmc.h
 EXPORTS = ["pmc_create", "pmc_destroy", "pmc_last_error", "pmc_load_phase", "pmc_unload_phase",
            "pmc_load_spots", "pmc_load_plan", "pmc_unload_plan", "pmc_request_items", "pmc_request_item_histories", "pmc_launch_shape", "pmc_dose",
-           "pmc_dose_device", "pmc_dose_device_notify", "pmc_dose_device_noalloc", "pmc_balance_from_counters",
+           "pmc_dose_device", "pmc_dose_device_notify", "pmc_dose_device_noalloc", "pmc_atomic_log", "pmc_atomic_replay",
+           "pmc_balance_from_counters",
            "pmc_convert_device", "pmc_trace", "pmc_split_histories", "pmc_bytes_in_use",
            "pmc_graph_create", "pmc_graph_launch", "pmc_graph_destroy", "pmc_influence_boxes",
            "pmc_influence", "pmc_influence_read", "pmc_influence_device", "pmc_influence_free",
@@ -158,6 +159,8 @@ def lib():
         L.pmc_dose_device.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp]
         L.pmc_dose_device_notify.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, vp]
         L.pmc_dose_device_noalloc.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp]
+        L.pmc_atomic_log.argtypes = [vp, C.POINTER(pmc_request), vp, vp, vp, vp, u32, vp]
+        L.pmc_atomic_replay.argtypes = [vp, vp, vp, u32, vp, u32]
         L.pmc_balance_from_counters.argtypes = [vp, C.POINTER(pmc_request), vp, vp,
                                                 C.POINTER(pmc_balance)]
         L.pmc_convert_device.argtypes = [vp, i32, vp, u64, vp, vp, vp]
@@ -298,6 +301,18 @@ def pmc_dose_device_noalloc(ctx, req: Request, stream: int, dev_tallies: Sequenc
     tp = (C.c_void_p * req.n_phases)(*[int(p) for p in dev_tallies])
     _check(lib().pmc_dose_device_noalloc(ctx, C.byref(req.c), C.c_void_p(stream), tp,
                                          C.c_void_p(dev_counters)), ctx)
+
+
+def pmc_atomic_log(ctx, req: Request, stream: int, dev_tallies: Sequence[int], dev_counters: int,
+                   dev_log: int, per_lane: int, dev_log_count: int) -> None:
+    tp = (C.c_void_p * req.n_phases)(*[int(p) for p in dev_tallies])
+    _check(lib().pmc_atomic_log(ctx, C.byref(req.c), C.c_void_p(stream), tp, C.c_void_p(dev_counters),
+                                C.c_void_p(dev_log), per_lane, C.c_void_p(dev_log_count)), ctx)
+
+
+def pmc_atomic_replay(ctx, stream: int, dev_log: int, per_lane: int, dev_log_count: int, n_lanes: int) -> None:
+    _check(lib().pmc_atomic_replay(ctx, C.c_void_p(stream), C.c_void_p(dev_log), per_lane,
+                                   C.c_void_p(dev_log_count), n_lanes), ctx)
 
 
 def pmc_dose_device_notify(ctx, req: Request, stream: int, dev_tallies: Sequence[int],

@@ -176,3 +176,67 @@ def test_core_mode_mixed_calibrations_and_mask(P):
         assert not tp[0][body.reshape(-1) == 0].any()
     finally:
         e.close()
+
+
+def test_atomic_log_and_replay(P):
+    """The measurement hook of the deposit-address pattern: a logged block-
+    engine launch gives the same tallies and counters as the plain one; the
+    lanes' logged counts add up to the device-wide atomics the counters
+    report; every logged address is an 8-byte slot of one of the request's
+    tallies; the replay adds exactly one per replayed entry to the tallies
+    (so each replayed atomic hit the logged voxel), with a per-lane cap
+    below some lanes' counts."""
+    import torch
+    wl = W.workload_thorax4d(n_histories=300_000, shape_xyz=(96, 96, 60))
+    e = engine(P, wl)
+    try:
+        phases = [1, 4, 8]
+        nv = wl.phases[0].nvox
+        st = torch.cuda.current_stream()
+        grid = 12
+        lanes = grid * 1024
+        req = P.Request(wl.n_histories, phases, engine=P.PMC_ENGINE_PERSISTENT, tally_mode=P.PMC_TALLY_CORE,
+                        grid_blocks=grid)
+        ref = [torch.zeros(nv, dtype=torch.int64, device="cuda") for _ in phases]
+        cref = torch.zeros(P.PMC_COUNTERS, dtype=torch.int64, device="cuda")
+        P.pmc_dose_device(e.ctx, req, st.cuda_stream, [t.data_ptr() for t in ref], cref.data_ptr())
+        tal = [torch.zeros(nv, dtype=torch.int64, device="cuda") for _ in phases]
+        cnt = torch.zeros(P.PMC_COUNTERS, dtype=torch.int64, device="cuda")
+        cap = 64
+        log = torch.zeros(cap * lanes, dtype=torch.int64, device="cuda")
+        count = torch.zeros(lanes, dtype=torch.int32, device="cuda")
+        say("logged block-engine launch", wl.n_histories, "lanes", lanes)
+        P.pmc_atomic_log(e.ctx, req, st.cuda_stream, [t.data_ptr() for t in tal], cnt.data_ptr(),
+                         log.data_ptr(), cap, count.data_ptr())
+        torch.cuda.synchronize()
+        for a, b in zip(tal, ref):
+            assert torch.equal(a, b)
+        assert torch.equal(cnt, cref)
+        c = count.cpu().numpy().astype(np.int64)
+        assert c.sum() == int(cnt[12].item()) and c.max() > cap
+        n_rep = np.minimum(c, cap)
+        lg = log.cpu().numpy().reshape(cap, lanes)
+        used = np.arange(cap)[:, None] < n_rep[None, :]
+        addr = lg[used].astype(np.uint64)
+        base = np.array([t.data_ptr() for t in tal], dtype=np.uint64)
+        order = np.argsort(base)
+        w = np.searchsorted(base[order], addr, side="right") - 1
+        assert np.all(w >= 0)
+        which = order[w]
+        off = addr - base[which]
+        assert np.all(off % 8 == 0) and np.all(off // 8 < nv)
+        before = [t.clone() for t in tal]
+        say("replay", int(n_rep.sum()), "atomics")
+        P.pmc_atomic_replay(e.ctx, st.cuda_stream, log.data_ptr(), cap, count.data_ptr(), lanes)
+        torch.cuda.synchronize()
+        added = np.zeros(len(phases) * nv, dtype=np.int64)
+        np.add.at(added, which.astype(np.int64) * nv + (off // 8).astype(np.int64), 1)
+        for i, (a, b) in enumerate(zip(tal, before)):
+            assert np.array_equal((a - b).cpu().numpy(), added[i * nv:(i + 1) * nv]), i
+        with pytest.raises(P.PmcError):  # the log needs the block engine
+            P.pmc_atomic_log(e.ctx, P.Request(1000, [1], engine=P.PMC_ENGINE_PERSISTENT,
+                                              tally_mode=P.PMC_TALLY_LANE, grid_blocks=grid),
+                             st.cuda_stream, [tal[0].data_ptr()], cnt.data_ptr(), log.data_ptr(), cap,
+                             count.data_ptr())
+    finally:
+        e.close()
