@@ -12,11 +12,20 @@ HIP graph and replayed.  Plain engine (reported beside it): one launch per
 phase, one history per thread, no refill, no graph.  Both give identical
 integer tallies (checked).
 
-Latency (reported beside it): a Poisson stream of single-phase dose requests
-of mixed grid and history counts served by the serving loop (persistent
-engine, slices, least-slowdown order) and, on the same requests, by the
-plain engine serially in arrival order; p50/p99 of arrival -> dose on the
-host, and identical doses per request (checked).
+Also measured, each with its own check:
+* roofline: the transport kernel's device-wide atomics against a replay of
+  its own logged deposit addresses, and its VALU rate;
+* serving: a Poisson stream of single-phase requests of mixed grid and
+  history counts at loads 0.5, 0.8 and 1.2 x the plain engine's service
+  rate, with the full and a forced 2 GiB device-memory budget; p50/p99 of
+  arrival -> dose on the host against the plain engine run serially;
+  identical doses per request;
+* the 40^3 water and 128^3 slab configurations; phantoms shaped like the
+  paper's lung, esophagus and liver cases (Table I grids); the robust-
+  optimisation workload (90 calculations + influence matrices); delivery
+  simulation, deformable accumulation and the 25-trial 4D loop;
+* the FP64 oracle on the host (cpu_baseline), timed on a sample of the same
+  histories and used as the accuracy check of the GPU's.
 
 Prints one JSON line.
 """
@@ -118,7 +127,16 @@ def parse():
     p.add_argument("--acc-cpu-seconds", type=float, default=10.0)
     p.add_argument("--latency-requests", type=int, default=200,
                    help="served-stream requests for the p50/p99 latency comparison (0 = skip)")
-    p.add_argument("--latency-load", type=float, default=0.8)
+    p.add_argument("--latency-loads", type=str, default="0.5,0.8,1.2",
+                   help="served-stream loads (x the plain engine's service rate)")
+    p.add_argument("--latency-budgets-gb", type=str, default="0,2",
+                   help="device-memory budgets of the serving loop, GiB (0 = 0.9 x free)")
+    p.add_argument("--cases", type=str, default="lung,esophagus,liver",
+                   help="patient-shaped 4D cases to measure ('' = none)")
+    p.add_argument("--case-steps", type=int, default=3)
+    p.add_argument("--case-cpu-seconds", type=float, default=5.0)
+    p.add_argument("--no-robust", action="store_true")
+    p.add_argument("--no-configs", action="store_true")
     p.add_argument("--mode", choices=["bench", "single-history", "copy-calibration", "accumulation-scan"],
                    default="bench")
     return p.parse_args()
@@ -142,6 +160,12 @@ def main():
         t0 = time.time()
         served = serve.prebuild(a.latency_requests, workers=8)
         log(f"served stream: {a.latency_requests} requests generated in {time.time() - t0:.1f} s")
+    cases = {}
+    if a.mode == "bench" and a.cases:
+        for name in a.cases.split(","):
+            t0 = time.time()
+            cases[name] = W.workload_case(name, 50_000_000, workers=8)
+            log(f"case {name}: {len(cases[name].plan.spots)} spots, 10 phases generated in {time.time() - t0:.1f} s")
 
     if a.mode == "copy-calibration":
         # plain device-to-device copies of 4 GiB (far larger than the 256 MB
@@ -331,25 +355,45 @@ def main():
         gpu_sample = [t.cpu().numpy() for t in tallies]
     eng.close()
     latency = None
+    serving = None
     if served is not None:
-        log(f"served stream: {a.latency_requests} requests at load {a.latency_load}")
-        res = serve.run_scenario(a.latency_requests, a.latency_load, prebuilt=served,
-                                 log=lambda m: log("serve:", m))
+        loads = [float(x) for x in a.latency_loads.split(",")]
+        budgets = [int(float(x) * 2**30) for x in a.latency_budgets_gb.split(",")]
+        log(f"served stream: {a.latency_requests} requests at loads {loads}, budgets {a.latency_budgets_gb} GiB "
+            f"(0 = 0.9 x free)")
+        res = serve.run_grid(a.latency_requests, loads, budgets, prebuilt=served,
+                             log=lambda m: log("serve:", m))
         keys = ("p50_latency_s", "p99_latency_s", "mean_latency_s", "max_latency_s",
-                "throughput_hist_per_s", "makespan_s", "slices")
-        latency = {
-            "workload": f"served stream: {a.latency_requests} single-phase thorax requests, grids 64^3 to "
-                        f"256x256x160, 50-3000 spots, 1e5-5e7 histories (log-uniform), Poisson "
-                        f"arrivals at {a.latency_load} x the plain engine's service rate",
-            "arrival_rate_hz": res["arrival_rate_hz"],
-            "batched": {k: res["batched"][k] for k in keys},
-            "plain_serial": {k: res["plain-serial"][k] for k in keys},
-            "identical_doses": res["identical_doses"], "requests": a.latency_requests,
-        }
-        log(f"latency p50/p99: batched {latency['batched']['p50_latency_s'] * 1e3:.0f}/"
-            f"{latency['batched']['p99_latency_s'] * 1e3:.0f} ms, plain "
-            f"{latency['plain_serial']['p50_latency_s'] * 1e3:.0f}/"
-            f"{latency['plain_serial']['p99_latency_s'] * 1e3:.0f} ms")
+                "throughput_hist_per_s", "makespan_s", "slices", "peak_bytes", "phantom_loads", "evictions")
+        workload = (f"served stream: {a.latency_requests} single-phase thorax requests, grids 64^3 to "
+                    f"256x256x160, 50-3000 spots, 1e5-5e7 histories (log-uniform), Poisson arrivals at a "
+                    f"load x the plain engine's service rate")
+        serving = {"workload": workload, "plain_calibration_hist_per_s": res["plain_calibration_hist_per_s"],
+                   "scenarios": [{"load": sc["load"], "budget": sc["budget"], "budget_bytes": sc["budget_bytes"],
+                                  "arrival_rate_hz": sc["arrival_rate_hz"],
+                                  "batched": {k: sc["batched"].get(k) for k in keys},
+                                  "plain_serial": {k: sc["plain_serial"].get(k) for k in keys},
+                                  "identical_doses": sc["identical_doses"],
+                                  "batched_p99_le_plain": sc["batched"]["p99_latency_s"]
+                                  <= sc["plain_serial"]["p99_latency_s"]}
+                                 for sc in res["scenarios"]]}
+        head = next((sc for sc in serving["scenarios"] if sc["load"] == 0.8 and sc["budget"] == "full"),
+                    serving["scenarios"][0])
+        latency = {"workload": workload.replace("a load", f"{head['load']}"), "load": head["load"],
+                   "budget": head["budget"], "arrival_rate_hz": head["arrival_rate_hz"],
+                   "batched": head["batched"], "plain_serial": head["plain_serial"],
+                   "identical_doses": head["identical_doses"], "requests": a.latency_requests}
+        for sc in serving["scenarios"]:
+            log(f"latency load {sc['load']} budget {sc['budget']}: batched p50/p99 "
+                f"{sc['batched']['p50_latency_s'] * 1e3:.0f}/{sc['batched']['p99_latency_s'] * 1e3:.0f} ms, "
+                f"plain {sc['plain_serial']['p50_latency_s'] * 1e3:.0f}/"
+                f"{sc['plain_serial']['p99_latency_s'] * 1e3:.0f} ms, identical {sc['identical_doses']}")
+    configs = None if a.no_configs else configs_bench(not a.no_cpu_baseline)
+    case_out = {}
+    for name, cwl in cases.items():
+        case_out[name] = case_bench(cwl, a.case_steps, 1, 0 if a.no_cpu_baseline else a.case_cpu_seconds)
+        cases[name] = None
+    robust_out = None if a.no_robust else robust_bench(0 if a.no_cpu_baseline else 5.0)
     cpu = None if a.no_cpu_baseline else cpu_baseline(wl, k_sample, gpu_sample)
     out = {
         "metric": "proton histories/s; p50/p99 dose-request latency, batched vs plain, 1 MI355X",
@@ -364,6 +408,10 @@ def main():
                    "launch": tuned, "graph": graph is not None},
         "plain": plain,
         "latency": latency,
+        "serving": serving,
+        "cases": case_out or None,
+        "robust": robust_out,
+        "configs": configs,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accumulation": accumulation,
@@ -939,20 +987,22 @@ def cpu_sample_size(wl, target_s):
     return k2
 
 
-def cpu_baseline(wl, k, gpu_sample):
+def cpu_baseline(wl, k, gpu_sample, label=None):
     """The FP64 oracle on the host, on the first k histories of every spot,
     timed; then the accuracy check of the GPU's tallies of the same
     histories against it: voxels above 10 % of the phase's maximum dose pass
     if |dD| <= 1 % of that maximum or <= 3 sigma_diff (sqrt 2 x the oracle's
-    sigma from 10 history batches); total energy within 0.1 %."""
+    sigma from 10 history batches), in at least 99.5 % of them (the same
+    random numbers); total energy within 0.1 %."""
     import numpy as np
     import oracle
     cores = os.cpu_count() or 1
     t = time.perf_counter()
-    _, b = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k, n_threads=cores)
+    _, b = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k, n_threads=cores,
+                              request_id=wl.request_id)
     dt = time.perf_counter() - t
     out = {"value": b["histories"] / dt, "unit": "histories/s", "cores": cores, "kind": "oracle",
-           "sample": f"first {k} histories of every spot of the thorax4d plan "
+           "sample": f"first {k} histories of every spot of the {label or wl.name} plan "
                      f"({b['histories']} histories, {b['steps']} steps, {dt:.1f} s, FP64)",
            "steps_per_history": b["steps"] / max(b["histories"], 1)}
     if gpu_sample is None:
@@ -962,7 +1012,7 @@ def cpu_baseline(wl, k, gpu_sample):
     s2 = [np.zeros(ph.hu.size) for ph in wl.phases]
     for r in range(nb):
         tb, _ = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k, n_threads=cores,
-                                   h_mod=nb, h_rem=r)
+                                   request_id=wl.request_id, h_mod=nb, h_rem=r)
         for i, x in enumerate(tb):
             x = x.astype(np.float64)
             s1[i] += x
@@ -992,7 +1042,232 @@ def cpu_baseline(wl, k, gpu_sample):
                                 "least 99.5 % of them; total energy within 0.1 %",
                        "voxels": n_sel, "pass_frac": frac, "energy_rel": e_rel,
                        "passed": bool(frac >= SAME_SEED_MIN_PASS and e_rel <= 1e-3)}
-    log(f"accuracy on the sample: {n_sel} voxels above 10 % Dmax, pass {frac:.4f}, dE {e_rel:.2e}")
+    log(f"accuracy on the {label or wl.name} sample: {n_sel} voxels above 10 % Dmax, pass {frac:.4f}, "
+        f"dE {e_rel:.2e}")
+    return out
+
+
+def gpu_first_k(eng, pmc, wl, phases, k, tally_mode, tallies, counters, stream, torch):
+    """The GPU's tallies of the first k histories of every spot of the
+    request: the first round of work items of k histories (queue order:
+    the first run of every spot, in plan order)."""
+    import numpy as np
+    per = pmc.pmc_split_histories(wl.plan.spots, phases, wl.n_histories)
+    req = pmc.Request(wl.n_histories, phases, request_id=wl.request_id, engine=pmc.PMC_ENGINE_PERSISTENT,
+                      chunk=k, tally_mode=tally_mode, item_begin=0, item_end=int(np.count_nonzero(per)))
+    for t in tallies:
+        t.zero_()
+    pmc.pmc_dose_device(eng.ctx, req, stream.cuda_stream, [t.data_ptr() for t in tallies], counters.data_ptr())
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in tallies]
+
+
+def case_bench(wl, steps, plain_steps, cpu_seconds):
+    """One 4D dose calculation of a patient-shaped case (10 phases, the
+    case's plan, wl.n_histories): the library's default launch shape and
+    its graph, timed as the thorax step; the plain engine beside it
+    (identical tallies); the oracle on a sample of the same histories."""
+    import numpy as np
+    import torch
+    from paper_1809_03927_amd import pmc
+    eng = pmc.Engine(device=0, precision=pmc.PMC_FP32, seed=wl.seed)
+    try:
+        eng.load_workload(wl)
+        phases = list(range(len(wl.phases)))
+        nv = wl.phases[0].nvox
+        tallies = [torch.zeros(nv, dtype=torch.int64, device="cuda") for _ in phases]
+        doses = [torch.zeros(nv, dtype=torch.float64, device="cuda") for _ in phases]
+        counters = torch.zeros(pmc.PMC_COUNTERS, dtype=torch.int64, device="cuda")
+        stream = torch.cuda.current_stream()
+        tptr = [t.data_ptr() for t in tallies]
+        req_b = pmc.Request(wl.n_histories, phases, request_id=wl.request_id, engine=pmc.PMC_ENGINE_PERSISTENT)
+        shape = pmc.pmc_launch_shape(eng.ctx, req_b)
+
+        def eager(req):
+            for t in tallies:
+                t.zero_()
+            counters.zero_()
+            pmc.pmc_dose_device(eng.ctx, req, stream.cuda_stream, tptr, counters.data_ptr())
+            for i, p in enumerate(phases):
+                pmc.pmc_convert_device(eng.ctx, p, tptr[i], wl.n_histories, stream.cuda_stream,
+                                       doses[i].data_ptr(), None)
+
+        def timed(fn, n, warm):
+            for _ in range(warm):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / n
+
+        def balance(req):
+            c = counters.cpu().numpy().astype(np.uint64)
+            dep = sum((int((t >> 32).sum().item()) << 32) + int((t & 0xFFFFFFFF).sum().item()) for t in tallies)
+            b = pmc.pmc_balance_from_counters(eng.ctx, req, c, dep)
+            b["atomics"] = int(c[12])
+            return b
+
+        eager(req_b)
+        torch.cuda.synchronize()
+        g = pmc.pmc_graph_create(eng.ctx, req_b, tptr, counters.data_ptr(), [d.data_ptr() for d in doses])
+        try:
+            sec_b = timed(lambda: pmc.pmc_graph_launch(g, stream.cuda_stream, eng.ctx), steps, 1)
+        finally:
+            pmc.pmc_graph_destroy(g)
+        bal = balance(req_b)
+        assert bal["deposited"] + bal["escaped"] + bal["nuclear"] == bal["incident"], bal
+        assert bal["histories"] == wl.n_histories
+        tal_b = [t.clone() for t in tallies]
+        req_p = pmc.Request(wl.n_histories, phases, request_id=wl.request_id, engine=pmc.PMC_ENGINE_PLAIN)
+        sec_p = timed(lambda: eager(req_p), plain_steps, 0)
+        same = all(torch.equal(x, y) for x, y in zip(tal_b, tallies))
+        assert same, f"{wl.name}: plain and batched tallies differ"
+        del tal_b
+        c = wl.name.split("4d_")[0]
+        out = {"workload": f"{c}-shaped 4D: 10 phases x {'x'.join(map(str, wl.phases[0].shape_xyz))} at "
+                           f"{'x'.join(f'{v:g}' for v in wl.phases[0].spacing_mm)} mm, {len(wl.plan.spots)} spots "
+                           f"in {len(wl.plan.fields)} fields, {wl.n_histories:.0e} histories",
+               "value": wl.n_histories / sec_b, "unit": "histories/s", "ms_per_step": sec_b * 1e3,
+               "steps": steps, "steps_per_history": bal["steps"] / wl.n_histories,
+               "atomics_per_history": bal["atomics"] / wl.n_histories,
+               "spots_per_phase": np.bincount(wl.plan.spots["phase"], minlength=len(phases)).tolist(),
+               "launch": {k: shape[k] for k in ("block_size", "chunk", "refill_min", "tally_mode")},
+               "plain": {"value": wl.n_histories / sec_p, "ms_per_step": sec_p * 1e3,
+                         "speedup_batched_vs_plain": sec_p / sec_b, "tallies_identical": same}}
+        log(f"{c}: batched {sec_b * 1e3:.1f} ms/step ({wl.n_histories / sec_b:.3g} histories/s, "
+            f"{bal['steps'] / wl.n_histories:.1f} steps/history), plain {sec_p * 1e3:.1f} ms (x{sec_p / sec_b:.2f})")
+        if cpu_seconds:
+            k = cpu_sample_size(wl, cpu_seconds)
+            sample = gpu_first_k(eng, pmc, wl, phases, k, shape["tally_mode"], tallies, counters, stream, torch)
+            out["cpu_baseline"] = cpu_baseline(wl, k, sample, label=c)
+        return out
+    finally:
+        eng.close()
+
+
+def robust_bench(cpu_seconds):
+    """Robust-optimisation scale (the future use of Sec. 4.C): the thorax 4D
+    phantom, 10 phases x 9 scenarios of the 3-field 8000-spot plan, 2e7
+    histories per calculation, all 90 arriving at once, through the serving
+    loop (batched) and one after the other with the plain engine (doses
+    identical); the 1 % influence matrix of the nominal scenario on all ten
+    phases.  The oracle checks a sample of one calculation (RSP x 1.035,
+    phase 3)."""
+    import numpy as np
+    import torch
+    from paper_1809_03927_amd import pmc, robust
+    from paper_1809_03927_amd import workloads as W
+    res = robust.run(n_histories=20_000_000, log=lambda m: log("robust:", m))
+    keys = ("p50_latency_s", "p99_latency_s", "mean_latency_s", "max_latency_s", "throughput_hist_per_s",
+            "makespan_s")
+    out = {"workload": f"robust: thorax 4D 10 phases x 9 scenarios (setup +-3 mm x/y/z, RSP x 1.035/0.965) "
+                       f"= {res['calculations']} calculations of the 3-field {res['spots']}-spot plan, "
+                       f"{res['histories_per_calculation']:.0e} histories each, all arriving at once",
+           "value": res["batched"]["throughput_hist_per_s"], "unit": "histories/s",
+           "batched": {k: res["batched"][k] for k in keys},
+           "plain_serial": {k: res["plain-serial"][k] for k in keys},
+           "speedup_batched_vs_plain": res["plain-serial"]["makespan_s"] / res["batched"]["makespan_s"],
+           "identical_doses": res["identical_doses"], "calculations": res["calculations"],
+           "influence": {k: res["influence"][k] for k in ("rel_threshold", "total_seconds", "total_nnz",
+                                                          "histories_per_s")}}
+    out["influence"]["per_phase_ms"] = [round(x["seconds"] * 1e3, 1) for x in res["influence"]["phases"]]
+    log(f"robust: batched {res['batched']['makespan_s']:.2f} s, plain {res['plain-serial']['makespan_s']:.2f} s "
+        f"(x{out['speedup_batched_vs_plain']:.2f}); influence {res['influence']['total_seconds']:.2f} s for 10 phases")
+    if cpu_seconds:
+        name, shift, scale = W.ROBUST_SCENARIOS[7]
+        ph = W.scaled_calibration(W.make_thorax((256, 256, 160), 3, 10), scale)
+        plan = W.plan_robust(5, shift_mm=shift)
+        plan.spots["phase"] = 0
+        wl = W.Workload(f"robust_{name}_phase3", [ph], plan, 20_000_000, seed=5)
+        eng = pmc.Engine(device=0, precision=pmc.PMC_FP32, seed=wl.seed)
+        try:
+            eng.load_workload(wl)
+            tallies = [torch.zeros(ph.nvox, dtype=torch.int64, device="cuda")]
+            counters = torch.zeros(pmc.PMC_COUNTERS, dtype=torch.int64, device="cuda")
+            k = cpu_sample_size(wl, cpu_seconds)
+            sample = gpu_first_k(eng, pmc, wl, [0], k, 0, tallies, counters, torch.cuda.current_stream(), torch)
+        finally:
+            eng.close()
+        out["cpu_baseline"] = cpu_baseline(wl, k, sample, label=f"robust {name} phase 3")
+    return out
+
+
+def configs_bench(cpu):
+    """The two single-phase configurations: 40^3 water with one 150 MeV spot
+    (1e5 histories) and the 128^3 slabs with 500 spots (1e7 histories):
+    histories/s of the persistent engine (autotuned over lane and block
+    shapes, items of a few histories per lane included) and of the plain
+    engine; the oracle timed at one thread and at every host thread (the
+    water case in full, the slabs on the first 20 and 200 histories of every
+    spot)."""
+    import numpy as np
+    import torch
+    from paper_1809_03927_amd import autotune, pmc
+    from paper_1809_03927_amd import workloads as W
+    out = {}
+    for wl in (W.workload_tiny(), W.workload_slabs()):
+        eng = pmc.Engine(device=0, precision=pmc.PMC_FP32, seed=wl.seed)
+        try:
+            eng.load_workload(wl)
+            nv = wl.phases[0].nvox
+            t = torch.zeros(nv, dtype=torch.int64, device="cuda")
+            c = torch.zeros(pmc.PMC_COUNTERS, dtype=torch.int64, device="cuda")
+            st = torch.cuda.current_stream()
+            res = {}
+            e = wl.plan.spots["energy_MeV"]
+            key = autotune.shape_key(torch.cuda.get_device_name(0), [wl.phases[0].shape_xyz],
+                                     len(wl.plan.spots), wl.n_histories, (float(e.min()), float(e.max())))
+            dflt = pmc.pmc_launch_shape(eng.ctx, pmc.Request(wl.n_histories, [0], request_id=wl.request_id,
+                                                             engine=pmc.PMC_ENGINE_PERSISTENT))
+            tuned = autotune.tune(eng.ctx, [0], key, [t.data_ptr()], c.data_ptr(), st.cuda_stream,
+                                  torch.cuda.synchronize, wl.n_histories, request_id=wl.request_id,
+                                  cache_path=None, candidates=autotune.SMALL_CANDIDATES, repeats=2,
+                                  prefer=(dflt["block_size"], dflt["chunk"], dflt["refill_min"], dflt["tally_mode"]))
+            shape = {k: tuned[k] for k in ("block_size", "chunk", "refill_min", "tally_mode")}
+            for label, engine in (("batched", pmc.PMC_ENGINE_PERSISTENT), ("plain", pmc.PMC_ENGINE_PLAIN)):
+                kw = shape if engine == pmc.PMC_ENGINE_PERSISTENT else {}
+                req = pmc.Request(wl.n_histories, [0], request_id=wl.request_id, engine=engine, **kw)
+                spans = []
+                for r in range(4):
+                    t.zero_()
+                    c.zero_()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(st)
+                    pmc.pmc_dose_device(eng.ctx, req, st.cuda_stream, [t.data_ptr()], c.data_ptr())
+                    e1.record(st)
+                    torch.cuda.synchronize()
+                    if r:
+                        spans.append(e0.elapsed_time(e1))
+                res[label] = {"value": wl.n_histories / (np.mean(spans) * 1e-3), "ms": float(np.mean(spans))}
+                res[label + "_tally"] = t.clone()
+            same = torch.equal(res.pop("batched_tally"), res.pop("plain_tally"))
+        finally:
+            eng.close()
+        entry = {"workload": wl.name, "histories": wl.n_histories, "unit": "histories/s",
+                 "batched": {**res["batched"], "launch": shape}, "plain": res["plain"],
+                 "speedup_batched_vs_plain": res["batched"]["value"] / res["plain"]["value"],
+                 "tallies_identical": bool(same)}
+        if cpu:
+            import oracle
+            cores = os.cpu_count() or 1
+            k1, kn = (None, None) if wl.n_histories <= 100_000 else (20, 200)
+            orc = {}
+            for threads, k in ((1, k1), (cores, kn)):
+                t0 = time.perf_counter()
+                if k is None:
+                    _, _, b = oracle.dose(wl.phases, wl.plan, wl.n_histories, wl.seed, n_threads=threads,
+                                          with_dose=False)
+                else:
+                    _, b = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k, n_threads=threads)
+                dt = time.perf_counter() - t0
+                orc[f"threads_{threads}"] = {"value": b["histories"] / dt, "histories": b["histories"],
+                                             "seconds": dt, "full_run": k is None}
+            entry["cpu_baseline"] = {"kind": "oracle", "unit": "histories/s", "cores": cores, **orc}
+        log(f"{wl.name}: batched {entry['batched']['value']:.3g}, plain {entry['plain']['value']:.3g} histories/s"
+            + (f"; oracle {entry['cpu_baseline']}" if cpu else ""))
+        out[wl.name] = entry
     return out
 
 

@@ -31,6 +31,10 @@ REFILLS = (32, 48, 64)
 # (block, chunk, refill, tally mode)
 LANE_CANDIDATES = [(b, c, r, pmc.PMC_TALLY_LANE) for b, c, r in itertools.product(BLOCKS, CHUNKS, REFILLS)]
 CORE_CANDIDATES = [(1024, c, r, pmc.PMC_TALLY_CORE) for c in (4096, 8192, 16384) for r in (32, 64)]
+# small requests: work items of a few histories per lane, so that every CU
+# gets some
+SMALL_CANDIDATES = (LANE_CANDIDATES
+                    + [(1024, c, 64, pmc.PMC_TALLY_CORE) for c in (1024, 2048, 4096, 8192)])
 # a short list for large requests, timed at full size
 FULL_SIZE_CANDIDATES = CORE_CANDIDATES + [(1024, 256, 64, pmc.PMC_TALLY_LANE),
                                           (512, 64, 64, pmc.PMC_TALLY_LANE)]

@@ -535,6 +535,18 @@ int32_t core_capacity(const pmc_context *ctx, bool lut_lds) {
 }
 
 // Requires a validated request.
+// Histories per work item of the block engine: kCoreChunk (8 per lane of a
+// block), halved down to one per lane while the request has fewer than that
+// per CU (small requests: more, shorter items spread over more CUs).
+int32_t core_chunk(const pmc_context *ctx, const pmc_request *req) {
+  if (req->chunk > 0) return req->chunk;
+  const int64_t n_cu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+  const int64_t per_cu = (int64_t)(req->n_histories / (uint64_t)n_cu);
+  int32_t c = kCoreChunk;
+  while (c > pmc::kCoreBlock && c > per_cu) c >>= 1;
+  return c;
+}
+
 LaunchShape launch_shape(const pmc_context *ctx, const pmc_request *req) {
   const bool persistent = req->engine == PMC_ENGINE_PERSISTENT;
   const bool fp32 = ctx->precision != PMC_FP64;
@@ -547,23 +559,26 @@ LaunchShape launch_shape(const pmc_context *ctx, const pmc_request *req) {
     s.mode = PMC_TALLY_LANE;
     const int32_t cap = fp32 ? core_capacity(ctx, same_lut(ctx, req)) : 0;
     if (cap >= kCoreMinEntries && (req->block_size == 0 || req->block_size == pmc::kCoreBlock)) {
+      // the mode is decided on items of kCoreChunk (or the given chunk); a
+      // small request then gets shorter items (core_chunk)
       const int64_t chunk = req->chunk > 0 ? req->chunk : kCoreChunk;
       const std::vector<pmc_spot> &sp = ctx->plans.at(req->plan).spots;
       std::vector<int64_t> per(sp.size(), 0);
       if (split(sp.data(), (int64_t)sp.size(), req->phases, req->n_phases, req->n_histories, per.data()) == 0) {
+        // at least one history per lane of a block per item on average
+        // (counting a spot's partial last item with its full ones): spots
+        // with fewer histories spread better over the lanes of many waves
+        // (lane engine)
         int64_t items = 0;
-        for (int64_t h : per) items += (h + chunk - 1) / chunk;
-        // at least one history per lane of a block per item, and per lane of
-        // the device: smaller requests spread better over lanes of many waves
-        if ((int64_t)req->n_histories >= (int64_t)pmc::kCoreBlock * items &&
-            (int64_t)req->n_histories >= (int64_t)pmc::kCoreBlock * n_cu)
-          s.mode = PMC_TALLY_CORE;
+        for (int64_t h : per)
+          if (h > 0) items += std::max<int64_t>(1, h / chunk);
+        if ((int64_t)req->n_histories >= (int64_t)pmc::kCoreBlock * items) s.mode = PMC_TALLY_CORE;
       }
     }
   }
   if (s.mode == PMC_TALLY_CORE) {
     s.block = pmc::kCoreBlock;
-    s.chunk = req->chunk > 0 ? req->chunk : kCoreChunk;
+    s.chunk = core_chunk(ctx, req);
     s.core_cap = core_capacity(ctx, same_lut(ctx, req));
     return s;
   }
@@ -959,11 +974,18 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     }
     unsigned grid = (unsigned)req->grid_blocks;
     if (grid == 0 && a.cores) {
-      grid = (unsigned)ctx->n_cu;  // one block per CU: the core takes the LDS
+      // one block per CU (the core takes the LDS), but no more blocks than
+      // work items: a block works on one item at a time
+      grid = (unsigned)std::max(1, std::min(ctx->n_cu, a.n_items));
     } else if (grid == 0) {
       int per_cu = pmc::persistent_blocks_per_cu(a, fp64);
       if (per_cu < 1) per_cu = 1;
       grid = (unsigned)(ctx->n_cu * per_cu);
+      // no more blocks than it takes to start every history of the launch
+      // at once (small requests: the others would only stage their tables)
+      const uint64_t hist = std::min<uint64_t>(req->n_histories, (uint64_t)a.n_items * (uint64_t)P.chunk);
+      const uint64_t need = (hist + (uint64_t)a.block - 1) / (uint64_t)a.block;
+      if (need < grid) grid = (unsigned)std::max<uint64_t>(1, need);
     }
     a.grid = grid;
     HIP_TRY(ctx, pmc::launch_persistent(a, fp64, st), "transport_persistent launch");

@@ -846,6 +846,63 @@ def run_scenario(n_requests=200, load=0.8, seed=4, budget_bytes=0, h_lo=1e5, h_h
         pmc.pmc_destroy(ctx)
 
 
+def run_grid(n_requests=200, loads=(0.5, 0.8, 1.2), budgets=(0, 2 << 30), seed=4, h_lo=1e5, h_hi=5e7,
+             slice_histories=4_000_000, launch=None, workers=0, log=None, policy="small-first",
+             n_streams=2, prebuilt=None, small=2.2e6):
+    """The same served stream at several loads and device-memory budgets.
+    The plain engine's service rate is calibrated once; per load the stream
+    is served once by the plain engine serially in arrival order (one
+    request at a time: the budget does not change it) and once per budget by
+    the batched loop (budget 0 = 0.9 x free device memory).  Every batched
+    run's doses must equal the plain run's request by request."""
+    if prebuilt is None:
+        prebuilt = prebuild(n_requests, seed, h_lo, h_hi, workers, log)
+    reqs0, phantoms, plans = prebuilt
+    import torch
+    from . import pmc
+    free, _ = torch.cuda.mem_get_info()
+    full = int(0.9 * free)
+    ctx_full = pmc.pmc_create(0, pmc.PMC_FP32, seed, full)
+    out = {"requests": n_requests, "scenarios": []}
+    try:
+        rate_plain = calibrate_plain(ctx_full, seed, h_lo, h_hi, log)
+        out["plain_calibration_hist_per_s"] = rate_plain
+        for load in loads:
+            lam = load * rate_plain / log_uniform_mean(h_lo, h_hi)
+            reqs = [dataclasses.replace(r, arrival_s=r.arrival_s / lam) for r in reqs0]
+            s_plain, ex_plain, _ = serve_gpu(ctx_full, reqs, phantoms, plans, pmc.PMC_ENGINE_PLAIN, "fifo", full,
+                                             None, slice_histories, log, rate_hist_per_s=rate_plain,
+                                             n_streams=1, small_histories=small)
+            for key in list(ex_plain.slot_of):
+                ex_plain.unload_phantom(key)
+            if log:
+                log(f"load {load}: plain-serial p50 {s_plain['p50_latency_s'] * 1e3:.1f} ms, p99 "
+                    f"{s_plain['p99_latency_s'] * 1e3:.1f} ms")
+            for budget in budgets:
+                b = int(budget or full)
+                ctx = ctx_full if not budget else pmc.pmc_create(0, pmc.PMC_FP32, seed, b)
+                try:
+                    s, ex, _ = serve_gpu(ctx, reqs, phantoms, plans, pmc.PMC_ENGINE_PERSISTENT, policy, b, launch,
+                                         slice_histories, log, rate_hist_per_s=rate_plain, n_streams=n_streams,
+                                         small_histories=small)
+                    for key in list(ex.slot_of):
+                        ex.unload_phantom(key)
+                finally:
+                    if budget:
+                        pmc.pmc_destroy(ctx)
+                same = int(sum(ex.digests[k] == ex_plain.digests.get(k) for k in ex.digests))
+                out["scenarios"].append({"load": load, "budget_bytes": b, "budget": "forced" if budget else "full",
+                                         "arrival_rate_hz": lam, "batched": s, "plain_serial": s_plain,
+                                         "identical_doses": same})
+                if log:
+                    log(f"load {load}, budget {b / 2**30:.1f} GiB: batched p50 {s['p50_latency_s'] * 1e3:.1f} ms, "
+                        f"p99 {s['p99_latency_s'] * 1e3:.1f} ms, {s['throughput_hist_per_s']:.3g} histories/s; "
+                        f"identical doses {same}/{len(ex.digests)}")
+        return out
+    finally:
+        pmc.pmc_destroy(ctx_full)
+
+
 def main():
     p = argparse.ArgumentParser(description="Serve a Poisson stream of dose requests on one GPU.")
     p.add_argument("--requests", type=int, default=200)

@@ -519,6 +519,219 @@ def plan_robust(seed=5, shift_mm=(0.0, 0.0, 0.0)) -> Plan:
                        directions=ROBUST_DIRECTIONS, spots_per_field=[2667, 2667, 2666], iso=iso)
 
 
+# ----------------------------------------------------------------------------
+# Synthetic phantoms shaped like the paper's three patient cases (Table I:
+# lung, esophagus and liver; the CT grids, voxel sizes, field counts, tumour
+# volumes and motion amplitudes of the table).  The anatomy is synthetic:
+# painted geometric structures, sampled at voxel centres, on a grid centred
+# on the origin; the breathing moves the listed structures along +z by
+# d(t) = A sin^4(pi t / 4 s) with A the table's tumour motion.
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class Case:
+    name: str
+    grid: Tuple[int, int, int]            # voxels x, y, z (Table I)
+    voxel_mm: Tuple[float, float, float]  # (Table I)
+    fields: int                           # (Table I)
+    motion_mm: float                      # tumour motion amplitude (Table I)
+    tumour_cm3: float                     # tumour volume (Table I)
+    body_ab_mm: Tuple[float, float]       # body elliptic cylinder semi-axes x, y
+    directions: Tuple[Tuple[float, float, float], ...]
+    pitch_mm: float                       # spot and layer spacing
+    seed: int
+
+
+CASES = {
+    "lung": Case("lung", (427, 246, 161), (1.27, 1.27, 2.00), 3, 5.4, 79.6, (170.0, 115.0),
+                 ((0.0, -1.0, 0.0), (1.0, 0.0, 0.0), (1.0 / math.sqrt(2.0), -1.0 / math.sqrt(2.0), 0.0)),
+                 5.0, 41),
+    "esophagus": Case("esophagus", (430, 272, 235), (1.27, 1.27, 2.00), 2, 5.3, 204.4, (170.0, 120.0),
+                      ((0.0, 1.0, 0.0), (-1.0 / math.sqrt(2.0), 1.0 / math.sqrt(2.0), 0.0)), 6.0, 42),
+    "liver": Case("liver", (452, 307, 281), (1.27, 1.27, 1.50), 3, 7.5, 581.0, (180.0, 130.0),
+                  ((0.0, -1.0, 0.0), (-1.0, 0.0, 0.0), (-1.0 / math.sqrt(2.0), 1.0 / math.sqrt(2.0), 0.0)),
+                  7.0, 43),
+}
+
+
+def _case_axes(c: Case):
+    nx, ny, nz = c.grid
+    sp = c.voxel_mm
+    org = tuple(-0.5 * n * d for n, d in zip(c.grid, sp))
+    x = org[0] + (np.arange(nx) + 0.5) * sp[0]
+    y = org[1] + (np.arange(ny) + 0.5) * sp[1]
+    z = org[2] + (np.arange(nz) + 0.5) * sp[2]
+    return sp, org, x[None, None, :], y[None, :, None], z[:, None, None]
+
+
+def case_tumour(c: Case, d: float):
+    """Tumour of the case at breathing shift d: ('sphere', centre, r) or
+    ('cylinder', (x, y, z centre), r, half-length) along z."""
+    if c.name == "esophagus":
+        half = 0.5 * c.tumour_cm3 * 1000.0 / (math.pi * 20.0 ** 2)
+        return ("cylinder", (0.0, -40.0, 0.0 + d), 20.0, half)
+    r = (3.0 * c.tumour_cm3 * 1000.0 / (4.0 * math.pi)) ** (1.0 / 3.0)
+    centre = (-85.0, 20.0, -10.0 + d) if c.name == "lung" else (-60.0, 15.0, 10.0 + d)
+    return ("sphere", centre, r)
+
+
+def make_case(name: str, phase: int = 0, n_phases: int = 10, period: float = 4.0) -> Phase:
+    """One breathing phase of the named case.
+
+    Every case: air -1000; body elliptic cylinder HU 40; vertebral body
+    (cylinder r 15 mm, 0.7 b behind the centre) HU 700.
+    * lung: lungs (ellipsoids at (+-85, 10, -20) mm, semi-axes 60, 75, 110)
+      HU -750 and a spherical tumour (79.6 cm^3 at (-85, 20, -10)) HU 40,
+      both moving;
+    * esophagus: lungs at (+-85, 10, 0), semi-axes (60, 75, 160), moving;
+      heart (ellipsoid at (20, 45, -60), semi-axes 55, 45, 55) HU 40; a
+      tumour cylinder around the esophagus (r 20 mm, 204.4 cm^3, along z at
+      (0, -40)) HU 50 with an air lumen (r 5 mm) HU -900, both moving;
+    * liver: lung bases at (+-85, 10, 150), semi-axes (60, 75, 80), moving;
+      liver (ellipsoid at (-55, 10, 20), semi-axes 110, 85, 95) HU 60 and a
+      spherical tumour (581 cm^3 at (-60, 15, 10)) HU 30, both moving.
+    """
+    c = CASES[name]
+    sp, org, X, Y, Z = _case_axes(c)
+    nx, ny, nz = c.grid
+    d = breathing_shift_mm(period * phase / n_phases, amplitude=c.motion_mm, period=period)
+    hu = np.full((nz, ny, nx), -1000, dtype=np.int16)
+    a, b = c.body_ab_mm
+    body = (X / a) ** 2 + (Y / b) ** 2 <= 1.0
+    hu[np.broadcast_to(body, hu.shape)] = 40
+
+    def ellipsoid(cx, cy, cz, ax, ay, az):
+        return ((X - cx) / ax) ** 2 + ((Y - cy) / ay) ** 2 + ((Z - cz) / az) ** 2 <= 1.0
+
+    def paint(mask, value):
+        hu[np.broadcast_to(mask, hu.shape)] = value
+
+    if name == "lung":
+        for cx in (-85.0, 85.0):
+            paint(ellipsoid(cx, 10.0, -20.0 + d, 60.0, 75.0, 110.0), -750)
+    elif name == "esophagus":
+        for cx in (-85.0, 85.0):
+            paint(ellipsoid(cx, 10.0, 0.0 + d, 60.0, 75.0, 160.0), -750)
+        paint(ellipsoid(20.0, 45.0, -60.0, 55.0, 45.0, 55.0), 40)
+    else:
+        for cx in (-85.0, 85.0):
+            paint(ellipsoid(cx, 10.0, 150.0 + d, 60.0, 75.0, 80.0), -750)
+        paint(ellipsoid(-55.0, 10.0, 20.0 + d, 110.0, 85.0, 95.0), 60)
+    paint((X ** 2 + (Y + 0.7 * b) ** 2 <= 15.0 ** 2), 700)
+    t = case_tumour(c, d)
+    if t[0] == "sphere":
+        (tx, ty, tz), r = t[1], t[2]
+        paint((X - tx) ** 2 + (Y - ty) ** 2 + (Z - tz) ** 2 <= r * r, 40 if name == "lung" else 30)
+    else:
+        (tx, ty, tz), r, half = t[1], t[2], t[3]
+        along = np.abs(Z - tz) <= half
+        paint(((X - tx) ** 2 + (Y - ty) ** 2 <= r * r) & along, 50)
+        paint(((X - tx) ** 2 + (Y - ty) ** 2 <= 5.0 ** 2) & along, -900)
+    return Phase(hu, sp, org, CALIB_HU.copy(), CALIB_RHO.copy(), CALIB_RSP.copy())
+
+
+def _energy_for_wet_cm(R: float) -> float:
+    """Proton energy (MeV) whose range in water is R cm, from the
+    Bragg-Kleeman rule R = 0.0022 E^1.77 (a plan-making approximation)."""
+    return (R / 0.0022) ** (1.0 / 1.77)
+
+
+def _wet_to_tumour(ph: Phase, c: Case, direction, iso) -> Tuple[float, float]:
+    """Water-equivalent depth (cm) from where the beam axis through `iso`
+    enters the grid to the tumour's near and far surfaces (0.5 mm samples of
+    the phase's stopping-power ratio along the axis)."""
+    w = np.asarray(direction, float) / np.linalg.norm(direction)
+    ext = np.array(c.grid) * np.array(c.voxel_mm)
+    org = np.array(ph.origin_mm)
+    ts = np.arange(-1000.0, 1000.0, 0.5)
+    pts = np.asarray(iso)[None, :] + ts[:, None] * w[None, :]
+    idx = np.floor((pts - org) / np.array(c.voxel_mm)).astype(int)
+    inside = np.all((idx >= 0) & (idx < np.array(c.grid)), axis=1) & np.all(pts - org < ext, axis=1)
+    idx, pts = idx[inside], pts[inside]
+    hu = ph.hu[idx[:, 2], idx[:, 1], idx[:, 0]].astype(float)
+    wet = np.cumsum(np.interp(hu, ph.calib_hu, ph.calib_rsp)) * 0.05
+    t = case_tumour(c, 0.0)
+    if t[0] == "sphere":
+        (tx, ty, tz), r = t[1], t[2]
+        intum = np.sum((pts - np.array([tx, ty, tz])) ** 2, axis=1) <= r * r
+    else:
+        (tx, ty, tz), r, half = t[1], t[2], t[3]
+        intum = ((pts[:, 0] - tx) ** 2 + (pts[:, 1] - ty) ** 2 <= r * r) & (np.abs(pts[:, 2] - tz) <= half)
+    k = np.nonzero(intum)[0]
+    return float(wet[k[0]]), float(wet[k[-1]])
+
+
+def plan_case(name: str, start_phase: Optional[int] = None, n_phases: int = 10) -> Plan:
+    """Plan of a case: per field, spots on a square grid of pitch_mm in the
+    beam's eye view covering the tumour's projection plus 5 mm, in energy
+    layers pitch_mm of water apart from 5 mm before the tumour's near
+    surface to 5 mm beyond its far surface (along the field's central axis,
+    high to low energy), serpentine; sigma 7 -> 4 mm with energy; weights
+    lognormal(0, 0.5); breathing phases by the simplified delivery clock (2
+    ms per spot, 1 s layer switch, 4 s period, random start phase)."""
+    c = CASES[name]
+    rng = np.random.Generator(np.random.PCG64(c.seed))
+    if start_phase is None:
+        start_phase = int(rng.integers(0, n_phases))
+    ph0 = make_case(name, 0, n_phases)
+    t = case_tumour(c, 0.0)
+    iso = t[1]
+    fields, rows = [], []
+    for fi, dvec in enumerate(c.directions[:c.fields]):
+        w = np.asarray(dvec, float) / np.linalg.norm(dvec)
+        u = np.cross(np.array([0.0, 0.0, 1.0]), w)
+        u = u / np.linalg.norm(u)
+        v = np.cross(w, u)
+        fields.append(make_field(iso, w, u))
+        near, far = _wet_to_tumour(ph0, c, w, iso)
+        r_lo, r_hi = max(near - 0.5, 0.5), far + 0.5
+        step = c.pitch_mm / 10.0
+        n_layers = int(math.floor((r_hi - r_lo) / step)) + 1
+        # BEV footprint: the tumour's projection on (u, v) plus 5 mm
+        if t[0] == "sphere":
+            half_u = half_v = t[2] + 5.0
+        else:
+            half_u = abs(u[2]) * t[3] + t[2] + 5.0
+            half_v = abs(v[2]) * t[3] + t[2] + 5.0
+        nu = int(2 * half_u // c.pitch_mm) + 1
+        nv = int(2 * half_v // c.pitch_mm) + 1
+        pos = [(pu, pv) for (pu, pv) in layer_grid(nu, nv, c.pitch_mm)
+               if t[0] == "cylinder" or pu * pu + pv * pv <= half_u * half_u]
+        counts = []
+        for l in range(n_layers):
+            R = r_hi - l * step
+            e = min(max(_energy_for_wet_cm(R), 70.0), 230.0)
+            sig = 7.0 - 3.0 * (e - 70.0) / 160.0
+            for (pu, pv) in pos:
+                rows.append((e, pu, pv, sig, 0.0, 0, fi))
+            counts.append(len(pos))
+        phs = assign_phases(counts, start_phase, n_phases=n_phases)
+        base = len(rows) - len(phs)
+        for k, p in enumerate(phs):
+            r = list(rows[base + k])
+            r[5] = int(p)
+            rows[base + k] = tuple(r)
+    spots = _spots(rows)
+    spots["weight"] = rng.lognormal(0.0, 0.5, size=len(spots))
+    return Plan(np.array(fields, dtype=FIELD_DTYPE), spots)
+
+
+def workload_case(name: str, n_histories: int = 50_000_000, n_phases: int = 10, workers: int = 0) -> Workload:
+    """The 4D dose calculation of a case: its breathing phases and plan.
+    workers > 0 generates the phases in forked processes (call it before
+    the process touches the GPU)."""
+    if workers > 0:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, n_phases)) as pool:
+            phases = pool.starmap(make_case, [(name, p, n_phases) for p in range(n_phases)])
+    else:
+        phases = [make_case(name, p, n_phases) for p in range(n_phases)]
+    c = CASES[name]
+    plan = plan_case(name, n_phases=n_phases)
+    return Workload(f"{name}4d_{c.grid[0]}x{c.grid[1]}x{c.grid[2]}x{n_phases}", phases, plan, n_histories,
+                    seed=c.seed)
+
+
 def scaled_calibration(phase: Phase, rsp_scale: float) -> Phase:
     """Same phase with its HU->RSP calibration scaled (range uncertainty)."""
     return dataclasses.replace(phase, calib_rsp=phase.calib_rsp * rsp_scale)

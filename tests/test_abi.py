@@ -137,9 +137,11 @@ def test_dose_validation_order(P, vctx):
 def test_launch_shape_defaults(P):
     """Lane mode: work items shrink for small requests so that every resident
     wave (16 per compute unit, 256 units assumed without a device) gets about
-    four of them.  Core mode for large requests with many histories per spot
-    (items of 8192 averaging >= 4096 histories, >= 4 per compute unit).
-    Explicit values pass through."""
+    four of them.  Core mode once the work items (a spot's partial last item
+    counted with its full ones) average at least one history per lane of a
+    1024-thread block; its items hold 8192 histories, halved down to 1024
+    while the request has fewer than that per compute unit.  Explicit values
+    pass through."""
     ctx = P.pmc_create(device=-1)
     pers, lane, core = P.PMC_ENGINE_PERSISTENT, P.PMC_TALLY_LANE, P.PMC_TALLY_CORE
     try:
@@ -152,13 +154,17 @@ def test_launch_shape_defaults(P):
             got = P.pmc_launch_shape(ctx, P.Request(n, [0], engine=pers, tally_mode=lane))
             assert got == {"block_size": 1024, "chunk": chunk, "refill_min": 64, "tally_mode": lane,
                            "core_capacity": 0}, n
-        # core mode from 1024 histories per lane of the device on (items average >= 1024)
-        cap = P.pmc_launch_shape(ctx, P.Request(1024 * 256, [0], engine=pers))
-        assert cap["tally_mode"] == core and cap["chunk"] == 8192 and cap["block_size"] == 1024
-        assert cap["core_capacity"] > 4096
-        assert P.pmc_launch_shape(ctx, P.Request(1024 * 256 - 1, [0], engine=pers))["tally_mode"] == lane
+        # one spot: core mode from 1024 histories on, items of 1024 up to 8192
+        # per compute unit, then of 8192
+        for n, chunk in [(1024, 1024), (100_000, 1024), (2048 * 256 - 1, 1024), (2048 * 256, 2048),
+                         (8192 * 256 - 1, 4096), (8192 * 256, 8192), (P.PMC_MAX_HISTORIES, 8192)]:
+            got = P.pmc_launch_shape(ctx, P.Request(n, [0], engine=pers))
+            assert got["tally_mode"] == core and got["chunk"] == chunk and got["block_size"] == 1024, (n, got)
+            assert got["core_capacity"] > 4096
+        assert P.pmc_launch_shape(ctx, P.Request(1023, [0], engine=pers))["tally_mode"] == lane
         # forced modes, explicit shapes
-        assert P.pmc_launch_shape(ctx, P.Request(10, [0], engine=pers, tally_mode=core))["chunk"] == 8192
+        assert P.pmc_launch_shape(ctx, P.Request(10, [0], engine=pers, tally_mode=core))["chunk"] == 1024
+        assert P.pmc_launch_shape(ctx, P.Request(10**7, [0], engine=pers, tally_mode=core))["chunk"] == 8192
         assert P.pmc_launch_shape(ctx, P.Request(P.PMC_MAX_HISTORIES, [0], engine=pers,
                                                  tally_mode=lane))["tally_mode"] == lane
         assert P.pmc_launch_shape(ctx, P.Request(P.PMC_MAX_HISTORIES, [0], engine=pers,
