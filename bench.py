@@ -602,16 +602,19 @@ def fourd_bench(eng, wl, trials, tally_mode):
     fd.close()
     mc = float(np.mean(out["time_mc_s"]))
     acc = float(np.mean(out["time_accumulation_s"]))
+    host = float(np.mean(out["time_host_s"]))
     dl = out["time_delivery_s"] / trials
     log(f"4D dose: {trials} trials in {total:.2f} s: per trial delivery {dl * 1e3:.1f} ms (one call for all), "
-        f"MC {mc * 1e3:.0f} ms, accumulation {acc * 1e3:.0f} ms")
+        f"device MC {mc * 1e3:.0f} ms, accumulation {acc * 1e3:.0f} ms; host load + enqueue {host * 1e3:.0f} ms "
+        f"(overlapped with the previous trial)")
     return {
         "workload": f"thorax4d phases and plan (250 MU, {len(sp)} spots), {trials} delivery trials "
                     f"(start phase U{{0..9}}, period U{{3..7}} s, sigma 0.4 s, synchrotron uncertainty, "
                     f"repainted 0.005 MU), {wl.n_histories:.0e} histories per 4D dose, EMTM n={ACC_N_SUB} "
                     f"onto phase {ref}",
         "trials": trials, "total_s": total, "s_per_trial": total / trials,
-        "per_trial_s": {"delivery": dl, "mc": mc, "accumulation": acc},
+        "per_trial_s": {"delivery": dl, "mc_device": mc, "accumulation_device": acc,
+                        "host_load_and_enqueue": host},
         "mean_delivery_time_s": float(out["delivery"]["time"].mean()),
         "context": "the paper's Table II: 246-367 s per 4D dose (delivery 7 s, MC 135-175 s on eight GTX "
                    "Titan X, accumulation 45-122 s); other hardware and inputs",

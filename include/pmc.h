@@ -111,7 +111,9 @@ typedef struct {
                              0 = default (see pmc_launch_shape) */
   int32_t chunk;          /* persistent engine: histories per work item; 0 = default */
   int32_t refill_min;     /* persistent engine: refill when >= this many lanes of a wave are idle (1..64); 0 = default */
-  int32_t grid_blocks;    /* persistent engine: blocks; 0 = enough to fill the device */
+  int32_t grid_blocks;    /* persistent engine: blocks; 0 = enough to fill the device, but no more
+                             than the work items (block engine) or than start every history
+                             at once (lane engine) */
   int32_t plan;           /* plan id (pmc_load_plan; pmc_load_spots loads plan 0) */
   int32_t tally_mode;     /* persistent engine: PMC_TALLY_*; 0 = library's choice */
   uint64_t item_begin;    /* persistent engine: run only work items [item_begin, item_end) */
@@ -176,13 +178,31 @@ int pmc_load_phase(pmc_context *ctx, int32_t phase, const int16_t *hu, int32_t n
 int pmc_unload_phase(pmc_context *ctx, int32_t phase);
 
 /* Load (or replace) plan `plan` (0..1023): fields and spots with their phase
- * indices.  A context holds several plans; a request names the one it uses. */
+ * indices -- the plan of Appendix A (per spot: position, energy, weight)
+ * split into the sub-plans of Sec. 2.B (the breathing phase each spot is
+ * delivered in).  Histories of a request are split over its spots in
+ * proportion to their weights.  A context holds several plans; a request
+ * names the one it uses.  Validation as documented for pmc_spot and
+ * pmc_field; PMC_E_INVAL on the first bad spot or field. */
 int pmc_load_plan(pmc_context *ctx, int32_t plan, const pmc_field *fields, int32_t n_fields,
                   const pmc_spot *spots, int64_t n_spots);
 
-/* pmc_load_plan for plan 0. */
+/* pmc_load_plan for plan 0 (the calls named by the problem statement:
+ * pmc_load_phase, pmc_load_spots, pmc_dose). */
 int pmc_load_spots(pmc_context *ctx, const pmc_field *fields, int32_t n_fields,
                    const pmc_spot *spots, int64_t n_spots);
+
+/* The sub-plans of one delivery (Sec. 2.B: per breathing phase, the spots
+ * delivered in it and their weighting) loaded as plan `plan`: for every
+ * spot s (array order) and phase p (ascending) with mu[s * n_phases + p] >
+ * 0, spot s on phase phase_ids[p] with weight that MU -- a spot delivered
+ * over several phases becomes one spot per phase.  mu is one trial of
+ * pmc_delivery_simulate's mu_out (MU per spot and phase).  *n_subplan_spots
+ * (nullable) receives the spot count.  PMC_E_INVAL for negative or
+ * non-finite MU, bad phase ids, or no MU at all; then as pmc_load_plan. */
+int pmc_load_subplans(pmc_context *ctx, int32_t plan, const pmc_field *fields, int32_t n_fields,
+                      const pmc_spot *spots, int64_t n_spots, const double *mu, int32_t n_phases,
+                      const int32_t *phase_ids, int64_t *n_subplan_spots);
 
 /* Forget a plan and free the device data prepared for it. */
 int pmc_unload_plan(pmc_context *ctx, int32_t plan);
@@ -219,13 +239,15 @@ typedef struct {
 
 /* Launch shape the library uses for req: the request's own values where
  * set, else the defaults.
- *  - tally_mode: PMC_TALLY_CORE for the FP32 persistent engine when its work
- *    items of `chunk` histories average at least 1024 (one per lane of a
- *    block), the request has at least 1024 histories per compute unit and
- *    the LDS holds at least 4096 core entries; else PMC_TALLY_LANE.
+ *  - tally_mode: PMC_TALLY_CORE for the FP32 persistent engine when work
+ *    items of `chunk` (default 8192) histories, a spot's partial last item
+ *    counted with its full ones, average at least 1024 histories (one per
+ *    lane of a block) and the LDS holds at least 4096 core entries; else
+ *    PMC_TALLY_LANE.
  *  - block_size: 1024 for the FP32 persistent engine (PMC_TALLY_CORE takes
  *    only 1024), 256 for FP64 and for the plain engine.
- *  - chunk: PMC_TALLY_CORE 8192; PMC_TALLY_LANE the largest of 256, 128, 64
+ *  - chunk: PMC_TALLY_CORE 8192, halved down to 1024 while the request has
+ *    fewer histories than that per compute unit; PMC_TALLY_LANE the largest of 256, 128, 64
  *    for which the request still has about four work items per resident wave
  *    (16 waves per compute unit).
  *  - refill_min: 64.
@@ -235,11 +257,15 @@ int pmc_launch_shape(pmc_context *ctx, const pmc_request *req, pmc_shape *out);
 
 /* ---- dose ------------------------------------------------------------------ */
 
-/* Simulate req->n_histories histories over the spots of the listed phases
- * and return, for each listed phase i, the dose grid dose_out[i] (Gy per
- * history, nx*ny*nz doubles; NULL entries skipped), optionally the raw
- * tally tally_out[i] (int64, 2^-32 MeV) and the density grid density_out[i]
- * (g/cm^3), and the energy balance.  Blocks until done. */
+/* The Monte Carlo dose of Sec. 2.C: simulate req->n_histories histories
+ * (class II condensed-history transport) over the spots of the listed
+ * phases -- the N_g per-phase runs of a field, here in one call -- and
+ * return, for each listed phase i, the dose on its CT grid dose_out[i] (Gy
+ * per history, nx*ny*nz doubles; NULL entries skipped; dose = deposited
+ * energy / (density x voxel volume), as Eq. (4) relates them), optionally
+ * the raw tally tally_out[i] (int64, 2^-32 MeV) and the density grid
+ * density_out[i] (g/cm^3, the engine's HU conversion), and the energy
+ * balance.  Blocks until done. */
 int pmc_dose(pmc_context *ctx, const pmc_request *req, double *const *dose_out,
              int64_t *const *tally_out, double *const *density_out, pmc_balance *balance_out);
 

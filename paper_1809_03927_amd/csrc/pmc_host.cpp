@@ -1354,6 +1354,35 @@ int pmc_load_spots(pmc_context *ctx, const pmc_field *fields, int32_t n_fields,
   return pmc_load_plan(ctx, 0, fields, n_fields, spots, n_spots);
 }
 
+int pmc_load_subplans(pmc_context *ctx, int32_t plan, const pmc_field *fields, int32_t n_fields,
+                      const pmc_spot *spots, int64_t n_spots, const double *mu, int32_t n_phases,
+                      const int32_t *phase_ids, int64_t *n_subplan_spots) {
+  if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
+  ctx->err.clear();
+  if (!spots || !mu || !phase_ids || n_spots < 1 || n_phases < 1 || n_phases > PMC_MAX_PHASES)
+    return fail(ctx, PMC_E_INVAL, "need spots, MU and 1..%d phase ids", PMC_MAX_PHASES);
+  for (int32_t p = 0; p < n_phases; ++p)
+    if (phase_ids[p] < 0 || phase_ids[p] > kMaxPhaseId)
+      return fail(ctx, PMC_E_INVAL, "phase id %d outside 0..%d", phase_ids[p], kMaxPhaseId);
+  std::vector<pmc_spot> out;
+  for (int64_t s = 0; s < n_spots; ++s)
+    for (int32_t p = 0; p < n_phases; ++p) {
+      const double m = mu[s * n_phases + p];
+      if (!(std::isfinite(m) && m >= 0.0))
+        return fail(ctx, PMC_E_INVAL, "MU of spot %lld in phase %d must be finite and >= 0", (long long)s, p);
+      if (m > 0.0) {
+        pmc_spot sp = spots[s];
+        sp.phase = phase_ids[p];
+        sp.weight = m;
+        out.push_back(sp);
+      }
+    }
+  if (out.empty()) return fail(ctx, PMC_E_INVAL, "no MU delivered: the sub-plans are empty");
+  const int rc = pmc_load_plan(ctx, plan, fields, n_fields, out.data(), (int64_t)out.size());
+  if (rc == PMC_OK && n_subplan_spots) *n_subplan_spots = (int64_t)out.size();
+  return rc;
+}
+
 int pmc_unload_plan(pmc_context *ctx, int32_t plan) {
   if (!ctx) return fail(nullptr, PMC_E_INVAL, "context is NULL");
   ctx->err.clear();

@@ -2,9 +2,10 @@
 
 1. Beam-delivery simulation of every trial at once (Sec. 2.B,
    pmc_delivery_simulate): the MU of every spot per breathing phase.
-2. Per trial, the sub-plans as one plan: every (spot, phase) that received
-   MU becomes a spot of that phase weighted by that MU (Sec. 2.B: the
-   weighting between phases comes from the delivery, Eq. (2) adds no other).
+2. Per trial, the sub-plans as one plan (pmc_load_subplans): every (spot,
+   phase) that received MU becomes a spot of that phase weighted by that MU
+   (Sec. 2.B: the weighting between phases comes from the delivery, Eq. (2)
+   adds no other).
 3. The Monte Carlo dose of all phases in one batched persistent launch
    (Sec. 2.C, pmc_dose_device): histories split over the sub-plan spots in
    proportion to MU.
@@ -13,7 +14,11 @@
 
 The trials are the delivery-uncertainty study of Sec. 2.B (start phase,
 breathing period, synchrotron parameters drawn per trial).  PyTorch owns the
-device buffers and the stream; every step runs in libpmc.
+device buffers and the stream; every step runs in libpmc.  Trials are
+pipelined: the host loads trial i+1's sub-plans and prepares its work items
+while the device still runs trial i (everything is enqueued on one stream,
+so trial i's accumulation has read the tallies before trial i+1 clears
+them); the host waits only at the end.
 """
 from __future__ import annotations
 
@@ -23,17 +28,6 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import pmc
-
-
-def sub_plan(spots: np.ndarray, mu: np.ndarray, phase_ids: Sequence[int]) -> np.ndarray:
-    """One trial's delivery as plan spots: for every plan spot (plan order)
-    and breathing phase (ascending) with MU > 0, that spot on phase
-    phase_ids[p] with weight = the MU delivered there."""
-    s_idx, p_idx = np.nonzero(mu > 0.0)
-    out = spots[s_idx].copy()
-    out["phase"] = np.asarray(phase_ids, dtype=np.int32)[p_idx]
-    out["weight"] = mu[s_idx, p_idx]
-    return out
 
 
 class FourD:
@@ -68,39 +62,49 @@ class FourD:
     def run(self, delivery, n_histories: int, request_id: int = 0, keep: bool = True) -> dict:
         """All trials of `delivery`; returns the accumulated doses (host, Gy
         per history of each trial's run) if keep, the report mask, the
-        delivery result and wall times per component (s)."""
+        delivery result, the wall time of the delivery call and of the whole
+        loop, and per trial the host time to load and enqueue it and the
+        device times of its Monte Carlo and accumulation (events)."""
         torch = self.torch
         st = self.stream
         t0 = time.perf_counter()
         dl = pmc.pmc_delivery_simulate(self.ctx, delivery, self.spots, len(self.fields))
         t_delivery = time.perf_counter() - t0
-        doses, t_mc, t_acc = [], [], []
+        kept, t_host, events = [], [], []
         tptr = [t.data_ptr() for t in self.tallies]
         acc = pmc.pmc_accumulate_device if self.method == "emtm" else pmc.pmc_accumulate_dim_device
+        t_loop = time.perf_counter()
         for trial in range(delivery.n_trials):
             t1 = time.perf_counter()
-            sp = sub_plan(self.spots, dl["mu"][trial], self.phase_ids)
-            pmc.pmc_load_plan(self.ctx, self.plan_id, self.fields, sp)
+            pmc.pmc_load_subplans(self.ctx, self.plan_id, self.fields, self.spots, dl["mu"][trial],
+                                  self.phase_ids)
             req = pmc.Request(n_histories, self.phase_ids, request_id=request_id + trial,
                               engine=pmc.PMC_ENGINE_PERSISTENT, plan=self.plan_id, tally_mode=self.tally_mode)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
             with torch.cuda.stream(st):
                 for t in self.tallies:
                     t.zero_()
                 self.counters.zero_()
+                ev[0].record(st)
             pmc.pmc_dose_device(self.ctx, req, st.cuda_stream, tptr, self.counters.data_ptr())
-            st.synchronize()
-            t2 = time.perf_counter()
+            ev[1].record(st)
             acc(self.ctx, self.phase_ids[self.ref], tptr[self.ref], [self.phase_ids[p] for p in self.src],
                 self.dvf_ids, [tptr[p] for p in self.src], self.n_sub, n_histories, st.cuda_stream,
                 self.dose.data_ptr(), self.mask.data_ptr())
-            st.synchronize()
-            t3 = time.perf_counter()
+            ev[2].record(st)
             if keep:
-                doses.append(self.dose.cpu().numpy())
-            t_mc.append(t2 - t1)
-            t_acc.append(t3 - t2)
-        return {"doses": doses, "mask": self.mask.cpu().numpy().astype(bool), "delivery": dl,
-                "time_delivery_s": t_delivery, "time_mc_s": t_mc, "time_accumulation_s": t_acc}
+                with torch.cuda.stream(st):
+                    host = torch.empty(self.nvox, dtype=torch.float64, pin_memory=True)
+                    host.copy_(self.dose, non_blocking=True)
+                kept.append(host)
+            events.append(ev)
+            t_host.append(time.perf_counter() - t1)
+        st.synchronize()
+        total = time.perf_counter() - t_loop
+        return {"doses": [h.numpy() for h in kept], "mask": self.mask.cpu().numpy().astype(bool), "delivery": dl,
+                "time_delivery_s": t_delivery, "time_loop_s": total, "time_host_s": t_host,
+                "time_mc_s": [e[0].elapsed_time(e[1]) * 1e-3 for e in events],
+                "time_accumulation_s": [e[1].elapsed_time(e[2]) * 1e-3 for e in events]}
 
     def close(self):
         try:

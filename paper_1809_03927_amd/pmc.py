@@ -32,7 +32,7 @@ ERROR_NAMES = {0: "PMC_OK", -1: "PMC_E_INVAL", -2: "PMC_E_NOPHASE", -3: "PMC_E_B
 
 # every symbol declared in include/pmc.h
 EXPORTS = ["pmc_create", "pmc_destroy", "pmc_last_error", "pmc_load_phase", "pmc_unload_phase",
-           "pmc_load_spots", "pmc_load_plan", "pmc_unload_plan", "pmc_request_items", "pmc_request_item_histories", "pmc_launch_shape", "pmc_dose",
+           "pmc_load_spots", "pmc_load_plan", "pmc_load_subplans", "pmc_unload_plan", "pmc_request_items", "pmc_request_item_histories", "pmc_launch_shape", "pmc_dose",
            "pmc_dose_device", "pmc_dose_device_notify", "pmc_dose_device_noalloc", "pmc_atomic_log", "pmc_atomic_replay",
            "pmc_balance_from_counters",
            "pmc_convert_device", "pmc_trace", "pmc_split_histories", "pmc_bytes_in_use",
@@ -143,6 +143,7 @@ def lib():
         L.pmc_unload_phase.argtypes = [vp, i32]
         L.pmc_load_spots.argtypes = [vp, vp, i32, vp, i64]
         L.pmc_load_plan.argtypes = [vp, i32, vp, i32, vp, i64]
+        L.pmc_load_subplans.argtypes = [vp, i32, vp, i32, vp, i64, vp, i32, vp, vp]
         L.pmc_unload_plan.argtypes = [vp, i32]
         L.pmc_request_items.argtypes = [vp, C.POINTER(pmc_request), C.POINTER(u64)]
         L.pmc_request_item_histories.argtypes = [vp, C.POINTER(pmc_request), vp, u64, C.POINTER(u64)]
@@ -240,6 +241,22 @@ def pmc_load_plan(ctx, plan_id: int, fields: np.ndarray, spots: np.ndarray) -> N
     f = np.ascontiguousarray(fields, dtype=FIELD_DTYPE)
     s = np.ascontiguousarray(spots, dtype=SPOT_DTYPE)
     _check(lib().pmc_load_plan(ctx, plan_id, _ptr(f), len(f), _ptr(s), len(s)), ctx)
+
+
+def pmc_load_subplans(ctx, plan_id: int, fields: np.ndarray, spots: np.ndarray, mu: np.ndarray,
+                      phase_ids: Sequence[int]) -> int:
+    """mu: (n_spots, n_phases) MU of one delivery trial; returns the number
+    of sub-plan spots loaded as plan plan_id."""
+    f = np.ascontiguousarray(fields, dtype=FIELD_DTYPE)
+    s = np.ascontiguousarray(spots, dtype=SPOT_DTYPE)
+    m = np.ascontiguousarray(mu, dtype=np.float64)
+    ids = np.ascontiguousarray(phase_ids, dtype=np.int32)
+    if m.shape != (len(s), len(ids)):
+        raise ValueError("mu must be (n_spots, n_phases)")
+    n = C.c_int64(0)
+    _check(lib().pmc_load_subplans(ctx, plan_id, _ptr(f), len(f), _ptr(s), len(s), _ptr(m), len(ids),
+                                   _ptr(ids), C.byref(n)), ctx)
+    return int(n.value)
 
 
 def pmc_unload_plan(ctx, plan_id: int) -> None:

@@ -135,3 +135,84 @@ def test_gated_breathing_run(P, F):
         fd.close()
     finally:
         e.close()
+
+
+# ----------------------------------------------------------------------------
+# the whole pipeline against the oracle's composition (oracle.fourd)
+# ----------------------------------------------------------------------------
+
+def small_4d(shape=(64, 64, 40)):
+    phases = [W.make_thorax(shape, p, 10) for p in range(10)]
+    ref = 5
+    dvfs = [None if p == ref else W.thorax_dvf(p, ref, n_phases=10) for p in range(10)]
+    plan = W.plan_thorax(3, n_layers=3, grid=(4, 3), n_phases=10)
+    sp = plan.spots.copy()
+    sp["weight"] = sp["weight"] / sp["weight"].sum() * 20.0
+    return phases, ref, dvfs, plan.fields, sp
+
+
+def run_fourd(P, F, precision, phases, ref, dvfs, fields, sp, d, n_sub, n_hist, seed, tally_mode):
+    e = P.Engine(device=0, precision=precision, seed=seed)
+    try:
+        for p, ph in enumerate(phases):
+            e.load_phase(p, ph)
+        ids = []
+        for p, dv in enumerate(dvfs):
+            if dv is not None:
+                P.pmc_load_dvf(e.ctx, 100 + p, dv)
+            ids.append(None if dv is None else 100 + p)
+        fd = F.FourD(e.ctx, fields, sp, list(range(len(phases))), ref, ids, phases[0].nvox, n_sub=n_sub,
+                     tally_mode=tally_mode)
+        out = fd.run(d, n_hist, request_id=0)
+        fd.close()
+        return out
+    finally:
+        e.close()
+
+
+def test_fourd_fp64_equals_the_oracle_composition(P, F):
+    """FP64 engine: delivery, sub-plans, transport of all ten phases and
+    EMTM (n = 2) against the oracle's composition of the same steps, two
+    trials: the MU per spot and phase identical (no near-tie decision in
+    these timelines), and the accumulated dose equal to rounding in every
+    voxel (the transports agree to the last units of the fixed-point tally
+    per step; no history of these runs meets a near-tie decision)."""
+    from delivery_check import compare
+    from oracle import fourd as OF
+    phases, ref, dvfs, fields, sp = small_4d()
+    d = W.Delivery(n_trials=2, period_sd_s=0.3, seed=8)
+    say("4D FP64 vs oracle composition")
+    out = run_fourd(P, F, P.PMC_FP64, phases, ref, dvfs, fields, sp, d, 2, 20_000, 7, P.PMC_TALLY_LANE)
+    dl, doses, _ = OF.fourd(phases, fields, sp, d, ref, dvfs, 2, 20_000, 7)
+    assert compare(out["delivery"], dl, sp, len(fields), max_flips=0) == 0
+    for t in range(d.n_trials):
+        g, o = out["doses"][t], doses[t]
+        assert np.array_equal(g > 0, o > 0)
+        mx = o.max()
+        sel = o > 0.1 * mx
+        dmax = float(np.max(np.abs(g - o))) / mx
+        say(f"trial {t}: {int(sel.sum())} voxels above 10 %, max |dD|/Dmax {dmax:.2e}, "
+            f"total {abs(g.sum() / o.sum() - 1):.2e}")
+        assert sel.sum() > 200 and dmax <= 1e-6
+        assert abs(g.sum() / o.sum() - 1.0) <= 1e-9
+
+
+def test_fourd_fp32_matches_the_oracle_composition(P, F):
+    """FP32 engine (the library's launch shape), one trial, EMTM n = 1,
+    against the oracle's composition with the same keys: the voxel
+    criterion on the accumulated dose (above 10 % of its maximum, within
+    1 % of it or 3 sigma_diff, sigma from 10 history batches of the
+    composition) in at least the same-seed fraction, no bias."""
+    from delivery_check import compare
+    from oracle import fourd as OF
+    from parity import SAME_SEED_MIN_PASS, dose_parity
+    phases, ref, dvfs, fields, sp = small_4d()
+    d = W.Delivery(n_trials=1, period_sd_s=0.3, seed=8)
+    say("4D FP32 vs oracle composition")
+    out = run_fourd(P, F, P.PMC_FP32, phases, ref, dvfs, fields, sp, d, 1, 40_000, 7, P.PMC_TALLY_AUTO)
+    dl, doses, batches = OF.fourd(phases, fields, sp, d, ref, dvfs, 1, 40_000, 7, n_batches=10)
+    assert compare(out["delivery"], dl, sp, len(fields), max_flips=0) == 0
+    b = np.array(batches[0])
+    sigma = np.sqrt(10.0 * b.var(axis=0, ddof=1))
+    frac, e_rel, zmean, zrms, nv = dose_parity(out["doses"][0], doses[0], sigma, "4D FP32 vs oracle")
+    assert nv > 200 and frac >= SAME_SEED_MIN_PASS and e_rel <= 1e-3 and abs(zmean) < 0.2, (frac, e_rel, zmean)
