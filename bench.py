@@ -65,8 +65,11 @@ METHOD_VALU_PER_STEP = 250
 # Valid only for the sources they were measured on (hash below) and that
 # launch shape; otherwise null.
 PROFILED_TRAFFIC_BYTES = 172.2e9
-PROFILED_MEMSIDE_ATOMICS = 4.098e9
-PROFILED_KERNEL_HASH = "698bebd8d8e87ae1"
+PROFILED_MEMSIDE_ATOMICS = 4.0978e9
+# memory-side atomic requests of the replay probe per atomic it issues
+# (TCC_EA0_ATOMIC_sum 2.1434e9 for 2.147e9 replayed, same profile)
+PROFILED_REPLAY_MEMSIDE_PER_ISSUED = 2.1434e9 / 2.147e9
+PROFILED_KERNEL_HASH = "3c34a41722a9ffaa"
 
 # Deformable accumulation (energy/mass transfer, Sec. 2.D.2): the per-phase
 # tallies of the 4D run accumulated onto one reference phase with n^3
@@ -480,36 +483,49 @@ def atomic_probe(eng, pmc, wl, phases, tuned, tallies, counters, stream, torch):
 def roofline_fields(bal, kern_ms, probe, kernel_name, shape_b, wl, grid, pmc):
     """The dominant kernel's roofline: device-wide int64 atomics per second
     against the replay of its own address pattern (the binding roof of the
-    block engine), with the VALU view beside it."""
+    block engine), with the VALU view beside it.  Rates are memory-side
+    requests (TCC_EA0_ATOMIC_sum of the profile of these sources, over the
+    live-timed durations) when the profile matches the sources and launch;
+    else the atomics each kernel issues (exact counts, live)."""
     kern_s = kern_ms * 1e-3
     issued = bal["atomics"] / kern_s
     lane_steps_s = bal["steps"] / kern_s
     default_cfg = wl.n_histories == 50_000_000 and grid == (256, 256, 160)
     profiled = (default_cfg and kernel_hash() == PROFILED_KERNEL_HASH
                 and shape_b["tally_mode"] == pmc.PMC_TALLY_CORE and shape_b["chunk"] == 8192)
-    out = {
-        "bound": "atomic" if probe else "alu",
-        "achieved": issued / 1e9 if probe else lane_steps_s * VALU_PER_STEP / 1e12,
-        "peak": probe["per_s"] / 1e9 if probe else PEAK_LANE_OPS / 1e12,
-        "unit": "G device-wide int64 atomics/s" if probe else "T lane-VALU-instr/s",
-        "frac": issued / probe["per_s"] if probe else lane_steps_s * VALU_PER_STEP / PEAK_LANE_OPS,
-        "traffic": PROFILED_TRAFFIC_BYTES if profiled else None,
-        "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, rocprofv3, copy-calibrated)",
-        "kernel": kernel_name, "kernel_ms": kern_ms,
-        "atomics_per_launch": int(bal["atomics"]),
-        "memory_side_atomics_per_launch": PROFILED_MEMSIDE_ATOMICS if profiled else None,
-        "peak_source": None if not probe else (
-            f"pmc_atomic_replay of the kernel's logged deposit addresses: the first {probe['per_lane_cap']} "
-            f"device-wide atomics of each of its {probe['lanes']} lanes ({probe['replayed']:.4g} of "
-            f"{probe['logged_total']:.4g}), in logged order, back to back"),
-        "valu": {
-            "peak_T_lane_instr_per_s": PEAK_LANE_OPS / 1e12,
-            "lane_steps_per_s": lane_steps_s,
-            "executed_per_step": VALU_PER_STEP,
-            "frac_executed": lane_steps_s * VALU_PER_STEP / PEAK_LANE_OPS,
-            "method_per_step": METHOD_VALU_PER_STEP,
-            "frac_method": lane_steps_s * METHOD_VALU_PER_STEP / PEAK_LANE_OPS,
-        },
+    out = {"kernel": kernel_name, "kernel_ms": kern_ms, "atomics_per_launch": int(bal["atomics"]),
+           "traffic": PROFILED_TRAFFIC_BYTES if profiled else None,
+           "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, rocprofv3, copy-calibrated)"}
+    if probe:
+        replay_s = probe["ms"] * 1e-3
+        issued_peak = probe["per_s"]
+        if profiled:
+            achieved = PROFILED_MEMSIDE_ATOMICS / kern_s
+            peak = probe["replayed"] * PROFILED_REPLAY_MEMSIDE_PER_ISSUED / replay_s
+            unit = "G memory-side int64 atomics/s"
+        else:
+            achieved, peak, unit = issued, issued_peak, "G device-wide int64 atomics/s (issued)"
+        out.update({
+            "bound": "atomic", "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": unit,
+            "frac": achieved / peak,
+            "memory_side_atomics_per_launch": PROFILED_MEMSIDE_ATOMICS if profiled else None,
+            "issued": {"achieved": issued / 1e9, "peak": issued_peak / 1e9, "frac": issued / issued_peak},
+            "peak_source": (f"pmc_atomic_replay of the kernel's logged deposit addresses: the first "
+                            f"{probe['per_lane_cap']} device-wide atomics of each of its {probe['lanes']} lanes "
+                            f"({probe['replayed']:.4g} of {probe['logged_total']:.4g}), in logged order, back "
+                            f"to back, {probe['ms']:.1f} ms"),
+        })
+    else:
+        out.update({"bound": "alu", "achieved": lane_steps_s * VALU_PER_STEP / 1e12,
+                    "peak": PEAK_LANE_OPS / 1e12, "unit": "T lane-VALU-instr/s",
+                    "frac": lane_steps_s * VALU_PER_STEP / PEAK_LANE_OPS})
+    out["valu"] = {
+        "peak_T_lane_instr_per_s": PEAK_LANE_OPS / 1e12,
+        "lane_steps_per_s": lane_steps_s,
+        "executed_per_step": VALU_PER_STEP,
+        "frac_executed": lane_steps_s * VALU_PER_STEP / PEAK_LANE_OPS,
+        "method_per_step": METHOD_VALU_PER_STEP,
+        "frac_method": lane_steps_s * METHOD_VALU_PER_STEP / PEAK_LANE_OPS,
     }
     return out
 
