@@ -177,15 +177,25 @@ template <typename R> struct Geo {
 //   kTallyGrid  the phase tally (one global atomic per voxel visit)
 //   kTallyBox   the spot's box tally (influence calculations); deposits
 //               outside the box are only counted
-//   kTallyCore  inside the spot's core box: the block's LDS copy of the core
+//   kTallyCore  inside the spot's core: the block's LDS copy of the core
 //               (flushed into the phase tally when the block is done with the
-//               spot); outside it: the phase tally
+//               spot); outside it: the phase tally.  The core is a box of
+//               the grid (a slice core of a beam along a grid axis)
+//   kTallySlice kTallyCore with a slice core whose windows follow an
+//               oblique beam (SliceCore)
 //   kTallyBoxCore  kTallyBox whose core window (inside the box) adds into
 //               the block's LDS copy (flushed into the box tally)
-//   kTallyCoreLog  kTallyCore that also writes the address of every global
-//               atomic into a per-lane log (measurement of the deposit
-//               address pattern; the tallies are the same)
-constexpr int kTallyGrid = 0, kTallyBox = 1, kTallyCore = 2, kTallyBoxCore = 3, kTallyCoreLog = 4;
+//   kTallyCoreLog, kTallySliceLog  kTallyCore, kTallySlice that also write
+//               the address of every global atomic into a per-lane log
+//               (measurement of the deposit address pattern; the tallies are
+//               the same)
+constexpr int kTallyGrid = 0, kTallyBox = 1, kTallyCore = 2, kTallyBoxCore = 3, kTallyCoreLog = 4,
+              kTallySlice = 5, kTallySliceLog = 6;
+
+template <int TM>
+constexpr bool kPhaseCore = TM == kTallyCore || TM == kTallyCoreLog || TM == kTallySlice || TM == kTallySliceLog;
+template <int TM>
+constexpr bool kLogged = TM == kTallyCoreLog || TM == kTallySliceLog;
 
 // the box a lane's spot tallies into (kTallyBox: global, kTallyCore: LDS);
 // kTallyBoxCore: the box (global) and its core window (LDS)
@@ -197,7 +207,16 @@ struct BoxLane {
   // kTallyCoreLog: entry n of this lane is log[n * log_stride + log_lane], n < log_cap
   unsigned long long *log;
   uint32_t log_cap, log_stride, log_lane;
+  // kTallySlice, kTallySliceLog: the spot's slice core (SliceCore; sn = 0: none)
+  int32_t sd, sa, se, sj0, sn, swa, swe, scells;
+  int32_t sA[2], sB[2], smax[2];
 };
+
+// corner of a slice-core window along one axis at slice j (SliceCore)
+__device__ __forceinline__ int32_t slice_corner(int32_t A, int32_t Bs, int32_t j, int32_t mx) {
+  const int32_t c = (A + Bs * j) >> 16;
+  return c < 0 ? 0 : (c > mx ? mx : c);
+}
 
 // physics tables per node i: (R, mu_delta, omega^2, dl2 / (R_{i+1} - R_i)),
 // linear in log2 E between nodes; the last entry is the inverse slope of R
@@ -448,13 +467,27 @@ __device__ __forceinline__ void start_history(Lane<R> &L, const SpotDev<R> &sp, 
 }
 
 // Tally key of a deposit.  kTallyGrid: the voxel index; kTallyBox: the
-// box-local entry, -2 outside the box; kTallyCore: -3 - (core-local entry)
-// inside the core, else the voxel index; kTallyBoxCore: -2 outside the box,
+// box-local entry, -2 outside the box; kTallyCore, kTallySlice: -3 - (core
+// entry) inside the core, else the voxel index; kTallyBoxCore: -2 outside the box,
 // -3 - (window-local entry) inside the window, else the box-local entry.  The
 // lane is still in the voxel of the step.
 template <typename R, int TM>
 __device__ __forceinline__ int32_t tally_key(const Lane<R> &L, const BoxLane &B, int32_t v) {
   if constexpr (TM == kTallyGrid) {
+    return v;
+  } else if constexpr (TM == kTallyCore || TM == kTallyCoreLog) {
+    const int32_t x = L.ix - B.lo[0], y = L.iy - B.lo[1], z = L.iz - B.lo[2];
+    const bool in = (uint32_t)x < (uint32_t)B.n[0] && (uint32_t)y < (uint32_t)B.n[1] &&
+                    (uint32_t)z < (uint32_t)B.n[2];
+    return in ? -3 - (x + B.n[0] * (y + B.n[1] * z)) : v;
+  } else if constexpr (TM == kTallySlice || TM == kTallySliceLog) {
+    const int32_t j = pick3(L.ix, L.iy, L.iz, B.sd) - B.sj0;
+    if ((uint32_t)j < (uint32_t)B.sn) {
+      const int32_t x = pick3(L.ix, L.iy, L.iz, B.sa) - slice_corner(B.sA[0], B.sB[0], j, B.smax[0]);
+      const int32_t y = pick3(L.ix, L.iy, L.iz, B.se) - slice_corner(B.sA[1], B.sB[1], j, B.smax[1]);
+      if ((uint32_t)x < (uint32_t)B.swa && (uint32_t)y < (uint32_t)B.swe)
+        return -3 - (j * B.scells + x + B.swa * y);
+    }
     return v;
   } else if constexpr (TM == kTallyBoxCore) {
     const int32_t x = L.ix - B.lo[0], y = L.iy - B.lo[1], z = L.iz - B.lo[2];
@@ -466,12 +499,11 @@ __device__ __forceinline__ int32_t tally_key(const Lane<R> &L, const BoxLane &B,
                          (uint32_t)cz < (uint32_t)B.cn[2];
     return in_core ? -3 - (cx + B.cn[0] * (cy + B.cn[1] * cz)) : x + B.n[0] * (y + B.n[1] * z);
   } else {
+    static_assert(TM == kTallyBox, "tally mode");
     const int32_t x = L.ix - B.lo[0], y = L.iy - B.lo[1], z = L.iz - B.lo[2];
     const bool in = (uint32_t)x < (uint32_t)B.n[0] && (uint32_t)y < (uint32_t)B.n[1] &&
                     (uint32_t)z < (uint32_t)B.n[2];
-    const int32_t e = x + B.n[0] * (y + B.n[1] * z);
-    if constexpr (TM == kTallyBox) return in ? e : -2;
-    else return in ? -3 - e : v;
+    return in ? x + B.n[0] * (y + B.n[1] * z) : -2;
   }
 }
 
@@ -485,14 +517,14 @@ __device__ __forceinline__ void commit_acc(const Lane<R> &L, const Geo<R> &G, co
       return;
     }
     atomic_add_u64(&B.base[L.acc_v], (unsigned long long)L.acc);
-  } else if constexpr (TM == kTallyCore || TM == kTallyCoreLog) {
+  } else if constexpr (kPhaseCore<TM>) {
     if (L.acc_v <= -3) {  // LDS: the block's copy of the core
       __hip_atomic_fetch_add(&B.base[-3 - L.acc_v], (unsigned long long)L.acc, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
       return;
     }
     atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
-    if constexpr (TM == kTallyCoreLog) log_atomic(B, C.atomics, &G.tally[L.acc_v]);
+    if constexpr (kLogged<TM>) log_atomic(B, C.atomics, &G.tally[L.acc_v]);
   } else if constexpr (TM == kTallyBoxCore) {
     if (L.acc_v <= -3) {  // LDS: the block's copy of the core window
       __hip_atomic_fetch_add(&B.core[-3 - L.acc_v], (unsigned long long)L.acc, __ATOMIC_RELAXED,

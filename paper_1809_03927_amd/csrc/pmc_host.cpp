@@ -102,6 +102,7 @@ struct Prepared {
   // device offsets into the request scratch buffer
   size_t off_spots = 0, off_items = 0, off_luts = 0, off_targets = 0, off_cores = 0;
   int32_t core_cap = 0;  // PMC_TALLY_CORE: LDS tally entries per block
+  bool slanted = false;  // PMC_TALLY_CORE: some slice core follows an oblique beam
   std::vector<size_t> off_ids, off_first;
   std::vector<unsigned char> staging;  // host image uploaded into the scratch
   std::vector<TargetDev> targets;      // last uploaded target table
@@ -599,6 +600,8 @@ LaunchShape launch_shape(const pmc_context *ctx, const pmc_request *req) {
 int default_chunk(const pmc_context *ctx, const pmc_request *req) { return launch_shape(ctx, req).chunk; }
 
 pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s);
+pmc::SliceCore slice_core(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s,
+                          int32_t cap);
 
 // Core box of a spot: its voxel box if that fits `cap` entries, else the box's
 // full extent along the beam's main axis and a window across it, centred in
@@ -783,33 +786,41 @@ int build_request(pmc_context *ctx, const pmc_request *req, Prepared &P) {
   off = align256(off + sizeof(SpotDev<R>) * (size_t)n_spots);
   P.off_items = off;
   off = align256(off + sizeof(WorkItem) * items.size());
-  // core boxes (block engine), by spot, inside the grid of the spot's phase
-  std::vector<pmc::CoreDev> cores;
+  // slice cores (block engine), by spot, inside the grid of the spot's phase
+  std::vector<pmc::SliceCore> cores;
   if (mode == PMC_TALLY_CORE) {
     P.core_cap = shape.core_cap;
-    cores.assign(n_spots, pmc::CoreDev{});
-    // the voxel boxes (a host march along every spot axis), on host threads
-    std::vector<pmc_box> sbox((size_t)n_spots, pmc_box{{0, 0, 0}, {0, 0, 0}});
+    cores.assign(n_spots, pmc::SliceCore{});
+    // a host march along every spot axis, on host threads
     parallel_for(n_spots, [&](int64_t s) {
       const pmc_spot &sp = plan.spots[s];
       if (P.per_spot[s] == 0 || slot_of.find(sp.phase) == slot_of.end()) return;
-      sbox[s] = spot_box(ctx, ctx->phases.at(sp.phase), plan.fields[sp.field], sp);
+      cores[s] = slice_core(ctx, ctx->phases.at(sp.phase), plan.fields[sp.field], sp, P.core_cap);
     });
     for (int64_t s = 0; s < n_spots; ++s) {
-      const pmc_spot &sp = plan.spots[s];
-      if (P.per_spot[s] == 0 || slot_of.find(sp.phase) == slot_of.end()) continue;
-      const PhaseRec &ph = ctx->phases.at(sp.phase);
-      const pmc_field &f = plan.fields[sp.field];
+      const pmc::SliceCore &c = cores[s];
+      if (c.n_sl == 0) continue;
+      if (c.B[0] != 0 || c.B[1] != 0) P.slanted = true;
+      const PhaseRec &ph = ctx->phases.at(plan.spots[s].phase);
       const int n[3] = {ph.nx, ph.ny, ph.nz};
-      pmc::CoreDev c = core_of(to_entry_face(sbox[s], f, n), f, P.core_cap);
-      bool ok = (long long)c.n[0] * c.n[1] * c.n[2] <= (long long)P.core_cap;
-      for (int k = 0; k < 3; ++k) ok = ok && c.lo[k] >= 0 && c.n[k] >= 0 && c.lo[k] + c.n[k] <= n[k];
-      if (!ok) return fail(ctx, PMC_E_STATE, "internal: core box of spot %lld out of range", (long long)s);
-      cores[s] = c;
+      bool ok = c.d >= 0 && c.d < 3 && c.n_sl > 0 && c.wa > 0 && c.we > 0 &&
+                (long long)c.n_sl * c.wa * c.we <= (long long)P.core_cap;
+      if (ok) {
+        const int a = (c.d + 1) % 3, e = (c.d + 2) % 3;
+        ok = c.j0 >= 0 && (long long)c.j0 + c.n_sl <= n[c.d] && c.wa <= n[a] && c.we <= n[e] &&
+             c.amax[0] == n[a] - c.wa && c.amax[1] == n[e] - c.we;
+        // the corners A + B j in int32 for every slice
+        for (int i = 0; i < 2 && ok; ++i) {
+          const long long step = (long long)c.B[i] * (c.n_sl - 1);
+          ok = std::llabs((long long)c.A[i]) < 2147483647LL && std::llabs(step) < 2147483647LL &&
+               std::llabs((long long)c.A[i] + step) < 2147483647LL;
+        }
+      }
+      if (!ok) return fail(ctx, PMC_E_STATE, "internal: slice core of spot %lld out of range", (long long)s);
     }
   }
   P.off_cores = off;
-  off = align256(off + sizeof(pmc::CoreDev) * cores.size());
+  off = align256(off + sizeof(pmc::SliceCore) * cores.size());
   P.off_luts = off;
   off = align256(off + sizeof(R) * lut_elems * (size_t)n_luts);
   P.off_targets = off;
@@ -828,7 +839,7 @@ int build_request(pmc_context *ctx, const pmc_request *req, Prepared &P) {
   };
   put(P.off_spots, sd.data(), sizeof(SpotDev<R>) * sd.size());
   put(P.off_items, items.data(), sizeof(WorkItem) * items.size());
-  put(P.off_cores, cores.data(), sizeof(pmc::CoreDev) * cores.size());
+  put(P.off_cores, cores.data(), sizeof(pmc::SliceCore) * cores.size());
   for (int32_t l = 0; l < n_luts; ++l) {
     const PhaseRec &ph = ctx->phases[phases[l]];
     const void *src = sizeof(R) == 4 ? (const void *)ph.lut32.data() : (const void *)ph.lut64.data();
@@ -949,7 +960,8 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     a.refill_min = shape.refill;
     a.block = shape.block;
     if (P.mode == PMC_TALLY_CORE && !box) {
-      a.cores = reinterpret_cast<const pmc::CoreDev *>(scratch_at(P.off_cores));
+      a.slices = reinterpret_cast<const pmc::SliceCore *>(scratch_at(P.off_cores));
+      a.slanted = P.slanted;
       a.core_cap = P.core_cap;
       a.block = pmc::kCoreBlock;
     } else if (box && box->cores) {
@@ -967,13 +979,13 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
     }
     a.drained = drained;
     if (log) {
-      if (!a.cores || !a.lut_lds) return fail(ctx, PMC_E_INVAL, "the address log needs the block engine with one LUT");
+      if (!a.slices || !a.lut_lds) return fail(ctx, PMC_E_INVAL, "the address log needs the block engine with one LUT");
       a.log = log->log;
       a.log_cap = log->cap;
       a.log_count = log->count;
     }
     unsigned grid = (unsigned)req->grid_blocks;
-    if (grid == 0 && a.cores) {
+    if (grid == 0 && (a.cores || a.slices)) {
       // one block per CU (the core takes the LDS), but no more blocks than
       // work items: a block works on one item at a time
       grid = (unsigned)std::max(1, std::min(ctx->n_cu, a.n_items));
@@ -1923,10 +1935,25 @@ double rsp_at(const PhaseRec &ph, long long v) {
 // L the geometric length of that axis segment.
 constexpr double kBodyRsp = 0.1;
 
-pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s) {
-  pmc_box b = {{0, 0, 0}, {0, 0, 0}};
-  double w[3], u[3], v[3], c[3], d[3], ext[3];
-  const int n[3] = {ph.nx, ph.ny, ph.nz};
+// The central axis of a spot in grid coordinates (cm from the grid corner):
+// c + t w, BEV axes u and v, voxel size d; [t_in, t_out) inside the grid
+// box; t_body where it first meets matter, t_end at water-equivalent depth
+// R(E) + margin_cm (or the grid exit).  False if the axis misses the grid or
+// meets no matter.
+struct AxisRay {
+  double w[3], u[3], v[3], c[3], d[3];
+  int n[3];
+  double t_in, t_out, t_body, t_end;
+};
+
+bool axis_ray(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s,
+              double margin_cm, AxisRay &A) {
+  double *w = A.w, *u = A.u, *v = A.v, *c = A.c, *d = A.d;
+  double ext[3];
+  int *n = A.n;
+  n[0] = ph.nx;
+  n[1] = ph.ny;
+  n[2] = ph.nz;
   const double nw = norm3(f.direction), nu = norm3(f.bev_u);
   for (int k = 0; k < 3; ++k) {
     w[k] = f.direction[k] / nw;
@@ -1947,12 +1974,12 @@ pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f,
       t_in = std::max(t_in, std::min(t1, t2));
       t_out = std::min(t_out, std::max(t1, t2));
     } else if (c[k] < 0.0 || c[k] >= ext[k]) {
-      return b;
+      return false;
     }
   }
-  if (!(t_in < t_out)) return b;
+  if (!(t_in < t_out)) return false;
   // march the axis through the voxels, accumulating water-equivalent depth
-  const double target = table_range(ctx->tabs, s.energy_MeV) + 3.0;
+  const double target = table_range(ctx->tabs, s.energy_MeV) + margin_cm;
   int idx[3];
   double t_max[3], t_step[3];
   const double tm = 0.5 * (t_in + std::min(t_out, t_in + 1e-6));
@@ -1984,23 +2011,99 @@ pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f,
     if (idx[ax] < 0 || idx[ax] >= n[ax]) break;
     t_max[ax] += t_step[ax];
   }
-  if (t_body == -HUGE_VAL) return b;  // no matter on the axis
-  const double L = t_end - t_body;
+  if (t_body == -HUGE_VAL) return false;  // no matter on the axis
+  A.t_in = t_in;
+  A.t_out = t_out;
+  A.t_body = t_body;
+  A.t_end = t_end;
+  return true;
+}
+
+pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s) {
+  pmc_box b = {{0, 0, 0}, {0, 0, 0}};
+  AxisRay A;
+  if (!axis_ray(ctx, ph, f, s, 3.0, A)) return b;
+  const double L = A.t_end - A.t_body;
   const double sig = 0.1 * s.sigma_mm;
   const double r = 3.0 * std::sqrt(sig * sig + (0.035 * L) * (0.035 * L));
   for (int k = 0; k < 3; ++k) {
-    const double a = c[k] + t_body * w[k], e = c[k] + t_end * w[k];
-    const double half = r * (std::fabs(u[k]) + std::fabs(v[k]));
+    const double a = A.c[k] + A.t_body * A.w[k], e = A.c[k] + A.t_end * A.w[k];
+    const double half = r * (std::fabs(A.u[k]) + std::fabs(A.v[k]));
     const double lo = std::min(a, e) - half, hi = std::max(a, e) + half;
-    long long il = (long long)std::floor(lo / d[k]), ih = (long long)std::floor(hi / d[k]) + 1;
-    il = std::max(0LL, std::min((long long)n[k], il));
-    ih = std::max(0LL, std::min((long long)n[k], ih));
+    long long il = (long long)std::floor(lo / A.d[k]), ih = (long long)std::floor(hi / A.d[k]) + 1;
+    il = std::max(0LL, std::min((long long)A.n[k], il));
+    ih = std::max(0LL, std::min((long long)A.n[k], ih));
     b.lo[k] = (int32_t)il;
     b.hi[k] = (int32_t)ih;
   }
   for (int k = 0; k < 3; ++k)
     if (b.hi[k] <= b.lo[k]) return pmc_box{{0, 0, 0}, {0, 0, 0}};
   return b;
+}
+
+// Block-engine core of a spot for phase tallies (pmc::SliceCore).  The
+// slices are those of the grid axis d closest to the beam, from the face
+// where the axis enters the grid to the slice where it reaches
+// water-equivalent depth R(E) + 1 cm (beyond it the protons have stopped);
+// each holds a window of the same wa x we voxels across, centred on the
+// axis at the slice's middle plane and clamped into the grid, so that the
+// core follows an oblique beam.  The window's aspect ratio is that of the
+// beam's cross-section cut by a slice.  n_sl wa we <= cap; no core (n_sl =
+// 0) when the axis misses the grid, meets no matter, or the slices alone
+// exceed cap.
+pmc::SliceCore slice_core(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s,
+                          int32_t cap) {
+  pmc::SliceCore sc = {};
+  AxisRay A;
+  if (cap <= 0 || !axis_ray(ctx, ph, f, s, 1.0, A)) return sc;
+  int d = 0;
+  for (int k = 1; k < 3; ++k)
+    if (std::fabs(A.w[k]) > std::fabs(A.w[d])) d = k;
+  const int a = (d + 1) % 3, e = (d + 2) % 3;
+  auto slice_at = [&](double t) {
+    const long long j = (long long)std::floor((A.c[d] + t * A.w[d]) / A.d[d]);
+    return std::max(0LL, std::min((long long)A.n[d] - 1, j));
+  };
+  // the entry slice: just inside the grid (t_in is on its face)
+  const long long j_in = slice_at(A.t_in + 1e-9 * (A.t_out - A.t_in)), j_end = slice_at(A.t_end);
+  const long long j0 = std::min(j_in, j_end), n_sl = std::llabs(j_end - j_in) + 1;
+  if (n_sl > cap || n_sl > (1 << 15)) return sc;
+  const long long cells = cap / n_sl;
+  // cross-section of the beam in a slice: a lateral offset r (along u or v)
+  // moves the crossing point by r (u_k - u_d w_k / w_d) along axis k
+  auto foot = [&](int k) {
+    const double p = A.u[k] - A.u[d] * A.w[k] / A.w[d], q = A.v[k] - A.v[d] * A.w[k] / A.w[d];
+    return std::max(1e-3, std::sqrt(p * p + q * q)) / A.d[k];
+  };
+  long long wa = (long long)std::floor(std::sqrt((double)cells * foot(a) / foot(e)));
+  wa = std::max(1LL, std::min(wa, (long long)A.n[a]));
+  long long we = std::max(1LL, std::min(cells / wa, (long long)A.n[e]));
+  wa = std::max(1LL, std::min(cells / we, (long long)A.n[a]));
+  // window corner along k at slice j: the axis at the slice's middle plane
+  // minus half the width, in 16.16 fixed point, linear in j
+  const int ax[2] = {a, e};
+  const long long wid[2] = {wa, we};
+  for (int i = 0; i < 2; ++i) {
+    const int k = ax[i];
+    const double slope = A.w[k] * A.d[d] / (A.w[d] * A.d[k]);  // voxels along k per slice
+    const double t0 = ((double)j0 + 0.5) * A.d[d] - A.c[d];
+    const double first = (A.c[k] + t0 / A.w[d] * A.w[k]) / A.d[k] - 0.5 * (double)wid[i] + 0.5;
+    const double fa = std::floor(first * 65536.0), fb = std::floor(slope * 65536.0 + 0.5);
+    // every corner A + B j of the slices in int32
+    const double lim = 2147483647.0 - 65536.0;
+    if (!(std::fabs(fa) < lim && std::fabs(fb * (double)(n_sl - 1)) < lim &&
+          std::fabs(fa + fb * (double)(n_sl - 1)) < lim))
+      return pmc::SliceCore{};
+    sc.A[i] = (int32_t)fa;
+    sc.B[i] = (int32_t)fb;
+    sc.amax[i] = (int32_t)(A.n[k] - wid[i]);
+  }
+  sc.d = d;
+  sc.j0 = (int32_t)j0;
+  sc.n_sl = (int32_t)n_sl;
+  sc.wa = (int32_t)wa;
+  sc.we = (int32_t)we;
+  return sc;
 }
 
 long long box_entries(const pmc_box &b) {

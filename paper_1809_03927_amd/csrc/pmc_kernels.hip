@@ -262,7 +262,7 @@ size_t core_fixed_lds(bool lut_lds) {
          sizeof(unsigned long long) * kNc * (kCoreBlock / 64 + 1) + 16;
 }
 
-template <typename R, bool LUT_LDS, bool BOX, bool LOG = false>
+template <typename R, bool LUT_LDS, bool BOX, bool LOG = false, bool SLICE = false>
 __global__ void __launch_bounds__(kCoreBlock)
 transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict__ items,
                int32_t n_items, const TargetDev *__restrict__ targets,
@@ -270,11 +270,13 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
                const typename M<R>::R4 *__restrict__ tab_g, R l2e0, R inv_dl2, R dl2,
                uint32_t k0, uint32_t k1, uint32_t flags, int32_t refill_min,
                unsigned long long *cursor, unsigned long long *counters,
-               const CoreDev *__restrict__ cores, int32_t core_cap, const BoxDev *__restrict__ boxes,
+               const SliceCore *__restrict__ slices, const CoreDev *__restrict__ cores, int32_t core_cap,
+               const BoxDev *__restrict__ boxes,
                unsigned long long *box_tally, long long box_bias, unsigned int *drained_flag,
                unsigned long long *log, uint32_t log_cap, uint32_t *log_count) {
-  static_assert(!(LOG && BOX), "the address log covers the phase tallies");
-  constexpr int TM = BOX ? kTallyBoxCore : (LOG ? kTallyCoreLog : kTallyCore);
+  static_assert(!(LOG && BOX) && !(SLICE && BOX), "the address log and slice cores cover the phase tallies");
+  constexpr int TM = BOX ? kTallyBoxCore
+                         : (SLICE ? (LOG ? kTallySliceLog : kTallySlice) : (LOG ? kTallyCoreLog : kTallyCore));
   extern __shared__ __align__(16) unsigned char smem[];
   using R2 = typename M<R>::R2;
   using R4 = typename M<R>::R4;
@@ -317,15 +319,40 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
     const int32_t tgt = __builtin_amdgcn_readfirstlane(sp.target);
     const Geo<R> G = geo_of<R>(targets[tgt]);
     const R2 *lut = LUT_LDS ? lut_s : luts_g + (size_t)G.lut * kLutSize;
-    int32_t cn[3], clo[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      clo[a] = __builtin_amdgcn_readfirstlane(cores[spot].lo[a]);
-      cn[a] = __builtin_amdgcn_readfirstlane(cores[spot].n[a]);
-    }
-    const long long n_core = (long long)cn[0] * cn[1] * cn[2];
-    const bool use_core = n_core > 0 && n_core <= (long long)core_cap;
+    int32_t cn[3] = {0, 0, 0}, clo[3] = {0, 0, 0};
+    long long n_core;
     BoxLane B;
+    if constexpr (BOX) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        clo[a] = __builtin_amdgcn_readfirstlane(cores[spot].lo[a]);
+        cn[a] = __builtin_amdgcn_readfirstlane(cores[spot].n[a]);
+      }
+      n_core = (long long)cn[0] * cn[1] * cn[2];
+    } else {
+      const SliceCore &sc = slices[spot];
+      B.sd = __builtin_amdgcn_readfirstlane(sc.d);
+      B.sa = B.sd == 2 ? 0 : B.sd + 1;
+      B.se = B.sd == 0 ? 2 : B.sd - 1;
+      B.sj0 = __builtin_amdgcn_readfirstlane(sc.j0);
+      B.sn = __builtin_amdgcn_readfirstlane(sc.n_sl);
+      B.swa = __builtin_amdgcn_readfirstlane(sc.wa);
+      B.swe = __builtin_amdgcn_readfirstlane(sc.we);
+      B.scells = B.swa * B.swe;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        B.sA[i] = __builtin_amdgcn_readfirstlane(sc.A[i]);
+        B.sB[i] = __builtin_amdgcn_readfirstlane(sc.B[i]);
+        B.smax[i] = __builtin_amdgcn_readfirstlane(sc.amax[i]);
+      }
+      n_core = (long long)B.sn * B.scells;
+      // without SLICE every core of the launch is straight (a beam along a
+      // grid axis: constant corners), a box of the grid; one that is not is
+      // left without a core
+      if constexpr (!SLICE)
+        if (B.sB[0] != 0 || B.sB[1] != 0) n_core = 0;
+    }
+    const bool use_core = n_core > 0 && n_core <= (long long)core_cap;
     if constexpr (BOX) {
       // the box's first entry relative to this batch's scratch (64-bit)
       const unsigned long long rel = (unsigned long long)(boxes[spot].offset - box_bias);
@@ -342,10 +369,17 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
       B.core = core;
     } else {
       B.base = core;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        B.lo[a] = clo[a];
-        B.n[a] = use_core ? cn[a] : 0;  // no core: every deposit goes to the tally
+      if (!use_core) B.sn = 0;  // no core: every deposit goes to the tally
+      if constexpr (!SLICE) {
+        // the straight core as a box of the grid, entries x fastest
+        const int32_t c0 = slice_corner(B.sA[0], 0, 0, B.smax[0]), c1 = slice_corner(B.sA[1], 0, 0, B.smax[1]);
+        const int32_t sn = B.sn;
+        B.lo[0] = B.sd == 0 ? B.sj0 : (B.sa == 0 ? c0 : c1);
+        B.lo[1] = B.sd == 1 ? B.sj0 : (B.sa == 1 ? c0 : c1);
+        B.lo[2] = B.sd == 2 ? B.sj0 : (B.sa == 2 ? c0 : c1);
+        B.n[0] = B.sd == 0 ? sn : (B.sa == 0 ? B.swa : B.swe);
+        B.n[1] = B.sd == 1 ? sn : (B.sa == 1 ? B.swa : B.swe);
+        B.n[2] = B.sd == 2 ? sn : (B.sa == 2 ? B.swa : B.swe);
       }
       if constexpr (LOG) {
         B.log = log;
@@ -384,17 +418,31 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
     }
     __syncthreads();  // every history of the item has ended: the core is complete
     if (use_core) {
-      const int32_t nxy = cn[0] * cn[1];
       for (int e = threadIdx.x; e < (int)n_core; e += blockDim.x) {
         const unsigned long long v = core[e];
         if (v) {
           core[e] = 0ull;
-          const int32_t z = e / nxy, r = e - z * nxy, y = r / cn[0], x = r - y * cn[0];
           if constexpr (BOX) {
+            const int32_t nxy = cn[0] * cn[1];
+            const int32_t z = e / nxy, r = e - z * nxy, y = r / cn[0], x = r - y * cn[0];
             const int32_t bx = clo[0] - B.lo[0] + x, by = clo[1] - B.lo[1] + y, bz = clo[2] - B.lo[2] + z;
             atomic_add_u64(&B.base[bx + B.n[0] * (by + B.n[1] * bz)], v);
+          } else if constexpr (!SLICE) {
+            const int32_t nxy = B.n[0] * B.n[1];
+            const int32_t z = e / nxy, r = e - z * nxy, y = r / B.n[0], x = r - y * B.n[0];
+            const int32_t vox = (B.lo[0] + x) + G.n[0] * ((B.lo[1] + y) + G.n[1] * (B.lo[2] + z));
+            atomic_add_u64(&G.tally[vox], v);
+            if constexpr (LOG) log_atomic(B, C.atomics, &G.tally[vox]);
           } else {
-            const int32_t vox = (clo[0] + x) + G.n[0] * ((clo[1] + y) + G.n[1] * (clo[2] + z));
+            // entry -> slice j, across (x, y) -> grid voxel
+            const int32_t j = e / B.scells, r = e - j * B.scells, y = r / B.swa, x = r - y * B.swa;
+            const int32_t cd = B.sj0 + j;
+            const int32_t ca = slice_corner(B.sA[0], B.sB[0], j, B.smax[0]) + x;
+            const int32_t ce = slice_corner(B.sA[1], B.sB[1], j, B.smax[1]) + y;
+            const int32_t ix = B.sd == 0 ? cd : (B.sa == 0 ? ca : ce);
+            const int32_t iy = B.sd == 1 ? cd : (B.sa == 1 ? ca : ce);
+            const int32_t iz = B.sd == 2 ? cd : (B.sa == 2 ? ca : ce);
+            const int32_t vox = ix + G.n[0] * (iy + G.n[1] * iz);
             atomic_add_u64(&G.tally[vox], v);
             if constexpr (LOG) log_atomic(B, C.atomics, &G.tally[vox]);
           }
@@ -794,16 +842,21 @@ static hipError_t launch_core_t(const PersistentLaunch &a, hipStream_t st) {
     const size_t lds = core_fixed_lds(a.lut_lds) + sizeof(unsigned long long) * (size_t)a.core_cap;
     const bool box = a.boxes != nullptr;
     if (a.log && (box || !a.lut_lds)) return hipErrorInvalidValue;  // logged: phase tallies, one LUT
-    auto kern = a.log ? transport_core<R, true, false, true>
-                      : a.lut_lds ? (box ? transport_core<R, true, true> : transport_core<R, true, false>)
-                                  : (box ? transport_core<R, false, true> : transport_core<R, false, false>);
+    // slice cores that follow an oblique beam need the general key; cores
+    // that are all boxes of the grid take the cheaper one
+    const bool sl = a.slanted;
+    auto kern = a.log ? (sl ? transport_core<R, true, false, true, true> : transport_core<R, true, false, true>)
+              : a.lut_lds ? (box ? transport_core<R, true, true>
+                                 : (sl ? transport_core<R, true, false, false, true> : transport_core<R, true, false>))
+                          : (box ? transport_core<R, false, true>
+                                 : (sl ? transport_core<R, false, false, false, true> : transport_core<R, false, false>));
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(a.grid), dim3(kCoreBlock), lds, st, (const SpotDev<R> *)a.spots,
                        a.items, a.n_items, a.targets, (const R2 *)a.luts, (const R4 *)a.tab,
                        (R)a.l2e0, (R)a.inv_dl2, (R)a.dl2, a.k0, a.k1, a.flags, a.refill_min, a.cursor,
-                       a.counters, a.cores, a.core_cap, a.boxes, a.box_tally, a.box_bias, a.drained,
+                       a.counters, a.slices, a.cores, a.core_cap, a.boxes, a.box_tally, a.box_bias, a.drained,
                        a.log, a.log_cap, a.log_count);
     return hipGetLastError();
   }
@@ -811,7 +864,7 @@ static hipError_t launch_core_t(const PersistentLaunch &a, hipStream_t st) {
 
 template <typename R>
 static hipError_t launch_persistent_t(const PersistentLaunch &a, hipStream_t st) {
-  if (a.cores) return launch_core_t<R>(a, st);
+  if (a.cores || a.slices) return launch_core_t<R>(a, st);
   const size_t lds = persistent_lds<R>(a);
   const bool box = a.boxes != nullptr;
   if (a.lut_lds && box) launch_persistent_v<R, true, true>(a, lds, st);
