@@ -185,12 +185,13 @@ template <typename R> struct Geo {
 //               oblique beam (SliceCore)
 //   kTallyBoxCore  kTallyBox whose core window (inside the box) adds into
 //               the block's LDS copy (flushed into the box tally)
+//   kTallyBoxSlice kTallyBoxCore with a slice core inside the box
 //   kTallyCoreLog, kTallySliceLog  kTallyCore, kTallySlice that also write
 //               the address of every global atomic into a per-lane log
 //               (measurement of the deposit address pattern; the tallies are
 //               the same)
 constexpr int kTallyGrid = 0, kTallyBox = 1, kTallyCore = 2, kTallyBoxCore = 3, kTallyCoreLog = 4,
-              kTallySlice = 5, kTallySliceLog = 6;
+              kTallySlice = 5, kTallySliceLog = 6, kTallyBoxSlice = 7;
 
 template <int TM>
 constexpr bool kPhaseCore = TM == kTallyCore || TM == kTallyCoreLog || TM == kTallySlice || TM == kTallySliceLog;
@@ -207,15 +208,16 @@ struct BoxLane {
   // kTallyCoreLog: entry n of this lane is log[n * log_stride + log_lane], n < log_cap
   unsigned long long *log;
   uint32_t log_cap, log_stride, log_lane;
-  // kTallySlice, kTallySliceLog: the spot's slice core (SliceCore; sn = 0: none)
+  // kTallySlice, kTallySliceLog, kTallyBoxSlice: the spot's slice core
+  // (SliceCore; sn = 0: none)
   int32_t sd, sa, se, sj0, sn, swa, swe, scells;
-  int32_t sA[2], sB[2], smax[2];
+  int32_t sA[2], sB[2], smin[2], smax[2];
 };
 
 // corner of a slice-core window along one axis at slice j (SliceCore)
-__device__ __forceinline__ int32_t slice_corner(int32_t A, int32_t Bs, int32_t j, int32_t mx) {
+__device__ __forceinline__ int32_t slice_corner(int32_t A, int32_t Bs, int32_t j, int32_t mn, int32_t mx) {
   const int32_t c = (A + Bs * j) >> 16;
-  return c < 0 ? 0 : (c > mx ? mx : c);
+  return c < mn ? mn : (c > mx ? mx : c);
 }
 
 // physics tables per node i: (R, mu_delta, omega^2, dl2 / (R_{i+1} - R_i)),
@@ -237,6 +239,18 @@ __device__ __forceinline__ void set3(T &x0, T &x1, T &x2, int k, T v) {
   x0 = k == 0 ? v : x0;
   x1 = k == 1 ? v : x1;
   x2 = k == 2 ? v : x2;
+}
+
+// core entry of the lane's voxel in the slice core of B, or -1
+template <typename R>
+__device__ __forceinline__ int32_t slice_entry(const Lane<R> &L, const BoxLane &B) {
+  const int32_t j = pick3(L.ix, L.iy, L.iz, B.sd) - B.sj0;
+  if ((uint32_t)j < (uint32_t)B.sn) {
+    const int32_t x = pick3(L.ix, L.iy, L.iz, B.sa) - slice_corner(B.sA[0], B.sB[0], j, B.smin[0], B.smax[0]);
+    const int32_t y = pick3(L.ix, L.iy, L.iz, B.se) - slice_corner(B.sA[1], B.sB[1], j, B.smin[1], B.smax[1]);
+    if ((uint32_t)x < (uint32_t)B.swa && (uint32_t)y < (uint32_t)B.swe) return j * B.scells + x + B.swa * y;
+  }
+  return -1;
 }
 
 // Pointers that reach a kernel through device memory (tables of targets,
@@ -481,14 +495,15 @@ __device__ __forceinline__ int32_t tally_key(const Lane<R> &L, const BoxLane &B,
                     (uint32_t)z < (uint32_t)B.n[2];
     return in ? -3 - (x + B.n[0] * (y + B.n[1] * z)) : v;
   } else if constexpr (TM == kTallySlice || TM == kTallySliceLog) {
-    const int32_t j = pick3(L.ix, L.iy, L.iz, B.sd) - B.sj0;
-    if ((uint32_t)j < (uint32_t)B.sn) {
-      const int32_t x = pick3(L.ix, L.iy, L.iz, B.sa) - slice_corner(B.sA[0], B.sB[0], j, B.smax[0]);
-      const int32_t y = pick3(L.ix, L.iy, L.iz, B.se) - slice_corner(B.sA[1], B.sB[1], j, B.smax[1]);
-      if ((uint32_t)x < (uint32_t)B.swa && (uint32_t)y < (uint32_t)B.swe)
-        return -3 - (j * B.scells + x + B.swa * y);
-    }
-    return v;
+    const int32_t c = slice_entry(L, B);
+    return c >= 0 ? -3 - c : v;
+  } else if constexpr (TM == kTallyBoxSlice) {
+    const int32_t x = L.ix - B.lo[0], y = L.iy - B.lo[1], z = L.iz - B.lo[2];
+    if (!((uint32_t)x < (uint32_t)B.n[0] && (uint32_t)y < (uint32_t)B.n[1] &&
+          (uint32_t)z < (uint32_t)B.n[2]))
+      return -2;
+    const int32_t c = slice_entry(L, B);
+    return c >= 0 ? -3 - c : x + B.n[0] * (y + B.n[1] * z);
   } else if constexpr (TM == kTallyBoxCore) {
     const int32_t x = L.ix - B.lo[0], y = L.iy - B.lo[1], z = L.iz - B.lo[2];
     if (!((uint32_t)x < (uint32_t)B.n[0] && (uint32_t)y < (uint32_t)B.n[1] &&
@@ -525,7 +540,7 @@ __device__ __forceinline__ void commit_acc(const Lane<R> &L, const Geo<R> &G, co
     }
     atomic_add_u64(&G.tally[L.acc_v], (unsigned long long)L.acc);
     if constexpr (kLogged<TM>) log_atomic(B, C.atomics, &G.tally[L.acc_v]);
-  } else if constexpr (TM == kTallyBoxCore) {
+  } else if constexpr (TM == kTallyBoxCore || TM == kTallyBoxSlice) {
     if (L.acc_v <= -3) {  // LDS: the block's copy of the core window
       __hip_atomic_fetch_add(&B.core[-3 - L.acc_v], (unsigned long long)L.acc, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);

@@ -601,7 +601,7 @@ int default_chunk(const pmc_context *ctx, const pmc_request *req) { return launc
 
 pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s);
 pmc::SliceCore slice_core(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s,
-                          int32_t cap);
+                          int32_t cap, const pmc_box *inside = nullptr);
 
 // Core box of a spot: its voxel box if that fits `cap` entries, else the box's
 // full extent along the beam's main axis and a window across it, centred in
@@ -808,7 +808,7 @@ int build_request(pmc_context *ctx, const pmc_request *req, Prepared &P) {
       if (ok) {
         const int a = (c.d + 1) % 3, e = (c.d + 2) % 3;
         ok = c.j0 >= 0 && (long long)c.j0 + c.n_sl <= n[c.d] && c.wa <= n[a] && c.we <= n[e] &&
-             c.amax[0] == n[a] - c.wa && c.amax[1] == n[e] - c.we;
+             c.amin[0] == 0 && c.amin[1] == 0 && c.amax[0] == n[a] - c.wa && c.amax[1] == n[e] - c.we;
         // the corners A + B j in int32 for every slice
         for (int i = 0; i < 2 && ok; ++i) {
           const long long step = (long long)c.B[i] * (c.n_sl - 1);
@@ -875,6 +875,7 @@ struct BoxArgs {
   int32_t n_items;
   const pmc::CoreDev *cores;  // block engine: core window of every spot's box (else null)
   int32_t core_cap;
+  const pmc::SliceCore *slices;  // block engine with an oblique field: slice cores instead
 };
 
 // Address log of a block-engine launch (pmc_atomic_log).
@@ -964,8 +965,10 @@ int enqueue_prepared(pmc_context *ctx, Prepared &P, const pmc_request *req, hipS
       a.slanted = P.slanted;
       a.core_cap = P.core_cap;
       a.block = pmc::kCoreBlock;
-    } else if (box && box->cores) {
+    } else if (box && (box->cores || box->slices)) {
       a.cores = box->cores;
+      a.slices = box->slices;
+      a.slanted = box->slices != nullptr;
       a.core_cap = box->core_cap;
       a.block = pmc::kCoreBlock;
     }
@@ -2041,21 +2044,29 @@ pmc_box spot_box(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f,
   return b;
 }
 
-// Block-engine core of a spot for phase tallies (pmc::SliceCore).  The
-// slices are those of the grid axis d closest to the beam, from the face
-// where the axis enters the grid to the slice where it reaches
-// water-equivalent depth R(E) + 1 cm (beyond it the protons have stopped);
-// each holds a window of the same wa x we voxels across, centred on the
-// axis at the slice's middle plane and clamped into the grid, so that the
-// core follows an oblique beam.  The window's aspect ratio is that of the
-// beam's cross-section cut by a slice.  n_sl wa we <= cap; no core (n_sl =
-// 0) when the axis misses the grid, meets no matter, or the slices alone
-// exceed cap.
+// Block-engine core of a spot (pmc::SliceCore).  The slices are those of
+// the grid axis d closest to the beam, from the face where the axis enters
+// the grid to the slice where it reaches water-equivalent depth R(E) + 1 cm
+// (beyond it the protons have stopped); each holds a window of the same
+// wa x we voxels across, centred on the axis at the slice's middle plane and
+// clamped into the grid, so that the core follows an oblique beam.  The
+// window's aspect ratio is that of the beam's cross-section cut by a slice.
+// With `inside` (influence calculations) slices and windows are kept inside
+// that box.  n_sl wa we <= cap; no core (n_sl = 0) when the axis misses the
+// grid or the box, meets no matter, or the slices alone exceed cap.
 pmc::SliceCore slice_core(const pmc_context *ctx, const PhaseRec &ph, const pmc_field &f, const pmc_spot &s,
-                          int32_t cap) {
+                          int32_t cap, const pmc_box *inside) {
   pmc::SliceCore sc = {};
   AxisRay A;
   if (cap <= 0 || !axis_ray(ctx, ph, f, s, 1.0, A)) return sc;
+  int rlo[3] = {0, 0, 0}, rhi[3] = {A.n[0], A.n[1], A.n[2]};
+  if (inside) {
+    for (int k = 0; k < 3; ++k) {
+      rlo[k] = std::max(0, inside->lo[k]);
+      rhi[k] = std::min(A.n[k], inside->hi[k]);
+      if (rhi[k] <= rlo[k]) return sc;
+    }
+  }
   int d = 0;
   for (int k = 1; k < 3; ++k)
     if (std::fabs(A.w[k]) > std::fabs(A.w[d])) d = k;
@@ -2066,7 +2077,10 @@ pmc::SliceCore slice_core(const pmc_context *ctx, const PhaseRec &ph, const pmc_
   };
   // the entry slice: just inside the grid (t_in is on its face)
   const long long j_in = slice_at(A.t_in + 1e-9 * (A.t_out - A.t_in)), j_end = slice_at(A.t_end);
-  const long long j0 = std::min(j_in, j_end), n_sl = std::llabs(j_end - j_in) + 1;
+  const long long j0 = std::max((long long)rlo[d], std::min(j_in, j_end));
+  const long long j1 = std::min((long long)rhi[d] - 1, std::max(j_in, j_end));
+  if (j1 < j0) return sc;
+  const long long n_sl = j1 - j0 + 1;
   if (n_sl > cap || n_sl > (1 << 15)) return sc;
   const long long cells = cap / n_sl;
   // cross-section of the beam in a slice: a lateral offset r (along u or v)
@@ -2075,10 +2089,11 @@ pmc::SliceCore slice_core(const pmc_context *ctx, const PhaseRec &ph, const pmc_
     const double p = A.u[k] - A.u[d] * A.w[k] / A.w[d], q = A.v[k] - A.v[d] * A.w[k] / A.w[d];
     return std::max(1e-3, std::sqrt(p * p + q * q)) / A.d[k];
   };
+  const long long na = rhi[a] - rlo[a], ne = rhi[e] - rlo[e];
   long long wa = (long long)std::floor(std::sqrt((double)cells * foot(a) / foot(e)));
-  wa = std::max(1LL, std::min(wa, (long long)A.n[a]));
-  long long we = std::max(1LL, std::min(cells / wa, (long long)A.n[e]));
-  wa = std::max(1LL, std::min(cells / we, (long long)A.n[a]));
+  wa = std::max(1LL, std::min(wa, na));
+  long long we = std::max(1LL, std::min(cells / wa, ne));
+  wa = std::max(1LL, std::min(cells / we, na));
   // window corner along k at slice j: the axis at the slice's middle plane
   // minus half the width, in 16.16 fixed point, linear in j
   const int ax[2] = {a, e};
@@ -2096,7 +2111,8 @@ pmc::SliceCore slice_core(const pmc_context *ctx, const PhaseRec &ph, const pmc_
       return pmc::SliceCore{};
     sc.A[i] = (int32_t)fa;
     sc.B[i] = (int32_t)fb;
-    sc.amax[i] = (int32_t)(A.n[k] - wid[i]);
+    sc.amin[i] = rlo[k];
+    sc.amax[i] = (int32_t)(rhi[k] - wid[i]);
   }
   sc.d = d;
   sc.j0 = (int32_t)j0;
@@ -2241,17 +2257,50 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
       item_chunk = core_chunk;
     }
   }
+  // the core of every spot: when some field runs oblique to the grid, slice
+  // cores inside the boxes (windows that follow the beam axis); else a
+  // window of each box
   std::vector<pmc::CoreDev> cores;
+  std::vector<pmc::SliceCore> slices;
+  bool slanted = false;
   if (core_cap > 0) {
-    cores.assign((size_t)n_spots, pmc::CoreDev{});
+    slices.assign((size_t)n_spots, pmc::SliceCore{});
+    parallel_for(n_spots, [&](int64_t s) {
+      if (P->per_spot[s] == 0) return;
+      const pmc_spot &sp = plan.spots[s];
+      slices[s] = slice_core(ctx, ph, plan.fields[sp.field], sp, core_cap, &bx[s]);
+    });
     for (int64_t s = 0; s < n_spots; ++s) {
-      if (P->per_spot[s] == 0) continue;
-      pmc::CoreDev c = core_of(bx[s], plan.fields[plan.spots[s].field], core_cap);
-      bool ok = (long long)c.n[0] * c.n[1] * c.n[2] <= (long long)core_cap;
-      for (int k = 0; k < 3; ++k)
-        ok = ok && c.n[k] >= 0 && c.lo[k] >= bx[s].lo[k] && c.lo[k] + c.n[k] <= bx[s].hi[k];
-      if (!ok) return fail(ctx, PMC_E_STATE, "internal: core window of spot %lld outside its box", (long long)s);
-      cores[s] = c;
+      const pmc::SliceCore &c = slices[s];
+      if (c.n_sl == 0) continue;
+      if (c.B[0] != 0 || c.B[1] != 0) slanted = true;
+      bool ok = c.d >= 0 && c.d < 3 && c.wa > 0 && c.we > 0 &&
+                (long long)c.n_sl * c.wa * c.we <= (long long)core_cap;
+      if (ok) {
+        const int a = (c.d + 1) % 3, e = (c.d + 2) % 3;
+        ok = c.j0 >= bx[s].lo[c.d] && c.j0 + c.n_sl <= bx[s].hi[c.d] && c.amin[0] == bx[s].lo[a] &&
+             c.amin[1] == bx[s].lo[e] && c.amax[0] == bx[s].hi[a] - c.wa && c.amax[1] == bx[s].hi[e] - c.we &&
+             c.amax[0] >= c.amin[0] && c.amax[1] >= c.amin[1];
+        for (int i = 0; i < 2 && ok; ++i) {
+          const long long step = (long long)c.B[i] * (c.n_sl - 1);
+          ok = std::llabs((long long)c.A[i]) < 2147483647LL && std::llabs(step) < 2147483647LL &&
+               std::llabs((long long)c.A[i] + step) < 2147483647LL;
+        }
+      }
+      if (!ok) return fail(ctx, PMC_E_STATE, "internal: slice core of spot %lld outside its box", (long long)s);
+    }
+    if (!slanted) {
+      slices.clear();
+      cores.assign((size_t)n_spots, pmc::CoreDev{});
+      for (int64_t s = 0; s < n_spots; ++s) {
+        if (P->per_spot[s] == 0) continue;
+        pmc::CoreDev c = core_of(bx[s], plan.fields[plan.spots[s].field], core_cap);
+        bool ok = (long long)c.n[0] * c.n[1] * c.n[2] <= (long long)core_cap;
+        for (int k = 0; k < 3; ++k)
+          ok = ok && c.n[k] >= 0 && c.lo[k] >= bx[s].lo[k] && c.lo[k] + c.n[k] <= bx[s].hi[k];
+        if (!ok) return fail(ctx, PMC_E_STATE, "internal: core window of spot %lld outside its box", (long long)s);
+        cores[s] = c;
+      }
     }
   }
   // each batch's work items, in queue order over its spots
@@ -2271,7 +2320,8 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
   const size_t o_toff = off; off = align256(off + sizeof(long long) * (size_t)max_tiles);
   const size_t o_coff = off; off = align256(off + sizeof(long long) * (size_t)(max_chunks + 1));
   const size_t o_items = off; off = align256(off + sizeof(WorkItem) * bitems.size());
-  const size_t o_cores = off; off = align256(off + sizeof(pmc::CoreDev) * cores.size());
+  const size_t o_cores = off;
+  off = align256(off + std::max(sizeof(pmc::CoreDev) * cores.size(), sizeof(pmc::SliceCore) * slices.size()));
   ctx->inf_n_rows = -1;
   ctx->inf_nnz = 0;
   rc = ensure(ctx, ctx->inf_work, std::max<size_t>(off, 256), "influence work buffer");
@@ -2298,9 +2348,13 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
     HIP_TRY(ctx, copy_sync(ctx, d_items, bitems.data(), sizeof(WorkItem) * bitems.size(),
                            hipMemcpyHostToDevice), "upload batch work items");
   auto *d_cores = reinterpret_cast<pmc::CoreDev *>(work + o_cores);
+  auto *d_slices = reinterpret_cast<pmc::SliceCore *>(work + o_cores);
   if (!cores.empty())
     HIP_TRY(ctx, copy_sync(ctx, d_cores, cores.data(), sizeof(pmc::CoreDev) * cores.size(),
                            hipMemcpyHostToDevice), "upload core windows");
+  if (!slices.empty())
+    HIP_TRY(ctx, copy_sync(ctx, d_slices, slices.data(), sizeof(pmc::SliceCore) * slices.size(),
+                           hipMemcpyHostToDevice), "upload slice cores");
   HIP_TRY(ctx, pmc::launch_fill_u64(counters, PMC_COUNTERS, 0ull, st), "counter reset");
   unsigned __int128 deposited = 0;
   uint64_t nnz = 0;
@@ -2321,7 +2375,8 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
       if (rc) return rc;
       const BoxArgs ba = {d_boxes, scratch, base, d_items + batch_first[b],
                           (int32_t)(batch_first[b + 1] - batch_first[b]),
-                          core_cap > 0 ? d_cores : nullptr, core_cap};
+                          core_cap > 0 && !slanted ? d_cores : nullptr, core_cap,
+                          core_cap > 0 && slanted ? d_slices : nullptr};
       rc = enqueue_prepared<R>(ctx, *P, &br, st, no_tally, counters, static_cast<unsigned char *>(P->buf.p),
                                cursor, true, &ba);
       if (rc) return rc;

@@ -63,20 +63,21 @@ struct CoreDev {
   int32_t pad[2];
 };
 
-// Core of one spot for the block engine with phase tallies: slices
-// d = j0 + j (0 <= j < n_sl) of the grid axis d closest to the beam, each
-// with a window of wa x we voxels across (axes a = (d + 1) % 3 and
-// e = (d + 2) % 3) whose corner follows the beam axis:
-// corner_i(j) = clamp((A[i] + B[i] j) >> 16, 0, amax[i]) along a (i = 0)
-// and e (i = 1).  Voxel (corner_0(j) + x, corner_1(j) + y) of slice j is
-// core entry j wa we + x + wa y.  n_sl = 0: no core.
+// Core of one spot for the block engine: slices d = j0 + j (0 <= j < n_sl)
+// of the grid axis d closest to the beam, each with a window of wa x we
+// voxels across (axes a = (d + 1) % 3 and e = (d + 2) % 3) whose corner
+// follows the beam axis: corner_i(j) = clamp((A[i] + B[i] j) >> 16,
+// amin[i], amax[i]) along a (i = 0) and e (i = 1), inside the grid (phase
+// tallies) or the spot's box (influence calculations).  Voxel
+// (corner_0(j) + x, corner_1(j) + y) of slice j is core entry
+// j wa we + x + wa y.  n_sl = 0: no core.
 struct SliceCore {
   int32_t d, j0, n_sl, wa, we;
   int32_t A[2], B[2];
-  int32_t amax[2];
-  int32_t pad;
+  int32_t amin[2], amax[2];
+  int32_t pad[3];
 };
-static_assert(sizeof(SliceCore) == 48, "SliceCore layout");
+static_assert(sizeof(SliceCore) == 64, "SliceCore layout");
 
 constexpr int kTile = 1024;  // box entries per compaction tile (256 threads x 4)
 
@@ -128,8 +129,9 @@ struct PersistentLaunch {
   // host-visible flag set to 1 once every work item has been taken (nullable)
   unsigned int *drained = nullptr;
   // block engine (slices or cores != nullptr): one block per work item, LDS
-  // room for core_cap tally entries per block; the core of each spot: slices
-  // (phase tallies) or a window of its box (influence calculations)
+  // room for core_cap tally entries per block; the core of each spot: its
+  // slices, or for influence calculations whose cores are all straight (beams
+  // along a grid axis) the same cores as windows of the boxes
   const SliceCore *slices = nullptr;
   bool slanted = false;  // some slice core follows an oblique beam
   const CoreDev *cores = nullptr;

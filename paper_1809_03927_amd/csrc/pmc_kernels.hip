@@ -274,8 +274,8 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
                const BoxDev *__restrict__ boxes,
                unsigned long long *box_tally, long long box_bias, unsigned int *drained_flag,
                unsigned long long *log, uint32_t log_cap, uint32_t *log_count) {
-  static_assert(!(LOG && BOX) && !(SLICE && BOX), "the address log and slice cores cover the phase tallies");
-  constexpr int TM = BOX ? kTallyBoxCore
+  static_assert(!(LOG && BOX), "the address log covers the phase tallies");
+  constexpr int TM = BOX ? (SLICE ? kTallyBoxSlice : kTallyBoxCore)
                          : (SLICE ? (LOG ? kTallySliceLog : kTallySlice) : (LOG ? kTallyCoreLog : kTallyCore));
   extern __shared__ __align__(16) unsigned char smem[];
   using R2 = typename M<R>::R2;
@@ -319,10 +319,12 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
     const int32_t tgt = __builtin_amdgcn_readfirstlane(sp.target);
     const Geo<R> G = geo_of<R>(targets[tgt]);
     const R2 *lut = LUT_LDS ? lut_s : luts_g + (size_t)G.lut * kLutSize;
+    // the spot's core: a window of its box (influence calculations with
+    // straight cores) or its slices
     int32_t cn[3] = {0, 0, 0}, clo[3] = {0, 0, 0};
     long long n_core;
     BoxLane B;
-    if constexpr (BOX) {
+    if constexpr (BOX && !SLICE) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         clo[a] = __builtin_amdgcn_readfirstlane(cores[spot].lo[a]);
@@ -343,6 +345,7 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
       for (int i = 0; i < 2; ++i) {
         B.sA[i] = __builtin_amdgcn_readfirstlane(sc.A[i]);
         B.sB[i] = __builtin_amdgcn_readfirstlane(sc.B[i]);
+        B.smin[i] = __builtin_amdgcn_readfirstlane(sc.amin[i]);
         B.smax[i] = __builtin_amdgcn_readfirstlane(sc.amax[i]);
       }
       n_core = (long long)B.sn * B.scells;
@@ -366,13 +369,16 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
         B.clo[a] = clo[a];
         B.cn[a] = use_core ? cn[a] : 0;  // no core: the box tally takes every deposit
       }
+      if constexpr (SLICE)
+        if (!use_core) B.sn = 0;
       B.core = core;
     } else {
       B.base = core;
       if (!use_core) B.sn = 0;  // no core: every deposit goes to the tally
       if constexpr (!SLICE) {
         // the straight core as a box of the grid, entries x fastest
-        const int32_t c0 = slice_corner(B.sA[0], 0, 0, B.smax[0]), c1 = slice_corner(B.sA[1], 0, 0, B.smax[1]);
+        const int32_t c0 = slice_corner(B.sA[0], 0, 0, B.smin[0], B.smax[0]);
+        const int32_t c1 = slice_corner(B.sA[1], 0, 0, B.smin[1], B.smax[1]);
         const int32_t sn = B.sn;
         B.lo[0] = B.sd == 0 ? B.sj0 : (B.sa == 0 ? c0 : c1);
         B.lo[1] = B.sd == 1 ? B.sj0 : (B.sa == 1 ? c0 : c1);
@@ -422,7 +428,7 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
         const unsigned long long v = core[e];
         if (v) {
           core[e] = 0ull;
-          if constexpr (BOX) {
+          if constexpr (BOX && !SLICE) {
             const int32_t nxy = cn[0] * cn[1];
             const int32_t z = e / nxy, r = e - z * nxy, y = r / cn[0], x = r - y * cn[0];
             const int32_t bx = clo[0] - B.lo[0] + x, by = clo[1] - B.lo[1] + y, bz = clo[2] - B.lo[2] + z;
@@ -437,14 +443,18 @@ transport_core(const SpotDev<R> *__restrict__ spots, const WorkItem *__restrict_
             // entry -> slice j, across (x, y) -> grid voxel
             const int32_t j = e / B.scells, r = e - j * B.scells, y = r / B.swa, x = r - y * B.swa;
             const int32_t cd = B.sj0 + j;
-            const int32_t ca = slice_corner(B.sA[0], B.sB[0], j, B.smax[0]) + x;
-            const int32_t ce = slice_corner(B.sA[1], B.sB[1], j, B.smax[1]) + y;
+            const int32_t ca = slice_corner(B.sA[0], B.sB[0], j, B.smin[0], B.smax[0]) + x;
+            const int32_t ce = slice_corner(B.sA[1], B.sB[1], j, B.smin[1], B.smax[1]) + y;
             const int32_t ix = B.sd == 0 ? cd : (B.sa == 0 ? ca : ce);
             const int32_t iy = B.sd == 1 ? cd : (B.sa == 1 ? ca : ce);
             const int32_t iz = B.sd == 2 ? cd : (B.sa == 2 ? ca : ce);
-            const int32_t vox = ix + G.n[0] * (iy + G.n[1] * iz);
-            atomic_add_u64(&G.tally[vox], v);
-            if constexpr (LOG) log_atomic(B, C.atomics, &G.tally[vox]);
+            if constexpr (BOX) {  // the slices lie inside the box
+              atomic_add_u64(&B.base[(ix - B.lo[0]) + B.n[0] * ((iy - B.lo[1]) + B.n[1] * (iz - B.lo[2]))], v);
+            } else {
+              const int32_t vox = ix + G.n[0] * (iy + G.n[1] * iz);
+              atomic_add_u64(&G.tally[vox], v);
+              if constexpr (LOG) log_atomic(B, C.atomics, &G.tally[vox]);
+            }
           }
           C.atomics += 1;
         }
@@ -846,9 +856,9 @@ static hipError_t launch_core_t(const PersistentLaunch &a, hipStream_t st) {
     // that are all boxes of the grid take the cheaper one
     const bool sl = a.slanted;
     auto kern = a.log ? (sl ? transport_core<R, true, false, true, true> : transport_core<R, true, false, true>)
-              : a.lut_lds ? (box ? transport_core<R, true, true>
+              : a.lut_lds ? (box ? (sl ? transport_core<R, true, true, false, true> : transport_core<R, true, true>)
                                  : (sl ? transport_core<R, true, false, false, true> : transport_core<R, true, false>))
-                          : (box ? transport_core<R, false, true>
+                          : (box ? (sl ? transport_core<R, false, true, false, true> : transport_core<R, false, true>)
                                  : (sl ? transport_core<R, false, false, false, true> : transport_core<R, false, false>));
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
