@@ -638,6 +638,7 @@ def fourd_bench(eng, wl, trials, tally_mode):
 
 
 DELIVERY_TRIALS = 25
+DELIVERY_SCALING_TRIALS = (25, 100, 400)
 DELIVERY_SCENARIOS = {
     "free": {},
     "gated": {"gate_lo": 3, "gate_hi": 7},        # CT30-CT70, 50 % duty cycle
@@ -690,6 +691,24 @@ def delivery_bench(eng, cpu_trials):
     rp = out["scenarios"]["repainted"]
     out["value"] = rp["value"]
     out["ms_per_call"] = rp["ms_per_call"]
+    # scaling with the number of trials (repainted): every (trial, field)
+    # timeline is one block, so throughput grows with the timelines until
+    # they fill the device; the MU output (trials x spots x 10 doubles)
+    # comes back to the host in each call
+    d0 = results["repainted"][0]
+    scaling = []
+    for n_t in DELIVERY_SCALING_TRIALS:
+        d = W.Delivery(**{**d0.__dict__, "n_trials": n_t})
+        pmc.pmc_delivery_simulate(eng.ctx, d, sp, n_f)
+        t0 = time.perf_counter()
+        pmc.pmc_delivery_simulate(eng.ctx, d, sp, n_f)
+        sec = time.perf_counter() - t0
+        deliveries = float(np.ceil(sp["weight"] / d.max_mu).sum()) * n_t
+        scaling.append({"trials": n_t, "timelines": n_t * n_f, "ms_per_call": sec * 1e3,
+                        "deliveries_per_s": deliveries / sec})
+        log(f"delivery scaling: {n_t} trials ({n_t * n_f} timelines) {sec * 1e3:.1f} ms, "
+            f"{deliveries / sec:.3g} deliveries/s")
+    out["trial_scaling"] = scaling
     out["roofline"] = {
         "bound": "latency",
         "note": "each (trial, field) timeline is serial: 75 threads, one dependent FP64 chain each; "
