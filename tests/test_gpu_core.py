@@ -1,8 +1,8 @@
 """Block engine (PMC_TALLY_CORE) on the GPU, through the C ABI: deposits
 accumulated per spot in LDS and flushed once per work item give integer
 tallies identical to the plain engine's, for every work-item size, phase
-count and slicing, whether the spot's core box holds its whole voxel box or
-only a window of it."""
+count and slicing, for beams along a grid axis (box-shaped cores) and
+oblique to it (slice cores that follow the beam)."""
 import sys
 
 import numpy as np
@@ -79,6 +79,45 @@ def test_core_mode_thorax_windows(P, shape):
         say("box entries max", int(entries.max()), "capacity", cap)
         if shape == (128, 128, 80):
             assert entries.max() > cap
+    finally:
+        e.close()
+
+
+# fields at angles to the grid axes: main axes x, y and z, slopes of both signs
+OBLIQUE = ((0.0, -1.0, 0.0), (1.0, 0.0, 0.0), (0.6, -0.8, 0.0), (-0.3, 0.5, 0.81), (0.25, 0.35, -0.9))
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 40), (128, 128, 80)])
+def test_core_mode_oblique_fields(P, shape):
+    """Slice cores that follow beams oblique to the grid give tallies
+    identical to the plain engine's, for two work-item sizes and over item
+    slices."""
+    import torch
+    ph = W.make_thorax(shape, 0, 10)
+    plan = W.plan_thorax(3, n_layers=6, directions=OBLIQUE, n_phases=10)
+    plan.spots["phase"] = 0
+    wl = W.Workload("thorax_oblique", [ph], plan, 400_000, seed=7)
+    e = engine(P, wl)
+    try:
+        say("core vs plain, oblique fields", shape, len(plan.spots), "spots")
+        _, t_plain, _, b_plain = e.dose(wl.n_histories, [0], engine=P.PMC_ENGINE_PLAIN)
+        for chunk in (0, 256):
+            _, t_c, _, b_c = e.dose(wl.n_histories, [0], engine=P.PMC_ENGINE_PERSISTENT,
+                                    tally_mode=P.PMC_TALLY_CORE, chunk=chunk)
+            assert np.array_equal(t_c[0], t_plain[0]), chunk
+            assert b_c == b_plain
+        req = P.Request(wl.n_histories, [0], engine=P.PMC_ENGINE_PERSISTENT, tally_mode=P.PMC_TALLY_CORE,
+                        chunk=256)
+        n_items = P.pmc_request_items(e.ctx, req)
+        tal = torch.zeros(ph.nvox, dtype=torch.int64, device="cuda")
+        cnt = torch.zeros(P.PMC_COUNTERS, dtype=torch.int64, device="cuda")
+        st = torch.cuda.current_stream()
+        cuts = [0, n_items // 3, n_items // 3 + 1, n_items]
+        say("oblique core slices", cuts)
+        for b, c in zip(cuts, cuts[1:]):
+            P.pmc_dose_device(e.ctx, req.slice(b, c), st.cuda_stream, [tal.data_ptr()], cnt.data_ptr())
+        torch.cuda.synchronize()
+        assert np.array_equal(tal.cpu().numpy(), t_plain[0])
     finally:
         e.close()
 
