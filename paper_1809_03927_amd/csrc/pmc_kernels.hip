@@ -541,7 +541,7 @@ __global__ void fill_u64_kernel(unsigned long long *p, long long n, unsigned lon
 // of the box tallies are coalesced and the entries of a wave are consecutive.
 // ---------------------------------------------------------------------------
 constexpr int kInfBlock = 256;
-constexpr int kTilesPerBlock = 8;  // consecutive tiles per block: one owner search per block
+constexpr int kWriteTiles = 64;  // influence_write: consecutive tiles per block (one wave reads their counts)
 static_assert(kTile == 4 * kInfBlock, "tile = 4 entries per thread");
 
 __device__ __forceinline__ int tile_owner(const long long *tile_first, int n_spots, long long t) {
@@ -559,13 +559,13 @@ struct InfEntry {
   int32_t v;     // voxel of the phase grid; set only when T > 0
 };
 
-// Box entry e (< 2^31: a box is never larger than its grid) of spot box bx;
-// the voxel and its density are looked up only for entries with energy, the
-// ~90 % of empty entries cost one coalesced load.
-__device__ __forceinline__ InfEntry inf_entry(const InfluenceLaunch &a, const BoxDev &bx,
-                                              const long long *tb, int32_t e) {
+// Box entry e (< 2^31: a box is never larger than its grid) of spot box bx,
+// whose tally T is already loaded; the voxel and its density are looked up
+// only for entries with energy (the ~90 % of empty entries cost nothing more).
+__device__ __forceinline__ InfEntry inf_entry_of(const InfluenceLaunch &a, const BoxDev &bx, long long T,
+                                                 int32_t e) {
   InfEntry r;
-  r.T = tb[e];
+  r.T = T;
   r.rho = 0.0;
   r.v = 0;
   if (r.T > 0) {
@@ -616,36 +616,65 @@ __device__ __forceinline__ void flush_spot_max(const InfluenceLaunch &a, int j, 
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The tally words of tile t for this thread: entries threadIdx.x + k kInfBlock
+// of the tile.  Boxes lie back to back in whole tiles from the batch's first
+// entry, so tile t starts at entry t kTile whatever spot owns it (padding
+// entries are zero).
+__device__ __forceinline__ void load_tile(const InfluenceLaunch &a, long long t, long long v[4]) {
+  const long long *p = a.box_tally + t * kTile + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = p[k * kInfBlock];
+}
+
+constexpr int kTilesAhead = 2;  // pass 1: tiles whose loads are in flight beyond the current one
+
 // Pass 1 over a run of tiles per block: per spot, the maximum of
 // tally / density; the 128-bit sum of all tallies; per tile, the number of
 // entries with energy (tile_count, zero before), so that later passes skip
 // empty tiles.  Running values stay in registers: the block issues one max
-// atomic per spot it meets and one sum atomic per wave, and no barrier.
+// atomic per spot it meets and one sum atomic per wave, and no barrier.  The
+// loads of the next kTilesAhead tiles are issued before the current tile is
+// examined (most tiles are empty, and a tile's loads alone would leave the
+// memory system idle between them).
 __global__ void __launch_bounds__(kInfBlock) influence_max(InfluenceLaunch a, long long tiles_per_block) {
   const long long t_begin = (long long)blockIdx.x * tiles_per_block;
   const long long t_end = t_begin + tiles_per_block < a.n_tiles ? t_begin + tiles_per_block : a.n_tiles;
   if (t_begin >= t_end) return;
   int j = tile_owner(a.tile_first, a.n_spots, t_begin);
+  BoxDev bx = a.boxes[j];
+  long long tf = a.tile_first[j], tf_next = a.tile_first[j + 1];
   double m = 0.0;
   unsigned long long lo32 = 0, hi32 = 0;
+  long long q[kTilesAhead + 1][4] = {};
+#pragma unroll
+  for (int i = 0; i <= kTilesAhead; ++i)
+    if (t_begin + i < t_end) load_tile(a, t_begin + i, q[i]);
   for (long long t = t_begin; t < t_end; ++t) {
-    const int jt = advance_owner(a.tile_first, j, t);
-    if (jt != j) {  // block-uniform
+    long long cur[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cur[k] = q[0][k];
+#pragma unroll
+    for (int i = 0; i < kTilesAhead; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[i][k] = q[i + 1][k];
+    if (t + kTilesAhead + 1 < t_end) load_tile(a, t + kTilesAhead + 1, q[kTilesAhead]);
+    if (t >= tf_next) {  // block-uniform: the tile belongs to a later spot
       flush_spot_max(a, j, m);
       m = 0.0;
-      j = jt;
+      j = advance_owner(a.tile_first, j, t);
+      bx = a.boxes[j];
+      tf = a.tile_first[j];
+      tf_next = a.tile_first[j + 1];
     }
-    const BoxDev bx = a.boxes[j];
     const int32_t ne = bx.n[0] * bx.n[1] * bx.n[2];
-    const int32_t e0 = (int32_t)((t - a.tile_first[j]) * kTile);
-    const long long *tb = a.box_tally + (bx.offset - a.box_bias);
+    const int32_t e0 = (int32_t)((t - tf) * kTile);
     uint32_t nz = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int32_t e = e0 + (int32_t)threadIdx.x + k * kInfBlock;
       double sc = 0.0;
       if (e < ne) {
-        const InfEntry x = inf_entry(a, bx, tb, e);
+        const InfEntry x = inf_entry_of(a, bx, cur[k], e);
         sc = inf_score(x);
         const unsigned long long T = (unsigned long long)x.T;  // >= 0
         lo32 += T & 0xffffffffull;
@@ -667,29 +696,44 @@ __global__ void __launch_bounds__(kInfBlock) influence_max(InfluenceLaunch a, lo
   }
 }
 
+// The tiles among [t0, t0 + 64) before t_end whose word in `per_tile` is
+// nonzero, as a bit mask (bit i: tile t0 + i).  Every wave of the block reads
+// the same words, so the mask is block-uniform.
+__device__ __forceinline__ unsigned long long live_tiles(const uint32_t *per_tile, long long t0, long long t_end) {
+  const long long t = t0 + (threadIdx.x & 63);
+  const uint32_t c = t < t_end ? per_tile[t] : 0u;
+  return __ballot(c != 0u);
+}
+
 // Pass 2: per tile, the number of entries at or above the spot's threshold
-// (tile_keep, zero before); tiles without energy are skipped.
+// (tile_keep, zero before).  The block reads the tile counts 64 at a time and
+// visits only the tiles with energy.
 __global__ void __launch_bounds__(kInfBlock) influence_count(InfluenceLaunch a, long long tiles_per_block) {
   const long long t_begin = (long long)blockIdx.x * tiles_per_block;
   const long long t_end = t_begin + tiles_per_block < a.n_tiles ? t_begin + tiles_per_block : a.n_tiles;
   if (t_begin >= t_end) return;
-  int j = tile_owner(a.tile_first, a.n_spots, t_begin);
-  for (long long t = t_begin; t < t_end; ++t) {
-    if (a.tile_count[t] == 0) continue;  // block-uniform: nothing in this tile
-    j = advance_owner(a.tile_first, j, t);
-    const BoxDev bx = a.boxes[j];
-    const int32_t ne = bx.n[0] * bx.n[1] * bx.n[2];
-    const int32_t e0 = (int32_t)((t - a.tile_first[j]) * kTile);
-    const long long *tb = a.box_tally + (bx.offset - a.box_bias);
-    const double thr = a.rel_threshold * __longlong_as_double((long long)a.spot_max[j]);
-    uint32_t c = 0;
+  int j = -1;
+  for (long long t0 = t_begin; t0 < t_end; t0 += 64) {
+    unsigned long long live = live_tiles(a.tile_count, t0, t_end);
+    while (live) {
+      const long long t = t0 + __builtin_ctzll(live);
+      live &= live - 1;
+      j = j < 0 ? tile_owner(a.tile_first, a.n_spots, t) : advance_owner(a.tile_first, j, t);
+      const BoxDev bx = a.boxes[j];
+      const int32_t ne = bx.n[0] * bx.n[1] * bx.n[2];
+      const int32_t e0 = (int32_t)((t - a.tile_first[j]) * kTile);
+      const double thr = a.rel_threshold * __longlong_as_double((long long)a.spot_max[j]);
+      long long v[4];
+      load_tile(a, t, v);
+      uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int32_t e = e0 + (int32_t)threadIdx.x + k * kInfBlock;
-      c += wave_count(e < ne && inf_keep(inf_entry(a, bx, tb, e), thr));
+      for (int k = 0; k < 4; ++k) {
+        const int32_t e = e0 + (int32_t)threadIdx.x + k * kInfBlock;
+        c += wave_count(e < ne && inf_keep(inf_entry_of(a, bx, v[k], e), thr));
+      }
+      if ((threadIdx.x & 63) == 0 && c)
+        __hip_atomic_fetch_add(&a.tile_keep[t], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if ((threadIdx.x & 63) == 0 && c)
-      __hip_atomic_fetch_add(&a.tile_keep[t], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -755,28 +799,32 @@ __device__ __forceinline__ unsigned long long tile_offset(const InfluenceLaunch 
 }
 
 // Pass 4: entries of the tile at or above the threshold, in entry order, at
-// the tile's offset.
+// the tile's offset.  A block owns kWriteTiles consecutive tiles, reads
+// their kept counts at once and visits only the tiles with kept entries.
 __global__ void __launch_bounds__(kInfBlock) influence_write(InfluenceLaunch a) {
   __shared__ uint32_t wcount[kInfBlock / 64];
-  const long long t_begin = (long long)blockIdx.x * kTilesPerBlock;
-  const long long t_end = t_begin + kTilesPerBlock < a.n_tiles ? t_begin + kTilesPerBlock : a.n_tiles;
-  int j = tile_owner(a.tile_first, a.n_spots, t_begin);
-  for (long long t = t_begin; t < t_end; ++t) {
-    if (a.tile_keep[t] == 0) continue;  // block-uniform: nothing kept in this tile
-    j = advance_owner(a.tile_first, j, t);
+  const long long t_begin = (long long)blockIdx.x * kWriteTiles;
+  const long long t_end = t_begin + kWriteTiles < a.n_tiles ? t_begin + kWriteTiles : a.n_tiles;
+  unsigned long long live = live_tiles(a.tile_keep, t_begin, t_end);  // block-uniform
+  int j = -1;
+  while (live) {
+    const long long t = t_begin + __builtin_ctzll(live);
+    live &= live - 1;
+    j = j < 0 ? tile_owner(a.tile_first, a.n_spots, t) : advance_owner(a.tile_first, j, t);
     const BoxDev bx = a.boxes[j];
     const int32_t ne = bx.n[0] * bx.n[1] * bx.n[2];
     const int32_t e0 = (int32_t)((t - a.tile_first[j]) * kTile);
-    const long long *tb = a.box_tally + (bx.offset - a.box_bias);
     const double thr = a.rel_threshold * __longlong_as_double((long long)a.spot_max[j]);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     unsigned long long pos = (unsigned long long)a.nnz_base + tile_offset(a, t);
+    long long v[4];
+    load_tile(a, t, v);
     for (int k = 0; k < 4; ++k) {  // sub-tiles of 256 consecutive entries, in order
       const int32_t e = e0 + (int32_t)threadIdx.x + k * kInfBlock;
       InfEntry x = {};
       bool keep = false;
       if (e < ne) {
-        x = inf_entry(a, bx, tb, e);
+        x = inf_entry_of(a, bx, v[k], e);
         keep = inf_keep(x, thr);
       }
       const unsigned long long bal = __ballot(keep);
@@ -963,7 +1011,7 @@ hipError_t launch_influence_reduce(const InfluenceLaunch &a, hipStream_t st) {
 }
 
 hipError_t launch_influence_write(const InfluenceLaunch &a, hipStream_t st) {
-  const unsigned blocks = (unsigned)((a.n_tiles + kTilesPerBlock - 1) / kTilesPerBlock);
+  const unsigned blocks = (unsigned)((a.n_tiles + kWriteTiles - 1) / kWriteTiles);
   if (a.n_tiles > 0)
     hipLaunchKernelGGL(influence_write, dim3(blocks), dim3(kInfBlock), 0, st, a);
   if (a.n_spots > 0)
