@@ -163,6 +163,9 @@ struct pmc_context {
   // influence calculations: box tallies of a batch of spots, bookkeeping,
   // and the result (CSR rows, one per plan spot)
   DevBuf box_scratch, inf_work;
+  // leading entries of box_scratch known to be zero: every influence batch
+  // clears the tiles it wrote, so later batches need not zero them again
+  long long box_zero = 0;
   DevBuf inf_rows, inf_voxel, inf_value;
   size_t inf_cap = 0;        // capacity of inf_voxel / inf_value, entries
   int64_t inf_n_rows = -1;   // -1: no result
@@ -1204,6 +1207,7 @@ void pmc_destroy(pmc_context *ctx) {
     release(ctx, ctx->cursor);
     release(ctx, ctx->counters);
     release(ctx, ctx->box_scratch);
+    ctx->box_zero = 0;
     release(ctx, ctx->inf_work);
     release(ctx, ctx->inf_rows);
     release(ctx, ctx->inf_voxel);
@@ -2160,6 +2164,7 @@ int grow_csr(pmc_context *ctx, size_t need, hipStream_t st) {
 
 void free_influence(pmc_context *ctx) {
   release(ctx, ctx->box_scratch);
+  ctx->box_zero = 0;
   release(ctx, ctx->inf_work);
   release(ctx, ctx->inf_rows);
   release(ctx, ctx->inf_voxel);
@@ -2326,9 +2331,11 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
   ctx->inf_nnz = 0;
   rc = ensure(ctx, ctx->inf_work, std::max<size_t>(off, 256), "influence work buffer");
   if (rc) return rc;
+  void *const old_scratch = ctx->box_scratch.p;
   rc = ensure(ctx, ctx->box_scratch, std::max<size_t>((size_t)max_entries * sizeof(long long), 256),
               "influence box tallies");
   if (rc) return rc;
+  if (ctx->box_scratch.p != old_scratch) ctx->box_zero = 0;  // memory of the pool: contents unknown
   rc = ensure(ctx, ctx->inf_rows, sizeof(int64_t) * (size_t)(n_spots + 1), "influence rows");
   if (rc) return rc;
   rc = ensure(ctx, ctx->counters, sizeof(uint64_t) * PMC_COUNTERS, "counters");
@@ -2364,7 +2371,14 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
     const int64_t s0 = cuts[b], s1 = cuts[b + 1];
     const long long base = offset[s0], entries = offset[s1] - base;
     const long long n_tiles = entries / pmc::kTile;
-    HIP_TRY(ctx, pmc::launch_fill_u64(scratch, entries, 0ull, st), "zero box tallies");
+    // the batch's box tallies start at zero: only entries beyond the part
+    // known to be zero are filled; until this batch has cleared the tiles it
+    // writes (the last pass) nothing is known to be zero
+    if (entries > ctx->box_zero)
+      HIP_TRY(ctx, pmc::launch_fill_u64(scratch + ctx->box_zero, entries - ctx->box_zero, 0ull, st),
+              "zero box tallies");
+    const long long zero_after = std::max(ctx->box_zero, entries);
+    ctx->box_zero = 0;
     HIP_TRY(ctx, pmc::launch_fill_u64(d_max, s1 - s0, 0ull, st), "zero maxima");
     HIP_TRY(ctx, pmc::launch_fill_u64(d_dep, 2, 0ull, st), "zero sums");
     if (batch_first[b + 1] > batch_first[b]) {
@@ -2425,6 +2439,7 @@ int influence(pmc_context *ctx, const pmc_request *req_in, const pmc_box *boxes_
     L.voxel = static_cast<int32_t *>(ctx->inf_voxel.p);
     L.value = static_cast<float *>(ctx->inf_value.p);
     HIP_TRY(ctx, pmc::launch_influence_write(L, st), "influence write");
+    ctx->box_zero = zero_after;  // the write pass ends by clearing every tile with energy
     nnz += hostv[0];
     ctx->inf_nnz = nnz;
   }

@@ -279,7 +279,7 @@ hipError_t launch_emtm_ratio(const EmtmRatio &a, hipStream_t st);
 hipError_t launch_emtm_mask(const EmtmMask &a, hipStream_t st);
 
 hipError_t launch_influence_reduce(const InfluenceLaunch &a, hipStream_t st);  // max, sum, count, scan
-hipError_t launch_influence_write(const InfluenceLaunch &a, hipStream_t st);   // rows and entries
+hipError_t launch_influence_write(const InfluenceLaunch &a, hipStream_t st);   // rows and entries, then clears the tiles with energy
 
 struct TraceLaunch {
   const void *spot;  // host pointer to one SpotDev<R> (passed by value)

@@ -630,8 +630,8 @@ constexpr int kTilesAhead = 2;  // pass 1: tiles whose loads are in flight beyon
 
 // Pass 1 over a run of tiles per block: per spot, the maximum of
 // tally / density; the 128-bit sum of all tallies; per tile, the number of
-// entries with energy (tile_count, zero before), so that later passes skip
-// empty tiles.  Running values stay in registers: the block issues one max
+// nonzero entries (tile_count, zero before), so that later passes skip
+// empty tiles and the last one clears exactly the tiles written.  Running values stay in registers: the block issues one max
 // atomic per spot it meets and one sum atomic per wave, and no barrier.  The
 // loads of the next kTilesAhead tiles are issued before the current tile is
 // examined (most tiles are empty, and a tile's loads alone would leave the
@@ -681,7 +681,7 @@ __global__ void __launch_bounds__(kInfBlock) influence_max(InfluenceLaunch a, lo
         hi32 += T >> 32;
       }
       m = fmax(m, sc);
-      nz += wave_count(sc > 0.0);
+      nz += wave_count(cur[k] != 0);
     }
     if ((threadIdx.x & 63) == 0 && nz)
       __hip_atomic_fetch_add(&a.tile_count[t], nz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -850,6 +850,22 @@ __global__ void __launch_bounds__(kInfBlock) influence_write(InfluenceLaunch a) 
   }
 }
 
+// After pass 4: every tile with a nonzero entry back to zero, so that the
+// box tallies need no full fill before the next batch.
+__global__ void __launch_bounds__(kInfBlock) influence_clear(InfluenceLaunch a) {
+  const long long t_begin = (long long)blockIdx.x * kWriteTiles;
+  const long long t_end = t_begin + kWriteTiles < a.n_tiles ? t_begin + kWriteTiles : a.n_tiles;
+  unsigned long long live = live_tiles(a.tile_count, t_begin, t_end);
+  long long *tally = const_cast<long long *>(a.box_tally);
+  while (live) {
+    const long long t = t_begin + __builtin_ctzll(live);
+    live &= live - 1;
+    long long *p = tally + t * kTile + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k * kInfBlock] = 0;
+  }
+}
+
 __global__ void influence_rows(InfluenceLaunch a) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < a.n_spots) a.row_ptr[j] = a.nnz_base + (long long)tile_offset(a, a.tile_first[j]);
@@ -1012,8 +1028,10 @@ hipError_t launch_influence_reduce(const InfluenceLaunch &a, hipStream_t st) {
 
 hipError_t launch_influence_write(const InfluenceLaunch &a, hipStream_t st) {
   const unsigned blocks = (unsigned)((a.n_tiles + kWriteTiles - 1) / kWriteTiles);
-  if (a.n_tiles > 0)
+  if (a.n_tiles > 0) {
     hipLaunchKernelGGL(influence_write, dim3(blocks), dim3(kInfBlock), 0, st, a);
+    hipLaunchKernelGGL(influence_clear, dim3(blocks), dim3(kInfBlock), 0, st, a);
+  }
   if (a.n_spots > 0)
     hipLaunchKernelGGL(influence_rows, dim3((unsigned)((a.n_spots + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();
