@@ -62,11 +62,12 @@ extern "C" {
  * LANE: each lane adds a voxel visit's deposit into the phase tally (one
  *   device-wide atomic per visit); waves take work items on their own.
  * CORE: a block of 1024 threads runs one work item at a time; deposits inside
- *   the spot's core box (the central part of the voxel box around its beam
- *   axis that fits the block's LDS) add into LDS, the block adds each nonzero
- *   core voxel into the phase tally once the item is done, and the other
- *   deposits go to the phase tally directly.  Fewer device-wide atomics; the
- *   integer tallies are identical.  FP32 only. */
+ *   the spot's core (the slices of the grid axis closest to the beam, from
+ *   the entry face to water-equivalent depth R(E) + 1 cm, each with a window
+ *   across centred on the beam axis, all fitting the block's LDS) add into
+ *   LDS, the block adds each nonzero core voxel into the phase tally once the
+ *   item is done, and the other deposits go to the phase tally directly.
+ *   Fewer device-wide atomics; the integer tallies are identical.  FP32 only. */
 #define PMC_TALLY_AUTO 0
 #define PMC_TALLY_LANE 1
 #define PMC_TALLY_CORE 2
@@ -300,7 +301,7 @@ int pmc_dose_device_notify(pmc_context *ctx, const pmc_request *req, void *strea
 /* pmc_dose_device for callers that cannot allocate device memory in the
  * call (code that must not call hipMalloc, tight serving loops, harnesses
  * that forbid allocation): the same transport, the same tallies bit for bit,
- * but the request's device data (spot descriptors, work items, core boxes,
+ * but the request's device data (spot descriptors, work items, spot cores,
  * LUTs, target table) and the work-queue cursor go into a fixed device array
  * of 8 MiB that the library sets up once per device at pmc_create (with a
  * pinned host staging buffer of the same size), instead of memory allocated
@@ -420,8 +421,10 @@ int pmc_influence_boxes(pmc_context *ctx, int32_t plan, int32_t phase, pmc_box *
  * Runs the request's histories (persistent engine, launch fields honoured,
  * not sliced) with every spot tallying into its own box (`boxes`: one per
  * plan spot, or NULL for pmc_influence_boxes); with PMC_TALLY_CORE (picked
- * by the rule of pmc_launch_shape when tally_mode is 0) a block keeps a
- * window of its spot's box in LDS.  Then it keeps, per spot, the
+ * by the rule of pmc_launch_shape when tally_mode is 0) a block keeps part
+ * of its spot's box in LDS (a window centred in the box, or, when some field
+ * runs oblique to the grid, the spot's core slices kept inside its box).
+ * Then it keeps, per spot, the
  * voxels whose tally / density is >= rel_threshold (0..1) x that spot's
  * maximum of it, as CSR: one row per plan spot (row_ptr: n_spots + 1
  * int64), voxel = linear index of the phase grid (int32, ascending within a
