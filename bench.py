@@ -64,12 +64,12 @@ METHOD_VALU_PER_STEP = 250
 # requests (TCC_EA0_ATOMIC_sum) (profiles/transport_core_thorax4d_counters.md).
 # Valid only for the sources they were measured on (hash below) and that
 # launch shape; otherwise null.
-PROFILED_TRAFFIC_BYTES = 169.5e9
+PROFILED_TRAFFIC_BYTES = 169.0e9
 PROFILED_MEMSIDE_ATOMICS = 4.0190e9
 # memory-side atomic requests of the replay probe per atomic it issues
 # (TCC_EA0_ATOMIC_sum 2.1430e9 for 2.147e9 replayed, same profile)
 PROFILED_REPLAY_MEMSIDE_PER_ISSUED = 2.1430e9 / 2.147e9
-PROFILED_KERNEL_HASH = "48add8b74f132ad4"
+PROFILED_KERNEL_HASH = "75b89252d9311cbb"
 
 # Deformable accumulation (energy/mass transfer, Sec. 2.D.2): the per-phase
 # tallies of the 4D run accumulated onto one reference phase with n^3
