@@ -397,7 +397,7 @@ def main():
         case_out[name] = case_bench(cwl, a.case_steps, 1, 0 if a.no_cpu_baseline else a.case_cpu_seconds)
         cases[name] = None
     robust_out = None if a.no_robust else robust_bench(0 if a.no_cpu_baseline else 5.0)
-    cpu = None if a.no_cpu_baseline else cpu_baseline(wl, k_sample, gpu_sample)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(wl, k_sample, gpu_sample, single_thread=True)
     out = {
         "metric": "proton histories/s; p50/p99 dose-request latency, batched vs plain, 1 MI355X",
         "value": wl.n_histories / sec_b, "unit": "histories/s", "n_gpus": 1, "steps": a.steps,
@@ -1025,13 +1025,14 @@ def cpu_sample_size(wl, target_s):
     return k2
 
 
-def cpu_baseline(wl, k, gpu_sample, label=None):
+def cpu_baseline(wl, k, gpu_sample, label=None, single_thread=False):
     """The FP64 oracle on the host, on the first k histories of every spot,
-    timed; then the accuracy check of the GPU's tallies of the same
-    histories against it: voxels above 10 % of the phase's maximum dose pass
-    if |dD| <= 1 % of that maximum or <= 3 sigma_diff (sqrt 2 x the oracle's
-    sigma from 10 history batches), in at least 99.5 % of them (the same
-    random numbers); total energy within 0.1 %."""
+    timed (with single_thread also on one thread, on the first k / cores
+    histories of every spot); then the accuracy check of the GPU's tallies
+    of the same histories against it: voxels above 10 % of the phase's
+    maximum dose pass if |dD| <= 1 % of that maximum or <= 3 sigma_diff
+    (sqrt 2 x the oracle's sigma from 10 history batches), in at least 99.5 %
+    of them (the same random numbers); total energy within 0.1 %."""
     import numpy as np
     import oracle
     cores = os.cpu_count() or 1
@@ -1043,6 +1044,16 @@ def cpu_baseline(wl, k, gpu_sample, label=None):
            "sample": f"first {k} histories of every spot of the {label or wl.name} plan "
                      f"({b['histories']} histories, {b['steps']} steps, {dt:.1f} s, FP64)",
            "steps_per_history": b["steps"] / max(b["histories"], 1)}
+    if single_thread:
+        k1 = max(1, k // cores)
+        t = time.perf_counter()
+        _, b1 = oracle.dose_subset(wl.phases, wl.plan, wl.n_histories, wl.seed, 0, k1, n_threads=1,
+                                   request_id=wl.request_id)
+        dt1 = time.perf_counter() - t
+        out["threads_1"] = {"value": b1["histories"] / dt1, "histories": b1["histories"], "seconds": dt1,
+                            "sample": f"first {k1} histories of every spot"}
+        log(f"cpu baseline on one thread: {b1['histories']} histories in {dt1:.1f} s "
+            f"({b1['histories'] / dt1:.3g} histories/s)")
     if gpu_sample is None:
         return out
     nb = 10
