@@ -630,12 +630,13 @@ constexpr int kTilesAhead = 2;  // pass 1: tiles whose loads are in flight beyon
 
 // Pass 1 over a run of tiles per block: per spot, the maximum of
 // tally / density; the 128-bit sum of all tallies; per tile, the number of
-// nonzero entries (tile_count, zero before), so that later passes skip
-// empty tiles and the last one clears exactly the tiles written.  Running values stay in registers: the block issues one max
-// atomic per spot it meets and one sum atomic per wave, and no barrier.  The
-// loads of the next kTilesAhead tiles are issued before the current tile is
-// examined (most tiles are empty, and a tile's loads alone would leave the
-// memory system idle between them).
+// nonzero entries (tile_count, zero before), so that later passes skip empty
+// tiles and the last one clears exactly the tiles written.  Running values
+// stay in registers: the block issues one max atomic per spot it meets and
+// one sum atomic per wave, and no barrier.  The loads of the next
+// kTilesAhead tiles are issued before the current tile is examined (most
+// tiles are empty, and a tile's loads alone would leave the memory system
+// idle between them).
 __global__ void __launch_bounds__(kInfBlock) influence_max(InfluenceLaunch a, long long tiles_per_block) {
   const long long t_begin = (long long)blockIdx.x * tiles_per_block;
   const long long t_end = t_begin + tiles_per_block < a.n_tiles ? t_begin + tiles_per_block : a.n_tiles;
