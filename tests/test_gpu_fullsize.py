@@ -345,3 +345,32 @@ def test_full_size_delivery(full, scenario):
     say(f"full-size delivery {scenario}: {flips} timelines with a flipped near-tie decision")
     # MU conserved per spot and trial
     assert np.allclose(got["mu"].sum(axis=2), sp["weight"][None, :], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("name", ["liver", "esophagus"])
+def test_case_phantom_full_size_equals_plain(name):
+    """A patient-shaped case at the benchmark's size (5e7 histories over ten
+    phases, fields oblique to the grid: the block engine's slice cores):
+    batched tallies and balance equal the plain engine's."""
+    from paper_1809_03927_amd import pmc
+    say(f"case {name}: generating")
+    wl = W.workload_case(name)
+    e = pmc.Engine(device=0, precision=pmc.PMC_FP32, seed=wl.seed)
+    try:
+        e.load_workload(wl)
+        phases = list(range(len(wl.phases)))
+        req = pmc.Request(wl.n_histories, phases, request_id=wl.request_id, engine=pmc.PMC_ENGINE_PERSISTENT)
+        shape = pmc.pmc_launch_shape(e.ctx, req)
+        assert shape["tally_mode"] == pmc.PMC_TALLY_CORE
+        nv = [ph.nvox for ph in wl.phases]
+        say(f"case {name}: batched")
+        _, t_b, _, b_b = pmc.pmc_dose(e.ctx, req, nv, want_dose=False)
+        assert b_b["deposited"] + b_b["escaped"] + b_b["nuclear"] == b_b["incident"]
+        say(f"case {name}: plain")
+        req_p = pmc.Request(wl.n_histories, phases, request_id=wl.request_id, engine=pmc.PMC_ENGINE_PLAIN)
+        _, t_p, _, b_p = pmc.pmc_dose(e.ctx, req_p, nv, want_dose=False)
+        assert b_p == b_b
+        for i in phases:
+            assert np.array_equal(t_p[i], t_b[i]), i
+    finally:
+        e.close()
